@@ -1,0 +1,76 @@
+"""Oracle decoders and structural checks for converted formats.  Test infrastructure only.
+
+A conversion is correct when decoding the converted arrays gives back exactly the canonical
+triplets (same coordinates, bit-identical values) and the format's ordering rules hold.
+
+CRS (Section 2): row_ptr[m+1] non-decreasing from 0 to nnz; columns ascend inside a row.
+CSB with Hilbert order inside blocks, CSBH (Sections 3.1 and 4.1): beta x beta blocks; blk_ptr has
+one entry per block in row-wise block order plus a final nnz; inside a block each entry's local
+row and column are packed into one 32-bit word, row in the upper 16 bits; entries of a block
+follow the Hilbert order of their local (row, col).
+"""
+import numpy as np
+
+from .curves import hilbert_index_array
+
+
+def decode_crs(row_ptr):
+    """Row index of every stored entry of a CRS matrix."""
+    row_ptr = np.asarray(row_ptr, np.int64)
+    return np.repeat(np.arange(len(row_ptr) - 1, dtype=np.int64), np.diff(row_ptr))
+
+
+def check_crs(m, n, row_ptr, col, val, canon_row, canon_col, canon_val):
+    """Raise AssertionError unless the CRS arrays equal the canonical triplets exactly."""
+    row_ptr = np.asarray(row_ptr, np.int64)
+    assert row_ptr.shape == (m + 1,), "row_ptr length"
+    assert row_ptr[0] == 0 and row_ptr[-1] == len(col) == len(val), "row_ptr ends"
+    assert np.all(np.diff(row_ptr) >= 0), "row_ptr not monotone"
+    rows = decode_crs(row_ptr)
+    assert len(rows) == len(canon_row), "entry count"
+    assert np.array_equal(rows, np.asarray(canon_row, np.int64)), "row indices"
+    assert np.array_equal(np.asarray(col, np.int64), np.asarray(canon_col, np.int64)), "columns"
+    a = np.asarray(val, np.float64).view(np.int64)
+    b = np.asarray(canon_val, np.float64).view(np.int64)
+    assert np.array_equal(a, b), "values differ bitwise"
+
+
+def beta_blocks(m, n, log2_beta):
+    beta = 1 << log2_beta
+    return (m + beta - 1) // beta, (n + beta - 1) // beta
+
+
+def decode_csbh(m, n, log2_beta, blk_ptr, packed, val):
+    """Decode CSBH arrays to triplets in storage order: (row, col, val, block, local_r, local_c)."""
+    nbr, nbc = beta_blocks(m, n, log2_beta)
+    blk_ptr = np.asarray(blk_ptr, np.int64)
+    assert blk_ptr.shape == (nbr * nbc + 1,), "blk_ptr length"
+    blk = np.repeat(np.arange(nbr * nbc, dtype=np.int64), np.diff(blk_ptr))
+    p = np.asarray(packed, np.uint32).astype(np.int64)
+    lr = p >> 16
+    lc = p & 0xFFFF
+    row = (blk // nbc) * (1 << log2_beta) + lr
+    col = (blk % nbc) * (1 << log2_beta) + lc
+    return row, col, np.asarray(val, np.float64), blk, lr, lc
+
+
+def check_csbh(m, n, log2_beta, blk_ptr, packed, val, canon_row, canon_col, canon_val):
+    """Raise AssertionError unless the CSBH arrays hold exactly the canonical triplets, blocks are
+    in row-wise order, and entries inside each block follow the Hilbert order strictly."""
+    blk_ptr = np.asarray(blk_ptr, np.int64)
+    assert blk_ptr[0] == 0 and blk_ptr[-1] == len(packed) == len(val), "blk_ptr ends"
+    assert np.all(np.diff(blk_ptr) >= 0), "blk_ptr not monotone"
+    row, col, v, blk, lr, lc = decode_csbh(m, n, log2_beta, blk_ptr, packed, val)
+    beta = 1 << log2_beta
+    assert np.all(lr < beta) and np.all(lc < beta), "local index >= beta"
+    assert np.all(row < m) and np.all(col < n), "entry outside the matrix"
+    h = hilbert_index_array(log2_beta, lr, lc)
+    same = blk[1:] == blk[:-1]
+    assert np.all(h[1:][same] > h[:-1][same]), "not strictly increasing Hilbert order in a block"
+    # compare as multisets keyed by (row, col); coordinates are unique after summing repeats
+    order = np.lexsort((col, row))
+    assert np.array_equal(row[order], np.asarray(canon_row, np.int64)), "rows"
+    assert np.array_equal(col[order], np.asarray(canon_col, np.int64)), "cols"
+    a = v[order].view(np.int64)
+    b = np.asarray(canon_val, np.float64).view(np.int64)
+    assert np.array_equal(a, b), "values differ bitwise"

@@ -1,0 +1,440 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU)."""
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import curves, formats, measure, mergepath, spmv
+
+
+def _cells(tokens):
+    return [tuple(int(v) for v in t.split(",")) for t in tokens]
+
+
+# ---------------------------------------------------------------- Algorithm 1 and triplets
+
+
+def _dense(m, n, row, col, val):
+    A = np.zeros((m, n))
+    for r, c, v in zip(row, col, val):
+        A[r, c] += v
+    return A
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_alg1_matches_dense_matvec_tiny(seed):
+    rng = np.random.default_rng(seed)
+    m, n = rng.integers(1, 40, size=2)
+    E = int(rng.integers(0, 200))
+    row = rng.integers(0, m, E).astype(np.int32)
+    col = rng.integers(0, n, E).astype(np.int32)
+    val = rng.uniform(-1, 1, E)
+    x = rng.uniform(-1, 1, n)
+    ref = spmv.reference(m, n, row, col, val, x)
+    dense = _dense(m, n, row, col, val) @ x
+    assert np.allclose(ref["y_ref"], dense, rtol=0, atol=1e-13 * (1 + np.abs(dense).max()))
+    assert np.allclose(ref["y_plain"], dense, rtol=0, atol=1e-12 * (1 + np.abs(dense).max()))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_alg1_exact_on_integers(seed):
+    rng = np.random.default_rng(100 + seed)
+    m, n, E = 50, 37, 900
+    row = rng.integers(0, m, E).astype(np.int32)
+    col = rng.integers(0, n, E).astype(np.int32)
+    val = rng.integers(-3, 4, E).astype(np.float64)
+    x = rng.integers(-3, 4, n).astype(np.float64)
+    ref = spmv.reference(m, n, row, col, val, x)
+    exact = np.zeros(m, dtype=object)
+    for r, c, v in zip(row, col, val):
+        exact[r] += int(v) * int(x[c])
+    assert [int(v) for v in ref["y_plain"]] == list(exact)
+    assert measure.equal_ignoring_zero_sign(ref["y_plain"], ref["y_ref"])
+
+
+def test_alg1_special_cases():
+    # identity gives x exactly
+    n = 33
+    x = synth.xvec(n, seed=5)
+    idx = np.arange(n, dtype=np.int32)
+    r = spmv.reference(n, n, idx, idx, np.ones(n), x)
+    assert np.array_equal(r["y_plain"], x) and np.array_equal(r["y_ref"], x)
+    # diagonal
+    d = synth.values(n, seed=6)
+    r = spmv.reference(n, n, idx, idx, d, x)
+    assert np.array_equal(r["y_plain"], d * x)
+    # nnz = 0 and all rows empty: y is +0
+    r = spmv.reference(7, 5, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), np.ones(5))
+    assert np.array_equal(r["y_plain"].view(np.int64), np.zeros(7, np.int64))
+    assert np.array_equal(r["row_ptr"], np.zeros(8, np.int64))
+    # 1 x 1
+    r = spmv.reference(1, 1, np.array([0], np.int32), np.array([0], np.int32), np.array([2.5]),
+                       np.array([-4.0]))
+    assert r["y_plain"][0] == -10.0
+    # m != n, one fully dense row among empty ones
+    m, n = 5, 300
+    row = np.full(n, 3, np.int32)
+    col = np.arange(n, dtype=np.int32)
+    val = np.ones(n)
+    x = np.arange(n, dtype=np.float64)
+    r = spmv.reference(m, n, row, col, val, x)
+    assert list(r["y_plain"]) == [0, 0, 0, n * (n - 1) / 2, 0]
+
+
+def test_negative_zero_products_give_positive_zero():
+    # 0 * (-1) = -0; Algorithm 1 starts each row at +0 so the row's result is +0
+    r = spmv.reference(2, 2, np.array([0, 1], np.int32), np.array([1, 1], np.int32),
+                       np.array([0.0, 1.0]), np.array([1.0, -1.0]))
+    assert r["y_plain"][0] == 0.0 and not np.signbit(r["y_plain"][0])
+    assert not np.signbit(r["y_ref"][0])
+
+
+def test_duplicates_summed_in_original_order():
+    # three repeats of (0, 0); their sum must be ((v0 + v1) + v2) in input order
+    v = np.array([1e16, 1.0, -1e16])
+    r, c, s, _ = spmv.canonical_coo(1, 1, np.zeros(3, np.int32), np.zeros(3, np.int32), v)
+    assert len(s) == 1 and s[0] == (1e16 + 1.0) + -1e16 == 0.0
+    v2 = np.array([1.0, 1e16, -1e16])
+    _, _, s2, _ = spmv.canonical_coo(1, 1, np.zeros(3, np.int32), np.zeros(3, np.int32), v2)
+    assert s2[0] == (1.0 + 1e16) + -1e16
+
+
+def test_canonical_matches_dictionary_accumulation():
+    rng = np.random.default_rng(7)
+    m, n, E = 20, 9, 600
+    row = rng.integers(0, m, E).astype(np.int32)
+    col = rng.integers(0, n, E).astype(np.int32)
+    val = rng.uniform(-1, 1, E)
+    acc = {}
+    for r, c, v in zip(row, col, val):  # input order
+        key = (int(r), int(c))
+        acc[key] = acc[key] + v if key in acc else v
+    keys = sorted(acc)
+    cr, cc, cv, _ = spmv.canonical_coo(m, n, row, col, val)
+    assert list(zip(cr.tolist(), cc.tolist())) == keys
+    assert np.array_equal(cv, np.array([acc[k] for k in keys]))
+
+
+def test_shuffled_input_gives_identical_crs_on_integers():
+    row, col = synth.rmat(10, 8, seed=3)
+    val = synth.values(len(row), seed=3, kind="int")
+    p = synth.permutation(len(row), seed=9)
+    a = spmv.crs(1024, 1024, row, col, val)
+    b = spmv.crs(1024, 1024, row[p], col[p], val[p])
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def test_row_sums_match_triplet_path():
+    # A * 1 equals the row sums computed straight from the raw triplets (exact on integers)
+    row, col = synth.rmat(11, 16, seed=4)
+    val = synth.values(len(row), seed=4, kind="int")
+    m = n = 2048
+    ones = np.ones(n)
+    y = spmv.alg1(*spmv.crs(m, n, row, col, val), ones)
+    sums = np.zeros(m)
+    np.add.at(sums, row, val)
+    assert np.array_equal(y, sums)
+    yt = spmv.triplet_spmv(m, row, col, val, ones)
+    assert np.array_equal(y, yt)
+
+
+def test_permutation_invariance_on_integers():
+    # (P A Q^T)(Q x) = P (A x)
+    m = n = 1024
+    row, col = synth.rmat(10, 16, seed=8)
+    val = synth.values(len(row), seed=8, kind="int")
+    x = synth.xvec(n, seed=8, kind="int")
+    P = synth.permutation(m, seed=11)
+    Q = synth.permutation(n, seed=12)
+    y = spmv.alg1(*spmv.crs(m, n, row, col, val), x)
+    Pinv = np.empty_like(P); Pinv[P] = np.arange(m)
+    Qinv = np.empty_like(Q); Qinv[Q] = np.arange(n)
+    # row i of the new matrix is old row P[i]; column j is old column Q[j]
+    y2 = spmv.alg1(*spmv.crs(m, n, Pinv[row].astype(np.int32), Qinv[col].astype(np.int32), val),
+                   x[Q])
+    assert np.array_equal(y2, y[P])
+
+
+def test_linearity_within_tolerance():
+    m = n = 512
+    row, col = synth.rmat(9, 16, seed=2)
+    val = synth.values(len(row), seed=2)
+    x1 = synth.values(n, seed=21)
+    x2 = synth.values(n, seed=22)
+    rp, c, v = spmv.crs(m, n, row, col, val)
+    _, y1, s1 = spmv.alg1_accurate(rp, c, v, x1)
+    _, y2, s2 = spmv.alg1_accurate(rp, c, v, x2)
+    _, y12, s12 = spmv.alg1_accurate(rp, c, v, 2.0 * x1 - 3.0 * x2)
+    err = np.abs(y12 - (2 * y1 - 3 * y2))
+    assert np.all(err <= 1e-14 * (2 * s1 + 3 * s2 + s12) + 1e-300)
+
+
+def test_accurate_sum_against_exact_rational():
+    rng = np.random.default_rng(5)
+    # one long ill-conditioned row: large cancelling terms plus small ones
+    k = 4000
+    a = np.concatenate([rng.uniform(-1, 1, k) * 1e8, rng.uniform(-1, 1, k)])
+    xs = np.concatenate([np.ones(k), rng.uniform(-1, 1, k)])
+    a = np.concatenate([a, -a[:k]])
+    xs = np.concatenate([xs, np.ones(k)])
+    n = len(a)
+    rp = np.array([0, n], np.int64)
+    col = np.arange(n, dtype=np.int32)
+    yp, yr, s = spmv.alg1_accurate(rp, col, a, xs)
+    exact = sum(Fraction(float(u)) * Fraction(float(v)) for u, v in zip(a, xs))
+    exact_f = float(exact)
+    assert abs(yr[0] - exact_f) <= 2 * 2.0 ** -53 * abs(exact_f) + 1e-300
+    assert s[0] == pytest.approx(float(sum(abs(Fraction(float(u)) * Fraction(float(v)))
+                                           for u, v in zip(a, xs))), rel=1e-12)
+    # the plain sum is far worse here, which is why the reference is the accurate one
+    assert abs(yp[0] - exact_f) > abs(yr[0] - exact_f)
+
+
+def test_accurate_sum_matches_fsum_random():
+    rng = np.random.default_rng(6)
+    for _ in range(20):
+        k = int(rng.integers(1, 3000))
+        a = rng.uniform(-1, 1, k)
+        xs = rng.uniform(-1, 1, k)
+        _, yr, _ = spmv.alg1_accurate(np.array([0, k], np.int64), np.arange(k, dtype=np.int32), a, xs)
+        exact = float(sum(Fraction(float(u)) * Fraction(float(v)) for u, v in zip(a, xs)))
+        assert abs(yr[0] - exact) <= 2.0 ** -52 * abs(exact) + 1e-300
+
+
+def test_rows_reference_matches_full():
+    m = n = 2048
+    row, col = synth.rmat(11, 16, seed=1)
+    val = synth.values(len(row), seed=1)
+    x = synth.xvec(n, seed=1)
+    full = spmv.reference(m, n, row, col, val, x)
+    rows = np.array([0, 1, 5, 100, 2047, 1024])
+    rr, yp, yr, s = spmv.rows_reference(m, n, row, col, val, x, rows)
+    assert np.array_equal(yp, full["y_plain"][rr])
+    assert np.array_equal(yr, full["y_ref"][rr])
+
+
+# ---------------------------------------------------------------- curves
+
+
+def test_hilbert_matches_figure(golden):
+    for size, *cells in golden("hilbert_figure.txt"):
+        k = int(size).bit_length() - 1
+        assert curves.hilbert_order(k) == _cells(cells)
+
+
+def test_zmorton_matches_figure(golden):
+    for size, *cells in golden("zmorton_figure.txt"):
+        k = int(size).bit_length() - 1
+        assert curves.zmorton_order(k) == _cells(cells)
+
+
+@pytest.mark.parametrize("k", range(0, 8))
+def test_hilbert_bijective_unit_steps(k):
+    side = 1 << k
+    order = curves.hilbert_order(k)
+    assert len(set(order)) == side * side
+    for (r0, c0), (r1, c1) in zip(order, order[1:]):
+        assert abs(r0 - r1) + abs(c0 - c1) == 1  # one index changes, by one (Section 4.1)
+
+
+@pytest.mark.parametrize("k", [9, 10, 13])
+def test_hilbert_array_bijective_large(k):
+    side = 1 << k
+    rng = np.random.default_rng(k)
+    if k <= 10:
+        r, c = np.divmod(np.arange(side * side, dtype=np.int64), side)
+        d = curves.hilbert_index_array(k, r, c)
+        assert np.array_equal(np.sort(d), np.arange(side * side))
+    else:
+        r = rng.integers(0, side, 2000)
+        c = rng.integers(0, side, 2000)
+        d = curves.hilbert_index_array(k, r, c)
+        assert np.all((d >= 0) & (d < side * side))
+    r = rng.integers(0, side, 500)
+    c = rng.integers(0, side, 500)
+    d = curves.hilbert_index_array(k, r, c)
+    assert [curves.hilbert_index(k, a, b) for a, b in zip(r, c)] == d.tolist()
+
+
+def test_hilbert_unit_steps_k10_vectorised():
+    # every consecutive pair of the 1024 x 1024 curve differs by one in exactly one index
+    k = 10
+    side = 1 << k
+    r, c = np.divmod(np.arange(side * side, dtype=np.int64), side)
+    d = curves.hilbert_index_array(k, r, c)
+    order = np.argsort(d)
+    rr, cc = r[order], c[order]
+    steps = np.abs(np.diff(rr)) + np.abs(np.diff(cc))
+    assert np.all(steps == 1)
+    assert rr[0] == 0 and cc[0] == 0
+
+
+# ---------------------------------------------------------------- merge path
+
+
+def test_merge_path_matches_figure(golden):
+    g = {row[0]: row[1:] for row in golden("merge_path_figure.txt")}
+    A = [int(v) for v in g["A"]]
+    B = [int(v) for v in g["B"]]
+    p = int(g["threads"][0])
+    path, merged = mergepath.walk(A, B)
+    assert path == _cells(g["path"])
+    assert ["%s%d" % (s, v) for s, v in merged] == g["merged"]
+    items = (len(A) + len(B)) // p
+    assert mergepath.splits(A, B, items) == _cells(g["splits"])
+    for i, j in path:
+        assert mergepath.is_path_point(A, B, i, j)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_merge_walk_equals_stable_merge(seed):
+    rng = np.random.default_rng(seed)
+    A = sorted(rng.integers(0, 20, int(rng.integers(0, 30))).tolist())
+    B = sorted(rng.integers(0, 20, int(rng.integers(0, 30))).tolist())
+    _, merged = mergepath.walk(A, B)
+    # reference: sort tagged items by (value, list) with A before B on ties, stable within lists
+    tagged = sorted([(v, 0, i) for i, v in enumerate(A)] + [(v, 1, i) for i, v in enumerate(B)])
+    assert [("A" if t == 0 else "B", v) for v, t, _ in tagged] == merged
+    path, _ = mergepath.walk(A, B)
+    on = {(i, j) for i, j in path}
+    for i in range(len(A) + 1):
+        for j in range(len(B) + 1):
+            assert mergepath.is_path_point(A, B, i, j) == ((i, j) in on)
+
+
+def test_merge_spmv_bands_equals_alg1_on_integers():
+    m = n = 256
+    row, col = synth.rmat(8, 16, seed=6)
+    val = synth.values(len(row), seed=6, kind="int")
+    x = synth.xvec(n, seed=6, kind="int")
+    rp, c, v = spmv.crs(m, n, row, col, val)
+    y = spmv.alg1(rp, c, v, x)
+    for items in (1, 3, 7, 64, 1000, 10 ** 6):
+        yb, carries = mergepath.spmv_bands(rp, c, v, x, items)
+        assert np.array_equal(yb, y)
+
+
+def test_merge_spmv_long_row_spans_bands():
+    # one row of 50 entries split over bands of 8 items must carry across 6+ bands
+    n = 50
+    rp = np.array([0, 0, n, n], np.int64)
+    col = np.arange(n, dtype=np.int32)
+    v = np.ones(n)
+    x = np.arange(n, dtype=np.float64)
+    yb, carries = mergepath.spmv_bands(rp, col, v, x, 8)
+    assert list(yb) == [0.0, n * (n - 1) / 2, 0.0]
+    assert sum(1 for r, _ in carries if r == 1) >= 6
+
+
+# ---------------------------------------------------------------- block size, break-even
+
+
+def test_csb_block_size_range():
+    assert measure.csb_log2_beta_range(1 << 14) == (7, 10)
+    assert measure.csb_log2_beta_range(1 << 24) == (12, 15)
+    assert measure.csb_log2_beta_range(10 ** 7) == (12, 15)
+    assert measure.csb_log2_beta_range(1) == (0, 3)
+    # 4^t >= n boundary
+    assert measure.ceil_log2_sqrt(17) == 3 and measure.ceil_log2_sqrt(16) == 2
+
+
+def test_csb_block_size_rule():
+    assert measure.csb_log2_beta(1 << 14, 1 << 14) == 10
+    assert measure.csb_log2_beta(1 << 24, 1 << 24) == 13  # budget of 64 KiB of doubles
+    assert measure.csb_log2_beta(10 ** 7, 10 ** 7) == 13
+    # without an on-chip budget the paper's 16-bit cap applies: n = 2^30 -> range (15, 18) -> 16
+    assert measure.csb_log2_beta(1 << 30, 1 << 30, lds_bytes=1 << 40) == 16
+    assert measure.csb_log2_beta(1 << 24, 1 << 24, lds_bytes=1 << 40) == 15
+
+
+def test_break_even_reproduces_paper(golden):
+    for fmt, mach, dens, s_crs, s_fmt, c_crs, c_fmt, pub in golden("break_even_tables.txt"):
+        nstar = measure.break_even_from_ratios(float(c_fmt), float(c_crs), float(s_crs),
+                                               float(s_fmt))
+        # tables are rounded to one decimal, so the count is recovered to within ~1%
+        assert abs(nstar - float(pub)) <= 0.01 * float(pub) + 0.5, (fmt, nstar, pub)
+    assert round(measure.break_even_from_ratios(10.9, 7.8, 2.9, 3.3)) == 26
+    assert round(measure.break_even_from_ratios(69.6, 7.8, 2.9, 3.4)) == 420
+    assert measure.break_even(5.0, 1.0, 1.0, 1.0) == math.inf
+    assert measure.break_even(3.0, 1.0, 2.0, 1.0) == 2.0
+
+
+def test_scaled_error_metric():
+    e = measure.scaled_error([1.0, 0.0, -0.0, 1e-3], [1.0 + 1e-15, 0.0, 0.0, 0.0], [1.0, 0.0, 0.0, 0.0])
+    assert e[0] == pytest.approx(1e-15, rel=1e-3) and e[1] == 0 and e[2] == 0 and e[3] == np.inf
+    assert measure.equal_ignoring_zero_sign([0.0, -0.0, 1.0], [-0.0, 0.0, 1.0])
+    assert not measure.equal_ignoring_zero_sign([1.0], [np.nextafter(1.0, 2.0)])
+
+
+# ---------------------------------------------------------------- format decoders
+
+
+def test_check_crs_hand_made():
+    # 3x4: row 0 = {(0,1)=2}, row 1 empty, row 2 = {(2,0)=-1, (2,3)=5}
+    rp = [0, 1, 1, 3]
+    formats.check_crs(3, 4, rp, [1, 0, 3], [2.0, -1.0, 5.0], [0, 2, 2], [1, 0, 3], [2.0, -1.0, 5.0])
+    with pytest.raises(AssertionError):
+        formats.check_crs(3, 4, rp, [1, 3, 0], [2.0, 5.0, -1.0], [0, 2, 2], [1, 0, 3],
+                          [2.0, -1.0, 5.0])
+    with pytest.raises(AssertionError):
+        formats.check_crs(3, 4, [0, 2, 2, 3], [1, 0, 3], [2.0, -1.0, 5.0], [0, 2, 2], [1, 0, 3],
+                          [2.0, -1.0, 5.0])
+
+
+def test_check_csbh_hand_made():
+    # 4x4 matrix, beta = 2 (k=1): blocks (0,0),(0,1),(1,0),(1,1)
+    # entries: (0,0)=1, (1,0)=2, (0,1)=3 in block 0; (3,3)=4 in block 3
+    # Hilbert order of 2x2 local cells: (0,0),(1,0),(1,1),(0,1)
+    blk_ptr = [0, 3, 3, 3, 4]
+    packed = [(0 << 16) | 0, (1 << 16) | 0, (0 << 16) | 1, (1 << 16) | 1]
+    val = [1.0, 2.0, 3.0, 4.0]
+    formats.check_csbh(4, 4, 1, blk_ptr, packed, val, [0, 0, 1, 3], [0, 1, 0, 3],
+                       [1.0, 3.0, 2.0, 4.0])
+    with pytest.raises(AssertionError):  # row-major instead of Hilbert inside block 0
+        formats.check_csbh(4, 4, 1, blk_ptr, [0, 1, 1 << 16, (1 << 16) | 1], [1.0, 3.0, 2.0, 4.0],
+                           [0, 0, 1, 3], [0, 1, 0, 3], [1.0, 3.0, 2.0, 4.0])
+
+
+# ---------------------------------------------------------------- generators (parity unpinned)
+
+
+def test_rmat_s14_statistics():
+    row, col = synth.rmat(14, 16, seed=0)
+    assert len(row) == 262144
+    key = row.astype(np.int64) * 16384 + col
+    u = np.unique(key)
+    assert 0.85 < len(u) / len(row) < 0.89
+    counts = np.bincount(u // 16384, minlength=16384)
+    assert 0.30 < np.mean(counts == 0) < 0.36
+    # first-level quadrant frequencies within 5 sigma of (a, b, c, d)
+    top_r = row >> 13
+    top_c = col >> 13
+    E = len(row)
+    for (qr, qc), p in {(0, 0): .57, (0, 1): .19, (1, 0): .19, (1, 1): .05}.items():
+        f = np.sum((top_r == qr) & (top_c == qc))
+        assert abs(f - p * E) < 5 * math.sqrt(E * p * (1 - p))
+
+
+def test_chunglu_small_statistics():
+    n, E = 100_000, 2_000_000
+    row, col = synth.chunglu(n, E, 2.1, seed=0)
+    assert row.min() >= 0 and row.max() < n and col.min() >= 0 and col.max() < n
+    w = np.arange(1, n + 1, dtype=np.float64) ** (-1 / 1.1)
+    p0 = w[0] / w.sum()
+    f0 = np.mean(row == 0)
+    assert abs(f0 - p0) < 5 * math.sqrt(p0 * (1 - p0) / E)
+
+
+def test_generators_deterministic():
+    a = synth.rmat(10, 4, seed=3)
+    b = synth.rmat(10, 4, seed=3)
+    assert all(np.array_equal(u, v) for u, v in zip(a, b))
+    assert not np.array_equal(synth.rmat(10, 4, seed=4)[0], a[0])
+    v = synth.values(1000, seed=1, kind="int")
+    assert set(np.unique(v).tolist()) <= set(range(-3, 4))
+    f = synth.values(100000, seed=1)
+    assert f.min() >= -1 and f.max() < 1 and abs(f.mean()) < 0.02
