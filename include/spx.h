@@ -1,0 +1,181 @@
+/*
+ * spx.h -- C ABI of libspx, sparse matrix-vector multiplication y = A x on AMD MI355X (gfx950).
+ *
+ * The operations follow the problem statement of Bergmans, Meerbergen and Vandebril, "Algorithms
+ * for Parallel Shared-Memory Sparse Matrix-Vector Multiplication on Unstructured Matrices"
+ * (arXiv 2502.19284):
+ *   - A is an m x n sparse matrix with nnz stored entries, x and y are dense, y = A x (Section 1);
+ *   - A arrives in the triplet (coordinate) format: row_ind, col_ind, data (Section 2);
+ *   - before any product the triplets are converted to the format an algorithm needs, and the
+ *     conversion cost is measured and reported beside the product (Sections 5.1 and 6.2).
+ *
+ * Conventions of every entry point
+ *   - Pointers named "device" must point to memory of the current HIP device; host pointers are
+ *     marked "host".  Nothing here takes ownership of caller memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.  All device work
+ *     is enqueued on it.
+ *   - Return value: SPX_OK (0) or a negative spx_status.  No C++ exception crosses the ABI.
+ *     Argument errors are reported before any device work is enqueued.  A thread-local message
+ *     with details is available from spx_last_error_message().
+ *   - Indices are 0-based int32.  Values and vectors are IEEE binary64 unless stated otherwise.
+ */
+#ifndef SPX_H
+#define SPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+typedef int32_t spx_status;
+#define SPX_OK 0
+#define SPX_ERR_INVALID_ARG -1 /* null pointer, negative size, unknown enum value        */
+#define SPX_ERR_INDEX -2       /* a triplet index outside [0,m) x [0,n)                   */
+#define SPX_ERR_RANGE -3       /* a size beyond the int32 index range (nnz >= 2^31 ...)   */
+#define SPX_ERR_ALIAS -4       /* x and y overlap                                          */
+#define SPX_ERR_NOMEM -5       /* device allocation failed                                 */
+#define SPX_ERR_HIP -6         /* a HIP runtime call failed                                */
+#define SPX_ERR_UNSUPPORTED -7 /* valid request that this build does not implement         */
+
+/* ------------------------------------------------------------------ enums */
+typedef int32_t spx_format;
+/* CRS (Section 2) with rows split among workgroups: short rows are grouped into row blocks of
+ * bounded size, rows longer than a threshold are split into chunks whose partial sums are added
+ * in chunk order.  Row-parallel like the paper's ParCRS baseline (Section 5.1). */
+#define SPX_CSR_ROWSPLIT 0
+/* CRS processed by merge-path bands of equal length over (row ends, entries) (Section 3.3). */
+#define SPX_CSR_MERGE 1
+/* Compressed sparse blocks with Hilbert order inside each block, CSBH (Sections 3.1 and 4.1). */
+#define SPX_CSB_HILBERT 2
+
+typedef int32_t spx_dtype;
+#define SPX_F64 0
+
+/* ------------------------------------------------------------------ inputs */
+/* Triplet format (Section 2): entry i is (row[i], col[i], val[i]).  Entries may come in any order
+ * and may repeat a coordinate; repeats are summed in increasing i by default.  Explicit zeros are
+ * kept as stored entries. */
+typedef struct {
+    int32_t m;          /* rows,    >= 0                                   */
+    int32_t n;          /* columns, >= 0                                   */
+    int64_t nnz;        /* number of triplets, 0 <= nnz < 2^31             */
+    const int32_t* row; /* device, nnz entries (may be NULL when nnz == 0) */
+    const int32_t* col; /* device, nnz entries                             */
+    const void* val;    /* device, nnz values of type val_type             */
+    spx_dtype val_type; /* SPX_F64                                         */
+} spx_coo_desc;
+
+typedef struct {
+    int32_t sum_duplicates; /* 1: sum repeated coordinates (default); 0: keep each as an entry  */
+    int32_t log2_beta;      /* CSBH block side 2^log2_beta; 0 = block-size rule (Section 3.1)  */
+    int32_t validate;       /* 1: check every index on the device (default); 0: trust input    */
+    int32_t tile_items;     /* work per tile/unit; 0 = default for the format                  */
+} spx_convert_opts;
+
+typedef struct {
+    float convert_ms;  /* device time of the whole conversion, events on `stream`      */
+    int64_t nnz_out;   /* stored entries after repeats were summed                      */
+    int64_t bytes;     /* device bytes held by the handle                               */
+    int32_t log2_beta; /* CSBH block side used (0 for CRS formats)                      */
+    int32_t parts;     /* work units of the format (tiles, row blocks, block-row chunks)*/
+} spx_convert_report;
+
+typedef struct spx_matrix_s* spx_matrix;
+
+typedef struct {
+    int32_t m, n;
+    int64_t nnz;       /* stored entries                        */
+    spx_format format;
+    int32_t log2_beta; /* CSBH only                             */
+    int64_t bytes;     /* device bytes held by the handle       */
+    int64_t parts;     /* work units                            */
+    spx_dtype value_type;
+} spx_matrix_info;
+
+/* Arrays of a converted matrix that spx_matrix_export can copy out. */
+typedef int32_t spx_array;
+#define SPX_ARRAY_ROW_PTR 0 /* CRS formats: int32[m+1]                                      */
+#define SPX_ARRAY_COL_IND 1 /* CRS formats: int32[nnz], ascending inside a row              */
+#define SPX_ARRAY_VALUES 2  /* all formats: float64[nnz] in storage order                   */
+#define SPX_ARRAY_BLK_PTR 3 /* CSBH: int32[nbr*nbc+1], blocks in row-wise order             */
+#define SPX_ARRAY_PACKED 4  /* CSBH: uint32[nnz], (local_row << 16) | local_col, Hilbert order */
+#define SPX_ARRAY_PARTS 5   /* format's work-unit table, int32 (layout is internal)          */
+
+/* Optional device allocator: alloc returns NULL on failure; free accepts what alloc returned. */
+typedef void* (*spx_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*spx_free_fn)(void* ptr, void* stream, void* ctx);
+
+/* ------------------------------------------------------------------ entry points */
+
+/* Fill *opts with the defaults: sum_duplicates=1, log2_beta=0, validate=1, tile_items=0. */
+spx_status spx_convert_opts_default(spx_convert_opts* opts);
+
+/*
+ * Convert triplets to `fmt` (Section 5.1: sort the entries into the format's order, then fill and
+ * compress the arrays).  The sort is a stable device radix sort on the format's key:
+ *   CRS:  (row, col);
+ *   CSBH: (block row, block column, Hilbert index of the local (row, col) in the block).
+ * Repeated coordinates become one entry whose value is the sum in increasing triplet index.
+ * The work-unit table the product uses is built here as well, and counted in the conversion.
+ *
+ * coo:  host pointer to the descriptor; its arrays are device memory owned by the caller and
+ *       only read.
+ * opts: host, may be NULL for defaults.
+ * out:  host; receives a new handle on success, NULL on any error.
+ * rep:  host, may be NULL.  convert_ms covers all device work of the call.
+ * The call returns after the device work is complete (it reads back the entry count).
+ * Errors: INVALID_ARG, RANGE (m, n or nnz beyond int32, or a CSBH key beyond 64 bits), INDEX
+ * (validate=1 and an index out of range), NOMEM, HIP.  On error every temporary is freed.
+ */
+spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt, const spx_convert_opts* opts,
+                       void* stream, spx_matrix* out, spx_convert_report* rep);
+
+/*
+ * y = A x (Algorithm 1's result; y is overwritten, rows without entries give +0).
+ * x: device, n doubles.  y: device, m doubles.  x and y must not overlap (SPX_ERR_ALIAS).
+ * Asynchronous on `stream`.  A handle holds per-product scratch, so at most one product per
+ * handle may be in flight at a time; products on different handles may overlap freely.
+ */
+spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* stream);
+
+/* Sizes and format of a handle.  info: host. */
+spx_status spx_matrix_get_info(spx_matrix A, spx_matrix_info* info);
+
+/*
+ * Copy one array of the handle into caller memory `dst` (device, `bytes` long) on `stream`,
+ * asynchronously.  Errors: INVALID_ARG when the array does not exist for the format or when
+ * `bytes` is smaller than the array (the required size is written to *needed if not NULL).
+ */
+spx_status spx_matrix_export(spx_matrix A, spx_array which, void* dst, int64_t bytes,
+                             int64_t* needed, void* stream);
+
+/* Wait for the handle's device work, then free everything it holds.  NULL is accepted. */
+spx_status spx_matrix_destroy(spx_matrix A);
+
+/*
+ * Number of products after which `fmt` pays for its longer conversion against the reference CRS
+ * path: the N where conv_fmt + N * spmv_fmt = conv_ref + N * spmv_ref (Section 7 reports such
+ * counts).  Returns +infinity when spmv_fmt >= spmv_ref.  Times in any one unit.
+ */
+double spx_break_even(double conv_fmt, double conv_ref, double spmv_ref, double spmv_fmt);
+
+/* Route the library's device allocations through caller functions (both NULL = hipMalloc and
+ * hipFree).  Affects allocations made after the call; not thread-safe against running calls. */
+spx_status spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free_fn, void* ctx);
+
+/* Static text for a status code. */
+const char* spx_status_string(spx_status s);
+
+/* Details of the last error on the calling thread ("" when none). */
+const char* spx_last_error_message(void);
+
+/* Library version as "major.minor.patch". */
+const char* spx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPX_H */

@@ -1,0 +1,9 @@
+"""spx -- sparse matrix-vector multiplication y = A x on AMD MI355X (gfx950).
+
+A from-scratch HIP implementation of the formats and load-balancing strategies studied by
+Bergmans, Meerbergen and Vandebril (arXiv 2502.19284): row-split CRS, merge-path CRS and
+compressed sparse blocks in Hilbert order (CSBH), with conversion from triplets by device radix
+sort.  The C ABI is include/spx.h; this package is its thin Python binding.
+"""
+from .spx import (ARRAYS, FORMATS, LIB_PATH, Matrix, SpxError, break_even, convert,  # noqa: F401
+                  header_functions, load, use_torch_allocator, version)

@@ -1,0 +1,439 @@
+// k_convert.hip -- triplet -> format conversion kernels (gfx950).
+//
+// The conversion follows the two steps of Section 5.1: (1) sort the entries into the order the
+// format needs, (2) fill and compress the format's arrays.  Step 1 is a stable LSD radix sort of
+// a 64-bit key with the original triplet index as payload; step 2 sums repeated coordinates in
+// increasing triplet index, gathers values, and turns per-row (per-block) end marks into
+// row_ptr (blk_ptr) with a max-scan.
+#include "dev_scan.h"
+#include "spx_internal.h"
+
+// ------------------------------------------------------------------ small utilities
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static unsigned grid_for(int64_t n, int nt, unsigned cap = 1u << 20) {
+    int64_t g = (n + nt - 1) / nt;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+__global__ void k_init_readback(Readback* rb) {
+    rb->err = 0;
+    rb->pad = 0;
+    rb->masks[0] = 0ull;
+    rb->masks[1] = ~0ull;
+    for (int i = 0; i < 4; ++i) rb->totals[i] = 0;
+}
+
+hipError_t launch_init_readback(Readback* rb, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_readback, dim3(1), dim3(1), 0, s, rb);
+    return hipGetLastError();
+}
+
+size_t scan_tile_count(int64_t n) { return n <= 0 ? 1 : (size_t)spx_div_up(n, SCAN_TILE); }
+
+// ------------------------------------------------------------------ sort keys
+
+// Hilbert index of local cell (row y, column x) in a 2^k x 2^k block: the classical
+// quadrant-by-quadrant descent (quadrant order q = 0..3 is (x<h,y<h), (x<h,y>=h), (x>=h,y>=h),
+// (x>=h,y<h); entering quadrants 0 and 3 transposes / anti-transposes the remaining bits).
+__device__ __forceinline__ uint32_t hilbert_xy2d(int k, uint32_t x, uint32_t y) {
+    uint32_t d = 0;
+    for (int l = k - 1; l >= 0; --l) {
+        const uint32_t h = 1u << l;
+        const uint32_t rx = (x >> l) & 1u, ry = (y >> l) & 1u;
+        d += h * h * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {  // reflect the low bits through the anti-diagonal
+                x = (h - 1) - (x & (h - 1));
+                y = (h - 1) - (y & (h - 1));
+            }
+            const uint32_t t = x;
+            x = y;
+            y = t;
+        }
+    }
+    return d;
+}
+
+// Inverse of hilbert_xy2d: local (x = column, y = row) of index d, built up from the finest
+// level, undoing each level's transform.
+__device__ __forceinline__ void hilbert_d2xy(int k, uint32_t d, uint32_t* px, uint32_t* py) {
+    uint32_t x = 0, y = 0, t = d;
+    for (int l = 0; l < k; ++l) {
+        const uint32_t h = 1u << l;
+        const uint32_t rx = 1u & (t >> 1);
+        const uint32_t ry = 1u & (t ^ rx);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = (h - 1) - x;
+                y = (h - 1) - y;
+            }
+            const uint32_t tmp = x;
+            x = y;
+            y = tmp;
+        }
+        x += h * rx;
+        y += h * ry;
+        t >>= 2;
+    }
+    *px = x;
+    *py = y;
+}
+
+template <typename KeyFn>
+__device__ __forceinline__ void keys_body(const int32_t* __restrict__ row,
+                                          const int32_t* __restrict__ col, int64_t E, int32_t m,
+                                          int32_t n, uint64_t* __restrict__ keys, uint32_t* err,
+                                          unsigned long long* masks, KeyFn fn) {
+    unsigned long long orv = 0, andv = ~0ull;
+    uint32_t bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = row[i], c = col[i];
+        const bool ok = (r >= 0) & (r < m) & (c >= 0) & (c < n);
+        bad |= ok ? 0u : 1u;
+        const uint64_t key = ok ? fn((uint32_t)r, (uint32_t)c) : 0ull;
+        keys[i] = key;
+        orv |= key;
+        andv &= key;
+    }
+    orv = wave_reduce<unsigned long long, OpOr<unsigned long long>>(orv);
+    andv = wave_reduce<unsigned long long, OpAnd<unsigned long long>>(andv);
+    const uint64_t anybad = __ballot(bad != 0);
+    if (__lane_id() == 0) {
+        atomicOr(&masks[0], orv);
+        atomicAnd(&masks[1], andv);
+        if (anybad) atomicOr(err, 1u);
+    }
+}
+
+struct KeyCsr {
+    int cbits;
+    __device__ uint64_t operator()(uint32_t r, uint32_t c) const {
+        return ((uint64_t)r << cbits) | (uint64_t)c;
+    }
+};
+
+struct KeyCsbh {
+    int k;
+    uint64_t nbc;
+    __device__ uint64_t operator()(uint32_t r, uint32_t c) const {
+        const uint32_t mask = (1u << k) - 1u;
+        const uint64_t blk = (uint64_t)(r >> k) * nbc + (uint64_t)(c >> k);
+        return (blk << (2 * k)) | (uint64_t)hilbert_xy2d(k, c & mask, r & mask);
+    }
+};
+
+template <typename KeyFn>
+__global__ __launch_bounds__(256) void k_keys(const int32_t* row, const int32_t* col, int64_t E,
+                                              int32_t m, int32_t n, uint64_t* keys, uint32_t* err,
+                                              unsigned long long* masks, KeyFn fn) {
+    keys_body(row, col, E, m, n, keys, err, masks, fn);
+}
+
+hipError_t launch_keys_csr(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+                           int32_t n, int cbits, uint64_t* keys, uint32_t* err,
+                           unsigned long long* masks, hipStream_t s) {
+    hipLaunchKernelGGL((k_keys<KeyCsr>), dim3(grid_for(E, 256, 1u << 16)), dim3(256), 0, s, row,
+                       col, E, m, n, keys, err, masks, KeyCsr{cbits});
+    return hipGetLastError();
+}
+
+hipError_t launch_keys_csbh(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+                            int32_t n, int k, int64_t nbc, uint64_t* keys, uint32_t* err,
+                            unsigned long long* masks, hipStream_t s) {
+    hipLaunchKernelGGL((k_keys<KeyCsbh>), dim3(grid_for(E, 256, 1u << 16)), dim3(256), 0, s,
+                       row, col, E, m, n, keys, err, masks, KeyCsbh{k, (uint64_t)nbc});
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ radix sort
+//
+// One pass per 8-bit digit (least significant first):
+//   upsweep   : per-tile digit histogram, stored digit-major: hist[d * tiles + t]
+//   scan      : exclusive scan of hist gives each (digit, tile) its first output slot
+//   downsweep : each tile ranks its keys stably (original order within equal digits), reorders
+//               them in LDS by digit, and writes each digit's run contiguously.
+// Stable ranking: wave w of the tile takes keys [w*1024, (w+1)*1024) of the tile in 16 rounds of
+// 64 consecutive keys; lanes holding the same digit find each other with 8 ballots (one per
+// digit bit) and rank by lower-lane count; a per-wave LDS counter per digit carries the running
+// count across rounds.  Wave offsets are then added per digit in wave order.
+
+#define RSORT_WAVES (RSORT_NT / SPX_WAVE)
+#define RSORT_ROUNDS (RSORT_TILE / RSORT_WAVES / SPX_WAVE)
+
+size_t radix_hist_elems(int64_t E) { return (size_t)256 * spx_div_up(E, RSORT_TILE); }
+
+__global__ __launch_bounds__(RSORT_NT) void k_rsort_upsweep(const uint64_t* __restrict__ keys,
+                                                            int64_t E, int shift,
+                                                            uint32_t* __restrict__ hist,
+                                                            int64_t tiles) {
+    __shared__ uint32_t cnt[RSORT_WAVES][256];
+    for (int i = threadIdx.x; i < RSORT_WAVES * 256; i += RSORT_NT) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int w = threadIdx.x / SPX_WAVE;
+    const int64_t base = (int64_t)blockIdx.x * RSORT_TILE;
+#pragma unroll
+    for (int i = 0; i < RSORT_IPT; ++i) {
+        const int64_t idx = base + i * RSORT_NT + threadIdx.x;
+        if (idx < E) atomicAdd(&cnt[w][(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    uint32_t c = 0;
+#pragma unroll
+    for (int ww = 0; ww < RSORT_WAVES; ++ww) c += cnt[ww][threadIdx.x];
+    hist[(int64_t)threadIdx.x * tiles + blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(RSORT_NT) void k_rsort_downsweep(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t E, int shift,
+    const uint32_t* __restrict__ hist, int64_t tiles) {
+    __shared__ uint32_t wcnt[RSORT_WAVES][256];
+    __shared__ uint32_t dstart[256];
+    __shared__ uint32_t goff[256];
+    __shared__ uint32_t stmp[RSORT_WAVES];
+    __shared__ uint64_t skey[RSORT_TILE];
+    __shared__ uint32_t sval[RSORT_TILE];
+
+    const int tid = threadIdx.x;
+    const int w = tid / SPX_WAVE;
+    const int lane = __lane_id();
+    for (int i = tid; i < RSORT_WAVES * 256; i += RSORT_NT) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+
+    const int64_t tile_base = (int64_t)blockIdx.x * RSORT_TILE;
+    const int64_t wave_base = tile_base + (int64_t)w * (RSORT_TILE / RSORT_WAVES);
+    const uint64_t lt = spx_lanemask_lt();
+    uint64_t key[RSORT_ROUNDS];
+    uint32_t val[RSORT_ROUNDS];
+    uint32_t rank[RSORT_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < RSORT_ROUNDS; ++r) {
+        const int64_t idx = wave_base + r * SPX_WAVE + lane;
+        const bool valid = idx < E;
+        key[r] = valid ? kin[idx] : 0ull;
+        val[r] = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
+        const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < RS_RADIX_BITS; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const uint32_t below = (uint32_t)__popcll(peers & lt);
+        const uint32_t count = (uint32_t)__popcll(peers);
+        const uint32_t basec = wcnt[w][d];
+        __builtin_amdgcn_wave_barrier();
+        if (valid && below == 0) wcnt[w][d] = basec + count;
+        __builtin_amdgcn_wave_barrier();
+        rank[r] = basec + below;
+    }
+    __syncthreads();
+    // per digit: exclusive offsets of the waves, then the tile's exclusive digit starts
+    uint32_t run = 0;
+#pragma unroll
+    for (int ww = 0; ww < RSORT_WAVES; ++ww) {
+        const uint32_t t = wcnt[ww][tid];
+        wcnt[ww][tid] = run;
+        run += t;
+    }
+    uint32_t tile_total;
+    const uint32_t ex = block_excl_scan<RSORT_NT, uint32_t, OpSum<uint32_t>>(run, stmp, &tile_total);
+    dstart[tid] = ex;
+    goff[tid] = hist[(int64_t)tid * tiles + blockIdx.x];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RSORT_ROUNDS; ++r) {
+        const int64_t idx = wave_base + r * SPX_WAVE + lane;
+        if (idx < E) {
+            const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+            const uint32_t lp = dstart[d] + wcnt[w][d] + rank[r];
+            skey[lp] = key[r];
+            sval[lp] = val[r];
+        }
+    }
+    __syncthreads();
+    const int64_t rem = E - tile_base;
+    const int cnt = rem < RSORT_TILE ? (int)rem : RSORT_TILE;
+    for (int i = tid; i < cnt; i += RSORT_NT) {
+        const uint64_t k = skey[i];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const int64_t dst = (int64_t)goff[d] + (i - (int)dstart[d]);
+        kout[dst] = k;
+        vout[dst] = sval[i];
+    }
+}
+
+__global__ void k_iota_u32(uint32_t* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (uint32_t)i;
+}
+
+struct LoadU32 {
+    const uint32_t* p;
+    __device__ uint32_t operator()(int64_t i) const { return p[i]; }
+};
+struct StoreExclU32 {
+    uint32_t* p;
+    __device__ void operator()(int64_t i, uint32_t incl, uint32_t item) const { p[i] = incl - item; }
+};
+
+hipError_t radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t E,
+                            uint64_t vary, uint32_t* hist, uint32_t* tile_sums, hipStream_t s,
+                            bool* in_second) {
+    *in_second = false;
+    if (E <= 0) return hipSuccess;
+    const int64_t tiles = spx_div_up(E, RSORT_TILE);
+    const int64_t hn = 256 * tiles;
+    uint64_t* kin = k0;
+    uint64_t* kout = k1;
+    uint32_t* vin = nullptr;  // first executed pass reads the implicit identity payload
+    uint32_t* vout = v1;
+    uint32_t* vother = v0;
+    bool second = false;
+    for (int shift = 0; shift < 64; shift += RS_RADIX_BITS) {
+        if (((vary >> shift) & 0xFFull) == 0) continue;
+        hipLaunchKernelGGL(k_rsort_upsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0, s, kin, E,
+                           shift, hist, tiles);
+        hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32{hist}, hn, tile_sums,
+                                                               (uint32_t*)nullptr, s);
+        if (e != hipSuccess) return e;
+        e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32{hist}, StoreExclU32{hist}, hn,
+                                                   tile_sums, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_rsort_downsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0, s, kin,
+                           vin, kout, vout, E, shift, hist, tiles);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // swap roles
+        uint64_t* kt = kin;
+        kin = kout;
+        kout = kt;
+        uint32_t* vt = vout;
+        vin = vt;
+        vout = vother;
+        vother = vt;
+        second = !second;
+    }
+    if (vin == nullptr) {  // no pass ran: keys already in order, payload is the identity
+        hipLaunchKernelGGL(k_iota_u32, dim3(grid_for(E, 256)), dim3(256), 0, s, v0, E);
+        second = false;
+    }
+    *in_second = second;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ repeats, gather, offsets
+
+struct LoadHead {
+    const uint64_t* keys;
+    __device__ uint32_t operator()(int64_t i) const {
+        return (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+    }
+};
+struct StoreHeadPos {
+    int32_t* head_pos;
+    __device__ void operator()(int64_t i, uint32_t incl, uint32_t item) const {
+        if (item) head_pos[incl - 1] = (int32_t)i;
+    }
+};
+
+hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_sums,
+                              uint32_t* total, hipStream_t s) {
+    return scan_phase12<uint32_t, OpSum<uint32_t>>(LoadHead{keys}, E, tile_sums, total, s);
+}
+
+hipError_t launch_dedup_heads(const uint64_t* keys, int64_t E, const uint32_t* tile_sums,
+                              int32_t* head_pos, hipStream_t s) {
+    return scan_phase3<uint32_t, OpSum<uint32_t>>(LoadHead{keys}, StoreHeadPos{head_pos}, E,
+                                                  tile_sums, s);
+}
+
+// Output entry u covers sorted positions [s, e): s = head_pos[u] (or u without summing), e the
+// next head (or E).  Its value is val[perm[s]] + val[perm[s+1]] + ... in increasing position,
+// which is increasing triplet index because the sort is stable.  The last entry of each row
+// (block) writes u+1 at its row (block), for the max-scan that follows.
+template <bool CSBH>
+__global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ keys,
+                                                const uint32_t* __restrict__ perm,
+                                                const double* __restrict__ val_in,
+                                                const int32_t* __restrict__ head_pos, int64_t E,
+                                                int64_t nnz_out, int shiftbits,
+                                                int32_t* __restrict__ idx_out,
+                                                double* __restrict__ val_out,
+                                                int32_t* __restrict__ ends) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < nnz_out;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = head_pos ? head_pos[u] : u;
+        const int64_t e = head_pos ? (u + 1 < nnz_out ? (int64_t)head_pos[u + 1] : E) : u + 1;
+        const uint64_t key = keys[s];
+        double acc = val_in[perm[s]];
+        for (int64_t j = s + 1; j < e; ++j) acc = acc + val_in[perm[j]];
+        val_out[u] = acc;
+        const uint64_t major = key >> shiftbits;
+        if (CSBH) {
+            const int k = shiftbits >> 1;
+            uint32_t lc, lr;
+            hilbert_d2xy(k, (uint32_t)(key & ((1ull << shiftbits) - 1ull)), &lc, &lr);
+            idx_out[u] = (int32_t)((lr << 16) | lc);
+        } else {
+            idx_out[u] = (int32_t)(key & ((1ull << shiftbits) - 1ull));
+        }
+        const bool last = (e >= E) || ((keys[e] >> shiftbits) != major);
+        if (last) ends[major] = (int32_t)(u + 1);
+    }
+}
+
+hipError_t launch_gather_csr(const uint64_t* keys, const uint32_t* perm, const double* val_in,
+                             const int32_t* head_pos, int64_t E, int64_t nnz_out, int cbits,
+                             int32_t* col_out, double* val_out, int32_t* row_end, hipStream_t s) {
+    if (nnz_out <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_gather<false>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
+                       perm, val_in, head_pos, E, nnz_out, cbits, col_out, val_out, row_end);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_csbh(const uint64_t* keys, const uint32_t* perm, const double* val_in,
+                              const int32_t* head_pos, int64_t E, int64_t nnz_out, int k,
+                              uint32_t* packed_out, double* val_out, int32_t* blk_end,
+                              hipStream_t s) {
+    if (nnz_out <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_gather<true>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
+                       perm, val_in, head_pos, E, nnz_out, 2 * k, (int32_t*)packed_out, val_out,
+                       blk_end);
+    return hipGetLastError();
+}
+
+struct LoadI32 {
+    const int32_t* p;
+    __device__ int32_t operator()(int64_t i) const { return p[i]; }
+};
+struct StoreInclI32 {
+    int32_t* p;
+    __device__ void operator()(int64_t i, int32_t incl, int32_t) const { p[i] = incl; }
+};
+
+hipError_t launch_max_scan_i32(int32_t* ends, int64_t len, uint32_t* tile_sums, hipStream_t s) {
+    if (len <= 0) return hipSuccess;
+    int32_t* ts = (int32_t*)tile_sums;
+    hipError_t e = scan_phase12<int32_t, OpMax<int32_t>>(LoadI32{ends}, len, ts, (int32_t*)nullptr,
+                                                         s);
+    if (e != hipSuccess) return e;
+    return scan_phase3<int32_t, OpMax<int32_t>>(LoadI32{ends}, StoreInclI32{ends}, len, ts, s);
+}

@@ -1,0 +1,606 @@
+// spx_api.cpp -- C ABI of libspx: argument checks, conversion orchestration, product dispatch.
+//
+// Every argument check runs on the host before any HIP call, so invalid requests fail without
+// touching a device.  Device work is enqueued on the caller's stream; conversion reads back a few
+// counters (index errors, entry count, work-unit counts) and therefore synchronises the stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "spx_internal.h"
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_last_error;
+
+static spx_status fail(spx_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static spx_status fail(spx_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(SPX_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                        __FILE__, __LINE__);                                                    \
+    } while (0)
+
+extern "C" const char* spx_status_string(spx_status s) {
+    switch (s) {
+        case SPX_OK: return "SPX_OK";
+        case SPX_ERR_INVALID_ARG: return "SPX_ERR_INVALID_ARG";
+        case SPX_ERR_INDEX: return "SPX_ERR_INDEX";
+        case SPX_ERR_RANGE: return "SPX_ERR_RANGE";
+        case SPX_ERR_ALIAS: return "SPX_ERR_ALIAS";
+        case SPX_ERR_NOMEM: return "SPX_ERR_NOMEM";
+        case SPX_ERR_HIP: return "SPX_ERR_HIP";
+        case SPX_ERR_UNSUPPORTED: return "SPX_ERR_UNSUPPORTED";
+        default: return "SPX_ERR_UNKNOWN";
+    }
+}
+
+extern "C" const char* spx_last_error_message(void) { return g_last_error.c_str(); }
+
+extern "C" const char* spx_version(void) { return "0.1.0"; }
+
+// ------------------------------------------------------------------ allocation
+
+static spx_alloc_fn g_alloc = nullptr;
+static spx_free_fn g_free = nullptr;
+static void* g_alloc_ctx = nullptr;
+
+extern "C" spx_status spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free_fn, void* ctx) {
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(SPX_ERR_INVALID_ARG, "spx_set_allocator: give both functions or neither");
+    g_alloc = alloc;
+    g_free = free_fn;
+    g_alloc_ctx = ctx;
+    return SPX_OK;
+}
+
+void* spx_dev_alloc(size_t bytes, hipStream_t s) {
+    if (bytes == 0) return nullptr;
+    if (g_alloc) return g_alloc(bytes, (void*)s, g_alloc_ctx);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void spx_dev_free(void* p, hipStream_t s) {
+    if (!p) return;
+    if (g_free) g_free(p, (void*)s, g_alloc_ctx);
+    else (void)hipFree(p);
+}
+
+// Allocations of one call; freed on scope exit unless released to a handle.
+struct AllocSet {
+    hipStream_t s;
+    std::vector<void*> ptrs;
+    size_t bytes = 0;
+    explicit AllocSet(hipStream_t st) : s(st) {}
+    ~AllocSet() {
+        for (void* p : ptrs) spx_dev_free(p, s);
+    }
+    template <typename T>
+    spx_status get(T** out, size_t count, const char* what) {
+        *out = nullptr;
+        if (count == 0) return SPX_OK;
+        void* p = spx_dev_alloc(count * sizeof(T), s);
+        if (!p) return fail(SPX_ERR_NOMEM, "device allocation of %zu bytes for %s failed",
+                            count * sizeof(T), what);
+        ptrs.push_back(p);
+        bytes += count * sizeof(T);
+        *out = (T*)p;
+        return SPX_OK;
+    }
+};
+
+#define SPX_TRY(expr)                  \
+    do {                               \
+        spx_status st_ = (expr);       \
+        if (st_ != SPX_OK) return st_; \
+    } while (0)
+
+// ------------------------------------------------------------------ helpers
+
+static int ceil_log2_u64(uint64_t v) {  // smallest b with 2^b >= v (v >= 1)
+    int b = 0;
+    while (b < 64 && (1ull << b) < v) ++b;
+    return b;
+}
+
+// Block size rule of Section 3.1 (equation eq:CSB-BlockSize): start at 3 + ceil(log2 sqrt n),
+// lower while beta > 2^16 or the beta-entry output slice (doubles) exceeds the LDS budget.
+static int csbh_default_log2_beta(int64_t m, int64_t n) {
+    const int64_t d = m > n ? m : n;
+    int t = 0;
+    while (t < 32 && (int64_t)1 << (2 * t) < d) ++t;  // 4^t >= d
+    int k = t + 3;
+    while (k > 0 && ((1ll << k) > (1ll << 16) || (1ll << k) * 8 > CB_LDS_BUDGET)) --k;
+    return k;
+}
+
+static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return na > 0 && nb > 0 && a0 < b0 + nb && b0 < a0 + na;
+}
+
+extern "C" spx_status spx_convert_opts_default(spx_convert_opts* opts) {
+    if (!opts) return fail(SPX_ERR_INVALID_ARG, "opts is NULL");
+    opts->sum_duplicates = 1;
+    opts->log2_beta = 0;
+    opts->validate = 1;
+    opts->tile_items = 0;
+    return SPX_OK;
+}
+
+extern "C" double spx_break_even(double conv_fmt, double conv_ref, double spmv_ref,
+                                 double spmv_fmt) {
+    const double gain = spmv_ref - spmv_fmt;
+    if (!(gain > 0)) return std::numeric_limits<double>::infinity();
+    return (conv_fmt - conv_ref) / gain;
+}
+
+// ------------------------------------------------------------------ conversion
+
+static spx_status sync_read(void* host, const void* dev, size_t bytes, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SPX_OK;
+}
+
+// Sort + sum repeats.  Produces sorted keys/perm, head positions and nnz_out.
+struct SortedEntries {
+    uint64_t* keys = nullptr;
+    uint32_t* perm = nullptr;
+    int32_t* head_pos = nullptr;  // null when repeats are kept
+    int64_t nnz_out = 0;
+};
+
+static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_format fmt, int k,
+                                 int64_t nbc, int cbits, int sum_dup, hipStream_t s,
+                                 SortedEntries* out) {
+    const int64_t E = coo->nnz;
+    uint64_t *k0, *k1;
+    uint32_t *v0, *v1, *hist, *tsums;
+    Readback* rb_dev;
+    SPX_TRY(tmp.get(&k0, E, "sort keys"));
+    SPX_TRY(tmp.get(&k1, E, "sort keys"));
+    SPX_TRY(tmp.get(&v0, E, "sort payload"));
+    SPX_TRY(tmp.get(&v1, E, "sort payload"));
+    const size_t hn = radix_hist_elems(E);
+    SPX_TRY(tmp.get(&hist, hn, "radix histogram"));
+    size_t ts = scan_tile_count((int64_t)hn);
+    if (scan_tile_count(E) > ts) ts = scan_tile_count(E);
+    SPX_TRY(tmp.get(&tsums, ts, "scan tile sums"));
+    SPX_TRY(tmp.get(&rb_dev, 1, "readback"));
+
+    HIP_TRY(launch_init_readback(rb_dev, s));
+    if (fmt == SPX_CSB_HILBERT)
+        HIP_TRY(launch_keys_csbh(coo->row, coo->col, E, coo->m, coo->n, k, nbc, k0, &rb_dev->err,
+                                 rb_dev->masks, s));
+    else
+        HIP_TRY(launch_keys_csr(coo->row, coo->col, E, coo->m, coo->n, cbits, k0, &rb_dev->err,
+                                rb_dev->masks, s));
+    Readback rb;
+    SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+    if (rb.err) return fail(SPX_ERR_INDEX, "a triplet index lies outside [0,%d) x [0,%d)", coo->m,
+                            coo->n);
+    const uint64_t vary = rb.masks[0] ^ rb.masks[1];
+    bool second = false;
+    HIP_TRY(radix_sort_pairs(k0, v0, k1, v1, E, vary, hist, tsums, s, &second));
+    out->keys = second ? k1 : k0;
+    out->perm = second ? v1 : v0;
+    if (!sum_dup) {
+        out->head_pos = nullptr;
+        out->nnz_out = E;
+        return SPX_OK;
+    }
+    HIP_TRY(launch_dedup_count(out->keys, E, tsums, &rb_dev->totals[0], s));
+    SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+    out->nnz_out = rb.totals[0];
+    SPX_TRY(tmp.get(&out->head_pos, (size_t)out->nnz_out, "head positions"));
+    HIP_TRY(launch_dedup_heads(out->keys, E, tsums, out->head_pos, s));
+    return SPX_OK;
+}
+
+// Moves an allocation of `tmp` to the handle, which frees it in spx_matrix_destroy.
+static void keep(AllocSet& tmp, spx_matrix_s* A, void* p) {
+    if (!p) return;
+    for (auto& q : tmp.ptrs)
+        if (q == p) {
+            q = nullptr;
+            A->owned.push_back(p);
+            return;
+        }
+}
+
+static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
+                               const spx_convert_opts* o, hipStream_t s, spx_matrix_s* A,
+                               AllocSet& tmp) {
+    const int64_t E = coo->nnz;
+    const int32_t m = coo->m, n = coo->n;
+    A->m = m;
+    A->n = n;
+    A->fmt = fmt;
+    const int cbits = ceil_log2_u64((uint64_t)(n > 1 ? n : 1));
+    const int rbits = ceil_log2_u64((uint64_t)(m > 1 ? m : 1));
+    int k = 0;
+    int64_t nbr = 0, nbc = 0;
+    if (fmt == SPX_CSB_HILBERT) {
+        k = o->log2_beta > 0 ? o->log2_beta : csbh_default_log2_beta(m, n);
+        if (k < 1 || k > 16)
+            return fail(SPX_ERR_INVALID_ARG, "log2_beta %d outside [1,16]", k);
+        if (((int64_t)1 << k) * 8 > 160 * 1024 - 16)
+            return fail(SPX_ERR_UNSUPPORTED, "log2_beta %d: output slice exceeds LDS", k);
+        nbr = ((int64_t)m + (1 << k) - 1) >> k;
+        nbc = ((int64_t)n + (1 << k) - 1) >> k;
+        if (nbr < 1) nbr = 1;
+        if (nbc < 1) nbc = 1;
+        if ((double)nbr * (double)nbc >= 2147483647.0)
+            return fail(SPX_ERR_RANGE, "%lld x %lld blocks exceed the int32 block pointer range",
+                        (long long)nbr, (long long)nbc);
+        const int kb = ceil_log2_u64((uint64_t)(nbr * nbc));
+        if (kb + 2 * k > 64) return fail(SPX_ERR_RANGE, "CSBH sort key exceeds 64 bits");
+        A->log2_beta = k;
+        A->nbr = nbr;
+        A->nbc = nbc;
+    } else if (rbits + cbits > 64) {
+        return fail(SPX_ERR_RANGE, "CRS sort key exceeds 64 bits");
+    }
+
+    SortedEntries se;
+    if (E > 0) SPX_TRY(sort_and_dedup(tmp, coo, fmt, k, nbc, cbits, o->sum_duplicates, s, &se));
+    const int64_t nnz = se.nnz_out;
+    A->nnz = nnz;
+
+    uint32_t* tsums;
+    Readback* rb_dev;
+    size_t tsn = scan_tile_count((int64_t)m + 2);
+    SPX_TRY(tmp.get(&rb_dev, 1, "readback"));
+    HIP_TRY(launch_init_readback(rb_dev, s));
+
+    double* val_out;
+    SPX_TRY(tmp.get(&val_out, (size_t)nnz, "values"));
+    keep(tmp, A, val_out);
+    A->val = val_out;
+    const double* val_in = (const double*)coo->val;
+
+    if (fmt == SPX_CSB_HILBERT) {
+        const int64_t nblk = nbr * nbc;
+        int32_t *bp;
+        uint32_t* packed;
+        SPX_TRY(tmp.get(&bp, (size_t)nblk + 1, "blk_ptr"));
+        SPX_TRY(tmp.get(&packed, (size_t)nnz, "packed indices"));
+        keep(tmp, A, bp);
+        keep(tmp, A, packed);
+        A->blk_ptr = bp;
+        A->packed = packed;
+        HIP_TRY(launch_fill_i32(bp, nblk + 1, 0, s));
+        HIP_TRY(launch_gather_csbh(se.keys, se.perm, val_in, se.head_pos, E, nnz, k, packed,
+                                   val_out, bp + 1, s));
+        if (scan_tile_count(nblk) > tsn) tsn = scan_tile_count(nblk);
+        SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
+        HIP_TRY(launch_max_scan_i32(bp + 1, nblk, tsums, s));
+        // work units
+        int64_t unit = o->tile_items > 0 ? o->tile_items : CB_UNIT_DEFAULT;
+        int32_t *unit_ptr, *slot_ptr, *split_ptr;
+        SPX_TRY(tmp.get(&unit_ptr, (size_t)nbr, "unit ptr"));
+        SPX_TRY(tmp.get(&slot_ptr, (size_t)nbr, "slot ptr"));
+        SPX_TRY(tmp.get(&split_ptr, (size_t)nbr, "split ptr"));
+        HIP_TRY(csbh_plan(bp, nbr, nbc, unit, unit_ptr, slot_ptr, split_ptr, rb_dev->totals, s));
+        Readback rb;
+        SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+        A->cb_nunits = (int32_t)rb.totals[0];
+        A->cb_nslots = (int32_t)rb.totals[1];
+        A->cb_nsplit = (int32_t)rb.totals[2];
+        int4 *units, *split;
+        double* partials;
+        SPX_TRY(tmp.get(&units, (size_t)A->cb_nunits, "units"));
+        SPX_TRY(tmp.get(&split, (size_t)A->cb_nsplit, "split rows"));
+        SPX_TRY(tmp.get(&partials, (size_t)A->cb_nslots << k, "partial slices"));
+        keep(tmp, A, units);
+        keep(tmp, A, split);
+        keep(tmp, A, partials);
+        A->cb_units = units;
+        A->cb_split = split;
+        A->cb_partials = partials;
+        HIP_TRY(csbh_units(bp, nbr, nbc, unit, unit_ptr, slot_ptr, split_ptr, units, split, s));
+        A->parts = A->cb_nunits;
+        return SPX_OK;
+    }
+
+    // CRS formats
+    int32_t *rp, *col;
+    SPX_TRY(tmp.get(&rp, (size_t)m + 1, "row_ptr"));
+    SPX_TRY(tmp.get(&col, (size_t)nnz, "col_ind"));
+    keep(tmp, A, rp);
+    keep(tmp, A, col);
+    A->row_ptr = rp;
+    A->col = col;
+    HIP_TRY(launch_fill_i32(rp, (int64_t)m + 1, 0, s));
+    HIP_TRY(launch_gather_csr(se.keys, se.perm, val_in, se.head_pos, E, nnz, cbits, col, val_out,
+                              rp + 1, s));
+    SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
+    HIP_TRY(launch_max_scan_i32(rp + 1, m, tsums, s));
+
+    if (fmt == SPX_CSR_MERGE) {
+        const int64_t total = (int64_t)m + nnz;
+        const int64_t tiles = (total + MP_TILE - 1) / MP_TILE;
+        if (tiles >= INT32_MAX) return fail(SPX_ERR_RANGE, "too many merge tiles");
+        A->mp_tiles = (int32_t)tiles;
+        int2* coords;
+        int32_t* crow;
+        double* cval;
+        SPX_TRY(tmp.get(&coords, (size_t)tiles + 1, "merge coordinates"));
+        SPX_TRY(tmp.get(&crow, (size_t)tiles, "carry rows"));
+        SPX_TRY(tmp.get(&cval, (size_t)tiles, "carry values"));
+        keep(tmp, A, coords);
+        keep(tmp, A, crow);
+        keep(tmp, A, cval);
+        A->mp_coords = coords;
+        A->mp_carry_row = crow;
+        A->mp_carry_val = cval;
+        if (tiles > 0) HIP_TRY(launch_merge_coords(rp, m, nnz, coords, (int32_t)tiles, s));
+        A->parts = tiles;
+        HIP_TRY(hipStreamSynchronize(s));
+        return SPX_OK;
+    }
+
+    // row split
+    uint32_t* tsb;
+    SPX_TRY(tmp.get(&tsb, tsn, "scan tile sums"));
+    HIP_TRY(rowsplit_count(rp, m, tsums, tsb, rb_dev->totals, s));
+    Readback rb;
+    SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+    const int32_t nflags = (int32_t)rb.totals[0];  // blocks + sentinel
+    const int32_t nlong = (int32_t)rb.totals[1];
+    A->rs_nb = nflags - 1;
+    A->rs_nlong = nlong;
+    int32_t *blocks, *long_rows = nullptr, *chunk_ptr = nullptr;
+    SPX_TRY(tmp.get(&blocks, (size_t)nflags, "row blocks"));
+    keep(tmp, A, blocks);
+    A->rs_blocks = blocks;
+    if (nlong > 0) {
+        SPX_TRY(tmp.get(&long_rows, (size_t)nlong, "long rows"));
+        SPX_TRY(tmp.get(&chunk_ptr, (size_t)nlong + 1, "chunk pointers"));
+        keep(tmp, A, long_rows);
+        keep(tmp, A, chunk_ptr);
+    }
+    A->rs_long_rows = long_rows;
+    A->rs_chunk_ptr = chunk_ptr;
+    HIP_TRY(rowsplit_fill(rp, m, tsums, tsb, blocks, long_rows, s));
+    if (nlong > 0) {
+        HIP_TRY(rowsplit_chunks(rp, long_rows, nlong, chunk_ptr, tsums, &rb_dev->totals[2], s));
+        SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+        A->rs_nchunks = (int32_t)rb.totals[2];
+        double* partials;
+        SPX_TRY(tmp.get(&partials, (size_t)A->rs_nchunks, "chunk partials"));
+        keep(tmp, A, partials);
+        A->rs_partials = partials;
+    }
+    A->parts = A->rs_nb;
+    HIP_TRY(hipStreamSynchronize(s));
+    return SPX_OK;
+}
+
+static int64_t sum_owned_bytes(const spx_matrix_s* A) {
+    int64_t b = 0;
+    b += (A->row_ptr ? ((int64_t)A->m + 1) * 4 : 0);
+    b += (A->col ? A->nnz * 4 : 0);
+    b += (A->val ? A->nnz * 8 : 0);
+    b += (A->blk_ptr ? (A->nbr * A->nbc + 1) * 4 : 0);
+    b += (A->packed ? A->nnz * 4 : 0);
+    b += (A->mp_coords ? ((int64_t)A->mp_tiles + 1) * 8 + (int64_t)A->mp_tiles * 12 : 0);
+    b += (A->rs_blocks ? ((int64_t)A->rs_nb + 1) * 4 : 0);
+    b += (A->rs_long_rows ? (int64_t)A->rs_nlong * 8 + 4 + (int64_t)A->rs_nchunks * 8 : 0);
+    b += (A->cb_units ? (int64_t)A->cb_nunits * 16 + (int64_t)A->cb_nsplit * 16 : 0);
+    b += (A->cb_partials ? ((int64_t)A->cb_nslots << A->log2_beta) * 8 : 0);
+    return b;
+}
+
+extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
+                                  const spx_convert_opts* opts, void* stream, spx_matrix* out,
+                                  spx_convert_report* rep) {
+    g_last_error.clear();
+    if (!out) return fail(SPX_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!coo) return fail(SPX_ERR_INVALID_ARG, "coo is NULL");
+    if (fmt != SPX_CSR_ROWSPLIT && fmt != SPX_CSR_MERGE && fmt != SPX_CSB_HILBERT)
+        return fail(SPX_ERR_INVALID_ARG, "unknown format %d", (int)fmt);
+    if (coo->m < 0 || coo->n < 0 || coo->nnz < 0)
+        return fail(SPX_ERR_INVALID_ARG, "negative size (m=%d n=%d nnz=%lld)", coo->m, coo->n,
+                    (long long)coo->nnz);
+    if (coo->nnz >= 2147483647LL)
+        return fail(SPX_ERR_RANGE, "nnz %lld does not fit the int32 index range",
+                    (long long)coo->nnz);
+    if (coo->val_type != SPX_F64)
+        return fail(SPX_ERR_UNSUPPORTED, "value type %d (only SPX_F64)", (int)coo->val_type);
+    if (coo->nnz > 0 && (!coo->row || !coo->col || !coo->val))
+        return fail(SPX_ERR_INVALID_ARG, "null triplet array with nnz > 0");
+    if (coo->nnz > 0 && (coo->m == 0 || coo->n == 0))
+        return fail(SPX_ERR_INDEX, "entries given for an empty (%d x %d) matrix", coo->m, coo->n);
+    spx_convert_opts o;
+    spx_convert_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.sum_duplicates != 0 && o.sum_duplicates != 1)
+        return fail(SPX_ERR_INVALID_ARG, "sum_duplicates must be 0 or 1");
+    if (o.log2_beta < 0 || o.log2_beta > 16)
+        return fail(SPX_ERR_INVALID_ARG, "log2_beta %d outside [0,16]", o.log2_beta);
+    if (o.tile_items < 0) return fail(SPX_ERR_INVALID_ARG, "tile_items < 0");
+    if (fmt != SPX_CSB_HILBERT && o.tile_items != 0)
+        return fail(SPX_ERR_UNSUPPORTED, "tile_items is only adjustable for CSBH");
+
+    hipStream_t s = (hipStream_t)stream;
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (rep) {
+        HIP_TRY(hipEventCreate(&ev0));
+        if (hipEventCreate(&ev1) != hipSuccess) {
+            (void)hipEventDestroy(ev0);
+            return fail(SPX_ERR_HIP, "hipEventCreate failed");
+        }
+        (void)hipEventRecord(ev0, s);
+    }
+    spx_matrix_s* A = new (std::nothrow) spx_matrix_s();
+    if (!A) return fail(SPX_ERR_NOMEM, "host allocation failed");
+    A->device = device;
+    spx_status st;
+    {
+        AllocSet tmp(s);
+        st = convert_impl(coo, fmt, &o, s, A, tmp);
+        if (st == SPX_OK) {
+            hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess)
+                st = fail(SPX_ERR_HIP, "conversion failed on the device: %s",
+                          hipGetErrorString(e));
+        } else {
+            (void)hipStreamSynchronize(s);
+        }
+    }  // temporaries freed here
+    if (st != SPX_OK) {
+        for (void* p : A->owned) spx_dev_free(p, s);
+        delete A;
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        return st;
+    }
+    A->bytes = sum_owned_bytes(A);
+    A->last_stream = s;
+    if (rep) {
+        (void)hipEventRecord(ev1, s);
+        (void)hipEventSynchronize(ev1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev0, ev1);
+        rep->convert_ms = ms;
+        rep->nnz_out = A->nnz;
+        rep->bytes = A->bytes;
+        rep->log2_beta = A->log2_beta;
+        rep->parts = (int32_t)A->parts;
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
+    *out = A;
+    return SPX_OK;
+}
+
+// ------------------------------------------------------------------ product and handle
+
+extern "C" spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* stream) {
+    if (!A) return fail(SPX_ERR_INVALID_ARG, "matrix handle is NULL");
+    if (A->m > 0 && !y) return fail(SPX_ERR_INVALID_ARG, "y is NULL");
+    if (A->n > 0 && !x) return fail(SPX_ERR_INVALID_ARG, "x is NULL");
+    if (ranges_overlap(x, (size_t)A->n * 8, y, (size_t)A->m * 8))
+        return fail(SPX_ERR_ALIAS, "x and y overlap");
+    if (A->m == 0) return SPX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    A->last_stream = s;
+    switch (A->fmt) {
+        case SPX_CSR_MERGE: HIP_TRY(spmv_merge(A, x, y, s)); break;
+        case SPX_CSR_ROWSPLIT: HIP_TRY(spmv_rowsplit(A, x, y, s)); break;
+        case SPX_CSB_HILBERT: HIP_TRY(spmv_csbh(A, x, y, s)); break;
+        default: return fail(SPX_ERR_INVALID_ARG, "corrupt handle");
+    }
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_matrix_get_info(spx_matrix A, spx_matrix_info* info) {
+    if (!A || !info) return fail(SPX_ERR_INVALID_ARG, "NULL argument");
+    info->m = A->m;
+    info->n = A->n;
+    info->nnz = A->nnz;
+    info->format = A->fmt;
+    info->log2_beta = A->log2_beta;
+    info->bytes = A->bytes;
+    info->parts = A->parts;
+    info->value_type = SPX_F64;
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_matrix_export(spx_matrix A, spx_array which, void* dst, int64_t bytes,
+                                        int64_t* needed, void* stream) {
+    if (!A) return fail(SPX_ERR_INVALID_ARG, "matrix handle is NULL");
+    const void* src = nullptr;
+    int64_t len = 0;
+    bool exists = false;
+    const bool crs = A->fmt != SPX_CSB_HILBERT;
+    switch (which) {
+        case SPX_ARRAY_ROW_PTR:
+            exists = crs;
+            src = A->row_ptr;
+            len = ((int64_t)A->m + 1) * 4;
+            break;
+        case SPX_ARRAY_COL_IND:
+            exists = crs;
+            src = A->col;
+            len = A->nnz * 4;
+            break;
+        case SPX_ARRAY_VALUES:
+            exists = true;
+            src = A->val;
+            len = A->nnz * 8;
+            break;
+        case SPX_ARRAY_BLK_PTR:
+            exists = !crs;
+            src = A->blk_ptr;
+            len = (A->nbr * A->nbc + 1) * 4;
+            break;
+        case SPX_ARRAY_PACKED:
+            exists = !crs;
+            src = A->packed;
+            len = A->nnz * 4;
+            break;
+        case SPX_ARRAY_PARTS:
+            exists = true;
+            if (A->fmt == SPX_CSR_MERGE) {
+                src = A->mp_coords;
+                len = ((int64_t)A->mp_tiles + 1) * 8;
+            } else if (A->fmt == SPX_CSR_ROWSPLIT) {
+                src = A->rs_blocks;
+                len = A->rs_blocks ? ((int64_t)A->rs_nb + 1) * 4 : 0;
+            } else {
+                src = A->cb_units;
+                len = (int64_t)A->cb_nunits * 16;
+            }
+            break;
+        default: return fail(SPX_ERR_INVALID_ARG, "unknown array %d", (int)which);
+    }
+    if (!exists)
+        return fail(SPX_ERR_INVALID_ARG, "array %d does not exist for format %d", (int)which,
+                    (int)A->fmt);
+    if (src == nullptr) len = 0;
+    if (needed) *needed = len;
+    if (bytes < len)
+        return fail(SPX_ERR_INVALID_ARG, "destination holds %lld of %lld bytes",
+                    (long long)bytes, (long long)len);
+    if (len == 0) return SPX_OK;
+    if (!dst) return fail(SPX_ERR_INVALID_ARG, "dst is NULL");
+    HIP_TRY(hipMemcpyAsync(dst, src, (size_t)len, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_matrix_destroy(spx_matrix A) {
+    if (!A) return SPX_OK;
+    (void)hipStreamSynchronize(A->last_stream);
+    for (void* p : A->owned) spx_dev_free(p, A->last_stream);
+    delete A;
+    return SPX_OK;
+}

@@ -1,0 +1,142 @@
+// spx_internal.h -- handle layout and kernel launchers shared by the libspx sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/spx.h"
+
+// ------------------------------------------------------------------ tuning constants
+// merge-path CRS: threads per tile and items (row ends + entries) per thread
+#define MP_NT 256
+#define MP_IPT 8
+#define MP_TILE (MP_NT * MP_IPT)
+
+// row-split CRS: a row block holds < RS_NNZ entries and <= RS_ROWS rows; rows longer than
+// RS_LONG are split into chunks of RS_CHUNK entries whose partial sums are added in order
+#define RS_NT 256
+#define RS_LONG 1024
+#define RS_NNZ 2048
+#define RS_ROWS 1024
+#define RS_CHUNK 8192
+
+// CSBH: workgroup size and entries per thread per sweep; a work unit covers at most
+// csbh_unit_nnz entries of one block row (default below, overridable by tile_items)
+#define CB_NT 512
+#define CB_IPT 8
+#define CB_UNIT_DEFAULT (1 << 17)
+#define CB_LDS_BUDGET (64 * 1024)    // bytes of the output slice kept in LDS
+#define CB_BP_STAGE_MAX 8192         // block pointers staged in LDS when nbc+1 <= this
+
+// radix sort: 8-bit digits, 256 threads x 16 keys per tile
+#define RS_RADIX_BITS 8
+#define RSORT_NT 256
+#define RSORT_IPT 16
+#define RSORT_TILE (RSORT_NT * RSORT_IPT)
+
+struct spx_matrix_s {
+    int32_t m = 0, n = 0;
+    int64_t nnz = 0;
+    spx_format fmt = 0;
+    int32_t log2_beta = 0;
+    int device = 0;
+    int64_t bytes = 0;
+    hipStream_t last_stream = nullptr;
+    // CRS formats
+    int32_t* row_ptr = nullptr;  // m+1
+    int32_t* col = nullptr;      // nnz
+    double* val = nullptr;       // nnz (all formats)
+    // CSBH
+    int32_t* blk_ptr = nullptr;  // nbr*nbc+1
+    uint32_t* packed = nullptr;  // nnz
+    int64_t nbr = 0, nbc = 0;
+    // merge-path partition
+    int2* mp_coords = nullptr;   // tiles+1
+    int32_t mp_tiles = 0;
+    int32_t* mp_carry_row = nullptr;
+    double* mp_carry_val = nullptr;
+    // row-split partition
+    int32_t* rs_blocks = nullptr;  // nb+1 row starts
+    int32_t rs_nb = 0;
+    int32_t* rs_long_rows = nullptr;
+    int32_t* rs_chunk_ptr = nullptr;  // nlong+1
+    int32_t rs_nlong = 0, rs_nchunks = 0;
+    double* rs_partials = nullptr;    // nchunks
+    // CSBH partition
+    int4* cb_units = nullptr;       // {block row, first entry, end entry, partial slot or -1}
+    int32_t cb_nunits = 0;
+    int4* cb_split = nullptr;       // {block row, first slot, slots, 0}
+    int32_t cb_nsplit = 0;
+    int32_t cb_nslots = 0;
+    double* cb_partials = nullptr;  // nslots * beta
+    int64_t parts = 0;
+    std::vector<void*> owned;  // device allocations freed by spx_matrix_destroy
+};
+
+// Small device block read back by the host during conversion.
+struct Readback {
+    uint32_t err;
+    uint32_t pad;
+    unsigned long long masks[2];  // OR and AND of all sort keys
+    uint32_t totals[4];
+};
+
+// ------------------------------------------------------------------ allocation
+void* spx_dev_alloc(size_t bytes, hipStream_t s);
+void spx_dev_free(void* p, hipStream_t s);
+
+// ------------------------------------------------------------------ conversion launchers
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_init_readback(Readback* rb, hipStream_t s);
+hipError_t launch_keys_csr(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+                           int32_t n, int cbits, uint64_t* keys, uint32_t* err,
+                           unsigned long long* masks, hipStream_t s);
+hipError_t launch_keys_csbh(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+                            int32_t n, int k, int64_t nbc, uint64_t* keys, uint32_t* err,
+                            unsigned long long* masks, hipStream_t s);
+// Stable LSD radix sort of (keys, index payload).  Digits whose bits never vary (per `vary`)
+// are skipped.  On return *in_second says whether the result is in (k1, v1).
+hipError_t radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t E,
+                            uint64_t vary, uint32_t* hist, uint32_t* tile_sums, hipStream_t s,
+                            bool* in_second);
+size_t radix_hist_elems(int64_t E);
+hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_sums,
+                              uint32_t* total, hipStream_t s);
+hipError_t launch_dedup_heads(const uint64_t* keys, int64_t E, const uint32_t* tile_sums,
+                              int32_t* head_pos, hipStream_t s);
+hipError_t launch_gather_csr(const uint64_t* keys, const uint32_t* perm, const double* val_in,
+                             const int32_t* head_pos, int64_t E, int64_t nnz_out, int cbits,
+                             int32_t* col_out, double* val_out, int32_t* row_end, hipStream_t s);
+hipError_t launch_gather_csbh(const uint64_t* keys, const uint32_t* perm, const double* val_in,
+                              const int32_t* head_pos, int64_t E, int64_t nnz_out, int k,
+                              uint32_t* packed_out, double* val_out, int32_t* blk_end,
+                              hipStream_t s);
+// In-place inclusive max-scan of ends[0..len) (turns "end of last entry" marks into pointers).
+hipError_t launch_max_scan_i32(int32_t* ends, int64_t len, uint32_t* tile_sums, hipStream_t s);
+size_t scan_tile_count(int64_t n);
+
+// ------------------------------------------------------------------ partitions
+hipError_t launch_merge_coords(const int32_t* row_ptr, int32_t m, int64_t nnz, int2* coords,
+                               int32_t tiles, hipStream_t s);
+// row-split: phase 1 counts (blocks+sentinel, long rows); phase 2 fills
+hipError_t rowsplit_count(const int32_t* row_ptr, int32_t m, uint32_t* tile_sums_a,
+                          uint32_t* tile_sums_b, uint32_t* totals, hipStream_t s);
+hipError_t rowsplit_fill(const int32_t* row_ptr, int32_t m, const uint32_t* tile_sums_a,
+                         const uint32_t* tile_sums_b, int32_t* blocks, int32_t* long_rows,
+                         hipStream_t s);
+hipError_t rowsplit_chunks(const int32_t* row_ptr, const int32_t* long_rows, int32_t nlong,
+                           int32_t* chunk_ptr, uint32_t* tile_sums, uint32_t* total,
+                           hipStream_t s);
+// CSBH: plan = per block row unit and slot counts (scanned), then the unit table
+hipError_t csbh_plan(const int32_t* blk_ptr, int64_t nbr, int64_t nbc, int64_t unit_nnz,
+                     int32_t* unit_ptr, int32_t* slot_ptr, int32_t* split_ptr, uint32_t* totals,
+                     hipStream_t s);
+hipError_t csbh_units(const int32_t* blk_ptr, int64_t nbr, int64_t nbc, int64_t unit_nnz,
+                      const int32_t* unit_ptr, const int32_t* slot_ptr, const int32_t* split_ptr,
+                      int4* units, int4* split, hipStream_t s);
+
+// ------------------------------------------------------------------ products
+hipError_t spmv_merge(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
+hipError_t spmv_rowsplit(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
+hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);

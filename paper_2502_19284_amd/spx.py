@@ -1,0 +1,250 @@
+"""ctypes binding of libspx (include/spx.h): argument marshalling only.
+
+Every step of conversion and product runs in the library's HIP kernels; this module only checks
+tensor dtypes/devices, passes raw device pointers and the current torch stream, and turns status
+codes into exceptions.  torch supplies device memory and streams.  If libspx.so is missing the
+import of the binding's entry points fails loudly (there is no CPU fallback).
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libspx.so")
+
+SPX_OK = 0
+STATUS = {0: "SPX_OK", -1: "SPX_ERR_INVALID_ARG", -2: "SPX_ERR_INDEX", -3: "SPX_ERR_RANGE",
+          -4: "SPX_ERR_ALIAS", -5: "SPX_ERR_NOMEM", -6: "SPX_ERR_HIP", -7: "SPX_ERR_UNSUPPORTED"}
+FORMATS = {"rowsplit": 0, "merge": 1, "csbh": 2}
+FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
+ARRAYS = {"row_ptr": (0, torch.int32), "col_ind": (1, torch.int32), "values": (2, torch.float64),
+          "blk_ptr": (3, torch.int32), "packed": (4, torch.int32), "parts": (5, torch.int32)}
+
+
+class SpxError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        self.name = STATUS.get(status, "SPX_ERR_UNKNOWN")
+        super().__init__("%s: %s" % (self.name, message))
+
+
+class CooDesc(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("val_type", ctypes.c_int32)]
+
+
+class ConvertOpts(ctypes.Structure):
+    _fields_ = [("sum_duplicates", ctypes.c_int32), ("log2_beta", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("tile_items", ctypes.c_int32)]
+
+
+class ConvertReport(ctypes.Structure):
+    _fields_ = [("convert_ms", ctypes.c_float), ("nnz_out", ctypes.c_int64),
+                ("bytes", ctypes.c_int64), ("log2_beta", ctypes.c_int32),
+                ("parts", ctypes.c_int32)]
+
+
+class MatrixInfo(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("format", ctypes.c_int32), ("log2_beta", ctypes.c_int32),
+                ("bytes", ctypes.c_int64), ("parts", ctypes.c_int64),
+                ("value_type", ctypes.c_int32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+_lib = None
+_alloc_refs = None
+
+
+def load(path=LIB_PATH):
+    """Load libspx.so and declare its signatures.  Raises if the library was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libspx.so not found at %s: build it with "
+                           "paper_2502_19284_amd.build.build()" % path)
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    L.spx_convert_opts_default.argtypes = [ctypes.POINTER(ConvertOpts)]
+    L.spx_convert.argtypes = [ctypes.POINTER(CooDesc), ctypes.c_int32, ctypes.POINTER(ConvertOpts),
+                              P, ctypes.POINTER(P), ctypes.POINTER(ConvertReport)]
+    L.spx_spmv.argtypes = [P, P, P, P]
+    L.spx_matrix_get_info.argtypes = [P, ctypes.POINTER(MatrixInfo)]
+    L.spx_matrix_export.argtypes = [P, ctypes.c_int32, P, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_int64), P]
+    L.spx_matrix_destroy.argtypes = [P]
+    L.spx_set_allocator.argtypes = [ALLOC_FN, FREE_FN, P]
+    for f in (L.spx_convert_opts_default, L.spx_convert, L.spx_spmv, L.spx_matrix_get_info,
+              L.spx_matrix_export, L.spx_matrix_destroy, L.spx_set_allocator):
+        f.restype = ctypes.c_int32
+    L.spx_break_even.argtypes = [ctypes.c_double] * 4
+    L.spx_break_even.restype = ctypes.c_double
+    L.spx_status_string.argtypes = [ctypes.c_int32]
+    L.spx_status_string.restype = ctypes.c_char_p
+    L.spx_last_error_message.argtypes = []
+    L.spx_last_error_message.restype = ctypes.c_char_p
+    L.spx_version.argtypes = []
+    L.spx_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != SPX_OK:
+        msg = load().spx_last_error_message().decode()
+        raise SpxError(status, msg)
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def use_torch_allocator(enable=True):
+    """Route the library's device allocations through torch's caching allocator."""
+    global _alloc_refs
+    L = load()
+    if not enable:
+        _check(L.spx_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        _alloc_refs = None
+        return
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                      int(stream or 0))
+        except Exception:  # out of memory or invalid request -> NULL -> SPX_ERR_NOMEM
+            return None
+
+    def _free(ptr, stream, ctx):
+        if ptr:
+            torch.cuda.caching_allocator_delete(ptr)
+
+    refs = (ALLOC_FN(_alloc), FREE_FN(_free))
+    _check(L.spx_set_allocator(refs[0], refs[1], None))
+    _alloc_refs = refs
+
+
+def break_even(conv_fmt, conv_ref, spmv_ref, spmv_fmt):
+    """Products after which a format pays for its longer conversion (inf if it is not faster)."""
+    return float(load().spx_break_even(conv_fmt, conv_ref, spmv_ref, spmv_fmt))
+
+
+def _dev_tensor(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+class Matrix:
+    """A converted matrix held by libspx.  Use .spmv(x) for y = A x."""
+
+    def __init__(self, handle, fmt, report):
+        self._h = handle
+        self.format = fmt
+        self.convert_ms = float(report.convert_ms)
+        info = MatrixInfo()
+        _check(load().spx_matrix_get_info(self._h, ctypes.byref(info)))
+        self.shape = (info.m, info.n)
+        self.nnz = int(info.nnz)
+        self.bytes = int(info.bytes)
+        self.log2_beta = int(info.log2_beta)
+        self.parts = int(info.parts)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("matrix was destroyed")
+        return self._h
+
+    def spmv(self, x, out=None, stream=None):
+        """y = A x on the current (or given) stream; returns y (float64, length m)."""
+        m, n = self.shape
+        _dev_tensor(x, torch.float64, "x")
+        if x.numel() != n:
+            raise ValueError("x has %d entries, expected %d" % (x.numel(), n))
+        if out is None:
+            out = torch.empty(m, dtype=torch.float64, device=x.device)
+        _dev_tensor(out, torch.float64, "out")
+        if out.numel() != m:
+            raise ValueError("out has %d entries, expected %d" % (out.numel(), m))
+        _check(load().spx_spmv(self.handle, ctypes.c_void_p(x.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def export(self, name, stream=None):
+        """Copy one of the handle's arrays into a new device tensor."""
+        which, dtype = ARRAYS[name]
+        L = load()
+        need = ctypes.c_int64(-1)
+        st = L.spx_matrix_export(self.handle, which, None, 0, ctypes.byref(need), None)
+        if need.value < 0:  # the array does not exist for this format
+            _check(st)
+        nelem = need.value // torch.empty(0, dtype=dtype).element_size()
+        t = torch.empty(nelem, dtype=dtype, device=torch.cuda.current_device())
+        _check(L.spx_matrix_export(self.handle, which, ctypes.c_void_p(t.data_ptr()),
+                                   need.value, None, _stream_ptr(stream)))
+        return t
+
+    def close(self):
+        if self._h is not None:
+            load().spx_matrix_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __repr__(self):
+        return "Matrix(%s, shape=%s, nnz=%d)" % (self.format, self.shape, self.nnz)
+
+
+def convert(row, col, val, shape, fmt="merge", sum_duplicates=True, log2_beta=0,
+            tile_items=0, stream=None):
+    """Convert device triplets (int32 row, int32 col, float64 val) to a Matrix of format `fmt`
+    ('rowsplit', 'merge' or 'csbh')."""
+    if fmt not in FORMATS:
+        raise ValueError("unknown format %r (expected one of %s)" % (fmt, sorted(FORMATS)))
+    m, n = int(shape[0]), int(shape[1])
+    _dev_tensor(row, torch.int32, "row")
+    _dev_tensor(col, torch.int32, "col")
+    _dev_tensor(val, torch.float64, "val")
+    E = row.numel()
+    if col.numel() != E or val.numel() != E:
+        raise ValueError("row, col and val must have the same length")
+    desc = CooDesc(m, n, E, ctypes.c_void_p(row.data_ptr() if E else 0),
+                   ctypes.c_void_p(col.data_ptr() if E else 0),
+                   ctypes.c_void_p(val.data_ptr() if E else 0), 0)
+    opts = ConvertOpts(1 if sum_duplicates else 0, int(log2_beta), 1, int(tile_items))
+    rep = ConvertReport()
+    h = ctypes.c_void_p()
+    L = load()
+    _check(L.spx_convert(ctypes.byref(desc), FORMATS[fmt], ctypes.byref(opts),
+                         _stream_ptr(stream), ctypes.byref(h), ctypes.byref(rep)))
+    return Matrix(h, fmt, rep)
+
+
+def version():
+    return load().spx_version().decode()
+
+
+def header_functions():
+    """Names of the entry points declared in include/spx.h."""
+    import re
+    hdr = os.path.join(_PKG, "..", "include", "spx.h")
+    with open(hdr) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\*?\s+\**(spx_[a-z_0-9]+)\(", text,
+                                 re.M)))
+

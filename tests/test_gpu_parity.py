@@ -1,0 +1,342 @@
+"""GPU parity: every format's conversion and product against the CPU oracle, through the C ABI.
+
+Bar: bit-exact for integer work (conversion arrays, partitions, integer-valued products);
+row-scaled error |y - y_ref| / sum_k |a_ik x_k| <= 1e-12 for floating-point products, where
+y_ref is the oracle's compensated Algorithm 1.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import formats, measure, mergepath, spmv
+
+pytestmark = pytest.mark.gpu
+FMTS = ["rowsplit", "merge", "csbh"]
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def spx():
+    import torch
+
+    from ._lib import ensure_built
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ensure_built()
+    import paper_2502_19284_amd as spx
+    spx.use_torch_allocator(True)
+    return spx
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _run(spx, fmt, m, n, row, col, val, x, **kw):
+    import torch
+    A = spx.convert(_dev(row, torch.int32), _dev(col, torch.int32), _dev(val, torch.float64),
+                    (m, n), fmt, **kw)
+    y = A.spmv(_dev(x, torch.float64))
+    torch.cuda.synchronize()
+    return A, y.cpu().numpy()
+
+
+def _check_float(y, ref, what):
+    err = measure.scaled_error(y, ref["y_ref"], ref["scale"])
+    worst = float(err.max()) if len(err) else 0.0
+    assert worst <= TOL, "%s: max scaled error %.3g at row %d" % (what, worst, int(err.argmax()))
+    return worst
+
+
+def _check_int(y, ref, what):
+    assert measure.equal_ignoring_zero_sign(y, ref["y_plain"]), what
+
+
+def _check_structure(A, m, n, row, col, val):
+    cr, cc, cv, _ = spmv.canonical_coo(m, n, row, col, val)
+    if A.format == "csbh":
+        formats.check_csbh(m, n, A.log2_beta, A.export("blk_ptr").cpu().numpy(),
+                           A.export("packed").cpu().numpy().view(np.uint32),
+                           A.export("values").cpu().numpy(), cr, cc, cv)
+    else:
+        formats.check_crs(m, n, A.export("row_ptr").cpu().numpy(),
+                          A.export("col_ind").cpu().numpy(), A.export("values").cpu().numpy(),
+                          cr, cc, cv)
+    assert A.nnz == len(cr)
+
+
+# ---------------------------------------------------------------- hand-made edge cases
+
+
+def _cases():
+    cases = {}
+    n = 37
+    idx = np.arange(n, dtype=np.int32)
+    cases["identity"] = (n, n, idx, idx, np.ones(n))
+    cases["diagonal"] = (n, n, idx, idx, synth.values(n, seed=3))
+    cases["empty_nnz0"] = (9, 5, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    cases["one_by_one"] = (1, 1, np.array([0], np.int32), np.array([0], np.int32), np.array([2.5]))
+    # m != n, one dense row among empty ones (the almost-dense-row case)
+    cases["dense_row"] = (7, 5000, np.full(5000, 4, np.int32), np.arange(5000, dtype=np.int32),
+                          synth.values(5000, seed=4))
+    # heavy repeats of a few coordinates, in scrambled order
+    rng = np.random.default_rng(5)
+    r = rng.integers(0, 3, 4000).astype(np.int32)
+    c = rng.integers(0, 3, 4000).astype(np.int32)
+    cases["repeats"] = (3, 3, r, c, synth.values(4000, seed=5))
+    # explicit zeros and entries whose products are -0
+    cases["zeros"] = (4, 4, np.array([0, 1, 1, 3], np.int32), np.array([1, 1, 2, 3], np.int32),
+                      np.array([0.0, -0.0, 0.0, 1.0]))
+    # a single entry in the last row and column
+    cases["corner"] = (1000, 999, np.array([999], np.int32), np.array([998], np.int32),
+                       np.array([-1.5]))
+    return cases
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("case", sorted(_cases()))
+def test_handmade(spx, fmt, case):
+    m, n, row, col, val = _cases()[case]
+    say("handmade", case, fmt, m, n, len(row))
+    x = synth.xvec(n, seed=7)
+    x[::5] = -x[::5]
+    ref = spmv.reference(m, n, row, col, val, x)
+    A, y = _run(spx, fmt, m, n, row, col, val, x)
+    _check_float(y, ref, case)
+    _check_structure(A, m, n, row, col, val)
+    # empty rows are +0 exactly
+    empty = np.diff(ref["row_ptr"]) == 0
+    assert np.all(y[empty] == 0.0) and not np.any(np.signbit(y[empty]))
+
+
+# ---------------------------------------------------------------- R-MAT scale 14 (float and integer)
+
+
+@pytest.fixture(scope="module")
+def rmat14():
+    m = n = 1 << 14
+    row, col = synth.rmat(14, 16, seed=0)
+    out = {}
+    for kind in ("float", "int"):
+        val = synth.values(len(row), seed=0, kind=kind)
+        x = synth.xvec(n, seed=0, kind=kind)
+        out[kind] = (val, x, spmv.reference(m, n, row, col, val, x))
+    return m, n, row, col, out
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_rmat14_float(spx, rmat14, fmt):
+    m, n, row, col, d = rmat14
+    val, x, ref = d["float"]
+    say("rmat14 float", fmt)
+    A, y = _run(spx, fmt, m, n, row, col, val, x)
+    worst = _check_float(y, ref, "rmat14 " + fmt)
+    say("  max scaled error %.3g, parts %d" % (worst, A.parts))
+    _check_structure(A, m, n, row, col, val)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_rmat14_int_bit_exact(spx, rmat14, fmt):
+    m, n, row, col, d = rmat14
+    val, x, ref = d["int"]
+    say("rmat14 int", fmt)
+    A, y = _run(spx, fmt, m, n, row, col, val, x)
+    _check_int(y, ref, "rmat14 int " + fmt)
+    _check_structure(A, m, n, row, col, val)
+
+
+def test_merge_tile_starts_match_oracle(spx, rmat14):
+    import torch
+    m, n, row, col, d = rmat14
+    val, x, ref = d["int"]
+    A = spx.convert(_dev(row, torch.int32), _dev(col, torch.int32), _dev(val, torch.float64),
+                    (m, n), "merge")
+    coords = A.export("parts").cpu().numpy().reshape(-1, 2)
+    tile = 2048
+    rp = ref["row_ptr"]
+    want = mergepath.splits(list(rp[1:]), list(range(int(rp[-1]))), tile)
+    assert [tuple(c) for c in coords.tolist()] == [tuple(w) for w in want]
+
+
+# ---------------------------------------------------------------- ragged sizes, long rows, many tiles
+
+
+def _ragged_matrix(seed, m, n, E, long_rows=()):
+    rng = np.random.default_rng(seed)
+    row = rng.integers(0, m, E).astype(np.int32)
+    col = rng.integers(0, n, E).astype(np.int32)
+    parts_r = [row]
+    parts_c = [col]
+    for r, length in long_rows:
+        parts_r.append(np.full(length, r, np.int32))
+        parts_c.append(rng.integers(0, n, length).astype(np.int32))
+    row = np.concatenate(parts_r)
+    col = np.concatenate(parts_c)
+    p = rng.permutation(len(row))
+    return row[p], col[p]
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("kind", ["float", "int"])
+def test_ragged_long_rows(spx, fmt, kind):
+    # rows far longer than a row block, a merge tile and a row-split chunk, beside short rows,
+    # with sizes that are not multiples of any tile
+    m, n = 5003, 7777
+    row, col = _ragged_matrix(11, m, n, 150_001,
+                              long_rows=[(0, 30_000), (2500, 1500), (5002, 20_000), (17, 9000)])
+    val = synth.values(len(row), seed=12, kind=kind)
+    x = synth.xvec(n, seed=13, kind=kind)
+    say("ragged", fmt, kind, len(row))
+    ref = spmv.reference(m, n, row, col, val, x)
+    A, y = _run(spx, fmt, m, n, row, col, val, x)
+    if kind == "int":
+        _check_int(y, ref, "ragged int " + fmt)
+    else:
+        _check_float(y, ref, "ragged " + fmt)
+    _check_structure(A, m, n, row, col, val)
+
+
+@pytest.mark.parametrize("log2_beta,unit", [(1, 0), (4, 64), (6, 1000), (9, 5000), (13, 0)])
+def test_csbh_block_sizes_and_split_rows(spx, log2_beta, unit):
+    # small units force block rows to be split into several units with partial slices
+    m, n = 3001, 4099
+    row, col = _ragged_matrix(21, m, n, 60_000, long_rows=[(100, 12_000)])
+    val = synth.values(len(row), seed=22, kind="int")
+    x = synth.xvec(n, seed=23, kind="int")
+    say("csbh beta", log2_beta, "unit", unit)
+    ref = spmv.reference(m, n, row, col, val, x)
+    A, y = _run(spx, "csbh", m, n, row, col, val, x, log2_beta=log2_beta, tile_items=unit)
+    assert A.log2_beta == log2_beta
+    _check_int(y, ref, "csbh int beta %d" % log2_beta)
+    _check_structure(A, m, n, row, col, val)
+
+
+def test_csbh_default_block_size_rule(spx, rmat14):
+    import torch
+    m, n, row, col, d = rmat14
+    A = spx.convert(_dev(row, torch.int32), _dev(col, torch.int32),
+                    _dev(d["float"][0], torch.float64), (m, n), "csbh")
+    assert A.log2_beta == measure.csb_log2_beta(m, n) == 10
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_keep_repeats_option(spx, fmt):
+    # sum_duplicates=False keeps each triplet as a stored entry; y is unchanged
+    m, n = 300, 200
+    row, col = _ragged_matrix(31, m, n, 20_000)
+    val = synth.values(len(row), seed=32, kind="int")
+    x = synth.xvec(n, seed=33, kind="int")
+    ref = spmv.reference(m, n, row, col, val, x)
+    A, y = _run(spx, fmt, m, n, row, col, val, x, sum_duplicates=False)
+    assert A.nnz == len(row)
+    _check_int(y, ref, "keep repeats " + fmt)
+
+
+# ---------------------------------------------------------------- invariants
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_permutation_and_order_invariance_int(spx, fmt):
+    m = n = 1 << 12
+    row, col = synth.rmat(12, 16, seed=41)
+    val = synth.values(len(row), seed=41, kind="int")
+    x = synth.xvec(n, seed=41, kind="int")
+    _, y = _run(spx, fmt, m, n, row, col, val, x)
+    # (P A Q^T)(Q x) = P (A x)
+    P = synth.permutation(m, seed=42)
+    Q = synth.permutation(n, seed=43)
+    Pinv = np.empty_like(P)
+    Pinv[P] = np.arange(m)
+    Qinv = np.empty_like(Q)
+    Qinv[Q] = np.arange(n)
+    _, y2 = _run(spx, fmt, m, n, Pinv[row].astype(np.int32), Qinv[col].astype(np.int32), val,
+                 x[Q])
+    assert measure.equal_ignoring_zero_sign(y2, y[P])
+    # shuffled triplet order: same stored matrix, same y
+    S = synth.permutation(len(row), seed=44)
+    _, y3 = _run(spx, fmt, m, n, row[S], col[S], val[S], x)
+    assert measure.equal_ignoring_zero_sign(y3, y)
+    # A 1 = row sums
+    ones = np.ones(n)
+    _, y4 = _run(spx, fmt, m, n, row, col, val, ones)
+    sums = np.zeros(m)
+    np.add.at(sums, row, val)
+    assert measure.equal_ignoring_zero_sign(y4, sums)
+
+
+@pytest.mark.parametrize("fmt", ["rowsplit", "merge"])
+def test_repeat_runs_bitwise_identical(spx, rmat14, fmt):
+    import torch
+    m, n, row, col, d = rmat14
+    val, x, _ = d["float"]
+    A = spx.convert(_dev(row, torch.int32), _dev(col, torch.int32), _dev(val, torch.float64),
+                    (m, n), fmt)
+    xd = _dev(x, torch.float64)
+    y1 = A.spmv(xd).cpu().numpy()
+    y2 = A.spmv(xd).cpu().numpy()
+    assert np.array_equal(y1.view(np.int64), y2.view(np.int64))
+
+
+def test_linearity_float(spx, rmat14):
+    import torch
+    m, n, row, col, d = rmat14
+    val, x1, ref1 = d["float"]
+    x2 = synth.values(n, seed=99)
+    for fmt in FMTS:
+        A = spx.convert(_dev(row, torch.int32), _dev(col, torch.int32), _dev(val, torch.float64),
+                        (m, n), fmt)
+        y1 = A.spmv(_dev(x1, torch.float64)).cpu().numpy()
+        y2 = A.spmv(_dev(x2, torch.float64)).cpu().numpy()
+        y12 = A.spmv(_dev(2 * x1 - 3 * x2, torch.float64)).cpu().numpy()
+        s = ref1["scale"]
+        _, _, s2 = spmv.alg1_accurate(ref1["row_ptr"], ref1["col"], ref1["val"], x2)
+        assert np.all(np.abs(y12 - (2 * y1 - 3 * y2)) <= 1e-12 * (2 * s + 3 * s2) + 1e-300)
+
+
+# ---------------------------------------------------------------- errors through the ABI
+
+
+def test_error_paths(spx):
+    import torch
+    row = _dev(np.array([0, 5], np.int32), torch.int32)
+    col = _dev(np.array([0, 1], np.int32), torch.int32)
+    val = _dev(np.array([1.0, 2.0]), torch.float64)
+    with pytest.raises(spx.SpxError) as e:
+        spx.convert(row, col, val, (5, 5), "merge")
+    assert e.value.name == "SPX_ERR_INDEX"
+    with pytest.raises(spx.SpxError) as e:
+        spx.convert(_dev(np.array([0, -1], np.int32), torch.int32), col, val, (5, 5), "csbh")
+    assert e.value.name == "SPX_ERR_INDEX"
+    A = spx.convert(_dev(np.array([0, 4], np.int32), torch.int32), col, val, (5, 5), "rowsplit")
+    buf = torch.zeros(10, dtype=torch.float64, device="cuda")
+    with pytest.raises(spx.SpxError) as e:
+        A.spmv(buf[0:5], out=buf[3:8])
+    assert e.value.name == "SPX_ERR_ALIAS"
+    with pytest.raises(TypeError):
+        A.spmv(torch.zeros(5, dtype=torch.float32, device="cuda"))
+    with pytest.raises(spx.SpxError):
+        A.export("blk_ptr")
+    A.close()
+    with pytest.raises(RuntimeError):
+        A.spmv(buf[0:5])
+
+
+def test_report_and_info(spx, rmat14):
+    import torch
+    m, n, row, col, d = rmat14
+    val = d["float"][0]
+    for fmt in FMTS:
+        A = spx.convert(_dev(row, torch.int32), _dev(col, torch.int32), _dev(val, torch.float64),
+                        (m, n), fmt)
+        assert A.convert_ms > 0
+        assert A.nnz == len(d["float"][2]["col"])
+        assert A.bytes >= A.nnz * 12
+        assert A.parts > 0
