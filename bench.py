@@ -1,0 +1,312 @@
+#!/usr/bin/env python3
+"""SpMV benchmark on one MI355X: prints one JSON line.
+
+One step = one pass of the whole path over the resident triplets of the workload:
+  convert triplets -> row-split CRS, merge-path CRS and CSBH (validate, sort keys, radix sort,
+  sum repeats, offsets, work-unit tables), one y = A x in each format, and the conversion report
+  (conversion time and break-even count against row-split CRS).
+value = useful SpMV flops of the step (3 products x 2 nnz) / step time.
+
+Beside the step, each format's product is also timed alone (the steady state of a resident
+matrix, 10 warm-up and --spmv-reps timed products, minimum and median as in the paper's
+protocol), and its main kernel is set against the HBM roofline with the bytes model
+  B = 12 nnz + 4 (m+1) + 8 n_touched + 8 m (+ format-specific tables).
+Kernel durations come from the library's HIP-event profiler (events on the launch stream).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+METRIC = "SpMV GFLOP/s + % HBM roofline (R-MAT s24); served p99 latency at req/s"
+FMTS = ("rowsplit", "merge", "csbh")
+# kernel that does the product's work in each format
+SPMV_KERNEL = {"rowsplit": "spmv_rowsplit", "merge": "spmv_merge", "csbh": "spmv_csbh"}
+WORKLOADS = {
+    "rmat24": "R-MAT scale 24 (m = n = 16,777,216), edge factor 16 (268,435,456 raw entries), "
+              "(a,b,c,d) = (0.57,0.19,0.19,0.05), repeats summed, FP64 values and x U(-1,1), "
+              "int32 indices, seed 0",
+    "chunglu": "Chung-Lu power law, gamma 2.1, n = 10,000,000, 200,000,000 raw entries, repeats "
+               "summed, FP64 values and x U(-1,1), int32 indices, seed 0",
+    "rmat14": "R-MAT scale 14 (m = n = 16,384), edge factor 16, (a,b,c,d) = "
+              "(0.57,0.19,0.19,0.05), FP64 values and x U(-1,1), seed 0",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2502_19284_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def spmv_bytes(fmt, m, nnz, n_touched, A):
+    """Algorithmic bytes of one product (matrix read once, x touched columns once, y once)."""
+    b = 12 * nnz + 8 * n_touched + 8 * m
+    if fmt in ("rowsplit", "merge"):
+        b += 4 * (m + 1)
+    if fmt == "merge":
+        b += 8 * (A.parts + 1) + 12 * A.parts  # tile starts, carry rows and values
+    if fmt == "rowsplit":
+        b += 4 * (A.parts + 1)
+    if fmt == "csbh":
+        beta = 1 << A.log2_beta
+        nbr = (m + beta - 1) // beta
+        nbc = (A.shape[1] + beta - 1) // beta
+        b += 4 * (nbr * nbc + 1) + 16 * A.parts
+    return b
+
+
+def kernel_bytes(name, E, nnz, m, passes):
+    """Algorithmic bytes per launch of conversion kernels (None when not modelled)."""
+    if name == "rsort_downsweep":
+        # read key + payload, write key + payload; the first pass has an implicit payload
+        return E * (24 * passes - 4) / passes
+    if name == "rsort_upsweep":
+        return 8 * E
+    if name == "keys":
+        return 16 * E
+    if name == "gather":
+        return 20 * E + 16 * nnz
+    return None
+
+
+def copy_probe(torch, nbytes=2 << 30, reps=20):
+    """Plain device-to-device copy (torch) as the achievable-bandwidth reference: GB/s counting
+    read + write."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    best = 1e30
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return 2 * nbytes / (best * 1e-3) / 1e9
+
+
+def cpu_baseline(w, budget_s=12.0):
+    """The oracle's Algorithm 1 (sequential, as printed) on a bounded sample of the same matrix:
+    the rows whose index hashes into 1/8 of the range.  Only the product is timed."""
+    import numpy as np
+
+    from oracle import spmv as ref
+    m, n = w["m"], w["n"]
+    rows = np.arange(m, dtype=np.uint64)
+    keep = ((rows * np.uint64(2654435761)) & np.uint64(0xFFFFFFFF)) < np.uint64(1 << 29)
+    sel = keep[w["row"]]
+    r = w["row"][sel]
+    local = (np.cumsum(keep) - 1)[r].astype(np.int32)
+    nrows = int(keep.sum())
+    rp, c, v = ref.crs(nrows, n, local, w["col"][sel], w["val"][sel])
+    nnz = int(rp[-1])
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        ref.alg1(rp, c, v, w["x"])
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start > budget_s or len(times) >= 50:
+            break
+    best = min(times)
+    return {"value": round(2 * nnz / best / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "oracle Algorithm 1 (sequential, plain FP64) on the %d rows (1/8 of the "
+                      "rows, chosen by a multiplicative hash of the row index) holding %d of "
+                      "the workload's stored entries; minimum of %d runs, %.1f s of timed CPU work"
+                      % (nrows, nnz, len(times), sum(times)),
+            "ms_min": round(best * 1e3, 3), "ms_median": round(statistics.median(times) * 1e3, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
+    ap.add_argument("--spmv-reps", type=int, default=100)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--formats", default=",".join(FMTS))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus %d is not supported (the multi-GPU "
+              "sharding is described in DESIGN.md, not run)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    fmts = [f for f in args.formats.split(",") if f]
+
+    import numpy as np
+    import torch
+
+    import paper_2502_19284_amd as spx
+    import synth
+    if not os.path.exists(spx.LIB_PATH):
+        from paper_2502_19284_amd import build as spx_build
+        spx_build.build()
+    spx.load()
+    torch.cuda.set_device(0)
+    spx.use_torch_allocator(True)
+
+    t0 = time.perf_counter()
+    w = synth.workload(args.workload, seed=0)
+    m, n, E = w["m"], w["n"], len(w["row"])
+    log("generated %s: m=%d n=%d raw=%d in %.1f s" % (args.workload, m, n, E,
+                                                       time.perf_counter() - t0))
+    n_touched = int(np.count_nonzero(np.bincount(w["col"], minlength=n)))
+    dev = lambda a, t: torch.from_numpy(a).to("cuda", dtype=t)
+    row_d, col_d = dev(w["row"], torch.int32), dev(w["col"], torch.int32)
+    val_d, x_d = dev(w["val"], torch.float64), dev(w["x"], torch.float64)
+    ybuf = {f: torch.empty(m, dtype=torch.float64, device="cuda") for f in fmts}
+    torch.cuda.synchronize()
+    copy_gbs = copy_probe(torch)
+    log("copy probe %.0f GB/s" % copy_gbs)
+
+    conv_ms = {f: [] for f in fmts}
+    spmv_ms = {f: [] for f in fmts}
+    info = {}
+
+    def step(record):
+        for f in fmts:
+            A = spx.convert(row_d, col_d, val_d, (m, n), f)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            A.spmv(x_d, out=ybuf[f])
+            e1.record()
+            if record:
+                e1.synchronize()
+                conv_ms[f].append(A.convert_ms)
+                spmv_ms[f].append(e0.elapsed_time(e1))
+                info[f] = dict(nnz=A.nnz, parts=A.parts, log2_beta=A.log2_beta, bytes=A.bytes)
+            A.close()
+
+    for i in range(args.warmup):
+        step(False)
+        log("warmup step %d done" % (i + 1))
+    torch.cuda.synchronize()
+    spx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+        log("step %d done" % (i + 1))
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    kstats = spx.profile_collect()
+    spx.profile_enable(False)
+    nnz = info[fmts[0]]["nnz"]
+    ms_per_step = t_steps / args.steps * 1e3
+    value = len(fmts) * 2.0 * nnz / (ms_per_step * 1e-3) / 1e9
+
+    # dominant kernel of the step
+    dom = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
+    converts = args.steps * len(fmts)
+    passes = kstats.get("rsort_downsweep", {}).get("launches", 0) / max(converts, 1)
+    dom_bytes = kernel_bytes(dom[0], E, nnz, m, passes if passes else 1)
+    roofline = None
+    if dom_bytes is not None:
+        ach = dom_bytes / (dom[1]["avg_ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": dom[0], "avg_ms": round(dom[1]["avg_ms"], 4),
+                    "launches": dom[1]["launches"], "bytes_per_launch": int(dom_bytes),
+                    "share_of_step": round(dom[1]["total_ms"] / (t_steps * 1e3), 3)}
+
+    # steady-state product of a resident matrix, per format
+    spmv = {}
+    for f in fmts:
+        A = spx.convert(row_d, col_d, val_d, (m, n), f)
+        for _ in range(10):
+            A.spmv(x_d, out=ybuf[f])
+        torch.cuda.synchronize()
+        spx.profile_enable(True)
+        times = []
+        for _ in range(args.spmv_reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            A.spmv(x_d, out=ybuf[f])
+            e1.record()
+            times.append((e0, e1))
+        torch.cuda.synchronize()
+        ks = spx.profile_collect()
+        spx.profile_enable(False)
+        ms = [a.elapsed_time(b) for a, b in times]
+        kname = SPMV_KERNEL[f]
+        kavg = ks[kname]["avg_ms"]
+        kmin = ks[kname]["min_ms"]
+        B = spmv_bytes(f, m, A.nnz, n_touched, A)
+        ach = B / (kavg * 1e-3) / 1e9
+        spmv[f] = {
+            "ms_min": round(min(ms), 4), "ms_median": round(statistics.median(ms), 4),
+            "gflops_min_time": round(2 * A.nnz / (min(ms) * 1e-3) / 1e9, 1),
+            "gflops_median_time": round(2 * A.nnz / (statistics.median(ms) * 1e-3) / 1e9, 1),
+            "kernels": {k: round(v["avg_ms"], 4) for k, v in ks.items()},
+            "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "frac_of_copy": round(ach / copy_gbs, 4), "bytes_per_launch": int(B),
+                         "avg_ms": round(kavg, 4), "min_ms": round(kmin, 4)},
+            "parts": A.parts, "log2_beta": A.log2_beta,
+        }
+        log("spmv %-8s median %.4f ms  %.1f GFLOP/s  kernel %.4f ms  %.1f%% of HBM peak"
+            % (f, statistics.median(ms), spmv[f]["gflops_median_time"], kavg, 100 * ach / HBM_PEAK_GBS))
+        A.close()
+
+    conv = {f: {"ms_min": round(min(conv_ms[f]), 3),
+                "ms_median": round(statistics.median(conv_ms[f]), 3)} for f in fmts}
+    be = {}
+    if "rowsplit" in fmts:
+        ref_conv = conv["rowsplit"]["ms_min"]
+        ref_spmv = spmv["rowsplit"]["ms_min"]
+        for f in fmts:
+            conv[f]["in_rowsplit_products"] = round(conv[f]["ms_min"] / ref_spmv, 1)
+            if f != "rowsplit":
+                N = spx.break_even(conv[f]["ms_min"], ref_conv, ref_spmv, spmv[f]["ms_min"])
+                be[f] = None if math.isinf(N) else round(N, 1)
+
+    best = max(fmts, key=lambda f: spmv[f]["gflops_median_time"])
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "m": m, "n": n, "raw_entries": E,
+                   "nnz": nnz, "n_touched_columns": n_touched, "formats": fmts,
+                   "step": "convert triplets to each format, one y = A x per format, "
+                           "conversion report"},
+        "roofline": roofline,
+        "spmv_steady": {"best_format": best,
+                        "gflops": spmv[best]["gflops_median_time"],
+                        "hbm_frac": spmv[best]["roofline"]["frac"]},
+        "spmv": spmv, "convert": conv, "break_even_vs_rowsplit": be,
+        "copy_probe_gbs": round(copy_gbs, 1),
+        "step_kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in kstats.items()},
+        "kernel_src": src_hash("k_spmv.hip", "k_convert.hip"),
+    }
+    if args.cpu_baseline:
+        del row_d, col_d, val_d
+        torch.cuda.empty_cache()
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -166,6 +166,25 @@ double spx_break_even(double conv_fmt, double conv_ref, double spmv_ref, double 
  * hipFree).  Affects allocations made after the call; not thread-safe against running calls. */
 spx_status spx_set_allocator(spx_alloc_fn alloc, spx_free_fn free_fn, void* ctx);
 
+/*
+ * Per-kernel timing (measurement aid; the paper reports minimum times over repeated runs,
+ * Section 5.2).  While enabled, every kernel the library launches is bracketed by HIP events on
+ * its launch stream.  spx_profile_enable clears the statistics; spx_profile_collect waits for the
+ * recorded events and returns one record per kernel name (sorted by name).
+ */
+typedef struct {
+    char name[48];     /* kernel name                        */
+    int64_t launches;  /* launches recorded since enabling   */
+    double total_ms;   /* summed event-to-event durations    */
+    double min_ms;
+    double max_ms;
+} spx_kernel_stat;
+
+spx_status spx_profile_enable(int32_t enable);
+/* out: host array of `max` records (may be NULL when max == 0); *count receives the number of
+ * kernels recorded, which may exceed max. */
+spx_status spx_profile_collect(spx_kernel_stat* out, int32_t max, int32_t* count);
+
 /* Static text for a status code. */
 const char* spx_status_string(spx_status s);
 

@@ -6,4 +6,5 @@ compressed sparse blocks in Hilbert order (CSBH), with conversion from triplets 
 sort.  The C ABI is include/spx.h; this package is its thin Python binding.
 """
 from .spx import (ARRAYS, FORMATS, LIB_PATH, Matrix, SpxError, break_even, convert,  # noqa: F401
-                  header_functions, load, use_torch_allocator, version)
+                  header_functions, load, profile_collect, profile_enable, use_torch_allocator,
+                  version)

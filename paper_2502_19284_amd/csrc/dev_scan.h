@@ -10,6 +10,7 @@
 // Between phase 2 and 3 the caller may read the total back to size the output.
 #pragma once
 #include "dev_common.h"
+#include "spx_prof.h"
 
 #define SCAN_NT 256
 #define SCAN_IPT 16
@@ -112,9 +113,9 @@ static inline hipError_t scan_phase12(Load ld, int64_t n, T* tile_sums, T* total
                                       hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const unsigned nt = spx_div_up(n, SCAN_TILE);
-    hipLaunchKernelGGL((scan_tile_reduce<T, Op, Load>), dim3(nt), dim3(SCAN_NT), 0, s, ld, n,
+    SPX_LAUNCH("scan_tile_reduce", (scan_tile_reduce<T, Op, Load>), dim3(nt), dim3(SCAN_NT), 0, s, ld, n,
                        tile_sums);
-    hipLaunchKernelGGL((scan_tile_sums<T, Op>), dim3(1), dim3(SCAN_NT), 0, s, tile_sums,
+    SPX_LAUNCH("scan_tile_sums", (scan_tile_sums<T, Op>), dim3(1), dim3(SCAN_NT), 0, s, tile_sums,
                        (int64_t)nt, total);
     return hipGetLastError();
 }
@@ -124,7 +125,7 @@ static inline hipError_t scan_phase3(Load ld, Store st, int64_t n, const T* tile
                                      hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const unsigned nt = spx_div_up(n, SCAN_TILE);
-    hipLaunchKernelGGL((scan_tile_apply<T, Op, Load, Store>), dim3(nt), dim3(SCAN_NT), 0, s, ld,
+    SPX_LAUNCH("scan_tile_apply", (scan_tile_apply<T, Op, Load, Store>), dim3(nt), dim3(SCAN_NT), 0, s, ld,
                        st, n, tile_sums);
     return hipGetLastError();
 }

@@ -25,7 +25,7 @@ static unsigned grid_for(int64_t n, int nt, unsigned cap = 1u << 20) {
 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+    SPX_LAUNCH("fill_i32", k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 
@@ -38,7 +38,7 @@ __global__ void k_init_readback(Readback* rb) {
 }
 
 hipError_t launch_init_readback(Readback* rb, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_readback, dim3(1), dim3(1), 0, s, rb);
+    SPX_LAUNCH("init_readback", k_init_readback, dim3(1), dim3(1), 0, s, rb);
     return hipGetLastError();
 }
 
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_keys(const int32_t* row, const int32_t*
 hipError_t launch_keys_csr(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
                            int32_t n, int cbits, uint64_t* keys, uint32_t* err,
                            unsigned long long* masks, hipStream_t s) {
-    hipLaunchKernelGGL((k_keys<KeyCsr>), dim3(grid_for(E, 256, 1u << 16)), dim3(256), 0, s, row,
+    SPX_LAUNCH("keys", (k_keys<KeyCsr>), dim3(grid_for(E, 256, 1u << 16)), dim3(256), 0, s, row,
                        col, E, m, n, keys, err, masks, KeyCsr{cbits});
     return hipGetLastError();
 }
@@ -155,7 +155,7 @@ hipError_t launch_keys_csr(const int32_t* row, const int32_t* col, int64_t E, in
 hipError_t launch_keys_csbh(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
                             int32_t n, int k, int64_t nbc, uint64_t* keys, uint32_t* err,
                             unsigned long long* masks, hipStream_t s) {
-    hipLaunchKernelGGL((k_keys<KeyCsbh>), dim3(grid_for(E, 256, 1u << 16)), dim3(256), 0, s,
+    SPX_LAUNCH("keys", (k_keys<KeyCsbh>), dim3(grid_for(E, 256, 1u << 16)), dim3(256), 0, s,
                        row, col, E, m, n, keys, err, masks, KeyCsbh{k, (uint64_t)nbc});
     return hipGetLastError();
 }
@@ -309,7 +309,7 @@ hipError_t radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* 
     bool second = false;
     for (int shift = 0; shift < 64; shift += RS_RADIX_BITS) {
         if (((vary >> shift) & 0xFFull) == 0) continue;
-        hipLaunchKernelGGL(k_rsort_upsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0, s, kin, E,
+        SPX_LAUNCH("rsort_upsweep", k_rsort_upsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0, s, kin, E,
                            shift, hist, tiles);
         hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32{hist}, hn, tile_sums,
                                                                (uint32_t*)nullptr, s);
@@ -317,7 +317,7 @@ hipError_t radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* 
         e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32{hist}, StoreExclU32{hist}, hn,
                                                    tile_sums, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_rsort_downsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0, s, kin,
+        SPX_LAUNCH("rsort_downsweep", k_rsort_downsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0, s, kin,
                            vin, kout, vout, E, shift, hist, tiles);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -332,7 +332,7 @@ hipError_t radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* 
         second = !second;
     }
     if (vin == nullptr) {  // no pass ran: keys already in order, payload is the identity
-        hipLaunchKernelGGL(k_iota_u32, dim3(grid_for(E, 256)), dim3(256), 0, s, v0, E);
+        SPX_LAUNCH("iota_u32", k_iota_u32, dim3(grid_for(E, 256)), dim3(256), 0, s, v0, E);
         second = false;
     }
     *in_second = second;
@@ -404,7 +404,7 @@ hipError_t launch_gather_csr(const uint64_t* keys, const uint32_t* perm, const d
                              const int32_t* head_pos, int64_t E, int64_t nnz_out, int cbits,
                              int32_t* col_out, double* val_out, int32_t* row_end, hipStream_t s) {
     if (nnz_out <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_gather<false>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
+    SPX_LAUNCH("gather", (k_gather<false>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
                        perm, val_in, head_pos, E, nnz_out, cbits, col_out, val_out, row_end);
     return hipGetLastError();
 }
@@ -414,7 +414,7 @@ hipError_t launch_gather_csbh(const uint64_t* keys, const uint32_t* perm, const 
                               uint32_t* packed_out, double* val_out, int32_t* blk_end,
                               hipStream_t s) {
     if (nnz_out <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_gather<true>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
+    SPX_LAUNCH("gather", (k_gather<true>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
                        perm, val_in, head_pos, E, nnz_out, 2 * k, (int32_t*)packed_out, val_out,
                        blk_end);
     return hipGetLastError();

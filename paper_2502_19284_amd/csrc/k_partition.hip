@@ -34,7 +34,7 @@ __global__ void k_merge_coords(const int32_t* __restrict__ row_ptr, int32_t m, i
 hipError_t launch_merge_coords(const int32_t* row_ptr, int32_t m, int64_t nnz, int2* coords,
                                int32_t tiles, hipStream_t s) {
     const unsigned g = spx_div_up((int64_t)tiles + 1, 256);
-    hipLaunchKernelGGL(k_merge_coords, dim3(g), dim3(256), 0, s, row_ptr, m, nnz, coords, tiles);
+    SPX_LAUNCH("merge_coords", k_merge_coords, dim3(g), dim3(256), 0, s, row_ptr, m, nnz, coords, tiles);
     return hipGetLastError();
 }
 
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void k_csbh_plan(const int32_t* __restrict__ b
 hipError_t csbh_plan(const int32_t* blk_ptr, int64_t nbr, int64_t nbc, int64_t unit_nnz,
                      int32_t* unit_ptr, int32_t* slot_ptr, int32_t* split_ptr, uint32_t* totals,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_csbh_plan, dim3(1), dim3(256), 0, s, blk_ptr, nbr, nbc, unit_nnz,
+    SPX_LAUNCH("csbh_plan", k_csbh_plan, dim3(1), dim3(256), 0, s, blk_ptr, nbr, nbc, unit_nnz,
                        unit_ptr, slot_ptr, split_ptr, totals);
     return hipGetLastError();
 }
@@ -194,7 +194,7 @@ __global__ void k_csbh_units(const int32_t* __restrict__ blk_ptr, int64_t nbr, i
 hipError_t csbh_units(const int32_t* blk_ptr, int64_t nbr, int64_t nbc, int64_t unit_nnz,
                       const int32_t* unit_ptr, const int32_t* slot_ptr, const int32_t* split_ptr,
                       int4* units, int4* split, hipStream_t s) {
-    hipLaunchKernelGGL(k_csbh_units, dim3(spx_div_up(nbr, 256)), dim3(256), 0, s, blk_ptr, nbr,
+    SPX_LAUNCH("csbh_units", k_csbh_units, dim3(spx_div_up(nbr, 256)), dim3(256), 0, s, blk_ptr, nbr,
                        nbc, unit_nnz, unit_ptr, slot_ptr, split_ptr, units, split);
     return hipGetLastError();
 }

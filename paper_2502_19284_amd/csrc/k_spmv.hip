@@ -166,9 +166,9 @@ __global__ void k_spmv_merge_fixup(const int32_t* __restrict__ carry_row,
 
 hipError_t spmv_merge(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
     if (A->mp_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spmv_merge, dim3(A->mp_tiles), dim3(MP_NT), 0, s, A->row_ptr, A->col,
+    SPX_LAUNCH("spmv_merge", k_spmv_merge, dim3(A->mp_tiles), dim3(MP_NT), 0, s, A->row_ptr, A->col,
                        A->val, x, y, A->mp_coords, A->mp_carry_row, A->mp_carry_val, A->m);
-    hipLaunchKernelGGL(k_spmv_merge_fixup, dim3(spx_div_up(A->mp_tiles, 256)), dim3(256), 0, s,
+    SPX_LAUNCH("spmv_merge_fixup", k_spmv_merge_fixup, dim3(spx_div_up(A->mp_tiles, 256)), dim3(256), 0, s,
                        A->mp_carry_row, A->mp_carry_val, A->mp_tiles, y, A->m);
     return hipGetLastError();
 }
@@ -260,13 +260,13 @@ __global__ void k_spmv_rowsplit_finish(const int32_t* __restrict__ long_rows,
 
 hipError_t spmv_rowsplit(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
     if (A->rs_nb > 0)
-        hipLaunchKernelGGL(k_spmv_rowsplit, dim3(A->rs_nb), dim3(RS_NT), 0, s, A->row_ptr, A->col,
+        SPX_LAUNCH("spmv_rowsplit", k_spmv_rowsplit, dim3(A->rs_nb), dim3(RS_NT), 0, s, A->row_ptr, A->col,
                            A->val, x, y, A->rs_blocks);
     if (A->rs_nlong > 0) {
-        hipLaunchKernelGGL(k_spmv_rowsplit_long, dim3(A->rs_nchunks), dim3(RS_NT), 0, s,
+        SPX_LAUNCH("spmv_rowsplit_long", k_spmv_rowsplit_long, dim3(A->rs_nchunks), dim3(RS_NT), 0, s,
                            A->row_ptr, A->col, A->val, x, A->rs_long_rows, A->rs_chunk_ptr,
                            A->rs_nlong, A->rs_partials);
-        hipLaunchKernelGGL(k_spmv_rowsplit_finish, dim3(spx_div_up(A->rs_nlong, 256)), dim3(256),
+        SPX_LAUNCH("spmv_rowsplit_finish", k_spmv_rowsplit_finish, dim3(spx_div_up(A->rs_nlong, 256)), dim3(256),
                            0, s, A->rs_long_rows, A->rs_chunk_ptr, A->rs_nlong, A->rs_partials, y);
     }
     return hipGetLastError();
@@ -368,11 +368,11 @@ hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStrea
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_spmv_csbh, dim3(A->cb_nunits), dim3(CB_NT), lds, s, A->blk_ptr,
+    SPX_LAUNCH("spmv_csbh", k_spmv_csbh, dim3(A->cb_nunits), dim3(CB_NT), lds, s, A->blk_ptr,
                        A->packed, A->val, x, y, A->cb_partials, A->cb_units, A->log2_beta,
                        (int32_t)A->nbc, A->m, stage_bp);
     if (A->cb_nsplit > 0)
-        hipLaunchKernelGGL(k_spmv_csbh_reduce, dim3(A->cb_nsplit), dim3(256), 0, s, A->cb_split,
+        SPX_LAUNCH("spmv_csbh_reduce", k_spmv_csbh_reduce, dim3(A->cb_nsplit), dim3(256), 0, s, A->cb_split,
                            A->cb_partials, y, A->log2_beta, A->m);
     return hipGetLastError();
 }

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "../../include/spx.h"
+#include "spx_prof.h"
 
 // ------------------------------------------------------------------ tuning constants
 // merge-path CRS: threads per tile and items (row ends + entries) per thread

@@ -53,6 +53,12 @@ class MatrixInfo(ctypes.Structure):
                 ("value_type", ctypes.c_int32)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("min_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -82,6 +88,11 @@ def load(path=LIB_PATH):
     for f in (L.spx_convert_opts_default, L.spx_convert, L.spx_spmv, L.spx_matrix_get_info,
               L.spx_matrix_export, L.spx_matrix_destroy, L.spx_set_allocator):
         f.restype = ctypes.c_int32
+    L.spx_profile_enable.argtypes = [ctypes.c_int32]
+    L.spx_profile_enable.restype = ctypes.c_int32
+    L.spx_profile_collect.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32)]
+    L.spx_profile_collect.restype = ctypes.c_int32
     L.spx_break_even.argtypes = [ctypes.c_double] * 4
     L.spx_break_even.restype = ctypes.c_double
     L.spx_status_string.argtypes = [ctypes.c_int32]
@@ -128,6 +139,28 @@ def use_torch_allocator(enable=True):
     refs = (ALLOC_FN(_alloc), FREE_FN(_free))
     _check(L.spx_set_allocator(refs[0], refs[1], None))
     _alloc_refs = refs
+
+
+def profile_enable(enable=True):
+    """Start (clearing earlier records) or stop per-kernel HIP-event timing in the library."""
+    _check(load().spx_profile_enable(1 if enable else 0))
+
+
+def profile_collect():
+    """Per-kernel launch statistics since profile_enable: {name: dict(launches, total_ms,
+    min_ms, max_ms, avg_ms)}.  Waits for the recorded events."""
+    L = load()
+    cnt = ctypes.c_int32(0)
+    _check(L.spx_profile_collect(None, 0, ctypes.byref(cnt)))
+    buf = (KernelStat * max(cnt.value, 1))()
+    _check(L.spx_profile_collect(buf, cnt.value, ctypes.byref(cnt)))
+    out = {}
+    for i in range(cnt.value):
+        s = buf[i]
+        out[s.name.decode()] = dict(launches=int(s.launches), total_ms=s.total_ms,
+                                    min_ms=s.min_ms, max_ms=s.max_ms,
+                                    avg_ms=s.total_ms / max(s.launches, 1))
+    return out
 
 
 def break_even(conv_fmt, conv_ref, spmv_ref, spmv_fmt):
