@@ -71,8 +71,11 @@ typedef struct {
 typedef struct {
     int32_t sum_duplicates; /* 1: sum repeated coordinates (default); 0: keep each as an entry  */
     int32_t log2_beta;      /* CSBH block side 2^log2_beta; 0 = block-size rule (Section 3.1)  */
-    int32_t validate;       /* 1: check every index on the device (default); 0: trust input    */
+    int32_t validate;       /* indices are always checked (fused into the key build); 0 or 1  */
     int32_t tile_items;     /* work per tile/unit; 0 = default for the format                  */
+    int32_t hot_columns;    /* CRS formats: at most this many of the most frequent columns get a
+                             * compact copy of their x values per product (x_hot); -1 = automatic
+                             * (up to 2^20 when n >= 2^19), 0 = off.  y is unchanged by it.      */
 } spx_convert_opts;
 
 typedef struct {
@@ -110,7 +113,8 @@ typedef void (*spx_free_fn)(void* ptr, void* stream, void* ctx);
 
 /* ------------------------------------------------------------------ entry points */
 
-/* Fill *opts with the defaults: sum_duplicates=1, log2_beta=0, validate=1, tile_items=0. */
+/* Fill *opts with the defaults: sum_duplicates=1, log2_beta=0, validate=1, tile_items=0,
+ * hot_columns=-1. */
 spx_status spx_convert_opts_default(spx_convert_opts* opts);
 
 /*

@@ -2,9 +2,9 @@
 //
 // The conversion follows the two steps of Section 5.1: (1) sort the entries into the order the
 // format needs, (2) fill and compress the format's arrays.  Step 1 is a stable LSD radix sort of
-// a 64-bit key with the original triplet index as payload; step 2 sums repeated coordinates in
-// increasing triplet index, gathers values, and turns per-row (per-block) end marks into
-// row_ptr (blk_ptr) with a max-scan.
+// a 64-bit key that carries each triplet's value along; step 2 sums repeated coordinates in
+// increasing triplet index and turns per-row (per-block) end marks into row_ptr (blk_ptr) with a
+// max-scan.
 #include "dev_scan.h"
 #include "spx_internal.h"
 
@@ -110,15 +110,31 @@ __device__ __forceinline__ void keys_body(const int32_t* __restrict__ row,
         orv |= key;
         andv &= key;
     }
+    // one atomic per workgroup (the grid is capped at KEYS_MAX_GRID workgroups)
+    __shared__ unsigned long long s_or[4], s_and[4];
+    __shared__ uint32_t s_bad[4];
     orv = wave_reduce<unsigned long long, OpOr<unsigned long long>>(orv);
     andv = wave_reduce<unsigned long long, OpAnd<unsigned long long>>(andv);
     const uint64_t anybad = __ballot(bad != 0);
+    const int w = threadIdx.x / SPX_WAVE;
     if (__lane_id() == 0) {
+        s_or[w] = orv;
+        s_and[w] = andv;
+        s_bad[w] = anybad ? 1u : 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 4; ++i) {
+            orv |= s_or[i];
+            andv &= s_and[i];
+        }
         atomicOr(&masks[0], orv);
         atomicAnd(&masks[1], andv);
-        if (anybad) atomicOr(err, 1u);
+        if (s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]) atomicOr(err, 1u);
     }
 }
+
+#define KEYS_MAX_GRID 2048
 
 struct KeyCsr {
     int cbits;
@@ -147,7 +163,7 @@ __global__ __launch_bounds__(256) void k_keys(const int32_t* row, const int32_t*
 hipError_t launch_keys_csr(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
                            int32_t n, int cbits, uint64_t* keys, uint32_t* err,
                            unsigned long long* masks, hipStream_t s) {
-    SPX_LAUNCH("keys", (k_keys<KeyCsr>), dim3(grid_for(E, 256, 1u << 16)), dim3(256), 0, s, row,
+    SPX_LAUNCH("keys", (k_keys<KeyCsr>), dim3(grid_for(E, 256, KEYS_MAX_GRID)), dim3(256), 0, s, row,
                        col, E, m, n, keys, err, masks, KeyCsr{cbits});
     return hipGetLastError();
 }
@@ -155,7 +171,7 @@ hipError_t launch_keys_csr(const int32_t* row, const int32_t* col, int64_t E, in
 hipError_t launch_keys_csbh(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
                             int32_t n, int k, int64_t nbc, uint64_t* keys, uint32_t* err,
                             unsigned long long* masks, hipStream_t s) {
-    SPX_LAUNCH("keys", (k_keys<KeyCsbh>), dim3(grid_for(E, 256, 1u << 16)), dim3(256), 0, s,
+    SPX_LAUNCH("keys", (k_keys<KeyCsbh>), dim3(grid_for(E, 256, KEYS_MAX_GRID)), dim3(256), 0, s,
                        row, col, E, m, n, keys, err, masks, KeyCsbh{k, (uint64_t)nbc});
     return hipGetLastError();
 }
@@ -199,15 +215,14 @@ __global__ __launch_bounds__(RSORT_NT) void k_rsort_upsweep(const uint64_t* __re
 }
 
 __global__ __launch_bounds__(RSORT_NT) void k_rsort_downsweep(
-    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t E, int shift,
+    const uint64_t* __restrict__ kin, const uint64_t* __restrict__ vin,
+    uint64_t* __restrict__ kout, uint64_t* __restrict__ vout, int64_t E, int shift,
     const uint32_t* __restrict__ hist, int64_t tiles) {
     __shared__ uint32_t wcnt[RSORT_WAVES][256];
     __shared__ uint32_t dstart[256];
     __shared__ uint32_t goff[256];
     __shared__ uint32_t stmp[RSORT_WAVES];
-    __shared__ uint64_t skey[RSORT_TILE];
-    __shared__ uint32_t sval[RSORT_TILE];
+    __shared__ uint64_t sbuf[RSORT_TILE];  // keys, then payloads, in tile-sorted order
 
     const int tid = threadIdx.x;
     const int w = tid / SPX_WAVE;
@@ -219,14 +234,12 @@ __global__ __launch_bounds__(RSORT_NT) void k_rsort_downsweep(
     const int64_t wave_base = tile_base + (int64_t)w * (RSORT_TILE / RSORT_WAVES);
     const uint64_t lt = spx_lanemask_lt();
     uint64_t key[RSORT_ROUNDS];
-    uint32_t val[RSORT_ROUNDS];
-    uint32_t rank[RSORT_ROUNDS];
+    uint32_t pos[RSORT_ROUNDS];
 #pragma unroll
     for (int r = 0; r < RSORT_ROUNDS; ++r) {
         const int64_t idx = wave_base + r * SPX_WAVE + lane;
         const bool valid = idx < E;
         key[r] = valid ? kin[idx] : 0ull;
-        val[r] = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
         const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -241,7 +254,7 @@ __global__ __launch_bounds__(RSORT_NT) void k_rsort_downsweep(
         __builtin_amdgcn_wave_barrier();
         if (valid && below == 0) wcnt[w][d] = basec + count;
         __builtin_amdgcn_wave_barrier();
-        rank[r] = basec + below;
+        pos[r] = basec + below;
     }
     __syncthreads();
     // per digit: exclusive offsets of the waves, then the tile's exclusive digit starts
@@ -257,32 +270,43 @@ __global__ __launch_bounds__(RSORT_NT) void k_rsort_downsweep(
     dstart[tid] = ex;
     goff[tid] = hist[(int64_t)tid * tiles + blockIdx.x];
     __syncthreads();
+    const int64_t rem = E - tile_base;
+    const int cnt = rem < RSORT_TILE ? (int)rem : RSORT_TILE;
+    // phase 1: keys
 #pragma unroll
     for (int r = 0; r < RSORT_ROUNDS; ++r) {
         const int64_t idx = wave_base + r * SPX_WAVE + lane;
         if (idx < E) {
             const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
-            const uint32_t lp = dstart[d] + wcnt[w][d] + rank[r];
-            skey[lp] = key[r];
-            sval[lp] = val[r];
+            pos[r] += dstart[d] + wcnt[w][d];
+            sbuf[pos[r]] = key[r];
         }
     }
     __syncthreads();
-    const int64_t rem = E - tile_base;
-    const int cnt = rem < RSORT_TILE ? (int)rem : RSORT_TILE;
-    for (int i = tid; i < cnt; i += RSORT_NT) {
-        const uint64_t k = skey[i];
-        const uint32_t d = (uint32_t)(k >> shift) & 255u;
-        const int64_t dst = (int64_t)goff[d] + (i - (int)dstart[d]);
-        kout[dst] = k;
-        vout[dst] = sval[i];
+    uint32_t dst_lo[RSORT_IPT];  // output offset of LDS slot tid + q*NT, reused for the payload
+#pragma unroll
+    for (int q = 0; q < RSORT_IPT; ++q) {
+        const int i = q * RSORT_NT + tid;
+        if (i < cnt) {
+            const uint64_t k = sbuf[i];
+            const uint32_t d = (uint32_t)(k >> shift) & 255u;
+            dst_lo[q] = goff[d] + (uint32_t)(i - (int)dstart[d]);
+            kout[dst_lo[q]] = k;
+        }
     }
-}
-
-__global__ void k_iota_u32(uint32_t* p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = (uint32_t)i;
+    __syncthreads();
+    // phase 2: payloads, through the same LDS slots
+#pragma unroll
+    for (int r = 0; r < RSORT_ROUNDS; ++r) {
+        const int64_t idx = wave_base + r * SPX_WAVE + lane;
+        if (idx < E) sbuf[pos[r]] = vin[idx];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RSORT_IPT; ++q) {
+        const int i = q * RSORT_NT + tid;
+        if (i < cnt) vout[dst_lo[q]] = sbuf[i];
+    }
 }
 
 struct LoadU32 {
@@ -294,48 +318,44 @@ struct StoreExclU32 {
     __device__ void operator()(int64_t i, uint32_t incl, uint32_t item) const { p[i] = incl - item; }
 };
 
-hipError_t radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t E,
-                            uint64_t vary, uint32_t* hist, uint32_t* tile_sums, hipStream_t s,
-                            bool* in_second) {
-    *in_second = false;
+hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1,
+                            const uint64_t* vfirst, int64_t E, uint64_t vary, uint32_t* hist,
+                            uint32_t* tile_sums, hipStream_t s, const uint64_t** keys_sorted,
+                            const uint64_t** vals_sorted) {
+    *keys_sorted = k0;
+    *vals_sorted = vfirst;
     if (E <= 0) return hipSuccess;
     const int64_t tiles = spx_div_up(E, RSORT_TILE);
     const int64_t hn = 256 * tiles;
     uint64_t* kin = k0;
     uint64_t* kout = k1;
-    uint32_t* vin = nullptr;  // first executed pass reads the implicit identity payload
-    uint32_t* vout = v1;
-    uint32_t* vother = v0;
-    bool second = false;
+    const uint64_t* vin = vfirst;  // the first executed pass reads the caller's values
+    uint64_t* vout = v1;
+    uint64_t* vnext = v0;
     for (int shift = 0; shift < 64; shift += RS_RADIX_BITS) {
-        if (((vary >> shift) & 0xFFull) == 0) continue;
-        SPX_LAUNCH("rsort_upsweep", k_rsort_upsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0, s, kin, E,
-                           shift, hist, tiles);
+        if (((vary >> shift) & 0xFFull) == 0) continue;  // digit constant: order unchanged
+        SPX_LAUNCH("rsort_upsweep", k_rsort_upsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0, s,
+                   kin, E, shift, hist, tiles);
         hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32{hist}, hn, tile_sums,
                                                                (uint32_t*)nullptr, s);
         if (e != hipSuccess) return e;
         e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32{hist}, StoreExclU32{hist}, hn,
                                                    tile_sums, s);
         if (e != hipSuccess) return e;
-        SPX_LAUNCH("rsort_downsweep", k_rsort_downsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0, s, kin,
-                           vin, kout, vout, E, shift, hist, tiles);
+        SPX_LAUNCH("rsort_downsweep", k_rsort_downsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0,
+                   s, kin, vin, kout, vout, E, shift, hist, tiles);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        // swap roles
         uint64_t* kt = kin;
         kin = kout;
         kout = kt;
-        uint32_t* vt = vout;
-        vin = vt;
-        vout = vother;
-        vother = vt;
-        second = !second;
+        vin = vout;
+        uint64_t* vt = vout;
+        vout = vnext;
+        vnext = vt;
     }
-    if (vin == nullptr) {  // no pass ran: keys already in order, payload is the identity
-        SPX_LAUNCH("iota_u32", k_iota_u32, dim3(grid_for(E, 256)), dim3(256), 0, s, v0, E);
-        second = false;
-    }
-    *in_second = second;
+    *keys_sorted = kin;
+    *vals_sorted = vin;
     return hipGetLastError();
 }
 
@@ -366,13 +386,12 @@ hipError_t launch_dedup_heads(const uint64_t* keys, int64_t E, const uint32_t* t
 }
 
 // Output entry u covers sorted positions [s, e): s = head_pos[u] (or u without summing), e the
-// next head (or E).  Its value is val[perm[s]] + val[perm[s+1]] + ... in increasing position,
-// which is increasing triplet index because the sort is stable.  The last entry of each row
-// (block) writes u+1 at its row (block), for the max-scan that follows.
+// next head (or E).  Its value is vals[s] + vals[s+1] + ... in increasing position, i.e. in
+// increasing triplet index, because the sort that carried the values is stable.  The last entry
+// of each row (block) writes u+1 at its row (block), for the max-scan that follows.
 template <bool CSBH>
 __global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ keys,
-                                                const uint32_t* __restrict__ perm,
-                                                const double* __restrict__ val_in,
+                                                const double* __restrict__ vals,
                                                 const int32_t* __restrict__ head_pos, int64_t E,
                                                 int64_t nnz_out, int shiftbits,
                                                 int32_t* __restrict__ idx_out,
@@ -383,8 +402,8 @@ __global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ key
         const int64_t s = head_pos ? head_pos[u] : u;
         const int64_t e = head_pos ? (u + 1 < nnz_out ? (int64_t)head_pos[u + 1] : E) : u + 1;
         const uint64_t key = keys[s];
-        double acc = val_in[perm[s]];
-        for (int64_t j = s + 1; j < e; ++j) acc = acc + val_in[perm[j]];
+        double acc = vals[s];
+        for (int64_t j = s + 1; j < e; ++j) acc = acc + vals[j];
         val_out[u] = acc;
         const uint64_t major = key >> shiftbits;
         if (CSBH) {
@@ -400,23 +419,21 @@ __global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ key
     }
 }
 
-hipError_t launch_gather_csr(const uint64_t* keys, const uint32_t* perm, const double* val_in,
-                             const int32_t* head_pos, int64_t E, int64_t nnz_out, int cbits,
-                             int32_t* col_out, double* val_out, int32_t* row_end, hipStream_t s) {
+hipError_t launch_gather_csr(const uint64_t* keys, const double* vals, const int32_t* head_pos,
+                             int64_t E, int64_t nnz_out, int cbits, int32_t* col_out,
+                             double* val_out, int32_t* row_end, hipStream_t s) {
     if (nnz_out <= 0) return hipSuccess;
     SPX_LAUNCH("gather", (k_gather<false>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
-                       perm, val_in, head_pos, E, nnz_out, cbits, col_out, val_out, row_end);
+               vals, head_pos, E, nnz_out, cbits, col_out, val_out, row_end);
     return hipGetLastError();
 }
 
-hipError_t launch_gather_csbh(const uint64_t* keys, const uint32_t* perm, const double* val_in,
-                              const int32_t* head_pos, int64_t E, int64_t nnz_out, int k,
-                              uint32_t* packed_out, double* val_out, int32_t* blk_end,
-                              hipStream_t s) {
+hipError_t launch_gather_csbh(const uint64_t* keys, const double* vals, const int32_t* head_pos,
+                              int64_t E, int64_t nnz_out, int k, uint32_t* packed_out,
+                              double* val_out, int32_t* blk_end, hipStream_t s) {
     if (nnz_out <= 0) return hipSuccess;
     SPX_LAUNCH("gather", (k_gather<true>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
-                       perm, val_in, head_pos, E, nnz_out, 2 * k, (int32_t*)packed_out, val_out,
-                       blk_end);
+               vals, head_pos, E, nnz_out, 2 * k, (int32_t*)packed_out, val_out, blk_end);
     return hipGetLastError();
 }
 

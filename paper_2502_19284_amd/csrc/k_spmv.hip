@@ -8,6 +8,22 @@
 #include "dev_common.h"
 #include "spx_internal.h"
 
+// Streamed once per product: non-temporal loads/stores keep them from displacing x in L2.
+template <typename T>
+__device__ __forceinline__ T ntload(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void ntstore(T* p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+
+// x value of a stored column index: negative indices address the compact hot copy
+__device__ __forceinline__ double xval(const double* __restrict__ x,
+                                       const double* __restrict__ x_hot, int32_t c) {
+    return c < 0 ? x_hot[~c] : x[c];
+}
+
 // ================================================================== merge-path CRS (Section 3.3)
 //
 // Tile t of MP_TILE items covers diagonals [t*MP_TILE, (t+1)*MP_TILE) of the merge of
@@ -28,6 +44,7 @@ __global__ __launch_bounds__(MP_NT) void k_spmv_merge(const int32_t* __restrict_
                                                       const int32_t* __restrict__ col,
                                                       const double* __restrict__ val,
                                                       const double* __restrict__ x,
+                                                      const double* __restrict__ x_hot,
                                                       double* __restrict__ y,
                                                       const int2* __restrict__ coords,
                                                       int32_t* __restrict__ carry_row,
@@ -44,11 +61,11 @@ __global__ __launch_bounds__(MP_NT) void k_spmv_merge(const int32_t* __restrict_
     const int r0 = c0.x, k0 = c0.y;
     const int nrows = c1.x - r0, nnzt = c1.y - k0;
 
-    for (int i = tid; i < nrows; i += MP_NT) s_end[i] = row_ptr[r0 + 1 + i];
+    for (int i = tid; i < nrows; i += MP_NT) s_end[i] = ntload(row_ptr + r0 + 1 + i);
 #pragma unroll
     for (int q = 0; q < MP_IPT; ++q) {
         const int i = q * MP_NT + tid;
-        if (i < nnzt) s_prod[i] = val[k0 + i] * x[col[k0 + i]];
+        if (i < nnzt) s_prod[i] = ntload(val + k0 + i) * xval(x, x_hot, ntload(col + k0 + i));
     }
     __syncthreads();
 
@@ -146,7 +163,7 @@ __global__ __launch_bounds__(MP_NT) void k_spmv_merge(const int32_t* __restrict_
         }
     }
     __syncthreads();
-    for (int q = tid; q < nrows; q += MP_NT) y[r0 + q] = s_prod[q];
+    for (int q = tid; q < nrows; q += MP_NT) ntstore(y + r0 + q, s_prod[q]);
 }
 
 // Adds each tile's open value into y, tiles in order.  The first tile of a run of tiles that
@@ -166,8 +183,10 @@ __global__ void k_spmv_merge_fixup(const int32_t* __restrict__ carry_row,
 
 hipError_t spmv_merge(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
     if (A->mp_tiles <= 0) return hipSuccess;
+    hipError_t e = launch_hot_gather(A->hot_cols, A->nhot, x, A->x_hot, s);
+    if (e != hipSuccess) return e;
     SPX_LAUNCH("spmv_merge", k_spmv_merge, dim3(A->mp_tiles), dim3(MP_NT), 0, s, A->row_ptr, A->col,
-                       A->val, x, y, A->mp_coords, A->mp_carry_row, A->mp_carry_val, A->m);
+               A->val, x, A->x_hot, y, A->mp_coords, A->mp_carry_row, A->mp_carry_val, A->m);
     SPX_LAUNCH("spmv_merge_fixup", k_spmv_merge_fixup, dim3(spx_div_up(A->mp_tiles, 256)), dim3(256), 0, s,
                        A->mp_carry_row, A->mp_carry_val, A->mp_tiles, y, A->m);
     return hipGetLastError();
@@ -186,6 +205,7 @@ __global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit(const int32_t* __restri
                                                          const int32_t* __restrict__ col,
                                                          const double* __restrict__ val,
                                                          const double* __restrict__ x,
+                                                         const double* __restrict__ x_hot,
                                                          double* __restrict__ y,
                                                          const int32_t* __restrict__ blocks) {
     __shared__ double s_prod[RS_NNZ];
@@ -198,11 +218,11 @@ __global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit(const int32_t* __restri
     if (rows == 1 && nnzb > RS_LONG) return;  // long row: chunk kernels
     const bool staged = nnzb <= RS_NNZ && rows <= RS_ROWS;
     if (staged) {
-        for (int i = tid; i <= rows; i += RS_NT) s_rp[i] = row_ptr[rs + i] - base;
+        for (int i = tid; i <= rows; i += RS_NT) s_rp[i] = ntload(row_ptr + rs + i) - base;
 #pragma unroll
         for (int q = 0; q < RS_NNZ / RS_NT; ++q) {
             const int i = q * RS_NT + tid;
-            if (i < nnzb) s_prod[i] = val[base + i] * x[col[base + i]];
+            if (i < nnzb) s_prod[i] = ntload(val + base + i) * xval(x, x_hot, ntload(col + base + i));
         }
         __syncthreads();
     }
@@ -216,7 +236,7 @@ __global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit(const int32_t* __restri
             for (int k = a + gl; k < b; k += g) acc += s_prod[k];
         } else {
             const int a = row_ptr[rs + r], b = row_ptr[rs + r + 1];
-            for (int k = a + gl; k < b; k += g) acc += val[k] * x[col[k]];
+            for (int k = a + gl; k < b; k += g) acc += val[k] * xval(x, x_hot, col[k]);
         }
         for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, SPX_WAVE);
         if (gl == 0) y[rs + r] = acc;
@@ -226,7 +246,7 @@ __global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit(const int32_t* __restri
 __global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit_long(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, const double* __restrict__ x,
-    const int32_t* __restrict__ long_rows, const int32_t* __restrict__ chunk_ptr, int32_t nlong,
+    const double* __restrict__ x_hot, const int32_t* __restrict__ long_rows, const int32_t* __restrict__ chunk_ptr, int32_t nlong,
     double* __restrict__ partials) {
     __shared__ double s_tmp[RS_NT / SPX_WAVE];
     const int c = blockIdx.x;
@@ -240,11 +260,17 @@ __global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit_long(
     const int r = long_rows[lo];
     const int kb = row_ptr[r] + (c - chunk_ptr[lo]) * RS_CHUNK;
     const int ke = min(kb + RS_CHUNK, row_ptr[r + 1]);
-    double acc = 0.0;
-#pragma unroll 4
-    for (int k = kb + threadIdx.x; k < ke; k += RS_NT) acc += val[k] * x[col[k]];
-    acc = block_reduce<RS_NT, double, OpSum<double>>(acc, s_tmp);
-    if (threadIdx.x == 0) partials[c] = acc;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = kb + threadIdx.x;
+    for (; k + 3 * RS_NT < ke; k += 4 * RS_NT) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            acc[q] += ntload(val + k + q * RS_NT) * xval(x, x_hot, ntload(col + k + q * RS_NT));
+    }
+    for (; k < ke; k += RS_NT) acc[0] += ntload(val + k) * xval(x, x_hot, ntload(col + k));
+    double sum = block_reduce<RS_NT, double, OpSum<double>>((acc[0] + acc[1]) + (acc[2] + acc[3]),
+                                                             s_tmp);
+    if (threadIdx.x == 0) partials[c] = sum;
 }
 
 __global__ void k_spmv_rowsplit_finish(const int32_t* __restrict__ long_rows,
@@ -259,12 +285,14 @@ __global__ void k_spmv_rowsplit_finish(const int32_t* __restrict__ long_rows,
 }
 
 hipError_t spmv_rowsplit(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
+    hipError_t e = launch_hot_gather(A->hot_cols, A->nhot, x, A->x_hot, s);
+    if (e != hipSuccess) return e;
     if (A->rs_nb > 0)
-        SPX_LAUNCH("spmv_rowsplit", k_spmv_rowsplit, dim3(A->rs_nb), dim3(RS_NT), 0, s, A->row_ptr, A->col,
-                           A->val, x, y, A->rs_blocks);
+        SPX_LAUNCH("spmv_rowsplit", k_spmv_rowsplit, dim3(A->rs_nb), dim3(RS_NT), 0, s, A->row_ptr,
+                   A->col, A->val, x, A->x_hot, y, A->rs_blocks);
     if (A->rs_nlong > 0) {
         SPX_LAUNCH("spmv_rowsplit_long", k_spmv_rowsplit_long, dim3(A->rs_nchunks), dim3(RS_NT), 0, s,
-                           A->row_ptr, A->col, A->val, x, A->rs_long_rows, A->rs_chunk_ptr,
+                           A->row_ptr, A->col, A->val, x, A->x_hot, A->rs_long_rows, A->rs_chunk_ptr,
                            A->rs_nlong, A->rs_partials);
         SPX_LAUNCH("spmv_rowsplit_finish", k_spmv_rowsplit_finish, dim3(spx_div_up(A->rs_nlong, 256)), dim3(256),
                            0, s, A->rs_long_rows, A->rs_chunk_ptr, A->rs_nlong, A->rs_partials, y);
@@ -325,9 +353,9 @@ __global__ __launch_bounds__(CB_NT) void k_spmv_csbh(const int32_t* __restrict__
                         ++b;
                         next = bp[b + 1];
                     }
-                    const uint32_t p = packed[kk];
+                    const uint32_t p = ntload(packed + kk);
                     const int c = (b << k) + (int)(p & lmask);
-                    atomicAdd(&s_y[p >> 16], val[kk] * x[c]);
+                    atomicAdd(&s_y[p >> 16], ntload(val + kk) * x[c]);
                 }
             }
         }
@@ -336,7 +364,7 @@ __global__ __launch_bounds__(CB_NT) void k_spmv_csbh(const int32_t* __restrict__
     const int row0 = br << k;
     const int rows = min(beta, m - row0);
     if (slot < 0) {
-        for (int i = tid; i < rows; i += CB_NT) y[row0 + i] = s_y[i];
+        for (int i = tid; i < rows; i += CB_NT) ntstore(y + row0 + i, s_y[i]);
     } else {
         double* dst = partials + (int64_t)slot * beta;
         for (int i = tid; i < rows; i += CB_NT) dst[i] = s_y[i];

@@ -148,6 +148,7 @@ extern "C" spx_status spx_convert_opts_default(spx_convert_opts* opts) {
     opts->log2_beta = 0;
     opts->validate = 1;
     opts->tile_items = 0;
+    opts->hot_columns = -1;
     return SPX_OK;
 }
 
@@ -166,10 +167,10 @@ static spx_status sync_read(void* host, const void* dev, size_t bytes, hipStream
     return SPX_OK;
 }
 
-// Sort + sum repeats.  Produces sorted keys/perm, head positions and nnz_out.
+// Sort + sum repeats.  Produces sorted keys and values, head positions and nnz_out.
 struct SortedEntries {
-    uint64_t* keys = nullptr;
-    uint32_t* perm = nullptr;
+    const uint64_t* keys = nullptr;
+    const double* vals = nullptr;
     int32_t* head_pos = nullptr;  // null when repeats are kept
     int64_t nnz_out = 0;
 };
@@ -178,13 +179,13 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
                                  int64_t nbc, int cbits, int sum_dup, hipStream_t s,
                                  SortedEntries* out) {
     const int64_t E = coo->nnz;
-    uint64_t *k0, *k1;
-    uint32_t *v0, *v1, *hist, *tsums;
+    uint64_t *k0, *k1, *v0, *v1;
+    uint32_t *hist, *tsums;
     Readback* rb_dev;
     SPX_TRY(tmp.get(&k0, E, "sort keys"));
     SPX_TRY(tmp.get(&k1, E, "sort keys"));
-    SPX_TRY(tmp.get(&v0, E, "sort payload"));
-    SPX_TRY(tmp.get(&v1, E, "sort payload"));
+    SPX_TRY(tmp.get(&v0, E, "sort values"));
+    SPX_TRY(tmp.get(&v1, E, "sort values"));
     const size_t hn = radix_hist_elems(E);
     SPX_TRY(tmp.get(&hist, hn, "radix histogram"));
     size_t ts = scan_tile_count((int64_t)hn);
@@ -204,10 +205,10 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
     if (rb.err) return fail(SPX_ERR_INDEX, "a triplet index lies outside [0,%d) x [0,%d)", coo->m,
                             coo->n);
     const uint64_t vary = rb.masks[0] ^ rb.masks[1];
-    bool second = false;
-    HIP_TRY(radix_sort_pairs(k0, v0, k1, v1, E, vary, hist, tsums, s, &second));
-    out->keys = second ? k1 : k0;
-    out->perm = second ? v1 : v0;
+    const uint64_t* vs = nullptr;
+    HIP_TRY(radix_sort_pairs(k0, v0, k1, v1, (const uint64_t*)coo->val, E, vary, hist, tsums, s,
+                             &out->keys, &vs));
+    out->vals = (const double*)vs;
     if (!sum_dup) {
         out->head_pos = nullptr;
         out->nnz_out = E;
@@ -230,6 +231,63 @@ static void keep(AllocSet& tmp, spx_matrix_s* A, void* p) {
             A->owned.push_back(p);
             return;
         }
+}
+
+// Hot-column compaction: the (at most hot_max) columns with the largest sampled entry counts get
+// dense ranks, and their entries store ~rank.  The threshold is the smallest sampled count whose
+// column set fits in hot_max, found by bisection on device-side counts.
+static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot_opt,
+                                     Readback* rb_dev, hipStream_t s) {
+    const int64_t n = A->n, nnz = A->nnz;
+    int64_t hot_max = hot_opt;
+    if (hot_opt < 0) hot_max = n >= HOT_AUTO_MIN_N ? HOT_AUTO_MAX : 0;
+    if (hot_max > n) hot_max = n;
+    if (hot_max <= 0 || nnz <= 0) return SPX_OK;
+    uint32_t *freq, *tsums;
+    int32_t* colmap;
+    SPX_TRY(tmp.get(&freq, (size_t)n, "column counts"));
+    SPX_TRY(tmp.get(&colmap, (size_t)n, "column map"));
+    SPX_TRY(tmp.get(&tsums, scan_tile_count(n), "scan tile sums"));
+    HIP_TRY(hipMemsetAsync(freq, 0, (size_t)n * 4, s));
+    const int64_t stride = nnz > HOT_MAX_SAMPLES ? (nnz + HOT_MAX_SAMPLES - 1) / HOT_MAX_SAMPLES : 1;
+    HIP_TRY(launch_hot_count(A->col, nnz, stride, freq, s));
+    Readback rb;
+    auto count_ge = [&](uint32_t tau, uint32_t* out) -> spx_status {
+        HIP_TRY(launch_hot_count_ge(freq, n, tau, tsums, &rb_dev->totals[3], s));
+        SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+        *out = rb.totals[3];
+        return SPX_OK;
+    };
+    // smallest tau >= 1 with count_ge(tau) <= hot_max; count_ge is non-increasing in tau
+    uint32_t c1;
+    SPX_TRY(count_ge(1, &c1));
+    uint32_t tau = 1;
+    if (c1 > (uint64_t)hot_max) {
+        uint64_t lo = 2, hi = (uint64_t)((nnz + stride - 1) / stride) + 1;  // count_ge(hi) == 0
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) / 2;
+            uint32_t c;
+            SPX_TRY(count_ge((uint32_t)mid, &c));
+            if (c <= (uint64_t)hot_max) hi = mid;
+            else lo = mid + 1;
+        }
+        tau = (uint32_t)lo;
+    }
+    uint32_t nhot;
+    SPX_TRY(count_ge(tau, &nhot));
+    if (nhot == 0) return SPX_OK;
+    int32_t* hot_cols;
+    double* x_hot;
+    SPX_TRY(tmp.get(&hot_cols, nhot, "hot columns"));
+    SPX_TRY(tmp.get(&x_hot, nhot, "hot x"));
+    keep(tmp, A, hot_cols);
+    keep(tmp, A, x_hot);
+    HIP_TRY(launch_hot_ranks(freq, n, tau, tsums, colmap, hot_cols, s));
+    HIP_TRY(launch_hot_remap(A->col, nnz, colmap, s));
+    A->hot_cols = hot_cols;
+    A->x_hot = x_hot;
+    A->nhot = (int32_t)nhot;
+    return SPX_OK;
 }
 
 static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
@@ -281,7 +339,6 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
     SPX_TRY(tmp.get(&val_out, (size_t)nnz, "values"));
     keep(tmp, A, val_out);
     A->val = val_out;
-    const double* val_in = (const double*)coo->val;
 
     if (fmt == SPX_CSB_HILBERT) {
         const int64_t nblk = nbr * nbc;
@@ -294,7 +351,7 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
         A->blk_ptr = bp;
         A->packed = packed;
         HIP_TRY(launch_fill_i32(bp, nblk + 1, 0, s));
-        HIP_TRY(launch_gather_csbh(se.keys, se.perm, val_in, se.head_pos, E, nnz, k, packed,
+        HIP_TRY(launch_gather_csbh(se.keys, se.vals, se.head_pos, E, nnz, k, packed,
                                    val_out, bp + 1, s));
         if (scan_tile_count(nblk) > tsn) tsn = scan_tile_count(nblk);
         SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
@@ -336,10 +393,11 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
     A->row_ptr = rp;
     A->col = col;
     HIP_TRY(launch_fill_i32(rp, (int64_t)m + 1, 0, s));
-    HIP_TRY(launch_gather_csr(se.keys, se.perm, val_in, se.head_pos, E, nnz, cbits, col, val_out,
+    HIP_TRY(launch_gather_csr(se.keys, se.vals, se.head_pos, E, nnz, cbits, col, val_out,
                               rp + 1, s));
     SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
     HIP_TRY(launch_max_scan_i32(rp + 1, m, tsums, s));
+    SPX_TRY(select_hot_columns(tmp, A, o->hot_columns, rb_dev, s));
 
     if (fmt == SPX_CSR_MERGE) {
         const int64_t total = (int64_t)m + nnz;
@@ -413,6 +471,7 @@ static int64_t sum_owned_bytes(const spx_matrix_s* A) {
     b += (A->rs_long_rows ? (int64_t)A->rs_nlong * 8 + 4 + (int64_t)A->rs_nchunks * 8 : 0);
     b += (A->cb_units ? (int64_t)A->cb_nunits * 16 + (int64_t)A->cb_nsplit * 16 : 0);
     b += (A->cb_partials ? ((int64_t)A->cb_nslots << A->log2_beta) * 8 : 0);
+    b += (int64_t)A->nhot * 12;
     return b;
 }
 
@@ -445,6 +504,7 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
     if (o.log2_beta < 0 || o.log2_beta > 16)
         return fail(SPX_ERR_INVALID_ARG, "log2_beta %d outside [0,16]", o.log2_beta);
     if (o.tile_items < 0) return fail(SPX_ERR_INVALID_ARG, "tile_items < 0");
+    if (o.hot_columns < -1) return fail(SPX_ERR_INVALID_ARG, "hot_columns < -1");
     if (fmt != SPX_CSB_HILBERT && o.tile_items != 0)
         return fail(SPX_ERR_UNSUPPORTED, "tile_items is only adjustable for CSBH");
 
@@ -593,6 +653,10 @@ extern "C" spx_status spx_matrix_export(spx_matrix A, spx_array which, void* dst
                     (long long)bytes, (long long)len);
     if (len == 0) return SPX_OK;
     if (!dst) return fail(SPX_ERR_INVALID_ARG, "dst is NULL");
+    if (which == SPX_ARRAY_COL_IND && A->nhot > 0) {  // hot entries back to their columns
+        HIP_TRY(launch_hot_unmap(A->col, A->nnz, A->hot_cols, (int32_t*)dst, (hipStream_t)stream));
+        return SPX_OK;
+    }
     HIP_TRY(hipMemcpyAsync(dst, src, (size_t)len, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return SPX_OK;
 }

@@ -20,7 +20,7 @@
 #define RS_LONG 1024
 #define RS_NNZ 2048
 #define RS_ROWS 1024
-#define RS_CHUNK 8192
+#define RS_CHUNK 4096
 
 // CSBH: workgroup size and entries per thread per sweep; a work unit covers at most
 // csbh_unit_nnz entries of one block row (default below, overridable by tile_items)
@@ -71,6 +71,10 @@ struct spx_matrix_s {
     int32_t cb_nsplit = 0;
     int32_t cb_nslots = 0;
     double* cb_partials = nullptr;  // nslots * beta
+    // hot-column compaction (CRS formats): entries with col < 0 read x_hot[~col]
+    int32_t* hot_cols = nullptr;  // nhot original columns
+    int32_t nhot = 0;
+    double* x_hot = nullptr;      // per-product scratch, nhot values
     int64_t parts = 0;
     std::vector<void*> owned;  // device allocations freed by spx_matrix_destroy
 };
@@ -96,26 +100,44 @@ hipError_t launch_keys_csr(const int32_t* row, const int32_t* col, int64_t E, in
 hipError_t launch_keys_csbh(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
                             int32_t n, int k, int64_t nbc, uint64_t* keys, uint32_t* err,
                             unsigned long long* masks, hipStream_t s);
-// Stable LSD radix sort of (keys, index payload).  Digits whose bits never vary (per `vary`)
-// are skipped.  On return *in_second says whether the result is in (k1, v1).
-hipError_t radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t E,
-                            uint64_t vary, uint32_t* hist, uint32_t* tile_sums, hipStream_t s,
-                            bool* in_second);
+// Stable LSD radix sort of (keys in k0, 64-bit payloads read from vfirst).  Digits whose bits
+// never vary (per `vary`) are skipped.  k1, v0, v1 are scratch of E elements; the sorted arrays
+// are returned through keys_sorted / vals_sorted (one of the buffers, or vfirst if no pass ran).
+hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1,
+                            const uint64_t* vfirst, int64_t E, uint64_t vary, uint32_t* hist,
+                            uint32_t* tile_sums, hipStream_t s, const uint64_t** keys_sorted,
+                            const uint64_t** vals_sorted);
 size_t radix_hist_elems(int64_t E);
 hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_sums,
                               uint32_t* total, hipStream_t s);
 hipError_t launch_dedup_heads(const uint64_t* keys, int64_t E, const uint32_t* tile_sums,
                               int32_t* head_pos, hipStream_t s);
-hipError_t launch_gather_csr(const uint64_t* keys, const uint32_t* perm, const double* val_in,
-                             const int32_t* head_pos, int64_t E, int64_t nnz_out, int cbits,
-                             int32_t* col_out, double* val_out, int32_t* row_end, hipStream_t s);
-hipError_t launch_gather_csbh(const uint64_t* keys, const uint32_t* perm, const double* val_in,
-                              const int32_t* head_pos, int64_t E, int64_t nnz_out, int k,
-                              uint32_t* packed_out, double* val_out, int32_t* blk_end,
-                              hipStream_t s);
+hipError_t launch_gather_csr(const uint64_t* keys, const double* vals, const int32_t* head_pos,
+                             int64_t E, int64_t nnz_out, int cbits, int32_t* col_out,
+                             double* val_out, int32_t* row_end, hipStream_t s);
+hipError_t launch_gather_csbh(const uint64_t* keys, const double* vals, const int32_t* head_pos,
+                              int64_t E, int64_t nnz_out, int k, uint32_t* packed_out,
+                              double* val_out, int32_t* blk_end, hipStream_t s);
 // In-place inclusive max-scan of ends[0..len) (turns "end of last entry" marks into pointers).
 hipError_t launch_max_scan_i32(int32_t* ends, int64_t len, uint32_t* tile_sums, hipStream_t s);
 size_t scan_tile_count(int64_t n);
+
+// ------------------------------------------------------------------ hot columns
+#define HOT_AUTO_MAX (1 << 20)
+#define HOT_AUTO_MIN_N (1 << 19)
+#define HOT_MAX_SAMPLES (1 << 25)
+hipError_t launch_hot_count(const int32_t* col, int64_t nnz, int64_t stride, uint32_t* freq,
+                            hipStream_t s);
+hipError_t launch_hot_count_ge(const uint32_t* freq, int64_t n, uint32_t tau, uint32_t* tile_sums,
+                               uint32_t* total, hipStream_t s);
+hipError_t launch_hot_ranks(const uint32_t* freq, int64_t n, uint32_t tau,
+                            const uint32_t* tile_sums, int32_t* colmap, int32_t* hot_cols,
+                            hipStream_t s);
+hipError_t launch_hot_remap(int32_t* col, int64_t nnz, const int32_t* colmap, hipStream_t s);
+hipError_t launch_hot_gather(const int32_t* hot_cols, int32_t nhot, const double* x,
+                             double* x_hot, hipStream_t s);
+hipError_t launch_hot_unmap(const int32_t* col, int64_t nnz, const int32_t* hot_cols,
+                            int32_t* out, hipStream_t s);
 
 // ------------------------------------------------------------------ partitions
 hipError_t launch_merge_coords(const int32_t* row_ptr, int32_t m, int64_t nnz, int2* coords,

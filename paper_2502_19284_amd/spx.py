@@ -5,8 +5,10 @@ tensor dtypes/devices, passes raw device pointers and the current torch stream, 
 codes into exceptions.  torch supplies device memory and streams.  If libspx.so is missing the
 import of the binding's entry points fails loudly (there is no CPU fallback).
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import torch
 
@@ -37,7 +39,8 @@ class CooDesc(ctypes.Structure):
 
 class ConvertOpts(ctypes.Structure):
     _fields_ = [("sum_duplicates", ctypes.c_int32), ("log2_beta", ctypes.c_int32),
-                ("validate", ctypes.c_int32), ("tile_items", ctypes.c_int32)]
+                ("validate", ctypes.c_int32), ("tile_items", ctypes.c_int32),
+                ("hot_columns", ctypes.c_int32)]
 
 
 class ConvertReport(ctypes.Structure):
@@ -64,6 +67,8 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void
 
 _lib = None
 _alloc_refs = None
+_atexit_set = False
+_live = weakref.WeakSet()  # open Matrix handles
 
 
 def load(path=LIB_PATH):
@@ -139,6 +144,23 @@ def use_torch_allocator(enable=True):
     refs = (ALLOC_FN(_alloc), FREE_FN(_free))
     _check(L.spx_set_allocator(refs[0], refs[1], None))
     _alloc_refs = refs
+    global _atexit_set
+    if not _atexit_set:
+        atexit.register(_shutdown)
+        _atexit_set = True
+
+
+def _shutdown():
+    """At exit, while torch is still alive: free live handles, then drop the allocator hook."""
+    global _alloc_refs
+    for mat in list(_live):
+        try:
+            mat.close()
+        except Exception:
+            pass
+    if _lib is not None and _alloc_refs is not None:
+        _lib.spx_set_allocator(ALLOC_FN(), FREE_FN(), None)
+        _alloc_refs = None
 
 
 def profile_enable(enable=True):
@@ -192,6 +214,7 @@ class Matrix:
         self.bytes = int(info.bytes)
         self.log2_beta = int(info.log2_beta)
         self.parts = int(info.parts)
+        _live.add(self)
 
     @property
     def handle(self):
@@ -244,9 +267,10 @@ class Matrix:
 
 
 def convert(row, col, val, shape, fmt="merge", sum_duplicates=True, log2_beta=0,
-            tile_items=0, stream=None):
+            tile_items=0, hot_columns=-1, stream=None):
     """Convert device triplets (int32 row, int32 col, float64 val) to a Matrix of format `fmt`
-    ('rowsplit', 'merge' or 'csbh')."""
+    ('rowsplit', 'merge' or 'csbh').  hot_columns: -1 automatic, 0 off, k > 0 at most k columns
+    in the compact x copy (CRS formats)."""
     if fmt not in FORMATS:
         raise ValueError("unknown format %r (expected one of %s)" % (fmt, sorted(FORMATS)))
     m, n = int(shape[0]), int(shape[1])
@@ -259,7 +283,8 @@ def convert(row, col, val, shape, fmt="merge", sum_duplicates=True, log2_beta=0,
     desc = CooDesc(m, n, E, ctypes.c_void_p(row.data_ptr() if E else 0),
                    ctypes.c_void_p(col.data_ptr() if E else 0),
                    ctypes.c_void_p(val.data_ptr() if E else 0), 0)
-    opts = ConvertOpts(1 if sum_duplicates else 0, int(log2_beta), 1, int(tile_items))
+    opts = ConvertOpts(1 if sum_duplicates else 0, int(log2_beta), 1, int(tile_items),
+                       int(hot_columns))
     rep = ConvertReport()
     h = ctypes.c_void_p()
     L = load()

@@ -39,9 +39,10 @@ def test_status_strings(L):
 
 
 def test_opts_default(L):
-    o = B.ConvertOpts(7, 7, 7, 7)
+    o = B.ConvertOpts(7, 7, 7, 7, 7)
     assert L.spx_convert_opts_default(ctypes.byref(o)) == 0
-    assert (o.sum_duplicates, o.log2_beta, o.validate, o.tile_items) == (1, 0, 1, 0)
+    assert (o.sum_duplicates, o.log2_beta, o.validate, o.tile_items, o.hot_columns) == \
+        (1, 0, 1, 0, -1)
     assert L.spx_convert_opts_default(None) == -1
 
 
@@ -79,13 +80,15 @@ def test_convert_argument_errors(L):
     st, _ = _convert(L, d, fmt=9)
     assert st == -1
     assert "format" in L.spx_last_error_message().decode()
-    st, _ = _convert(L, d, opts=B.ConvertOpts(2, 0, 1, 0))
+    st, _ = _convert(L, d, opts=B.ConvertOpts(2, 0, 1, 0, -1))
     assert st == -1
-    st, _ = _convert(L, d, opts=B.ConvertOpts(1, 17, 1, 0))
+    st, _ = _convert(L, d, opts=B.ConvertOpts(1, 17, 1, 0, -1))
     assert st == -1
-    st, _ = _convert(L, d, opts=B.ConvertOpts(1, 0, 1, -3))
+    st, _ = _convert(L, d, opts=B.ConvertOpts(1, 0, 1, -3, -1))
     assert st == -1
-    st, _ = _convert(L, d, fmt=1, opts=B.ConvertOpts(1, 0, 1, 100))
+    st, _ = _convert(L, d, opts=B.ConvertOpts(1, 0, 1, 0, -2))
+    assert st == -1
+    st, _ = _convert(L, d, fmt=1, opts=B.ConvertOpts(1, 0, 1, 100, -1))
     assert st == -7
 
 

@@ -240,6 +240,23 @@ def test_keep_repeats_option(spx, fmt):
     _check_int(y, ref, "keep repeats " + fmt)
 
 
+@pytest.mark.parametrize("fmt", ["rowsplit", "merge"])
+@pytest.mark.parametrize("hot", [1, 100, 5000, 10 ** 6])
+def test_hot_column_compaction(spx, rmat14, fmt, hot):
+    # forced hot-column compaction on the scale-14 matrix: bit-exact on integers, and the exported
+    # col_ind (hot entries mapped back) still equals the canonical columns
+    m, n, row, col, d = rmat14
+    for kind in ("int", "float"):
+        val, x, ref = d[kind]
+        say("hot", fmt, hot, kind)
+        A, y = _run(spx, fmt, m, n, row, col, val, x, hot_columns=hot)
+        if kind == "int":
+            _check_int(y, ref, "hot %s %d" % (fmt, hot))
+        else:
+            _check_float(y, ref, "hot %s %d" % (fmt, hot))
+        _check_structure(A, m, n, row, col, val)
+
+
 # ---------------------------------------------------------------- invariants
 
 
