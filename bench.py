@@ -73,14 +73,15 @@ def spmv_bytes(fmt, m, nnz, n_touched, A):
 def kernel_bytes(name, E, nnz, m, passes):
     """Algorithmic bytes per launch of conversion kernels (None when not modelled)."""
     if name == "rsort_downsweep":
-        # read key + payload, write key + payload; the first pass has an implicit payload
-        return E * (24 * passes - 4) / passes
+        # read 8-byte key + 8-byte value, write both
+        return 32 * E
     if name == "rsort_upsweep":
         return 8 * E
     if name == "keys":
         return 16 * E
     if name == "gather":
-        return 20 * E + 16 * nnz
+        # sorted keys and values read once, head positions, column and value written
+        return 16 * E + 4 * nnz + 12 * nnz
     return None
 
 

@@ -183,7 +183,7 @@ hipError_t launch_keys_csbh(const int32_t* row, const int32_t* col, int64_t E, i
 //   scan      : exclusive scan of hist gives each (digit, tile) its first output slot
 //   downsweep : each tile ranks its keys stably (original order within equal digits), reorders
 //               them in LDS by digit, and writes each digit's run contiguously.
-// Stable ranking: wave w of the tile takes keys [w*1024, (w+1)*1024) of the tile in 16 rounds of
+// Stable ranking: wave w of the tile takes its quarter of the tile in rounds of
 // 64 consecutive keys; lanes holding the same digit find each other with 8 ballots (one per
 // digit bit) and rank by lower-lane count; a per-wave LDS counter per digit carries the running
 // count across rounds.  Wave offsets are then added per digit in wave order.

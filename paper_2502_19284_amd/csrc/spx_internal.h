@@ -30,10 +30,10 @@
 #define CB_LDS_BUDGET (64 * 1024)    // bytes of the output slice kept in LDS
 #define CB_BP_STAGE_MAX 8192         // block pointers staged in LDS when nbc+1 <= this
 
-// radix sort: 8-bit digits, 256 threads x 16 keys per tile
+// radix sort: 8-bit digits, 256 threads x 8 keys per tile
 #define RS_RADIX_BITS 8
 #define RSORT_NT 256
-#define RSORT_IPT 16
+#define RSORT_IPT 8
 #define RSORT_TILE (RSORT_NT * RSORT_IPT)
 
 struct spx_matrix_s {
@@ -125,7 +125,7 @@ size_t scan_tile_count(int64_t n);
 // ------------------------------------------------------------------ hot columns
 #define HOT_AUTO_MAX (1 << 20)
 #define HOT_AUTO_MIN_N (1 << 19)
-#define HOT_MAX_SAMPLES (1 << 25)
+#define HOT_MAX_SAMPLES (1 << 23)
 hipError_t launch_hot_count(const int32_t* col, int64_t nnz, int64_t stride, uint32_t* freq,
                             hipStream_t s);
 hipError_t launch_hot_count_ge(const uint32_t* freq, int64_t n, uint32_t tau, uint32_t* tile_sums,
