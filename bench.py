@@ -137,8 +137,82 @@ def cpu_baseline(w, budget_s=12.0):
             "ms_min": round(best * 1e3, 3), "ms_median": round(statistics.median(times) * 1e3, 3)}
 
 
+def _short(name):
+    name = name.split("(")[0].replace("void ", "")
+    return name.split("<")[0] + ("<csbh>" if "<true>" in name or "KeyCsbh" in name else "")
+
+
+def summarize_rocprof(prof_dir, label):
+    """Markdown summary of rocprofv3 CSV output (kernel stats + FETCH/WRITE per dispatch) and a
+    JSON traffic table for bench.py.  Counter calibration: the 2 GiB device copy of the copy
+    probe reads FETCH_SIZE / WRITE_SIZE for 2 GiB read and 2 GiB written."""
+    import csv
+    import collections
+    lines = []
+    stats = os.path.join(prof_dir, "trace", label + "_kernel_stats.csv")
+    rows = list(csv.DictReader(open(stats)))
+    lines.append("| kernel | calls | avg ms | min ms | max ms | share |")
+    lines.append("|---|---|---|---|---|---|")
+    for r in rows[:25]:
+        lines.append("| `%s` | %s | %.4f | %.4f | %.4f | %.1f%% |" % (
+            r["Name"].split("(")[0].replace("void ", "")[:70], r["Calls"],
+            float(r["AverageNs"]) / 1e6, float(r["MinNs"]) / 1e6, float(r["MaxNs"]) / 1e6,
+            float(r["Percentage"])))
+    cnt = {}
+    for c in ("fetch", "write"):
+        agg = collections.defaultdict(list)
+        for r in csv.DictReader(open(os.path.join(prof_dir, c, label + "_counter_collection.csv"))):
+            agg[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+        cnt[c] = agg
+    copy_key = [k for k in cnt["fetch"] if k[0].startswith("__amd_rocclr_copyBuffer")]
+    probe = max(copy_key, key=lambda k: max(cnt["fetch"][k]))
+    gib2 = 2 * 1024 * 1024  # KiB in 2 GiB
+    f_fac = gib2 / max(cnt["fetch"][probe])
+    w_fac = gib2 / max(cnt["write"][probe])
+    lines.append("")
+    lines.append("Counter calibration (2 GiB device copy of the copy probe): FETCH_SIZE x %.3f, "
+                 "WRITE_SIZE x %.3f." % (f_fac, w_fac))
+    lines.append("")
+    lines.append("| kernel | dispatches | FETCH KiB/dispatch | WRITE KiB/dispatch | "
+                 "HBM GB/dispatch (scaled) |")
+    lines.append("|---|---|---|---|---|")
+    per = collections.defaultdict(lambda: [[], []])
+    for (k, _), v in cnt["fetch"].items():
+        per[_short(k)][0] += v
+    for (k, _), v in cnt["write"].items():
+        per[_short(k)][1] += v
+    traffic = {}
+    for k, (fv, wv) in sorted(per.items(), key=lambda kv: -sum(kv[1][0])):
+        fa = sum(fv) / max(len(fv), 1)
+        wa = sum(wv) / max(len(wv), 1)
+        gb = (fa * f_fac + wa * w_fac) * 1024 / 1e9
+        traffic[k] = (fa * f_fac + wa * w_fac) * 1024
+        if gb > 0.01:
+            lines.append("| `%s` | %d | %.0f | %.0f | %.3f |" % (k[:60], len(fv), fa, wa, gb))
+    src = None
+    bj = os.path.join(prof_dir, "bench_trace.json")
+    if os.path.exists(bj):
+        src = json.loads(open(bj).read().strip().splitlines()[-1]).get("kernel_src")
+    return "\n".join(lines), {"kernel_src": src, "traffic_bytes_per_launch": traffic}
+
+
+def load_traffic(kernel):
+    """Measured HBM bytes per launch of `kernel` from profiles/, if taken on the current source."""
+    p = os.path.join(ROOT, "profiles", "traffic_rmat24.json")
+    if not os.path.exists(p):
+        return None
+    t = json.load(open(p))
+    if t.get("kernel_src") != src_hash("k_spmv.hip", "k_convert.hip"):
+        return None
+    v = t["traffic_bytes_per_launch"].get(kernel) or t["traffic_bytes_per_launch"].get("k_" + kernel)
+    return None if v is None else int(v)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--summarize-rocprof", metavar="DIR",
+                    help="print a markdown summary of rocprofv3 CSV output in DIR and write "
+                         "profiles/traffic_rmat24.json, then exit")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
@@ -147,6 +221,12 @@ def main():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--formats", default=",".join(FMTS))
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        md, tj = summarize_rocprof(args.summarize_rocprof, "rmat24")
+        with open(os.path.join(ROOT, "profiles", "traffic_rmat24.json"), "w") as f:
+            json.dump(tj, f, indent=1, sort_keys=True)
+        print(md)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported (the multi-GPU "
               "sharding is described in DESIGN.md, not run)" % args.gpus, file=sys.stderr)
@@ -225,7 +305,7 @@ def main():
     if dom_bytes is not None:
         ach = dom_bytes / (dom[1]["avg_ms"] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom[0]),
                     "kernel": dom[0], "avg_ms": round(dom[1]["avg_ms"], 4),
                     "launches": dom[1]["launches"], "bytes_per_launch": int(dom_bytes),
                     "share_of_step": round(dom[1]["total_ms"] / (t_steps * 1e3), 3)}
