@@ -50,6 +50,8 @@ typedef int32_t spx_format;
 #define SPX_CSR_MERGE 1
 /* Compressed sparse blocks with Hilbert order inside each block, CSBH (Sections 3.1 and 4.1). */
 #define SPX_CSB_HILBERT 2
+/* Compressed sparse blocks with Z-Morton order inside each block, CSB (Section 3.1). */
+#define SPX_CSB_ZMORTON 3
 
 typedef int32_t spx_dtype;
 #define SPX_F64 0
@@ -103,8 +105,9 @@ typedef int32_t spx_array;
 #define SPX_ARRAY_ROW_PTR 0 /* CRS formats: int32[m+1]                                      */
 #define SPX_ARRAY_COL_IND 1 /* CRS formats: int32[nnz], ascending inside a row              */
 #define SPX_ARRAY_VALUES 2  /* all formats: float64[nnz] in storage order                   */
-#define SPX_ARRAY_BLK_PTR 3 /* CSBH: int32[nbr*nbc+1], blocks in row-wise order             */
-#define SPX_ARRAY_PACKED 4  /* CSBH: uint32[nnz], (local_row << 16) | local_col, Hilbert order */
+#define SPX_ARRAY_BLK_PTR 3 /* CSB/CSBH: int32[nbr*nbc+1], blocks in row-wise order         */
+#define SPX_ARRAY_PACKED 4  /* CSB/CSBH: uint32[nnz], (local_row << 16) | local_col, in the
+                             * block's Hilbert (CSBH) or Z-Morton (CSB) order                  */
 #define SPX_ARRAY_PARTS 5   /* format's work-unit table, int32 (layout is internal)          */
 
 /* Optional device allocator: alloc returns NULL on failure; free accepts what alloc returned. */
@@ -121,7 +124,8 @@ spx_status spx_convert_opts_default(spx_convert_opts* opts);
  * Convert triplets to `fmt` (Section 5.1: sort the entries into the format's order, then fill and
  * compress the arrays).  The sort is a stable device radix sort on the format's key:
  *   CRS:  (row, col);
- *   CSBH: (block row, block column, Hilbert index of the local (row, col) in the block).
+ *   CSBH: (block row, block column, Hilbert index of the local (row, col) in the block);
+ *   CSB:  the same with the Z-Morton index.
  * Repeated coordinates become one entry whose value is the sum in increasing triplet index.
  * The work-unit table the product uses is built here as well, and counted in the conversion.
  *

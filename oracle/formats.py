@@ -4,14 +4,15 @@ A conversion is correct when decoding the converted arrays gives back exactly th
 triplets (same coordinates, bit-identical values) and the format's ordering rules hold.
 
 CRS (Section 2): row_ptr[m+1] non-decreasing from 0 to nnz; columns ascend inside a row.
-CSB with Hilbert order inside blocks, CSBH (Sections 3.1 and 4.1): beta x beta blocks; blk_ptr has
+CSB (Section 3.1) and CSB with Hilbert order inside blocks, CSBH (Section 4.1): beta x beta blocks;
+blk_ptr has
 one entry per block in row-wise block order plus a final nnz; inside a block each entry's local
 row and column are packed into one 32-bit word, row in the upper 16 bits; entries of a block
 follow the Hilbert order of their local (row, col).
 """
 import numpy as np
 
-from .curves import hilbert_index_array
+from .curves import hilbert_index_array, zmorton_index
 
 
 def decode_crs(row_ptr):
@@ -55,8 +56,15 @@ def decode_csbh(m, n, log2_beta, blk_ptr, packed, val):
 
 
 def check_csbh(m, n, log2_beta, blk_ptr, packed, val, canon_row, canon_col, canon_val):
-    """Raise AssertionError unless the CSBH arrays hold exactly the canonical triplets, blocks are
-    in row-wise order, and entries inside each block follow the Hilbert order strictly."""
+    """CSB with Hilbert order inside blocks (Section 4.1)."""
+    check_csb(m, n, log2_beta, blk_ptr, packed, val, canon_row, canon_col, canon_val, "hilbert")
+
+
+def check_csb(m, n, log2_beta, blk_ptr, packed, val, canon_row, canon_col, canon_val,
+              order="zmorton"):
+    """Raise AssertionError unless the CSB arrays hold exactly the canonical triplets, blocks are
+    in row-wise order, and entries inside each block follow the block order ('hilbert' or
+    'zmorton', Section 3.1) strictly."""
     blk_ptr = np.asarray(blk_ptr, np.int64)
     assert blk_ptr[0] == 0 and blk_ptr[-1] == len(packed) == len(val), "blk_ptr ends"
     assert np.all(np.diff(blk_ptr) >= 0), "blk_ptr not monotone"
@@ -64,9 +72,12 @@ def check_csbh(m, n, log2_beta, blk_ptr, packed, val, canon_row, canon_col, cano
     beta = 1 << log2_beta
     assert np.all(lr < beta) and np.all(lc < beta), "local index >= beta"
     assert np.all(row < m) and np.all(col < n), "entry outside the matrix"
-    h = hilbert_index_array(log2_beta, lr, lc)
+    if order == "hilbert":
+        h = hilbert_index_array(log2_beta, lr, lc)
+    else:
+        h = np.array([zmorton_index(log2_beta, a, b) for a, b in zip(lr, lc)], dtype=np.int64)
     same = blk[1:] == blk[:-1]
-    assert np.all(h[1:][same] > h[:-1][same]), "not strictly increasing Hilbert order in a block"
+    assert np.all(h[1:][same] > h[:-1][same]), "not strictly increasing %s order in a block" % order
     # compare as multisets keyed by (row, col); coordinates are unique after summing repeats
     order = np.lexsort((col, row))
     assert np.array_equal(row[order], np.asarray(canon_row, np.int64)), "rows"

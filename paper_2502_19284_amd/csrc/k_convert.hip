@@ -93,6 +93,25 @@ __device__ __forceinline__ void hilbert_d2xy(int k, uint32_t d, uint32_t* px, ui
     *py = y;
 }
 
+// Z-Morton index of local cell (row y, column x): bits interleaved with the row bit above the
+// column bit at every level (quadrants top-left, top-right, bottom-left, bottom-right).
+__device__ __forceinline__ uint32_t zmorton_xy2d(int k, uint32_t x, uint32_t y) {
+    uint32_t d = 0;
+    for (int l = 0; l < k; ++l)
+        d |= (((y >> l) & 1u) << (2 * l + 1)) | (((x >> l) & 1u) << (2 * l));
+    return d;
+}
+
+__device__ __forceinline__ void zmorton_d2xy(int k, uint32_t d, uint32_t* px, uint32_t* py) {
+    uint32_t x = 0, y = 0;
+    for (int l = 0; l < k; ++l) {
+        x |= ((d >> (2 * l)) & 1u) << l;
+        y |= ((d >> (2 * l + 1)) & 1u) << l;
+    }
+    *px = x;
+    *py = y;
+}
+
 template <typename KeyFn>
 __device__ __forceinline__ void keys_body(const int32_t* __restrict__ row,
                                           const int32_t* __restrict__ col, int64_t E, int32_t m,
@@ -143,13 +162,16 @@ struct KeyCsr {
     }
 };
 
-struct KeyCsbh {
+template <bool HILBERT>
+struct KeyCsb {
     int k;
     uint64_t nbc;
     __device__ uint64_t operator()(uint32_t r, uint32_t c) const {
         const uint32_t mask = (1u << k) - 1u;
         const uint64_t blk = (uint64_t)(r >> k) * nbc + (uint64_t)(c >> k);
-        return (blk << (2 * k)) | (uint64_t)hilbert_xy2d(k, c & mask, r & mask);
+        const uint32_t d = HILBERT ? hilbert_xy2d(k, c & mask, r & mask)
+                                   : zmorton_xy2d(k, c & mask, r & mask);
+        return (blk << (2 * k)) | (uint64_t)d;
     }
 };
 
@@ -168,11 +190,17 @@ hipError_t launch_keys_csr(const int32_t* row, const int32_t* col, int64_t E, in
     return hipGetLastError();
 }
 
-hipError_t launch_keys_csbh(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
-                            int32_t n, int k, int64_t nbc, uint64_t* keys, uint32_t* err,
-                            unsigned long long* masks, hipStream_t s) {
-    SPX_LAUNCH("keys", (k_keys<KeyCsbh>), dim3(grid_for(E, 256, KEYS_MAX_GRID)), dim3(256), 0, s,
-                       row, col, E, m, n, keys, err, masks, KeyCsbh{k, (uint64_t)nbc});
+hipError_t launch_keys_csb(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+                           int32_t n, int k, int64_t nbc, bool hilbert, uint64_t* keys,
+                           uint32_t* err, unsigned long long* masks, hipStream_t s) {
+    if (hilbert)
+        SPX_LAUNCH("keys", (k_keys<KeyCsb<true>>), dim3(grid_for(E, 256, KEYS_MAX_GRID)),
+                   dim3(256), 0, s, row, col, E, m, n, keys, err, masks,
+                   KeyCsb<true>{k, (uint64_t)nbc});
+    else
+        SPX_LAUNCH("keys", (k_keys<KeyCsb<false>>), dim3(grid_for(E, 256, KEYS_MAX_GRID)),
+                   dim3(256), 0, s, row, col, E, m, n, keys, err, masks,
+                   KeyCsb<false>{k, (uint64_t)nbc});
     return hipGetLastError();
 }
 
@@ -367,33 +395,21 @@ struct LoadHead {
         return (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
     }
 };
-struct StoreHeadPos {
-    int32_t* head_pos;
-    __device__ void operator()(int64_t i, uint32_t incl, uint32_t item) const {
-        if (item) head_pos[incl - 1] = (int32_t)i;
-    }
-};
-
 hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_sums,
                               uint32_t* total, hipStream_t s) {
     return scan_phase12<uint32_t, OpSum<uint32_t>>(LoadHead{keys}, E, tile_sums, total, s);
-}
-
-hipError_t launch_dedup_heads(const uint64_t* keys, int64_t E, const uint32_t* tile_sums,
-                              int32_t* head_pos, hipStream_t s) {
-    return scan_phase3<uint32_t, OpSum<uint32_t>>(LoadHead{keys}, StoreHeadPos{head_pos}, E,
-                                                  tile_sums, s);
 }
 
 // Output entry u covers sorted positions [s, e): s = head_pos[u] (or u without summing), e the
 // next head (or E).  Its value is vals[s] + vals[s+1] + ... in increasing position, i.e. in
 // increasing triplet index, because the sort that carried the values is stable.  The last entry
 // of each row (block) writes u+1 at its row (block), for the max-scan that follows.
-template <bool CSBH>
+// MODE 0: CRS (column index), 1: CSB Hilbert, 2: CSB Z-Morton (packed local row/column)
+template <int MODE>
 __global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ keys,
                                                 const double* __restrict__ vals,
                                                 const int32_t* __restrict__ head_pos, int64_t E,
-                                                int64_t nnz_out, int shiftbits,
+                                                int64_t nnz_out, int shiftbits, HotMap hm,
                                                 int32_t* __restrict__ idx_out,
                                                 double* __restrict__ val_out,
                                                 int32_t* __restrict__ ends) {
@@ -406,13 +422,15 @@ __global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ key
         for (int64_t j = s + 1; j < e; ++j) acc = acc + vals[j];
         val_out[u] = acc;
         const uint64_t major = key >> shiftbits;
-        if (CSBH) {
+        if (MODE != 0) {
             const int k = shiftbits >> 1;
+            const uint32_t d = (uint32_t)(key & ((1ull << shiftbits) - 1ull));
             uint32_t lc, lr;
-            hilbert_d2xy(k, (uint32_t)(key & ((1ull << shiftbits) - 1ull)), &lc, &lr);
+            if (MODE == 1) hilbert_d2xy(k, d, &lc, &lr);
+            else zmorton_d2xy(k, d, &lc, &lr);
             idx_out[u] = (int32_t)((lr << 16) | lc);
         } else {
-            idx_out[u] = (int32_t)(key & ((1ull << shiftbits) - 1ull));
+            idx_out[u] = hm.map((uint32_t)(key & ((1ull << shiftbits) - 1ull)));
         }
         const bool last = (e >= E) || ((keys[e] >> shiftbits) != major);
         if (last) ends[major] = (int32_t)(u + 1);
@@ -420,21 +438,82 @@ __global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ key
 }
 
 hipError_t launch_gather_csr(const uint64_t* keys, const double* vals, const int32_t* head_pos,
-                             int64_t E, int64_t nnz_out, int cbits, int32_t* col_out,
+                             int64_t E, int64_t nnz_out, int cbits, HotMap hm, int32_t* col_out,
                              double* val_out, int32_t* row_end, hipStream_t s) {
     if (nnz_out <= 0) return hipSuccess;
-    SPX_LAUNCH("gather", (k_gather<false>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
-               vals, head_pos, E, nnz_out, cbits, col_out, val_out, row_end);
+    SPX_LAUNCH("gather", (k_gather<0>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
+               vals, head_pos, E, nnz_out, cbits, hm, col_out, val_out, row_end);
     return hipGetLastError();
 }
 
-hipError_t launch_gather_csbh(const uint64_t* keys, const double* vals, const int32_t* head_pos,
-                              int64_t E, int64_t nnz_out, int k, uint32_t* packed_out,
-                              double* val_out, int32_t* blk_end, hipStream_t s) {
+hipError_t launch_gather_csb(const uint64_t* keys, const double* vals, const int32_t* head_pos,
+                             int64_t E, int64_t nnz_out, int k, bool hilbert, uint32_t* packed_out,
+                             double* val_out, int32_t* blk_end, hipStream_t s) {
     if (nnz_out <= 0) return hipSuccess;
-    SPX_LAUNCH("gather", (k_gather<true>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
-               vals, head_pos, E, nnz_out, 2 * k, (int32_t*)packed_out, val_out, blk_end);
+    if (hilbert)
+        SPX_LAUNCH("gather", (k_gather<1>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
+                   vals, head_pos, E, nnz_out, 2 * k, HotMap{}, (int32_t*)packed_out, val_out,
+                   blk_end);
+    else
+        SPX_LAUNCH("gather", (k_gather<2>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
+                   vals, head_pos, E, nnz_out, 2 * k, HotMap{}, (int32_t*)packed_out, val_out,
+                   blk_end);
     return hipGetLastError();
+}
+
+// The scan over run heads calls this for every sorted position: a head at position i becomes
+// output entry u = (heads before i); its run is summed in increasing position (= increasing
+// triplet index) and the row (block) end mark is set as in k_gather.
+template <int MODE>
+struct StoreGather {
+    const uint64_t* keys;
+    const double* vals;
+    int64_t E;
+    int shiftbits;
+    HotMap hm;
+    int32_t* idx_out;
+    double* val_out;
+    int32_t* ends;
+    __device__ void operator()(int64_t i, uint32_t incl, uint32_t item) const {
+        if (!item) return;
+        const int64_t u = (int64_t)incl - 1;
+        const uint64_t key = keys[i];
+        double acc = vals[i];
+        int64_t e = i + 1;
+        while (e < E && keys[e] == key) {
+            acc = acc + vals[e];
+            ++e;
+        }
+        val_out[u] = acc;
+        const uint64_t major = key >> shiftbits;
+        const uint32_t d = (uint32_t)(key & ((1ull << shiftbits) - 1ull));
+        if (MODE != 0) {
+            const int k = shiftbits >> 1;
+            uint32_t lc, lr;
+            if (MODE == 1) hilbert_d2xy(k, d, &lc, &lr);
+            else zmorton_d2xy(k, d, &lc, &lr);
+            idx_out[u] = (int32_t)((lr << 16) | lc);
+        } else {
+            idx_out[u] = hm.map(d);
+        }
+        if (e >= E || (keys[e] >> shiftbits) != major) ends[major] = (int32_t)(u + 1);
+    }
+};
+
+hipError_t launch_dedup_gather(const uint64_t* keys, const double* vals, int64_t E,
+                               const uint32_t* tile_sums, int mode, int shiftbits, HotMap hm,
+                               int32_t* idx_out, double* val_out, int32_t* ends, hipStream_t s) {
+    if (mode == 0)
+        return scan_phase3<uint32_t, OpSum<uint32_t>>(
+            LoadHead{keys}, StoreGather<0>{keys, vals, E, shiftbits, hm, idx_out, val_out, ends},
+            E, tile_sums, s);
+    if (mode == 1)
+        return scan_phase3<uint32_t, OpSum<uint32_t>>(
+            LoadHead{keys}, StoreGather<1>{keys, vals, E, shiftbits, hm, idx_out, val_out, ends},
+            E, tile_sums, s);
+    return scan_phase3<uint32_t, OpSum<uint32_t>>(
+        LoadHead{keys}, StoreGather<2>{keys, vals, E, shiftbits, hm, idx_out, val_out, ends}, E,
+        tile_sums, s);
 }
 
 struct LoadI32 {

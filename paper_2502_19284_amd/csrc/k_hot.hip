@@ -6,25 +6,28 @@
 // index) instead of the column.  Each product first gathers x_hot[h] = x[hot_cols[h]], a compact
 // array whose lines are all hot, and the kernels read x_hot[~c] for negative c.  Results are
 // unchanged: only the address a value is read from moves.
+//
+// The set is a bitmap over columns plus a prefix count per 64-bit word (3 MB for 2^24 columns,
+// L2-resident), so rank(c) = prefix[c/64] + popcount(bits[c/64] below c) costs two cached loads.
 #include "dev_scan.h"
 #include "spx_internal.h"
 
-// sampled column frequencies: every `stride`-th stored entry
-__global__ void k_hot_count(const int32_t* __restrict__ col, int64_t nnz, int64_t stride,
-                            uint32_t* __restrict__ freq) {
-    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride; i < nnz;
+// sampled column frequencies from the sorted keys: every `stride`-th key, column = key & cmask
+__global__ void k_hot_count(const uint64_t* __restrict__ keys, int64_t E, int64_t stride,
+                            uint64_t cmask, uint32_t* __restrict__ freq) {
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride; i < E;
          i += (int64_t)gridDim.x * blockDim.x * stride)
-        atomicAdd(&freq[col[i]], 1u);
+        atomicAdd(&freq[keys[i] & cmask], 1u);
 }
 
-hipError_t launch_hot_count(const int32_t* col, int64_t nnz, int64_t stride, uint32_t* freq,
-                            hipStream_t s) {
-    if (nnz <= 0) return hipSuccess;
-    int64_t samples = (nnz + stride - 1) / stride;
+hipError_t launch_hot_count(const uint64_t* keys, int64_t E, int64_t stride, uint64_t cmask,
+                            uint32_t* freq, hipStream_t s) {
+    if (E <= 0) return hipSuccess;
+    int64_t samples = (E + stride - 1) / stride;
     int64_t g = (samples + 255) / 256;
     if (g > 8192) g = 8192;
-    SPX_LAUNCH("hot_count", k_hot_count, dim3((unsigned)g), dim3(256), 0, s, col, nnz, stride,
-               freq);
+    SPX_LAUNCH("hot_count", k_hot_count, dim3((unsigned)g), dim3(256), 0, s, keys, E, stride,
+               cmask, freq);
     return hipGetLastError();
 }
 
@@ -40,42 +43,58 @@ hipError_t launch_hot_count_ge(const uint32_t* freq, int64_t n, uint32_t tau, ui
     return scan_phase12<uint32_t, OpSum<uint32_t>>(LoadGe{freq, tau}, n, tile_sums, total, s);
 }
 
-struct StoreHot {
-    int32_t* colmap;
-    int32_t* hot_cols;
-    __device__ void operator()(int64_t c, uint32_t incl, uint32_t item) const {
-        if (item) {
-            colmap[c] = (int32_t)(incl - 1);
-            hot_cols[incl - 1] = (int32_t)c;
-        } else {
-            colmap[c] = -1;
-        }
+// bitmap word w covers columns [64w, 64w+64); cnt[w] = its population
+__global__ void k_hot_bits(const uint32_t* __restrict__ freq, int64_t n, uint32_t tau,
+                           uint64_t* __restrict__ bits, uint32_t* __restrict__ cnt,
+                           int64_t nwords) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nwords) return;
+    uint64_t b = 0;
+    for (int j = 0; j < 64; ++j) {
+        const int64_t c = w * 64 + j;
+        if (c < n && freq[c] >= tau) b |= 1ull << j;
     }
+    bits[w] = b;
+    cnt[w] = (uint32_t)__popcll(b);
+}
+
+struct LoadU32H {
+    const uint32_t* p;
+    __device__ uint32_t operator()(int64_t i) const { return p[i]; }
+};
+struct StoreExclH {
+    uint32_t* p;
+    __device__ void operator()(int64_t i, uint32_t incl, uint32_t item) const { p[i] = incl - item; }
 };
 
-// colmap[c] = dense rank of c among hot columns (ascending column order) or -1
-hipError_t launch_hot_ranks(const uint32_t* freq, int64_t n, uint32_t tau,
-                            const uint32_t* tile_sums, int32_t* colmap, int32_t* hot_cols,
-                            hipStream_t s) {
-    return scan_phase3<uint32_t, OpSum<uint32_t>>(LoadGe{freq, tau}, StoreHot{colmap, hot_cols},
-                                                  n, tile_sums, s);
-}
-
-__global__ void k_hot_remap(int32_t* __restrict__ col, int64_t nnz,
-                            const int32_t* __restrict__ colmap) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = col[i];
-        const int32_t h = colmap[c];
-        col[i] = h >= 0 ? ~h : c;
+__global__ void k_hot_list(const uint64_t* __restrict__ bits, const uint32_t* __restrict__ pre,
+                           int64_t nwords, int32_t* __restrict__ hot_cols) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nwords) return;
+    uint64_t b = bits[w];
+    uint32_t r = pre[w];
+    while (b) {
+        const int j = __ffsll((unsigned long long)b) - 1;
+        hot_cols[r++] = (int32_t)(w * 64 + j);
+        b &= b - 1;
     }
 }
 
-hipError_t launch_hot_remap(int32_t* col, int64_t nnz, const int32_t* colmap, hipStream_t s) {
-    if (nnz <= 0) return hipSuccess;
-    int64_t g = (nnz + 255) / 256;
-    if (g > 65536) g = 65536;
-    SPX_LAUNCH("hot_remap", k_hot_remap, dim3((unsigned)g), dim3(256), 0, s, col, nnz, colmap);
+// bits/pre for the columns with frequency >= tau (pre: exclusive prefix of word populations),
+// hot_cols in ascending column order.  cnt must hold nwords entries and may alias pre.
+hipError_t launch_hot_set(const uint32_t* freq, int64_t n, uint32_t tau, uint64_t* bits,
+                          uint32_t* pre, int32_t* hot_cols, uint32_t* tile_sums, hipStream_t s) {
+    const int64_t nwords = (n + 63) / 64;
+    SPX_LAUNCH("hot_bits", k_hot_bits, dim3(spx_div_up(nwords, 256)), dim3(256), 0, s, freq, n,
+               tau, bits, pre, nwords);
+    hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32H{pre}, nwords, tile_sums,
+                                                           (uint32_t*)nullptr, s);
+    if (e != hipSuccess) return e;
+    e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32H{pre}, StoreExclH{pre}, nwords, tile_sums,
+                                               s);
+    if (e != hipSuccess) return e;
+    SPX_LAUNCH("hot_list", k_hot_list, dim3(spx_div_up(nwords, 256)), dim3(256), 0, s, bits, pre,
+               nwords, hot_cols);
     return hipGetLastError();
 }
 

@@ -167,11 +167,12 @@ static spx_status sync_read(void* host, const void* dev, size_t bytes, hipStream
     return SPX_OK;
 }
 
-// Sort + sum repeats.  Produces sorted keys and values, head positions and nnz_out.
+// Sort and count runs of equal keys.  Produces sorted keys and values, nnz_out, and (when
+// repeats are summed) the scanned tile counts of run heads that the fused gather consumes.
 struct SortedEntries {
     const uint64_t* keys = nullptr;
     const double* vals = nullptr;
-    int32_t* head_pos = nullptr;  // null when repeats are kept
+    const uint32_t* head_tiles = nullptr;  // null when repeats are kept
     int64_t nnz_out = 0;
 };
 
@@ -194,9 +195,9 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
     SPX_TRY(tmp.get(&rb_dev, 1, "readback"));
 
     HIP_TRY(launch_init_readback(rb_dev, s));
-    if (fmt == SPX_CSB_HILBERT)
-        HIP_TRY(launch_keys_csbh(coo->row, coo->col, E, coo->m, coo->n, k, nbc, k0, &rb_dev->err,
-                                 rb_dev->masks, s));
+    if (spx_is_csb(fmt))
+        HIP_TRY(launch_keys_csb(coo->row, coo->col, E, coo->m, coo->n, k, nbc,
+                                fmt == SPX_CSB_HILBERT, k0, &rb_dev->err, rb_dev->masks, s));
     else
         HIP_TRY(launch_keys_csr(coo->row, coo->col, E, coo->m, coo->n, cbits, k0, &rb_dev->err,
                                 rb_dev->masks, s));
@@ -210,15 +211,14 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
                              &out->keys, &vs));
     out->vals = (const double*)vs;
     if (!sum_dup) {
-        out->head_pos = nullptr;
+        out->head_tiles = nullptr;
         out->nnz_out = E;
         return SPX_OK;
     }
     HIP_TRY(launch_dedup_count(out->keys, E, tsums, &rb_dev->totals[0], s));
     SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
     out->nnz_out = rb.totals[0];
-    SPX_TRY(tmp.get(&out->head_pos, (size_t)out->nnz_out, "head positions"));
-    HIP_TRY(launch_dedup_heads(out->keys, E, tsums, out->head_pos, s));
+    out->head_tiles = tsums;
     return SPX_OK;
 }
 
@@ -234,23 +234,29 @@ static void keep(AllocSet& tmp, spx_matrix_s* A, void* p) {
 }
 
 // Hot-column compaction: the (at most hot_max) columns with the largest sampled entry counts get
-// dense ranks, and their entries store ~rank.  The threshold is the smallest sampled count whose
-// column set fits in hot_max, found by bisection on device-side counts.
+// dense ranks, and their entries will store ~rank.  Counts are sampled from the sorted keys
+// (repeats included).  The threshold is the smallest sampled count whose column set fits in
+// hot_max, found by bisection on device-side counts.  On return *hm describes the set (bitmap +
+// word prefixes, conversion temporaries) and the handle owns hot_cols and the x_hot scratch.
 static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot_opt,
-                                     Readback* rb_dev, hipStream_t s) {
-    const int64_t n = A->n, nnz = A->nnz;
+                                     const uint64_t* keys, int64_t E, uint64_t cmask,
+                                     Readback* rb_dev, hipStream_t s, HotMap* hm) {
+    const int64_t n = A->n;
+    *hm = HotMap{};
     int64_t hot_max = hot_opt;
     if (hot_opt < 0) hot_max = n >= HOT_AUTO_MIN_N ? HOT_AUTO_MAX : 0;
     if (hot_max > n) hot_max = n;
-    if (hot_max <= 0 || nnz <= 0) return SPX_OK;
-    uint32_t *freq, *tsums;
-    int32_t* colmap;
+    if (hot_max <= 0 || E <= 0) return SPX_OK;
+    uint32_t *freq, *tsums, *pre;
+    uint64_t* bits;
+    const int64_t nwords = (n + 63) / 64;
     SPX_TRY(tmp.get(&freq, (size_t)n, "column counts"));
-    SPX_TRY(tmp.get(&colmap, (size_t)n, "column map"));
     SPX_TRY(tmp.get(&tsums, scan_tile_count(n), "scan tile sums"));
+    SPX_TRY(tmp.get(&bits, (size_t)nwords, "hot bitmap"));
+    SPX_TRY(tmp.get(&pre, (size_t)nwords, "hot word prefixes"));
     HIP_TRY(hipMemsetAsync(freq, 0, (size_t)n * 4, s));
-    const int64_t stride = nnz > HOT_MAX_SAMPLES ? (nnz + HOT_MAX_SAMPLES - 1) / HOT_MAX_SAMPLES : 1;
-    HIP_TRY(launch_hot_count(A->col, nnz, stride, freq, s));
+    const int64_t stride = E > HOT_MAX_SAMPLES ? (E + HOT_MAX_SAMPLES - 1) / HOT_MAX_SAMPLES : 1;
+    HIP_TRY(launch_hot_count(keys, E, stride, cmask, freq, s));
     Readback rb;
     auto count_ge = [&](uint32_t tau, uint32_t* out) -> spx_status {
         HIP_TRY(launch_hot_count_ge(freq, n, tau, tsums, &rb_dev->totals[3], s));
@@ -263,7 +269,7 @@ static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot
     SPX_TRY(count_ge(1, &c1));
     uint32_t tau = 1;
     if (c1 > (uint64_t)hot_max) {
-        uint64_t lo = 2, hi = (uint64_t)((nnz + stride - 1) / stride) + 1;  // count_ge(hi) == 0
+        uint64_t lo = 2, hi = (uint64_t)((E + stride - 1) / stride) + 1;  // count_ge(hi) == 0
         while (lo < hi) {
             const uint64_t mid = (lo + hi) / 2;
             uint32_t c;
@@ -282,11 +288,12 @@ static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot
     SPX_TRY(tmp.get(&x_hot, nhot, "hot x"));
     keep(tmp, A, hot_cols);
     keep(tmp, A, x_hot);
-    HIP_TRY(launch_hot_ranks(freq, n, tau, tsums, colmap, hot_cols, s));
-    HIP_TRY(launch_hot_remap(A->col, nnz, colmap, s));
+    HIP_TRY(launch_hot_set(freq, n, tau, bits, pre, hot_cols, tsums, s));
     A->hot_cols = hot_cols;
     A->x_hot = x_hot;
     A->nhot = (int32_t)nhot;
+    hm->bits = bits;
+    hm->pre = pre;
     return SPX_OK;
 }
 
@@ -302,7 +309,7 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
     const int rbits = ceil_log2_u64((uint64_t)(m > 1 ? m : 1));
     int k = 0;
     int64_t nbr = 0, nbc = 0;
-    if (fmt == SPX_CSB_HILBERT) {
+    if (spx_is_csb(fmt)) {
         k = o->log2_beta > 0 ? o->log2_beta : csbh_default_log2_beta(m, n);
         if (k < 1 || k > 16)
             return fail(SPX_ERR_INVALID_ARG, "log2_beta %d outside [1,16]", k);
@@ -340,7 +347,7 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
     keep(tmp, A, val_out);
     A->val = val_out;
 
-    if (fmt == SPX_CSB_HILBERT) {
+    if (spx_is_csb(fmt)) {
         const int64_t nblk = nbr * nbc;
         int32_t *bp;
         uint32_t* packed;
@@ -351,8 +358,13 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
         A->blk_ptr = bp;
         A->packed = packed;
         HIP_TRY(launch_fill_i32(bp, nblk + 1, 0, s));
-        HIP_TRY(launch_gather_csbh(se.keys, se.vals, se.head_pos, E, nnz, k, packed,
-                                   val_out, bp + 1, s));
+        if (se.head_tiles)
+            HIP_TRY(launch_dedup_gather(se.keys, se.vals, E, se.head_tiles,
+                                        fmt == SPX_CSB_HILBERT ? 1 : 2, 2 * k, HotMap{},
+                                        (int32_t*)packed, val_out, bp + 1, s));
+        else
+            HIP_TRY(launch_gather_csb(se.keys, se.vals, nullptr, E, nnz, k,
+                                      fmt == SPX_CSB_HILBERT, packed, val_out, bp + 1, s));
         if (scan_tile_count(nblk) > tsn) tsn = scan_tile_count(nblk);
         SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
         HIP_TRY(launch_max_scan_i32(bp + 1, nblk, tsums, s));
@@ -393,11 +405,17 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
     A->row_ptr = rp;
     A->col = col;
     HIP_TRY(launch_fill_i32(rp, (int64_t)m + 1, 0, s));
-    HIP_TRY(launch_gather_csr(se.keys, se.vals, se.head_pos, E, nnz, cbits, col, val_out,
+    HotMap hm;
+    SPX_TRY(select_hot_columns(tmp, A, o->hot_columns, se.keys, E,
+                               cbits >= 64 ? ~0ull : ((1ull << cbits) - 1ull), rb_dev, s, &hm));
+    if (se.head_tiles)
+        HIP_TRY(launch_dedup_gather(se.keys, se.vals, E, se.head_tiles, 0, cbits, hm, col,
+                                    val_out, rp + 1, s));
+    else
+        HIP_TRY(launch_gather_csr(se.keys, se.vals, nullptr, E, nnz, cbits, hm, col, val_out,
                               rp + 1, s));
     SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
     HIP_TRY(launch_max_scan_i32(rp + 1, m, tsums, s));
-    SPX_TRY(select_hot_columns(tmp, A, o->hot_columns, rb_dev, s));
 
     if (fmt == SPX_CSR_MERGE) {
         const int64_t total = (int64_t)m + nnz;
@@ -482,7 +500,7 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
     if (!out) return fail(SPX_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!coo) return fail(SPX_ERR_INVALID_ARG, "coo is NULL");
-    if (fmt != SPX_CSR_ROWSPLIT && fmt != SPX_CSR_MERGE && fmt != SPX_CSB_HILBERT)
+    if (fmt != SPX_CSR_ROWSPLIT && fmt != SPX_CSR_MERGE && !spx_is_csb(fmt))
         return fail(SPX_ERR_INVALID_ARG, "unknown format %d", (int)fmt);
     if (coo->m < 0 || coo->n < 0 || coo->nnz < 0)
         return fail(SPX_ERR_INVALID_ARG, "negative size (m=%d n=%d nnz=%lld)", coo->m, coo->n,
@@ -505,8 +523,8 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
         return fail(SPX_ERR_INVALID_ARG, "log2_beta %d outside [0,16]", o.log2_beta);
     if (o.tile_items < 0) return fail(SPX_ERR_INVALID_ARG, "tile_items < 0");
     if (o.hot_columns < -1) return fail(SPX_ERR_INVALID_ARG, "hot_columns < -1");
-    if (fmt != SPX_CSB_HILBERT && o.tile_items != 0)
-        return fail(SPX_ERR_UNSUPPORTED, "tile_items is only adjustable for CSBH");
+    if (!spx_is_csb(fmt) && o.tile_items != 0)
+        return fail(SPX_ERR_UNSUPPORTED, "tile_items is only adjustable for CSB/CSBH");
 
     hipStream_t s = (hipStream_t)stream;
     int device = 0;
@@ -576,7 +594,8 @@ extern "C" spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* s
     switch (A->fmt) {
         case SPX_CSR_MERGE: HIP_TRY(spmv_merge(A, x, y, s)); break;
         case SPX_CSR_ROWSPLIT: HIP_TRY(spmv_rowsplit(A, x, y, s)); break;
-        case SPX_CSB_HILBERT: HIP_TRY(spmv_csbh(A, x, y, s)); break;
+        case SPX_CSB_HILBERT:
+        case SPX_CSB_ZMORTON: HIP_TRY(spmv_csbh(A, x, y, s)); break;
         default: return fail(SPX_ERR_INVALID_ARG, "corrupt handle");
     }
     return SPX_OK;
@@ -601,7 +620,7 @@ extern "C" spx_status spx_matrix_export(spx_matrix A, spx_array which, void* dst
     const void* src = nullptr;
     int64_t len = 0;
     bool exists = false;
-    const bool crs = A->fmt != SPX_CSB_HILBERT;
+    const bool crs = !spx_is_csb(A->fmt);
     switch (which) {
         case SPX_ARRAY_ROW_PTR:
             exists = crs;

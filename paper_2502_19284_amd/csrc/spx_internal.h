@@ -91,15 +91,28 @@ struct Readback {
 void* spx_dev_alloc(size_t bytes, hipStream_t s);
 void spx_dev_free(void* p, hipStream_t s);
 
+// Stored column index of column c: ~rank for hot columns, c otherwise (bits == null: no hot set).
+struct HotMap {
+    const uint64_t* bits = nullptr;
+    const uint32_t* pre = nullptr;
+    __device__ __forceinline__ int32_t map(uint32_t c) const {
+        if (!bits) return (int32_t)c;
+        const uint64_t b = bits[c >> 6];
+        const uint64_t bit = 1ull << (c & 63u);
+        if (!(b & bit)) return (int32_t)c;
+        return ~(int32_t)(pre[c >> 6] + (uint32_t)__popcll(b & (bit - 1ull)));
+    }
+};
+
 // ------------------------------------------------------------------ conversion launchers
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_init_readback(Readback* rb, hipStream_t s);
 hipError_t launch_keys_csr(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
                            int32_t n, int cbits, uint64_t* keys, uint32_t* err,
                            unsigned long long* masks, hipStream_t s);
-hipError_t launch_keys_csbh(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
-                            int32_t n, int k, int64_t nbc, uint64_t* keys, uint32_t* err,
-                            unsigned long long* masks, hipStream_t s);
+hipError_t launch_keys_csb(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+                           int32_t n, int k, int64_t nbc, bool hilbert, uint64_t* keys,
+                           uint32_t* err, unsigned long long* masks, hipStream_t s);
 // Stable LSD radix sort of (keys in k0, 64-bit payloads read from vfirst).  Digits whose bits
 // never vary (per `vary`) are skipped.  k1, v0, v1 are scratch of E elements; the sorted arrays
 // are returned through keys_sorted / vals_sorted (one of the buffers, or vfirst if no pass ran).
@@ -110,14 +123,18 @@ hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* 
 size_t radix_hist_elems(int64_t E);
 hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_sums,
                               uint32_t* total, hipStream_t s);
-hipError_t launch_dedup_heads(const uint64_t* keys, int64_t E, const uint32_t* tile_sums,
-                              int32_t* head_pos, hipStream_t s);
+// Fused: scan of run heads (tile counts from launch_dedup_count) + run sums + index/value
+// output + row (block) end marks.  mode 0 CRS, 1 CSB Hilbert, 2 CSB Z-Morton.
+hipError_t launch_dedup_gather(const uint64_t* keys, const double* vals, int64_t E,
+                               const uint32_t* tile_sums, int mode, int shiftbits, HotMap hm,
+                               int32_t* idx_out, double* val_out, int32_t* ends, hipStream_t s);
 hipError_t launch_gather_csr(const uint64_t* keys, const double* vals, const int32_t* head_pos,
-                             int64_t E, int64_t nnz_out, int cbits, int32_t* col_out,
+                             int64_t E, int64_t nnz_out, int cbits, HotMap hm, int32_t* col_out,
                              double* val_out, int32_t* row_end, hipStream_t s);
-hipError_t launch_gather_csbh(const uint64_t* keys, const double* vals, const int32_t* head_pos,
-                              int64_t E, int64_t nnz_out, int k, uint32_t* packed_out,
-                              double* val_out, int32_t* blk_end, hipStream_t s);
+hipError_t launch_gather_csb(const uint64_t* keys, const double* vals, const int32_t* head_pos,
+                             int64_t E, int64_t nnz_out, int k, bool hilbert, uint32_t* packed_out,
+                             double* val_out, int32_t* blk_end, hipStream_t s);
+static inline bool spx_is_csb(spx_format f) { return f == SPX_CSB_HILBERT || f == SPX_CSB_ZMORTON; }
 // In-place inclusive max-scan of ends[0..len) (turns "end of last entry" marks into pointers).
 hipError_t launch_max_scan_i32(int32_t* ends, int64_t len, uint32_t* tile_sums, hipStream_t s);
 size_t scan_tile_count(int64_t n);
@@ -126,18 +143,17 @@ size_t scan_tile_count(int64_t n);
 #define HOT_AUTO_MAX (1 << 20)
 #define HOT_AUTO_MIN_N (1 << 19)
 #define HOT_MAX_SAMPLES (1 << 23)
-hipError_t launch_hot_count(const int32_t* col, int64_t nnz, int64_t stride, uint32_t* freq,
-                            hipStream_t s);
+hipError_t launch_hot_count(const uint64_t* keys, int64_t E, int64_t stride, uint64_t cmask,
+                            uint32_t* freq, hipStream_t s);
 hipError_t launch_hot_count_ge(const uint32_t* freq, int64_t n, uint32_t tau, uint32_t* tile_sums,
                                uint32_t* total, hipStream_t s);
-hipError_t launch_hot_ranks(const uint32_t* freq, int64_t n, uint32_t tau,
-                            const uint32_t* tile_sums, int32_t* colmap, int32_t* hot_cols,
-                            hipStream_t s);
-hipError_t launch_hot_remap(int32_t* col, int64_t nnz, const int32_t* colmap, hipStream_t s);
+hipError_t launch_hot_set(const uint32_t* freq, int64_t n, uint32_t tau, uint64_t* bits,
+                          uint32_t* pre, int32_t* hot_cols, uint32_t* tile_sums, hipStream_t s);
 hipError_t launch_hot_gather(const int32_t* hot_cols, int32_t nhot, const double* x,
                              double* x_hot, hipStream_t s);
 hipError_t launch_hot_unmap(const int32_t* col, int64_t nnz, const int32_t* hot_cols,
                             int32_t* out, hipStream_t s);
+
 
 // ------------------------------------------------------------------ partitions
 hipError_t launch_merge_coords(const int32_t* row_ptr, int32_t m, int64_t nnz, int2* coords,

@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("SPX_LIBRARY") or os.path.join(_PKG, "libspx.so")
 SPX_OK = 0
 STATUS = {0: "SPX_OK", -1: "SPX_ERR_INVALID_ARG", -2: "SPX_ERR_INDEX", -3: "SPX_ERR_RANGE",
           -4: "SPX_ERR_ALIAS", -5: "SPX_ERR_NOMEM", -6: "SPX_ERR_HIP", -7: "SPX_ERR_UNSUPPORTED"}
-FORMATS = {"rowsplit": 0, "merge": 1, "csbh": 2}
+FORMATS = {"rowsplit": 0, "merge": 1, "csbh": 2, "csb": 3}
 FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
 ARRAYS = {"row_ptr": (0, torch.int32), "col_ind": (1, torch.int32), "values": (2, torch.float64),
           "blk_ptr": (3, torch.int32), "packed": (4, torch.int32), "parts": (5, torch.int32)}
@@ -269,7 +269,7 @@ class Matrix:
 def convert(row, col, val, shape, fmt="merge", sum_duplicates=True, log2_beta=0,
             tile_items=0, hot_columns=-1, stream=None):
     """Convert device triplets (int32 row, int32 col, float64 val) to a Matrix of format `fmt`
-    ('rowsplit', 'merge' or 'csbh').  hot_columns: -1 automatic, 0 off, k > 0 at most k columns
+    ('rowsplit', 'merge', 'csbh' or 'csb').  hot_columns: -1 automatic, 0 off, k > 0 at most k columns
     in the compact x copy (CRS formats)."""
     if fmt not in FORMATS:
         raise ValueError("unknown format %r (expected one of %s)" % (fmt, sorted(FORMATS)))

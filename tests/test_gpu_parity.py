@@ -13,7 +13,7 @@ import synth
 from oracle import formats, measure, mergepath, spmv
 
 pytestmark = pytest.mark.gpu
-FMTS = ["rowsplit", "merge", "csbh"]
+FMTS = ["rowsplit", "merge", "csbh", "csb"]
 TOL = 1e-12
 
 
@@ -62,10 +62,11 @@ def _check_int(y, ref, what):
 
 def _check_structure(A, m, n, row, col, val):
     cr, cc, cv, _ = spmv.canonical_coo(m, n, row, col, val)
-    if A.format == "csbh":
-        formats.check_csbh(m, n, A.log2_beta, A.export("blk_ptr").cpu().numpy(),
-                           A.export("packed").cpu().numpy().view(np.uint32),
-                           A.export("values").cpu().numpy(), cr, cc, cv)
+    if A.format in ("csbh", "csb"):
+        formats.check_csb(m, n, A.log2_beta, A.export("blk_ptr").cpu().numpy(),
+                          A.export("packed").cpu().numpy().view(np.uint32),
+                          A.export("values").cpu().numpy(), cr, cc, cv,
+                          "hilbert" if A.format == "csbh" else "zmorton")
     else:
         formats.check_crs(m, n, A.export("row_ptr").cpu().numpy(),
                           A.export("col_ind").cpu().numpy(), A.export("values").cpu().numpy(),
@@ -205,17 +206,18 @@ def test_ragged_long_rows(spx, fmt, kind):
 
 
 @pytest.mark.parametrize("log2_beta,unit", [(1, 0), (4, 64), (6, 1000), (9, 5000), (13, 0)])
-def test_csbh_block_sizes_and_split_rows(spx, log2_beta, unit):
+@pytest.mark.parametrize("fmt", ["csbh", "csb"])
+def test_csbh_block_sizes_and_split_rows(spx, log2_beta, unit, fmt):
     # small units force block rows to be split into several units with partial slices
     m, n = 3001, 4099
     row, col = _ragged_matrix(21, m, n, 60_000, long_rows=[(100, 12_000)])
     val = synth.values(len(row), seed=22, kind="int")
     x = synth.xvec(n, seed=23, kind="int")
-    say("csbh beta", log2_beta, "unit", unit)
+    say(fmt, "beta", log2_beta, "unit", unit)
     ref = spmv.reference(m, n, row, col, val, x)
-    A, y = _run(spx, "csbh", m, n, row, col, val, x, log2_beta=log2_beta, tile_items=unit)
+    A, y = _run(spx, fmt, m, n, row, col, val, x, log2_beta=log2_beta, tile_items=unit)
     assert A.log2_beta == log2_beta
-    _check_int(y, ref, "csbh int beta %d" % log2_beta)
+    _check_int(y, ref, "%s int beta %d" % (fmt, log2_beta))
     _check_structure(A, m, n, row, col, val)
 
 
