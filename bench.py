@@ -79,9 +79,9 @@ def kernel_bytes(name, E, nnz, m, passes):
         return 8 * E
     if name == "keys":
         return 16 * E
-    if name == "gather":
-        # sorted keys and values read once, head positions, column and value written
-        return 16 * E + 4 * nnz + 12 * nnz
+    if name in ("gather", "dedup_gather"):
+        # sorted keys and values read once, column (packed index) and value written
+        return 16 * E + 12 * nnz
     return None
 
 

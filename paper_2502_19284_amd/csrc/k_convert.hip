@@ -461,32 +461,67 @@ hipError_t launch_gather_csb(const uint64_t* keys, const double* vals, const int
     return hipGetLastError();
 }
 
-// The scan over run heads calls this for every sorted position: a head at position i becomes
-// output entry u = (heads before i); its run is summed in increasing position (= increasing
-// triplet index) and the row (block) end mark is set as in k_gather.
+// Fused repeat summing + populate.  Workgroup b owns the sorted positions of scan tile b (the
+// same SCAN_TILE tiling as launch_dedup_count, whose scanned tile counts give each tile's first
+// output index).  The tile's keys are staged in LDS; run heads are ranked with a workgroup scan;
+// then each head (processed in strided, coalesced order) sums its run in increasing position
+// (= increasing triplet index, the sort being stable), writes its index and value, and marks the
+// end of its row (block) for the max-scan.
+#define DG_NT SCAN_NT
+#define DG_IPT SCAN_IPT
+#define DG_TILE SCAN_TILE
+
 template <int MODE>
-struct StoreGather {
-    const uint64_t* keys;
-    const double* vals;
-    int64_t E;
-    int shiftbits;
-    HotMap hm;
-    int32_t* idx_out;
-    double* val_out;
-    int32_t* ends;
-    __device__ void operator()(int64_t i, uint32_t incl, uint32_t item) const {
-        if (!item) return;
-        const int64_t u = (int64_t)incl - 1;
-        const uint64_t key = keys[i];
-        double acc = vals[i];
-        int64_t e = i + 1;
-        while (e < E && keys[e] == key) {
-            acc = acc + vals[e];
+__global__ __launch_bounds__(DG_NT) void k_dedup_gather(
+    const uint64_t* __restrict__ keys, const double* __restrict__ vals, int64_t E,
+    const uint32_t* __restrict__ tile_off, int shiftbits, HotMap hm,
+    int32_t* __restrict__ idx_out, double* __restrict__ val_out, int32_t* __restrict__ ends) {
+    __shared__ uint64_t s_key[DG_TILE + 1];              // s_key[i+1] = keys[base+i]
+    __shared__ uint32_t s_u[DG_TILE + DG_TILE / 16];     // output index of head i (skewed)
+    __shared__ uint32_t s_tmp[DG_NT / SPX_WAVE];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * DG_TILE;
+    const int64_t rem = E - base;
+    const int cnt = rem < DG_TILE ? (int)rem : DG_TILE;
+    for (int i = tid; i < cnt; i += DG_NT) s_key[i + 1] = keys[base + i];
+    if (tid == 0) s_key[0] = base > 0 ? keys[base - 1] : ~keys[0];  // position 0 is a head
+    __syncthreads();
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < DG_IPT; ++j) {
+        const int i = tid * DG_IPT + j;
+        if (i < cnt && s_key[i + 1] != s_key[i]) ++c;
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan<DG_NT, uint32_t, OpSum<uint32_t>>(c, s_tmp, &total);
+    run += tile_off[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < DG_IPT; ++j) {
+        const int i = tid * DG_IPT + j;
+        if (i < cnt && s_key[i + 1] != s_key[i]) s_u[scan_skew(i)] = run++;
+    }
+    __syncthreads();
+    const uint64_t lowmask = (1ull << shiftbits) - 1ull;
+    for (int i = tid; i < cnt; i += DG_NT) {
+        const uint64_t key = s_key[i + 1];
+        if (key == s_key[i]) continue;
+        const int64_t u = s_u[scan_skew(i)];
+        double acc = vals[base + i];
+        int64_t e = i + 1;  // tile-relative position after the run
+        uint64_t next = 0;
+        bool more = false;
+        while (base + e < E) {
+            next = e < cnt ? s_key[e + 1] : keys[base + e];
+            if (next != key) {
+                more = true;
+                break;
+            }
+            acc = acc + vals[base + e];
             ++e;
         }
         val_out[u] = acc;
         const uint64_t major = key >> shiftbits;
-        const uint32_t d = (uint32_t)(key & ((1ull << shiftbits) - 1ull));
+        const uint32_t d = (uint32_t)(key & lowmask);
         if (MODE != 0) {
             const int k = shiftbits >> 1;
             uint32_t lc, lr;
@@ -496,24 +531,25 @@ struct StoreGather {
         } else {
             idx_out[u] = hm.map(d);
         }
-        if (e >= E || (keys[e] >> shiftbits) != major) ends[major] = (int32_t)(u + 1);
+        if (!more || (next >> shiftbits) != major) ends[major] = (int32_t)(u + 1);
     }
-};
+}
 
 hipError_t launch_dedup_gather(const uint64_t* keys, const double* vals, int64_t E,
                                const uint32_t* tile_sums, int mode, int shiftbits, HotMap hm,
                                int32_t* idx_out, double* val_out, int32_t* ends, hipStream_t s) {
+    if (E <= 0) return hipSuccess;
+    const unsigned g = spx_div_up(E, DG_TILE);
     if (mode == 0)
-        return scan_phase3<uint32_t, OpSum<uint32_t>>(
-            LoadHead{keys}, StoreGather<0>{keys, vals, E, shiftbits, hm, idx_out, val_out, ends},
-            E, tile_sums, s);
-    if (mode == 1)
-        return scan_phase3<uint32_t, OpSum<uint32_t>>(
-            LoadHead{keys}, StoreGather<1>{keys, vals, E, shiftbits, hm, idx_out, val_out, ends},
-            E, tile_sums, s);
-    return scan_phase3<uint32_t, OpSum<uint32_t>>(
-        LoadHead{keys}, StoreGather<2>{keys, vals, E, shiftbits, hm, idx_out, val_out, ends}, E,
-        tile_sums, s);
+        SPX_LAUNCH("dedup_gather", (k_dedup_gather<0>), dim3(g), dim3(DG_NT), 0, s, keys, vals, E,
+                   tile_sums, shiftbits, hm, idx_out, val_out, ends);
+    else if (mode == 1)
+        SPX_LAUNCH("dedup_gather", (k_dedup_gather<1>), dim3(g), dim3(DG_NT), 0, s, keys, vals, E,
+                   tile_sums, shiftbits, hm, idx_out, val_out, ends);
+    else
+        SPX_LAUNCH("dedup_gather", (k_dedup_gather<2>), dim3(g), dim3(DG_NT), 0, s, keys, vals, E,
+                   tile_sums, shiftbits, hm, idx_out, val_out, ends);
+    return hipGetLastError();
 }
 
 struct LoadI32 {
