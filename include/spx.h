@@ -55,6 +55,8 @@ typedef int32_t spx_format;
 
 typedef int32_t spx_dtype;
 #define SPX_F64 0
+#define SPX_F32 1  /* stored values only: products take FP32 x and y (spx_spmv_f32)      */
+#define SPX_BF16 2 /* bfloat16 stored values (round to nearest even); FP32 x and y        */
 
 /* ------------------------------------------------------------------ inputs */
 /* Triplet format (Section 2): entry i is (row[i], col[i], val[i]).  Entries may come in any order
@@ -78,6 +80,8 @@ typedef struct {
     int32_t hot_columns;    /* CRS formats: at most this many of the most frequent columns get a
                              * compact copy of their x values per product (x_hot); -1 = automatic
                              * (up to 2^20 when n >= 2^19), 0 = off.  y is unchanged by it.      */
+    spx_dtype value_type;   /* stored value type: SPX_F64 (default), or SPX_F32 / SPX_BF16 for
+                             * the CRS formats (repeats are summed in FP64, then rounded once)   */
 } spx_convert_opts;
 
 typedef struct {
@@ -104,7 +108,7 @@ typedef struct {
 typedef int32_t spx_array;
 #define SPX_ARRAY_ROW_PTR 0 /* CRS formats: int32[m+1]                                      */
 #define SPX_ARRAY_COL_IND 1 /* CRS formats: int32[nnz], ascending inside a row              */
-#define SPX_ARRAY_VALUES 2  /* all formats: float64[nnz] in storage order                   */
+#define SPX_ARRAY_VALUES 2  /* all formats: values[nnz] in storage order, of the stored type */
 #define SPX_ARRAY_BLK_PTR 3 /* CSB/CSBH: int32[nbr*nbc+1], blocks in row-wise order         */
 #define SPX_ARRAY_PACKED 4  /* CSB/CSBH: uint32[nnz], (local_row << 16) | local_col, in the
                              * block's Hilbert (CSBH) or Z-Morton (CSB) order                  */
@@ -117,7 +121,7 @@ typedef void (*spx_free_fn)(void* ptr, void* stream, void* ctx);
 /* ------------------------------------------------------------------ entry points */
 
 /* Fill *opts with the defaults: sum_duplicates=1, log2_beta=0, validate=1, tile_items=0,
- * hot_columns=-1. */
+ * hot_columns=-1, value_type=SPX_F64. */
 spx_status spx_convert_opts_default(spx_convert_opts* opts);
 
 /*
@@ -148,6 +152,15 @@ spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt, const spx_conver
  * handle may be in flight at a time; products on different handles may overlap freely.
  */
 spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* stream);
+
+/*
+ * Reduced-precision product y = A x for a CRS matrix stored in FP32 or bfloat16 (value_type at
+ * conversion): x (n floats) and y (m floats) are device FP32; products and sums inside a merge
+ * tile or row block are FP32, sums that cross tiles and rows longer than a row block are FP64.
+ * Otherwise as spx_spmv.  Errors: UNSUPPORTED for an FP64 matrix (use spx_spmv), and spx_spmv
+ * returns UNSUPPORTED for a reduced-precision matrix.
+ */
+spx_status spx_spmv_f32(spx_matrix A, const float* x, float* y, void* stream);
 
 /* Sizes and format of a handle.  info: host. */
 spx_status spx_matrix_get_info(spx_matrix A, spx_matrix_info* info);

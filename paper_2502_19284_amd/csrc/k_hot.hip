@@ -98,20 +98,6 @@ hipError_t launch_hot_set(const uint32_t* freq, int64_t n, uint32_t tau, uint64_
     return hipGetLastError();
 }
 
-__global__ void k_hot_gather(const int32_t* __restrict__ hot_cols, int32_t nhot,
-                             const double* __restrict__ x, double* __restrict__ x_hot) {
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h < nhot) x_hot[h] = x[hot_cols[h]];
-}
-
-hipError_t launch_hot_gather(const int32_t* hot_cols, int32_t nhot, const double* x,
-                             double* x_hot, hipStream_t s) {
-    if (nhot <= 0) return hipSuccess;
-    SPX_LAUNCH("hot_gather", k_hot_gather, dim3(spx_div_up(nhot, 256)), dim3(256), 0, s,
-               hot_cols, nhot, x, x_hot);
-    return hipGetLastError();
-}
-
 // col_ind as the caller knows it: hot entries mapped back to their columns
 __global__ void k_hot_unmap(const int32_t* __restrict__ col, int64_t nnz,
                             const int32_t* __restrict__ hot_cols, int32_t* __restrict__ out) {

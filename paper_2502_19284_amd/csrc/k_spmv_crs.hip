@@ -1,0 +1,391 @@
+// k_spmv_crs.hip -- y = A x for the CRS formats (merge-path and row-split), gfx950.
+//
+// Templated on the stored value type V (double, float, or bfloat16 bits), the vector type X of
+// x and y (double for FP64 matrices, float for reduced-precision ones) and the accumulator ACC
+// used inside a tile or row block.  Sums that cross tiles (merge carries) and rows longer than a
+// row block (row-split long-row chunks) are always accumulated in FP64.
+//
+// All kernels are bound by memory traffic (about 12 bytes of matrix per 2 flops in FP64), and
+// within it by the x gathers (one cache request per entry).  Matrix streams and y use
+// non-temporal loads/stores so they do not displace x from L2; hot columns read the compact copy
+// x_hot (see k_hot.hip).  Every y element has a single writer; partial sums go to scratch and are
+// added by a second kernel in a fixed order, so results are deterministic.
+#include "dev_common.h"
+#include "spx_internal.h"
+
+template <typename T>
+__device__ __forceinline__ T ntload(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void ntstore(T* p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+
+// stored value -> arithmetic type
+__device__ __forceinline__ double vget(const double* p) { return ntload(p); }
+__device__ __forceinline__ float vget(const float* p) { return ntload(p); }
+__device__ __forceinline__ float vget(const uint16_t* p) {  // bfloat16: the upper half of a float
+    return __uint_as_float((uint32_t)ntload(p) << 16);
+}
+__device__ __forceinline__ double vget_plain(const double* p) { return *p; }
+__device__ __forceinline__ float vget_plain(const float* p) { return *p; }
+__device__ __forceinline__ float vget_plain(const uint16_t* p) {
+    return __uint_as_float((uint32_t)(*p) << 16);
+}
+
+// x value of a stored column index: negative indices address the compact hot copy
+template <typename X>
+__device__ __forceinline__ X xval(const X* __restrict__ x, const X* __restrict__ x_hot,
+                                  int32_t c) {
+    return c < 0 ? x_hot[~c] : x[c];
+}
+
+// ================================================================== merge-path CRS (Section 3.3)
+//
+// Tile t of MP_TILE items covers diagonals [t*MP_TILE, (t+1)*MP_TILE) of the merge of
+// A = row_ptr[1..m] (row ends) and B = 0..nnz-1 (entries).  The tile stages its row ends and the
+// products data[k]*x[col[k]] of its entries in LDS (coalesced loads, independent gathers), then
+// each thread walks MP_IPT items from its own split point: an entry adds its product to the
+// running value, a row end emits it.  The running value a thread leaves open is passed to later
+// threads by a segmented scan; the value the tile leaves open goes to carry[t] and is added into
+// y by the fix-up kernel.
+
+// segmented-sum combine: (flag, value) of an earlier then a later segment
+template <typename T>
+__device__ __forceinline__ void seg_combine(int& f, T& v, int f_later, T v_later) {
+    v = f_later ? v_later : v + v_later;
+    f = f | f_later;
+}
+
+template <typename V, typename X, typename ACC>
+__global__ __launch_bounds__(MP_NT) void k_spmv_merge(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const V* __restrict__ val, const X* __restrict__ x, const X* __restrict__ x_hot,
+    X* __restrict__ y, const int2* __restrict__ coords, int32_t* __restrict__ carry_row,
+    double* __restrict__ carry_val) {
+    __shared__ int32_t s_end[MP_TILE];
+    __shared__ ACC s_prod[MP_TILE];
+    __shared__ int s_wf[MP_NT / SPX_WAVE];
+    __shared__ ACC s_wv[MP_NT / SPX_WAVE];
+
+    const int tid = threadIdx.x;
+    const int t = blockIdx.x;
+    const int2 c0 = coords[t];
+    const int2 c1 = coords[t + 1];
+    const int r0 = c0.x, k0 = c0.y;
+    const int nrows = c1.x - r0, nnzt = c1.y - k0;
+
+    for (int i = tid; i < nrows; i += MP_NT) s_end[i] = ntload(row_ptr + r0 + 1 + i);
+#pragma unroll
+    for (int q = 0; q < MP_IPT; ++q) {
+        const int i = q * MP_NT + tid;
+        if (i < nnzt)
+            s_prod[i] = (ACC)vget(val + k0 + i) * (ACC)xval(x, x_hot, ntload(col + k0 + i));
+    }
+    __syncthreads();
+
+    const int items = nrows + nnzt;
+    const int d = min(tid * MP_IPT, items);
+    const int dend = min(d + MP_IPT, items);
+    int lo = max(0, d - nnzt), hi = min(d, nrows);
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_end[mid] <= k0 + d - mid - 1) lo = mid + 1;
+        else hi = mid;
+    }
+    const int i0 = lo;
+    int i = lo, j = d - lo;
+    ACC run = 0;
+    ACC outv[MP_IPT];
+    uint32_t endmask = 0;
+#pragma unroll
+    for (int q = 0; q < MP_IPT; ++q) {
+        outv[q] = 0;
+        if (d + q < dend) {
+            if (i < nrows && (j >= nnzt || s_end[i] <= k0 + j)) {
+                outv[q] = run;
+                run = 0;
+                endmask |= 1u << q;
+                ++i;
+            } else {
+                run += s_prod[j];
+                ++j;
+            }
+        }
+    }
+
+    // segmented exclusive scan of (has_end, open value) over the threads of the tile
+    int f = endmask != 0;
+    ACC v = run;
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < SPX_WAVE; o <<= 1) {
+        const int fu = __shfl_up(f, o, SPX_WAVE);
+        const ACC vu = __shfl_up(v, o, SPX_WAVE);
+        if (lane >= o) {
+            int fa = fu;
+            ACC va = vu;
+            seg_combine(fa, va, f, v);
+            f = fa;
+            v = va;
+        }
+    }
+    const int w = tid / SPX_WAVE;
+    if (lane == SPX_WAVE - 1) {
+        s_wf[w] = f;
+        s_wv[w] = v;
+    }
+    int fex = __shfl_up(f, 1, SPX_WAVE);
+    ACC vex = __shfl_up(v, 1, SPX_WAVE);
+    if (lane == 0) {
+        fex = 0;
+        vex = 0;
+    }
+    __syncthreads();
+    int fp = 0;
+    ACC vp = 0;
+    for (int ww = 0; ww < w; ++ww) seg_combine(fp, vp, s_wf[ww], s_wv[ww]);
+    seg_combine(fp, vp, fex, vex);
+    const ACC carry_in = vp;
+
+    // the tile's open value leaves through carry[t]
+    if (tid == MP_NT - 1) {
+        int ft = fp;
+        ACC vt = vp;
+        seg_combine(ft, vt, (int)(endmask != 0), run);
+        carry_row[t] = c1.x;  // m when nothing is left open
+        carry_val[t] = (double)vt;
+    }
+
+    // emit rows: stage in LDS (reusing s_prod), then coalesced stores
+    __syncthreads();
+    int r = i0;
+    bool first = true;
+#pragma unroll
+    for (int q = 0; q < MP_IPT; ++q) {
+        if (endmask & (1u << q)) {
+            ACC o = outv[q];
+            if (first) {
+                o = carry_in + o;
+                first = false;
+            }
+            s_prod[r] = o;
+            ++r;
+        }
+    }
+    __syncthreads();
+    for (int q = tid; q < nrows; q += MP_NT) ntstore(y + r0 + q, (X)s_prod[q]);
+}
+
+// Adds each tile's open value into y, tiles in order, in FP64.  The first tile of a run of tiles
+// that left the same row open sums the whole run, so every row is updated by one thread.
+template <typename X>
+__global__ void k_spmv_merge_fixup(const int32_t* __restrict__ carry_row,
+                                   const double* __restrict__ carry_val, int32_t tiles,
+                                   X* __restrict__ y, int32_t m) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tiles) return;
+    const int r = carry_row[t];
+    if (r >= m) return;
+    if (t > 0 && carry_row[t - 1] == r) return;
+    double acc = carry_val[t];
+    for (int u = t + 1; u < tiles && carry_row[u] == r; ++u) acc = acc + carry_val[u];
+    y[r] = (X)(acc + (double)y[r]);
+}
+
+template <typename X>
+__global__ void k_hot_gather_t(const int32_t* __restrict__ hot_cols, int32_t nhot,
+                               const X* __restrict__ x, X* __restrict__ x_hot) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h < nhot) x_hot[h] = x[hot_cols[h]];
+}
+
+template <typename X>
+static hipError_t hot_gather(const spx_matrix_s* A, const X* x, hipStream_t s) {
+    if (A->nhot <= 0) return hipSuccess;
+    SPX_LAUNCH("hot_gather", k_hot_gather_t<X>, dim3(spx_div_up(A->nhot, 256)), dim3(256), 0, s,
+               A->hot_cols, A->nhot, x, (X*)A->x_hot);
+    return hipGetLastError();
+}
+
+template <typename V, typename X, typename ACC>
+static hipError_t merge_t(const spx_matrix_s* A, const V* val, const X* x, X* y, hipStream_t s) {
+    if (A->mp_tiles <= 0) return hipSuccess;
+    hipError_t e = hot_gather<X>(A, x, s);
+    if (e != hipSuccess) return e;
+    SPX_LAUNCH("spmv_merge", (k_spmv_merge<V, X, ACC>), dim3(A->mp_tiles), dim3(MP_NT), 0, s,
+               A->row_ptr, A->col, val, x, (const X*)A->x_hot, y, A->mp_coords, A->mp_carry_row,
+               A->mp_carry_val);
+    SPX_LAUNCH("spmv_merge_fixup", k_spmv_merge_fixup<X>, dim3(spx_div_up(A->mp_tiles, 256)),
+               dim3(256), 0, s, A->mp_carry_row, A->mp_carry_val, A->mp_tiles, y, A->m);
+    return hipGetLastError();
+}
+
+// ================================================================== row-split CRS
+//
+// Workgroup b owns the rows [blocks[b], blocks[b+1]).  A block of short rows (< RS_NNZ entries,
+// <= RS_ROWS rows) stages its products in LDS with coalesced loads; then groups of g lanes
+// (g = largest power of two <= 64 with rows*g <= RS_NT) each reduce one row at a time, with a
+// shuffle tree inside the group.  Rows longer than RS_LONG are blocks on their own and are skipped
+// here: their RS_CHUNK-entry chunks are summed (in FP64) by k_spmv_rowsplit_long and the chunk
+// sums added in chunk order by k_spmv_rowsplit_finish.
+
+template <typename V, typename X, typename ACC>
+__global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const V* __restrict__ val, const X* __restrict__ x, const X* __restrict__ x_hot,
+    X* __restrict__ y, const int32_t* __restrict__ blocks) {
+    __shared__ ACC s_prod[RS_NNZ];
+    __shared__ int32_t s_rp[RS_ROWS + 1];
+    const int tid = threadIdx.x;
+    const int rs = blocks[blockIdx.x], re = blocks[blockIdx.x + 1];
+    const int rows = re - rs;
+    const int base = row_ptr[rs];
+    const int nnzb = row_ptr[re] - base;
+    if (rows == 1 && nnzb > RS_LONG) return;  // long row: chunk kernels
+    const bool staged = nnzb <= RS_NNZ && rows <= RS_ROWS;
+    if (staged) {
+        for (int i = tid; i <= rows; i += RS_NT) s_rp[i] = ntload(row_ptr + rs + i) - base;
+#pragma unroll
+        for (int q = 0; q < RS_NNZ / RS_NT; ++q) {
+            const int i = q * RS_NT + tid;
+            if (i < nnzb)
+                s_prod[i] =
+                    (ACC)vget(val + base + i) * (ACC)xval(x, x_hot, ntload(col + base + i));
+        }
+        __syncthreads();
+    }
+    int g = 64;
+    while (g > 1 && rows * g > RS_NT) g >>= 1;
+    const int grp = tid / g, gl = tid % g, ngrp = RS_NT / g;
+    for (int r = grp; r < rows; r += ngrp) {
+        ACC acc = 0;
+        if (staged) {
+            const int a = s_rp[r], b = s_rp[r + 1];
+            for (int k = a + gl; k < b; k += g) acc += s_prod[k];
+        } else {
+            const int a = row_ptr[rs + r], b = row_ptr[rs + r + 1];
+            for (int k = a + gl; k < b; k += g)
+                acc += (ACC)vget_plain(val + k) * (ACC)xval(x, x_hot, col[k]);
+        }
+        for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, SPX_WAVE);
+        if (gl == 0) y[rs + r] = (X)acc;
+    }
+}
+
+template <typename V, typename X>
+__global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit_long(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const V* __restrict__ val, const X* __restrict__ x, const X* __restrict__ x_hot,
+    const int32_t* __restrict__ long_rows, const int32_t* __restrict__ chunk_ptr, int32_t nlong,
+    double* __restrict__ partials) {
+    __shared__ double s_tmp[RS_NT / SPX_WAVE];
+    const int c = blockIdx.x;
+    // the long row that owns chunk c: last j with chunk_ptr[j] <= c
+    int lo = 0, hi = nlong - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (chunk_ptr[mid] <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    const int r = long_rows[lo];
+    const int kb = row_ptr[r] + (c - chunk_ptr[lo]) * RS_CHUNK;
+    const int ke = min(kb + RS_CHUNK, row_ptr[r + 1]);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = kb + threadIdx.x;
+    for (; k + 3 * RS_NT < ke; k += 4 * RS_NT) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            acc[q] += (double)vget(val + k + q * RS_NT) *
+                      (double)xval(x, x_hot, ntload(col + k + q * RS_NT));
+    }
+    for (; k < ke; k += RS_NT) acc[0] += (double)vget(val + k) * (double)xval(x, x_hot, ntload(col + k));
+    const double sum = block_reduce<RS_NT, double, OpSum<double>>((acc[0] + acc[1]) + (acc[2] + acc[3]),
+                                                                   s_tmp);
+    if (threadIdx.x == 0) partials[c] = sum;
+}
+
+template <typename X>
+__global__ void k_spmv_rowsplit_finish(const int32_t* __restrict__ long_rows,
+                                       const int32_t* __restrict__ chunk_ptr, int32_t nlong,
+                                       const double* __restrict__ partials, X* __restrict__ y) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nlong) return;
+    double acc = 0.0;
+    for (int c = chunk_ptr[j]; c < chunk_ptr[j + 1]; ++c) acc = acc + partials[c];
+    y[long_rows[j]] = (X)acc;
+}
+
+template <typename V, typename X, typename ACC>
+static hipError_t rowsplit_t(const spx_matrix_s* A, const V* val, const X* x, X* y,
+                             hipStream_t s) {
+    hipError_t e = hot_gather<X>(A, x, s);
+    if (e != hipSuccess) return e;
+    if (A->rs_nb > 0)
+        SPX_LAUNCH("spmv_rowsplit", (k_spmv_rowsplit<V, X, ACC>), dim3(A->rs_nb), dim3(RS_NT), 0,
+                   s, A->row_ptr, A->col, val, x, (const X*)A->x_hot, y, A->rs_blocks);
+    if (A->rs_nlong > 0) {
+        SPX_LAUNCH("spmv_rowsplit_long", (k_spmv_rowsplit_long<V, X>), dim3(A->rs_nchunks),
+                   dim3(RS_NT), 0, s, A->row_ptr, A->col, val, x, (const X*)A->x_hot,
+                   A->rs_long_rows, A->rs_chunk_ptr, A->rs_nlong, A->rs_partials);
+        SPX_LAUNCH("spmv_rowsplit_finish", k_spmv_rowsplit_finish<X>,
+                   dim3(spx_div_up(A->rs_nlong, 256)), dim3(256), 0, s, A->rs_long_rows,
+                   A->rs_chunk_ptr, A->rs_nlong, A->rs_partials, y);
+    }
+    return hipGetLastError();
+}
+
+// ================================================================== dispatch
+
+hipError_t spmv_merge(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
+    return merge_t<double, double, double>(A, A->val, x, y, s);
+}
+
+hipError_t spmv_rowsplit(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
+    return rowsplit_t<double, double, double>(A, A->val, x, y, s);
+}
+
+hipError_t spmv_crs_f32(const spx_matrix_s* A, const float* x, float* y, hipStream_t s) {
+    if (A->value_type == SPX_F32) {
+        const float* v = (const float*)A->val_lp;
+        return A->fmt == SPX_CSR_MERGE ? merge_t<float, float, float>(A, v, x, y, s)
+                                       : rowsplit_t<float, float, float>(A, v, x, y, s);
+    }
+    const uint16_t* v = (const uint16_t*)A->val_lp;
+    return A->fmt == SPX_CSR_MERGE ? merge_t<uint16_t, float, float>(A, v, x, y, s)
+                                   : rowsplit_t<uint16_t, float, float>(A, v, x, y, s);
+}
+
+// ================================================================== value rounding at conversion
+
+// round-to-nearest-even of a double to bfloat16 (8 significant bits), returned as its 16 bits
+__device__ __forceinline__ uint16_t bf16_rne(double v) {
+    if (v == 0.0 || !isfinite(v)) {
+        const float f = (float)v;
+        return (uint16_t)(__float_as_uint(f) >> 16);
+    }
+    int e;
+    frexp(v, &e);                      // |v| in [2^(e-1), 2^e)
+    const double q = ldexp(1.0, e - 8);  // spacing of 8-bit significands in that binade
+    const double r = rint(v / q) * q;  // v/q exact (power-of-two scaling); rint rounds to even
+    return (uint16_t)(__float_as_uint((float)r) >> 16);  // r has 8 significant bits: exact
+}
+
+__global__ void k_round_values(const double* __restrict__ in, int64_t n, int32_t vt,
+                               void* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (vt == SPX_F32) ((float*)out)[i] = (float)in[i];
+        else ((uint16_t*)out)[i] = bf16_rne(in[i]);
+    }
+}
+
+hipError_t launch_round_values(const double* in, int64_t n, int32_t vt, void* out,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 65536) g = 65536;
+    SPX_LAUNCH("round_values", k_round_values, dim3((unsigned)g), dim3(256), 0, s, in, n, vt, out);
+    return hipGetLastError();
+}

@@ -149,6 +149,7 @@ extern "C" spx_status spx_convert_opts_default(spx_convert_opts* opts) {
     opts->validate = 1;
     opts->tile_items = 0;
     opts->hot_columns = -1;
+    opts->value_type = SPX_F64;
     return SPX_OK;
 }
 
@@ -342,10 +343,15 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
     SPX_TRY(tmp.get(&rb_dev, 1, "readback"));
     HIP_TRY(launch_init_readback(rb_dev, s));
 
+    // FP64 values: kept by the handle, or (reduced precision) rounded once after the repeats are
+    // summed and then released with the other temporaries
     double* val_out;
     SPX_TRY(tmp.get(&val_out, (size_t)nnz, "values"));
-    keep(tmp, A, val_out);
-    A->val = val_out;
+    A->value_type = o->value_type;
+    if (o->value_type == SPX_F64) {
+        keep(tmp, A, val_out);
+        A->val = val_out;
+    }
 
     if (spx_is_csb(fmt)) {
         const int64_t nblk = nbr * nbc;
@@ -416,6 +422,22 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
                               rp + 1, s));
     SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
     HIP_TRY(launch_max_scan_i32(rp + 1, m, tsums, s));
+    if (o->value_type != SPX_F64) {
+        void* lp = nullptr;
+        if (o->value_type == SPX_F32) {
+            float* f;
+            SPX_TRY(tmp.get(&f, (size_t)nnz, "FP32 values"));
+            lp = f;
+        } else {
+            uint16_t* h;
+            SPX_TRY(tmp.get(&h, (size_t)nnz, "bfloat16 values"));
+            lp = h;
+        }
+        keep(tmp, A, lp);
+        A->val_lp = lp;
+        HIP_TRY(launch_round_values(val_out, nnz, o->value_type, lp, s));
+        // hot x copy holds FP32 values for these matrices (the buffer is large enough)
+    }
 
     if (fmt == SPX_CSR_MERGE) {
         const int64_t total = (int64_t)m + nnz;
@@ -482,6 +504,7 @@ static int64_t sum_owned_bytes(const spx_matrix_s* A) {
     b += (A->row_ptr ? ((int64_t)A->m + 1) * 4 : 0);
     b += (A->col ? A->nnz * 4 : 0);
     b += (A->val ? A->nnz * 8 : 0);
+    b += (A->val_lp ? A->nnz * (A->value_type == SPX_F32 ? 4 : 2) : 0);
     b += (A->blk_ptr ? (A->nbr * A->nbc + 1) * 4 : 0);
     b += (A->packed ? A->nnz * 4 : 0);
     b += (A->mp_coords ? ((int64_t)A->mp_tiles + 1) * 8 + (int64_t)A->mp_tiles * 12 : 0);
@@ -523,6 +546,10 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
         return fail(SPX_ERR_INVALID_ARG, "log2_beta %d outside [0,16]", o.log2_beta);
     if (o.tile_items < 0) return fail(SPX_ERR_INVALID_ARG, "tile_items < 0");
     if (o.hot_columns < -1) return fail(SPX_ERR_INVALID_ARG, "hot_columns < -1");
+    if (o.value_type != SPX_F64 && o.value_type != SPX_F32 && o.value_type != SPX_BF16)
+        return fail(SPX_ERR_INVALID_ARG, "unknown value_type %d", (int)o.value_type);
+    if (o.value_type != SPX_F64 && spx_is_csb(fmt))
+        return fail(SPX_ERR_UNSUPPORTED, "reduced-precision values are built for the CRS formats");
     if (!spx_is_csb(fmt) && o.tile_items != 0)
         return fail(SPX_ERR_UNSUPPORTED, "tile_items is only adjustable for CSB/CSBH");
 
@@ -582,8 +609,25 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
 
 // ------------------------------------------------------------------ product and handle
 
+extern "C" spx_status spx_spmv_f32(spx_matrix A, const float* x, float* y, void* stream) {
+    if (!A) return fail(SPX_ERR_INVALID_ARG, "matrix handle is NULL");
+    if (A->value_type == SPX_F64)
+        return fail(SPX_ERR_UNSUPPORTED, "FP64 matrix: use spx_spmv");
+    if (A->m > 0 && !y) return fail(SPX_ERR_INVALID_ARG, "y is NULL");
+    if (A->n > 0 && !x) return fail(SPX_ERR_INVALID_ARG, "x is NULL");
+    if (ranges_overlap(x, (size_t)A->n * 4, y, (size_t)A->m * 4))
+        return fail(SPX_ERR_ALIAS, "x and y overlap");
+    if (A->m == 0) return SPX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    A->last_stream = s;
+    HIP_TRY(spmv_crs_f32(A, x, y, s));
+    return SPX_OK;
+}
+
 extern "C" spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* stream) {
     if (!A) return fail(SPX_ERR_INVALID_ARG, "matrix handle is NULL");
+    if (A->value_type != SPX_F64)
+        return fail(SPX_ERR_UNSUPPORTED, "reduced-precision matrix: use spx_spmv_f32");
     if (A->m > 0 && !y) return fail(SPX_ERR_INVALID_ARG, "y is NULL");
     if (A->n > 0 && !x) return fail(SPX_ERR_INVALID_ARG, "x is NULL");
     if (ranges_overlap(x, (size_t)A->n * 8, y, (size_t)A->m * 8))
@@ -610,7 +654,7 @@ extern "C" spx_status spx_matrix_get_info(spx_matrix A, spx_matrix_info* info) {
     info->log2_beta = A->log2_beta;
     info->bytes = A->bytes;
     info->parts = A->parts;
-    info->value_type = SPX_F64;
+    info->value_type = A->value_type;
     return SPX_OK;
 }
 
@@ -634,8 +678,8 @@ extern "C" spx_status spx_matrix_export(spx_matrix A, spx_array which, void* dst
             break;
         case SPX_ARRAY_VALUES:
             exists = true;
-            src = A->val;
-            len = A->nnz * 8;
+            src = A->value_type == SPX_F64 ? (const void*)A->val : (const void*)A->val_lp;
+            len = A->nnz * (A->value_type == SPX_F64 ? 8 : A->value_type == SPX_F32 ? 4 : 2);
             break;
         case SPX_ARRAY_BLK_PTR:
             exists = !crs;

@@ -47,7 +47,9 @@ struct spx_matrix_s {
     // CRS formats
     int32_t* row_ptr = nullptr;  // m+1
     int32_t* col = nullptr;      // nnz
-    double* val = nullptr;       // nnz (all formats)
+    double* val = nullptr;       // nnz, FP64 matrices
+    int32_t value_type = SPX_F64;  // stored value type
+    void* val_lp = nullptr;      // nnz, FP32 or bfloat16 values of reduced-precision matrices
     // CSBH
     int32_t* blk_ptr = nullptr;  // nbr*nbc+1
     uint32_t* packed = nullptr;  // nnz
@@ -149,8 +151,6 @@ hipError_t launch_hot_count_ge(const uint32_t* freq, int64_t n, uint32_t tau, ui
                                uint32_t* total, hipStream_t s);
 hipError_t launch_hot_set(const uint32_t* freq, int64_t n, uint32_t tau, uint64_t* bits,
                           uint32_t* pre, int32_t* hot_cols, uint32_t* tile_sums, hipStream_t s);
-hipError_t launch_hot_gather(const int32_t* hot_cols, int32_t nhot, const double* x,
-                             double* x_hot, hipStream_t s);
 hipError_t launch_hot_unmap(const int32_t* col, int64_t nnz, const int32_t* hot_cols,
                             int32_t* out, hipStream_t s);
 
@@ -177,5 +177,9 @@ hipError_t csbh_units(const int32_t* blk_ptr, int64_t nbr, int64_t nbc, int64_t 
 
 // ------------------------------------------------------------------ products
 hipError_t spmv_merge(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
+// CRS product of a reduced-precision (FP32 / bfloat16) matrix with FP32 x and y
+hipError_t spmv_crs_f32(const spx_matrix_s* A, const float* x, float* y, hipStream_t s);
+// FP64 values -> FP32 (round to nearest) or bfloat16 bits (round to nearest even)
+hipError_t launch_round_values(const double* in, int64_t n, int32_t vt, void* out, hipStream_t s);
 hipError_t spmv_rowsplit(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
 hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);

@@ -20,6 +20,8 @@ STATUS = {0: "SPX_OK", -1: "SPX_ERR_INVALID_ARG", -2: "SPX_ERR_INDEX", -3: "SPX_
           -4: "SPX_ERR_ALIAS", -5: "SPX_ERR_NOMEM", -6: "SPX_ERR_HIP", -7: "SPX_ERR_UNSUPPORTED"}
 FORMATS = {"rowsplit": 0, "merge": 1, "csbh": 2, "csb": 3}
 FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
+VALUE_TYPES = {"f64": 0, "f32": 1, "bf16": 2}
+VALUE_TORCH = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}
 ARRAYS = {"row_ptr": (0, torch.int32), "col_ind": (1, torch.int32), "values": (2, torch.float64),
           "blk_ptr": (3, torch.int32), "packed": (4, torch.int32), "parts": (5, torch.int32)}
 
@@ -40,7 +42,7 @@ class CooDesc(ctypes.Structure):
 class ConvertOpts(ctypes.Structure):
     _fields_ = [("sum_duplicates", ctypes.c_int32), ("log2_beta", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("tile_items", ctypes.c_int32),
-                ("hot_columns", ctypes.c_int32)]
+                ("hot_columns", ctypes.c_int32), ("value_type", ctypes.c_int32)]
 
 
 class ConvertReport(ctypes.Structure):
@@ -85,6 +87,8 @@ def load(path=LIB_PATH):
     L.spx_convert.argtypes = [ctypes.POINTER(CooDesc), ctypes.c_int32, ctypes.POINTER(ConvertOpts),
                               P, ctypes.POINTER(P), ctypes.POINTER(ConvertReport)]
     L.spx_spmv.argtypes = [P, P, P, P]
+    L.spx_spmv_f32.argtypes = [P, P, P, P]
+    L.spx_spmv_f32.restype = ctypes.c_int32
     L.spx_matrix_get_info.argtypes = [P, ctypes.POINTER(MatrixInfo)]
     L.spx_matrix_export.argtypes = [P, ctypes.c_int32, P, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_int64), P]
@@ -214,6 +218,8 @@ class Matrix:
         self.bytes = int(info.bytes)
         self.log2_beta = int(info.log2_beta)
         self.parts = int(info.parts)
+        self.value_type = int(info.value_type)
+        self.vec_dtype = torch.float64 if self.value_type == 0 else torch.float32
         _live.add(self)
 
     @property
@@ -223,23 +229,28 @@ class Matrix:
         return self._h
 
     def spmv(self, x, out=None, stream=None):
-        """y = A x on the current (or given) stream; returns y (float64, length m)."""
+        """y = A x on the current (or given) stream; returns y of length m.  FP64 matrices take
+        and return float64 vectors, FP32/bfloat16 matrices float32 vectors."""
         m, n = self.shape
-        _dev_tensor(x, torch.float64, "x")
+        dt = self.vec_dtype
+        _dev_tensor(x, dt, "x")
         if x.numel() != n:
             raise ValueError("x has %d entries, expected %d" % (x.numel(), n))
         if out is None:
-            out = torch.empty(m, dtype=torch.float64, device=x.device)
-        _dev_tensor(out, torch.float64, "out")
+            out = torch.empty(m, dtype=dt, device=x.device)
+        _dev_tensor(out, dt, "out")
         if out.numel() != m:
             raise ValueError("out has %d entries, expected %d" % (out.numel(), m))
-        _check(load().spx_spmv(self.handle, ctypes.c_void_p(x.data_ptr()),
-                               ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        fn = load().spx_spmv if self.value_type == 0 else load().spx_spmv_f32
+        _check(fn(self.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                  _stream_ptr(stream)))
         return out
 
     def export(self, name, stream=None):
         """Copy one of the handle's arrays into a new device tensor."""
         which, dtype = ARRAYS[name]
+        if name == "values":
+            dtype = VALUE_TORCH[self.value_type]
         L = load()
         need = ctypes.c_int64(-1)
         st = L.spx_matrix_export(self.handle, which, None, 0, ctypes.byref(need), None)
@@ -267,10 +278,11 @@ class Matrix:
 
 
 def convert(row, col, val, shape, fmt="merge", sum_duplicates=True, log2_beta=0,
-            tile_items=0, hot_columns=-1, stream=None):
+            tile_items=0, hot_columns=-1, value_type="f64", stream=None):
     """Convert device triplets (int32 row, int32 col, float64 val) to a Matrix of format `fmt`
     ('rowsplit', 'merge', 'csbh' or 'csb').  hot_columns: -1 automatic, 0 off, k > 0 at most k columns
-    in the compact x copy (CRS formats)."""
+    in the compact x copy (CRS formats).  value_type: 'f64', or 'f32' / 'bf16' stored values
+    (CRS formats; products then take float32 x and y)."""
     if fmt not in FORMATS:
         raise ValueError("unknown format %r (expected one of %s)" % (fmt, sorted(FORMATS)))
     m, n = int(shape[0]), int(shape[1])
@@ -283,8 +295,10 @@ def convert(row, col, val, shape, fmt="merge", sum_duplicates=True, log2_beta=0,
     desc = CooDesc(m, n, E, ctypes.c_void_p(row.data_ptr() if E else 0),
                    ctypes.c_void_p(col.data_ptr() if E else 0),
                    ctypes.c_void_p(val.data_ptr() if E else 0), 0)
+    if value_type not in VALUE_TYPES:
+        raise ValueError("unknown value_type %r" % (value_type,))
     opts = ConvertOpts(1 if sum_duplicates else 0, int(log2_beta), 1, int(tile_items),
-                       int(hot_columns))
+                       int(hot_columns), VALUE_TYPES[value_type])
     rep = ConvertReport()
     h = ctypes.c_void_p()
     L = load()

@@ -39,10 +39,10 @@ def test_status_strings(L):
 
 
 def test_opts_default(L):
-    o = B.ConvertOpts(7, 7, 7, 7, 7)
+    o = B.ConvertOpts(7, 7, 7, 7, 7, 7)
     assert L.spx_convert_opts_default(ctypes.byref(o)) == 0
-    assert (o.sum_duplicates, o.log2_beta, o.validate, o.tile_items, o.hot_columns) == \
-        (1, 0, 1, 0, -1)
+    assert (o.sum_duplicates, o.log2_beta, o.validate, o.tile_items, o.hot_columns,
+            o.value_type) == (1, 0, 1, 0, -1, 0)
     assert L.spx_convert_opts_default(None) == -1
 
 
@@ -90,11 +90,16 @@ def test_convert_argument_errors(L):
     assert st == -1
     st, _ = _convert(L, d, fmt=1, opts=B.ConvertOpts(1, 0, 1, 100, -1))
     assert st == -7
+    st, _ = _convert(L, d, fmt=1, opts=B.ConvertOpts(1, 0, 1, 0, -1, 5))
+    assert st == -1
+    st, _ = _convert(L, d, fmt=2, opts=B.ConvertOpts(1, 0, 1, 0, -1, 1))
+    assert st == -7  # reduced precision is built for the CRS formats
 
 
 def test_handle_argument_errors(L):
     P = ctypes.c_void_p
     assert L.spx_spmv(None, P(0x1000), P(0x2000), None) == -1
+    assert L.spx_spmv_f32(None, P(0x1000), P(0x2000), None) == -1
     info = B.MatrixInfo()
     assert L.spx_matrix_get_info(None, ctypes.byref(info)) == -1
     assert L.spx_matrix_export(None, 0, None, 0, None, None) == -1

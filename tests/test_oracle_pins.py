@@ -438,3 +438,59 @@ def test_generators_deterministic():
     assert set(np.unique(v).tolist()) <= set(range(-3, 4))
     f = synth.values(100000, seed=1)
     assert f.min() >= -1 and f.max() < 1 and abs(f.mean()) < 0.02
+
+
+# ---------------------------------------------------------------- reduced-precision forms
+
+from oracle import precision  # noqa: E402
+
+
+def _bf16_candidates(x):
+    # brute force: all bfloat16 values (as float32 bit patterns with 16 zero low bits) around x
+    f = np.float32(x)
+    hi = int(np.array([f], np.float32).view(np.uint32)[0]) >> 16
+    cands = []
+    for h in range(hi - 2, hi + 3):
+        c = np.array([(h & 0xFFFF) << 16], np.uint32).view(np.float32)[0]
+        if np.isfinite(c):
+            cands.append((float(c), h & 0xFFFF))
+    return cands
+
+
+def test_bf16_rounding_brute_force():
+    rng = np.random.default_rng(17)
+    vals = np.concatenate([rng.uniform(-1, 1, 3000), rng.uniform(-300, 300, 1000),
+                           [1.0, -1.0, 3.0, 255.0, 256.0, 257.0, 1 + 2 ** -8, 1 + 3 * 2 ** -9,
+                            2 ** -130 * 0 + 1e-3]])
+    got = precision.round_bf16(vals)
+    for v, g in zip(vals, got):
+        cands = _bf16_candidates(v)
+        best = min(abs(c - v) for c, _ in cands)
+        near = [(c, h) for c, h in cands if abs(c - v) == best]
+        if len(near) == 2:  # a tie goes to the even significand
+            near = [(c, h) for c, h in near if h % 2 == 0]
+        assert g == near[0][0], (v, g, near)
+    # integers up to 256 are exact; 257 ties to 256 (even)
+    assert list(precision.round_bf16([3.0, -3.0, 256.0, 257.0])) == [3.0, -3.0, 256.0, 256.0]
+    assert precision.round_bf16([1 + 2 ** -8])[0] == 1.0          # tie -> even
+    assert precision.round_bf16([1 + 3 * 2 ** -9])[0] == 1 + 2 ** -7
+
+
+def test_f32_rounding_and_bound():
+    v = np.array([1 + 2 ** -24, 1 + 3 * 2 ** -25, 0.1])
+    r = precision.round_f32(v)
+    assert r[0] == 1.0 and r[1] == 1 + 2 ** -23
+    assert abs(r[2] - 0.1) <= 0.1 * precision.U32
+    # the bound covers a brute-force FP32 evaluation of random dot products
+    rng = np.random.default_rng(3)
+    for k in (1, 10, 1000):
+        a = rng.uniform(-1, 1, k)
+        x = rng.uniform(-1, 1, k)
+        af = a.astype(np.float32)
+        xf = x.astype(np.float32)
+        acc = np.float32(0)
+        for p in af * xf:
+            acc = np.float32(acc + p)
+        exact = float(sum(Fraction(float(u)) * Fraction(float(w)) for u, w in zip(a, x)))
+        s = float(np.sum(np.abs(a * x)))
+        assert abs(float(acc) - exact) <= precision.dot_error_bound(k, precision.U32) * s
