@@ -9,7 +9,7 @@ value = useful SpMV flops of the step (3 products x 2 nnz) / step time.
 
 Beside the step, each format's product is also timed alone (the steady state of a resident
 matrix, 10 warm-up and --spmv-reps timed products, minimum and median as in the paper's
-protocol), and its main kernel is set against the HBM roofline with the bytes model
+protocol), and its kernels (summed) are set against the HBM roofline with the bytes model
   B = 12 nnz + 4 (m+1) + 8 n_touched + 8 m (+ format-specific tables).
 Kernel durations come from the library's HIP-event profiler (events on the launch stream).
 """
@@ -28,8 +28,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 METRIC = "SpMV GFLOP/s + % HBM roofline (R-MAT s24); served p99 latency at req/s"
 FMTS = ("rowsplit", "merge", "csbh")
-# kernel that does the product's work in each format
-SPMV_KERNEL = {"rowsplit": "spmv_rowsplit", "merge": "spmv_merge", "csbh": "spmv_csbh"}
 WORKLOADS = {
     "rmat24": "R-MAT scale 24 (m = n = 16,777,216), edge factor 16 (268,435,456 raw entries), "
               "(a,b,c,d) = (0.57,0.19,0.19,0.05), repeats summed, FP64 values and x U(-1,1), "
@@ -39,6 +37,9 @@ WORKLOADS = {
     "rmat14": "R-MAT scale 14 (m = n = 16,384), edge factor 16, (a,b,c,d) = "
               "(0.57,0.19,0.19,0.05), FP64 values and x U(-1,1), seed 0",
 }
+
+
+KERNEL_SOURCES = ("k_spmv.hip", "k_spmv_crs.hip", "k_convert.hip", "k_hot.hip", "k_partition.hip")
 
 
 def log(*a):
@@ -53,9 +54,9 @@ def src_hash(*names):
     return h.hexdigest()[:16]
 
 
-def spmv_bytes(fmt, m, nnz, n_touched, A):
+def spmv_bytes(fmt, m, nnz, n_touched, A, val_bytes=8, vec_bytes=8):
     """Algorithmic bytes of one product (matrix read once, x touched columns once, y once)."""
-    b = 12 * nnz + 8 * n_touched + 8 * m
+    b = (4 + val_bytes) * nnz + vec_bytes * (n_touched + m)
     if fmt in ("rowsplit", "merge"):
         b += 4 * (m + 1)
     if fmt == "merge":
@@ -137,6 +138,85 @@ def cpu_baseline(w, budget_s=12.0):
             "ms_min": round(best * 1e3, 3), "ms_median": round(statistics.median(times) * 1e3, 3)}
 
 
+def time_products(spx, torch, A, x, y, reps):
+    """reps products of a resident matrix after 10 warm-up ones: per-call event times (ms) and
+    the library's per-kernel statistics over the timed calls."""
+    for _ in range(10):
+        A.spmv(x, out=y)
+    torch.cuda.synchronize()
+    spx.profile_enable(True)
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        A.spmv(x, out=y)
+        e1.record()
+        times.append((e0, e1))
+    torch.cuda.synchronize()
+    ks = spx.profile_collect()
+    spx.profile_enable(False)
+    return [a.elapsed_time(b) for a, b in times], ks
+
+
+def product_kernels(ks):
+    """The kernels of one product (each launched once per product) and their summed average and
+    minimum durations: the bytes model covers the whole product, so it is set against the time
+    of all its kernels."""
+    names = sorted(ks, key=lambda k: -ks[k]["avg_ms"])
+    return ("+".join(names), sum(ks[k]["avg_ms"] for k in names),
+            sum(ks[k]["min_ms"] for k in names))
+
+
+def precision_leg(spx, torch, args, row_d, col_d, val_d, x_d, m, n, n_touched, copy_gbs):
+    """FP32 and bfloat16 stored values (FP32 x, y) in the CRS formats: steady-state product, its
+    roofline, and the error against this library's FP64 product of the same matrix, per row
+    |y_lp - y_64| / (|A| |x|), with |A| |x| an FP64 product of the absolute stored values."""
+    A64 = spx.convert(row_d, col_d, val_d, (m, n), "rowsplit")
+    y64 = torch.empty(m, dtype=torch.float64, device="cuda")
+    A64.spmv(x_d, out=y64)
+    rp = A64.export("row_ptr").long()
+    ci = A64.export("col_ind")
+    va = A64.export("values")
+    A64.close()
+    rows = torch.repeat_interleave(torch.arange(m, device="cuda", dtype=torch.int32),
+                                   rp[1:] - rp[:-1])
+    Aabs = spx.convert(rows, ci, va.abs(), (m, n), "rowsplit")
+    s = torch.empty(m, dtype=torch.float64, device="cuda")
+    Aabs.spmv(x_d.abs(), out=s)
+    Aabs.close()
+    del rows, ci, va, rp
+    nzr = s > 0
+    x32 = x_d.float()
+    y32 = torch.empty(m, dtype=torch.float32, device="cuda")
+    out = {}
+    for vt, vb in (("f32", 4), ("bf16", 2)):
+        for f in ("rowsplit", "merge"):
+            A = spx.convert(row_d, col_d, val_d, (m, n), f, value_type=vt)
+            ms, ks = time_products(spx, torch, A, x32, y32, args.spmv_reps)
+            err = ((y32.double() - y64).abs()[nzr] / s[nzr])
+            kname, kavg, _ = product_kernels(ks)
+            B = spmv_bytes(f, m, A.nnz, n_touched, A, val_bytes=vb, vec_bytes=4)
+            ach = B / (kavg * 1e-3) / 1e9
+            out["%s_%s" % (f, vt)] = {
+                "ms_min": round(min(ms), 4), "ms_median": round(statistics.median(ms), 4),
+                "gflops_median_time": round(2 * A.nnz / (statistics.median(ms) * 1e-3) / 1e9, 1),
+                "kernels": {k: round(v["avg_ms"], 4) for k, v in ks.items()},
+                "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(ach / HBM_PEAK_GBS, 4),
+                             "frac_of_copy": round(ach / copy_gbs, 4), "bytes_per_launch": int(B),
+                             "avg_ms": round(kavg, 4)},
+                "scaled_error_vs_fp64": {"max": float(err.max()), "median": float(err.median())},
+                "convert_ms": round(A.convert_ms, 3),
+            }
+            log("spmv %-8s %-4s median %.4f ms  %.1f GFLOP/s  %.1f%% of HBM peak  err max %.2e"
+                % (f, vt, statistics.median(ms), out["%s_%s" % (f, vt)]["gflops_median_time"],
+                   100 * ach / HBM_PEAK_GBS, float(err.max())))
+            A.close()
+    return out
+
+
 def _short(name):
     name = name.split("(")[0].replace("void ", "")
     return name.split("<")[0] + ("<csbh>" if "<true>" in name or "KeyCsbh" in name else "")
@@ -202,7 +282,7 @@ def load_traffic(kernel):
     if not os.path.exists(p):
         return None
     t = json.load(open(p))
-    if t.get("kernel_src") != src_hash("k_spmv.hip", "k_convert.hip"):
+    if t.get("kernel_src") != src_hash(*KERNEL_SOURCES):
         return None
     v = t["traffic_bytes_per_launch"].get(kernel) or t["traffic_bytes_per_launch"].get("k_" + kernel)
     return None if v is None else int(v)
@@ -220,6 +300,8 @@ def main():
     ap.add_argument("--spmv-reps", type=int, default=100)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--formats", default=",".join(FMTS))
+    ap.add_argument("--precision", type=int, default=1,
+                    help="also time the FP32 / bfloat16 forms of the CRS formats")
     args = ap.parse_args()
     if args.summarize_rocprof:
         md, tj = summarize_rocprof(args.summarize_rocprof, "rmat24")
@@ -314,25 +396,8 @@ def main():
     spmv = {}
     for f in fmts:
         A = spx.convert(row_d, col_d, val_d, (m, n), f)
-        for _ in range(10):
-            A.spmv(x_d, out=ybuf[f])
-        torch.cuda.synchronize()
-        spx.profile_enable(True)
-        times = []
-        for _ in range(args.spmv_reps):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            A.spmv(x_d, out=ybuf[f])
-            e1.record()
-            times.append((e0, e1))
-        torch.cuda.synchronize()
-        ks = spx.profile_collect()
-        spx.profile_enable(False)
-        ms = [a.elapsed_time(b) for a, b in times]
-        kname = SPMV_KERNEL[f]
-        kavg = ks[kname]["avg_ms"]
-        kmin = ks[kname]["min_ms"]
+        ms, ks = time_products(spx, torch, A, x_d, ybuf[f], args.spmv_reps)
+        kname, kavg, kmin = product_kernels(ks)
         B = spmv_bytes(f, m, A.nnz, n_touched, A)
         ach = B / (kavg * 1e-3) / 1e9
         spmv[f] = {
@@ -349,6 +414,9 @@ def main():
         log("spmv %-8s median %.4f ms  %.1f GFLOP/s  kernel %.4f ms  %.1f%% of HBM peak"
             % (f, statistics.median(ms), spmv[f]["gflops_median_time"], kavg, 100 * ach / HBM_PEAK_GBS))
         A.close()
+
+    prec = precision_leg(spx, torch, args, row_d, col_d, val_d, x_d, m, n, n_touched, copy_gbs) \
+        if args.precision else None
 
     conv = {f: {"ms_min": round(min(conv_ms[f]), 3),
                 "ms_median": round(statistics.median(conv_ms[f]), 3)} for f in fmts}
@@ -377,9 +445,10 @@ def main():
                         "gflops": spmv[best]["gflops_median_time"],
                         "hbm_frac": spmv[best]["roofline"]["frac"]},
         "spmv": spmv, "convert": conv, "break_even_vs_rowsplit": be,
+        "reduced_precision": prec,
         "copy_probe_gbs": round(copy_gbs, 1),
         "step_kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in kstats.items()},
-        "kernel_src": src_hash("k_spmv.hip", "k_convert.hip"),
+        "kernel_src": src_hash(*KERNEL_SOURCES),
     }
     if args.cpu_baseline:
         del row_d, col_d, val_d

@@ -179,7 +179,8 @@ spx_status spx_matrix_destroy(spx_matrix A);
 /*
  * Number of products after which `fmt` pays for its longer conversion against the reference CRS
  * path: the N where conv_fmt + N * spmv_fmt = conv_ref + N * spmv_ref (Section 7 reports such
- * counts).  Returns +infinity when spmv_fmt >= spmv_ref.  Times in any one unit.
+ * counts).  Returns +infinity when spmv_fmt >= spmv_ref, and 0 when the format multiplies faster
+ * and converts no slower (it is ahead from the first product).  Times in any one unit.
  */
 double spx_break_even(double conv_fmt, double conv_ref, double spmv_ref, double spmv_fmt);
 

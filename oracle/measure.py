@@ -35,10 +35,13 @@ def csb_log2_beta(m, n, lds_bytes=64 * 1024, value_bytes=8):
 def break_even(conv_fmt, conv_crs, spmv_crs, spmv_fmt):
     """Number of products after which a format pays for its extra conversion time
     (Section 7 gives 26, 420, 472 and 1525 without a formula; this is the count N at which
-    conv_fmt + N*spmv_fmt = conv_crs + N*spmv_crs).  Inf when the format is not faster."""
+    conv_fmt + N*spmv_fmt = conv_crs + N*spmv_crs).  Inf when the format is not faster; 0 when it
+    is faster and converts no slower (it is ahead from the first product)."""
     gain = spmv_crs - spmv_fmt
     if gain <= 0:
         return math.inf
+    if conv_fmt <= conv_crs:
+        return 0.0
     return (conv_fmt - conv_crs) / gain
 
 

@@ -157,7 +157,8 @@ extern "C" double spx_break_even(double conv_fmt, double conv_ref, double spmv_r
                                  double spmv_fmt) {
     const double gain = spmv_ref - spmv_fmt;
     if (!(gain > 0)) return std::numeric_limits<double>::infinity();
-    return (conv_fmt - conv_ref) / gain;
+    // a format that converts no slower and multiplies faster is ahead from the first product
+    return conv_fmt <= conv_ref ? 0.0 : (conv_fmt - conv_ref) / gain;
 }
 
 // ------------------------------------------------------------------ conversion

@@ -118,6 +118,8 @@ def test_break_even_matches_oracle(L):
         assert spx.break_even(a, b, c, d) == pytest.approx(measure.break_even(a, b, c, d))
     assert math.isinf(spx.break_even(5, 1, 1, 1))
     assert math.isinf(spx.break_even(5, 1, 1, 2))
+    # faster product and no slower conversion: ahead from the first product
+    assert spx.break_even(1, 2, 3, 2) == 0.0 == measure.break_even(1, 2, 3, 2)
     # the paper's counts through the product's formula (times in ParCRS units)
     t_par = 1 / 2.9
     assert round(spx.break_even(10.9 * t_par, 7.8 * t_par, t_par, 1 / 3.3)) == 26

@@ -359,6 +359,12 @@ def test_break_even_reproduces_paper(golden):
         assert abs(nstar - float(pub)) <= 0.01 * float(pub) + 0.5, (fmt, nstar, pub)
     assert round(measure.break_even_from_ratios(10.9, 7.8, 2.9, 3.3)) == 26
     assert round(measure.break_even_from_ratios(69.6, 7.8, 2.9, 3.4)) == 420
+    # brute force on the definition: the first whole N at which the format's total time is
+    # no larger than the reference's
+    for cf, cr, sr, sf in [(10, 4, 3, 1), (4, 10, 3, 1), (5, 5, 2, 1), (7, 3, 1, 2)]:
+        first = next((N for N in range(0, 100) if cf + N * sf <= cr + N * sr), math.inf)
+        nb = measure.break_even(cf, cr, sr, sf)
+        assert (math.isinf(nb) and math.isinf(first)) or math.ceil(nb) == first
     assert measure.break_even(5.0, 1.0, 1.0, 1.0) == math.inf
     assert measure.break_even(3.0, 1.0, 2.0, 1.0) == 2.0
 
