@@ -58,6 +58,11 @@ typedef int32_t spx_dtype;
 #define SPX_F32 1  /* stored values only: products take FP32 x and y (spx_spmv_f32)      */
 #define SPX_BF16 2 /* bfloat16 stored values (round to nearest even); FP32 x and y        */
 
+/* Layout of the dense n x k (X) and m x k (Y) operands of spx_spmm. */
+typedef int32_t spx_layout;
+#define SPX_COL_MAJOR 0 /* element (i, c) at base[i + c * ld], ld >= rows (BLAS layout)  */
+#define SPX_ROW_MAJOR 1 /* element (i, c) at base[i * ld + c], ld >= k                   */
+
 /* ------------------------------------------------------------------ inputs */
 /* Triplet format (Section 2): entry i is (row[i], col[i], val[i]).  Entries may come in any order
  * and may repeat a coordinate; repeats are summed in increasing i by default.  Explicit zeros are
@@ -161,6 +166,23 @@ spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* stream);
  * returns UNSUPPORTED for a reduced-precision matrix.
  */
 spx_status spx_spmv_f32(spx_matrix A, const float* x, float* y, void* stream);
+
+/*
+ * Product with k right-hand sides, Y = A X: column c of Y is the product of Section 2 with column
+ * c of X, for c = 0 .. k-1, and the k products share one pass over the matrix.  X is n x k and Y
+ * is m x k, device memory, both in `layout` with leading dimensions ldx and ldy (see spx_layout);
+ * their element type is that of the matrix's products: double for FP64 matrices, float for FP32 and
+ * bfloat16 ones (accumulation as in spx_spmv / spx_spmv_f32).  Y is overwritten; X is only read.
+ * Any k >= 1 (columns are processed in chunks of 64).  CRS formats only.
+ * Scratch (a row-major copy of a column-major X chunk, compact hot rows, tile carries) is held by
+ * the handle, grown on demand and freed by spx_matrix_destroy; as for spx_spmv, one product call
+ * per handle may be in flight at a time.
+ * Errors: INVALID_ARG for k < 1, an unknown layout, a leading dimension below its minimum or a
+ * NULL operand; ALIAS when the spans of X and Y overlap; UNSUPPORTED for the CSB formats; RANGE
+ * when a span does not fit in 64 bits; NOMEM when scratch cannot be allocated.
+ */
+spx_status spx_spmm(spx_matrix A, int32_t k, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                    spx_layout layout, void* stream);
 
 /* Sizes and format of a handle.  info: host. */
 spx_status spx_matrix_get_info(spx_matrix A, spx_matrix_info* info);

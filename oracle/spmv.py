@@ -117,3 +117,18 @@ def rows_reference(m, n, row, col, val, x, rows):
     yp, yr, s = alg1_accurate(*crs(len(rows), n, local, np.asarray(col)[sel],
                                    np.asarray(val)[sel]), x)
     return rows, yp, yr, s
+
+
+def spmm(row_ptr, col_ind, data, X):
+    """Products with several right-hand sides: column c of the result is Algorithm 1 applied to
+    column c of X (n x k), so Y = A X column by column.  Returns (Y_plain, Y_ref, S), each m x k:
+    the plain sums, the accurate reference and the scale |A| |X| of alg1_accurate."""
+    X = np.asarray(X, np.float64)
+    m = len(row_ptr) - 1
+    k = X.shape[1]
+    Y = np.empty((m, k))
+    R = np.empty((m, k))
+    S = np.empty((m, k))
+    for c in range(k):
+        Y[:, c], R[:, c], S[:, c] = alg1_accurate(row_ptr, col_ind, data, np.ascontiguousarray(X[:, c]))
+    return Y, R, S

@@ -646,6 +646,104 @@ extern "C" spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* s
     return SPX_OK;
 }
 
+// Grows a handle-held scratch buffer to at least `need` bytes.  The previous buffer may still be
+// read by the handle's last product, so that stream is drained before the buffer is released.
+static spx_status grow_scratch(spx_matrix_s* A, void** p, size_t* have, size_t need,
+                               hipStream_t s, const char* what) {
+    if (need <= *have) return SPX_OK;
+    if (*p) {
+        HIP_TRY(hipStreamSynchronize(A->last_stream));
+        spx_dev_free(*p, A->last_stream);
+        *p = nullptr;
+        *have = 0;
+    }
+    *p = spx_dev_alloc(need, s);
+    if (!*p) return fail(SPX_ERR_NOMEM, "device allocation of %zu bytes for %s failed", need, what);
+    *have = need;
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_spmm(spx_matrix A, int32_t k, const void* x, int64_t ldx, void* y,
+                               int64_t ldy, spx_layout layout, void* stream) {
+    if (!A) return fail(SPX_ERR_INVALID_ARG, "matrix handle is NULL");
+    if (spx_is_csb(A->fmt))
+        return fail(SPX_ERR_UNSUPPORTED, "products with several right-hand sides are provided for "
+                                         "the CRS formats");
+    if (k < 1) return fail(SPX_ERR_INVALID_ARG, "k = %d, must be >= 1", k);
+    if (layout != SPX_COL_MAJOR && layout != SPX_ROW_MAJOR)
+        return fail(SPX_ERR_INVALID_ARG, "unknown layout %d", layout);
+    const int64_t m = A->m, n = A->n;
+    const int64_t es = A->value_type == SPX_F64 ? 8 : 4;
+    // spans in elements: last element + 1
+    int64_t xlen = 0, ylen = 0;
+    const int64_t big = INT64_MAX / 16;
+    if (layout == SPX_COL_MAJOR) {
+        if (ldx < (n > 1 ? n : 1) || ldy < (m > 1 ? m : 1))
+            return fail(SPX_ERR_INVALID_ARG, "column-major leading dimensions must be >= n (x) "
+                                             "and >= m (y)");
+        if (ldx > big / k || ldy > big / k) return fail(SPX_ERR_RANGE, "operand span too large");
+        xlen = n > 0 ? ldx * (k - 1) + n : 0;
+        ylen = m > 0 ? ldy * (k - 1) + m : 0;
+    } else {
+        if (ldx < k || ldy < k)
+            return fail(SPX_ERR_INVALID_ARG, "row-major leading dimensions must be >= k");
+        if ((n > 0 && ldx > big / n) || (m > 0 && ldy > big / m))
+            return fail(SPX_ERR_RANGE, "operand span too large");
+        xlen = n > 0 ? ldx * (n - 1) + k : 0;
+        ylen = m > 0 ? ldy * (m - 1) + k : 0;
+    }
+    if (m > 0 && !y) return fail(SPX_ERR_INVALID_ARG, "Y is NULL");
+    if (n > 0 && !x) return fail(SPX_ERR_INVALID_ARG, "X is NULL");
+    if (ranges_overlap(x, (size_t)(xlen * es), y, (size_t)(ylen * es)))
+        return fail(SPX_ERR_ALIAS, "X and Y overlap");
+    if (m == 0) return SPX_OK;
+    hipStream_t s = (hipStream_t)stream;
+
+    SpmmPlan P;
+    if (A->fmt == SPX_CSR_MERGE) {
+        P.coords = A->mp_coords;
+        P.tiles = A->mp_tiles;
+    } else {
+        if (!A->mm_coords) {
+            const int64_t tiles = ((int64_t)m + A->nnz + MP_TILE - 1) / MP_TILE;
+            void* p = spx_dev_alloc(((size_t)tiles + 1) * sizeof(int2), s);
+            if (!p) return fail(SPX_ERR_NOMEM, "device allocation for merge coordinates failed");
+            if (tiles > 0) {
+                const hipError_t e = launch_merge_coords(A->row_ptr, A->m, A->nnz, (int2*)p,
+                                                         (int32_t)tiles, s);
+                if (e != hipSuccess) {
+                    spx_dev_free(p, s);
+                    return fail(SPX_ERR_HIP, "merge coordinates: %s", hipGetErrorString(e));
+                }
+            }
+            A->mm_coords = (int2*)p;
+            A->mm_tiles = (int32_t)tiles;
+        }
+        P.coords = A->mm_coords;
+        P.tiles = A->mm_tiles;
+    }
+    const int64_t kc = spmm_chunk_cols(k);
+    if (!A->mm_carry_row) {  // one per tile; the tiling of a handle never changes
+        A->mm_carry_row = (int32_t*)spx_dev_alloc(((size_t)P.tiles + 1) * 4, s);
+        if (!A->mm_carry_row) return fail(SPX_ERR_NOMEM, "device allocation for carry rows failed");
+    }
+    SPX_TRY(grow_scratch(A, &A->mm_carry, &A->mm_carry_bytes, ((size_t)P.tiles + 1) * kc * 8, s,
+                         "SpMM carries"));
+    if (layout == SPX_COL_MAJOR && n > 0)
+        SPX_TRY(grow_scratch(A, &A->mm_z, &A->mm_z_bytes, (size_t)(n * kc * es), s,
+                             "row-major X copy"));
+    if (A->nhot > 0)
+        SPX_TRY(grow_scratch(A, &A->mm_h, &A->mm_h_bytes, (size_t)(A->nhot * kc * es), s,
+                             "hot X rows"));
+    P.carry_row = A->mm_carry_row;
+    P.carry_val = (double*)A->mm_carry;
+    P.z = A->mm_z;
+    P.h = A->mm_h;
+    A->last_stream = s;
+    HIP_TRY(spmm_crs(A, P, k, x, ldx, y, ldy, layout == SPX_ROW_MAJOR, s));
+    return SPX_OK;
+}
+
 extern "C" spx_status spx_matrix_get_info(spx_matrix A, spx_matrix_info* info) {
     if (!A || !info) return fail(SPX_ERR_INVALID_ARG, "NULL argument");
     info->m = A->m;
@@ -729,6 +827,8 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix A) {
     if (!A) return SPX_OK;
     (void)hipStreamSynchronize(A->last_stream);
     for (void* p : A->owned) spx_dev_free(p, A->last_stream);
+    for (void* p : {(void*)A->mm_coords, (void*)A->mm_carry_row, A->mm_carry, A->mm_z, A->mm_h})
+        spx_dev_free(p, A->last_stream);
     delete A;
     return SPX_OK;
 }

@@ -78,6 +78,16 @@ struct spx_matrix_s {
     int32_t nhot = 0;
     double* x_hot = nullptr;      // per-product scratch, nhot values
     int64_t parts = 0;
+    // SpMM scratch, grown on demand (freed by spx_matrix_destroy)
+    int2* mm_coords = nullptr;      // merge tiles of row-split matrices (tiles+1)
+    int32_t mm_tiles = 0;
+    int32_t* mm_carry_row = nullptr;
+    void* mm_carry = nullptr;       // tiles x chunk columns, FP64
+    size_t mm_carry_bytes = 0;
+    void* mm_z = nullptr;           // row-major copy of a column-major X chunk
+    size_t mm_z_bytes = 0;
+    void* mm_h = nullptr;           // hot rows of an X chunk
+    size_t mm_h_bytes = 0;
     std::vector<void*> owned;  // device allocations freed by spx_matrix_destroy
 };
 
@@ -182,4 +192,16 @@ hipError_t spmv_crs_f32(const spx_matrix_s* A, const float* x, float* y, hipStre
 // FP64 values -> FP32 (round to nearest) or bfloat16 bits (round to nearest even)
 hipError_t launch_round_values(const double* in, int64_t n, int32_t vt, void* out, hipStream_t s);
 hipError_t spmv_rowsplit(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
+// Y = A X with k right-hand sides (CRS formats): merge tiles, carries and X staging buffers
+struct SpmmPlan {
+    const int2* coords = nullptr;
+    int32_t tiles = 0;
+    int32_t* carry_row = nullptr;
+    double* carry_val = nullptr;  // tiles x spmm_chunk_cols(k)
+    void* z = nullptr;            // n x chunk, column-major X only
+    void* h = nullptr;            // nhot x chunk
+};
+int32_t spmm_chunk_cols(int32_t k);
+hipError_t spmm_crs(const spx_matrix_s* A, const SpmmPlan& P, int32_t k, const void* x,
+                    int64_t ldx, void* y, int64_t ldy, int row_major, hipStream_t s);
 hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);

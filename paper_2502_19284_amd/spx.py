@@ -20,6 +20,7 @@ STATUS = {0: "SPX_OK", -1: "SPX_ERR_INVALID_ARG", -2: "SPX_ERR_INDEX", -3: "SPX_
           -4: "SPX_ERR_ALIAS", -5: "SPX_ERR_NOMEM", -6: "SPX_ERR_HIP", -7: "SPX_ERR_UNSUPPORTED"}
 FORMATS = {"rowsplit": 0, "merge": 1, "csbh": 2, "csb": 3}
 FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
+LAYOUTS = {"col": 0, "row": 1}
 VALUE_TYPES = {"f64": 0, "f32": 1, "bf16": 2}
 VALUE_TORCH = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}
 ARRAYS = {"row_ptr": (0, torch.int32), "col_ind": (1, torch.int32), "values": (2, torch.float64),
@@ -89,6 +90,9 @@ def load(path=LIB_PATH):
     L.spx_spmv.argtypes = [P, P, P, P]
     L.spx_spmv_f32.argtypes = [P, P, P, P]
     L.spx_spmv_f32.restype = ctypes.c_int32
+    L.spx_spmm.argtypes = [P, ctypes.c_int32, P, ctypes.c_int64, P, ctypes.c_int64,
+                           ctypes.c_int32, P]
+    L.spx_spmm.restype = ctypes.c_int32
     L.spx_matrix_get_info.argtypes = [P, ctypes.POINTER(MatrixInfo)]
     L.spx_matrix_export.argtypes = [P, ctypes.c_int32, P, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_int64), P]
@@ -246,6 +250,34 @@ class Matrix:
                   _stream_ptr(stream)))
         return out
 
+    def spmm(self, X, out=None, stream=None):
+        """Y = A X for an n x k device tensor X (float64 for FP64 matrices, float32 otherwise).
+        The layout follows X's strides: column-major (stride (1, ld), e.g. the transpose of a
+        contiguous k x n tensor) or row-major (stride (ld, 1)).  Y is created in the same layout
+        unless `out` (m x k, either layout) is given.  Returns Y."""
+        m, n = self.shape
+        dt = self.vec_dtype
+        if not isinstance(X, torch.Tensor) or X.dim() != 2:
+            raise TypeError("X must be a 2-D tensor")
+        if X.dtype != dt or not X.is_cuda:
+            raise TypeError("X must be a %s CUDA tensor" % dt)
+        if X.shape[0] != n:
+            raise ValueError("X has %d rows, expected %d" % (X.shape[0], n))
+        k = X.shape[1]
+        lx, ldx = _layout_of(X)
+        if out is None:
+            out = (torch.empty((k, m), dtype=dt, device=X.device).t() if lx == 0
+                   else torch.empty((m, k), dtype=dt, device=X.device))
+        if not isinstance(out, torch.Tensor) or out.dim() != 2 or out.dtype != dt or \
+                not out.is_cuda or tuple(out.shape) != (m, k):
+            raise TypeError("out must be an m x k %s CUDA tensor" % dt)
+        ly, ldy = _layout_of(out)
+        if ly != lx:
+            raise ValueError("X and out must have the same layout")
+        _check(load().spx_spmm(self.handle, k, ctypes.c_void_p(X.data_ptr()), ldx,
+                               ctypes.c_void_p(out.data_ptr()), ldy, lx, _stream_ptr(stream)))
+        return out
+
     def export(self, name, stream=None):
         """Copy one of the handle's arrays into a new device tensor."""
         which, dtype = ARRAYS[name]
@@ -275,6 +307,19 @@ class Matrix:
 
     def __repr__(self):
         return "Matrix(%s, shape=%s, nnz=%d)" % (self.format, self.shape, self.nnz)
+
+
+def _layout_of(t):
+    """(layout code, leading dimension) of a 2-D tensor: column-major when the row stride is 1."""
+    rows, k = t.shape
+    s0, s1 = t.stride()
+    if k == 1 and (s0 == 1 or rows <= 1):
+        return LAYOUTS["col"], max(rows, 1)
+    if s0 == 1 or rows <= 1:
+        return LAYOUTS["col"], max(s1, rows, 1)
+    if s1 == 1:
+        return LAYOUTS["row"], s0
+    raise ValueError("operand must be column-major (stride (1, ld)) or row-major (stride (ld, 1))")
 
 
 def convert(row, col, val, shape, fmt="merge", sum_duplicates=True, log2_beta=0,

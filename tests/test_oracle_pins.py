@@ -500,3 +500,27 @@ def test_f32_rounding_and_bound():
         exact = float(sum(Fraction(float(u)) * Fraction(float(w)) for u, w in zip(a, x)))
         s = float(np.sum(np.abs(a * x)))
         assert abs(float(acc) - exact) <= precision.dot_error_bound(k, precision.U32) * s
+
+
+def test_spmm_equals_dense_product():
+    # Y = A X for several right-hand sides against a dense matrix product; integer values keep
+    # every sum exact, so equality is bitwise
+    rng = np.random.default_rng(11)
+    for m, n, E, k in [(7, 5, 20, 3), (1, 9, 6, 4), (12, 1, 15, 2), (6, 6, 0, 5)]:
+        row = rng.integers(0, m, E)
+        col = rng.integers(0, n, E)
+        val = rng.integers(-3, 4, E).astype(np.float64)
+        X = rng.integers(-3, 4, (n, k)).astype(np.float64)
+        dense = np.zeros((m, n))
+        np.add.at(dense, (row, col), val)
+        rp, c, v = spmv.crs(m, n, row, col, val)
+        Y, R, S = spmv.spmm(rp, c, v, X)
+        assert np.array_equal(Y, dense @ X) and np.array_equal(R, dense @ X)
+        assert np.array_equal(S, dense_abs(m, n, row, col, val) @ np.abs(X))
+
+
+def dense_abs(m, n, row, col, val):
+    """|A| of the summed entries (repeats summed first, then the absolute value)."""
+    d = np.zeros((m, n))
+    np.add.at(d, (row, col), val)
+    return np.abs(d)
