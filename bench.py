@@ -39,7 +39,8 @@ WORKLOADS = {
 }
 
 
-KERNEL_SOURCES = ("k_spmv.hip", "k_spmv_crs.hip", "k_convert.hip", "k_hot.hip", "k_partition.hip")
+KERNEL_SOURCES = ("k_spmv.hip", "k_spmv_crs.hip", "k_spmm.hip", "k_convert.hip", "k_hot.hip",
+                  "k_partition.hip")
 
 
 def log(*a):
@@ -217,6 +218,68 @@ def precision_leg(spx, torch, args, row_d, col_d, val_d, x_d, m, n, n_touched, c
     return out
 
 
+def spmm_leg(spx, torch, np, synth, args):
+    """Y = A X with k right-hand sides: Chung-Lu matrix (gamma 2.1, n = 10^7, 2*10^8 raw entries)
+    stored in FP32, FP32 column-major X and Y, merge-path CRS; per k the product time (10 warm-up,
+    --spmm-reps timed), GFLOP/s = 2 nnz k / t, and the bytes model
+      B = 8 nnz + 4 (m+1) + 4 k (n_touched + m) + merge tables
+    against all of the product's kernels (X staging, hot rows, tiles, carries)."""
+    t0 = time.perf_counter()
+    w = synth.workload("chunglu", seed=0)
+    m, n = w["m"], w["n"]
+    log("generated chunglu: m=%d n=%d raw=%d in %.1f s" % (m, n, len(w["row"]),
+                                                          time.perf_counter() - t0))
+    n_touched = int(np.count_nonzero(np.bincount(w["col"], minlength=n)))
+    dev = lambda a, t: torch.from_numpy(a).to("cuda", dtype=t)
+    A = spx.convert(dev(w["row"], torch.int32), dev(w["col"], torch.int32),
+                    dev(w["val"], torch.float64), (m, n), "merge", value_type="f32")
+    del w
+    torch.cuda.empty_cache()
+    gen = torch.Generator(device="cuda")
+    out = {"workload": WORKLOADS["chunglu"] + "; values stored FP32, X uniform(-1,1) FP32, "
+                       "column-major X and Y", "format": "merge", "nnz": A.nnz,
+           "n_touched_columns": n_touched, "convert_ms": round(A.convert_ms, 3), "k": {}}
+    for k in [int(v) for v in args.spmm_ks.split(",") if v]:
+        gen.manual_seed(k)
+        X = (torch.rand((k, n), generator=gen, device="cuda", dtype=torch.float32) * 2 - 1).t()
+        Y = torch.empty((k, m), dtype=torch.float32, device="cuda").t()
+        for _ in range(10):
+            A.spmm(X, out=Y)
+        torch.cuda.synchronize()
+        spx.profile_enable(True)
+        ev = []
+        for _ in range(args.spmm_reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            A.spmm(X, out=Y)
+            e1.record()
+            ev.append((e0, e1))
+        torch.cuda.synchronize()
+        ks = spx.profile_collect()
+        spx.profile_enable(False)
+        ms = [a.elapsed_time(b) for a, b in ev]
+        kname, kavg, _ = product_kernels(ks)
+        B = 8 * A.nnz + 4 * (m + 1) + 4 * k * (n_touched + m) + 12 * (A.parts + 1) + 8 * k * A.parts
+        ach = B / (kavg * 1e-3) / 1e9
+        med = statistics.median(ms)
+        out["k"][str(k)] = {
+            "ms_min": round(min(ms), 4), "ms_median": round(med, 4),
+            "gflops_median_time": round(2 * A.nnz * k / (med * 1e-3) / 1e9, 1),
+            "kernels": {kk: round(v["avg_ms"], 4) for kk, v in ks.items()},
+            "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": int(B),
+                         "avg_ms": round(kavg, 4)}}
+        log("spmm k=%2d median %.4f ms  %.1f GFLOP/s  %.1f%% of HBM peak  %s"
+            % (k, med, out["k"][str(k)]["gflops_median_time"], 100 * ach / HBM_PEAK_GBS,
+               out["k"][str(k)]["kernels"]))
+        del X, Y
+    A.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def _short(name):
     name = name.split("(")[0].replace("void ", "")
     return name.split("<")[0] + ("<csbh>" if "<true>" in name or "KeyCsbh" in name else "")
@@ -302,6 +365,10 @@ def main():
     ap.add_argument("--formats", default=",".join(FMTS))
     ap.add_argument("--precision", type=int, default=1,
                     help="also time the FP32 / bfloat16 forms of the CRS formats")
+    ap.add_argument("--spmm", type=int, default=1,
+                    help="also time Y = A X with k right-hand sides on the Chung-Lu matrix")
+    ap.add_argument("--spmm-ks", default="1,4,8,16,32")
+    ap.add_argument("--spmm-reps", type=int, default=20)
     args = ap.parse_args()
     if args.summarize_rocprof:
         md, tj = summarize_rocprof(args.summarize_rocprof, "rmat24")
@@ -418,6 +485,11 @@ def main():
     prec = precision_leg(spx, torch, args, row_d, col_d, val_d, x_d, m, n, n_touched, copy_gbs) \
         if args.precision else None
 
+    mm = None
+    if args.spmm:
+        del ybuf
+        mm = spmm_leg(spx, torch, np, synth, args)
+
     conv = {f: {"ms_min": round(min(conv_ms[f]), 3),
                 "ms_median": round(statistics.median(conv_ms[f]), 3)} for f in fmts}
     be = {}
@@ -446,6 +518,7 @@ def main():
                         "hbm_frac": spmv[best]["roofline"]["frac"]},
         "spmv": spmv, "convert": conv, "break_even_vs_rowsplit": be,
         "reduced_precision": prec,
+        "spmm": mm,
         "copy_probe_gbs": round(copy_gbs, 1),
         "step_kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in kstats.items()},
         "kernel_src": src_hash(*KERNEL_SOURCES),

@@ -174,7 +174,7 @@ spx_status spx_spmv_f32(spx_matrix A, const float* x, float* y, void* stream);
  * their element type is that of the matrix's products: double for FP64 matrices, float for FP32 and
  * bfloat16 ones (accumulation as in spx_spmv / spx_spmv_f32).  Y is overwritten; X is only read.
  * Any k >= 1 (columns are processed in chunks of 64).  CRS formats only.
- * Scratch (a row-major copy of a column-major X chunk, compact hot rows, tile carries) is held by
+ * Scratch (row-major copies of column-major X and Y chunks, compact hot rows, tile carries) is held by
  * the handle, grown on demand and freed by spx_matrix_destroy; as for spx_spmv, one product call
  * per handle may be in flight at a time.
  * Errors: INVALID_ARG for k < 1, an unknown layout, a leading dimension below its minimum or a

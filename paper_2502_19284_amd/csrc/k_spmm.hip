@@ -7,7 +7,10 @@
 // next to each other, so the kc lanes that serve one entry read one contiguous run (kc = 32 FP32
 // values = one 128-byte line) instead of kc scattered values.  A row-major X is read in place; a
 // column-major X (column c at X + c*ldx, the BLAS layout) is first copied into that row-major form
-// by an LDS-tiled transpose.  Hot columns (k_hot.hip) get their own compact rows.
+// by an LDS-tiled transpose.  Hot columns (k_hot.hip) get their own compact rows.  Y leaves the
+// same way: kc lanes store one row's kc results as one contiguous run, and a column-major Y is
+// written from a row-major scratch by the reverse transpose (scattered 4-byte stores into kc
+// columns cost several times the whole product).
 //
 // Work is split as in merge-path SpMV (Section 3.3): tile t covers MP_TILE items of the merge of
 // row ends and entries.  Within a tile, groups of KP lanes (KP = kc rounded up to a power of two)
@@ -39,6 +42,24 @@ __global__ __launch_bounds__(256) void k_spmm_stage(const X* __restrict__ x, int
     for (int e = threadIdx.x; e < rows * kc; e += 256) {
         const int r = e / kc, c = e % kc;
         z[(j0 + r) * kc + c] = s[r * (MM_KMAX + 1) + c];
+    }
+}
+
+// Y[i + c*ldy] = W[i*kc + c] for i < m, c < kc: row-major result chunk -> column-major Y
+template <typename X>
+__global__ __launch_bounds__(256) void k_spmm_unstage(const X* __restrict__ w, int32_t m,
+                                                      int32_t kc, X* __restrict__ y, int64_t ldy) {
+    __shared__ X s[MM_STAGE_ROWS * (MM_KMAX + 1)];
+    const int64_t i0 = (int64_t)blockIdx.x * MM_STAGE_ROWS;
+    const int rows = (int)min((int64_t)MM_STAGE_ROWS, (int64_t)m - i0);
+    for (int e = threadIdx.x; e < rows * kc; e += 256) {
+        const int r = e / kc, c = e % kc;
+        s[r * (MM_KMAX + 1) + c] = w[(i0 + r) * kc + c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < MM_STAGE_ROWS * kc; e += 256) {
+        const int c = e / MM_STAGE_ROWS, r = e % MM_STAGE_ROWS;
+        if (r < rows) ntstore(y + i0 + r + (int64_t)c * ldy, s[r * (MM_KMAX + 1) + c]);
     }
 }
 
@@ -191,7 +212,9 @@ __global__ __launch_bounds__(MP_NT) void k_spmm_merge(
     }
 }
 
-// Adds each tile's open values into Y, tiles in order, in FP64 (one thread per row and column).
+// Adds each tile's open values into Y in FP64 (one thread per run of tiles that left the same row
+// open, and column).  A row can stay open over many tiles (up to nnz / MP_TILE), so the run is
+// read 8 tiles per step into 8 partial sums, combined in a fixed order: deterministic.
 template <typename X>
 __global__ void k_spmm_fixup(const int32_t* __restrict__ carry_row,
                              const double* __restrict__ carry_val, int32_t tiles, int32_t kc,
@@ -202,9 +225,23 @@ __global__ void k_spmm_fixup(const int32_t* __restrict__ carry_row,
     const int r = carry_row[t];
     if (r >= m) return;
     if (t > 0 && carry_row[t - 1] == r) return;
-    double acc = carry_val[e];
-    for (int u = t + 1; u < tiles && carry_row[u] == r; ++u)
-        acc = acc + carry_val[(int64_t)u * kc + c];
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool go = true;
+    for (int u = t; go; u += 8) {
+        int rr[8];
+        double vv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            rr[q] = u + q < tiles ? carry_row[u + q] : -1;
+            vv[q] = u + q < tiles ? carry_val[(int64_t)(u + q) * kc + c] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            go = go && rr[q] == r;
+            if (go) a[q] += vv[q];
+        }
+    }
+    const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     X* p = mm_yptr(y, ldy, row_major, (int64_t)r, c);
     *p = (X)(acc + (double)*p);
 }
@@ -259,16 +296,23 @@ static hipError_t spmm_t(const spx_matrix_s* A, const SpmmPlan& P, const V* val,
             SPX_LAUNCH("spmm_hot", k_spmm_hot<X>,
                        dim3((unsigned)spx_div_up((int64_t)A->nhot * kc, 256)), dim3(256), 0, s,
                        A->hot_cols, A->nhot, xr, ldr, kc, (X*)P.h);
-        X* yc = row_major ? y + c0 : y + (int64_t)c0 * ldy;
+        // results are produced row-major (kc lanes write one contiguous run per row); a
+        // column-major Y receives them through the scratch W and an LDS-tiled transpose
+        X* yc = row_major ? y + c0 : (X*)P.w;
+        const int64_t ldyc = row_major ? ldy : kc;
         if (P.tiles > 0) {
             hipError_t e = launch_spmm_merge<V, X, ACC>(kp, dim3(P.tiles), s, A, val, xr, ldr,
-                                                        (const X*)P.h, kc, yc, ldy, row_major,
+                                                        (const X*)P.h, kc, yc, ldyc, 1,
                                                         P.coords, P.carry_row, P.carry_val);
             if (e != hipSuccess) return e;
             SPX_LAUNCH("spmm_fixup", k_spmm_fixup<X>,
                        dim3((unsigned)spx_div_up((int64_t)P.tiles * kc, 256)), dim3(256), 0, s,
-                       P.carry_row, P.carry_val, P.tiles, kc, yc, ldy, row_major, A->m);
+                       P.carry_row, P.carry_val, P.tiles, kc, yc, ldyc, 1, A->m);
         }
+        if (!row_major)
+            SPX_LAUNCH("spmm_unstage", k_spmm_unstage<X>,
+                       dim3((unsigned)spx_div_up(A->m, MM_STAGE_ROWS)), dim3(256), 0, s,
+                       (const X*)P.w, A->m, kc, y + (int64_t)c0 * ldy, ldy);
     }
     return hipGetLastError();
 }

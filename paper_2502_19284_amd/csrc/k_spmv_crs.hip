@@ -158,8 +158,10 @@ __global__ __launch_bounds__(MP_NT) void k_spmv_merge(
     for (int q = tid; q < nrows; q += MP_NT) ntstore(y + r0 + q, (X)s_prod[q]);
 }
 
-// Adds each tile's open value into y, tiles in order, in FP64.  The first tile of a run of tiles
-// that left the same row open sums the whole run, so every row is updated by one thread.
+// Adds each tile's open value into y in FP64.  The first tile of a run of tiles that left the
+// same row open sums the whole run, so every row is updated by one thread; the run (up to
+// nnz / MP_TILE tiles for one long row) is read 8 tiles per step into 8 partial sums that are
+// combined in a fixed order, so results stay deterministic.
 template <typename X>
 __global__ void k_spmv_merge_fixup(const int32_t* __restrict__ carry_row,
                                    const double* __restrict__ carry_val, int32_t tiles,
@@ -169,8 +171,23 @@ __global__ void k_spmv_merge_fixup(const int32_t* __restrict__ carry_row,
     const int r = carry_row[t];
     if (r >= m) return;
     if (t > 0 && carry_row[t - 1] == r) return;
-    double acc = carry_val[t];
-    for (int u = t + 1; u < tiles && carry_row[u] == r; ++u) acc = acc + carry_val[u];
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool go = true;
+    for (int u = t; go; u += 8) {
+        int rr[8];
+        double vv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            rr[q] = u + q < tiles ? carry_row[u + q] : -1;
+            vv[q] = u + q < tiles ? carry_val[u + q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            go = go && rr[q] == r;
+            if (go) a[q] += vv[q];
+        }
+    }
+    const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     y[r] = (X)(acc + (double)y[r]);
 }
 

@@ -732,6 +732,9 @@ extern "C" spx_status spx_spmm(spx_matrix A, int32_t k, const void* x, int64_t l
     if (layout == SPX_COL_MAJOR && n > 0)
         SPX_TRY(grow_scratch(A, &A->mm_z, &A->mm_z_bytes, (size_t)(n * kc * es), s,
                              "row-major X copy"));
+    if (layout == SPX_COL_MAJOR)
+        SPX_TRY(grow_scratch(A, &A->mm_w, &A->mm_w_bytes, (size_t)(m * kc * es), s,
+                             "row-major Y scratch"));
     if (A->nhot > 0)
         SPX_TRY(grow_scratch(A, &A->mm_h, &A->mm_h_bytes, (size_t)(A->nhot * kc * es), s,
                              "hot X rows"));
@@ -739,6 +742,7 @@ extern "C" spx_status spx_spmm(spx_matrix A, int32_t k, const void* x, int64_t l
     P.carry_val = (double*)A->mm_carry;
     P.z = A->mm_z;
     P.h = A->mm_h;
+    P.w = A->mm_w;
     A->last_stream = s;
     HIP_TRY(spmm_crs(A, P, k, x, ldx, y, ldy, layout == SPX_ROW_MAJOR, s));
     return SPX_OK;
@@ -827,7 +831,8 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix A) {
     if (!A) return SPX_OK;
     (void)hipStreamSynchronize(A->last_stream);
     for (void* p : A->owned) spx_dev_free(p, A->last_stream);
-    for (void* p : {(void*)A->mm_coords, (void*)A->mm_carry_row, A->mm_carry, A->mm_z, A->mm_h})
+    for (void* p : {(void*)A->mm_coords, (void*)A->mm_carry_row, A->mm_carry, A->mm_z, A->mm_h,
+                    A->mm_w})
         spx_dev_free(p, A->last_stream);
     delete A;
     return SPX_OK;

@@ -88,6 +88,8 @@ struct spx_matrix_s {
     size_t mm_z_bytes = 0;
     void* mm_h = nullptr;           // hot rows of an X chunk
     size_t mm_h_bytes = 0;
+    void* mm_w = nullptr;           // row-major results of a chunk for a column-major Y
+    size_t mm_w_bytes = 0;
     std::vector<void*> owned;  // device allocations freed by spx_matrix_destroy
 };
 
@@ -199,6 +201,7 @@ struct SpmmPlan {
     int32_t* carry_row = nullptr;
     double* carry_val = nullptr;  // tiles x spmm_chunk_cols(k)
     void* z = nullptr;            // n x chunk, column-major X only
+    void* w = nullptr;            // m x chunk, row-major results for a column-major Y
     void* h = nullptr;            // nhot x chunk
 };
 int32_t spmm_chunk_cols(int32_t k);
