@@ -2,9 +2,12 @@
 
 A from-scratch HIP implementation of the formats and load-balancing strategies studied by
 Bergmans, Meerbergen and Vandebril (arXiv 2502.19284): row-split CRS, merge-path CRS and
-compressed sparse blocks in Hilbert order (CSBH), with conversion from triplets by device radix
-sort.  The C ABI is include/spx.h; this package is its thin Python binding.
+compressed sparse blocks in Hilbert (CSBH) or Z-Morton (CSB) order, with conversion from triplets
+by device radix sort; products with several right-hand sides; and a serving loop over resident
+matrices.  The C ABI is include/spx.h and include/spx_serve.h; this package is its thin Python
+binding.
 """
-from .spx import (ARRAYS, FORMATS, LIB_PATH, Matrix, SpxError, break_even, convert,  # noqa: F401
+from .spx import (ARRAYS, FORMATS, LIB_PATH, Matrix, Server, SpxError, break_even,  # noqa: F401
+                  convert,
                   header_functions, load, profile_collect, profile_enable, use_torch_allocator,
                   version)

@@ -53,6 +53,9 @@ extern "C" const char* spx_status_string(spx_status s) {
     }
 }
 
+// the same, for the other host sources of the library (spx_serve.cpp)
+spx_status spx_fail(spx_status s, const char* msg) { return fail(s, "%s", msg); }
+
 extern "C" const char* spx_last_error_message(void) { return g_last_error.c_str(); }
 
 extern "C" const char* spx_version(void) { return "0.1.0"; }

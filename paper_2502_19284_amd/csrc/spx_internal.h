@@ -101,6 +101,16 @@ struct Readback {
     uint32_t totals[4];
 };
 
+// ------------------------------------------------------------------ errors
+// Sets the calling thread's last error message and returns s.
+spx_status spx_fail(spx_status s, const char* msg);
+
+// ------------------------------------------------------------------ serving kernels
+hipError_t launch_serve_gather(const float* const* xs, int k, int n, float* X, hipStream_t s);
+hipError_t launch_serve_scatter(const float* Y, int k, int m, float* const* ys,
+                                const float* alpha, const float* beta, hipStream_t s);
+hipError_t launch_serve_axpb(float* y, int m, float alpha, float beta, hipStream_t s);
+
 // ------------------------------------------------------------------ allocation
 void* spx_dev_alloc(size_t bytes, hipStream_t s);
 void spx_dev_free(void* p, hipStream_t s);

@@ -65,6 +65,26 @@ class KernelStat(ctypes.Structure):
                 ("max_ms", ctypes.c_double)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_int64), ("slots", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("coalesce", ctypes.c_int32),
+                ("poll_us", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("matrix", ctypes.c_int32), ("kind", ctypes.c_int32), ("damping", ctypes.c_float),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("max_batch_seen", ctypes.c_int64), ("bytes_resident", ctypes.c_int64),
+                ("memory_budget", ctypes.c_int64), ("matrices", ctypes.c_int32),
+                ("in_flight", ctypes.c_int32)]
+
+
+REQUEST_KINDS = {"spmv": 0, "pagerank": 1}
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -72,6 +92,7 @@ _lib = None
 _alloc_refs = None
 _atexit_set = False
 _live = weakref.WeakSet()  # open Matrix handles
+_live_servers = weakref.WeakSet()
 
 
 def load(path=LIB_PATH):
@@ -100,6 +121,24 @@ def load(path=LIB_PATH):
     L.spx_set_allocator.argtypes = [ALLOC_FN, FREE_FN, P]
     for f in (L.spx_convert_opts_default, L.spx_convert, L.spx_spmv, L.spx_matrix_get_info,
               L.spx_matrix_export, L.spx_matrix_destroy, L.spx_set_allocator):
+        f.restype = ctypes.c_int32
+    L.spx_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
+    L.spx_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(P)]
+    L.spx_server_destroy.argtypes = [P]
+    L.spx_server_add_matrix.argtypes = [P, ctypes.POINTER(CooDesc), ctypes.c_int32,
+                                        ctypes.POINTER(ConvertOpts), P,
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int64)]
+    L.spx_server_remove_matrix.argtypes = [P, ctypes.c_int32]
+    L.spx_server_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.spx_server_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+    L.spx_server_replay.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
+    L.spx_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats)]
+    for f in (L.spx_server_opts_default, L.spx_server_create, L.spx_server_destroy,
+              L.spx_server_add_matrix, L.spx_server_remove_matrix, L.spx_server_submit,
+              L.spx_server_wait, L.spx_server_replay, L.spx_server_get_stats):
         f.restype = ctypes.c_int32
     L.spx_profile_enable.argtypes = [ctypes.c_int32]
     L.spx_profile_enable.restype = ctypes.c_int32
@@ -152,6 +191,10 @@ def use_torch_allocator(enable=True):
     refs = (ALLOC_FN(_alloc), FREE_FN(_free))
     _check(L.spx_set_allocator(refs[0], refs[1], None))
     _alloc_refs = refs
+    _register_shutdown()
+
+
+def _register_shutdown():
     global _atexit_set
     if not _atexit_set:
         atexit.register(_shutdown)
@@ -161,6 +204,11 @@ def use_torch_allocator(enable=True):
 def _shutdown():
     """At exit, while torch is still alive: free live handles, then drop the allocator hook."""
     global _alloc_refs
+    for srv in list(_live_servers):  # servers first: they hold matrices and a thread
+        try:
+            srv.close()
+        except Exception:
+            pass
     for mat in list(_live):
         try:
             mat.close()
@@ -309,6 +357,119 @@ class Matrix:
         return "Matrix(%s, shape=%s, nnz=%d)" % (self.format, self.shape, self.nnz)
 
 
+class Server:
+    """Serving loop over resident matrices (include/spx_serve.h).  Matrices are admitted by their
+    footprint bound against memory_budget; requests against one matrix that wait together are
+    coalesced into one product with several right-hand sides (coalesce=True), or served one per
+    launch in arrival order (coalesce=False, the plain path)."""
+
+    def __init__(self, memory_budget=None, slots=None, max_batch=None, coalesce=True,
+                 poll_us=None):
+        L = load()
+        o = ServerOpts()
+        _check(L.spx_server_opts_default(ctypes.byref(o)))
+        if memory_budget is not None:
+            o.memory_budget = int(memory_budget)
+        if slots is not None:
+            o.slots = int(slots)
+        if max_batch is not None:
+            o.max_batch = int(max_batch)
+        if poll_us is not None:
+            o.poll_us = int(poll_us)
+        o.coalesce = 1 if coalesce else 0
+        h = ctypes.c_void_p()
+        _check(L.spx_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.max_batch = o.max_batch if coalesce else 1
+        self._shapes = {}
+        self._held = {}  # ticket -> (x, y) kept alive until waited for
+        _live_servers.add(self)
+        _register_shutdown()
+
+    def add_matrix(self, row, col, val, shape, fmt="merge", value_type="f32", hot_columns=-1,
+                   stream=None):
+        """Convert device triplets and keep them resident; returns (matrix id, footprint bound)."""
+        m, n = shape
+        _dev_tensor(row, torch.int32, "row")
+        _dev_tensor(col, torch.int32, "col")
+        _dev_tensor(val, torch.float64, "val")
+        if not (row.numel() == col.numel() == val.numel()):
+            raise ValueError("row, col and val must have the same length")
+        L = load()
+        coo = CooDesc(m, n, row.numel(), row.data_ptr(), col.data_ptr(), val.data_ptr(), 0)
+        opts = ConvertOpts()
+        _check(L.spx_convert_opts_default(ctypes.byref(opts)))
+        opts.hot_columns = int(hot_columns)
+        opts.value_type = VALUE_TYPES[value_type]
+        mid = ctypes.c_int32()
+        nb = ctypes.c_int64()
+        _check(L.spx_server_add_matrix(self._h, ctypes.byref(coo), FORMATS[fmt], ctypes.byref(opts),
+                                       _stream_ptr(stream), ctypes.byref(mid), ctypes.byref(nb)))
+        self._shapes[mid.value] = (m, n)
+        return mid.value, nb.value
+
+    def remove_matrix(self, mid):
+        _check(load().spx_server_remove_matrix(self._h, int(mid)))
+        self._shapes.pop(mid, None)
+
+    def request(self, mid, x, y, kind="spmv", damping=0.85):
+        """A Request struct for submit / replay (x, y: float32 device vectors)."""
+        _dev_tensor(x, torch.float32, "x")
+        _dev_tensor(y, torch.float32, "y")
+        return Request(int(mid), REQUEST_KINDS[kind], float(damping), x.data_ptr(), y.data_ptr())
+
+    def submit(self, mid, x, y, kind="spmv", damping=0.85):
+        """Queue y = A x (kind 'spmv') or y = d A x + (1 - d) / n ('pagerank'); returns a ticket."""
+        r = self.request(mid, x, y, kind, damping)
+        t = ctypes.c_uint64()
+        _check(load().spx_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._held[t.value] = (x, y)
+        return t.value
+
+    def wait(self, ticket):
+        """Block until the request is done; returns its latency in microseconds."""
+        lat = ctypes.c_double()
+        try:
+            _check(load().spx_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(lat)))
+        finally:
+            self._held.pop(ticket, None)
+        return lat.value
+
+    def replay(self, requests, arrival_us):
+        """Submit requests[i] (Request structs from request()) at arrival_us[i] microseconds after
+        the call starts, wait for all; returns (latencies in us as a list, wall time in us).  The
+        caller keeps the request vectors alive for the duration of the call."""
+        import numpy as np
+        cnt = len(requests)
+        arr = (Request * cnt)(*requests)
+        at = np.ascontiguousarray(arrival_us, dtype=np.float64)
+        if len(at) != cnt:
+            raise ValueError("one arrival time per request")
+        lat = np.empty(cnt, dtype=np.float64)
+        wall = ctypes.c_double()
+        _check(load().spx_server_replay(
+            self._h, arr, at.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cnt,
+            lat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(wall)))
+        return lat, wall.value
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().spx_server_get_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h is not None:
+            load().spx_server_destroy(self._h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def _layout_of(t):
     """(layout code, leading dimension) of a 2-D tensor: column-major when the row stride is 1."""
     rows, k = t.shape
@@ -357,11 +518,13 @@ def version():
 
 
 def header_functions():
-    """Names of the entry points declared in include/spx.h."""
+    """Names of the entry points declared in include/*.h."""
+    import glob
     import re
-    hdr = os.path.join(_PKG, "..", "include", "spx.h")
-    with open(hdr) as f:
-        text = f.read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\*?\s+\**(spx_[a-z_0-9]+)\(", text,
-                                 re.M)))
+    names = set()
+    for hdr in sorted(glob.glob(os.path.join(_PKG, "..", "include", "*.h"))):
+        with open(hdr) as f:
+            text = f.read()
+        names.update(re.findall(r"^\s*(?:const\s+)?[a-z_]+\*?\s+\**(spx_[a-z_0-9]+)\(", text, re.M))
+    return sorted(names)
 

@@ -123,3 +123,27 @@ def test_break_even_matches_oracle(L):
     # the paper's counts through the product's formula (times in ParCRS units)
     t_par = 1 / 2.9
     assert round(spx.break_even(10.9 * t_par, 7.8 * t_par, t_par, 1 / 3.3)) == 26
+
+
+def test_server_argument_errors(L):
+    o = B.ServerOpts()
+    assert L.spx_server_opts_default(ctypes.byref(o)) == 0
+    assert (o.memory_budget, o.slots, o.max_batch, o.coalesce, o.poll_us) == (64 << 30, 4, 32, 1, 0)
+    h = ctypes.c_void_p()
+    for field, bad in (("slots", 0), ("slots", 17), ("max_batch", 0), ("max_batch", 65),
+                       ("memory_budget", 0), ("poll_us", -1), ("poll_us", 1001)):
+        b = B.ServerOpts()
+        L.spx_server_opts_default(ctypes.byref(b))
+        setattr(b, field, bad)
+        assert L.spx_server_create(ctypes.byref(b), ctypes.byref(h)) == -1, field
+        assert h.value is None
+    assert L.spx_server_create(ctypes.byref(o), None) == -1
+    t = ctypes.c_uint64()
+    r = B.Request(1, 0, 0.85, None, None)
+    assert L.spx_server_submit(None, ctypes.byref(r), ctypes.byref(t)) == -1
+    assert L.spx_server_wait(None, 1, None) == -1
+    assert L.spx_server_remove_matrix(None, 1) == -1
+    assert L.spx_server_get_stats(None, None) == -1
+    assert L.spx_server_replay(None, None, None, 0, None, None) == -1
+    assert L.spx_server_add_matrix(None, None, 1, None, None, None, None) == -1
+    assert L.spx_server_destroy(None) == 0
