@@ -280,6 +280,103 @@ def spmm_leg(spx, torch, np, synth, args):
     return out
 
 
+SERVE_MATRICES = (
+    "64 resident matrices, FP32 values uniform(-1,1), merge-path CRS: 56 R-MAT "
+    "(a,b,c,d) = (0.57,0.19,0.19,0.05) with scale 16 + i mod 7 and edge factor 8/16/32 by "
+    "(i div 7) mod 3, seed 1000 + i; 8 Erdos-Renyi with n = 2^(16 + j mod 5), average degree 8, "
+    "seed 2000 + j")
+
+
+def serve_matrices(synth, np):
+    """The serving workload's matrices as (m, n, row, col, val) generators."""
+    for i in range(56):
+        scale, ef = 16 + i % 7, (8, 16, 32)[(i // 7) % 3]
+        row, col = synth.rmat(scale, ef, seed=1000 + i)
+        yield (1 << scale, 1 << scale, row, col, synth.values(len(row), seed=1000 + i))
+    for j in range(8):
+        n = 1 << (16 + j % 5)
+        row, col = synth.uniform(n, n, 8 * n, seed=2000 + j)
+        yield (n, n, row, col, synth.values(len(row), seed=2000 + j))
+
+
+def serving_leg(spx, torch, np, synth, args):
+    """Open-loop serving: Poisson arrivals at each rate for --serve-seconds, matrix chosen by a
+    Zipf(1) popularity over a seeded permutation of the 64 matrices, half SpMV and half PageRank
+    steps (damping 0.85).  The same schedule is replayed against the coalescing server (4 slots,
+    batches of up to 32) and the plain path (one request per launch, arrival order).  Latency is
+    submit -> completion seen by the scheduler; throughput is completed requests / wall time."""
+    t0 = time.perf_counter()
+    srv = {"coalesced": spx.Server(slots=4, max_batch=32), "plain": spx.Server(coalesce=False)}
+    ids = {k: [] for k in srv}
+    shapes = []
+    for m, n, row, col, val in serve_matrices(synth, np):
+        d = [torch.from_numpy(a).to("cuda") for a in (row, col, val)]
+        for k, S in srv.items():
+            mid, _ = S.add_matrix(d[0], d[1], d[2], (m, n), "merge", value_type="f32")
+            ids[k].append(mid)
+        shapes.append((m, n))
+        del d
+    log("serving: 64 matrices admitted in %.1f s" % (time.perf_counter() - t0))
+    st0 = srv["coalesced"].stats()
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(64)
+    pop = 1.0 / np.arange(1, 65)
+    pop = pop / pop.sum()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    xs = [torch.rand(n, generator=gen, device="cuda") * 2 - 1 for (m, n) in shapes]
+    ring = 64
+    ys = [[torch.empty(m, device="cuda") for _ in range(ring)] for (m, n) in shapes]
+    out = {"matrices": SERVE_MATRICES, "bytes_resident": st0["bytes_resident"],
+           "popularity": "Zipf(1) over a seeded permutation", "mix": "50% SpMV, 50% PageRank step",
+           "rates": {}}
+
+    def schedule(rate, seconds, seed):
+        r = np.random.default_rng(seed)
+        cnt = max(1, int(rate * seconds))
+        arr = np.cumsum(r.exponential(1e6 / rate, cnt))
+        which = perm[r.choice(64, cnt, p=pop)]
+        kind = r.integers(0, 2, cnt)
+        return arr, which, kind
+
+    def reqs_for(S, key, which, kind):
+        cnt = [0] * 64
+        rq = []
+        for w, kd in zip(which, kind):
+            y = ys[w][cnt[w] % ring]
+            cnt[w] += 1
+            rq.append(S.request(ids[key][w], xs[w], y, "pagerank" if kd else "spmv", 0.85))
+        return rq
+
+    # warm-up: every batch width and both paths
+    arr, which, kind = schedule(20000.0, 0.2, 99)
+    for key, S in srv.items():
+        S.replay(reqs_for(S, key, which, kind), arr)
+    for rate in [float(v) for v in args.serve_rates.split(",") if v]:
+        arr, which, kind = schedule(rate, args.serve_seconds, int(rate))
+        row = {}
+        for key, S in srv.items():
+            b0 = S.stats()["batches"]
+            lat, wall = S.replay(reqs_for(S, key, which, kind), arr)
+            nb = S.stats()["batches"] - b0
+            row[key] = {"requests": len(lat), "p50_us": round(float(np.percentile(lat, 50)), 1),
+                        "p99_us": round(float(np.percentile(lat, 99)), 1),
+                        "mean_us": round(float(lat.mean()), 1),
+                        "throughput_req_s": round(len(lat) / (wall * 1e-6), 1),
+                        "batches": nb, "mean_batch": round(len(lat) / max(nb, 1), 2)}
+        log("serve %6.0f req/s: coalesced p50 %.0f us p99 %.0f us (%.0f req/s, batch %.1f) | "
+            "plain p50 %.0f us p99 %.0f us (%.0f req/s)"
+            % (rate, row["coalesced"]["p50_us"], row["coalesced"]["p99_us"],
+               row["coalesced"]["throughput_req_s"], row["coalesced"]["mean_batch"],
+               row["plain"]["p50_us"], row["plain"]["p99_us"], row["plain"]["throughput_req_s"]))
+        out["rates"][str(int(rate))] = row
+    for S in srv.values():
+        S.close()
+    del xs, ys
+    torch.cuda.empty_cache()
+    return out
+
+
 def _short(name):
     name = name.split("(")[0].replace("void ", "")
     return name.split("<")[0] + ("<csbh>" if "<true>" in name or "KeyCsbh" in name else "")
@@ -369,6 +466,10 @@ def main():
                     help="also time Y = A X with k right-hand sides on the Chung-Lu matrix")
     ap.add_argument("--spmm-ks", default="1,4,8,16,32")
     ap.add_argument("--spmm-reps", type=int, default=20)
+    ap.add_argument("--serve", type=int, default=1,
+                    help="also run the serving loop over 64 resident matrices")
+    ap.add_argument("--serve-rates", default="1000,5000,10000,20000,50000")
+    ap.add_argument("--serve-seconds", type=float, default=0.5)
     args = ap.parse_args()
     if args.summarize_rocprof:
         md, tj = summarize_rocprof(args.summarize_rocprof, "rmat24")
@@ -490,6 +591,10 @@ def main():
         del ybuf
         mm = spmm_leg(spx, torch, np, synth, args)
 
+    served = None
+    if args.serve:
+        served = serving_leg(spx, torch, np, synth, args)
+
     conv = {f: {"ms_min": round(min(conv_ms[f]), 3),
                 "ms_median": round(statistics.median(conv_ms[f]), 3)} for f in fmts}
     be = {}
@@ -519,6 +624,7 @@ def main():
         "spmv": spmv, "convert": conv, "break_even_vs_rowsplit": be,
         "reduced_precision": prec,
         "spmm": mm,
+        "serving": served,
         "copy_probe_gbs": round(copy_gbs, 1),
         "step_kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in kstats.items()},
         "kernel_src": src_hash(*KERNEL_SOURCES),
