@@ -7,7 +7,8 @@ by device radix sort; products with several right-hand sides; and a serving loop
 matrices.  The C ABI is include/spx.h and include/spx_serve.h; this package is its thin Python
 binding.
 """
-from .spx import (ARRAYS, FORMATS, LIB_PATH, Matrix, Server, SpxError, break_even,  # noqa: F401
+from .spx import (ARRAYS, FORMATS, LIB_PATH, PLANS, Batch, Matrix, Server,  # noqa: F401
+                  SpxError, break_even,
                   convert,
                   header_functions, load, profile_collect, profile_enable, use_torch_allocator,
                   version)

@@ -1,0 +1,269 @@
+// k_batch.hip -- one persistent launch for the products of many matrices (gfx950).
+//
+// The launch has a fixed number of workgroups; workgroup b processes work items b, b + G, ...
+// of the batch's item list, where an item is one tile of one matrix.  Merge tiles follow the
+// merge-path product of Section 3.3 with the matrix's own tile length (256 * ipt items): the
+// tile stages its row ends and products in LDS, every thread walks ipt items, a segmented scan
+// passes open values between threads, and the value the tile leaves open goes to carry[t].  The
+// workgroup that completes a matrix's last merge tile (a device-scope counter per matrix,
+// released and acquired with device fences) adds that matrix's carries into y in tile order and
+// resets the counter for the next launch, so no second launch, memset or host step is needed.
+// Row tiles hand whole rows to lane groups sized to the tile's average row length.
+//
+// Values are FP32 or bfloat16, x and y FP32; sums inside a tile are FP32, carries FP64.
+#include "dev_common.h"
+#include "dev_values.h"
+#include "spx_internal.h"
+
+#define BT_NT 256
+#define BT_MAX_IPT 16
+#define BT_MAX_ITEMS (BT_NT * BT_MAX_IPT)
+
+__device__ __forceinline__ float bt_val(const BatchMat& M, int64_t k) {
+    return M.bf16 ? __uint_as_float((uint32_t)ntload((const uint16_t*)M.val + k) << 16)
+                  : ntload((const float*)M.val + k);
+}
+
+__device__ __forceinline__ float bt_x(const float* __restrict__ x,
+                                      const int32_t* __restrict__ hot, int32_t c) {
+    return c >= 0 ? x[c] : x[hot[~c]];
+}
+
+template <typename T>
+__device__ __forceinline__ void bt_seg(int& f, T& v, int f_later, T v_later) {
+    v = f_later ? v_later : v + v_later;
+    f = f | f_later;
+}
+
+template <int IPT>
+__device__ void bt_merge(const BatchMat& M, int t, const float* __restrict__ x,
+                         float* __restrict__ y, int32_t* s_end, float* s_prod, int* s_wf,
+                         float* s_wv) {
+    const int tid = threadIdx.x;
+    const int2 c0 = M.coords[t];
+    const int2 c1 = M.coords[t + 1];
+    const int r0 = c0.x, k0 = c0.y;
+    const int nrows = c1.x - r0, nnzt = c1.y - k0;
+    for (int i = tid; i < nrows; i += BT_NT) s_end[i] = ntload(M.row_ptr + r0 + 1 + i);
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        const int i = q * BT_NT + tid;
+        if (i < nnzt) s_prod[i] = bt_val(M, (int64_t)k0 + i) * bt_x(x, M.hot_cols, ntload(M.col + k0 + i));
+    }
+    __syncthreads();
+
+    const int items = nrows + nnzt;
+    const int d = min(tid * IPT, items);
+    const int dend = min(d + IPT, items);
+    int lo = max(0, d - nnzt), hi = min(d, nrows);
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_end[mid] <= k0 + d - mid - 1) lo = mid + 1;
+        else hi = mid;
+    }
+    const int i0 = lo;
+    int i = lo, j = d - lo;
+    float run = 0;
+    float outv[IPT];
+    uint32_t endmask = 0;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        outv[q] = 0;
+        if (d + q < dend) {
+            if (i < nrows && (j >= nnzt || s_end[i] <= k0 + j)) {
+                outv[q] = run;
+                run = 0;
+                endmask |= 1u << q;
+                ++i;
+            } else {
+                run += s_prod[j];
+                ++j;
+            }
+        }
+    }
+    int f = endmask != 0;
+    float v = run;
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < SPX_WAVE; o <<= 1) {
+        const int fu = __shfl_up(f, o, SPX_WAVE);
+        const float vu = __shfl_up(v, o, SPX_WAVE);
+        if (lane >= o) {
+            int fa = fu;
+            float va = vu;
+            bt_seg(fa, va, f, v);
+            f = fa;
+            v = va;
+        }
+    }
+    const int w = tid / SPX_WAVE;
+    if (lane == SPX_WAVE - 1) {
+        s_wf[w] = f;
+        s_wv[w] = v;
+    }
+    int fex = __shfl_up(f, 1, SPX_WAVE);
+    float vex = __shfl_up(v, 1, SPX_WAVE);
+    if (lane == 0) {
+        fex = 0;
+        vex = 0;
+    }
+    __syncthreads();
+    int fp = 0;
+    float vp = 0;
+    for (int ww = 0; ww < w; ++ww) bt_seg(fp, vp, s_wf[ww], s_wv[ww]);
+    bt_seg(fp, vp, fex, vex);
+    const float carry_in = vp;
+    if (tid == BT_NT - 1) {
+        int ft = fp;
+        float vt = vp;
+        bt_seg(ft, vt, (int)(endmask != 0), run);
+        M.carry_row[t] = c1.x;  // m when nothing is left open
+        M.carry_val[t] = (double)vt;
+    }
+    __syncthreads();
+    int r = i0;
+    bool first = true;
+#pragma unroll
+    for (int q = 0; q < IPT; ++q) {
+        if (endmask & (1u << q)) {
+            float o = outv[q];
+            if (first) {
+                o = carry_in + o;
+                first = false;
+            }
+            s_prod[r] = o;
+            ++r;
+        }
+    }
+    __syncthreads();
+    for (int q = tid; q < nrows; q += BT_NT) y[r0 + q] = s_prod[q];
+}
+
+__device__ void bt_rows(const BatchMat& M, int t, const float* __restrict__ x,
+                        float* __restrict__ y) {
+    const int r0 = t * M.rows_per_tile;
+    const int r1 = min(M.m, r0 + M.rows_per_tile);
+    const int rows = r1 - r0;
+    const int base = M.row_ptr[r0];
+    const int nz = M.row_ptr[r1] - base;
+    const int avg = rows > 0 ? (nz + rows - 1) / rows : 0;
+    int g = 1;
+    while (g < SPX_WAVE && g < avg) g <<= 1;
+    const int tid = threadIdx.x;
+    const int grp = tid / g, gl = tid % g, ngrp = BT_NT / g;
+    for (int r = grp; r < rows; r += ngrp) {
+        const int a = M.row_ptr[r0 + r], b = M.row_ptr[r0 + r + 1];
+        float acc = 0;
+        for (int k = a + gl; k < b; k += g) acc += bt_val(M, k) * bt_x(x, M.hot_cols, ntload(M.col + k));
+        for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, SPX_WAVE);
+        if (gl == 0) y[r0 + r] = acc;
+    }
+}
+
+// The matrix's carries into y, run by run (see k_spmv_merge_fixup), by one workgroup.
+__device__ void bt_fixup(const BatchMat& M, float* __restrict__ y) {
+    for (int t = threadIdx.x; t < M.tiles; t += BT_NT) {
+        const int r = M.carry_row[t];
+        if (r >= M.m) continue;
+        if (t > 0 && M.carry_row[t - 1] == r) continue;
+        double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        bool go = true;
+        for (int u = t; go; u += 8) {
+            int rr[8];
+            double vv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                rr[q] = u + q < M.tiles ? M.carry_row[u + q] : -1;
+                vv[q] = u + q < M.tiles ? M.carry_val[u + q] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                go = go && rr[q] == r;
+                if (go) a[q] += vv[q];
+            }
+        }
+        const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        y[r] = (float)(acc + (double)y[r]);
+    }
+}
+
+__global__ __launch_bounds__(BT_NT) void k_batch_spmv(const BatchMat* __restrict__ mats,
+                                                      const int2* __restrict__ items,
+                                                      int32_t nitems,
+                                                      const float* const* __restrict__ xs,
+                                                      float* const* __restrict__ ys,
+                                                      uint32_t* __restrict__ done) {
+    __shared__ int32_t s_end[BT_MAX_ITEMS];
+    __shared__ float s_prod[BT_MAX_ITEMS];
+    __shared__ int s_wf[BT_NT / SPX_WAVE];
+    __shared__ float s_wv[BT_NT / SPX_WAVE];
+    __shared__ int s_last;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 w = items[it];
+        const BatchMat M = mats[w.x];
+        const float* x = xs[w.x];
+        float* y = ys[w.x];
+        if (M.plan == SPX_PLAN_MERGE_4) bt_merge<4>(M, w.y, x, y, s_end, s_prod, s_wf, s_wv);
+        else if (M.plan == SPX_PLAN_MERGE_8) bt_merge<8>(M, w.y, x, y, s_end, s_prod, s_wf, s_wv);
+        else if (M.plan == SPX_PLAN_MERGE_16) bt_merge<16>(M, w.y, x, y, s_end, s_prod, s_wf, s_wv);
+        else bt_rows(M, w.y, x, y);
+        if (M.plan <= SPX_PLAN_MERGE_16) {
+            // the workgroup that finishes the matrix's last tile adds its carries
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __threadfence();
+                s_last = atomicAdd(&done[w.x], 1u) == (uint32_t)(M.tiles - 1);
+            }
+            __syncthreads();
+            if (s_last) {
+                __threadfence();
+                bt_fixup(M, y);
+                if (threadIdx.x == 0) done[w.x] = 0;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batch_spmv(const BatchMat* mats, const int2* items, int32_t nitems,
+                             int32_t grid, const float* const* xs, float* const* ys,
+                             uint32_t* done, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    SPX_LAUNCH("batch_spmv", k_batch_spmv, dim3(grid), dim3(BT_NT), 0, s, mats, items, nitems, xs,
+               ys, done);
+    return hipGetLastError();
+}
+
+// longest row: *out = max over rows of row_ptr[i+1] - row_ptr[i] (out starts at 0)
+__global__ void k_batch_maxlen(const int32_t* __restrict__ row_ptr, int32_t m,
+                               uint32_t* __restrict__ out) {
+    uint32_t best = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        best = max(best, (uint32_t)(row_ptr[i + 1] - row_ptr[i]));
+    best = wave_reduce<uint32_t, OpMax<uint32_t>>(best);
+    if (__lane_id() == 0) atomicMax(out, best);
+}
+
+hipError_t launch_batch_maxlen(const int32_t* row_ptr, int32_t m, uint32_t* out, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    int64_t g = spx_div_up(m, 256);
+    if (g > 1024) g = 1024;
+    SPX_LAUNCH("batch_maxlen", k_batch_maxlen, dim3((unsigned)g), dim3(256), 0, s, row_ptr, m,
+               out);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t g = spx_div_up(n, 256);
+    if (g > 4096) g = 4096;
+    SPX_LAUNCH("fill_u32", k_fill_u32, dim3((unsigned)g), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}

@@ -15,11 +15,11 @@
 // first.  Binary search for the number of row ends i: A[p] = row_ptr[p+1] precedes B[d-p-1] =
 // d-p-1 exactly when row_ptr[p+1] <= d-p-1.
 __global__ void k_merge_coords(const int32_t* __restrict__ row_ptr, int32_t m, int64_t nnz,
-                               int2* __restrict__ coords, int32_t tiles) {
+                               int2* __restrict__ coords, int32_t tiles, int32_t tile_items) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t > tiles) return;
     const int64_t total = (int64_t)m + nnz;
-    int64_t d = t * MP_TILE;
+    int64_t d = t * tile_items;
     if (d > total) d = total;
     int64_t lo = d - nnz > 0 ? d - nnz : 0;
     int64_t hi = d < m ? d : m;
@@ -32,9 +32,10 @@ __global__ void k_merge_coords(const int32_t* __restrict__ row_ptr, int32_t m, i
 }
 
 hipError_t launch_merge_coords(const int32_t* row_ptr, int32_t m, int64_t nnz, int2* coords,
-                               int32_t tiles, hipStream_t s) {
+                               int32_t tiles, hipStream_t s, int32_t tile_items) {
     const unsigned g = spx_div_up((int64_t)tiles + 1, 256);
-    SPX_LAUNCH("merge_coords", k_merge_coords, dim3(g), dim3(256), 0, s, row_ptr, m, nnz, coords, tiles);
+    SPX_LAUNCH("merge_coords", k_merge_coords, dim3(g), dim3(256), 0, s, row_ptr, m, nnz, coords,
+               tiles, tile_items);
     return hipGetLastError();
 }
 

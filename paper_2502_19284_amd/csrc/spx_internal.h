@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "../../include/spx.h"
+#include "../../include/spx_batch.h"
 #include "spx_prof.h"
 
 // ------------------------------------------------------------------ tuning constants
@@ -111,6 +112,28 @@ hipError_t launch_serve_scatter(const float* Y, int k, int m, float* const* ys,
                                 const float* alpha, const float* beta, hipStream_t s);
 hipError_t launch_serve_axpb(float* y, int m, float alpha, float beta, hipStream_t s);
 
+// ------------------------------------------------------------------ batched products
+// One matrix of a batch as the persistent product kernel sees it.
+struct BatchMat {
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const void* val;            // FP32 values, or bfloat16 bits when bf16
+    const int32_t* hot_cols;    // entries with col < 0 read x[hot_cols[~col]]
+    const int2* coords;         // merge plans: tiles + 1 tile starts
+    int32_t* carry_row;         // merge plans: one per tile
+    double* carry_val;
+    int32_t m, n;
+    int32_t plan;               // SPX_PLAN_* (never AUTO here)
+    int32_t tiles;              // work items of this matrix
+    int32_t rows_per_tile;      // row plans
+    int32_t bf16;
+};
+hipError_t launch_batch_spmv(const BatchMat* mats, const int2* items, int32_t nitems,
+                             int32_t grid, const float* const* xs, float* const* ys,
+                             uint32_t* done, hipStream_t s);
+hipError_t launch_batch_maxlen(const int32_t* row_ptr, int32_t m, uint32_t* out, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+
 // ------------------------------------------------------------------ allocation
 void* spx_dev_alloc(size_t bytes, hipStream_t s);
 void spx_dev_free(void* p, hipStream_t s);
@@ -178,8 +201,9 @@ hipError_t launch_hot_unmap(const int32_t* col, int64_t nnz, const int32_t* hot_
 
 
 // ------------------------------------------------------------------ partitions
+// tile t starts on diagonal t * tile_items
 hipError_t launch_merge_coords(const int32_t* row_ptr, int32_t m, int64_t nnz, int2* coords,
-                               int32_t tiles, hipStream_t s);
+                               int32_t tiles, hipStream_t s, int32_t tile_items = MP_TILE);
 // row-split: phase 1 counts (blocks+sentinel, long rows); phase 2 fills
 hipError_t rowsplit_count(const int32_t* row_ptr, int32_t m, uint32_t* tile_sums_a,
                           uint32_t* tile_sums_b, uint32_t* totals, hipStream_t s);

@@ -92,7 +92,7 @@ _lib = None
 _alloc_refs = None
 _atexit_set = False
 _live = weakref.WeakSet()  # open Matrix handles
-_live_servers = weakref.WeakSet()
+_live_containers = weakref.WeakSet()
 
 
 def load(path=LIB_PATH):
@@ -139,6 +139,17 @@ def load(path=LIB_PATH):
     for f in (L.spx_server_opts_default, L.spx_server_create, L.spx_server_destroy,
               L.spx_server_add_matrix, L.spx_server_remove_matrix, L.spx_server_submit,
               L.spx_server_wait, L.spx_server_replay, L.spx_server_get_stats):
+        f.restype = ctypes.c_int32
+    L.spx_batch_create.argtypes = [ctypes.POINTER(P), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32), P, ctypes.POINTER(P),
+                                   ctypes.POINTER(ctypes.c_int32)]
+    L.spx_batch_bind.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), P]
+    L.spx_batch_spmv.argtypes = [P, P]
+    L.spx_batch_get_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int32)]
+    L.spx_batch_destroy.argtypes = [P]
+    for f in (L.spx_batch_create, L.spx_batch_bind, L.spx_batch_spmv, L.spx_batch_get_info,
+              L.spx_batch_destroy):
         f.restype = ctypes.c_int32
     L.spx_profile_enable.argtypes = [ctypes.c_int32]
     L.spx_profile_enable.restype = ctypes.c_int32
@@ -204,7 +215,7 @@ def _register_shutdown():
 def _shutdown():
     """At exit, while torch is still alive: free live handles, then drop the allocator hook."""
     global _alloc_refs
-    for srv in list(_live_servers):  # servers first: they hold matrices and a thread
+    for srv in list(_live_containers):  # servers and batches first: they use matrices
         try:
             srv.close()
         except Exception:
@@ -357,6 +368,68 @@ class Matrix:
         return "Matrix(%s, shape=%s, nnz=%d)" % (self.format, self.shape, self.nnz)
 
 
+PLANS = {"auto": 0, "merge4": 1, "merge8": 2, "merge16": 3, "rows512": 4, "rows2048": 5}
+PLAN_NAMES = {v: k for k, v in PLANS.items()}
+
+
+class Batch:
+    """Products of many CRS matrices (FP32 / bfloat16 values) in one persistent launch
+    (include/spx_batch.h).  plans: None (autotune every matrix) or one PLANS name per matrix.
+    The matrices must stay open while the batch exists."""
+
+    def __init__(self, matrices, plans=None, stream=None):
+        L = load()
+        cnt = len(matrices)
+        hs = (ctypes.c_void_p * cnt)(*[A.handle for A in matrices])
+        pl = None if plans is None else (ctypes.c_int32 * cnt)(*[PLANS[p] for p in plans])
+        chosen = (ctypes.c_int32 * cnt)()
+        h = ctypes.c_void_p()
+        _check(L.spx_batch_create(hs, cnt, pl, _stream_ptr(stream), ctypes.byref(h), chosen))
+        self._h = h
+        self.matrices = list(matrices)
+        self.plans = [PLAN_NAMES[c] for c in chosen]
+        self._bound = None
+        _live_containers.add(self)
+        _register_shutdown()
+
+    def bind(self, xs, ys, stream=None):
+        """Use float32 device vectors xs[i] (n_i) and ys[i] (m_i) for the following products."""
+        if len(xs) != len(self.matrices) or len(ys) != len(self.matrices):
+            raise ValueError("one x and one y per matrix")
+        for A, x, y in zip(self.matrices, xs, ys):
+            _dev_tensor(x, torch.float32, "x")
+            _dev_tensor(y, torch.float32, "y")
+            if x.numel() != A.shape[1] or y.numel() != A.shape[0]:
+                raise ValueError("vector length does not match its matrix")
+        cnt = len(xs)
+        px = (ctypes.c_void_p * cnt)(*[x.data_ptr() for x in xs])
+        py = (ctypes.c_void_p * cnt)(*[y.data_ptr() for y in ys])
+        _check(load().spx_batch_bind(self._h, px, py, _stream_ptr(stream)))
+        self._bound = (list(xs), list(ys))
+
+    def spmv(self, stream=None):
+        """y_i = A_i x_i for every matrix: one launch on the current (or given) stream."""
+        _check(load().spx_batch_spmv(self._h, _stream_ptr(stream)))
+
+    def info(self):
+        it = ctypes.c_int64()
+        wg = ctypes.c_int32()
+        _check(load().spx_batch_get_info(self._h, ctypes.byref(it), ctypes.byref(wg)))
+        return {"items": it.value, "workgroups": wg.value}
+
+    def close(self):
+        if self._h is not None:
+            load().spx_batch_destroy(self._h)
+            self._h = None
+            self._bound = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Server:
     """Serving loop over resident matrices (include/spx_serve.h).  Matrices are admitted by their
     footprint bound against memory_budget; requests against one matrix that wait together are
@@ -383,7 +456,7 @@ class Server:
         self.max_batch = o.max_batch if coalesce else 1
         self._shapes = {}
         self._held = {}  # ticket -> (x, y) kept alive until waited for
-        _live_servers.add(self)
+        _live_containers.add(self)
         _register_shutdown()
 
     def add_matrix(self, row, col, val, shape, fmt="merge", value_type="f32", hot_columns=-1,
