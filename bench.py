@@ -280,6 +280,114 @@ def spmm_leg(spx, torch, np, synth, args):
     return out
 
 
+def batch_matrices(synth, np, count):
+    """count uneven matrices: rows log-uniform in [1e3, 1e6], average degree log-uniform in
+    [4, 64], even i Chung-Lu (gamma 2.1), odd i Erdos-Renyi; FP32 values uniform(-1,1)."""
+    rng = np.random.default_rng(512)
+    for i in range(count):
+        n = int(np.exp(rng.uniform(np.log(1e3), np.log(1e6))))
+        deg = float(np.exp(rng.uniform(np.log(4), np.log(64))))
+        E = int(n * deg)
+        if i % 2:
+            row, col = synth.uniform(n, n, E, seed=3000 + i)
+        else:
+            row, col = synth.chunglu(n, E, 2.1, seed=3000 + i)
+        yield n, n, row, col, synth.values(E, seed=3000 + i)
+
+
+def batch_leg(spx, torch, np, synth, args):
+    """Products of --batch-count uneven matrices (merge-path CRS, FP32): one launch per matrix
+    (eager, and captured in a graph) against the batch's single persistent launch (eager, and in
+    a graph), with autotuned plans and with one fixed plan for all."""
+    t0 = time.perf_counter()
+    hs, xs, ys = [], [], []
+    nnz = 0
+    bytes_model = 0
+    for m, n, row, col, val in batch_matrices(synth, np, args.batch_count):
+        n_touched = int(np.count_nonzero(np.bincount(col, minlength=n)))
+        d = [torch.from_numpy(a).to("cuda") for a in (row, col, val)]
+        A = spx.convert(d[0], d[1], d[2], (m, n), "merge", value_type="f32")
+        del d
+        hs.append(A)
+        xs.append(torch.rand(n, device="cuda") * 2 - 1)
+        ys.append(torch.empty(m, device="cuda"))
+        nnz += A.nnz
+        bytes_model += 8 * A.nnz + 4 * (m + 1) + 4 * (n_touched + m)
+    log("batch: %d matrices, %d stored entries, converted in %.1f s"
+        % (len(hs), nnz, time.perf_counter() - t0))
+
+    def timed(fn, reps=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def per_matrix():
+        for A, x, y in zip(hs, xs, ys):
+            A.spmv(x, out=y)
+
+    def graphed(fn):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        return g
+
+    out = {"matrices": "%d uneven: rows log-uniform in [1e3, 1e6], average degree log-uniform "
+                       "in [4, 64], alternately Chung-Lu (gamma 2.1) and Erdos-Renyi; FP32 values"
+                       % len(hs), "nnz": nnz, "bytes_model": bytes_model}
+    res = {}
+    res["per_matrix_eager_ms"] = timed(per_matrix)
+    g1 = graphed(per_matrix)
+    res["per_matrix_graph_ms"] = timed(g1.replay)
+    del g1
+    t1 = time.perf_counter()
+    B = spx.Batch(hs)
+    out["autotune_s"] = round(time.perf_counter() - t1, 2)
+    out["plans"] = {p: B.plans.count(p) for p in sorted(set(B.plans))}
+    B.bind(xs, ys)
+    out["launch"] = B.info()
+    res["batch_eager_ms"] = timed(B.spmv)
+    g2 = graphed(B.spmv)
+    res["batch_graph_ms"] = timed(g2.replay)
+    del g2
+    B.close()
+    Bf = spx.Batch(hs, ["merge8"] * len(hs))
+    Bf.bind(xs, ys)
+    res["batch_fixed_merge8_ms"] = timed(Bf.spmv)
+    Bf.close()
+    for k, v in res.items():
+        out[k] = round(v, 4)
+    best = min(res["batch_eager_ms"], res["batch_graph_ms"])
+    out["gflops_batch"] = round(2 * nnz / (best * 1e-3) / 1e9, 1)
+    out["gflops_per_matrix_eager"] = round(2 * nnz / (res["per_matrix_eager_ms"] * 1e-3) / 1e9, 1)
+    ach = bytes_model / (best * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": "batch_spmv", "achieved": round(ach, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                       "bytes_per_launch": int(bytes_model)}
+    log("batch: per-matrix eager %.3f ms, per-matrix graph %.3f ms, one launch %.3f ms "
+        "(graph %.3f ms), fixed merge8 %.3f ms; plans %s"
+        % (res["per_matrix_eager_ms"], res["per_matrix_graph_ms"], res["batch_eager_ms"],
+           res["batch_graph_ms"], res["batch_fixed_merge8_ms"], out["plans"]))
+    for A in hs:
+        A.close()
+    del xs, ys
+    torch.cuda.empty_cache()
+    return out
+
+
 SERVE_MATRICES = (
     "64 resident matrices, FP32 values uniform(-1,1), merge-path CRS: 56 R-MAT "
     "(a,b,c,d) = (0.57,0.19,0.19,0.05) with scale 16 + i mod 7 and edge factor 8/16/32 by "
@@ -466,6 +574,9 @@ def main():
                     help="also time Y = A X with k right-hand sides on the Chung-Lu matrix")
     ap.add_argument("--spmm-ks", default="1,4,8,16,32")
     ap.add_argument("--spmm-reps", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=1,
+                    help="also time 512 uneven matrices in one persistent launch")
+    ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve", type=int, default=1,
                     help="also run the serving loop over 64 resident matrices")
     ap.add_argument("--serve-rates", default="1000,5000,10000,20000,50000")
@@ -591,6 +702,10 @@ def main():
         del ybuf
         mm = spmm_leg(spx, torch, np, synth, args)
 
+    bt = None
+    if args.batch:
+        bt = batch_leg(spx, torch, np, synth, args)
+
     served = None
     if args.serve:
         served = serving_leg(spx, torch, np, synth, args)
@@ -624,6 +739,7 @@ def main():
         "spmv": spmv, "convert": conv, "break_even_vs_rowsplit": be,
         "reduced_precision": prec,
         "spmm": mm,
+        "batch": bt,
         "serving": served,
         "copy_probe_gbs": round(copy_gbs, 1),
         "step_kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in kstats.items()},

@@ -2,22 +2,28 @@
  * spx_batch.h -- one launch for the products of many matrices (part of libspx).
  *
  * A batch holds a set of converted CRS matrices (handles from spx_convert, FP32 or bfloat16
- * values) and computes y_i = A_i x_i for all of them with a single persistent kernel launch.  Each
- * matrix is cut into work items by its own plan:
+ * values) and computes y_i = A_i x_i for all of them with one product launch over the work items
+ * of every matrix, followed by one small launch that adds the merge tiles' carries.  Each matrix
+ * is cut into work items by its own plan:
  *   - merge tiles: 256 * ipt consecutive items of the merge of row ends and entries (Section
- *     3.3), ipt in {4, 8, 16}; the values a tile leaves open are added by the last work item of
- *     the matrix to finish, in tile order;
+ *     3.3), ipt in {4, 8, 16}; the values a tile leaves open are added in tile order by the
+ *     fix-up launch;
  *   - row tiles: `rows` consecutive whole rows, each row reduced by a group of lanes sized to the
  *     tile's average row length (for matrices whose rows are all at most 1024 entries long).
- * The workgroups of the launch take the work items of all matrices in a fixed stride, so small
- * and large matrices share the device without one launch per matrix.
+ * The workgroups of the product launch take the work items of all matrices in a fixed stride
+ * (persistent workgroups when the grid is smaller than the item count), so small and large
+ * matrices share the device without one launch per matrix.
  *
  * The plan of each matrix is chosen by an autotuner at creation (unless fixed by the caller): it
  * times every candidate (merge tiles with ipt 4, 8, 16; row tiles of 512 or 2048 entries when the
- * rows allow) on the matrix alone and keeps the fastest.
+ * rows allow) on the matrix alone, its tiles repeated to at least 8192 work items so that the
+ * device is as full as inside a batch, and keeps the cheapest per pass.  It then times the whole
+ * batch with one workgroup per item and with persistent grids of 4096 and 1024 workgroups, for
+ * those plans and with 16-item merge tiles turned into 8-item ones (the largest tile sets the
+ * launch's LDS size, hence the occupancy of every workgroup), and keeps the fastest.
  *
- * A product is one kernel launch with no allocation, no host synchronisation and no memset, so it
- * can be captured in a HIP graph and replayed.  Its completion counters reset themselves.
+ * A product is two kernel launches with no allocation, no host synchronisation and no memset, so
+ * it can be captured in a HIP graph and replayed.
  * Results are deterministic; they equal each matrix's product within the FP32 dot-product error
  * bound (integer-valued inputs: exactly).
  */

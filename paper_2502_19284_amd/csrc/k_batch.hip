@@ -1,14 +1,13 @@
-// k_batch.hip -- one persistent launch for the products of many matrices (gfx950).
+// k_batch.hip -- one launch for the products of many matrices (gfx950).
 //
-// The launch has a fixed number of workgroups; workgroup b processes work items b, b + G, ...
-// of the batch's item list, where an item is one tile of one matrix.  Merge tiles follow the
-// merge-path product of Section 3.3 with the matrix's own tile length (256 * ipt items): the
-// tile stages its row ends and products in LDS, every thread walks ipt items, a segmented scan
-// passes open values between threads, and the value the tile leaves open goes to carry[t].  The
-// workgroup that completes a matrix's last merge tile (a device-scope counter per matrix,
-// released and acquired with device fences) adds that matrix's carries into y in tile order and
-// resets the counter for the next launch, so no second launch, memset or host step is needed.
-// Row tiles hand whole rows to lane groups sized to the tile's average row length.
+// The product launch has G workgroups; workgroup b processes work items b, b + G, ... of the
+// batch's item list, where an item is one tile of one matrix.  Merge tiles follow the merge-path
+// product of Section 3.3 with the matrix's own tile length (256 * ipt items): the tile stages its
+// row ends and products in LDS, every thread walks ipt items, a segmented scan passes open
+// values between threads, and the value the tile leaves open goes to carry[t].  Row tiles hand
+// whole rows to lane groups sized to the tile's average row length.  A second, small launch adds
+// every merge matrix's carries into y in tile order (a device-wide handshake inside the product
+// launch would need a release/acquire pair per tile, which costs more than the launch).
 //
 // Values are FP32 or bfloat16, x and y FP32; sums inside a tile are FP32, carries FP64.
 #include "dev_common.h"
@@ -16,8 +15,6 @@
 #include "spx_internal.h"
 
 #define BT_NT 256
-#define BT_MAX_IPT 16
-#define BT_MAX_ITEMS (BT_NT * BT_MAX_IPT)
 
 __device__ __forceinline__ float bt_val(const BatchMat& M, int64_t k) {
     return M.bf16 ? __uint_as_float((uint32_t)ntload((const uint16_t*)M.val + k) << 16)
@@ -160,44 +157,16 @@ __device__ void bt_rows(const BatchMat& M, int t, const float* __restrict__ x,
     }
 }
 
-// The matrix's carries into y, run by run (see k_spmv_merge_fixup), by one workgroup.
-__device__ void bt_fixup(const BatchMat& M, float* __restrict__ y) {
-    for (int t = threadIdx.x; t < M.tiles; t += BT_NT) {
-        const int r = M.carry_row[t];
-        if (r >= M.m) continue;
-        if (t > 0 && M.carry_row[t - 1] == r) continue;
-        double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        bool go = true;
-        for (int u = t; go; u += 8) {
-            int rr[8];
-            double vv[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                rr[q] = u + q < M.tiles ? M.carry_row[u + q] : -1;
-                vv[q] = u + q < M.tiles ? M.carry_val[u + q] : 0.0;
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                go = go && rr[q] == r;
-                if (go) a[q] += vv[q];
-            }
-        }
-        const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-        y[r] = (float)(acc + (double)y[r]);
-    }
-}
-
 __global__ __launch_bounds__(BT_NT) void k_batch_spmv(const BatchMat* __restrict__ mats,
                                                       const int2* __restrict__ items,
-                                                      int32_t nitems,
+                                                      int32_t nitems, int32_t max_tile,
                                                       const float* const* __restrict__ xs,
-                                                      float* const* __restrict__ ys,
-                                                      uint32_t* __restrict__ done) {
-    __shared__ int32_t s_end[BT_MAX_ITEMS];
-    __shared__ float s_prod[BT_MAX_ITEMS];
+                                                      float* const* __restrict__ ys) {
+    extern __shared__ int32_t s_dyn[];  // max_tile row ends, then max_tile products
     __shared__ int s_wf[BT_NT / SPX_WAVE];
     __shared__ float s_wv[BT_NT / SPX_WAVE];
-    __shared__ int s_last;
+    int32_t* s_end = s_dyn;
+    float* s_prod = (float*)(s_dyn + max_tile);
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int2 w = items[it];
         const BatchMat M = mats[w.x];
@@ -207,30 +176,53 @@ __global__ __launch_bounds__(BT_NT) void k_batch_spmv(const BatchMat* __restrict
         else if (M.plan == SPX_PLAN_MERGE_8) bt_merge<8>(M, w.y, x, y, s_end, s_prod, s_wf, s_wv);
         else if (M.plan == SPX_PLAN_MERGE_16) bt_merge<16>(M, w.y, x, y, s_end, s_prod, s_wf, s_wv);
         else bt_rows(M, w.y, x, y);
-        if (M.plan <= SPX_PLAN_MERGE_16) {
-            // the workgroup that finishes the matrix's last tile adds its carries
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                __threadfence();
-                s_last = atomicAdd(&done[w.x], 1u) == (uint32_t)(M.tiles - 1);
-            }
-            __syncthreads();
-            if (s_last) {
-                __threadfence();
-                bt_fixup(M, y);
-                if (threadIdx.x == 0) done[w.x] = 0;
-            }
-        }
         __syncthreads();
     }
 }
 
+// One thread per work item: the first merge tile of every run of tiles that left the same row
+// open adds the run's carries (read 8 tiles per step, fixed combination order) into y.
+__global__ void k_batch_fixup(const BatchMat* __restrict__ mats, const int2* __restrict__ items,
+                              int32_t nitems, float* const* __restrict__ ys) {
+    const int it = blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= nitems) return;
+    const int2 w = items[it];
+    const BatchMat& M = mats[w.x];
+    if (M.plan > SPX_PLAN_MERGE_16) return;
+    const int t = w.y;
+    const int r = M.carry_row[t];
+    if (r >= M.m) return;
+    if (t > 0 && M.carry_row[t - 1] == r) return;
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool go = true;
+    for (int u = t; go; u += 8) {
+        int rr[8];
+        double vv[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            rr[q] = u + q < M.tiles ? M.carry_row[u + q] : -1;
+            vv[q] = u + q < M.tiles ? M.carry_val[u + q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            go = go && rr[q] == r;
+            if (go) a[q] += vv[q];
+        }
+    }
+    const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    float* y = ys[w.x];
+    y[r] = (float)(acc + (double)y[r]);
+}
+
 hipError_t launch_batch_spmv(const BatchMat* mats, const int2* items, int32_t nitems,
-                             int32_t grid, const float* const* xs, float* const* ys,
-                             uint32_t* done, hipStream_t s) {
+                             int32_t grid, int32_t max_tile, const float* const* xs,
+                             float* const* ys, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    SPX_LAUNCH("batch_spmv", k_batch_spmv, dim3(grid), dim3(BT_NT), 0, s, mats, items, nitems, xs,
-               ys, done);
+    const size_t lds = (size_t)max_tile * 8;
+    SPX_LAUNCH("batch_spmv", k_batch_spmv, dim3(grid), dim3(BT_NT), lds, s, mats, items, nitems,
+               max_tile, xs, ys);
+    SPX_LAUNCH("batch_fixup", k_batch_fixup, dim3(spx_div_up(nitems, 256)), dim3(256), 0, s, mats,
+               items, nitems, ys);
     return hipGetLastError();
 }
 

@@ -18,6 +18,9 @@ constexpr int kRowPlanMaxRow = 1024;  // row tiles only when no row is longer (F
 constexpr int kCandidates[] = {SPX_PLAN_MERGE_4, SPX_PLAN_MERGE_8, SPX_PLAN_MERGE_16,
                                SPX_PLAN_ROWS_512, SPX_PLAN_ROWS_2048};
 constexpr int kTuneWarm = 2, kTuneReps = 8;
+// A candidate is timed on at least this many work items (the matrix's tiles repeated), so that
+// it is measured at full occupancy, the condition it will run under inside a batch.
+constexpr int64_t kTuneItems = 8192;
 
 bool is_merge(int plan) { return plan >= SPX_PLAN_MERGE_4 && plan <= SPX_PLAN_MERGE_16; }
 int plan_ipt(int plan) {
@@ -50,7 +53,7 @@ struct spx_batch_s {
     int2* items = nullptr;
     int64_t nitems = 0;
     int32_t grid = 0;
-    uint32_t* done = nullptr;
+    int32_t max_tile = 256;
     const float** xs = nullptr;  // device tables
     float** ys = nullptr;
     bool bound = false;
@@ -80,6 +83,113 @@ static hipError_t apply_plan(BatchMat& M, int plan, int64_t nnz, hipStream_t s) 
     M.rows_per_tile = (int32_t)std::max<int64_t>(1, std::min<int64_t>(target / avg, 4096));
     M.tiles = (int32_t)((M.m + M.rows_per_tile - 1) / M.rows_per_tile);
     return hipSuccess;
+}
+
+// Upper bound of the work items of a batch under any plans.
+static int64_t items_bound(const spx_matrix* mats, int32_t count) {
+    int64_t b = 0;
+    for (int32_t i = 0; i < count; ++i)
+        b += std::max<int64_t>(mats[i]->m, ((int64_t)mats[i]->m + mats[i]->nnz) / 1024 + 2);
+    return std::max<int64_t>(b, 1);
+}
+
+// Applies `plan`, rebuilds the item list (matrices in order, tiles in order) and the device
+// tables, sets max_tile and a default grid (one workgroup per item).
+static hipError_t build_tables(spx_batch_s* B, const std::vector<int32_t>& plan, hipStream_t s) {
+    std::vector<int2> items;
+    B->max_tile = 256;
+    for (int32_t i = 0; i < B->count; ++i) {
+        const hipError_t e = apply_plan(B->host[i], plan[i], B->handles[i]->nnz, s);
+        if (e != hipSuccess) return e;
+        for (int32_t t = 0; t < B->host[i].tiles; ++t) items.push_back(make_int2(i, t));
+        if (is_merge(plan[i])) B->max_tile = std::max(B->max_tile, 256 * plan_ipt(plan[i]));
+    }
+    B->nitems = (int64_t)items.size();
+    B->grid = (int32_t)std::min<int64_t>(std::max<int64_t>(B->nitems, 1), 1 << 20);
+    hipError_t e = hipSuccess;
+    if (!items.empty())
+        e = hipMemcpyAsync(B->items, items.data(), items.size() * sizeof(int2),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->mats, B->host.data(), B->count * sizeof(BatchMat),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
+}
+
+// Times the whole batch (zero x shared by all matrices, a scratch y per matrix) for the plans as
+// tuned and with 16-item merge tiles replaced by 8-item ones, each with one workgroup per item
+// and with persistent grids of 4096 and 1024 workgroups; keeps the fastest.
+static hipError_t tune_batch(spx_batch_s* B, const std::vector<int32_t>& plan, int64_t max_n,
+                             hipStream_t s) {
+    Dev tmp;
+    tmp.s = s;
+    int64_t total_m = 0;
+    for (const BatchMat& M : B->host) total_m += M.m;
+    float* xt = tmp.get<float>(max_n);
+    float* yt = tmp.get<float>(total_m);
+    if (!xt || !yt) {
+        tmp.release();
+        return hipErrorOutOfMemory;
+    }
+    std::vector<const float*> hx(B->count, xt);
+    std::vector<float*> hy(B->count);
+    int64_t off = 0;
+    for (int32_t i = 0; i < B->count; ++i) {
+        hy[i] = yt + off;
+        off += B->host[i].m;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMemsetAsync(xt, 0, max_n * 4, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->xs, hx.data(), B->count * sizeof(void*), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->ys, hy.data(), B->count * sizeof(void*), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    std::vector<std::vector<int32_t>> variants{plan};
+    if (std::count(plan.begin(), plan.end(), SPX_PLAN_MERGE_16) > 0) {
+        std::vector<int32_t> v = plan;
+        for (int32_t& p : v)
+            if (p == SPX_PLAN_MERGE_16) p = SPX_PLAN_MERGE_8;
+        variants.push_back(v);
+    }
+    float best = 0;
+    size_t best_v = 0;
+    int32_t best_g = B->grid;
+    for (size_t vi = 0; vi < variants.size() && e == hipSuccess; ++vi) {
+        e = build_tables(B, variants[vi], s);
+        const int64_t all = B->grid;
+        for (int64_t g : {all, (int64_t)4096, (int64_t)1024}) {
+            if (e != hipSuccess) break;
+            if (g != all && g >= all) continue;  // a persistent grid only when it is smaller
+            for (int r = 0; r < kTuneWarm && e == hipSuccess; ++r)
+                e = launch_batch_spmv(B->mats, B->items, (int32_t)B->nitems, (int32_t)g,
+                                      B->max_tile, B->xs, B->ys, s);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int r = 0; r < 3 && e == hipSuccess; ++r)
+                e = launch_batch_spmv(B->mats, B->items, (int32_t)B->nitems, (int32_t)g,
+                                      B->max_tile, B->xs, B->ys, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && (best == 0 || ms < best)) {
+                best = ms;
+                best_v = vi;
+                best_g = (int32_t)g;
+            }
+        }
+    }
+    if (e == hipSuccess) {
+        e = build_tables(B, variants[best_v], s);
+        B->grid = best_g;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    tmp.release();
+    return e;
 }
 
 extern "C" spx_status spx_batch_create(const spx_matrix* mats, int32_t count,
@@ -160,13 +270,9 @@ extern "C" spx_status spx_batch_create(const spx_matrix* mats, int32_t count,
         tune = tune || plan[i] == SPX_PLAN_AUTO;
     }
     BatchMat* one = B->dev.get<BatchMat>(1);
-    uint32_t* done = B->dev.get<uint32_t>(count);
     const float** xs = (const float**)B->dev.get<void*>(count);
     float** ys = (float**)B->dev.get<void*>(count);
-    if (!one || !done || !xs || !ys)
-        return bail(spx_fail(SPX_ERR_NOMEM, "device allocation failed"));
-    e = launch_fill_u32(done, count, 0u, s);
-    if (e != hipSuccess) return bail(herr(e, "counters"));
+    if (!one || !xs || !ys) return bail(spx_fail(SPX_ERR_NOMEM, "device allocation failed"));
     if (tune) {
         Dev tmp;
         tmp.s = s;
@@ -177,6 +283,7 @@ extern "C" spx_status spx_batch_create(const spx_matrix* mats, int32_t count,
         for (int32_t i = 0; i < count; ++i)
             it_cap = std::max<int64_t>(it_cap, std::max<int64_t>(mats[i]->m,
                                                                  ((int64_t)mats[i]->m + mats[i]->nnz) / 1024 + 2));
+        it_cap += kTuneItems;
         int2* it = tmp.get<int2>(it_cap);
         const float** xst = (const float**)tmp.get<void*>(1);
         float** yst = (float**)tmp.get<void*>(1);
@@ -205,22 +312,27 @@ extern "C" spx_status spx_batch_create(const spx_matrix* mats, int32_t count,
                     best = cand;
                     break;
                 }
-                hit.resize(M.tiles);
-                for (int32_t t = 0; t < M.tiles; ++t) hit[t] = make_int2(0, t);
-                e = hipMemcpyAsync(it, hit.data(), M.tiles * sizeof(int2), hipMemcpyHostToDevice, s);
+                // the tiles repeated up to kTuneItems items; repeats rewrite the same outputs of
+                // the scratch y, whose values are not used
+                const int64_t reps = (kTuneItems + M.tiles - 1) / M.tiles;
+                const int32_t nit = (int32_t)(reps * M.tiles);
+                hit.resize(nit);
+                for (int32_t q = 0; q < nit; ++q) hit[q] = make_int2(0, q % M.tiles);
+                e = hipMemcpyAsync(it, hit.data(), nit * sizeof(int2), hipMemcpyHostToDevice, s);
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(one, &M, sizeof(BatchMat), hipMemcpyHostToDevice, s);
-                const int32_t grid = (int32_t)std::min<int64_t>(M.tiles, 1024);
+                const int32_t mt = is_merge(cand) ? 256 * plan_ipt(cand) : 256;
                 for (int r = 0; r < kTuneWarm && e == hipSuccess; ++r)
-                    e = launch_batch_spmv(one, it, M.tiles, grid, xst, yst, done, s);
+                    e = launch_batch_spmv(one, it, nit, nit, mt, xst, yst, s);
                 if (e == hipSuccess) e = hipEventRecord(e0, s);
                 for (int r = 0; r < kTuneReps && e == hipSuccess; ++r)
-                    e = launch_batch_spmv(one, it, M.tiles, grid, xst, yst, done, s);
+                    e = launch_batch_spmv(one, it, nit, nit, mt, xst, yst, s);
                 if (e == hipSuccess) e = hipEventRecord(e1, s);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float ms = 0;
                 if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
                 if (e != hipSuccess) break;
+                ms /= (float)reps;  // cost of one pass over the matrix
                 if (best_ms == 0 || ms < best_ms) {
                     best_ms = ms;
                     best = cand;
@@ -235,30 +347,23 @@ extern "C" spx_status spx_batch_create(const spx_matrix* mats, int32_t count,
         if (e != hipSuccess) return bail(herr(e, "autotuning"));
     }
 
-    // final plans and the item list (matrices in order, tiles in order)
-    std::vector<int2> items;
-    for (int32_t i = 0; i < count; ++i) {
-        e = apply_plan(B->host[i], plan[i], mats[i]->nnz, s);
-        if (e != hipSuccess) return bail(herr(e, "plans"));
-        for (int32_t t = 0; t < B->host[i].tiles; ++t) items.push_back(make_int2(i, t));
-        if (chosen) chosen[i] = plan[i];
-    }
-    B->nitems = (int64_t)items.size();
-    if (B->nitems >= INT32_MAX) return bail(spx_fail(SPX_ERR_RANGE, "too many work items"));
-    B->items = B->dev.get<int2>(items.size());
-    B->mats = B->dev.get<BatchMat>(count);
-    if (!B->items || !B->mats) return bail(spx_fail(SPX_ERR_NOMEM, "device allocation failed"));
-    e = hipMemcpyAsync(B->items, items.data(), items.size() * sizeof(int2),
-                       hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(B->mats, B->host.data(), count * sizeof(BatchMat),
-                           hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return bail(herr(e, "tables"));
-    B->grid = (int32_t)std::min<int64_t>(B->nitems, 1024);
-    B->done = done;
+    // final plans and the item list
     B->xs = xs;
     B->ys = ys;
+    B->items = B->dev.get<int2>(items_bound(mats, count));
+    B->mats = B->dev.get<BatchMat>(count);
+    if (!B->items || !B->mats) return bail(spx_fail(SPX_ERR_NOMEM, "device allocation failed"));
+    e = build_tables(B, plan, s);
+    if (e == hipSuccess && B->nitems >= INT32_MAX)
+        return bail(spx_fail(SPX_ERR_RANGE, "too many work items"));
+    if (e == hipSuccess && tune && B->nitems > 1024) {
+        // whole-batch choices: the launch shape, and whether merge tiles of 16 items per thread
+        // (which set the launch's LDS size for every workgroup) beat 8 items per thread
+        e = tune_batch(B, plan, max_n, s);
+    }
+    if (e != hipSuccess) return bail(herr(e, "plans"));
+    if (chosen)
+        for (int32_t i = 0; i < count; ++i) chosen[i] = B->host[i].plan;
     *out = B;
     return SPX_OK;
 }
@@ -300,8 +405,8 @@ extern "C" spx_status spx_batch_bind(spx_batch B, const float* const* xs, float*
 extern "C" spx_status spx_batch_spmv(spx_batch B, void* stream) {
     if (!B) return spx_fail(SPX_ERR_INVALID_ARG, "batch is NULL");
     if (!B->bound) return spx_fail(SPX_ERR_INVALID_ARG, "no vectors bound");
-    const hipError_t e = launch_batch_spmv(B->mats, B->items, (int32_t)B->nitems, B->grid, B->xs,
-                                           B->ys, B->done, (hipStream_t)stream);
+    const hipError_t e = launch_batch_spmv(B->mats, B->items, (int32_t)B->nitems, B->grid,
+                                           B->max_tile, B->xs, B->ys, (hipStream_t)stream);
     if (e != hipSuccess) return herr(e, "batch product");
     return SPX_OK;
 }

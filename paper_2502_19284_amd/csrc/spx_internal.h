@@ -128,9 +128,11 @@ struct BatchMat {
     int32_t rows_per_tile;      // row plans
     int32_t bf16;
 };
+// product launch (grid workgroups, max_tile = largest merge tile of the batch, or 256) and the
+// carry fix-up launch
 hipError_t launch_batch_spmv(const BatchMat* mats, const int2* items, int32_t nitems,
-                             int32_t grid, const float* const* xs, float* const* ys,
-                             uint32_t* done, hipStream_t s);
+                             int32_t grid, int32_t max_tile, const float* const* xs,
+                             float* const* ys, hipStream_t s);
 hipError_t launch_batch_maxlen(const int32_t* row_ptr, int32_t m, uint32_t* out, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
