@@ -584,6 +584,7 @@ def main():
     args = ap.parse_args()
     if args.summarize_rocprof:
         md, tj = summarize_rocprof(args.summarize_rocprof, "rmat24")
+        os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
         with open(os.path.join(ROOT, "profiles", "traffic_rmat24.json"), "w") as f:
             json.dump(tj, f, indent=1, sort_keys=True)
         print(md)

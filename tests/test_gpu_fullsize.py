@@ -148,3 +148,61 @@ def test_ones_gives_row_sums(big, fmt):
     err = measure.scaled_error(y, sums, scale)
     assert err.max() <= 1e-12, err.max()
     A.close()
+
+
+def _sampled_crs(w, rows):
+    """Canonical CRS of the sampled rows (renumbered 0..len-1), as rows_reference builds it."""
+    mask = np.zeros(w["m"], dtype=bool)
+    mask[rows] = True
+    sel = np.flatnonzero(mask[w["row"]])
+    local = np.searchsorted(rows, w["row"][sel]).astype(np.int32)
+    return spmv.crs(len(rows), w["n"], local, w["col"][sel], w["val"][sel])
+
+
+@pytest.mark.parametrize("fmt", ["rowsplit", "merge"])
+@pytest.mark.parametrize("vt", ["f32", "bf16"])
+def test_sampled_rows_reduced_precision(big, fmt, vt):
+    # FP32 / bfloat16 stored values at full size: sampled rows within the FP32 dot-product bound
+    # of the oracle on the rounded inputs; the error against the unrounded FP64 oracle is printed
+    import torch
+
+    from oracle import precision
+    spx, w, dev, (rows, yp, yr, sc) = big
+    A = spx.convert(dev["row"], dev["col"], dev["val"], (w["m"], w["n"]), fmt, value_type=vt)
+    y = A.spmv(dev["x"].float())
+    torch.cuda.synchronize()
+    got = y[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    rp, cc, cv = _sampled_crs(w, rows)
+    rv = precision.round_f32(cv) if vt == "f32" else precision.round_bf16(cv)
+    _, yr_r, s_r = spmv.alg1_accurate(rp, cc, rv, precision.round_f32(w["x"]))
+    lens = np.diff(rp) + 2
+    err = measure.scaled_error(got, yr_r, s_r)
+    assert np.all(err <= precision.dot_error_bound(lens, 0.0) + 1e-300)
+    e64 = measure.scaled_error(got, yr, sc)
+    u = precision.U32 if vt == "f32" else precision.UBF16
+    assert np.all(e64 <= precision.dot_error_bound(lens, u))
+    say("  %s %s vs FP64 oracle on %d rows: max %.3g median %.3g" % (fmt, vt, len(rows), e64.max(),
+                                                                       np.median(e64)))
+    A.close()
+
+
+def test_spmm_sampled_rows(big):
+    # Y = A X with 4 column-major right-hand sides (FP32 values) on sampled rows of every column
+    import torch
+
+    from oracle import precision
+    spx, w, dev, (rows, yp, yr, sc) = big
+    k = 4
+    X = np.stack([synth.xvec(w["n"], seed=40 + c) for c in range(k)], axis=1)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda", dtype=torch.float32).t()
+    A = spx.convert(dev["row"], dev["col"], dev["val"], (w["m"], w["n"]), "merge",
+                    value_type="f32")
+    Y = A.spmm(Xd)
+    torch.cuda.synchronize()
+    got = Y[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    rp, cc, cv = _sampled_crs(w, rows)
+    _, R, S = spmv.spmm(rp, cc, precision.round_f32(cv), precision.round_f32(X))
+    bound = precision.dot_error_bound(np.diff(rp) + 2, 0.0)[:, None]
+    err = np.abs(got - R)
+    assert np.all(err <= bound * S + 1e-300)
+    A.close()
