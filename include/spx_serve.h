@@ -17,10 +17,11 @@
  *       SPX_REQ_PAGERANK:  y = d A x + (1 - d) / n   (one power-iteration step with damping d on a
  *                          column-stochastic A; the caller supplies the normalised matrix)
  *   - A scheduler thread owns all device work after admission.  It keeps up to `slots` batches in
- *     flight, each on its own stream.  Whenever a slot is free it takes the matrix whose oldest
- *     waiting request is oldest, coalesces up to max_batch of that matrix's waiting requests
- *     (oldest first) and launches them as one product; a matrix has at most one batch in flight.
- *     Requests that arrive while batches run are admitted as slots free up (continuous batching).
+ *     flight, each on its own stream with its own product scratch.  Whenever a slot is free it
+ *     takes the matrix whose oldest waiting request is oldest, coalesces up to max_batch of that
+ *     matrix's waiting requests (oldest first) and launches them as one product; a popular matrix
+ *     may have batches on several slots at once.  Requests that arrive while batches run are
+ *     admitted as slots free up (continuous batching).
  *   - With coalesce = 0 the server is the plain path: one slot, one request per launch, in arrival
  *     order, through the single-vector product.
  *   - Each column of a batched product is the same computation as the request alone up to the
@@ -71,7 +72,8 @@ typedef struct {
     int32_t in_flight;       /* batches on the device now                              */
 } spx_server_stats;
 
-/* Defaults: budget 64 GiB, 4 slots, max_batch 32, coalesce 1, poll_us 5. */
+/* Defaults: budget 64 GiB, 4 slots, max_batch 32, coalesce 1, poll_us 0 (the scheduler yields
+ * instead of sleeping while batches are in flight). */
 spx_status spx_server_opts_default(spx_server_opts* opts);
 
 /* Create a server (starts its scheduler thread and streams on the current device). */

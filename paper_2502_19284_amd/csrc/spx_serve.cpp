@@ -3,9 +3,10 @@
 // One scheduler thread per server does all device work after admission.  Requests are queued per
 // matrix under one mutex; the scheduler polls its in-flight batches (one HIP event per slot),
 // retires the finished ones, and fills free slots with the matrix whose oldest waiting request is
-// oldest, coalescing up to max_batch of its waiting requests into one product.  Admission,
-// conversion and the product scratch of a matrix are settled on the caller's thread, so the
-// scheduler itself never allocates except to grow its per-slot staging buffers.
+// oldest, coalescing up to max_batch of its waiting requests into one product.  Product scratch
+// (carries, hot rows, staging of X and Y) belongs to the slot, not to the matrix, so a popular
+// matrix can have batches on several slots at once.  Admission and conversion run on the
+// caller's thread; the scheduler only allocates to grow its slot buffers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,8 +40,10 @@ struct Mat {
     int32_t id = 0, m = 0, n = 0;
     int64_t bytes = 0;
     std::deque<Req*> waiting;
-    bool busy = false;  // a batch of this matrix is on the device
+    int32_t in_flight = 0;  // batches of this matrix on the device
     int64_t outstanding = 0;
+    const int2* coords = nullptr;  // merge tiles of the product (the handle's)
+    int32_t tiles = 0, nhot = 0;
 };
 
 struct Slot {
@@ -52,6 +55,11 @@ struct Slot {
     float* X = nullptr;  // n x k, row-major
     float* Y = nullptr;  // m x k, row-major
     size_t xcap = 0, ycap = 0;
+    // product scratch owned by the slot, so that one matrix may have batches on several slots
+    int32_t* crow = nullptr;  // tile carry rows
+    double* cval = nullptr;   // tile carries, tiles x k
+    float* H = nullptr;       // hot rows of X, nhot x k
+    size_t crow_cap = 0, cval_cap = 0, hcap = 0;
     void* dtab = nullptr;  // device: k x pointers, k y pointers, k alphas, k betas
     void* htab = nullptr;  // pinned host mirror
 };
@@ -104,7 +112,8 @@ extern "C" spx_status spx_server_opts_default(spx_server_opts* o) {
 }
 
 // Upper bound of what a resident matrix holds: stored arrays for nnz <= E entries, both
-// partitions' tables, the hot-column tables and the product scratch for max_batch columns.
+// partitions' tables, the hot-column tables, and the product scratch of max_batch columns that
+// its batches occupy in the slots.
 static int64_t footprint_bound(const spx_coo_desc* c, int32_t vt, int32_t max_batch) {
     const int64_t m = c->m, n = c->n, E = c->nnz;
     const int64_t vs = vt == SPX_F32 ? 4 : 2;
@@ -170,7 +179,7 @@ void spx_server_s::retire(Slot& sl, double t, spx_status st) {
     }
     n_done += (int64_t)sl.batch.size();
     sl.mat->outstanding -= (int64_t)sl.batch.size();
-    sl.mat->busy = false;
+    --sl.mat->in_flight;
     sl.mat = nullptr;
     sl.batch.clear();
     sl.busy = false;
@@ -178,39 +187,62 @@ void spx_server_s::retire(Slot& sl, double t, spx_status st) {
     cv_done.notify_all();
 }
 
-static hipError_t grow(float** p, size_t* cap, size_t need) {
+// Grows an idle slot's buffer to `need` elements (hipFree waits for the device).
+template <typename T>
+static hipError_t grow(T** p, size_t* cap, size_t need) {
     if (need <= *cap) return hipSuccess;
     if (*p) (void)hipFree(*p);
     *p = nullptr;
     *cap = 0;
-    hipError_t e = hipMalloc((void**)p, need * sizeof(float));
+    hipError_t e = hipMalloc((void**)p, need * sizeof(T));
     if (e == hipSuccess) *cap = need;
     return e;
 }
 
-// Enqueues the slot's batch (lock not held; the slot and its matrix are reserved).
+// Enqueues the slot's batch (lock not held; the slot is reserved).  The plain path runs the
+// single-vector product on the handle; the coalescing path runs the product with k right-hand
+// sides (k = 1 included) on the slot's own scratch, so batches of one matrix may overlap.
 spx_status spx_server_s::launch(Slot& sl) {
     Mat* M = sl.mat;
     const int k = (int)sl.batch.size();
     hipStream_t s = sl.stream;
     hipError_t e;
-    if (k == 1) {
-        const spx_request& r = sl.batch[0]->r;
-        spx_status st = spx_spmv_f32(M->A, r.x, r.y, s);
+    const spx_request& r0 = sl.batch[0]->r;
+    const float beta0 = (1.0f - r0.damping) / (float)M->n;
+    if (!o.coalesce) {
+        spx_status st = spx_spmv_f32(M->A, r0.x, r0.y, s);
         if (st != SPX_OK) return st;
-        if (r.kind == SPX_REQ_PAGERANK) {
-            e = launch_serve_axpb(r.y, M->m, r.damping, (1.0f - r.damping) / (float)M->n, s);
+        if (r0.kind == SPX_REQ_PAGERANK) {
+            e = launch_serve_axpb(r0.y, M->m, r0.damping, beta0, s);
             if (e != hipSuccess) return hip_fail(e, "epilogue");
         }
+        e = hipEventRecord(sl.done, s);
+        return e == hipSuccess ? SPX_OK : hip_fail(e, "event");
+    }
+    const size_t before = (sl.xcap + sl.ycap + sl.hcap) * 4 + sl.crow_cap * 4 + sl.cval_cap * 8;
+    e = grow(&sl.crow, &sl.crow_cap, (size_t)M->tiles + 1);
+    if (e == hipSuccess) e = grow(&sl.cval, &sl.cval_cap, ((size_t)M->tiles + 1) * k);
+    if (e == hipSuccess) e = grow(&sl.H, &sl.hcap, (size_t)M->nhot * k);
+    if (e == hipSuccess && k > 1) e = grow(&sl.X, &sl.xcap, (size_t)M->n * k);
+    if (e == hipSuccess && k > 1) e = grow(&sl.Y, &sl.ycap, (size_t)M->m * k);
+    if (e != hipSuccess) return hip_fail(e, "slot buffers");
+    {
+        const size_t after = (sl.xcap + sl.ycap + sl.hcap) * 4 + sl.crow_cap * 4 + sl.cval_cap * 8;
+        std::lock_guard<std::mutex> g(mu);
+        staging += (int64_t)(after - before);
+    }
+    SpmmPlan P;
+    P.coords = M->coords;
+    P.tiles = M->tiles;
+    P.carry_row = sl.crow;
+    P.carry_val = sl.cval;
+    P.h = sl.H;
+    if (k == 1) {  // x and y are already a 1-column row-major X and Y
+        e = spmm_crs(M->A, P, 1, r0.x, 1, r0.y, 1, 1, s);
+        if (e == hipSuccess && r0.kind == SPX_REQ_PAGERANK)
+            e = launch_serve_axpb(r0.y, M->m, r0.damping, beta0, s);
+        if (e != hipSuccess) return hip_fail(e, "product");
     } else {
-        size_t xc = sl.xcap, yc = sl.ycap;
-        e = grow(&sl.X, &sl.xcap, (size_t)M->n * k);
-        if (e == hipSuccess) e = grow(&sl.Y, &sl.ycap, (size_t)M->m * k);
-        if (e != hipSuccess) return hip_fail(e, "staging buffers");
-        {
-            std::lock_guard<std::mutex> g(mu);
-            staging += (int64_t)((sl.xcap - xc) + (sl.ycap - yc)) * 4;
-        }
         char* h = (char*)sl.htab;
         const float** xs = (const float**)h;
         float** ys = (float**)(h + kMaxBatch * sizeof(void*));
@@ -228,13 +260,13 @@ spx_status spx_server_s::launch(Slot& sl) {
         if (e != hipSuccess) return hip_fail(e, "request table");
         char* d = (char*)sl.dtab;
         e = launch_serve_gather((const float* const*)d, k, M->n, sl.X, s);
-        if (e != hipSuccess) return hip_fail(e, "gather");
-        spx_status st = spx_spmm(M->A, k, sl.X, k, sl.Y, k, SPX_ROW_MAJOR, s);
-        if (st != SPX_OK) return st;
+        if (e == hipSuccess) e = spmm_crs(M->A, P, k, sl.X, k, sl.Y, k, 1, s);
         float* dal = (float*)(d + 2 * kMaxBatch * sizeof(void*));
-        e = launch_serve_scatter(sl.Y, k, M->m, (float* const*)(d + kMaxBatch * sizeof(void*)),
-                                 dal, dal + kMaxBatch, s);
-        if (e != hipSuccess) return hip_fail(e, "scatter");
+        if (e == hipSuccess)
+            e = launch_serve_scatter(sl.Y, k, M->m,
+                                     (float* const*)(d + kMaxBatch * sizeof(void*)), dal,
+                                     dal + kMaxBatch, s);
+        if (e != hipSuccess) return hip_fail(e, "batched product");
     }
     e = hipEventRecord(sl.done, s);
     if (e != hipSuccess) return hip_fail(e, "event");
@@ -258,7 +290,7 @@ void spx_server_s::run() {
             Mat* best = nullptr;
             for (auto& kv : mats) {
                 Mat* M = kv.second;
-                if (M->busy || M->waiting.empty()) continue;
+                if (M->waiting.empty()) continue;
                 if (!best || M->waiting.front()->t_submit < best->waiting.front()->t_submit)
                     best = M;
             }
@@ -269,7 +301,7 @@ void spx_server_s::run() {
                 best->waiting.pop_front();
             }
             waiting_total -= k;
-            best->busy = true;
+            ++best->in_flight;
             sl.mat = best;
             sl.busy = true;
             ++in_flight;
@@ -310,8 +342,8 @@ extern "C" spx_status spx_server_destroy(spx_server S) {
     }
     for (auto& sl : S->slots) {
         (void)hipStreamSynchronize(sl.stream);
-        if (sl.X) (void)hipFree(sl.X);
-        if (sl.Y) (void)hipFree(sl.Y);
+        for (void* p : {(void*)sl.X, (void*)sl.Y, (void*)sl.crow, (void*)sl.cval, (void*)sl.H})
+            if (p) (void)hipFree(p);
         (void)hipHostFree(sl.htab);
         (void)hipFree(sl.dtab);
         (void)hipEventDestroy(sl.done);
@@ -353,26 +385,30 @@ extern "C" spx_status spx_server_add_matrix(spx_server S, const spx_coo_desc* co
         unreserve();
         return st;
     }
-    // settle the product scratch for max_batch columns now, so the scheduler never allocates
-    const int32_t kb = S->o.max_batch;
-    if (kb > 1 && coo->m > 0) {
+    // a row-split handle gets its merge tiles for products with several right-hand sides here,
+    // through one product, so the scheduler never allocates on a handle
+    const int2* coords = A->mp_coords;
+    int32_t tiles = A->mp_tiles;
+    if (S->o.coalesce && A->fmt == SPX_CSR_ROWSPLIT && coo->m > 0) {
         float *X = nullptr, *Y = nullptr;
-        hipError_t e = hipMalloc((void**)&X, ((size_t)std::max(coo->n, 1)) * kb * 4);
-        if (e == hipSuccess) e = hipMalloc((void**)&Y, (size_t)coo->m * kb * 4);
-        if (e == hipSuccess) e = hipMemsetAsync(X, 0, ((size_t)std::max(coo->n, 1)) * kb * 4,
-                                               (hipStream_t)stream);
+        hipError_t e = hipMalloc((void**)&X, (size_t)std::max(coo->n, 1) * 4);
+        if (e == hipSuccess) e = hipMalloc((void**)&Y, (size_t)coo->m * 4);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(X, 0, (size_t)std::max(coo->n, 1) * 4, (hipStream_t)stream);
         if (e == hipSuccess) {
-            st = spx_spmm(A, kb, X, kb, Y, kb, SPX_ROW_MAJOR, stream);
+            st = spx_spmm(A, 1, X, 1, Y, 1, SPX_ROW_MAJOR, stream);
             e = hipStreamSynchronize((hipStream_t)stream);
         }
         if (X) (void)hipFree(X);
         if (Y) (void)hipFree(Y);
-        if (st == SPX_OK && e != hipSuccess) st = hip_fail(e, "scratch set-up");
+        if (st == SPX_OK && e != hipSuccess) st = hip_fail(e, "merge tiles");
         if (st != SPX_OK) {
             spx_matrix_destroy(A);
             unreserve();
             return st;
         }
+        coords = A->mm_coords;
+        tiles = A->mm_tiles;
     }
     Mat* M = new (std::nothrow) Mat;
     if (!M) {
@@ -384,6 +420,9 @@ extern "C" spx_status spx_server_add_matrix(spx_server S, const spx_coo_desc* co
     M->m = coo->m;
     M->n = coo->n;
     M->bytes = need;
+    M->coords = coords;
+    M->tiles = tiles;
+    M->nhot = A->nhot;
     {
         std::lock_guard<std::mutex> g(S->mu);
         M->id = S->next_id++;
