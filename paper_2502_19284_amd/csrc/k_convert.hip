@@ -463,8 +463,9 @@ hipError_t launch_gather_csb(const uint64_t* keys, const double* vals, const int
 
 // Fused repeat summing + populate.  Workgroup b owns the sorted positions of scan tile b (the
 // same SCAN_TILE tiling as launch_dedup_count, whose scanned tile counts give each tile's first
-// output index).  The tile's keys are staged in LDS; run heads are ranked with a workgroup scan;
-// then each head (processed in strided, coalesced order) sums its run in increasing position
+// output index).  The tile's keys are staged in LDS and every item's value is loaded up front;
+// run heads are ranked by ballots in strided item order; then each head sums its run in increasing
+// position
 // (= increasing triplet index, the sort being stable), writes its index and value, and marks the
 // end of its row (block) for the max-scan.
 #define DG_NT SCAN_NT
@@ -476,37 +477,58 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
     const uint64_t* __restrict__ keys, const double* __restrict__ vals, int64_t E,
     const uint32_t* __restrict__ tile_off, int shiftbits, HotMap hm,
     int32_t* __restrict__ idx_out, double* __restrict__ val_out, int32_t* __restrict__ ends) {
-    __shared__ uint64_t s_key[DG_TILE + 1];              // s_key[i+1] = keys[base+i]
-    __shared__ uint32_t s_u[DG_TILE + DG_TILE / 16];     // output index of head i (skewed)
-    __shared__ uint32_t s_tmp[DG_NT / SPX_WAVE];
+    constexpr int NW = DG_NT / SPX_WAVE;
+    __shared__ uint64_t s_key[DG_TILE + 1];  // s_key[i+1] = keys[base+i]
+    __shared__ uint32_t s_pre[DG_IPT][NW];   // heads before (row j, wave w) within the tile
     const int tid = threadIdx.x;
+    const int w = tid / SPX_WAVE;
+    const int lane = __lane_id();
     const int64_t base = (int64_t)blockIdx.x * DG_TILE;
     const int64_t rem = E - base;
     const int cnt = rem < DG_TILE ? (int)rem : DG_TILE;
-    for (int i = tid; i < cnt; i += DG_NT) s_key[i + 1] = keys[base + i];
+    // keys staged in LDS; every item's own value loaded up front (coalesced, all in flight)
+    double v[DG_IPT];
+#pragma unroll
+    for (int j = 0; j < DG_IPT; ++j) {
+        const int i = tid + j * DG_NT;
+        if (i < cnt) s_key[i + 1] = keys[base + i];
+        v[j] = i < cnt ? vals[base + i] : 0.0;
+    }
     if (tid == 0) s_key[0] = base > 0 ? keys[base - 1] : ~keys[0];  // position 0 is a head
     __syncthreads();
-    uint32_t c = 0;
+    // output index of each head: heads are ranked in item order i = tid + j * DG_NT, so a
+    // ballot per (row j, wave) and a prefix over the DG_IPT x NW wave counts suffice
+    const uint64_t lt = spx_lanemask_lt();
+    uint32_t rank[DG_IPT];
+    uint32_t heads = 0;
 #pragma unroll
     for (int j = 0; j < DG_IPT; ++j) {
-        const int i = tid * DG_IPT + j;
-        if (i < cnt && s_key[i + 1] != s_key[i]) ++c;
+        const int i = tid + j * DG_NT;
+        const bool head = i < cnt && s_key[i + 1] != s_key[i];
+        const uint64_t bal = __ballot(head);
+        rank[j] = (uint32_t)__popcll(bal & lt);
+        heads |= (head ? 1u : 0u) << j;
+        if (lane == 0) s_pre[j][w] = (uint32_t)__popcll(bal);
     }
-    uint32_t total;
-    uint32_t run = block_excl_scan<DG_NT, uint32_t, OpSum<uint32_t>>(c, s_tmp, &total);
-    run += tile_off[blockIdx.x];
-#pragma unroll
-    for (int j = 0; j < DG_IPT; ++j) {
-        const int i = tid * DG_IPT + j;
-        if (i < cnt && s_key[i + 1] != s_key[i]) s_u[scan_skew(i)] = run++;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = tile_off[blockIdx.x];
+        for (int j = 0; j < DG_IPT; ++j)
+            for (int ww = 0; ww < NW; ++ww) {
+                const uint32_t c = s_pre[j][ww];
+                s_pre[j][ww] = run;
+                run += c;
+            }
     }
     __syncthreads();
     const uint64_t lowmask = (1ull << shiftbits) - 1ull;
-    for (int i = tid; i < cnt; i += DG_NT) {
+#pragma unroll
+    for (int j = 0; j < DG_IPT; ++j) {
+        if (!((heads >> j) & 1u)) continue;
+        const int i = tid + j * DG_NT;
         const uint64_t key = s_key[i + 1];
-        if (key == s_key[i]) continue;
-        const int64_t u = s_u[scan_skew(i)];
-        double acc = vals[base + i];
+        const int64_t u = s_pre[j][w] + rank[j];
+        double acc = v[j];
         int64_t e = i + 1;  // tile-relative position after the run
         uint64_t next = 0;
         bool more = false;

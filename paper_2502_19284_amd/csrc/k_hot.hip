@@ -7,8 +7,9 @@
 // array whose lines are all hot, and the kernels read x_hot[~c] for negative c.  Results are
 // unchanged: only the address a value is read from moves.
 //
-// The set is a bitmap over columns plus a prefix count per 64-bit word (3 MB for 2^24 columns,
-// L2-resident), so rank(c) = prefix[c/64] + popcount(bits[c/64] below c) costs two cached loads.
+// The set is a bitmap over columns plus a prefix count per 64-bit word, packed into one 16-byte
+// word per 64 columns (4 MB for 2^24 columns, L2-resident), so rank(c) = prefix + popcount(bits
+// below c) costs one cached load.
 #include "dev_scan.h"
 #include "spx_internal.h"
 
@@ -95,6 +96,48 @@ hipError_t launch_hot_set(const uint32_t* freq, int64_t n, uint32_t tau, uint64_
     if (e != hipSuccess) return e;
     SPX_LAUNCH("hot_list", k_hot_list, dim3(spx_div_up(nwords, 256)), dim3(256), 0, s, bits, pre,
                nwords, hot_cols);
+    return hipGetLastError();
+}
+
+__global__ void k_hot_pack(const uint64_t* __restrict__ bits, const uint32_t* __restrict__ pre,
+                           int64_t nwords, uint4* __restrict__ words) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nwords) return;
+    const uint64_t b = bits[w];
+    words[w] = make_uint4((uint32_t)b, (uint32_t)(b >> 32), pre[w], 0u);
+}
+
+hipError_t launch_hot_pack(const uint64_t* bits, const uint32_t* pre, int64_t nwords,
+                           uint4* words, hipStream_t s) {
+    if (nwords <= 0) return hipSuccess;
+    SPX_LAUNCH("hot_pack", k_hot_pack, dim3(spx_div_up(nwords, 256)), dim3(256), 0, s, bits, pre,
+               nwords, words);
+    return hipGetLastError();
+}
+
+// Histogram of the sampled column counts (the last bin collects every count >= bins-1), kept per
+// workgroup in LDS and added once per bin.
+__global__ __launch_bounds__(256) void k_hot_freq_hist(const uint32_t* __restrict__ freq,
+                                                       int64_t n, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[HOT_HIST_BINS];
+    for (int i = threadIdx.x; i < HOT_HIST_BINS; i += 256) h[i] = 0;
+    __syncthreads();
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t f = freq[c];
+        atomicAdd(&h[f < HOT_HIST_BINS - 1 ? f : HOT_HIST_BINS - 1], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < HOT_HIST_BINS; i += 256)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+hipError_t launch_hot_freq_hist(const uint32_t* freq, int64_t n, uint32_t* hist, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t g = spx_div_up(n, 256);
+    if (g > 1024) g = 1024;
+    SPX_LAUNCH("hot_freq_hist", k_hot_freq_hist, dim3((unsigned)g), dim3(256), 0, s, freq, n,
+               hist);
     return hipGetLastError();
 }
 

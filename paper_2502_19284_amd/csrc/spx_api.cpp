@@ -269,12 +269,25 @@ static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot
         *out = rb.totals[3];
         return SPX_OK;
     };
-    // smallest tau >= 1 with count_ge(tau) <= hot_max; count_ge is non-increasing in tau
-    uint32_t c1;
-    SPX_TRY(count_ge(1, &c1));
-    uint32_t tau = 1;
-    if (c1 > (uint64_t)hot_max) {
-        uint64_t lo = 2, hi = (uint64_t)((E + stride - 1) / stride) + 1;  // count_ge(hi) == 0
+    // smallest tau >= 1 with count_ge(tau) <= hot_max; count_ge is non-increasing in tau.  A
+    // histogram of the counts answers every tau below HOT_HIST_BINS - 1 with one readback;
+    // larger thresholds fall back to bisection with device-side counts.
+    uint32_t* fh;
+    SPX_TRY(tmp.get(&fh, HOT_HIST_BINS, "count histogram"));
+    HIP_TRY(hipMemsetAsync(fh, 0, HOT_HIST_BINS * 4, s));
+    HIP_TRY(launch_hot_freq_hist(freq, n, fh, s));
+    std::vector<uint32_t> hh(HOT_HIST_BINS);
+    SPX_TRY(sync_read(hh.data(), fh, HOT_HIST_BINS * 4, s));
+    uint64_t suffix = 0;  // count_ge(t) for t = HOT_HIST_BINS - 1 down to 1
+    uint32_t tau = 0;
+    for (int t = HOT_HIST_BINS - 1; t >= 1; --t) {
+        suffix += hh[t];
+        if (suffix > (uint64_t)hot_max) break;
+        tau = (uint32_t)t;
+    }
+    if (tau == 0) {  // even count_ge(HOT_HIST_BINS - 1) exceeds hot_max
+        uint64_t lo = HOT_HIST_BINS, hi = (uint64_t)((E + stride - 1) / stride) + 1;
+        if (hi < lo) hi = lo;  // count_ge(hi) == 0
         while (lo < hi) {
             const uint64_t mid = (lo + hi) / 2;
             uint32_t c;
@@ -293,12 +306,14 @@ static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot
     SPX_TRY(tmp.get(&x_hot, nhot, "hot x"));
     keep(tmp, A, hot_cols);
     keep(tmp, A, x_hot);
+    uint4* words;
+    SPX_TRY(tmp.get(&words, (size_t)nwords, "hot words"));
     HIP_TRY(launch_hot_set(freq, n, tau, bits, pre, hot_cols, tsums, s));
+    HIP_TRY(launch_hot_pack(bits, pre, nwords, words, s));
     A->hot_cols = hot_cols;
     A->x_hot = x_hot;
     A->nhot = (int32_t)nhot;
-    hm->bits = bits;
-    hm->pre = pre;
+    hm->words = words;
     return SPX_OK;
 }
 

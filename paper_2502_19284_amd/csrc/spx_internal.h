@@ -34,7 +34,9 @@
 // radix sort: 8-bit digits, 256 threads x 8 keys per tile
 #define RS_RADIX_BITS 8
 #define RSORT_NT 256
+#ifndef RSORT_IPT
 #define RSORT_IPT 8
+#endif
 #define RSORT_TILE (RSORT_NT * RSORT_IPT)
 
 struct spx_matrix_s {
@@ -140,16 +142,18 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 void* spx_dev_alloc(size_t bytes, hipStream_t s);
 void spx_dev_free(void* p, hipStream_t s);
 
-// Stored column index of column c: ~rank for hot columns, c otherwise (bits == null: no hot set).
+// Stored column index of column c: ~rank for hot columns, c otherwise (words == null: no hot
+// set).  One 16-byte word per 64 columns: {bitmap low half, bitmap high half, number of hot
+// columns before the word, 0}, so a lookup is a single load.
 struct HotMap {
-    const uint64_t* bits = nullptr;
-    const uint32_t* pre = nullptr;
+    const uint4* words = nullptr;
     __device__ __forceinline__ int32_t map(uint32_t c) const {
-        if (!bits) return (int32_t)c;
-        const uint64_t b = bits[c >> 6];
+        if (!words) return (int32_t)c;
+        const uint4 wd = words[c >> 6];
+        const uint64_t b = ((uint64_t)wd.y << 32) | (uint64_t)wd.x;
         const uint64_t bit = 1ull << (c & 63u);
         if (!(b & bit)) return (int32_t)c;
-        return ~(int32_t)(pre[c >> 6] + (uint32_t)__popcll(b & (bit - 1ull)));
+        return ~(int32_t)(wd.z + (uint32_t)__popcll(b & (bit - 1ull)));
     }
 };
 
@@ -198,6 +202,12 @@ hipError_t launch_hot_count_ge(const uint32_t* freq, int64_t n, uint32_t tau, ui
                                uint32_t* total, hipStream_t s);
 hipError_t launch_hot_set(const uint32_t* freq, int64_t n, uint32_t tau, uint64_t* bits,
                           uint32_t* pre, int32_t* hot_cols, uint32_t* tile_sums, hipStream_t s);
+// words[w] = {bits[w] low, bits[w] high, pre[w], 0}
+hipError_t launch_hot_pack(const uint64_t* bits, const uint32_t* pre, int64_t nwords,
+                           uint4* words, hipStream_t s);
+// hist[min(freq[c], bins-1)] += 1 over all columns (hist zeroed by the caller)
+#define HOT_HIST_BINS 4096
+hipError_t launch_hot_freq_hist(const uint32_t* freq, int64_t n, uint32_t* hist, hipStream_t s);
 hipError_t launch_hot_unmap(const int32_t* col, int64_t nnz, const int32_t* hot_cols,
                             int32_t* out, hipStream_t s);
 
