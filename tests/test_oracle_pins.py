@@ -524,3 +524,48 @@ def dense_abs(m, n, row, col, val):
     d = np.zeros((m, n))
     np.add.at(d, (row, col), val)
     return np.abs(d)
+
+
+def test_hilbert_prefix_is_block_order():
+    # the Hilbert index of level K2 + k of (row, col), shifted right by 2k, is the Hilbert index of
+    # level K2 of the block (row >> k, col >> k): the curve visits every aligned sub-square whole
+    rng = np.random.default_rng(21)
+    for K2, k in [(1, 1), (2, 3), (3, 2), (5, 4)]:
+        side = 1 << (K2 + k)
+        r = rng.integers(0, side, 4000)
+        c = rng.integers(0, side, 4000)
+        full = curves.hilbert_index_array(K2 + k, r, c)
+        assert np.array_equal(full >> (2 * k), curves.hilbert_index_array(K2, r >> k, c >> k))
+
+
+def test_bcoh_partitions_and_order():
+    from oracle import bcoh
+    rng = np.random.default_rng(4)
+    # partitions: cover the rows, never span more than WINDOW rows, split where the cumulative
+    # raw count crosses a multiple of the target
+    m, E = 30000, 500_000
+    rows = np.minimum(rng.zipf(1.3, E) - 1, m - 1)
+    st = bcoh.partition_starts(m, rows, E)
+    assert st[0] == 0 and st[-1] == m and np.all(np.diff(st) > 0)
+    assert np.all(np.diff(st) <= bcoh.WINDOW)
+    cum = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=m))])
+    t = bcoh.target(E)
+    for a, b in zip(st[:-1], st[1:]):  # inside a partition no row crosses a bucket boundary
+        inner = np.arange(a + 1, b)
+        assert np.all(cum[inner] // t == cum[inner - 1] // t)
+        assert (a % bcoh.WINDOW == 0) or a == 0 or cum[a] // t != cum[a - 1] // t
+    # order on a small example, checked by brute force against the definitions
+    m, n, k = 40, 36, 2
+    r = rng.integers(0, m, 300)
+    c = rng.integers(0, n, 300)
+    st = np.array([0, 13, 29, m])
+    for hil in (False, True):
+        perm, part, br, bc = bcoh.order(m, n, k, r, c, st, hil)
+        K2 = bcoh.ceil_log2(max(-(-m // 4), -(-n // 4)))
+        def bkey(i):
+            p = int(np.searchsorted(st, r[i], side="right") - 1)
+            if hil:
+                return (p, curves.hilbert_index(K2 + k, r[i], c[i]))
+            return (p, curves.hilbert_index(K2, r[i] >> k, c[i] >> k), r[i], c[i])
+        want = sorted(range(len(r)), key=lambda i: (bkey(i), i))
+        assert [bkey(i) for i in perm] == [bkey(i) for i in want]
