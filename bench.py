@@ -64,11 +64,14 @@ def spmv_bytes(fmt, m, nnz, n_touched, A, val_bytes=8, vec_bytes=8):
         b += 8 * (A.parts + 1) + 12 * A.parts  # tile starts, carry rows and values
     if fmt == "rowsplit":
         b += 4 * (A.parts + 1)
-    if fmt == "csbh":
+    if fmt in ("csbh", "csb"):
         beta = 1 << A.log2_beta
         nbr = (m + beta - 1) // beta
         nbc = (A.shape[1] + beta - 1) // beta
         b += 4 * (nbr * nbc + 1) + 16 * A.parts
+    if fmt in ("bcohc", "bcohch"):
+        nb = A.export("blk_coord").numel()
+        b += 8 * (nb + 1) + 8 * (A.parts + 1)  # block pointers and coordinates, partition table
     return b
 
 
@@ -568,6 +571,8 @@ def main():
     ap.add_argument("--spmv-reps", type=int, default=100)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--formats", default=",".join(FMTS))
+    ap.add_argument("--extra-formats", default="csb,bcohc,bcohch",
+                    help="formats timed outside the step: conversion and steady-state product")
     ap.add_argument("--precision", type=int, default=1,
                     help="also time the FP32 / bfloat16 forms of the CRS formats")
     ap.add_argument("--spmm", type=int, default=1,
@@ -672,10 +677,21 @@ def main():
                     "launches": dom[1]["launches"], "bytes_per_launch": int(dom_bytes),
                     "share_of_step": round(dom[1]["total_ms"] / (t_steps * 1e3), 3)}
 
-    # steady-state product of a resident matrix, per format
+    # steady-state product of a resident matrix, per format (the extra formats also get their
+    # conversion timed here, best of two)
+    extra = [f for f in args.extra_formats.split(",") if f and f not in fmts]
     spmv = {}
-    for f in fmts:
-        A = spx.convert(row_d, col_d, val_d, (m, n), f)
+    for f in fmts + extra:
+        if f in extra:
+            ybuf[f] = torch.empty(m, dtype=torch.float64, device="cuda")
+            conv_ms[f] = []
+            for _ in range(2):
+                A = spx.convert(row_d, col_d, val_d, (m, n), f)
+                conv_ms[f].append(A.convert_ms)
+                if len(conv_ms[f]) < 2:
+                    A.close()
+        else:
+            A = spx.convert(row_d, col_d, val_d, (m, n), f)
         ms, ks = time_products(spx, torch, A, x_d, ybuf[f], args.spmv_reps)
         kname, kavg, kmin = product_kernels(ks)
         B = spmv_bytes(f, m, A.nnz, n_touched, A)
@@ -712,18 +728,18 @@ def main():
         served = serving_leg(spx, torch, np, synth, args)
 
     conv = {f: {"ms_min": round(min(conv_ms[f]), 3),
-                "ms_median": round(statistics.median(conv_ms[f]), 3)} for f in fmts}
+                "ms_median": round(statistics.median(conv_ms[f]), 3)} for f in fmts + extra}
     be = {}
     if "rowsplit" in fmts:
         ref_conv = conv["rowsplit"]["ms_min"]
         ref_spmv = spmv["rowsplit"]["ms_min"]
-        for f in fmts:
+        for f in fmts + extra:
             conv[f]["in_rowsplit_products"] = round(conv[f]["ms_min"] / ref_spmv, 1)
             if f != "rowsplit":
                 N = spx.break_even(conv[f]["ms_min"], ref_conv, ref_spmv, spmv[f]["ms_min"])
                 be[f] = None if math.isinf(N) else round(N, 1)
 
-    best = max(fmts, key=lambda f: spmv[f]["gflops_median_time"])
+    best = max(fmts + extra, key=lambda f: spmv[f]["gflops_median_time"])
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -731,6 +747,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "m": m, "n": n, "raw_entries": E,
                    "nnz": nnz, "n_touched_columns": n_touched, "formats": fmts,
+                   "extra_formats": extra,
                    "step": "convert triplets to each format, one y = A x per format, "
                            "conversion report"},
         "roofline": roofline,

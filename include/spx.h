@@ -52,6 +52,14 @@ typedef int32_t spx_format;
 #define SPX_CSB_HILBERT 2
 /* Compressed sparse blocks with Z-Morton order inside each block, CSB (Section 3.1). */
 #define SPX_CSB_ZMORTON 3
+/* Row-distributed blocks with compressed triplets, BCOHC (Section 3.2, hybrid variants): the rows
+ * are cut into partitions of about equal entry count (one per workgroup, each at most 8192 rows),
+ * a partition's beta x beta blocks are stored in Hilbert order, and inside a block the entries are
+ * packed (local_row << 16) | local_col in row-wise order.  The block level keeps an explicit block
+ * coordinate per block instead of the paper's BICRS increments (GPU threads need random access). */
+#define SPX_BCOHC 4
+/* BCOHCH: as BCOHC with every partition's entries sorted by the Hilbert curve over (row, col). */
+#define SPX_BCOHCH 5
 
 typedef int32_t spx_dtype;
 #define SPX_F64 0
@@ -79,7 +87,8 @@ typedef struct {
 
 typedef struct {
     int32_t sum_duplicates; /* 1: sum repeated coordinates (default); 0: keep each as an entry  */
-    int32_t log2_beta;      /* CSBH block side 2^log2_beta; 0 = block-size rule (Section 3.1)  */
+    int32_t log2_beta;      /* CSB/CSBH/BCOHC/BCOHCH block side 2^log2_beta; 0 = block-size
+                             * rule (Section 3.1)                                            */
     int32_t validate;       /* indices are always checked (fused into the key build); 0 or 1  */
     int32_t tile_items;     /* work per tile/unit; 0 = default for the format                  */
     int32_t hot_columns;    /* CRS formats: at most this many of the most frequent columns get a
@@ -114,10 +123,13 @@ typedef int32_t spx_array;
 #define SPX_ARRAY_ROW_PTR 0 /* CRS formats: int32[m+1]                                      */
 #define SPX_ARRAY_COL_IND 1 /* CRS formats: int32[nnz], ascending inside a row              */
 #define SPX_ARRAY_VALUES 2  /* all formats: values[nnz] in storage order, of the stored type */
-#define SPX_ARRAY_BLK_PTR 3 /* CSB/CSBH: int32[nbr*nbc+1], blocks in row-wise order         */
+#define SPX_ARRAY_BLK_PTR 3 /* CSB/CSBH: int32[nbr*nbc+1], blocks in row-wise order;
+                             * BCOHC/BCOHCH: int32[blocks+1], first entry of each stored block */
 #define SPX_ARRAY_PACKED 4  /* CSB/CSBH: uint32[nnz], (local_row << 16) | local_col, in the
                              * block's Hilbert (CSBH) or Z-Morton (CSB) order                  */
-#define SPX_ARRAY_PARTS 5   /* format's work-unit table, int32 (layout is internal)          */
+#define SPX_ARRAY_PARTS 5   /* format's work-unit table, int32 (layout is internal; BCOHC /
+                             * BCOHCH: P+1 partition first rows, then P+1 first blocks)     */
+#define SPX_ARRAY_BLK_COORD 6 /* BCOHC/BCOHCH: uint32[blocks], (block_row << 16) | block_col */
 
 /* Optional device allocator: alloc returns NULL on failure; free accepts what alloc returned. */
 typedef void* (*spx_alloc_fn)(size_t bytes, void* stream, void* ctx);
@@ -144,8 +156,10 @@ spx_status spx_convert_opts_default(spx_convert_opts* opts);
  * out:  host; receives a new handle on success, NULL on any error.
  * rep:  host, may be NULL.  convert_ms covers all device work of the call.
  * The call returns after the device work is complete (it reads back the entry count).
- * Errors: INVALID_ARG, RANGE (m, n or nnz beyond int32, or a CSBH key beyond 64 bits), INDEX
- * (validate=1 and an index out of range), NOMEM, HIP.  On error every temporary is freed.
+ * Errors: INVALID_ARG, RANGE (m, n or nnz beyond int32, or a CSB / BCOHC key beyond 64 bits),
+ * INDEX (validate=1 and an index out of range), UNSUPPORTED (reduced-precision values for the
+ * block formats; sum_duplicates=0 for BCOHC / BCOHCH), NOMEM, HIP.  On error every temporary is
+ * freed.
  */
 spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt, const spx_convert_opts* opts,
                        void* stream, spx_matrix* out, spx_convert_report* rep);

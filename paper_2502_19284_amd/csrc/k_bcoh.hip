@@ -1,0 +1,219 @@
+// k_bcoh.hip -- BCOHC / BCOHCH: row-distributed blocks with compressed triplets (gfx950).
+//
+// The paper's workers (threads with a static share of rows of about equal entry count) become
+// partitions, one workgroup each.  A partition is a range of whole rows of at most BH_WINDOW
+// rows, so its output rows live in LDS for the whole product; its beta x beta blocks are stored
+// in Hilbert order, and inside a block the entries are packed (local_row << 16) | local_col in
+// row-wise order (BCOHC) or in the order of the Hilbert curve over the partition (BCOHCH).  The
+// block level keeps an explicit (block row, block column) per block and the first entry of each
+// block, where the paper keeps BICRS increments (which a single thread decodes in sequence).
+#include "dev_common.h"
+#include "dev_curves.h"
+#include "dev_scan.h"
+#include "dev_values.h"
+#include "spx_internal.h"
+
+// ------------------------------------------------------------------ conversion
+
+__global__ void k_bcoh_rows(const int32_t* __restrict__ row, const int32_t* __restrict__ col,
+                            int64_t E, int32_t m, int32_t n, uint32_t* __restrict__ counts,
+                            uint32_t* __restrict__ err) {
+    uint32_t bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = row[i], c = col[i];
+        const bool ok = (r >= 0) & (r < m) & (c >= 0) & (c < n);
+        if (ok) atomicAdd(&counts[r], 1u);
+        bad |= ok ? 0u : 1u;
+    }
+    if (__ballot(bad != 0) && __lane_id() == 0) atomicOr(err, 1u);
+}
+
+hipError_t launch_bcoh_rows(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+                            int32_t n, uint32_t* counts, uint32_t* err, hipStream_t s) {
+    if (E <= 0) return hipSuccess;
+    int64_t g = spx_div_up(E, 256);
+    if (g > 8192) g = 8192;
+    SPX_LAUNCH("bcoh_rows", k_bcoh_rows, dim3((unsigned)g), dim3(256), 0, s, row, col, E, m, n,
+               counts, err);
+    return hipGetLastError();
+}
+
+// Row r starts a partition when it is row 0, a multiple of BH_WINDOW, or when the raw entries
+// before it and before row r - 1 lie in different multiples of the target count.
+struct LoadPartStart {
+    const uint32_t* cum;
+    uint32_t target;
+    __device__ uint32_t operator()(int64_t r) const {
+        if (r == 0 || r % BH_WINDOW == 0) return 1u;
+        return (cum[r] / target) != (cum[r - 1] / target) ? 1u : 0u;
+    }
+};
+struct StorePart {
+    int32_t* part_of;
+    int32_t* part_row;
+    __device__ void operator()(int64_t r, uint32_t incl, uint32_t item) const {
+        part_of[r] = (int32_t)incl - 1;
+        if (item) part_row[incl - 1] = (int32_t)r;
+    }
+};
+
+hipError_t launch_bcoh_partitions(const uint32_t* cum, int32_t m, uint32_t target,
+                                  int32_t* part_of, int32_t* part_row, uint32_t* tile_sums,
+                                  uint32_t* total, hipStream_t s) {
+    const LoadPartStart ld{cum, target};
+    hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(ld, m, tile_sums, total, s);
+    if (e != hipSuccess) return e;
+    return scan_phase3<uint32_t, OpSum<uint32_t>>(ld, StorePart{part_of, part_row}, m, tile_sums,
+                                                  s);
+}
+
+struct LoadU32B {
+    const uint32_t* p;
+    __device__ uint32_t operator()(int64_t i) const { return p[i]; }
+};
+struct StoreInclU32 {
+    uint32_t* p;
+    __device__ void operator()(int64_t i, uint32_t incl, uint32_t) const { p[i] = incl; }
+};
+
+hipError_t launch_incl_scan_u32(uint32_t* a, int64_t n, uint32_t* tile_sums, uint32_t* total,
+                                hipStream_t s) {
+    hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32B{a}, n, tile_sums, total, s);
+    if (e != hipSuccess) return e;
+    return scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32B{a}, StoreInclU32{a}, n, tile_sums, s);
+}
+
+// Entry u starts a block when incl[u] exceeds incl[u-1]; the block's key (partition << 2*K2 |
+// Hilbert block index) was stored at majors[u] by the populate step.
+__global__ void k_bcoh_blocks(const uint32_t* __restrict__ incl,
+                              const uint64_t* __restrict__ majors, int64_t nnz, int K2,
+                              int32_t* __restrict__ blk_ptr, uint32_t* __restrict__ blk_coord,
+                              int32_t* __restrict__ blk_part) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < nnz;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = incl[u];
+        if (u > 0 && incl[u - 1] == c) continue;
+        const uint32_t b = c - 1;
+        const uint64_t mj = majors[u];
+        const uint64_t hb = mj & ((1ull << (2 * K2)) - 1ull);
+        uint32_t bc, br;
+        hilbert_d2xy64(K2, hb, &bc, &br);
+        blk_ptr[b] = (int32_t)u;
+        blk_coord[b] = (br << 16) | bc;
+        blk_part[b] = (int32_t)(mj >> (2 * K2));
+    }
+}
+
+hipError_t launch_bcoh_blocks(const uint32_t* incl, const uint64_t* majors, int64_t nnz, int K2,
+                              int32_t* blk_ptr, uint32_t* blk_coord, int32_t* blk_part,
+                              hipStream_t s) {
+    if (nnz <= 0) return hipSuccess;
+    int64_t g = spx_div_up(nnz, 256);
+    if (g > 65536) g = 65536;
+    SPX_LAUNCH("bcoh_blocks", k_bcoh_blocks, dim3((unsigned)g), dim3(256), 0, s, incl, majors,
+               nnz, K2, blk_ptr, blk_coord, blk_part);
+    return hipGetLastError();
+}
+
+// part_blk[p] = first block whose partition is >= p (blocks are in partition order), p = 0..P
+__global__ void k_bcoh_part_blk(const int32_t* __restrict__ blk_part, int64_t nb, int32_t P,
+                                int32_t* __restrict__ part_blk) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > P) return;
+    int64_t lo = 0, hi = nb;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (blk_part[mid] < p) lo = mid + 1;
+        else hi = mid;
+    }
+    part_blk[p] = (int32_t)lo;
+}
+
+hipError_t launch_bcoh_part_blk(const int32_t* blk_part, int64_t nb, int32_t P,
+                                int32_t* part_blk, hipStream_t s) {
+    SPX_LAUNCH("bcoh_part_blk", k_bcoh_part_blk, dim3(spx_div_up((int64_t)P + 1, 256)), dim3(256),
+               0, s, blk_part, nb, P, part_blk);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ product
+//
+// Workgroup p owns the rows [part_row[p], part_row[p+1]) and their slice of y in LDS.  It walks
+// the partition's entries in storage order, BH_IPT consecutive entries per thread: a thread finds
+// the block of its first entry by binary search over the partition's block pointers and moves
+// forward from there; each product is added into the slice (LDS float atomics), and the slice is
+// written to y at the end.
+
+#define BH_NT 512
+#define BH_IPT 8
+
+__global__ __launch_bounds__(BH_NT) void k_spmv_bcoh(
+    const int32_t* __restrict__ part_row, const int32_t* __restrict__ part_blk,
+    const int32_t* __restrict__ blk_ptr, const uint32_t* __restrict__ blk_coord,
+    const uint32_t* __restrict__ packed, const double* __restrict__ val,
+    const double* __restrict__ x, double* __restrict__ y, int k) {
+    extern __shared__ double s_y[];
+    const int tid = threadIdx.x;
+    const int p = blockIdx.x;
+    const int r0 = part_row[p], rows = part_row[p + 1] - r0;
+    const int b0 = part_blk[p], b1 = part_blk[p + 1];
+    const int e0 = blk_ptr[b0], e1 = blk_ptr[b1];
+    for (int i = tid; i < rows; i += BH_NT) s_y[i] = 0.0;
+    __syncthreads();
+    const uint32_t lmask = 0xFFFFu;
+    for (int base = e0; base < e1; base += BH_NT * BH_IPT) {
+        const int kf = base + tid * BH_IPT;
+        if (kf < e1) {
+            int lo = b0, hi = b1 - 1;  // last block b with blk_ptr[b] <= kf
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (blk_ptr[mid] <= kf) lo = mid;
+                else hi = mid - 1;
+            }
+            int b = lo;
+            int next = blk_ptr[b + 1];
+            uint32_t bc = blk_coord[b];
+#pragma unroll
+            for (int q = 0; q < BH_IPT; ++q) {
+                const int kk = kf + q;
+                if (kk < e1) {
+                    while (next <= kk) {
+                        ++b;
+                        next = blk_ptr[b + 1];
+                        bc = blk_coord[b];
+                    }
+                    const uint32_t pk = ntload(packed + kk);
+                    const int row = (int)((bc >> 16) << k) + (int)(pk >> 16);
+                    const int colx = (int)((bc & lmask) << k) + (int)(pk & lmask);
+                    atomicAdd(&s_y[row - r0], ntload(val + kk) * x[colx]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < rows; i += BH_NT) ntstore(y + r0 + i, s_y[i]);
+}
+
+hipError_t spmv_bcoh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
+    if (A->bh_nparts <= 0) return hipSuccess;
+    SPX_LAUNCH("spmv_bcoh", k_spmv_bcoh, dim3(A->bh_nparts), dim3(BH_NT),
+               (size_t)BH_WINDOW * sizeof(double), s, A->bh_part_row, A->bh_part_blk,
+               A->bh_blk_ptr, A->bh_blk_coord, A->packed, A->val, x, y, A->log2_beta);
+    return hipGetLastError();
+}
+
+struct StoreExclU32B {
+    uint32_t* p;
+    __device__ void operator()(int64_t i, uint32_t incl, uint32_t item) const {
+        p[i] = incl - item;
+    }
+};
+
+hipError_t launch_excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n,
+                                uint32_t* tile_sums, uint32_t* total, hipStream_t s) {
+    hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32B{in}, n, tile_sums, total, s);
+    if (e != hipSuccess) return e;
+    return scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32B{in}, StoreExclU32B{out}, n, tile_sums,
+                                                  s);
+}

@@ -5,6 +5,7 @@
 // a 64-bit key that carries each triplet's value along; step 2 sums repeated coordinates in
 // increasing triplet index and turns per-row (per-block) end marks into row_ptr (blk_ptr) with a
 // max-scan.
+#include "dev_curves.h"
 #include "dev_scan.h"
 #include "spx_internal.h"
 
@@ -45,72 +46,6 @@ hipError_t launch_init_readback(Readback* rb, hipStream_t s) {
 size_t scan_tile_count(int64_t n) { return n <= 0 ? 1 : (size_t)spx_div_up(n, SCAN_TILE); }
 
 // ------------------------------------------------------------------ sort keys
-
-// Hilbert index of local cell (row y, column x) in a 2^k x 2^k block: the classical
-// quadrant-by-quadrant descent (quadrant order q = 0..3 is (x<h,y<h), (x<h,y>=h), (x>=h,y>=h),
-// (x>=h,y<h); entering quadrants 0 and 3 transposes / anti-transposes the remaining bits).
-__device__ __forceinline__ uint32_t hilbert_xy2d(int k, uint32_t x, uint32_t y) {
-    uint32_t d = 0;
-    for (int l = k - 1; l >= 0; --l) {
-        const uint32_t h = 1u << l;
-        const uint32_t rx = (x >> l) & 1u, ry = (y >> l) & 1u;
-        d += h * h * ((3u * rx) ^ ry);
-        if (ry == 0) {
-            if (rx == 1) {  // reflect the low bits through the anti-diagonal
-                x = (h - 1) - (x & (h - 1));
-                y = (h - 1) - (y & (h - 1));
-            }
-            const uint32_t t = x;
-            x = y;
-            y = t;
-        }
-    }
-    return d;
-}
-
-// Inverse of hilbert_xy2d: local (x = column, y = row) of index d, built up from the finest
-// level, undoing each level's transform.
-__device__ __forceinline__ void hilbert_d2xy(int k, uint32_t d, uint32_t* px, uint32_t* py) {
-    uint32_t x = 0, y = 0, t = d;
-    for (int l = 0; l < k; ++l) {
-        const uint32_t h = 1u << l;
-        const uint32_t rx = 1u & (t >> 1);
-        const uint32_t ry = 1u & (t ^ rx);
-        if (ry == 0) {
-            if (rx == 1) {
-                x = (h - 1) - x;
-                y = (h - 1) - y;
-            }
-            const uint32_t tmp = x;
-            x = y;
-            y = tmp;
-        }
-        x += h * rx;
-        y += h * ry;
-        t >>= 2;
-    }
-    *px = x;
-    *py = y;
-}
-
-// Z-Morton index of local cell (row y, column x): bits interleaved with the row bit above the
-// column bit at every level (quadrants top-left, top-right, bottom-left, bottom-right).
-__device__ __forceinline__ uint32_t zmorton_xy2d(int k, uint32_t x, uint32_t y) {
-    uint32_t d = 0;
-    for (int l = 0; l < k; ++l)
-        d |= (((y >> l) & 1u) << (2 * l + 1)) | (((x >> l) & 1u) << (2 * l));
-    return d;
-}
-
-__device__ __forceinline__ void zmorton_d2xy(int k, uint32_t d, uint32_t* px, uint32_t* py) {
-    uint32_t x = 0, y = 0;
-    for (int l = 0; l < k; ++l) {
-        x |= ((d >> (2 * l)) & 1u) << l;
-        y |= ((d >> (2 * l + 1)) & 1u) << l;
-    }
-    *px = x;
-    *py = y;
-}
 
 template <typename KeyFn>
 __device__ __forceinline__ void keys_body(const int32_t* __restrict__ row,
@@ -175,6 +110,28 @@ struct KeyCsb {
     }
 };
 
+// BCOHC: (partition, Hilbert index of the block, row-wise position inside the block);
+// BCOHCH: (partition, Hilbert index of (row, col) at level K2 + k), whose leading 2*K2 bits are
+// the block's Hilbert index.
+template <bool HIL>
+struct KeyBcoh {
+    const int32_t* part_of;
+    int k, K2;
+    __device__ uint64_t operator()(uint32_t r, uint32_t c) const {
+        const int pshift = 2 * (K2 + k);
+        const uint64_t p = (uint64_t)part_of[r];
+        uint64_t d;
+        if (HIL) {
+            d = hilbert_xy2d64(K2 + k, c, r);
+        } else {
+            const uint32_t mask = (1u << k) - 1u;
+            const uint64_t hb = hilbert_xy2d64(K2, c >> k, r >> k);
+            d = (hb << (2 * k)) | ((uint64_t)(r & mask) << k) | (uint64_t)(c & mask);
+        }
+        return (pshift < 64 ? (p << pshift) : 0ull) | d;
+    }
+};
+
 template <typename KeyFn>
 __global__ __launch_bounds__(256) void k_keys(const int32_t* row, const int32_t* col, int64_t E,
                                               int32_t m, int32_t n, uint64_t* keys, uint32_t* err,
@@ -201,6 +158,21 @@ hipError_t launch_keys_csb(const int32_t* row, const int32_t* col, int64_t E, in
         SPX_LAUNCH("keys", (k_keys<KeyCsb<false>>), dim3(grid_for(E, 256, KEYS_MAX_GRID)),
                    dim3(256), 0, s, row, col, E, m, n, keys, err, masks,
                    KeyCsb<false>{k, (uint64_t)nbc});
+    return hipGetLastError();
+}
+
+hipError_t launch_keys_bcoh(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+                            int32_t n, const int32_t* part_of, int k, int K2, bool hilbert,
+                            uint64_t* keys, uint32_t* err, unsigned long long* masks,
+                            hipStream_t s) {
+    if (hilbert)
+        SPX_LAUNCH("keys", (k_keys<KeyBcoh<true>>), dim3(grid_for(E, 256, KEYS_MAX_GRID)),
+                   dim3(256), 0, s, row, col, E, m, n, keys, err, masks,
+                   KeyBcoh<true>{part_of, k, K2});
+    else
+        SPX_LAUNCH("keys", (k_keys<KeyBcoh<false>>), dim3(grid_for(E, 256, KEYS_MAX_GRID)),
+                   dim3(256), 0, s, row, col, E, m, n, keys, err, masks,
+                   KeyBcoh<false>{part_of, k, K2});
     return hipGetLastError();
 }
 
@@ -476,7 +448,8 @@ template <int MODE>
 __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
     const uint64_t* __restrict__ keys, const double* __restrict__ vals, int64_t E,
     const uint32_t* __restrict__ tile_off, int shiftbits, HotMap hm,
-    int32_t* __restrict__ idx_out, double* __restrict__ val_out, int32_t* __restrict__ ends) {
+    int32_t* __restrict__ idx_out, double* __restrict__ val_out, int32_t* __restrict__ ends,
+    int K, uint64_t* __restrict__ majors) {
     constexpr int NW = DG_NT / SPX_WAVE;
     __shared__ uint64_t s_key[DG_TILE + 1];  // s_key[i+1] = keys[base+i]
     __shared__ uint32_t s_pre[DG_IPT][NW];   // heads before (row j, wave w) within the tile
@@ -544,6 +517,25 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
         val_out[u] = acc;
         const uint64_t major = key >> shiftbits;
         const uint32_t d = (uint32_t)(key & lowmask);
+        if (MODE >= 3) {  // BCOHC / BCOHCH: packed local position, block-start flag
+            const int k = shiftbits >> 1;
+            const uint32_t mask = (1u << k) - 1u;
+            uint32_t lc, lr;
+            if (MODE == 3) {
+                lr = d >> k;
+                lc = d & mask;
+            } else {
+                uint32_t x, y;
+                hilbert_d2xy64(K, key & ((1ull << (2 * K)) - 1ull), &x, &y);
+                lr = y & mask;
+                lc = x & mask;
+            }
+            idx_out[u] = (int32_t)((lr << 16) | lc);
+            const bool bstart = (s_key[i] >> shiftbits) != major;
+            ends[u] = bstart ? 1 : 0;
+            if (bstart) majors[u] = major;
+            continue;
+        }
         if (MODE != 0) {
             const int k = shiftbits >> 1;
             uint32_t lc, lr;
@@ -559,18 +551,24 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
 
 hipError_t launch_dedup_gather(const uint64_t* keys, const double* vals, int64_t E,
                                const uint32_t* tile_sums, int mode, int shiftbits, HotMap hm,
-                               int32_t* idx_out, double* val_out, int32_t* ends, hipStream_t s) {
+                               int32_t* idx_out, double* val_out, int32_t* ends, hipStream_t s,
+                               int K, uint64_t* majors) {
     if (E <= 0) return hipSuccess;
     const unsigned g = spx_div_up(E, DG_TILE);
-    if (mode == 0)
-        SPX_LAUNCH("dedup_gather", (k_dedup_gather<0>), dim3(g), dim3(DG_NT), 0, s, keys, vals, E,
-                   tile_sums, shiftbits, hm, idx_out, val_out, ends);
-    else if (mode == 1)
-        SPX_LAUNCH("dedup_gather", (k_dedup_gather<1>), dim3(g), dim3(DG_NT), 0, s, keys, vals, E,
-                   tile_sums, shiftbits, hm, idx_out, val_out, ends);
-    else
-        SPX_LAUNCH("dedup_gather", (k_dedup_gather<2>), dim3(g), dim3(DG_NT), 0, s, keys, vals, E,
-                   tile_sums, shiftbits, hm, idx_out, val_out, ends);
+#define DG_CASE(M)                                                                              \
+    case M:                                                                                     \
+        SPX_LAUNCH("dedup_gather", (k_dedup_gather<M>), dim3(g), dim3(DG_NT), 0, s, keys, vals, \
+                   E, tile_sums, shiftbits, hm, idx_out, val_out, ends, K, majors);             \
+        break;
+    switch (mode) {
+        DG_CASE(0)
+        DG_CASE(1)
+        DG_CASE(2)
+        DG_CASE(3)
+        DG_CASE(4)
+        default: return hipErrorInvalidValue;
+    }
+#undef DG_CASE
     return hipGetLastError();
 }
 

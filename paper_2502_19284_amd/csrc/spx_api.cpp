@@ -5,6 +5,7 @@
 // counters (index errors, entry count, work-unit counts) and therefore synchronises the stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -183,7 +184,8 @@ struct SortedEntries {
 
 static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_format fmt, int k,
                                  int64_t nbc, int cbits, int sum_dup, hipStream_t s,
-                                 SortedEntries* out) {
+                                 SortedEntries* out, const int32_t* part_of = nullptr,
+                                 int K2 = 0) {
     const int64_t E = coo->nnz;
     uint64_t *k0, *k1, *v0, *v1;
     uint32_t *hist, *tsums;
@@ -200,7 +202,10 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
     SPX_TRY(tmp.get(&rb_dev, 1, "readback"));
 
     HIP_TRY(launch_init_readback(rb_dev, s));
-    if (spx_is_csb(fmt))
+    if (spx_is_bcoh(fmt))
+        HIP_TRY(launch_keys_bcoh(coo->row, coo->col, E, coo->m, coo->n, part_of, k, K2,
+                                 fmt == SPX_BCOHCH, k0, &rb_dev->err, rb_dev->masks, s));
+    else if (spx_is_csb(fmt))
         HIP_TRY(launch_keys_csb(coo->row, coo->col, E, coo->m, coo->n, k, nbc,
                                 fmt == SPX_CSB_HILBERT, k0, &rb_dev->err, rb_dev->masks, s));
     else
@@ -317,6 +322,93 @@ static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot
     return SPX_OK;
 }
 
+// BCOHC / BCOHCH: partitions of whole rows with about equal raw entry counts (at most
+// BH_WINDOW rows each), then one sort by (partition, Hilbert block index, position in block),
+// the fused repeat-sum + populate step, and the block and partition tables.
+static spx_status convert_bcoh(const spx_coo_desc* coo, spx_format fmt, int k, int K2,
+                               hipStream_t s, spx_matrix_s* A, AllocSet& tmp) {
+    const int64_t E = coo->nnz;
+    const int32_t m = coo->m;
+    Readback* rb_dev;
+    Readback rb;
+    SPX_TRY(tmp.get(&rb_dev, 1, "readback"));
+    HIP_TRY(launch_init_readback(rb_dev, s));
+    uint32_t *counts, *cum, *tsums;
+    int32_t *part_of, *part_row;
+    SPX_TRY(tmp.get(&counts, (size_t)m + 1, "row counts"));
+    SPX_TRY(tmp.get(&cum, (size_t)m + 1, "row count scan"));
+    SPX_TRY(tmp.get(&part_of, (size_t)m + 1, "row partitions"));
+    SPX_TRY(tmp.get(&part_row, (size_t)m + 2, "partition rows"));
+    size_t tsn = scan_tile_count((int64_t)m + 2);
+    if (scan_tile_count(E + 1) > tsn) tsn = scan_tile_count(E + 1);
+    SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
+    HIP_TRY(launch_fill_i32((int32_t*)counts, (int64_t)m + 1, 0, s));
+    HIP_TRY(launch_bcoh_rows(coo->row, coo->col, E, m, coo->n, counts, &rb_dev->err, s));
+    HIP_TRY(launch_excl_scan_u32(counts, cum, m, tsums, &rb_dev->totals[1], s));
+    const int64_t target64 = (E + BH_PARTS_TARGET - 1) / BH_PARTS_TARGET;
+    const uint32_t target = (uint32_t)(target64 > (1 << 16) ? target64 : (1 << 16));
+    HIP_TRY(launch_bcoh_partitions(cum, m, target, part_of, part_row, tsums, &rb_dev->totals[0],
+                                   s));
+    SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+    if (rb.err) return fail(SPX_ERR_INDEX, "a triplet index lies outside [0,%d) x [0,%d)", coo->m,
+                            coo->n);
+    const int32_t P = (int32_t)rb.totals[0];
+    HIP_TRY(launch_fill_i32(part_row + P, 1, m, s));
+    const int pbits = ceil_log2_u64((uint64_t)(P > 1 ? P : 1));
+    if (pbits + 2 * (K2 + k) > 64) return fail(SPX_ERR_RANGE, "BCOHC sort key exceeds 64 bits");
+
+    SortedEntries se;
+    if (E > 0) SPX_TRY(sort_and_dedup(tmp, coo, fmt, k, 0, 0, 1, s, &se, part_of, K2));
+    const int64_t nnz = se.nnz_out;
+    A->nnz = nnz;
+    double* val_out;
+    uint32_t *packed, *flags;
+    uint64_t* majors;
+    SPX_TRY(tmp.get(&val_out, (size_t)nnz, "values"));
+    SPX_TRY(tmp.get(&packed, (size_t)nnz, "packed indices"));
+    SPX_TRY(tmp.get(&flags, (size_t)nnz, "block flags"));
+    SPX_TRY(tmp.get(&majors, (size_t)nnz, "block keys"));
+    keep(tmp, A, val_out);
+    keep(tmp, A, packed);
+    A->val = val_out;
+    A->packed = packed;
+    int64_t nb = 0;
+    if (nnz > 0) {
+        HIP_TRY(launch_dedup_gather(se.keys, se.vals, E, se.head_tiles,
+                                    fmt == SPX_BCOHC ? 3 : 4, 2 * k, HotMap{}, (int32_t*)packed,
+                                    val_out, (int32_t*)flags, s, K2 + k, majors));
+        if (scan_tile_count(nnz) > tsn) {
+            SPX_TRY(tmp.get(&tsums, scan_tile_count(nnz), "scan tile sums"));
+            tsn = scan_tile_count(nnz);
+        }
+        HIP_TRY(launch_incl_scan_u32(flags, nnz, tsums, &rb_dev->totals[2], s));
+        SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+        nb = rb.totals[2];
+    }
+    int32_t *bptr, *bpart, *parts;
+    uint32_t* bcoord;
+    SPX_TRY(tmp.get(&bptr, (size_t)nb + 1, "block pointers"));
+    SPX_TRY(tmp.get(&bcoord, (size_t)nb + 1, "block coordinates"));
+    SPX_TRY(tmp.get(&bpart, (size_t)nb + 1, "block partitions"));
+    SPX_TRY(tmp.get(&parts, 2 * ((size_t)P + 1), "partition table"));
+    keep(tmp, A, bptr);
+    keep(tmp, A, bcoord);
+    keep(tmp, A, parts);
+    HIP_TRY(launch_bcoh_blocks(flags, majors, nnz, K2, bptr, bcoord, bpart, s));
+    HIP_TRY(launch_fill_i32(bptr + nb, 1, (int32_t)nnz, s));
+    HIP_TRY(hipMemcpyAsync(parts, part_row, ((size_t)P + 1) * 4, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_bcoh_part_blk(bpart, nb, P, parts + P + 1, s));
+    A->bh_part_row = parts;
+    A->bh_part_blk = parts + P + 1;
+    A->bh_nparts = P;
+    A->bh_blk_ptr = bptr;
+    A->bh_blk_coord = bcoord;
+    A->bh_nblocks = nb;
+    A->parts = P;
+    HIP_TRY(hipStreamSynchronize(s));
+    return SPX_OK;
+}
+
 static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
                                const spx_convert_opts* o, hipStream_t s, spx_matrix_s* A,
                                AllocSet& tmp) {
@@ -329,6 +421,20 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
     const int rbits = ceil_log2_u64((uint64_t)(m > 1 ? m : 1));
     int k = 0;
     int64_t nbr = 0, nbc = 0;
+    if (spx_is_bcoh(fmt)) {
+        k = o->log2_beta > 0 ? o->log2_beta : csbh_default_log2_beta(m, n);
+        if (k < 1 || k > 16)
+            return fail(SPX_ERR_INVALID_ARG, "log2_beta %d outside [1,16]", k);
+        nbr = ((int64_t)m + (1 << k) - 1) >> k;
+        nbc = ((int64_t)n + (1 << k) - 1) >> k;
+        const int K2 = ceil_log2_u64((uint64_t)std::max<int64_t>(1, std::max(nbr, nbc)));
+        if (K2 + k > 31) return fail(SPX_ERR_RANGE, "matrix too large for the Hilbert order");
+        A->log2_beta = k;
+        A->nbr = nbr;
+        A->nbc = nbc;
+        A->value_type = SPX_F64;
+        return convert_bcoh(coo, fmt, k, K2, s, A, tmp);
+    }
     if (spx_is_csb(fmt)) {
         k = o->log2_beta > 0 ? o->log2_beta : csbh_default_log2_beta(m, n);
         if (k < 1 || k > 16)
@@ -526,6 +632,7 @@ static int64_t sum_owned_bytes(const spx_matrix_s* A) {
     b += (A->val_lp ? A->nnz * (A->value_type == SPX_F32 ? 4 : 2) : 0);
     b += (A->blk_ptr ? (A->nbr * A->nbc + 1) * 4 : 0);
     b += (A->packed ? A->nnz * 4 : 0);
+    b += (A->bh_blk_ptr ? (A->bh_nblocks + 1) * 8 + 8 * ((int64_t)A->bh_nparts + 1) : 0);
     b += (A->mp_coords ? ((int64_t)A->mp_tiles + 1) * 8 + (int64_t)A->mp_tiles * 12 : 0);
     b += (A->rs_blocks ? ((int64_t)A->rs_nb + 1) * 4 : 0);
     b += (A->rs_long_rows ? (int64_t)A->rs_nlong * 8 + 4 + (int64_t)A->rs_nchunks * 8 : 0);
@@ -542,7 +649,7 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
     if (!out) return fail(SPX_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!coo) return fail(SPX_ERR_INVALID_ARG, "coo is NULL");
-    if (fmt != SPX_CSR_ROWSPLIT && fmt != SPX_CSR_MERGE && !spx_is_csb(fmt))
+    if (fmt != SPX_CSR_ROWSPLIT && fmt != SPX_CSR_MERGE && !spx_is_csb(fmt) && !spx_is_bcoh(fmt))
         return fail(SPX_ERR_INVALID_ARG, "unknown format %d", (int)fmt);
     if (coo->m < 0 || coo->n < 0 || coo->nnz < 0)
         return fail(SPX_ERR_INVALID_ARG, "negative size (m=%d n=%d nnz=%lld)", coo->m, coo->n,
@@ -567,8 +674,10 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
     if (o.hot_columns < -1) return fail(SPX_ERR_INVALID_ARG, "hot_columns < -1");
     if (o.value_type != SPX_F64 && o.value_type != SPX_F32 && o.value_type != SPX_BF16)
         return fail(SPX_ERR_INVALID_ARG, "unknown value_type %d", (int)o.value_type);
-    if (o.value_type != SPX_F64 && spx_is_csb(fmt))
+    if (o.value_type != SPX_F64 && (spx_is_csb(fmt) || spx_is_bcoh(fmt)))
         return fail(SPX_ERR_UNSUPPORTED, "reduced-precision values are built for the CRS formats");
+    if (spx_is_bcoh(fmt) && !o.sum_duplicates)
+        return fail(SPX_ERR_UNSUPPORTED, "BCOHC/BCOHCH are built with repeats summed");
     if (!spx_is_csb(fmt) && o.tile_items != 0)
         return fail(SPX_ERR_UNSUPPORTED, "tile_items is only adjustable for CSB/CSBH");
 
@@ -659,6 +768,8 @@ extern "C" spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* s
         case SPX_CSR_ROWSPLIT: HIP_TRY(spmv_rowsplit(A, x, y, s)); break;
         case SPX_CSB_HILBERT:
         case SPX_CSB_ZMORTON: HIP_TRY(spmv_csbh(A, x, y, s)); break;
+        case SPX_BCOHC:
+        case SPX_BCOHCH: HIP_TRY(spmv_bcoh(A, x, y, s)); break;
         default: return fail(SPX_ERR_INVALID_ARG, "corrupt handle");
     }
     return SPX_OK;
@@ -684,7 +795,7 @@ static spx_status grow_scratch(spx_matrix_s* A, void** p, size_t* have, size_t n
 extern "C" spx_status spx_spmm(spx_matrix A, int32_t k, const void* x, int64_t ldx, void* y,
                                int64_t ldy, spx_layout layout, void* stream) {
     if (!A) return fail(SPX_ERR_INVALID_ARG, "matrix handle is NULL");
-    if (spx_is_csb(A->fmt))
+    if (spx_is_csb(A->fmt) || spx_is_bcoh(A->fmt))
         return fail(SPX_ERR_UNSUPPORTED, "products with several right-hand sides are provided for "
                                          "the CRS formats");
     if (k < 1) return fail(SPX_ERR_INVALID_ARG, "k = %d, must be >= 1", k);
@@ -785,7 +896,8 @@ extern "C" spx_status spx_matrix_export(spx_matrix A, spx_array which, void* dst
     const void* src = nullptr;
     int64_t len = 0;
     bool exists = false;
-    const bool crs = !spx_is_csb(A->fmt);
+    const bool bcoh = spx_is_bcoh(A->fmt);
+    const bool crs = !spx_is_csb(A->fmt) && !bcoh;
     switch (which) {
         case SPX_ARRAY_ROW_PTR:
             exists = crs;
@@ -804,8 +916,13 @@ extern "C" spx_status spx_matrix_export(spx_matrix A, spx_array which, void* dst
             break;
         case SPX_ARRAY_BLK_PTR:
             exists = !crs;
-            src = A->blk_ptr;
-            len = (A->nbr * A->nbc + 1) * 4;
+            src = bcoh ? A->bh_blk_ptr : A->blk_ptr;
+            len = bcoh ? (A->bh_nblocks + 1) * 4 : (A->nbr * A->nbc + 1) * 4;
+            break;
+        case SPX_ARRAY_BLK_COORD:
+            exists = bcoh;
+            src = A->bh_blk_coord;
+            len = A->bh_nblocks * 4;
             break;
         case SPX_ARRAY_PACKED:
             exists = !crs;
@@ -820,6 +937,9 @@ extern "C" spx_status spx_matrix_export(spx_matrix A, spx_array which, void* dst
             } else if (A->fmt == SPX_CSR_ROWSPLIT) {
                 src = A->rs_blocks;
                 len = A->rs_blocks ? ((int64_t)A->rs_nb + 1) * 4 : 0;
+            } else if (bcoh) {
+                src = A->bh_part_row;
+                len = 8 * ((int64_t)A->bh_nparts + 1);
             } else {
                 src = A->cb_units;
                 len = (int64_t)A->cb_nunits * 16;

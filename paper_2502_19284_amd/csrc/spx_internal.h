@@ -53,6 +53,13 @@ struct spx_matrix_s {
     double* val = nullptr;       // nnz, FP64 matrices
     int32_t value_type = SPX_F64;  // stored value type
     void* val_lp = nullptr;      // nnz, FP32 or bfloat16 values of reduced-precision matrices
+    // BCOHC / BCOHCH
+    int32_t* bh_part_row = nullptr;   // P+1 first rows
+    int32_t* bh_part_blk = nullptr;   // P+1 first blocks (stored right after bh_part_row)
+    int32_t bh_nparts = 0;
+    int32_t* bh_blk_ptr = nullptr;    // nb+1
+    uint32_t* bh_blk_coord = nullptr; // nb, (block row << 16) | block column
+    int64_t bh_nblocks = 0;
     // CSBH
     int32_t* blk_ptr = nullptr;  // nbr*nbc+1
     uint32_t* packed = nullptr;  // nnz
@@ -177,10 +184,13 @@ size_t radix_hist_elems(int64_t E);
 hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_sums,
                               uint32_t* total, hipStream_t s);
 // Fused: scan of run heads (tile counts from launch_dedup_count) + run sums + index/value
-// output + row (block) end marks.  mode 0 CRS, 1 CSB Hilbert, 2 CSB Z-Morton.
+// output + row (block) end marks.  mode 0 CRS, 1 CSB Hilbert, 2 CSB Z-Morton; 3 BCOHC and
+// 4 BCOHCH (K = total Hilbert level of mode 4), where ends[u] receives 1 for an entry that starts
+// a block and 0 otherwise, and majors[u] the block key (key >> shiftbits) of block starts.
 hipError_t launch_dedup_gather(const uint64_t* keys, const double* vals, int64_t E,
                                const uint32_t* tile_sums, int mode, int shiftbits, HotMap hm,
-                               int32_t* idx_out, double* val_out, int32_t* ends, hipStream_t s);
+                               int32_t* idx_out, double* val_out, int32_t* ends, hipStream_t s,
+                               int K = 0, uint64_t* majors = nullptr);
 hipError_t launch_gather_csr(const uint64_t* keys, const double* vals, const int32_t* head_pos,
                              int64_t E, int64_t nnz_out, int cbits, HotMap hm, int32_t* col_out,
                              double* val_out, int32_t* row_end, hipStream_t s);
@@ -188,6 +198,34 @@ hipError_t launch_gather_csb(const uint64_t* keys, const double* vals, const int
                              int64_t E, int64_t nnz_out, int k, bool hilbert, uint32_t* packed_out,
                              double* val_out, int32_t* blk_end, hipStream_t s);
 static inline bool spx_is_csb(spx_format f) { return f == SPX_CSB_HILBERT || f == SPX_CSB_ZMORTON; }
+static inline bool spx_is_bcoh(spx_format f) { return f == SPX_BCOHC || f == SPX_BCOHCH; }
+
+// ------------------------------------------------------------------ BCOHC / BCOHCH
+#define BH_WINDOW 8192       // rows of one partition at most (its output slice lives in LDS)
+#define BH_PARTS_TARGET 2048 // partitions by entry count: target = max(2^16, ceil(E / this))
+// row counts of the raw triplets (validating every index; err set on a bad one)
+hipError_t launch_bcoh_rows(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+                            int32_t n, uint32_t* counts, uint32_t* err, hipStream_t s);
+// partitions from the exclusive row-count scan cum[0..m): part_of[r] for every row, part_row[p]
+// for every partition (part_row[P] = m written by the caller); *total = P
+hipError_t launch_bcoh_partitions(const uint32_t* cum, int32_t m, uint32_t target,
+                                  int32_t* part_of, int32_t* part_row, uint32_t* tile_sums,
+                                  uint32_t* total, hipStream_t s);
+hipError_t launch_keys_bcoh(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+                            int32_t n, const int32_t* part_of, int k, int K2, bool hilbert,
+                            uint64_t* keys, uint32_t* err, unsigned long long* masks,
+                            hipStream_t s);
+// block table from the block-head flags of the populate step (flags scanned in place into
+// inclusive counts) and the heads' block keys (partition << 2*K2 | Hilbert block index)
+hipError_t launch_bcoh_blocks(const uint32_t* incl, const uint64_t* majors, int64_t nnz, int K2,
+                              int32_t* blk_ptr, uint32_t* blk_coord, int32_t* blk_part,
+                              hipStream_t s);
+hipError_t launch_bcoh_part_blk(const int32_t* blk_part, int64_t nb, int32_t P,
+                                int32_t* part_blk, hipStream_t s);
+hipError_t launch_incl_scan_u32(uint32_t* a, int64_t n, uint32_t* tile_sums, uint32_t* total,
+                                hipStream_t s);
+hipError_t launch_excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n,
+                                uint32_t* tile_sums, uint32_t* total, hipStream_t s);
 // In-place inclusive max-scan of ends[0..len) (turns "end of last entry" marks into pointers).
 hipError_t launch_max_scan_i32(int32_t* ends, int64_t len, uint32_t* tile_sums, hipStream_t s);
 size_t scan_tile_count(int64_t n);
@@ -254,3 +292,4 @@ int32_t spmm_chunk_cols(int32_t k);
 hipError_t spmm_crs(const spx_matrix_s* A, const SpmmPlan& P, int32_t k, const void* x,
                     int64_t ldx, void* y, int64_t ldy, int row_major, hipStream_t s);
 hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
+hipError_t spmv_bcoh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);

@@ -18,7 +18,7 @@ import synth
 from oracle import curves, measure, spmv
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
-FMTS = ["rowsplit", "merge", "csbh"]
+FMTS = ["rowsplit", "merge", "csbh", "bcohc", "bcohch"]
 
 
 def say(*a):

@@ -10,10 +10,11 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import formats, measure, mergepath, spmv
+from oracle import bcoh, formats, measure, mergepath, spmv
 
 pytestmark = pytest.mark.gpu
-FMTS = ["rowsplit", "merge", "csbh", "csb"]
+FMTS = ["rowsplit", "merge", "csbh", "csb", "bcohc", "bcohch"]
+BCOH = ("bcohc", "bcohch")
 TOL = 1e-12
 
 
@@ -62,7 +63,15 @@ def _check_int(y, ref, what):
 
 def _check_structure(A, m, n, row, col, val):
     cr, cc, cv, _ = spmv.canonical_coo(m, n, row, col, val)
-    if A.format in ("csbh", "csb"):
+    if A.format in BCOH:
+        parts = A.export("parts").cpu().numpy()
+        P = A.parts
+        bcoh.check_bcoh(m, n, A.log2_beta, row, len(row), parts[:P + 1], parts[P + 1:],
+                        A.export("blk_ptr").cpu().numpy(),
+                        A.export("blk_coord").cpu().numpy().view(np.uint32),
+                        A.export("packed").cpu().numpy().view(np.uint32),
+                        A.export("values").cpu().numpy(), cr, cc, cv, A.format == "bcohch")
+    elif A.format in ("csbh", "csb"):
         formats.check_csb(m, n, A.log2_beta, A.export("blk_ptr").cpu().numpy(),
                           A.export("packed").cpu().numpy().view(np.uint32),
                           A.export("values").cpu().numpy(), cr, cc, cv,
@@ -237,6 +246,11 @@ def test_keep_repeats_option(spx, fmt):
     val = synth.values(len(row), seed=32, kind="int")
     x = synth.xvec(n, seed=33, kind="int")
     ref = spmv.reference(m, n, row, col, val, x)
+    if fmt in BCOH:  # built with repeats summed only
+        with pytest.raises(spx.SpxError) as e:
+            _run(spx, fmt, m, n, row, col, val, x, sum_duplicates=False)
+        assert e.value.status == -7
+        return
     A, y = _run(spx, fmt, m, n, row, col, val, x, sum_duplicates=False)
     assert A.nnz == len(row)
     _check_int(y, ref, "keep repeats " + fmt)
@@ -359,3 +373,27 @@ def test_report_and_info(spx, rmat14):
         assert A.nnz == len(d["float"][2]["col"])
         assert A.bytes >= A.nnz * 12
         assert A.parts > 0
+
+
+@pytest.mark.parametrize("fmt", BCOH)
+@pytest.mark.parametrize("log2_beta", [0, 3, 7])
+def test_bcoh_partitions_blocks_and_windows(spx, fmt, log2_beta):
+    # enough entries for several balance partitions, more rows than one window, a row longer than
+    # the balance target, empty rows, and block sizes from tiny to the default rule
+    rng = np.random.default_rng(12)
+    m, n = 20000, 9000
+    row = np.concatenate([rng.zipf(1.6, 200_000) % m, np.full(70_000, 12345), [m - 1]])
+    col = rng.integers(0, n, len(row))
+    row, col = row.astype(np.int32), col.astype(np.int32)
+    for kind in ("int", "float"):
+        val = synth.values(len(row), seed=13, kind=kind)
+        x = synth.xvec(n, seed=14, kind=kind)
+        ref = spmv.reference(m, n, row, col, val, x)
+        A, y = _run(spx, fmt, m, n, row, col, val, x, log2_beta=log2_beta)
+        say("  %s log2_beta %d: %d partitions" % (fmt, A.log2_beta, A.parts))
+        assert A.parts >= 4
+        if kind == "int":
+            _check_int(y, ref, fmt)
+        else:
+            _check_float(y, ref, fmt)
+        _check_structure(A, m, n, row, col, val)
