@@ -93,7 +93,7 @@ typedef struct {
     int32_t tile_items;     /* work per tile/unit; 0 = default for the format                  */
     int32_t hot_columns;    /* CRS formats: at most this many of the most frequent columns get a
                              * compact copy of their x values per product (x_hot); -1 = automatic
-                             * (up to 2^20 when n >= 2^19), 0 = off.  y is unchanged by it.      */
+                             * (up to 2^19 when n >= 2^19), 0 = off.  y is unchanged by it.      */
     spx_dtype value_type;   /* stored value type: SPX_F64 (default), or SPX_F32 / SPX_BF16 for
                              * the CRS formats (repeats are summed in FP64, then rounded once)   */
 } spx_convert_opts;

@@ -14,7 +14,8 @@ def build():
     """Compile liboracle.so (plain C, no contraction of multiply-add, no vector flags)."""
     tmp = LIB_PATH + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-                           "-shared", "-std=c11", os.path.join(_HERE, "ref.c"), "-o", tmp, "-lm"])
+                           "-fopenmp", "-shared", "-std=c11", os.path.join(_HERE, "ref.c"), "-o",
+                           tmp, "-lm"])
     os.replace(tmp, LIB_PATH)
 
 
@@ -33,6 +34,8 @@ def lib():
     L.ref_alg1.argtypes = [i64, p_i64, p_i32, p_f64, p_f64, p_f64]
     L.ref_alg1_accurate.argtypes = [i64, p_i64, p_i32, p_f64, p_f64, p_f64, p_f64, p_f64]
     L.ref_triplet_spmv.argtypes = [i64, p_i32, p_i32, p_f64, p_f64, i64, p_f64]
+    L.ref_parcrs.argtypes = [i64, p_i64, p_i32, p_f64, p_f64, p_f64, i64]
+    L.ref_parcrs.restype = ctypes.c_int
     for f in (L.ref_sum_runs, L.ref_alg1, L.ref_alg1_accurate, L.ref_triplet_spmv):
         f.restype = None
     _lib = L

@@ -9,6 +9,7 @@
  * written.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 
 /*
@@ -40,6 +41,28 @@ void ref_alg1(int64_t m, const int64_t* row_ptr, const int32_t* col_ind, const d
             y[i] = y[i] + data[k] * x[j];
         }
     }
+}
+
+/*
+ * ParCRS (Section 5.1): the rows of Algorithm 1 shared among OpenMP threads in dynamic chunks of
+ * `chunk` rows.  Each row is still summed by one thread in increasing k, so y equals Algorithm 1
+ * bit for bit; only the wall time changes.  Returns the number of threads used.
+ */
+int ref_parcrs(int64_t m, const int64_t* row_ptr, const int32_t* col_ind, const double* data,
+               const double* x, double* y, int64_t chunk) {
+    int used = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        used = omp_get_num_threads();
+#pragma omp for schedule(dynamic, chunk)
+        for (int64_t i = 0; i < m; ++i) {
+            double acc = 0.0;
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) acc = acc + data[k] * x[col_ind[k]];
+            y[i] = acc;
+        }
+    }
+    return used;
 }
 
 /*

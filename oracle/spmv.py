@@ -71,6 +71,17 @@ def alg1(row_ptr, col_ind, data, x):
     return y
 
 
+def parcrs(row_ptr, col_ind, data, x, chunk=512):
+    """ParCRS (Section 5.1): Algorithm 1 with rows shared among OpenMP threads in dynamic chunks;
+    every row is summed in the same order, so the result equals alg1 bit for bit.  Returns
+    (y, threads used)."""
+    m = len(row_ptr) - 1
+    y = np.empty(m)
+    used = lib().ref_parcrs(m, np.ascontiguousarray(row_ptr, np.int64), _i32(col_ind),
+                            _f64(data), _f64(x), y, int(chunk))
+    return y, used
+
+
 def alg1_accurate(row_ptr, col_ind, data, x):
     """Algorithm 1 plus the accurate reference: returns (y_plain, y_ref, scale).
 

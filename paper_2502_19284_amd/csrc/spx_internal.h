@@ -231,7 +231,7 @@ hipError_t launch_max_scan_i32(int32_t* ends, int64_t len, uint32_t* tile_sums, 
 size_t scan_tile_count(int64_t n);
 
 // ------------------------------------------------------------------ hot columns
-#define HOT_AUTO_MAX (1 << 20)
+#define HOT_AUTO_MAX (1 << 19)
 #define HOT_AUTO_MIN_N (1 << 19)
 #define HOT_MAX_SAMPLES (1 << 23)
 hipError_t launch_hot_count(const uint64_t* keys, int64_t E, int64_t stride, uint64_t cmask,

@@ -569,3 +569,19 @@ def test_bcoh_partitions_and_order():
             return (p, curves.hilbert_index(K2, r[i] >> k, c[i] >> k), r[i], c[i])
         want = sorted(range(len(r)), key=lambda i: (bkey(i), i))
         assert [bkey(i) for i in perm] == [bkey(i) for i in want]
+
+
+def test_parcrs_equals_algorithm1_bitwise():
+    # the row-parallel loop sums every row in the same order as Algorithm 1
+    rng = np.random.default_rng(6)
+    m, n, E = 5000, 4000, 60_000
+    row = rng.integers(0, m, E)
+    col = rng.integers(0, n, E)
+    val = rng.uniform(-1, 1, E)
+    x = rng.uniform(-1, 1, n)
+    rp, c, v = spmv.crs(m, n, row, col, val)
+    y1 = spmv.alg1(rp, c, v, x)
+    for chunk in (1, 7, 512):
+        y2, used = spmv.parcrs(rp, c, v, x, chunk)
+        assert used >= 1
+        assert np.array_equal(y1.view(np.int64), y2.view(np.int64))
