@@ -279,6 +279,18 @@ static hipError_t spmm_t(const spx_matrix_s* A, const SpmmPlan& P, const V* val,
         const int32_t kc = min((int32_t)MM_KMAX, k - c0);
         int kp = 1;
         while (kp < kc) kp <<= 1;
+        if (kc == 1) {
+            // one column held contiguously in X and Y: the single-vector merge-path product on
+            // the plan's tiles and scratch (its LDS-staged products keep more gathers in flight
+            // than a one-lane group walk, and nothing needs staging)
+            const X* x1 = row_major ? (ldx == 1 ? x + c0 : nullptr) : x + (int64_t)c0 * ldx;
+            X* y1 = row_major ? (ldy == 1 ? y + c0 : nullptr) : y + (int64_t)c0 * ldy;
+            if (x1 && y1) {
+                const hipError_t e = spmv_merge_on_plan(A, P, x1, y1, s);
+                if (e != hipSuccess) return e;
+                continue;
+            }
+        }
         const X* xr;
         int64_t ldr;
         if (row_major) {

@@ -206,17 +206,46 @@ static hipError_t hot_gather(const spx_matrix_s* A, const X* x, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The merge-path product on explicit tiles, carries and hot-x scratch (the handle's own for
+// spmv, a caller's plan for the one-column product of spx_spmm).
+template <typename V, typename X, typename ACC>
+static hipError_t merge_run(const spx_matrix_s* A, const V* val, const X* x, X* y,
+                            const int2* coords, int32_t tiles, int32_t* crow, double* cval,
+                            X* x_hot, hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    if (A->nhot > 0)
+        SPX_LAUNCH("hot_gather", k_hot_gather_t<X>, dim3(spx_div_up(A->nhot, 256)), dim3(256), 0,
+                   s, A->hot_cols, A->nhot, x, x_hot);
+    SPX_LAUNCH("spmv_merge", (k_spmv_merge<V, X, ACC>), dim3(tiles), dim3(MP_NT), 0, s,
+               A->row_ptr, A->col, val, x, (const X*)x_hot, y, coords, crow, cval);
+    SPX_LAUNCH("spmv_merge_fixup", k_spmv_merge_fixup<X>, dim3(spx_div_up(tiles, 256)),
+               dim3(256), 0, s, crow, cval, tiles, y, A->m);
+    return hipGetLastError();
+}
+
 template <typename V, typename X, typename ACC>
 static hipError_t merge_t(const spx_matrix_s* A, const V* val, const X* x, X* y, hipStream_t s) {
-    if (A->mp_tiles <= 0) return hipSuccess;
-    hipError_t e = hot_gather<X>(A, x, s);
-    if (e != hipSuccess) return e;
-    SPX_LAUNCH("spmv_merge", (k_spmv_merge<V, X, ACC>), dim3(A->mp_tiles), dim3(MP_NT), 0, s,
-               A->row_ptr, A->col, val, x, (const X*)A->x_hot, y, A->mp_coords, A->mp_carry_row,
-               A->mp_carry_val);
-    SPX_LAUNCH("spmv_merge_fixup", k_spmv_merge_fixup<X>, dim3(spx_div_up(A->mp_tiles, 256)),
-               dim3(256), 0, s, A->mp_carry_row, A->mp_carry_val, A->mp_tiles, y, A->m);
-    return hipGetLastError();
+    return merge_run<V, X, ACC>(A, val, x, y, A->mp_coords, A->mp_tiles, A->mp_carry_row,
+                                A->mp_carry_val, (X*)A->x_hot, s);
+}
+
+hipError_t spmv_merge_on_plan(const spx_matrix_s* A, const SpmmPlan& P, const void* x, void* y,
+                              hipStream_t s) {
+    switch (A->value_type) {
+        case SPX_F64:
+            return merge_run<double, double, double>(A, A->val, (const double*)x, (double*)y,
+                                                     P.coords, P.tiles, P.carry_row, P.carry_val,
+                                                     (double*)P.h, s);
+        case SPX_F32:
+            return merge_run<float, float, float>(A, (const float*)A->val_lp, (const float*)x,
+                                                  (float*)y, P.coords, P.tiles, P.carry_row,
+                                                  P.carry_val, (float*)P.h, s);
+        default:
+            return merge_run<uint16_t, float, float>(A, (const uint16_t*)A->val_lp,
+                                                     (const float*)x, (float*)y, P.coords,
+                                                     P.tiles, P.carry_row, P.carry_val,
+                                                     (float*)P.h, s);
+    }
 }
 
 // ================================================================== row-split CRS

@@ -289,6 +289,10 @@ struct SpmmPlan {
     void* h = nullptr;            // nhot x chunk
 };
 int32_t spmm_chunk_cols(int32_t k);
+// y = A x with the single-vector merge-path kernels on the plan's tiles and scratch (P.h holds the
+// hot x copy); used for one-column products on contiguous vectors
+hipError_t spmv_merge_on_plan(const spx_matrix_s* A, const SpmmPlan& P, const void* x, void* y,
+                              hipStream_t s);
 hipError_t spmm_crs(const spx_matrix_s* A, const SpmmPlan& P, int32_t k, const void* x,
                     int64_t ldx, void* y, int64_t ldy, int row_major, hipStream_t s);
 hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
