@@ -254,22 +254,23 @@ hipError_t spmv_merge_on_plan(const spx_matrix_s* A, const SpmmPlan& P, const vo
 // <= RS_ROWS rows) stages its products in LDS with coalesced loads; then groups of g lanes
 // (g = largest power of two <= 64 with rows*g <= RS_NT) each reduce one row at a time, with a
 // shuffle tree inside the group.  Rows longer than RS_LONG are blocks on their own and are skipped
-// here: their RS_CHUNK-entry chunks are summed (in FP64) by k_spmv_rowsplit_long and the chunk
-// sums added in chunk order by k_spmv_rowsplit_finish.
+// there: their RS_CHUNK-entry chunks are summed (in FP64) by other workgroups of the same launch
+// and the chunk sums added in chunk order by k_spmv_rowsplit_finish.
 
 template <typename V, typename X, typename ACC>
-__global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit(
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-    const V* __restrict__ val, const X* __restrict__ x, const X* __restrict__ x_hot,
-    X* __restrict__ y, const int32_t* __restrict__ blocks) {
-    __shared__ ACC s_prod[RS_NNZ];
-    __shared__ int32_t s_rp[RS_ROWS + 1];
+__device__ __forceinline__ void rowsplit_block(const int32_t* __restrict__ row_ptr,
+                                               const int32_t* __restrict__ col,
+                                               const V* __restrict__ val,
+                                               const X* __restrict__ x,
+                                               const X* __restrict__ x_hot, X* __restrict__ y,
+                                               const int32_t* __restrict__ blocks, int b,
+                                               ACC* s_prod, int32_t* s_rp) {
     const int tid = threadIdx.x;
-    const int rs = blocks[blockIdx.x], re = blocks[blockIdx.x + 1];
+    const int rs = blocks[b], re = blocks[b + 1];
     const int rows = re - rs;
     const int base = row_ptr[rs];
     const int nnzb = row_ptr[re] - base;
-    if (rows == 1 && nnzb > RS_LONG) return;  // long row: chunk kernels
+    if (rows == 1 && nnzb > RS_LONG) return;  // long row: chunk path
     const bool staged = nnzb <= RS_NNZ && rows <= RS_ROWS;
     if (staged) {
         for (int i = tid; i <= rows; i += RS_NT) s_rp[i] = ntload(row_ptr + rs + i) - base;
@@ -288,11 +289,11 @@ __global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit(
     for (int r = grp; r < rows; r += ngrp) {
         ACC acc = 0;
         if (staged) {
-            const int a = s_rp[r], b = s_rp[r + 1];
-            for (int k = a + gl; k < b; k += g) acc += s_prod[k];
+            const int a = s_rp[r], b2 = s_rp[r + 1];
+            for (int k = a + gl; k < b2; k += g) acc += s_prod[k];
         } else {
-            const int a = row_ptr[rs + r], b = row_ptr[rs + r + 1];
-            for (int k = a + gl; k < b; k += g)
+            const int a = row_ptr[rs + r], b2 = row_ptr[rs + r + 1];
+            for (int k = a + gl; k < b2; k += g)
                 acc += (ACC)vget_plain(val + k) * (ACC)xval(x, x_hot, col[k]);
         }
         for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, SPX_WAVE);
@@ -301,13 +302,15 @@ __global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit(
 }
 
 template <typename V, typename X>
-__global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit_long(
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-    const V* __restrict__ val, const X* __restrict__ x, const X* __restrict__ x_hot,
-    const int32_t* __restrict__ long_rows, const int32_t* __restrict__ chunk_ptr, int32_t nlong,
-    double* __restrict__ partials) {
-    __shared__ double s_tmp[RS_NT / SPX_WAVE];
-    const int c = blockIdx.x;
+__device__ __forceinline__ void rowsplit_chunk(const int32_t* __restrict__ row_ptr,
+                                               const int32_t* __restrict__ col,
+                                               const V* __restrict__ val,
+                                               const X* __restrict__ x,
+                                               const X* __restrict__ x_hot,
+                                               const int32_t* __restrict__ long_rows,
+                                               const int32_t* __restrict__ chunk_ptr,
+                                               int32_t nlong, double* __restrict__ partials,
+                                               int c, double* s_tmp) {
     // the long row that owns chunk c: last j with chunk_ptr[j] <= c
     int lo = 0, hi = nlong - 1;
     while (lo < hi) {
@@ -332,6 +335,27 @@ __global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit_long(
     if (threadIdx.x == 0) partials[c] = sum;
 }
 
+// One launch for both kinds of work: workgroups [0, nchunks) sum the long rows' chunks (the
+// heavier items first), the rest take the row blocks.
+template <typename V, typename X, typename ACC>
+__global__ __launch_bounds__(RS_NT) void k_spmv_rowsplit(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const V* __restrict__ val, const X* __restrict__ x, const X* __restrict__ x_hot,
+    X* __restrict__ y, const int32_t* __restrict__ blocks, const int32_t* __restrict__ long_rows,
+    const int32_t* __restrict__ chunk_ptr, int32_t nlong, int32_t nchunks,
+    double* __restrict__ partials) {
+    __shared__ ACC s_prod[RS_NNZ];
+    __shared__ int32_t s_rp[RS_ROWS + 1];
+    __shared__ double s_tmp[RS_NT / SPX_WAVE];
+    const int b = blockIdx.x;
+    if (b < nchunks)
+        rowsplit_chunk<V, X>(row_ptr, col, val, x, x_hot, long_rows, chunk_ptr, nlong, partials, b,
+                             s_tmp);
+    else
+        rowsplit_block<V, X, ACC>(row_ptr, col, val, x, x_hot, y, blocks, b - nchunks, s_prod,
+                                  s_rp);
+}
+
 template <typename X>
 __global__ void k_spmv_rowsplit_finish(const int32_t* __restrict__ long_rows,
                                        const int32_t* __restrict__ chunk_ptr, int32_t nlong,
@@ -348,13 +372,13 @@ static hipError_t rowsplit_t(const spx_matrix_s* A, const V* val, const X* x, X*
                              hipStream_t s) {
     hipError_t e = hot_gather<X>(A, x, s);
     if (e != hipSuccess) return e;
-    if (A->rs_nb > 0)
-        SPX_LAUNCH("spmv_rowsplit", (k_spmv_rowsplit<V, X, ACC>), dim3(A->rs_nb), dim3(RS_NT), 0,
-                   s, A->row_ptr, A->col, val, x, (const X*)A->x_hot, y, A->rs_blocks);
+    const int32_t nchunks = A->rs_nlong > 0 ? A->rs_nchunks : 0;
+    if (A->rs_nb + nchunks > 0)
+        SPX_LAUNCH("spmv_rowsplit", (k_spmv_rowsplit<V, X, ACC>), dim3(A->rs_nb + nchunks),
+                   dim3(RS_NT), 0, s, A->row_ptr, A->col, val, x, (const X*)A->x_hot, y,
+                   A->rs_blocks, A->rs_long_rows, A->rs_chunk_ptr, A->rs_nlong, nchunks,
+                   A->rs_partials);
     if (A->rs_nlong > 0) {
-        SPX_LAUNCH("spmv_rowsplit_long", (k_spmv_rowsplit_long<V, X>), dim3(A->rs_nchunks),
-                   dim3(RS_NT), 0, s, A->row_ptr, A->col, val, x, (const X*)A->x_hot,
-                   A->rs_long_rows, A->rs_chunk_ptr, A->rs_nlong, A->rs_partials);
         SPX_LAUNCH("spmv_rowsplit_finish", k_spmv_rowsplit_finish<X>,
                    dim3(spx_div_up(A->rs_nlong, 256)), dim3(256), 0, s, A->rs_long_rows,
                    A->rs_chunk_ptr, A->rs_nlong, A->rs_partials, y);
