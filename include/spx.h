@@ -169,6 +169,9 @@ spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt, const spx_conver
  * x: device, n doubles.  y: device, m doubles.  x and y must not overlap (SPX_ERR_ALIAS).
  * Asynchronous on `stream`.  A handle holds per-product scratch, so at most one product per
  * handle may be in flight at a time; products on different handles may overlap freely.
+ * Summation order: fixed for the CRS formats (repeated products are bitwise identical); the block
+ * formats (CSB, CSBH, BCOHC, BCOHCH) add products into an on-chip slice of y with float atomics,
+ * so their last bits may differ from run to run (always within the row-scaled 1e-12 bound).
  */
 spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* stream);
 
