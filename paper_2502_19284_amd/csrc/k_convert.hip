@@ -187,11 +187,22 @@ hipError_t launch_keys_bcoh(const int32_t* row, const int32_t* col, int64_t E, i
 // 64 consecutive keys; lanes holding the same digit find each other with 8 ballots (one per
 // digit bit) and rank by lower-lane count; a per-wave LDS counter per digit carries the running
 // count across rounds.  Wave offsets are then added per digit in wave order.
+// Both kernels visit tiles in the XCD-contiguous order of rs_tile_of.
 
 #define RSORT_WAVES (RSORT_NT / SPX_WAVE)
 #define RSORT_ROUNDS (RSORT_TILE / RSORT_WAVES / SPX_WAVE)
 
 size_t radix_hist_elems(int64_t E) { return (size_t)256 * spx_div_up(E, RSORT_TILE); }
+
+// Tile of workgroup b.  Workgroups are dealt to the 8 XCDs in turn (b mod 8); here each XCD takes
+// one contiguous range of tiles instead, so neighbouring tiles, which share histogram lines and
+// the partial lines at the ends of their output runs, go through one L2.  A bijection onto
+// [0, tiles) for any tile count.
+__device__ __forceinline__ int64_t rs_tile_of(int64_t b, int64_t tiles) {
+    const int64_t q = tiles >> 3, r = tiles & 7;
+    const int64_t x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
 
 __global__ __launch_bounds__(RSORT_NT) void k_rsort_upsweep(const uint64_t* __restrict__ keys,
                                                             int64_t E, int shift,
@@ -201,7 +212,8 @@ __global__ __launch_bounds__(RSORT_NT) void k_rsort_upsweep(const uint64_t* __re
     for (int i = threadIdx.x; i < RSORT_WAVES * 256; i += RSORT_NT) (&cnt[0][0])[i] = 0;
     __syncthreads();
     const int w = threadIdx.x / SPX_WAVE;
-    const int64_t base = (int64_t)blockIdx.x * RSORT_TILE;
+    const int64_t tile = rs_tile_of(blockIdx.x, tiles);
+    const int64_t base = tile * RSORT_TILE;
 #pragma unroll
     for (int i = 0; i < RSORT_IPT; ++i) {
         const int64_t idx = base + i * RSORT_NT + threadIdx.x;
@@ -211,7 +223,7 @@ __global__ __launch_bounds__(RSORT_NT) void k_rsort_upsweep(const uint64_t* __re
     uint32_t c = 0;
 #pragma unroll
     for (int ww = 0; ww < RSORT_WAVES; ++ww) c += cnt[ww][threadIdx.x];
-    hist[(int64_t)threadIdx.x * tiles + blockIdx.x] = c;
+    hist[(int64_t)threadIdx.x * tiles + tile] = c;
 }
 
 __global__ __launch_bounds__(RSORT_NT) void k_rsort_downsweep(
@@ -230,7 +242,8 @@ __global__ __launch_bounds__(RSORT_NT) void k_rsort_downsweep(
     for (int i = tid; i < RSORT_WAVES * 256; i += RSORT_NT) (&wcnt[0][0])[i] = 0;
     __syncthreads();
 
-    const int64_t tile_base = (int64_t)blockIdx.x * RSORT_TILE;
+    const int64_t tile = rs_tile_of(blockIdx.x, tiles);
+    const int64_t tile_base = tile * RSORT_TILE;
     const int64_t wave_base = tile_base + (int64_t)w * (RSORT_TILE / RSORT_WAVES);
     const uint64_t lt = spx_lanemask_lt();
     uint64_t key[RSORT_ROUNDS];
@@ -268,7 +281,7 @@ __global__ __launch_bounds__(RSORT_NT) void k_rsort_downsweep(
     uint32_t tile_total;
     const uint32_t ex = block_excl_scan<RSORT_NT, uint32_t, OpSum<uint32_t>>(run, stmp, &tile_total);
     dstart[tid] = ex;
-    goff[tid] = hist[(int64_t)tid * tiles + blockIdx.x];
+    goff[tid] = hist[(int64_t)tid * tiles + tile];
     __syncthreads();
     const int64_t rem = E - tile_base;
     const int cnt = rem < RSORT_TILE ? (int)rem : RSORT_TILE;
