@@ -449,13 +449,37 @@ hipError_t launch_gather_csb(const uint64_t* keys, const double* vals, const int
 // Fused repeat summing + populate.  Workgroup b owns the sorted positions of scan tile b (the
 // same SCAN_TILE tiling as launch_dedup_count, whose scanned tile counts give each tile's first
 // output index).  The tile's keys are staged in LDS and every item's value is loaded up front;
-// run heads are ranked by ballots in strided item order; then each head sums its run in increasing
-// position
-// (= increasing triplet index, the sort being stable), writes its index and value, and marks the
-// end of its row (block) for the max-scan.
+// run heads are ranked by ballots in strided item order (each ballot covers 64 consecutive
+// positions, so the ballots also form the tile's head bitmap).  Each head writes its index and
+// marks the end of its row (block) for the max-scan; its value is the run's sum in increasing
+// position (= increasing triplet index, the sort being stable), formed strictly left to right:
+//   * a run of at most DG_SHORT entries that ends inside the tile is summed by its head thread
+//     (loads issued four at a time ahead of the additions);
+//   * every other run (longer, or reaching past the tile) is summed by one wave: 64 positions are
+//     loaded at a time and one chain of additions walks them in order, up to the end of the run,
+//     wherever that is.
+// So a run of length L costs O(L) chained additions on one wave and O(L / 64) loads.
 #define DG_NT SCAN_NT
 #define DG_IPT SCAN_IPT
 #define DG_TILE SCAN_TILE
+#define DG_SHORT 16
+#define DG_LONG_MAX 256
+static_assert(DG_TILE / (DG_SHORT + 1) + 1 <= DG_LONG_MAX, "list of the tile's long runs");
+static_assert(DG_TILE == DG_IPT * DG_NT && DG_NT % SPX_WAVE == 0, "tile layout");
+
+__device__ __forceinline__ double dg_lane(double v, int k) {  // v of lane k (k wave-uniform)
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+
+template <int MODE>
+__device__ __forceinline__ void dg_mark_end(int32_t* ends, uint64_t key, int shiftbits, int64_t u,
+                                            bool more, uint64_t next) {
+    if (MODE >= 3) return;  // block starts are marked by the head
+    const uint64_t major = key >> shiftbits;
+    if (!more || (next >> shiftbits) != major) ends[major] = (int32_t)(u + 1);
+}
 
 template <int MODE>
 __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
@@ -464,8 +488,12 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
     int32_t* __restrict__ idx_out, double* __restrict__ val_out, int32_t* __restrict__ ends,
     int K, uint64_t* __restrict__ majors) {
     constexpr int NW = DG_NT / SPX_WAVE;
+    constexpr int NWORDS = DG_TILE / SPX_WAVE;
     __shared__ uint64_t s_key[DG_TILE + 1];  // s_key[i+1] = keys[base+i]
     __shared__ uint32_t s_pre[DG_IPT][NW];   // heads before (row j, wave w) within the tile
+    __shared__ uint64_t s_hb[NWORDS];        // head bitmap: bit i & 63 of word i >> 6
+    __shared__ uint32_t s_long_i[DG_LONG_MAX], s_long_u[DG_LONG_MAX];
+    __shared__ uint32_t s_nlong;
     const int tid = threadIdx.x;
     const int w = tid / SPX_WAVE;
     const int lane = __lane_id();
@@ -480,7 +508,10 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
         if (i < cnt) s_key[i + 1] = keys[base + i];
         v[j] = i < cnt ? vals[base + i] : 0.0;
     }
-    if (tid == 0) s_key[0] = base > 0 ? keys[base - 1] : ~keys[0];  // position 0 is a head
+    if (tid == 0) {
+        s_key[0] = base > 0 ? keys[base - 1] : ~keys[0];  // position 0 is a head
+        s_nlong = 0;
+    }
     __syncthreads();
     // output index of each head: heads are ranked in item order i = tid + j * DG_NT, so a
     // ballot per (row j, wave) and a prefix over the DG_IPT x NW wave counts suffice
@@ -494,7 +525,10 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
         const uint64_t bal = __ballot(head);
         rank[j] = (uint32_t)__popcll(bal & lt);
         heads |= (head ? 1u : 0u) << j;
-        if (lane == 0) s_pre[j][w] = (uint32_t)__popcll(bal);
+        if (lane == 0) {
+            s_pre[j][w] = (uint32_t)__popcll(bal);
+            s_hb[j * NW + w] = bal;  // positions [j * DG_NT + 64 w, +64)
+        }
     }
     __syncthreads();
     if (tid == 0) {
@@ -514,20 +548,33 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
         const int i = tid + j * DG_NT;
         const uint64_t key = s_key[i + 1];
         const int64_t u = s_pre[j][w] + rank[j];
-        double acc = v[j];
-        int64_t e = i + 1;  // tile-relative position after the run
-        uint64_t next = 0;
-        bool more = false;
-        while (base + e < E) {
-            next = e < cnt ? s_key[e + 1] : keys[base + e];
-            if (next != key) {
-                more = true;
-                break;
-            }
-            acc = acc + vals[base + e];
-            ++e;
+        // end of the run inside the tile: the next head, else the tile's end
+        int e = cnt;
+        {
+            int wi = i >> 6;
+            uint64_t b = (i & 63) == 63 ? 0ull : s_hb[wi] & (~0ull << ((i & 63) + 1));
+            while (b == 0ull && ++wi < NWORDS) b = s_hb[wi];
+            if (b != 0ull) e = wi * 64 + __builtin_ctzll(b);
         }
-        val_out[u] = acc;
+        const bool more = base + e < E;
+        const uint64_t next = e < cnt ? s_key[e + 1] : (more ? keys[base + e] : 0ull);
+        if ((!more || next != key) && e - i <= DG_SHORT) {
+            double acc = v[j];
+            for (int q0 = i + 1; q0 < e; q0 += 4) {  // four loads in flight, then add in order
+                double t[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) t[q] = q0 + q < e ? vals[base + q0 + q] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q0 + q < e) acc = acc + t[q];
+            }
+            val_out[u] = acc;
+            dg_mark_end<MODE>(ends, key, shiftbits, u, more, next);
+        } else {
+            const uint32_t slot = atomicAdd(&s_nlong, 1u);
+            s_long_i[slot] = (uint32_t)i;
+            s_long_u[slot] = (uint32_t)u;
+        }
         const uint64_t major = key >> shiftbits;
         const uint32_t d = (uint32_t)(key & lowmask);
         if (MODE >= 3) {  // BCOHC / BCOHCH: packed local position, block-start flag
@@ -547,9 +594,7 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
             const bool bstart = (s_key[i] >> shiftbits) != major;
             ends[u] = bstart ? 1 : 0;
             if (bstart) majors[u] = major;
-            continue;
-        }
-        if (MODE != 0) {
+        } else if (MODE != 0) {
             const int k = shiftbits >> 1;
             uint32_t lc, lr;
             if (MODE == 1) hilbert_d2xy(k, d, &lc, &lr);
@@ -558,7 +603,47 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
         } else {
             idx_out[u] = hm.map(d);
         }
-        if (!more || (next >> shiftbits) != major) ends[major] = (int32_t)(u + 1);
+    }
+    __syncthreads();
+    // the tile's long runs, one wave each: chunks of 64 positions, one chain of additions
+    const uint32_t nlong = s_nlong;
+    for (uint32_t r = w; r < nlong; r += NW) {
+        const int64_t p0 = base + s_long_i[r];
+        const int64_t u = s_long_u[r];
+        const uint64_t key = s_key[s_long_i[r] + 1];
+        int64_t p = p0;
+        uint64_t kc = p + lane < E ? keys[p + lane] : ~key;
+        double vc = p + lane < E ? vals[p + lane] : 0.0;
+        double acc = dg_lane(vc, 0);  // position p0 is the head itself
+        int k0 = 1;
+        bool more;
+        uint64_t next;
+        for (;;) {
+            const uint64_t match = __ballot(kc == key);
+            const int n1 = ~match == 0ull ? 64 : __builtin_ctzll(~match);  // leading run lanes
+            uint64_t kn = ~key;
+            double vn = 0.0;
+            if (n1 == 64) {  // the run fills the chunk: fetch the next one before adding
+                kn = p + 64 + lane < E ? keys[p + 64 + lane] : ~key;
+                vn = p + 64 + lane < E ? vals[p + 64 + lane] : 0.0;
+            }
+            for (int k = k0; k < n1; ++k) acc = acc + dg_lane(vc, k);
+            k0 = 0;
+            if (n1 < 64) {
+                more = p + n1 < E;
+                const int lo = __builtin_amdgcn_readlane((int)(uint32_t)kc, n1);
+                const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(kc >> 32), n1);
+                next = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+                break;
+            }
+            p += 64;
+            kc = kn;
+            vc = vn;
+        }
+        if (lane == 0) {
+            val_out[u] = acc;
+            dg_mark_end<MODE>(ends, key, shiftbits, u, more, next);
+        }
     }
 }
 
