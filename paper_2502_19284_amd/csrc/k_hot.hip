@@ -13,22 +13,55 @@
 #include "dev_scan.h"
 #include "spx_internal.h"
 
-// sampled column frequencies from the sorted keys: every `stride`-th key, column = key & cmask
-__global__ void k_hot_count(const uint64_t* __restrict__ keys, int64_t E, int64_t stride,
-                            uint64_t cmask, uint32_t* __restrict__ freq) {
-    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride; i < E;
-         i += (int64_t)gridDim.x * blockDim.x * stride)
-        atomicAdd(&freq[keys[i] & cmask], 1u);
+// Sampled column frequencies.  Sample s is the column of sorted key (s / HOT_RUN) * HOT_RUN *
+// stride + s % HOT_RUN (stride 1: key s), i.e. runs of HOT_RUN consecutive keys, one run per
+// HOT_RUN * stride keys.  The samples are sorted by column (radix sort) and each wave adds the
+// length of every run of equal columns among its 64 positions with one atomic, so a hot column
+// costs one atomic per wave that holds it instead of one per sample.
+__global__ void k_hot_sample(const uint64_t* __restrict__ keys, int64_t stride, int64_t ns,
+                             uint64_t cmask, uint64_t* __restrict__ S) {
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < ns;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = stride == 1 ? s : (s / HOT_RUN) * HOT_RUN * stride + s % HOT_RUN;
+        S[s] = keys[i] & cmask;
+    }
 }
 
-hipError_t launch_hot_count(const uint64_t* keys, int64_t E, int64_t stride, uint64_t cmask,
-                            uint32_t* freq, hipStream_t s) {
-    if (E <= 0) return hipSuccess;
-    int64_t samples = (E + stride - 1) / stride;
-    int64_t g = (samples + 255) / 256;
-    if (g > 8192) g = 8192;
-    SPX_LAUNCH("hot_count", k_hot_count, dim3((unsigned)g), dim3(256), 0, s, keys, E, stride,
-               cmask, freq);
+hipError_t launch_hot_sample(const uint64_t* keys, int64_t stride, int64_t ns, uint64_t cmask,
+                             uint64_t* S, hipStream_t s) {
+    if (ns <= 0) return hipSuccess;
+    const int64_t g = spx_div_up(ns, 256) < 8192 ? spx_div_up(ns, 256) : 8192;
+    SPX_LAUNCH("hot_sample", k_hot_sample, dim3((unsigned)g), dim3(256), 0, s, keys, stride, ns,
+               cmask, S);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_hot_count_sorted(const uint64_t* __restrict__ S,
+                                                          int64_t ns,
+                                                          uint32_t* __restrict__ freq) {
+    const int lane = __lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / SPX_WAVE;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / SPX_WAVE;
+    for (int64_t c0 = wave * SPX_WAVE; c0 < ns; c0 += nwaves * SPX_WAVE) {
+        const int64_t p = c0 + lane;
+        const bool valid = p < ns;
+        const uint64_t c = valid ? S[p] : 0ull;
+        const bool start = valid && (lane == 0 || S[p - 1] != c);
+        const uint64_t starts = __ballot(start);
+        const int nvalid = (int)__popcll(__ballot(valid));  // valid lanes form a prefix
+        if (start) {
+            const uint64_t above = lane == SPX_WAVE - 1 ? 0ull : starts >> (lane + 1);
+            int next = above ? lane + 1 + __builtin_ctzll(above) : SPX_WAVE;
+            if (next > nvalid) next = nvalid;
+            atomicAdd(&freq[c], (uint32_t)(next - lane));
+        }
+    }
+}
+
+hipError_t launch_hot_count_sorted(const uint64_t* S, int64_t ns, uint32_t* freq, hipStream_t s) {
+    if (ns <= 0) return hipSuccess;
+    const int64_t g = spx_div_up(ns, 256) < 8192 ? spx_div_up(ns, 256) : 8192;
+    SPX_LAUNCH("hot_count", k_hot_count_sorted, dim3((unsigned)g), dim3(256), 0, s, S, ns, freq);
     return hipGetLastError();
 }
 

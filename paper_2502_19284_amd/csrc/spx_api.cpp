@@ -265,8 +265,30 @@ static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot
     SPX_TRY(tmp.get(&bits, (size_t)nwords, "hot bitmap"));
     SPX_TRY(tmp.get(&pre, (size_t)nwords, "hot word prefixes"));
     HIP_TRY(hipMemsetAsync(freq, 0, (size_t)n * 4, s));
+    // samples: runs of HOT_RUN consecutive keys, one run per HOT_RUN * stride keys
     const int64_t stride = E > HOT_MAX_SAMPLES ? (E + HOT_MAX_SAMPLES - 1) / HOT_MAX_SAMPLES : 1;
-    HIP_TRY(launch_hot_count(keys, E, stride, cmask, freq, s));
+    int64_t ns = E;
+    if (stride > 1) {
+        const int64_t span = HOT_RUN * stride, runs = (E + span - 1) / span;
+        const int64_t last = E - (runs - 1) * span;
+        ns = (runs - 1) * HOT_RUN + (last < HOT_RUN ? last : HOT_RUN);
+    }
+    {
+        uint64_t *s0, *s1, *p0, *p1;
+        uint32_t *shist, *stsums;
+        SPX_TRY(tmp.get(&s0, (size_t)ns, "column samples"));
+        SPX_TRY(tmp.get(&s1, (size_t)ns, "column samples"));
+        SPX_TRY(tmp.get(&p0, (size_t)ns, "column samples"));
+        SPX_TRY(tmp.get(&p1, (size_t)ns, "column samples"));
+        const size_t hn = radix_hist_elems(ns);
+        SPX_TRY(tmp.get(&shist, hn, "radix histogram"));
+        SPX_TRY(tmp.get(&stsums, scan_tile_count((int64_t)hn), "scan tile sums"));
+        HIP_TRY(launch_hot_sample(keys, stride, ns, cmask, s0, s));
+        const uint64_t *sorted, *unused;
+        HIP_TRY(radix_sort_pairs(s0, p0, s1, p1, s0, ns, cmask, shist, stsums, s, &sorted,
+                                 &unused));
+        HIP_TRY(launch_hot_count_sorted(sorted, ns, freq, s));
+    }
     Readback rb;
     auto count_ge = [&](uint32_t tau, uint32_t* out) -> spx_status {
         HIP_TRY(launch_hot_count_ge(freq, n, tau, tsums, &rb_dev->totals[3], s));
@@ -291,7 +313,7 @@ static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot
         tau = (uint32_t)t;
     }
     if (tau == 0) {  // even count_ge(HOT_HIST_BINS - 1) exceeds hot_max
-        uint64_t lo = HOT_HIST_BINS, hi = (uint64_t)((E + stride - 1) / stride) + 1;
+        uint64_t lo = HOT_HIST_BINS, hi = (uint64_t)ns + 1;  // no column has more than ns
         if (hi < lo) hi = lo;  // count_ge(hi) == 0
         while (lo < hi) {
             const uint64_t mid = (lo + hi) / 2;

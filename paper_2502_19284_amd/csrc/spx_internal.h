@@ -234,8 +234,12 @@ size_t scan_tile_count(int64_t n);
 #define HOT_AUTO_MAX (1 << 19)
 #define HOT_AUTO_MIN_N (1 << 19)
 #define HOT_MAX_SAMPLES (1 << 23)
-hipError_t launch_hot_count(const uint64_t* keys, int64_t E, int64_t stride, uint64_t cmask,
-                            uint32_t* freq, hipStream_t s);
+#ifndef HOT_RUN
+#define HOT_RUN 8  // sampled keys come in runs of this many consecutive keys
+#endif
+hipError_t launch_hot_sample(const uint64_t* keys, int64_t stride, int64_t ns, uint64_t cmask,
+                             uint64_t* S, hipStream_t s);
+hipError_t launch_hot_count_sorted(const uint64_t* S, int64_t ns, uint32_t* freq, hipStream_t s);
 hipError_t launch_hot_count_ge(const uint32_t* freq, int64_t n, uint32_t tau, uint32_t* tile_sums,
                                uint32_t* total, hipStream_t s);
 hipError_t launch_hot_set(const uint32_t* freq, int64_t n, uint32_t tau, uint64_t* bits,
