@@ -183,14 +183,15 @@ hipError_t launch_keys_bcoh(const int32_t* row, const int32_t* col, int64_t E, i
 //   scan      : exclusive scan of hist gives each (digit, tile) its first output slot
 //   downsweep : each tile ranks its keys stably (original order within equal digits), reorders
 //               them in LDS by digit, and writes each digit's run contiguously.
-// Stable ranking: wave w of the tile takes its quarter of the tile in rounds of
-// 64 consecutive keys; lanes holding the same digit find each other with 8 ballots (one per
+// Stable ranking: wave w of the tile takes the w-th of RSORT_NT / 64 equal slices of the tile in
+// rounds of 64 consecutive keys; lanes holding the same digit find each other with 8 ballots (one per
 // digit bit) and rank by lower-lane count; a per-wave LDS counter per digit carries the running
 // count across rounds.  Wave offsets are then added per digit in wave order.
 // Both kernels visit tiles in the XCD-contiguous order of rs_tile_of.
 
 #define RSORT_WAVES (RSORT_NT / SPX_WAVE)
 #define RSORT_ROUNDS (RSORT_TILE / RSORT_WAVES / SPX_WAVE)
+static_assert(RSORT_NT >= 256 && RSORT_NT % SPX_WAVE == 0, "one thread per digit value");
 
 size_t radix_hist_elems(int64_t E) { return (size_t)256 * spx_div_up(E, RSORT_TILE); }
 
@@ -204,10 +205,9 @@ __device__ __forceinline__ int64_t rs_tile_of(int64_t b, int64_t tiles) {
     return x * q + (x < r ? x : r) + i;
 }
 
-__global__ __launch_bounds__(RSORT_NT) void k_rsort_upsweep(const uint64_t* __restrict__ keys,
-                                                            int64_t E, int shift,
-                                                            uint32_t* __restrict__ hist,
-                                                            int64_t tiles) {
+__device__ __forceinline__ void rsort_upsweep(const uint64_t* __restrict__ keys, int64_t E,
+                                              int shift, uint32_t* __restrict__ hist,
+                                              int64_t tiles) {
     __shared__ uint32_t cnt[RSORT_WAVES][256];
     for (int i = threadIdx.x; i < RSORT_WAVES * 256; i += RSORT_NT) (&cnt[0][0])[i] = 0;
     __syncthreads();
@@ -220,13 +220,15 @@ __global__ __launch_bounds__(RSORT_NT) void k_rsort_upsweep(const uint64_t* __re
         if (idx < E) atomicAdd(&cnt[w][(uint32_t)(keys[idx] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    uint32_t c = 0;
+    for (int d = threadIdx.x; d < 256; d += RSORT_NT) {
+        uint32_t c = 0;
 #pragma unroll
-    for (int ww = 0; ww < RSORT_WAVES; ++ww) c += cnt[ww][threadIdx.x];
-    hist[(int64_t)threadIdx.x * tiles + tile] = c;
+        for (int ww = 0; ww < RSORT_WAVES; ++ww) c += cnt[ww][d];
+        hist[(int64_t)d * tiles + tile] = c;
+    }
 }
 
-__global__ __launch_bounds__(RSORT_NT) void k_rsort_downsweep(
+__device__ __forceinline__ void rsort_downsweep(
     const uint64_t* __restrict__ kin, const uint64_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint64_t* __restrict__ vout, int64_t E, int shift,
     const uint32_t* __restrict__ hist, int64_t tiles) {
@@ -272,16 +274,20 @@ __global__ __launch_bounds__(RSORT_NT) void k_rsort_downsweep(
     __syncthreads();
     // per digit: exclusive offsets of the waves, then the tile's exclusive digit starts
     uint32_t run = 0;
+    if (tid < 256) {
 #pragma unroll
-    for (int ww = 0; ww < RSORT_WAVES; ++ww) {
-        const uint32_t t = wcnt[ww][tid];
-        wcnt[ww][tid] = run;
-        run += t;
+        for (int ww = 0; ww < RSORT_WAVES; ++ww) {
+            const uint32_t t = wcnt[ww][tid];
+            wcnt[ww][tid] = run;
+            run += t;
+        }
     }
     uint32_t tile_total;
     const uint32_t ex = block_excl_scan<RSORT_NT, uint32_t, OpSum<uint32_t>>(run, stmp, &tile_total);
-    dstart[tid] = ex;
-    goff[tid] = hist[(int64_t)tid * tiles + tile];
+    if (tid < 256) {
+        dstart[tid] = ex;
+        goff[tid] = hist[(int64_t)tid * tiles + tile];
+    }
     __syncthreads();
     const int64_t rem = E - tile_base;
     const int cnt = rem < RSORT_TILE ? (int)rem : RSORT_TILE;
@@ -322,6 +328,24 @@ __global__ __launch_bounds__(RSORT_NT) void k_rsort_downsweep(
     }
 }
 
+// The conversion's own sort and the sort of the hot-column sample run the same code under
+// different kernel names, so that per-kernel timings and counters keep them apart.
+#define RSORT_KERNELS(UP, DOWN)                                                                 \
+    __global__ __launch_bounds__(RSORT_NT) void UP(const uint64_t* __restrict__ keys, int64_t E, \
+                                                   int shift, uint32_t* __restrict__ hist,      \
+                                                   int64_t tiles) {                             \
+        rsort_upsweep(keys, E, shift, hist, tiles);                                             \
+    }                                                                                           \
+    __global__ __launch_bounds__(RSORT_NT) void DOWN(                                           \
+        const uint64_t* __restrict__ kin, const uint64_t* __restrict__ vin,                     \
+        uint64_t* __restrict__ kout, uint64_t* __restrict__ vout, int64_t E, int shift,         \
+        const uint32_t* __restrict__ hist, int64_t tiles) {                                     \
+        rsort_downsweep(kin, vin, kout, vout, E, shift, hist, tiles);                           \
+    }
+RSORT_KERNELS(k_rsort_upsweep, k_rsort_downsweep)
+RSORT_KERNELS(k_hot_rsort_upsweep, k_hot_rsort_downsweep)
+#undef RSORT_KERNELS
+
 struct LoadU32 {
     const uint32_t* p;
     __device__ uint32_t operator()(int64_t i) const { return p[i]; }
@@ -334,7 +358,7 @@ struct StoreExclU32 {
 hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1,
                             const uint64_t* vfirst, int64_t E, uint64_t vary, uint32_t* hist,
                             uint32_t* tile_sums, hipStream_t s, const uint64_t** keys_sorted,
-                            const uint64_t** vals_sorted) {
+                            const uint64_t** vals_sorted, bool hot_sample) {
     *keys_sorted = k0;
     *vals_sorted = vfirst;
     if (E <= 0) return hipSuccess;
@@ -347,16 +371,24 @@ hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* 
     uint64_t* vnext = v0;
     for (int shift = 0; shift < 64; shift += RS_RADIX_BITS) {
         if (((vary >> shift) & 0xFFull) == 0) continue;  // digit constant: order unchanged
-        SPX_LAUNCH("rsort_upsweep", k_rsort_upsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0, s,
-                   kin, E, shift, hist, tiles);
+        if (hot_sample)
+            SPX_LAUNCH("hot_rsort_upsweep", k_hot_rsort_upsweep, dim3((unsigned)tiles),
+                       dim3(RSORT_NT), 0, s, kin, E, shift, hist, tiles);
+        else
+            SPX_LAUNCH("rsort_upsweep", k_rsort_upsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0,
+                       s, kin, E, shift, hist, tiles);
         hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32{hist}, hn, tile_sums,
                                                                (uint32_t*)nullptr, s);
         if (e != hipSuccess) return e;
         e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32{hist}, StoreExclU32{hist}, hn,
                                                    tile_sums, s);
         if (e != hipSuccess) return e;
-        SPX_LAUNCH("rsort_downsweep", k_rsort_downsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0,
-                   s, kin, vin, kout, vout, E, shift, hist, tiles);
+        if (hot_sample)
+            SPX_LAUNCH("hot_rsort_downsweep", k_hot_rsort_downsweep, dim3((unsigned)tiles),
+                       dim3(RSORT_NT), 0, s, kin, vin, kout, vout, E, shift, hist, tiles);
+        else
+            SPX_LAUNCH("rsort_downsweep", k_rsort_downsweep, dim3((unsigned)tiles),
+                       dim3(RSORT_NT), 0, s, kin, vin, kout, vout, E, shift, hist, tiles);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint64_t* kt = kin;

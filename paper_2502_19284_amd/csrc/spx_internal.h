@@ -31,11 +31,14 @@
 #define CB_LDS_BUDGET (64 * 1024)    // bytes of the output slice kept in LDS
 #define CB_BP_STAGE_MAX 8192         // block pointers staged in LDS when nbc+1 <= this
 
-// radix sort: 8-bit digits, 256 threads x 8 keys per tile
+// radix sort: 8-bit digits, 1024 threads x 4 keys per tile (measured best of 256..1024 threads
+// and 2..16 keys per thread at 2^28 keys)
 #define RS_RADIX_BITS 8
-#define RSORT_NT 256
+#ifndef RSORT_NT
+#define RSORT_NT 1024
+#endif
 #ifndef RSORT_IPT
-#define RSORT_IPT 8
+#define RSORT_IPT 4
 #endif
 #define RSORT_TILE (RSORT_NT * RSORT_IPT)
 
@@ -176,10 +179,11 @@ hipError_t launch_keys_csb(const int32_t* row, const int32_t* col, int64_t E, in
 // Stable LSD radix sort of (keys in k0, 64-bit payloads read from vfirst).  Digits whose bits
 // never vary (per `vary`) are skipped.  k1, v0, v1 are scratch of E elements; the sorted arrays
 // are returned through keys_sorted / vals_sorted (one of the buffers, or vfirst if no pass ran).
+// hot_sample selects the separately named kernels used for the hot-column sample.
 hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1,
                             const uint64_t* vfirst, int64_t E, uint64_t vary, uint32_t* hist,
                             uint32_t* tile_sums, hipStream_t s, const uint64_t** keys_sorted,
-                            const uint64_t** vals_sorted);
+                            const uint64_t** vals_sorted, bool hot_sample = false);
 size_t radix_hist_elems(int64_t E);
 hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_sums,
                               uint32_t* total, hipStream_t s);
