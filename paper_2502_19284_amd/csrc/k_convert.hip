@@ -250,11 +250,13 @@ __device__ __forceinline__ void rsort_downsweep(
     const uint64_t lt = spx_lanemask_lt();
     uint64_t key[RSORT_ROUNDS];
     uint32_t pos[RSORT_ROUNDS];
+    uint64_t val[RSORT_ROUNDS];
 #pragma unroll
     for (int r = 0; r < RSORT_ROUNDS; ++r) {
         const int64_t idx = wave_base + r * SPX_WAVE + lane;
         const bool valid = idx < E;
         key[r] = valid ? kin[idx] : 0ull;
+        val[r] = valid ? vin[idx] : 0ull;  // payload fetched early, written after the keys
         const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -318,7 +320,7 @@ __device__ __forceinline__ void rsort_downsweep(
 #pragma unroll
     for (int r = 0; r < RSORT_ROUNDS; ++r) {
         const int64_t idx = wave_base + r * SPX_WAVE + lane;
-        if (idx < E) sbuf[pos[r]] = vin[idx];
+        if (idx < E) sbuf[pos[r]] = val[r];
     }
     __syncthreads();
 #pragma unroll
@@ -375,8 +377,8 @@ hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* 
             SPX_LAUNCH("hot_rsort_upsweep", k_hot_rsort_upsweep, dim3((unsigned)tiles),
                        dim3(RSORT_NT), 0, s, kin, E, shift, hist, tiles);
         else
-            SPX_LAUNCH("rsort_upsweep", k_rsort_upsweep, dim3((unsigned)tiles), dim3(RSORT_NT), 0,
-                       s, kin, E, shift, hist, tiles);
+            SPX_LAUNCH("rsort_upsweep", k_rsort_upsweep, dim3((unsigned)tiles),
+                       dim3(RSORT_NT), 0, s, kin, E, shift, hist, tiles);
         hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32{hist}, hn, tile_sums,
                                                                (uint32_t*)nullptr, s);
         if (e != hipSuccess) return e;
@@ -491,13 +493,16 @@ hipError_t launch_gather_csb(const uint64_t* keys, const double* vals, const int
 //     loaded at a time and one chain of additions walks them in order, up to the end of the run,
 //     wherever that is.
 // So a run of length L costs O(L) chained additions on one wave and O(L / 64) loads.
-#define DG_NT SCAN_NT
-#define DG_IPT SCAN_IPT
+#ifndef DG_NT
+#define DG_NT 1024
+#endif
+#define DG_IPT (SCAN_TILE / DG_NT)
 #define DG_TILE SCAN_TILE
 #define DG_SHORT 16
 #define DG_LONG_MAX 256
 static_assert(DG_TILE / (DG_SHORT + 1) + 1 <= DG_LONG_MAX, "list of the tile's long runs");
 static_assert(DG_TILE == DG_IPT * DG_NT && DG_NT % SPX_WAVE == 0, "tile layout");
+static_assert(DG_IPT * (DG_NT / SPX_WAVE) == SPX_WAVE, "one wave scans the (row, wave) counts");
 
 __device__ __forceinline__ double dg_lane(double v, int k) {  // v of lane k (k wave-uniform)
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
@@ -563,14 +568,10 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
         }
     }
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = tile_off[blockIdx.x];
-        for (int j = 0; j < DG_IPT; ++j)
-            for (int ww = 0; ww < NW; ++ww) {
-                const uint32_t c = s_pre[j][ww];
-                s_pre[j][ww] = run;
-                run += c;
-            }
+    if (w == 0) {  // exclusive prefix over the DG_IPT x NW counts in (row, wave) order
+        const uint32_t c = s_pre[lane / NW][lane % NW];
+        const uint32_t incl = wave_incl_scan<uint32_t, OpSum<uint32_t>>(c);
+        s_pre[lane / NW][lane % NW] = tile_off[blockIdx.x] + incl - c;
     }
     __syncthreads();
     const uint64_t lowmask = (1ull << shiftbits) - 1ull;
