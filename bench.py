@@ -75,10 +75,21 @@ def spmv_bytes(fmt, m, nnz, n_touched, A, val_bytes=8, vec_bytes=8):
     return b
 
 
-def kernel_bytes(name, E, nnz, m, passes):
-    """Algorithmic bytes per launch of conversion kernels (None when not modelled)."""
-    if name == "rsort_downsweep":
+def kernel_bytes(name, E, nnz, m, split_keys, split_levels):
+    """Algorithmic bytes per launch of conversion kernels (None when not modelled).
+
+    The sort's split levels move different numbers of keys (every key at the top levels, only
+    those of still-large segments below); split_keys / split_levels is their mean per launch."""
+    per_level = split_keys / split_levels if split_levels else 0
+    if name == "msd_scatter":
         # read 8-byte key + 8-byte value, write both
+        return 32 * per_level
+    if name == "msd_count":
+        return 8 * per_level
+    if name == "msd_local":
+        # every key and value read once and written once
+        return 32 * E
+    if name == "rsort_downsweep":
         return 32 * E
     if name == "rsort_upsweep":
         return 8 * E
@@ -644,6 +655,7 @@ def main():
     conv_ms = {f: [] for f in fmts}
     spmv_ms = {f: [] for f in fmts}
     info = {}
+    sort_split = {"keys": 0, "levels": 0}
 
     def step(record):
         for f in fmts:
@@ -657,7 +669,10 @@ def main():
                 e1.synchronize()
                 conv_ms[f].append(A.convert_ms)
                 spmv_ms[f].append(e0.elapsed_time(e1))
-                info[f] = dict(nnz=A.nnz, parts=A.parts, log2_beta=A.log2_beta, bytes=A.bytes)
+                info[f] = dict(nnz=A.nnz, parts=A.parts, log2_beta=A.log2_beta, bytes=A.bytes,
+                               sort_levels=A.sort_levels, sort_split_keys=A.sort_split_keys)
+                sort_split["keys"] += A.sort_split_keys
+                sort_split["levels"] += A.sort_levels
             A.close()
 
     for i in range(args.warmup):
@@ -680,9 +695,7 @@ def main():
 
     # dominant kernel of the step
     dom = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
-    converts = args.steps * len(fmts)
-    passes = kstats.get("rsort_downsweep", {}).get("launches", 0) / max(converts, 1)
-    dom_bytes = kernel_bytes(dom[0], E, nnz, m, passes if passes else 1)
+    dom_bytes = kernel_bytes(dom[0], E, nnz, m, sort_split["keys"], sort_split["levels"])
     roofline = None
     if dom_bytes is not None:
         ach = dom_bytes / (dom[1]["avg_ms"] * 1e-3) / 1e9

@@ -39,6 +39,7 @@ typedef int32_t spx_status;
 #define SPX_ERR_NOMEM -5       /* device allocation failed                                 */
 #define SPX_ERR_HIP -6         /* a HIP runtime call failed                                */
 #define SPX_ERR_UNSUPPORTED -7 /* valid request that this build does not implement         */
+#define SPX_ERR_DEVICE -8      /* a device-side bound was exceeded; the results are void    */
 
 /* ------------------------------------------------------------------ enums */
 typedef int32_t spx_format;
@@ -104,6 +105,8 @@ typedef struct {
     int64_t bytes;     /* device bytes held by the handle                               */
     int32_t log2_beta; /* CSBH block side used (0 for CRS formats)                      */
     int32_t parts;     /* work units of the format (tiles, row blocks, block-row chunks)*/
+    int64_t sort_split_keys; /* keys moved by the sort's global split levels, summed      */
+    int32_t sort_levels;     /* global split levels the sort ran                          */
 } spx_convert_report;
 
 typedef struct spx_matrix_s* spx_matrix;

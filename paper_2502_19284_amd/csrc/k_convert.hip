@@ -205,33 +205,36 @@ __device__ __forceinline__ int64_t rs_tile_of(int64_t b, int64_t tiles) {
     return x * q + (x < r ? x : r) + i;
 }
 
-__device__ __forceinline__ void rsort_upsweep(const uint64_t* __restrict__ keys, int64_t E,
-                                              int shift, uint32_t* __restrict__ hist,
-                                              int64_t tiles) {
+// Digit counts of keys[lo, lo + n), n <= RSORT_TILE: digit d's count is stored at hist[hb + d * hs].
+__device__ __forceinline__ void rs_count_tile(const uint64_t* __restrict__ keys, int64_t lo, int n,
+                                              int shift, uint32_t* __restrict__ hist, int64_t hb,
+                                              int64_t hs) {
     __shared__ uint32_t cnt[RSORT_WAVES][256];
     for (int i = threadIdx.x; i < RSORT_WAVES * 256; i += RSORT_NT) (&cnt[0][0])[i] = 0;
     __syncthreads();
     const int w = threadIdx.x / SPX_WAVE;
-    const int64_t tile = rs_tile_of(blockIdx.x, tiles);
-    const int64_t base = tile * RSORT_TILE;
 #pragma unroll
     for (int i = 0; i < RSORT_IPT; ++i) {
-        const int64_t idx = base + i * RSORT_NT + threadIdx.x;
-        if (idx < E) atomicAdd(&cnt[w][(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+        const int j = i * RSORT_NT + threadIdx.x;
+        if (j < n) atomicAdd(&cnt[w][(uint32_t)(keys[lo + j] >> shift) & 255u], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < 256; d += RSORT_NT) {
         uint32_t c = 0;
 #pragma unroll
         for (int ww = 0; ww < RSORT_WAVES; ++ww) c += cnt[ww][d];
-        hist[(int64_t)d * tiles + tile] = c;
+        hist[hb + d * hs] = c;
     }
 }
 
-__device__ __forceinline__ void rsort_downsweep(
-    const uint64_t* __restrict__ kin, const uint64_t* __restrict__ vin,
-    uint64_t* __restrict__ kout, uint64_t* __restrict__ vout, int64_t E, int shift,
-    const uint32_t* __restrict__ hist, int64_t tiles) {
+// Stable scatter of the tile keys[lo, lo + n) (with payloads) by digit: the keys of digit d go,
+// in tile order, to kout[goff_of(d) ...].  goff_of is called once per digit.
+template <typename GOff>
+__device__ __forceinline__ void rs_scatter_tile(const uint64_t* __restrict__ kin,
+                                                const uint64_t* __restrict__ vin,
+                                                uint64_t* __restrict__ kout,
+                                                uint64_t* __restrict__ vout, int64_t lo, int n,
+                                                int shift, GOff goff_of) {
     __shared__ uint32_t wcnt[RSORT_WAVES][256];
     __shared__ uint32_t dstart[256];
     __shared__ uint32_t goff[256];
@@ -244,19 +247,17 @@ __device__ __forceinline__ void rsort_downsweep(
     for (int i = tid; i < RSORT_WAVES * 256; i += RSORT_NT) (&wcnt[0][0])[i] = 0;
     __syncthreads();
 
-    const int64_t tile = rs_tile_of(blockIdx.x, tiles);
-    const int64_t tile_base = tile * RSORT_TILE;
-    const int64_t wave_base = tile_base + (int64_t)w * (RSORT_TILE / RSORT_WAVES);
+    const int wave_off = w * (RSORT_TILE / RSORT_WAVES);  // tile-relative
     const uint64_t lt = spx_lanemask_lt();
     uint64_t key[RSORT_ROUNDS];
     uint32_t pos[RSORT_ROUNDS];
     uint64_t val[RSORT_ROUNDS];
 #pragma unroll
     for (int r = 0; r < RSORT_ROUNDS; ++r) {
-        const int64_t idx = wave_base + r * SPX_WAVE + lane;
-        const bool valid = idx < E;
-        key[r] = valid ? kin[idx] : 0ull;
-        val[r] = valid ? vin[idx] : 0ull;  // payload fetched early, written after the keys
+        const int j = wave_off + r * SPX_WAVE + lane;
+        const bool valid = j < n;
+        key[r] = valid ? kin[lo + j] : 0ull;
+        val[r] = valid ? vin[lo + j] : 0ull;  // payload fetched early, written after the keys
         const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -288,16 +289,13 @@ __device__ __forceinline__ void rsort_downsweep(
     const uint32_t ex = block_excl_scan<RSORT_NT, uint32_t, OpSum<uint32_t>>(run, stmp, &tile_total);
     if (tid < 256) {
         dstart[tid] = ex;
-        goff[tid] = hist[(int64_t)tid * tiles + tile];
+        goff[tid] = goff_of(tid);
     }
     __syncthreads();
-    const int64_t rem = E - tile_base;
-    const int cnt = rem < RSORT_TILE ? (int)rem : RSORT_TILE;
     // phase 1: keys
 #pragma unroll
     for (int r = 0; r < RSORT_ROUNDS; ++r) {
-        const int64_t idx = wave_base + r * SPX_WAVE + lane;
-        if (idx < E) {
+        if (wave_off + r * SPX_WAVE + lane < n) {
             const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
             pos[r] += dstart[d] + wcnt[w][d];
             sbuf[pos[r]] = key[r];
@@ -308,7 +306,7 @@ __device__ __forceinline__ void rsort_downsweep(
 #pragma unroll
     for (int q = 0; q < RSORT_IPT; ++q) {
         const int i = q * RSORT_NT + tid;
-        if (i < cnt) {
+        if (i < n) {
             const uint64_t k = sbuf[i];
             const uint32_t d = (uint32_t)(k >> shift) & 255u;
             dst_lo[q] = goff[d] + (uint32_t)(i - (int)dstart[d]);
@@ -318,16 +316,39 @@ __device__ __forceinline__ void rsort_downsweep(
     __syncthreads();
     // phase 2: payloads, through the same LDS slots
 #pragma unroll
-    for (int r = 0; r < RSORT_ROUNDS; ++r) {
-        const int64_t idx = wave_base + r * SPX_WAVE + lane;
-        if (idx < E) sbuf[pos[r]] = val[r];
-    }
+    for (int r = 0; r < RSORT_ROUNDS; ++r)
+        if (wave_off + r * SPX_WAVE + lane < n) sbuf[pos[r]] = val[r];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < RSORT_IPT; ++q) {
         const int i = q * RSORT_NT + tid;
-        if (i < cnt) vout[dst_lo[q]] = sbuf[i];
+        if (i < n) vout[dst_lo[q]] = sbuf[i];
     }
+}
+
+struct GOffLsd {  // digit-major histogram of equal tiles, scanned
+    const uint32_t* hist;
+    int64_t tiles, tile;
+    __device__ uint32_t operator()(int d) const { return hist[(int64_t)d * tiles + tile]; }
+};
+
+__device__ __forceinline__ void rsort_upsweep(const uint64_t* __restrict__ keys, int64_t E,
+                                              int shift, uint32_t* __restrict__ hist,
+                                              int64_t tiles) {
+    const int64_t tile = rs_tile_of(blockIdx.x, tiles);
+    const int64_t lo = tile * RSORT_TILE;
+    const int n = E - lo < RSORT_TILE ? (int)(E - lo) : RSORT_TILE;
+    rs_count_tile(keys, lo, n, shift, hist, tile, tiles);
+}
+
+__device__ __forceinline__ void rsort_downsweep(
+    const uint64_t* __restrict__ kin, const uint64_t* __restrict__ vin,
+    uint64_t* __restrict__ kout, uint64_t* __restrict__ vout, int64_t E, int shift,
+    const uint32_t* __restrict__ hist, int64_t tiles) {
+    const int64_t tile = rs_tile_of(blockIdx.x, tiles);
+    const int64_t lo = tile * RSORT_TILE;
+    const int n = E - lo < RSORT_TILE ? (int)(E - lo) : RSORT_TILE;
+    rs_scatter_tile(kin, vin, kout, vout, lo, n, shift, GOffLsd{hist, tiles, tile});
 }
 
 // The conversion's own sort and the sort of the hot-column sample run the same code under
@@ -403,6 +424,496 @@ hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* 
     }
     *keys_sorted = kin;
     *vals_sorted = vin;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ MSD radix sort, LDS finish
+//
+// The conversion sort.  Digits are taken from the most significant varying one down.  A segment
+// is a range of positions whose keys agree on every digit above the current one; it starts as
+// [0, E).  Each level splits every segment longer than RS_LOCAL_MAX by one digit with a stable
+// counting pass (tiles never straddle segments; the digit offsets of all segments come from one
+// scan of a segment-major, digit-major, tile-minor histogram).  Parts of at most RS_LOCAL_MAX
+// keys leave the recursion: consecutive such parts of one segment are packed into chunks of at
+// most RS_LOCAL_MAX keys, and each chunk is sorted by one workgroup in LDS on its remaining
+// digits (stable passes over the digits that vary inside the chunk) and written to the output
+// buffer.  Parts still longer after the last varying digit hold equal keys and are copied.
+// Every pass is stable, so equal keys keep their input order: the result equals the LSD sort's.
+//
+// Buffers: level p reads B_p and writes B_{p+1}; B_0 = (k0, vfirst), B_odd = (k1, v1),
+// B_even>0 = (k0, v0).  The output is (k1, v1).  A chunk records which buffer holds it.
+
+#ifndef RS_LOCAL_MAX
+#define RS_LOCAL_MAX RSORT_TILE
+#endif
+
+struct MsdCounters {
+    uint32_t nbig, ntiles, nchunks, err, bigkeys;
+};
+
+__global__ void k_msd_init(int64_t E, int64_t* seg_start, uint32_t* seg_len, MsdChunk* chunks,
+                           MsdCounters* ctr) {
+    ctr->nbig = 0;
+    ctr->ntiles = 0;
+    ctr->nchunks = 0;
+    ctr->err = 0;
+    ctr->bigkeys = 0;
+    if (E > RS_LOCAL_MAX) {
+        seg_start[0] = 0;
+        seg_len[0] = (uint32_t)E;
+    } else {
+        chunks[0] = MsdChunk{0, (uint32_t)E, 64u};  // all bits, source B_0
+        ctr->nchunks = 1;
+    }
+}
+
+__global__ void k_msd_next_level(MsdCounters* ctr) {
+    ctr->nbig = 0;
+    ctr->ntiles = 0;
+    ctr->bigkeys = 0;
+}
+
+struct LoadNt {
+    const uint32_t* len;
+    __device__ uint32_t operator()(int64_t i) const {
+        return (len[i] + RSORT_TILE - 1) / RSORT_TILE;
+    }
+};
+
+// tile_seg[g] = the segment whose tiles include g (tbase strictly increasing, nb + 1 entries)
+__global__ void k_msd_tile_seg(const uint32_t* __restrict__ tbase, uint32_t nb, uint32_t T,
+                               uint32_t* __restrict__ tile_seg) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= T) return;
+    uint32_t lo = 0, hi = nb - 1;  // last s with tbase[s] <= g
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (tbase[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    tile_seg[g] = lo;
+}
+
+struct MsdTile {
+    int64_t lo;
+    int n;
+    int64_t hb;  // histogram index of (segment, digit 0, this tile)
+    int64_t hs;  // tiles of the segment (histogram stride between digits)
+    int64_t h0;  // histogram index of (segment, digit 0, tile 0)
+    int64_t start;
+};
+
+__device__ __forceinline__ MsdTile msd_tile(const int64_t* seg_start, const uint32_t* seg_len,
+                                            const uint32_t* tbase, const uint32_t* tile_seg,
+                                            uint32_t T) {
+    const uint32_t g = (uint32_t)rs_tile_of(blockIdx.x, T);
+    const uint32_t sg = tile_seg[g];
+    const uint32_t tb = tbase[sg];
+    const uint32_t t = g - tb;
+    const int64_t len = seg_len[sg];
+    MsdTile m;
+    m.start = seg_start[sg];
+    m.lo = m.start + (int64_t)t * RSORT_TILE;
+    const int64_t rem = len - (int64_t)t * RSORT_TILE;
+    m.n = rem < RSORT_TILE ? (int)rem : RSORT_TILE;
+    m.hs = tbase[sg + 1] - tb;
+    m.h0 = (int64_t)tb * 256;
+    m.hb = m.h0 + t;
+    return m;
+}
+
+__global__ __launch_bounds__(RSORT_NT) void k_msd_count(const uint64_t* __restrict__ keys,
+                                                        const int64_t* __restrict__ seg_start,
+                                                        const uint32_t* __restrict__ seg_len,
+                                                        const uint32_t* __restrict__ tbase,
+                                                        const uint32_t* __restrict__ tile_seg,
+                                                        uint32_t T, int shift,
+                                                        uint32_t* __restrict__ hist) {
+    const MsdTile m = msd_tile(seg_start, seg_len, tbase, tile_seg, T);
+    rs_count_tile(keys, m.lo, m.n, shift, hist, m.hb, m.hs);
+}
+
+struct GOffMsd {  // segment start + scanned (segment, digit, tile) entry - segment's first entry
+    const uint32_t* hist;
+    int64_t hb, hs, base;
+    __device__ uint32_t operator()(int d) const {
+        return (uint32_t)(base + (int64_t)hist[hb + (int64_t)d * hs]);
+    }
+};
+
+__global__ __launch_bounds__(RSORT_NT) void k_msd_scatter(
+    const uint64_t* __restrict__ kin, const uint64_t* __restrict__ vin,
+    uint64_t* __restrict__ kout, uint64_t* __restrict__ vout,
+    const int64_t* __restrict__ seg_start, const uint32_t* __restrict__ seg_len,
+    const uint32_t* __restrict__ tbase, const uint32_t* __restrict__ tile_seg, uint32_t T,
+    int shift, const uint32_t* __restrict__ hist) {
+    const MsdTile m = msd_tile(seg_start, seg_len, tbase, tile_seg, T);
+    const int64_t base = m.start - (int64_t)hist[m.h0];
+    rs_scatter_tile(kin, vin, kout, vout, m.lo, m.n, shift, GOffMsd{hist, m.hb, m.hs, base});
+}
+
+// One wave per segment: the 256 part sizes go to LDS, lane 0 walks them in digit order, packing
+// consecutive small parts into chunks and listing the large ones for the next level (or as copy
+// chunks after the last varying digit); the wave then reserves its list entries with one atomic
+// per list and writes them in parallel.
+#define MSD_CLS_NT 256
+__global__ __launch_bounds__(MSD_CLS_NT) void k_msd_classify(
+    const int64_t* __restrict__ seg_start, const uint32_t* __restrict__ seg_len,
+    const uint32_t* __restrict__ tbase, uint32_t nb, const uint32_t* __restrict__ hist, int last,
+    uint32_t meta, int64_t* __restrict__ nstart, uint32_t* __restrict__ nlen, uint32_t cap_big,
+    MsdChunk* __restrict__ chunks, uint32_t cap_chunks, MsdCounters* ctr) {
+    constexpr int NW = MSD_CLS_NT / SPX_WAVE;
+    __shared__ uint32_t s_cnt[NW][256];
+    __shared__ uint32_t s_off[NW][256];
+    __shared__ uint32_t s_olen[NW][256];   // outputs in digit order: length,
+    __shared__ uint32_t s_ooff[NW][256];   // offset in the segment,
+    __shared__ uint8_t s_obig[NW][256];    // 1: next-level segment, 0: chunk
+    __shared__ uint32_t s_nout[NW], s_cbase[NW], s_bbase[NW];
+    const int w = threadIdx.x / SPX_WAVE;
+    const int lane = __lane_id();
+    const uint32_t sg = blockIdx.x * NW + w;
+    if (sg >= nb) return;  // whole waves leave; no workgroup barrier below
+    const int64_t st = seg_start[sg];
+    const uint32_t len = seg_len[sg];
+    const int64_t hs = tbase[sg + 1] - tbase[sg];
+    const int64_t h0 = (int64_t)tbase[sg] * 256;
+    const uint32_t x0 = hist[h0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int d = lane + 64 * q;
+        const uint32_t xd = hist[h0 + d * hs];
+        const uint32_t xe = d < 255 ? hist[h0 + (d + 1) * hs] : x0 + len;
+        s_cnt[w][d] = xe - xd;
+        s_off[w][d] = xd - x0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+        uint32_t no = 0, nbig = 0, tiles = 0, coff = 0, cl = 0, bigkeys = 0;
+        for (int d = 0; d < 256; ++d) {
+            const uint32_t c = s_cnt[w][d];
+            if (c == 0) continue;
+            const uint32_t off = s_off[w][d];
+            if (c <= RS_LOCAL_MAX) {
+                if (cl > 0 && cl + c <= RS_LOCAL_MAX) {
+                    cl += c;
+                    continue;
+                }
+                if (cl > 0) {
+                    s_olen[w][no] = cl;
+                    s_ooff[w][no] = coff;
+                    s_obig[w][no++] = 0;
+                }
+                coff = off;
+                cl = c;
+            } else {
+                if (cl > 0) {
+                    s_olen[w][no] = cl;
+                    s_ooff[w][no] = coff;
+                    s_obig[w][no++] = 0;
+                }
+                cl = 0;
+                const bool big = !last;  // after the last varying digit: equal keys, copied
+                s_olen[w][no] = c;
+                s_ooff[w][no] = off;
+                s_obig[w][no++] = big ? 1 : 0;
+                if (big) {
+                    ++nbig;
+                    tiles += (c + RSORT_TILE - 1) / RSORT_TILE;
+                    bigkeys += c;
+                }
+            }
+        }
+        if (cl > 0) {
+            s_olen[w][no] = cl;
+            s_ooff[w][no] = coff;
+            s_obig[w][no++] = 0;
+        }
+        s_nout[w] = no;
+        s_cbase[w] = no - nbig > 0 ? atomicAdd(&ctr->nchunks, no - nbig) : 0u;
+        s_bbase[w] = nbig > 0 ? atomicAdd(&ctr->nbig, nbig) : 0u;
+        if (tiles > 0) {
+            atomicAdd(&ctr->ntiles, tiles);
+            atomicAdd(&ctr->bigkeys, bigkeys);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t no = s_nout[w];
+    uint32_t cb = s_cbase[w], bb = s_bbase[w];
+    for (uint32_t o0 = 0; o0 < no; o0 += SPX_WAVE) {  // outputs in order, ranked by ballots
+        const uint32_t o = o0 + lane;
+        const bool valid = o < no;
+        const bool big = valid && s_obig[w][o];
+        const uint64_t bbal = __ballot(big), cbal = __ballot(valid && !big);
+        const uint64_t lt = spx_lanemask_lt();
+        if (valid) {
+            const int64_t sub = st + s_ooff[w][o];
+            const uint32_t c = s_olen[w][o];
+            if (big) {
+                const uint32_t i = bb + (uint32_t)__popcll(bbal & lt);
+                if (i < cap_big) {
+                    nstart[i] = sub;
+                    nlen[i] = c;
+                } else {
+                    atomicOr(&ctr->err, 8u);
+                }
+            } else {
+                const uint32_t i = cb + (uint32_t)__popcll(cbal & lt);
+                if (i < cap_chunks) chunks[i] = MsdChunk{sub, c, meta};
+                else atomicOr(&ctr->err, 8u);
+            }
+        }
+        bb += (uint32_t)__popcll(bbal);
+        cb += (uint32_t)__popcll(cbal);
+    }
+}
+
+#ifndef MSD_LNT
+#define MSD_LNT 512
+#endif
+#define MSD_LWAVES (MSD_LNT / SPX_WAVE)
+#define MSD_LROUNDS (RS_LOCAL_MAX / MSD_LNT)
+static_assert(MSD_LNT >= 256 && RS_LOCAL_MAX % MSD_LNT == 0, "local sort shape");
+
+// One workgroup per chunk: keys and payloads of at most RS_LOCAL_MAX positions, stable LSD
+// passes in LDS over the digits below `hi` that vary inside the chunk, then the keys and the
+// payloads (each to its final position) are written to (kf, vf).  Chunks longer than
+// RS_LOCAL_MAX hold equal keys and are copied.
+__global__ __launch_bounds__(MSD_LNT) void k_msd_local(
+    const MsdChunk* __restrict__ chunks, const uint64_t* k0, const uint64_t* vfirst,
+    const uint64_t* v0, uint64_t* kf, uint64_t* vf) {
+    __shared__ uint64_t skey[RS_LOCAL_MAX];
+    __shared__ uint16_t sidx[RS_LOCAL_MAX];
+    __shared__ uint32_t wcnt[MSD_LWAVES][256];
+    __shared__ uint32_t dstart[256];
+    __shared__ uint32_t stmp[MSD_LWAVES];
+    __shared__ uint64_t sred[2][MSD_LWAVES];
+    const MsdChunk c = chunks[blockIdx.x];
+    const int src = (int)(c.meta >> 8);  // 0: B_0, 1: (k1, v1) = output, 2: (k0, v0)
+    const int hi = (int)(c.meta & 255u);
+    const uint64_t* ks = src == 1 ? kf : k0;
+    const uint64_t* vs = src == 0 ? vfirst : src == 1 ? vf : v0;
+    const int tid = threadIdx.x;
+    if (c.len > RS_LOCAL_MAX) {  // equal keys, already in input order
+        if (src != 1)
+            for (int64_t i = tid; i < c.len; i += MSD_LNT) {
+                kf[c.start + i] = ks[c.start + i];
+                vf[c.start + i] = vs[c.start + i];
+            }
+        return;
+    }
+    const int n = (int)c.len;
+    const int w = tid / SPX_WAVE;
+    const int lane = __lane_id();
+    const int wave_off = w * (RS_LOCAL_MAX / MSD_LWAVES);
+    const uint64_t lt = spx_lanemask_lt();
+    uint64_t key[MSD_LROUNDS], val[MSD_LROUNDS];
+    uint32_t idx[MSD_LROUNDS];
+    uint64_t vor = 0, vand = ~0ull;
+#pragma unroll
+    for (int r = 0; r < MSD_LROUNDS; ++r) {
+        const int j = wave_off + r * SPX_WAVE + lane;
+        key[r] = j < n ? ks[c.start + j] : 0ull;
+        val[r] = j < n ? vs[c.start + j] : 0ull;
+        idx[r] = (uint32_t)j;
+        if (j < n) {
+            vor |= key[r];
+            vand &= key[r];
+        }
+    }
+    // every load has landed before any thread can write the chunk back (it may be in place)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    vor = wave_reduce<uint64_t, OpOr<uint64_t>>(vor);
+    vand = wave_reduce<uint64_t, OpAnd<uint64_t>>(vand);
+    if (lane == 0) {
+        sred[0][w] = vor;
+        sred[1][w] = vand;
+    }
+    __syncthreads();
+    vor = 0;
+    vand = ~0ull;
+#pragma unroll
+    for (int ww = 0; ww < MSD_LWAVES; ++ww) {
+        vor |= sred[0][ww];
+        vand &= sred[1][ww];
+    }
+    const uint64_t vm = (vor ^ vand) & (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull));
+    for (int ds = 0; ds < hi; ds += RS_RADIX_BITS) {
+        if (((vm >> ds) & 255ull) == 0) continue;  // uniform: vm is the same in every thread
+        for (int i = tid; i < MSD_LWAVES * 256; i += MSD_LNT) (&wcnt[0][0])[i] = 0;
+        __syncthreads();
+        uint32_t pos[MSD_LROUNDS];
+#pragma unroll
+        for (int r = 0; r < MSD_LROUNDS; ++r) {
+            const bool valid = wave_off + r * SPX_WAVE + lane < n;
+            const uint32_t d = (uint32_t)(key[r] >> ds) & 255u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < RS_RADIX_BITS; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bal = __ballot(bit);
+                peers &= bit ? bal : ~bal;
+            }
+            const uint32_t below = (uint32_t)__popcll(peers & lt);
+            const uint32_t count = (uint32_t)__popcll(peers);
+            const uint32_t basec = wcnt[w][d];
+            __builtin_amdgcn_wave_barrier();
+            if (valid && below == 0) wcnt[w][d] = basec + count;
+            __builtin_amdgcn_wave_barrier();
+            pos[r] = basec + below;
+        }
+        __syncthreads();
+        uint32_t run = 0;
+        if (tid < 256) {
+#pragma unroll
+            for (int ww = 0; ww < MSD_LWAVES; ++ww) {
+                const uint32_t t = wcnt[ww][tid];
+                wcnt[ww][tid] = run;
+                run += t;
+            }
+        }
+        uint32_t total;
+        const uint32_t ex =
+            block_excl_scan<MSD_LNT, uint32_t, OpSum<uint32_t>>(run, stmp, &total);
+        if (tid < 256) dstart[tid] = ex;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < MSD_LROUNDS; ++r) {
+            if (wave_off + r * SPX_WAVE + lane < n) {
+                const uint32_t d = (uint32_t)(key[r] >> ds) & 255u;
+                const uint32_t p = dstart[d] + wcnt[w][d] + pos[r];
+                skey[p] = key[r];
+                sidx[p] = (uint16_t)idx[r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < MSD_LROUNDS; ++r) {
+            const int j = wave_off + r * SPX_WAVE + lane;
+            if (j < n) {
+                key[r] = skey[j];
+                idx[r] = sidx[j];
+            }
+        }
+        __syncthreads();
+    }
+    // keys in order; payload of the input position j goes to the final position of j
+#pragma unroll
+    for (int r = 0; r < MSD_LROUNDS; ++r) {
+        const int j = wave_off + r * SPX_WAVE + lane;
+        if (j < n) {
+            kf[c.start + j] = key[r];
+            sidx[idx[r]] = (uint16_t)j;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < MSD_LROUNDS; ++r) {
+        const int j = wave_off + r * SPX_WAVE + lane;
+        if (j < n) vf[c.start + sidx[j]] = val[r];
+    }
+}
+
+MsdSizes msd_sizes(int64_t E) {
+    MsdSizes z;
+    const int64_t tiles = spx_div_up(E > 0 ? E : 1, RSORT_TILE);
+    z.cap_big = E / (RS_LOCAL_MAX + 1) + 2;
+    z.cap_tiles = tiles + z.cap_big;
+    // per level at most 4 E / RS_LOCAL_MAX + 2 chunks (consecutive packed chunks of one segment
+    // hold more than RS_LOCAL_MAX keys together), at most 8 levels, copies, the single chunk
+    z.cap_chunks = 33 * spx_div_up(E > 0 ? E : 1, RS_LOCAL_MAX) + 32;
+    z.hist = 256 * z.cap_tiles;
+    z.tile_sums = scan_tile_count(z.hist) > scan_tile_count(z.cap_big + 1)
+                      ? scan_tile_count(z.hist)
+                      : scan_tile_count(z.cap_big + 1);
+    return z;
+}
+
+static hipError_t msd_read(MsdCounters* host, const MsdCounters* dev, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(host, dev, sizeof *host, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1,
+                          const uint64_t* vfirst, int64_t E, uint64_t vary, const MsdScratch& sc,
+                          hipStream_t s, const uint64_t** keys_sorted,
+                          const uint64_t** vals_sorted, int* failed, MsdStats* stats) {
+    *keys_sorted = k0;
+    *vals_sorted = vfirst;
+    *failed = 0;
+    *stats = MsdStats{};
+    if (E <= 0 || vary == 0) return hipSuccess;  // no key differs: the input order stands
+    MsdCounters* ctr = (MsdCounters*)sc.counters;
+    MsdCounters h{};
+    SPX_LAUNCH("msd_init", k_msd_init, dim3(1), dim3(1), 0, s, E, sc.seg_start[0], sc.seg_len[0],
+               sc.chunks, ctr);
+    uint32_t nb = E > RS_LOCAL_MAX ? 1u : 0u;
+    uint32_t T = nb ? (uint32_t)spx_div_up(E, RSORT_TILE) : 0u;
+    int p = 0;  // levels done
+    int64_t level_keys = E;
+    for (int shift = 64 - RS_RADIX_BITS; shift >= 0 && nb > 0; shift -= RS_RADIX_BITS) {
+        if (((vary >> shift) & 0xFFull) == 0) continue;  // constant digit: no split
+        const bool last = shift == 0 || (vary & ((1ull << shift) - 1ull)) == 0;
+        const int cur = p & 1;
+        const uint64_t* kin = p == 0 ? k0 : (p & 1) ? k1 : k0;
+        const uint64_t* vin = p == 0 ? vfirst : (p & 1) ? v1 : v0;
+        uint64_t* kout = (p & 1) ? k0 : k1;
+        uint64_t* vout = (p & 1) ? v0 : v1;
+        const uint32_t out_code = (p & 1) ? 2u : 1u;  // buffer that holds level p's output
+        // tiles of the level's segments
+        hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(
+            LoadNt{sc.seg_len[cur]}, nb, sc.tile_sums, sc.tbase + nb, s);
+        if (e != hipSuccess) return e;
+        e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadNt{sc.seg_len[cur]},
+                                                   StoreExclU32{sc.tbase}, nb, sc.tile_sums, s);
+        if (e != hipSuccess) return e;
+        SPX_LAUNCH("msd_tile_seg", k_msd_tile_seg, dim3(spx_div_up(T, 256)), dim3(256), 0, s,
+                   sc.tbase, nb, T, sc.tile_seg);
+        SPX_LAUNCH("msd_count", k_msd_count, dim3(T), dim3(RSORT_NT), 0, s, kin,
+                   sc.seg_start[cur], sc.seg_len[cur], sc.tbase, sc.tile_seg, T, shift, sc.hist);
+        const int64_t hn = (int64_t)256 * T;
+        e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32{sc.hist}, hn, sc.tile_sums,
+                                                    (uint32_t*)nullptr, s);
+        if (e != hipSuccess) return e;
+        e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32{sc.hist}, StoreExclU32{sc.hist}, hn,
+                                                   sc.tile_sums, s);
+        if (e != hipSuccess) return e;
+        SPX_LAUNCH("msd_scatter", k_msd_scatter, dim3(T), dim3(RSORT_NT), 0, s, kin, vin, kout,
+                   vout, sc.seg_start[cur], sc.seg_len[cur], sc.tbase, sc.tile_seg, T, shift,
+                   sc.hist);
+        SPX_LAUNCH("msd_next_level", k_msd_next_level, dim3(1), dim3(1), 0, s, ctr);
+        const uint32_t meta = (uint32_t)(shift + RS_RADIX_BITS) | (out_code << 8);
+        SPX_LAUNCH("msd_classify", k_msd_classify,
+                   dim3(spx_div_up(nb, MSD_CLS_NT / SPX_WAVE)), dim3(MSD_CLS_NT), 0, s,
+                   sc.seg_start[cur], sc.seg_len[cur], sc.tbase, nb, sc.hist, last ? 1 : 0, meta,
+                   sc.seg_start[cur ^ 1], sc.seg_len[cur ^ 1], (uint32_t)sc.z.cap_big, sc.chunks,
+                   (uint32_t)sc.z.cap_chunks, ctr);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = msd_read(&h, ctr, s);
+        if (e != hipSuccess) return e;
+        if (h.err) {
+            *failed = 1;
+            return hipSuccess;
+        }
+        stats->split_keys += level_keys;
+        stats->levels = p + 1;
+        level_keys = h.bigkeys;
+        nb = h.nbig;
+        T = h.ntiles;
+        ++p;
+    }
+    hipError_t e = msd_read(&h, ctr, s);
+    if (e != hipSuccess) return e;
+    if (h.err || nb > 0) {  // nb > 0 only if a level could not run: not reachable
+        *failed = 1;
+        return hipSuccess;
+    }
+    if (h.nchunks > 0)
+        SPX_LAUNCH("msd_local", k_msd_local, dim3(h.nchunks), dim3(MSD_LNT), 0, s, sc.chunks,
+                   (const uint64_t*)k0, vfirst, (const uint64_t*)v0, k1, v1);
+    *keys_sorted = k1;
+    *vals_sorted = v1;
     return hipGetLastError();
 }
 

@@ -50,6 +50,7 @@ extern "C" const char* spx_status_string(spx_status s) {
         case SPX_ERR_NOMEM: return "SPX_ERR_NOMEM";
         case SPX_ERR_HIP: return "SPX_ERR_HIP";
         case SPX_ERR_UNSUPPORTED: return "SPX_ERR_UNSUPPORTED";
+        case SPX_ERR_DEVICE: return "SPX_ERR_DEVICE";
         default: return "SPX_ERR_UNKNOWN";
     }
 }
@@ -180,6 +181,7 @@ struct SortedEntries {
     const double* vals = nullptr;
     const uint32_t* head_tiles = nullptr;  // null when repeats are kept
     int64_t nnz_out = 0;
+    MsdStats sort;
 };
 
 static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_format fmt, int k,
@@ -188,18 +190,28 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
                                  int K2 = 0) {
     const int64_t E = coo->nnz;
     uint64_t *k0, *k1, *v0, *v1;
-    uint32_t *hist, *tsums;
+    uint32_t* tsums;
     Readback* rb_dev;
     SPX_TRY(tmp.get(&k0, E, "sort keys"));
     SPX_TRY(tmp.get(&k1, E, "sort keys"));
     SPX_TRY(tmp.get(&v0, E, "sort values"));
     SPX_TRY(tmp.get(&v1, E, "sort values"));
-    const size_t hn = radix_hist_elems(E);
-    SPX_TRY(tmp.get(&hist, hn, "radix histogram"));
-    size_t ts = scan_tile_count((int64_t)hn);
-    if (scan_tile_count(E) > ts) ts = scan_tile_count(E);
-    SPX_TRY(tmp.get(&tsums, ts, "scan tile sums"));
+    SPX_TRY(tmp.get(&tsums, scan_tile_count(E), "scan tile sums"));
     SPX_TRY(tmp.get(&rb_dev, 1, "readback"));
+    MsdScratch sc;
+    sc.z = msd_sizes(E);
+    for (int i = 0; i < 2; ++i) {
+        SPX_TRY(tmp.get(&sc.seg_start[i], (size_t)sc.z.cap_big, "sort segments"));
+        SPX_TRY(tmp.get(&sc.seg_len[i], (size_t)sc.z.cap_big, "sort segments"));
+    }
+    SPX_TRY(tmp.get(&sc.tbase, (size_t)sc.z.cap_big + 1, "sort segment tiles"));
+    SPX_TRY(tmp.get(&sc.tile_seg, (size_t)sc.z.cap_tiles, "sort tile segments"));
+    SPX_TRY(tmp.get(&sc.hist, (size_t)sc.z.hist, "radix histogram"));
+    SPX_TRY(tmp.get(&sc.tile_sums, (size_t)sc.z.tile_sums, "scan tile sums"));
+    SPX_TRY(tmp.get(&sc.chunks, (size_t)sc.z.cap_chunks, "sort chunks"));
+    uint32_t* ctr;
+    SPX_TRY(tmp.get(&ctr, 8, "sort counters"));
+    sc.counters = ctr;
 
     HIP_TRY(launch_init_readback(rb_dev, s));
     if (spx_is_bcoh(fmt))
@@ -217,8 +229,10 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
                             coo->n);
     const uint64_t vary = rb.masks[0] ^ rb.masks[1];
     const uint64_t* vs = nullptr;
-    HIP_TRY(radix_sort_pairs(k0, v0, k1, v1, (const uint64_t*)coo->val, E, vary, hist, tsums, s,
-                             &out->keys, &vs));
+    int failed = 0;
+    HIP_TRY(radix_sort_msd(k0, v0, k1, v1, (const uint64_t*)coo->val, E, vary, sc, s, &out->keys,
+                           &vs, &failed, &out->sort));
+    if (failed) return fail(SPX_ERR_DEVICE, "radix sort: a device-side list overflowed");
     out->vals = (const double*)vs;
     if (!sum_dup) {
         out->head_tiles = nullptr;
@@ -381,6 +395,7 @@ static spx_status convert_bcoh(const spx_coo_desc* coo, spx_format fmt, int k, i
 
     SortedEntries se;
     if (E > 0) SPX_TRY(sort_and_dedup(tmp, coo, fmt, k, 0, 0, 1, s, &se, part_of, K2));
+    A->sort = se.sort;
     const int64_t nnz = se.nnz_out;
     A->nnz = nnz;
     double* val_out;
@@ -481,6 +496,7 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
 
     SortedEntries se;
     if (E > 0) SPX_TRY(sort_and_dedup(tmp, coo, fmt, k, nbc, cbits, o->sum_duplicates, s, &se));
+    A->sort = se.sort;
     const int64_t nnz = se.nnz_out;
     A->nnz = nnz;
 
@@ -750,6 +766,8 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
         rep->bytes = A->bytes;
         rep->log2_beta = A->log2_beta;
         rep->parts = (int32_t)A->parts;
+        rep->sort_split_keys = A->sort.split_keys;
+        rep->sort_levels = A->sort.levels;
         (void)hipEventDestroy(ev0);
         (void)hipEventDestroy(ev1);
     }

@@ -42,12 +42,19 @@
 #endif
 #define RSORT_TILE (RSORT_NT * RSORT_IPT)
 
+// statistics of the conversion sort (MSD radix sort with an LDS finish)
+struct MsdStats {
+    int32_t levels = 0;       // split levels run
+    int64_t split_keys = 0;   // keys moved by them, summed over the levels
+};
+
 struct spx_matrix_s {
     int32_t m = 0, n = 0;
     int64_t nnz = 0;
     spx_format fmt = 0;
     int32_t log2_beta = 0;
     int device = 0;
+    MsdStats sort;  // the conversion sort's split levels
     int64_t bytes = 0;
     hipStream_t last_stream = nullptr;
     // CRS formats
@@ -185,6 +192,33 @@ hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* 
                             uint32_t* tile_sums, hipStream_t s, const uint64_t** keys_sorted,
                             const uint64_t** vals_sorted, bool hot_sample = false);
 size_t radix_hist_elems(int64_t E);
+// MSD radix sort with an LDS finish (the conversion sort): same result as radix_sort_pairs (a
+// stable sort by the full key), sorted arrays returned in (k1, v1).  Scratch sizes from
+// msd_sizes(E); *failed is set when a device-side list overflowed (not expected by the bounds).
+struct MsdChunk {
+    int64_t start;
+    uint32_t len;
+    uint32_t meta;  // bits below which the chunk is unsorted | source buffer << 8
+};
+struct MsdSizes {
+    int64_t cap_big = 0, cap_tiles = 0, cap_chunks = 0, hist = 0, tile_sums = 0;
+};
+struct MsdScratch {
+    MsdSizes z;
+    int64_t* seg_start[2] = {nullptr, nullptr};
+    uint32_t* seg_len[2] = {nullptr, nullptr};
+    uint32_t* tbase = nullptr;     // cap_big + 1
+    uint32_t* tile_seg = nullptr;  // cap_tiles
+    uint32_t* hist = nullptr;      // z.hist
+    uint32_t* tile_sums = nullptr; // z.tile_sums
+    MsdChunk* chunks = nullptr;    // cap_chunks
+    void* counters = nullptr;      // 20 bytes
+};
+MsdSizes msd_sizes(int64_t E);
+hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1,
+                          const uint64_t* vfirst, int64_t E, uint64_t vary, const MsdScratch& sc,
+                          hipStream_t s, const uint64_t** keys_sorted,
+                          const uint64_t** vals_sorted, int* failed, MsdStats* stats);
 hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_sums,
                               uint32_t* total, hipStream_t s);
 // Fused: scan of run heads (tile counts from launch_dedup_count) + run sums + index/value

@@ -17,7 +17,8 @@ LIB_PATH = os.environ.get("SPX_LIBRARY") or os.path.join(_PKG, "libspx.so")
 
 SPX_OK = 0
 STATUS = {0: "SPX_OK", -1: "SPX_ERR_INVALID_ARG", -2: "SPX_ERR_INDEX", -3: "SPX_ERR_RANGE",
-          -4: "SPX_ERR_ALIAS", -5: "SPX_ERR_NOMEM", -6: "SPX_ERR_HIP", -7: "SPX_ERR_UNSUPPORTED"}
+          -4: "SPX_ERR_ALIAS", -5: "SPX_ERR_NOMEM", -6: "SPX_ERR_HIP", -7: "SPX_ERR_UNSUPPORTED",
+          -8: "SPX_ERR_DEVICE"}
 FORMATS = {"rowsplit": 0, "merge": 1, "csbh": 2, "csb": 3, "bcohc": 4, "bcohch": 5}
 FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
 LAYOUTS = {"col": 0, "row": 1}
@@ -50,7 +51,8 @@ class ConvertOpts(ctypes.Structure):
 class ConvertReport(ctypes.Structure):
     _fields_ = [("convert_ms", ctypes.c_float), ("nnz_out", ctypes.c_int64),
                 ("bytes", ctypes.c_int64), ("log2_beta", ctypes.c_int32),
-                ("parts", ctypes.c_int32)]
+                ("parts", ctypes.c_int32), ("sort_split_keys", ctypes.c_int64),
+                ("sort_levels", ctypes.c_int32)]
 
 
 class MatrixInfo(ctypes.Structure):
@@ -275,6 +277,8 @@ class Matrix:
         self._h = handle
         self.format = fmt
         self.convert_ms = float(report.convert_ms)
+        self.sort_split_keys = int(report.sort_split_keys)
+        self.sort_levels = int(report.sort_levels)
         info = MatrixInfo()
         _check(load().spx_matrix_get_info(self._h, ctypes.byref(info)))
         self.shape = (info.m, info.n)
