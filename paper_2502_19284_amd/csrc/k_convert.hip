@@ -1,10 +1,10 @@
 // k_convert.hip -- triplet -> format conversion kernels (gfx950).
 //
 // The conversion follows the two steps of Section 5.1: (1) sort the entries into the order the
-// format needs, (2) fill and compress the format's arrays.  Step 1 is a stable LSD radix sort of
-// a 64-bit key that carries each triplet's value along; step 2 sums repeated coordinates in
-// increasing triplet index and turns per-row (per-block) end marks into row_ptr (blk_ptr) with a
-// max-scan.
+// format needs, (2) fill and compress the format's arrays.  Step 1 is a stable radix sort of a
+// 64-bit key that carries each triplet's value along (MSD levels split the keys into segments of
+// at most 4096, each finished in LDS); step 2 sums repeated coordinates in increasing triplet
+// index and turns per-row (per-block) end marks into row_ptr (blk_ptr) with a max-scan.
 #include "dev_curves.h"
 #include "dev_scan.h"
 #include "spx_internal.h"
@@ -351,8 +351,7 @@ __device__ __forceinline__ void rsort_downsweep(
     rs_scatter_tile(kin, vin, kout, vout, lo, n, shift, GOffLsd{hist, tiles, tile});
 }
 
-// The conversion's own sort and the sort of the hot-column sample run the same code under
-// different kernel names, so that per-kernel timings and counters keep them apart.
+// LSD kernels: they sort the hot-column sample (the conversion itself uses the MSD sort below).
 #define RSORT_KERNELS(UP, DOWN)                                                                 \
     __global__ __launch_bounds__(RSORT_NT) void UP(const uint64_t* __restrict__ keys, int64_t E, \
                                                    int shift, uint32_t* __restrict__ hist,      \
@@ -365,7 +364,6 @@ __device__ __forceinline__ void rsort_downsweep(
         const uint32_t* __restrict__ hist, int64_t tiles) {                                     \
         rsort_downsweep(kin, vin, kout, vout, E, shift, hist, tiles);                           \
     }
-RSORT_KERNELS(k_rsort_upsweep, k_rsort_downsweep)
 RSORT_KERNELS(k_hot_rsort_upsweep, k_hot_rsort_downsweep)
 #undef RSORT_KERNELS
 
@@ -381,7 +379,7 @@ struct StoreExclU32 {
 hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1,
                             const uint64_t* vfirst, int64_t E, uint64_t vary, uint32_t* hist,
                             uint32_t* tile_sums, hipStream_t s, const uint64_t** keys_sorted,
-                            const uint64_t** vals_sorted, bool hot_sample) {
+                            const uint64_t** vals_sorted) {
     *keys_sorted = k0;
     *vals_sorted = vfirst;
     if (E <= 0) return hipSuccess;
@@ -394,24 +392,16 @@ hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* 
     uint64_t* vnext = v0;
     for (int shift = 0; shift < 64; shift += RS_RADIX_BITS) {
         if (((vary >> shift) & 0xFFull) == 0) continue;  // digit constant: order unchanged
-        if (hot_sample)
-            SPX_LAUNCH("hot_rsort_upsweep", k_hot_rsort_upsweep, dim3((unsigned)tiles),
-                       dim3(RSORT_NT), 0, s, kin, E, shift, hist, tiles);
-        else
-            SPX_LAUNCH("rsort_upsweep", k_rsort_upsweep, dim3((unsigned)tiles),
-                       dim3(RSORT_NT), 0, s, kin, E, shift, hist, tiles);
+        SPX_LAUNCH("hot_rsort_upsweep", k_hot_rsort_upsweep, dim3((unsigned)tiles),
+                   dim3(RSORT_NT), 0, s, kin, E, shift, hist, tiles);
         hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32{hist}, hn, tile_sums,
                                                                (uint32_t*)nullptr, s);
         if (e != hipSuccess) return e;
         e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32{hist}, StoreExclU32{hist}, hn,
                                                    tile_sums, s);
         if (e != hipSuccess) return e;
-        if (hot_sample)
-            SPX_LAUNCH("hot_rsort_downsweep", k_hot_rsort_downsweep, dim3((unsigned)tiles),
-                       dim3(RSORT_NT), 0, s, kin, vin, kout, vout, E, shift, hist, tiles);
-        else
-            SPX_LAUNCH("rsort_downsweep", k_rsort_downsweep, dim3((unsigned)tiles),
-                       dim3(RSORT_NT), 0, s, kin, vin, kout, vout, E, shift, hist, tiles);
+        SPX_LAUNCH("hot_rsort_downsweep", k_hot_rsort_downsweep, dim3((unsigned)tiles),
+                   dim3(RSORT_NT), 0, s, kin, vin, kout, vout, E, shift, hist, tiles);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint64_t* kt = kin;

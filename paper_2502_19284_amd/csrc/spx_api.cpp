@@ -300,7 +300,7 @@ static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot
         HIP_TRY(launch_hot_sample(keys, stride, ns, cmask, s0, s));
         const uint64_t *sorted, *unused;
         HIP_TRY(radix_sort_pairs(s0, p0, s1, p1, s0, ns, cmask, shist, stsums, s, &sorted,
-                                 &unused, true));
+                                 &unused));
         HIP_TRY(launch_hot_count_sorted(sorted, ns, freq, s));
     }
     Readback rb;

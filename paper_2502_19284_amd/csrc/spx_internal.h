@@ -186,11 +186,11 @@ hipError_t launch_keys_csb(const int32_t* row, const int32_t* col, int64_t E, in
 // Stable LSD radix sort of (keys in k0, 64-bit payloads read from vfirst).  Digits whose bits
 // never vary (per `vary`) are skipped.  k1, v0, v1 are scratch of E elements; the sorted arrays
 // are returned through keys_sorted / vals_sorted (one of the buffers, or vfirst if no pass ran).
-// hot_sample selects the separately named kernels used for the hot-column sample.
+// Used for the hot-column sample; its kernels carry hot_ names.
 hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1,
                             const uint64_t* vfirst, int64_t E, uint64_t vary, uint32_t* hist,
                             uint32_t* tile_sums, hipStream_t s, const uint64_t** keys_sorted,
-                            const uint64_t** vals_sorted, bool hot_sample = false);
+                            const uint64_t** vals_sorted);
 size_t radix_hist_elems(int64_t E);
 // MSD radix sort with an LDS finish (the conversion sort): same result as radix_sort_pairs (a
 // stable sort by the full key), sorted arrays returned in (k1, v1).  Scratch sizes from
