@@ -108,6 +108,21 @@ def _cases():
     # a single entry in the last row and column
     cases["corner"] = (1000, 999, np.array([999], np.int32), np.array([998], np.int32),
                        np.array([-1.5]))
+    # more than 4096 repeats of two coordinates among other entries, scrambled: the sort's
+    # segments of equal keys that stay larger than one workgroup's share after the last digit
+    rng = np.random.default_rng(11)
+    r = np.concatenate([np.full(9000, 5), np.full(6000, 999), rng.integers(0, 1000, 30000)])
+    c = np.concatenate([np.full(9000, 7), np.zeros(6000), rng.integers(0, 1000, 30000)])
+    perm = rng.permutation(len(r))
+    cases["long_repeats"] = (1000, 1000, r[perm].astype(np.int32), c[perm].astype(np.int32),
+                             synth.values(len(r), seed=11))
+    # one row of 20000 entries among 40000 scattered ones in a 70000 x 70000 matrix: split
+    # levels over row digits, then over column digits inside the long row
+    r = np.concatenate([np.full(20000, 3), rng.integers(0, 70000, 40000)])
+    c = np.concatenate([rng.integers(0, 70000, 20000), rng.integers(0, 70000, 40000)])
+    perm = rng.permutation(len(r))
+    cases["deep_split"] = (70000, 70000, r[perm].astype(np.int32), c[perm].astype(np.int32),
+                           synth.values(len(r), seed=12))
     return cases
 
 
