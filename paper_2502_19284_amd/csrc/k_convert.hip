@@ -205,9 +205,28 @@ __device__ __forceinline__ int64_t rs_tile_of(int64_t b, int64_t tiles) {
     return x * q + (x < r ? x : r) + i;
 }
 
+// Key sources of the counting and scatter passes: a key array, or CRS keys built from triplets
+// (row << cbits | col; 0 for an index outside the matrix, which is reported separately).
+struct KeyArr {
+    const uint64_t* k;
+    __device__ uint64_t operator()(int64_t i) const { return k[i]; }
+};
+struct KeyFromCsr {
+    const int32_t* row;
+    const int32_t* col;
+    int32_t m, n;
+    int cbits;
+    __device__ uint64_t operator()(int64_t i) const {
+        const int32_t r = row[i], c = col[i];
+        const bool ok = (r >= 0) & (r < m) & (c >= 0) & (c < n);
+        return ok ? ((uint64_t)(uint32_t)r << cbits) | (uint64_t)(uint32_t)c : 0ull;
+    }
+};
+
 // Digit counts of keys[lo, lo + n), n <= RSORT_TILE: digit d's count is stored at hist[hb + d * hs].
-__device__ __forceinline__ void rs_count_tile(const uint64_t* __restrict__ keys, int64_t lo, int n,
-                                              int shift, uint32_t* __restrict__ hist, int64_t hb,
+template <typename KeyLoad>
+__device__ __forceinline__ void rs_count_tile(KeyLoad keys, int64_t lo, int n, int shift,
+                                              uint32_t* __restrict__ hist, int64_t hb,
                                               int64_t hs) {
     __shared__ uint32_t cnt[RSORT_WAVES][256];
     for (int i = threadIdx.x; i < RSORT_WAVES * 256; i += RSORT_NT) (&cnt[0][0])[i] = 0;
@@ -216,7 +235,7 @@ __device__ __forceinline__ void rs_count_tile(const uint64_t* __restrict__ keys,
 #pragma unroll
     for (int i = 0; i < RSORT_IPT; ++i) {
         const int j = i * RSORT_NT + threadIdx.x;
-        if (j < n) atomicAdd(&cnt[w][(uint32_t)(keys[lo + j] >> shift) & 255u], 1u);
+        if (j < n) atomicAdd(&cnt[w][(uint32_t)(keys(lo + j) >> shift) & 255u], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < 256; d += RSORT_NT) {
@@ -229,9 +248,8 @@ __device__ __forceinline__ void rs_count_tile(const uint64_t* __restrict__ keys,
 
 // Stable scatter of the tile keys[lo, lo + n) (with payloads) by digit: the keys of digit d go,
 // in tile order, to kout[goff_of(d) ...].  goff_of is called once per digit.
-template <typename GOff>
-__device__ __forceinline__ void rs_scatter_tile(const uint64_t* __restrict__ kin,
-                                                const uint64_t* __restrict__ vin,
+template <typename KeyLoad, typename GOff>
+__device__ __forceinline__ void rs_scatter_tile(KeyLoad kin, const uint64_t* __restrict__ vin,
                                                 uint64_t* __restrict__ kout,
                                                 uint64_t* __restrict__ vout, int64_t lo, int n,
                                                 int shift, GOff goff_of) {
@@ -256,7 +274,7 @@ __device__ __forceinline__ void rs_scatter_tile(const uint64_t* __restrict__ kin
     for (int r = 0; r < RSORT_ROUNDS; ++r) {
         const int j = wave_off + r * SPX_WAVE + lane;
         const bool valid = j < n;
-        key[r] = valid ? kin[lo + j] : 0ull;
+        key[r] = valid ? kin(lo + j) : 0ull;
         val[r] = valid ? vin[lo + j] : 0ull;  // payload fetched early, written after the keys
         const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
@@ -338,7 +356,7 @@ __device__ __forceinline__ void rsort_upsweep(const uint64_t* __restrict__ keys,
     const int64_t tile = rs_tile_of(blockIdx.x, tiles);
     const int64_t lo = tile * RSORT_TILE;
     const int n = E - lo < RSORT_TILE ? (int)(E - lo) : RSORT_TILE;
-    rs_count_tile(keys, lo, n, shift, hist, tile, tiles);
+    rs_count_tile(KeyArr{keys}, lo, n, shift, hist, tile, tiles);
 }
 
 __device__ __forceinline__ void rsort_downsweep(
@@ -348,7 +366,7 @@ __device__ __forceinline__ void rsort_downsweep(
     const int64_t tile = rs_tile_of(blockIdx.x, tiles);
     const int64_t lo = tile * RSORT_TILE;
     const int n = E - lo < RSORT_TILE ? (int)(E - lo) : RSORT_TILE;
-    rs_scatter_tile(kin, vin, kout, vout, lo, n, shift, GOffLsd{hist, tiles, tile});
+    rs_scatter_tile(KeyArr{kin}, vin, kout, vout, lo, n, shift, GOffLsd{hist, tiles, tile});
 }
 
 // LSD kernels: they sort the hot-column sample (the conversion itself uses the MSD sort below).
@@ -433,24 +451,26 @@ hipError_t radix_sort_pairs(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* 
 // Buffers: level p reads B_p and writes B_{p+1}; B_0 = (k0, vfirst), B_odd = (k1, v1),
 // B_even>0 = (k0, v0).  The output is (k1, v1).  A chunk records which buffer holds it.
 
-#ifndef RS_LOCAL_MAX
-#define RS_LOCAL_MAX RSORT_TILE
-#endif
 
 struct MsdCounters {
-    uint32_t nbig, ntiles, nchunks, err, bigkeys;
+    uint32_t nbig, ntiles, nchunks, err, bigkeys, pad;
+    unsigned long long kor, kand;  // OR and AND of the keys (CRS keys built in the first level)
 };
 
-__global__ void k_msd_init(int64_t E, int64_t* seg_start, uint32_t* seg_len, MsdChunk* chunks,
-                           MsdCounters* ctr) {
+__global__ void k_msd_init(int64_t E, int64_t* seg_start, uint32_t* seg_len, uint32_t* tbase,
+                           MsdChunk* chunks, MsdCounters* ctr) {
     ctr->nbig = 0;
     ctr->ntiles = 0;
     ctr->nchunks = 0;
     ctr->err = 0;
     ctr->bigkeys = 0;
+    ctr->kor = 0ull;
+    ctr->kand = ~0ull;
     if (E > RS_LOCAL_MAX) {
         seg_start[0] = 0;
         seg_len[0] = (uint32_t)E;
+        tbase[0] = 0;  // the first level's table, for a first level that skips the tile scan
+        tbase[1] = (uint32_t)((E + RSORT_TILE - 1) / RSORT_TILE);
     } else {
         chunks[0] = MsdChunk{0, (uint32_t)E, 64u};  // all bits, source B_0
         ctr->nchunks = 1;
@@ -520,7 +540,7 @@ __global__ __launch_bounds__(RSORT_NT) void k_msd_count(const uint64_t* __restri
                                                         uint32_t T, int shift,
                                                         uint32_t* __restrict__ hist) {
     const MsdTile m = msd_tile(seg_start, seg_len, tbase, tile_seg, T);
-    rs_count_tile(keys, m.lo, m.n, shift, hist, m.hb, m.hs);
+    rs_count_tile(KeyArr{keys}, m.lo, m.n, shift, hist, m.hb, m.hs);
 }
 
 struct GOffMsd {  // segment start + scanned (segment, digit, tile) entry - segment's first entry
@@ -539,7 +559,91 @@ __global__ __launch_bounds__(RSORT_NT) void k_msd_scatter(
     int shift, const uint32_t* __restrict__ hist) {
     const MsdTile m = msd_tile(seg_start, seg_len, tbase, tile_seg, T);
     const int64_t base = m.start - (int64_t)hist[m.h0];
-    rs_scatter_tile(kin, vin, kout, vout, m.lo, m.n, shift, GOffMsd{hist, m.hb, m.hs, base});
+    rs_scatter_tile(KeyArr{kin}, vin, kout, vout, m.lo, m.n, shift, GOffMsd{hist, m.hb, m.hs, base});
+}
+
+// First level of a CRS conversion, straight from the triplets: digit counts of the tile (one
+// segment [0, E), equal tiles in the XCD order), the OR / AND of the keys and the index check.
+__global__ __launch_bounds__(RSORT_NT) void k_msd_count0_csr(KeyFromCsr kf, int64_t E, int shift,
+                                                             uint32_t T0,
+                                                             uint32_t* __restrict__ hist,
+                                                             MsdCounters* ctr) {
+    __shared__ uint32_t cnt[RSORT_WAVES][256];
+    __shared__ unsigned long long s_or[RSORT_WAVES], s_and[RSORT_WAVES];
+    __shared__ uint32_t s_bad[RSORT_WAVES];
+    for (int i = threadIdx.x; i < RSORT_WAVES * 256; i += RSORT_NT) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int w = threadIdx.x / SPX_WAVE;
+    const int64_t g = rs_tile_of(blockIdx.x, T0);
+    const int64_t lo = g * RSORT_TILE;
+    const int n = E - lo < RSORT_TILE ? (int)(E - lo) : RSORT_TILE;
+    unsigned long long orv = 0ull, andv = ~0ull;
+    uint32_t bad = 0;
+#pragma unroll
+    for (int i = 0; i < RSORT_IPT; ++i) {
+        const int j = i * RSORT_NT + threadIdx.x;
+        if (j < n) {
+            const int32_t r = kf.row[lo + j], c = kf.col[lo + j];
+            const bool ok = (r >= 0) & (r < kf.m) & (c >= 0) & (c < kf.n);
+            const uint64_t key =
+                ok ? ((uint64_t)(uint32_t)r << kf.cbits) | (uint64_t)(uint32_t)c : 0ull;
+            bad |= ok ? 0u : 1u;
+            orv |= key;
+            andv &= key;
+            atomicAdd(&cnt[w][(uint32_t)(key >> shift) & 255u], 1u);
+        }
+    }
+    orv = wave_reduce<unsigned long long, OpOr<unsigned long long>>(orv);
+    andv = wave_reduce<unsigned long long, OpAnd<unsigned long long>>(andv);
+    const uint64_t anybad = __ballot(bad != 0);
+    if (__lane_id() == 0) {
+        s_or[w] = orv;
+        s_and[w] = andv;
+        s_bad[w] = anybad ? 1u : 0u;
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < 256; d += RSORT_NT) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int ww = 0; ww < RSORT_WAVES; ++ww) c += cnt[ww][d];
+        hist[(int64_t)d * T0 + g] = c;
+    }
+    if (threadIdx.x == 0) {
+        uint32_t b = 0;
+        for (int ww = 0; ww < RSORT_WAVES; ++ww) {
+            orv |= s_or[ww];
+            andv &= s_and[ww];
+            b |= s_bad[ww];
+        }
+        // OR only gains bits and AND only loses them, so a value read here (however stale)
+        // that already agrees makes the atomic a no-op: most workgroups skip it, and the two
+        // words are not hammered by every tile
+        const unsigned long long cur_or = ctr->kor, cur_and = ctr->kand;
+        if ((cur_or | orv) != cur_or) atomicOr(&ctr->kor, orv);
+        if ((cur_and & andv) != cur_and) atomicAnd(&ctr->kand, andv);
+        if (b) atomicOr(&ctr->err, 1u);
+    }
+}
+
+__global__ __launch_bounds__(RSORT_NT) void k_msd_scatter0_csr(
+    KeyFromCsr kf, const uint64_t* __restrict__ vin, uint64_t* __restrict__ kout,
+    uint64_t* __restrict__ vout, int64_t E, int shift, uint32_t T0,
+    const uint32_t* __restrict__ hist) {
+    const int64_t g = rs_tile_of(blockIdx.x, T0);
+    const int64_t lo = g * RSORT_TILE;
+    const int n = E - lo < RSORT_TILE ? (int)(E - lo) : RSORT_TILE;
+    rs_scatter_tile(kf, vin, kout, vout, lo, n, shift, GOffLsd{hist, (int64_t)T0, g});
+}
+
+// Segments still large when no varying digit is left hold equal keys: copy chunks.
+__global__ void k_msd_flush(const int64_t* __restrict__ seg_start,
+                            const uint32_t* __restrict__ seg_len, uint32_t nb, uint32_t meta,
+                            MsdChunk* __restrict__ chunks, uint32_t cap_chunks, MsdCounters* ctr) {
+    const uint32_t sg = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sg >= nb) return;
+    const uint32_t i = atomicAdd(&ctr->nchunks, 1u);
+    if (i < cap_chunks) chunks[i] = MsdChunk{seg_start[sg], seg_len[sg], meta};
+    else atomicOr(&ctr->err, 8u);
 }
 
 // One wave per segment: the 256 part sizes go to LDS, lane 0 walks them in digit order, packing
@@ -827,21 +931,69 @@ static hipError_t msd_read(MsdCounters* host, const MsdCounters* dev, hipStream_
 hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1,
                           const uint64_t* vfirst, int64_t E, uint64_t vary, const MsdScratch& sc,
                           hipStream_t s, const uint64_t** keys_sorted,
-                          const uint64_t** vals_sorted, int* failed, MsdStats* stats) {
+                          const uint64_t** vals_sorted, int* failed, MsdStats* stats,
+                          const MsdCsrSource* csr) {
     *keys_sorted = k0;
     *vals_sorted = vfirst;
     *failed = 0;
     *stats = MsdStats{};
-    if (E <= 0 || vary == 0) return hipSuccess;  // no key differs: the input order stands
+    if (E <= 0) return hipSuccess;
+    if (!csr && vary == 0) return hipSuccess;  // no key differs: the input order stands
+    if (csr && E <= RS_LOCAL_MAX) return hipErrorInvalidValue;  // caller builds keys first
     MsdCounters* ctr = (MsdCounters*)sc.counters;
     MsdCounters h{};
     SPX_LAUNCH("msd_init", k_msd_init, dim3(1), dim3(1), 0, s, E, sc.seg_start[0], sc.seg_len[0],
-               sc.chunks, ctr);
+               sc.tbase, sc.chunks, ctr);
     uint32_t nb = E > RS_LOCAL_MAX ? 1u : 0u;
     uint32_t T = nb ? (uint32_t)spx_div_up(E, RSORT_TILE) : 0u;
     int p = 0;  // levels done
     int64_t level_keys = E;
-    for (int shift = 64 - RS_RADIX_BITS; shift >= 0 && nb > 0; shift -= RS_RADIX_BITS) {
+    int top = 64 - RS_RADIX_BITS;
+    hipError_t e;
+    if (csr) {
+        // first level from the triplets, on the top digit the matrix shape allows
+        const uint64_t kmax = ((uint64_t)(csr->m - 1) << csr->cbits) | (uint64_t)(csr->n - 1);
+        int tb = 0;
+        while (tb < 63 && (kmax >> (tb + 1)) != 0) ++tb;
+        const int shift0 = tb / RS_RADIX_BITS * RS_RADIX_BITS;
+        const KeyFromCsr kf{csr->row, csr->col, csr->m, csr->n, csr->cbits};
+        SPX_LAUNCH("msd_count", k_msd_count0_csr, dim3(T), dim3(RSORT_NT), 0, s, kf, E, shift0, T,
+                   sc.hist, ctr);
+        const int64_t hn = (int64_t)256 * T;
+        e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32{sc.hist}, hn, sc.tile_sums,
+                                                    (uint32_t*)nullptr, s);
+        if (e != hipSuccess) return e;
+        e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32{sc.hist}, StoreExclU32{sc.hist}, hn,
+                                                   sc.tile_sums, s);
+        if (e != hipSuccess) return e;
+        SPX_LAUNCH("msd_scatter", k_msd_scatter0_csr, dim3(T), dim3(RSORT_NT), 0, s, kf, vfirst,
+                   k1, v1, E, shift0, T, sc.hist);
+        SPX_LAUNCH("msd_next_level", k_msd_next_level, dim3(1), dim3(1), 0, s, ctr);
+        const uint32_t meta = (uint32_t)(shift0 + RS_RADIX_BITS) | (1u << 8);
+        SPX_LAUNCH("msd_classify", k_msd_classify, dim3(1), dim3(MSD_CLS_NT), 0, s,
+                   sc.seg_start[0], sc.seg_len[0], sc.tbase, 1u, sc.hist, shift0 == 0 ? 1 : 0,
+                   meta, sc.seg_start[1], sc.seg_len[1], (uint32_t)sc.z.cap_big, sc.chunks,
+                   (uint32_t)sc.z.cap_chunks, ctr);
+        e = msd_read(&h, ctr, s);
+        if (e != hipSuccess) return e;
+        if (h.err & 1u) {
+            *failed = 2;  // an index outside the matrix
+            return hipSuccess;
+        }
+        if (h.err) {
+            *failed = 1;
+            return hipSuccess;
+        }
+        vary = (uint64_t)(h.kor ^ h.kand);
+        stats->split_keys = E;
+        stats->levels = 1;
+        level_keys = h.bigkeys;
+        nb = h.nbig;
+        T = h.ntiles;
+        p = 1;
+        top = shift0 - RS_RADIX_BITS;
+    }
+    for (int shift = top; shift >= 0 && nb > 0; shift -= RS_RADIX_BITS) {
         if (((vary >> shift) & 0xFFull) == 0) continue;  // constant digit: no split
         const bool last = shift == 0 || (vary & ((1ull << shift) - 1ull)) == 0;
         const int cur = p & 1;
@@ -851,8 +1003,8 @@ hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1
         uint64_t* vout = (p & 1) ? v0 : v1;
         const uint32_t out_code = (p & 1) ? 2u : 1u;  // buffer that holds level p's output
         // tiles of the level's segments
-        hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(
-            LoadNt{sc.seg_len[cur]}, nb, sc.tile_sums, sc.tbase + nb, s);
+        e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadNt{sc.seg_len[cur]}, nb, sc.tile_sums,
+                                                    sc.tbase + nb, s);
         if (e != hipSuccess) return e;
         e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadNt{sc.seg_len[cur]},
                                                    StoreExclU32{sc.tbase}, nb, sc.tile_sums, s);
@@ -893,11 +1045,20 @@ hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1
         T = h.ntiles;
         ++p;
     }
-    hipError_t e = msd_read(&h, ctr, s);
-    if (e != hipSuccess) return e;
-    if (h.err || nb > 0) {  // nb > 0 only if a level could not run: not reachable
-        *failed = 1;
-        return hipSuccess;
+    if (p == 0) h.nchunks = 1;  // E <= RS_LOCAL_MAX: the single chunk written by k_msd_init
+    if (nb > 0) {
+        // large segments with no varying digit left (a first level on a digit that turned out
+        // to be the last varying one): equal keys, copied from the last level's output
+        const uint32_t meta = 64u | (((p - 1) & 1) ? 2u : 1u) << 8;
+        SPX_LAUNCH("msd_flush", k_msd_flush, dim3(spx_div_up(nb, 256)), dim3(256), 0, s,
+                   sc.seg_start[p & 1], sc.seg_len[p & 1], nb, meta, sc.chunks,
+                   (uint32_t)sc.z.cap_chunks, ctr);
+        e = msd_read(&h, ctr, s);
+        if (e != hipSuccess) return e;
+        if (h.err) {
+            *failed = 1;
+            return hipSuccess;
+        }
     }
     if (h.nchunks > 0)
         SPX_LAUNCH("msd_local", k_msd_local, dim3(h.nchunks), dim3(MSD_LNT), 0, s, sc.chunks,

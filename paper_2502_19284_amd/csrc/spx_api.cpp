@@ -184,6 +184,12 @@ struct SortedEntries {
     MsdStats sort;
 };
 
+static spx_status build_keys_and_sort(const spx_coo_desc* coo, spx_format fmt, int k, int64_t nbc,
+                                      int cbits, const int32_t* part_of, int K2, uint64_t* k0,
+                                      uint64_t* v0, uint64_t* k1, uint64_t* v1,
+                                      const MsdScratch& sc, Readback* rb_dev, hipStream_t s,
+                                      SortedEntries* out, const uint64_t** vs, int* failed);
+
 static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_format fmt, int k,
                                  int64_t nbc, int cbits, int sum_dup, hipStream_t s,
                                  SortedEntries* out, const int32_t* part_of = nullptr,
@@ -210,10 +216,45 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
     SPX_TRY(tmp.get(&sc.tile_sums, (size_t)sc.z.tile_sums, "scan tile sums"));
     SPX_TRY(tmp.get(&sc.chunks, (size_t)sc.z.cap_chunks, "sort chunks"));
     uint32_t* ctr;
-    SPX_TRY(tmp.get(&ctr, 8, "sort counters"));
+    SPX_TRY(tmp.get(&ctr, 16, "sort counters"));
     sc.counters = ctr;
 
     HIP_TRY(launch_init_readback(rb_dev, s));
+    const uint64_t* vs = nullptr;
+    int failed = 0;
+    if (!spx_is_bcoh(fmt) && !spx_is_csb(fmt) && E > RS_LOCAL_MAX) {
+        // CRS: the sort's first level builds the keys from the triplets (and checks them)
+        const MsdCsrSource src{coo->row, coo->col, coo->m, coo->n, cbits};
+        HIP_TRY(radix_sort_msd(k0, v0, k1, v1, (const uint64_t*)coo->val, E, 0, sc, s,
+                               &out->keys, &vs, &failed, &out->sort, &src));
+    } else {
+        SPX_TRY(build_keys_and_sort(coo, fmt, k, nbc, cbits, part_of, K2, k0, v0, k1, v1, sc,
+                                    rb_dev, s, out, &vs, &failed));
+    }
+    if (failed == 2)
+        return fail(SPX_ERR_INDEX, "a triplet index lies outside [0,%d) x [0,%d)", coo->m, coo->n);
+    if (failed) return fail(SPX_ERR_DEVICE, "radix sort: a device-side list overflowed");
+    out->vals = (const double*)vs;
+    if (!sum_dup) {
+        out->head_tiles = nullptr;
+        out->nnz_out = E;
+        return SPX_OK;
+    }
+    Readback rb;
+    HIP_TRY(launch_dedup_count(out->keys, E, tsums, &rb_dev->totals[0], s));
+    SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+    out->nnz_out = rb.totals[0];
+    out->head_tiles = tsums;
+    return SPX_OK;
+}
+
+// Keys by the format's key function (keys kernel, index check), then the sort.
+static spx_status build_keys_and_sort(const spx_coo_desc* coo, spx_format fmt, int k, int64_t nbc,
+                                      int cbits, const int32_t* part_of, int K2, uint64_t* k0,
+                                      uint64_t* v0, uint64_t* k1, uint64_t* v1,
+                                      const MsdScratch& sc, Readback* rb_dev, hipStream_t s,
+                                      SortedEntries* out, const uint64_t** vs, int* failed) {
+    const int64_t E = coo->nnz;
     if (spx_is_bcoh(fmt))
         HIP_TRY(launch_keys_bcoh(coo->row, coo->col, E, coo->m, coo->n, part_of, k, K2,
                                  fmt == SPX_BCOHCH, k0, &rb_dev->err, rb_dev->masks, s));
@@ -225,24 +266,13 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
                                 rb_dev->masks, s));
     Readback rb;
     SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
-    if (rb.err) return fail(SPX_ERR_INDEX, "a triplet index lies outside [0,%d) x [0,%d)", coo->m,
-                            coo->n);
-    const uint64_t vary = rb.masks[0] ^ rb.masks[1];
-    const uint64_t* vs = nullptr;
-    int failed = 0;
-    HIP_TRY(radix_sort_msd(k0, v0, k1, v1, (const uint64_t*)coo->val, E, vary, sc, s, &out->keys,
-                           &vs, &failed, &out->sort));
-    if (failed) return fail(SPX_ERR_DEVICE, "radix sort: a device-side list overflowed");
-    out->vals = (const double*)vs;
-    if (!sum_dup) {
-        out->head_tiles = nullptr;
-        out->nnz_out = E;
+    if (rb.err) {
+        *failed = 2;
         return SPX_OK;
     }
-    HIP_TRY(launch_dedup_count(out->keys, E, tsums, &rb_dev->totals[0], s));
-    SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
-    out->nnz_out = rb.totals[0];
-    out->head_tiles = tsums;
+    const uint64_t vary = rb.masks[0] ^ rb.masks[1];
+    HIP_TRY(radix_sort_msd(k0, v0, k1, v1, (const uint64_t*)coo->val, E, vary, sc, s, &out->keys,
+                           vs, failed, &out->sort));
     return SPX_OK;
 }
 

@@ -212,13 +212,26 @@ struct MsdScratch {
     uint32_t* hist = nullptr;      // z.hist
     uint32_t* tile_sums = nullptr; // z.tile_sums
     MsdChunk* chunks = nullptr;    // cap_chunks
-    void* counters = nullptr;      // 20 bytes
+    void* counters = nullptr;      // 40 bytes, 8-byte aligned
 };
+// CRS keys built from the triplets inside the sort's first level (row << cbits | col); only for
+// E > RS_LOCAL_MAX.  An index outside the matrix sets *failed = 2.
+struct MsdCsrSource {
+    const int32_t* row;
+    const int32_t* col;
+    int32_t m, n;
+    int cbits;
+};
+// segments of at most this many keys are finished in LDS by one workgroup
+#ifndef RS_LOCAL_MAX
+#define RS_LOCAL_MAX RSORT_TILE
+#endif
 MsdSizes msd_sizes(int64_t E);
 hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1,
                           const uint64_t* vfirst, int64_t E, uint64_t vary, const MsdScratch& sc,
                           hipStream_t s, const uint64_t** keys_sorted,
-                          const uint64_t** vals_sorted, int* failed, MsdStats* stats);
+                          const uint64_t** vals_sorted, int* failed, MsdStats* stats,
+                          const MsdCsrSource* csr = nullptr);
 hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_sums,
                               uint32_t* total, hipStream_t s);
 // Fused: scan of run heads (tile counts from launch_dedup_count) + run sums + index/value

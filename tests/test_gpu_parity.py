@@ -123,6 +123,13 @@ def _cases():
     perm = rng.permutation(len(r))
     cases["deep_split"] = (70000, 70000, r[perm].astype(np.int32), c[perm].astype(np.int32),
                            synth.values(len(r), seed=12))
+    # a large shape whose high row and column bits the entries never use (the CRS sort's first
+    # digit, chosen from the shape, is constant), and more than 4096 copies of one coordinate
+    cases["narrow_entries"] = (1 << 20, 1 << 20, rng.integers(0, 200, 9000).astype(np.int32),
+                               rng.integers(0, 300, 9000).astype(np.int32),
+                               synth.values(9000, seed=13))
+    cases["all_equal_large"] = (40, 50, np.full(7000, 17, np.int32), np.full(7000, 33, np.int32),
+                                synth.values(7000, seed=14))
     return cases
 
 
@@ -365,6 +372,23 @@ def test_error_paths(spx):
     with pytest.raises(spx.SpxError) as e:
         spx.convert(_dev(np.array([0, -1], np.int32), torch.int32), col, val, (5, 5), "csbh")
     assert e.value.name == "SPX_ERR_INDEX"
+    # the same checks with more triplets than one workgroup sorts alone (CRS keys are then built
+    # inside the sort)
+    big = 9000
+    r = np.arange(big, dtype=np.int32) % 5
+    c = np.arange(big, dtype=np.int32) % 7
+    v = _dev(np.ones(big), torch.float64)
+    for fmt in ("rowsplit", "merge"):
+        bad_r = r.copy()
+        bad_r[4321] = 5
+        with pytest.raises(spx.SpxError) as e:
+            spx.convert(_dev(bad_r, torch.int32), _dev(c, torch.int32), v, (5, 7), fmt)
+        assert e.value.name == "SPX_ERR_INDEX"
+        bad_c = c.copy()
+        bad_c[8999] = -1
+        with pytest.raises(spx.SpxError) as e:
+            spx.convert(_dev(r, torch.int32), _dev(bad_c, torch.int32), v, (5, 7), fmt)
+        assert e.value.name == "SPX_ERR_INDEX"
     A = spx.convert(_dev(np.array([0, 4], np.int32), torch.int32), col, val, (5, 5), "rowsplit")
     buf = torch.zeros(10, dtype=torch.float64, device="cuda")
     with pytest.raises(spx.SpxError) as e:
