@@ -15,28 +15,184 @@
 
 // ------------------------------------------------------------------ conversion
 
+// Raw entries per row.  A popular row would take one global atomic per entry on one address
+// (R-MAT's first row holds about 1 in 1000 entries), so every row has `copies` counters, in
+// arrays of m + 1, and workgroup g adds into copy g mod copies; k_bcoh_rows_sum adds the copies.
 __global__ void k_bcoh_rows(const int32_t* __restrict__ row, const int32_t* __restrict__ col,
                             int64_t E, int32_t m, int32_t n, uint32_t* __restrict__ counts,
-                            uint32_t* __restrict__ err) {
+                            int copies, uint32_t* __restrict__ err) {
+    uint32_t* mine = counts + (int64_t)(blockIdx.x % copies) * ((int64_t)m + 1);
     uint32_t bad = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t r = row[i], c = col[i];
         const bool ok = (r >= 0) & (r < m) & (c >= 0) & (c < n);
-        if (ok) atomicAdd(&counts[r], 1u);
+        if (ok) atomicAdd(&mine[r], 1u);
         bad |= ok ? 0u : 1u;
     }
     if (__ballot(bad != 0) && __lane_id() == 0) atomicOr(err, 1u);
 }
 
+__global__ void k_bcoh_rows_sum(uint32_t* __restrict__ counts, int32_t m, int copies) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= m;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t c = counts[r];
+        for (int q = 1; q < copies; ++q) c += counts[(int64_t)q * ((int64_t)m + 1) + r];
+        counts[r] = c;
+    }
+}
+
+int bcoh_row_copies(int32_t m) {
+    // up to 16 copies, at most 1 GiB of counters
+    int c = 16;
+    while (c > 1 && (int64_t)c * ((int64_t)m + 1) * 4 > (1ll << 30)) c >>= 1;
+    return c;
+}
+
 hipError_t launch_bcoh_rows(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
                             int32_t n, uint32_t* counts, uint32_t* err, hipStream_t s) {
     if (E <= 0) return hipSuccess;
+    const int copies = bcoh_row_copies(m);
     int64_t g = spx_div_up(E, 256);
     if (g > 8192) g = 8192;
     SPX_LAUNCH("bcoh_rows", k_bcoh_rows, dim3((unsigned)g), dim3(256), 0, s, row, col, E, m, n,
-               counts, err);
+               counts, copies, err);
+    if (copies > 1) {
+        int64_t gs = spx_div_up((int64_t)m + 1, 256);
+        if (gs > 65536) gs = 65536;
+        SPX_LAUNCH("bcoh_rows_sum", k_bcoh_rows_sum, dim3((unsigned)gs), dim3(256), 0, s, counts,
+                   m, copies);
+    }
     return hipGetLastError();
+}
+
+struct LoadU32B {
+    const uint32_t* p;
+    __device__ uint32_t operator()(int64_t i) const { return p[i]; }
+};
+
+struct StoreExclU32B {
+    uint32_t* p;
+    __device__ void operator()(int64_t i, uint32_t incl, uint32_t item) const {
+        p[i] = incl - item;
+    }
+};
+
+// Raw entries per row without one global atomic per entry (random atomics run at about 20 G/s
+// on this chip, so counting 2^28 entries that way costs ~14 ms): rows are bucketed by r >> wbits
+// (at most RC_BUCKETS buckets of 2^wbits <= 2^RC_WBITS_MAX rows) with one counting pass over
+// tiles of RC_TILE entries and one scatter of the row indices; then every bucket is counted in
+// LDS, in slices of about RC_SLICE entries (at most RC_SLICES per bucket), and written with plain
+// stores (one slice) or atomics (several).
+#define RC_TILE 65536
+#define RC_NT 1024
+#define RC_BUCKETS 4096
+#define RC_WBITS_MAX 14
+#define RC_SLICE (1 << 20)
+#define RC_SLICES 16
+
+int bcoh_row_bucket_bits(int32_t m) {  // -1: too many rows for the bucketed count
+    int w = 0;
+    while (w <= RC_WBITS_MAX && (((int64_t)m + (1ll << w) - 1) >> w) > RC_BUCKETS) ++w;
+    return w <= RC_WBITS_MAX ? w : -1;
+}
+
+__global__ __launch_bounds__(RC_NT) void k_rowc_hist(const int32_t* __restrict__ row,
+                                                     const int32_t* __restrict__ col, int64_t E,
+                                                     int32_t m, int32_t n, int wbits, int nbk,
+                                                     int64_t T, uint32_t* __restrict__ hist,
+                                                     uint32_t* __restrict__ err) {
+    __shared__ uint32_t cnt[RC_BUCKETS];
+    for (int i = threadIdx.x; i < nbk; i += RC_NT) cnt[i] = 0;
+    __syncthreads();
+    const int64_t t = blockIdx.x;
+    const int64_t lo = t * RC_TILE;
+    const int64_t hi = lo + RC_TILE < E ? lo + RC_TILE : E;
+    uint32_t bad = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += RC_NT) {
+        const int32_t r = row[i], c = col[i];
+        const bool ok = (r >= 0) & (r < m) & (c >= 0) & (c < n);
+        if (ok) atomicAdd(&cnt[r >> wbits], 1u);
+        bad |= ok ? 0u : 1u;
+    }
+    if (__ballot(bad != 0) && __lane_id() == 0) atomicOr(err, 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbk; b += RC_NT) hist[(int64_t)b * T + t] = cnt[b];
+}
+
+__global__ __launch_bounds__(RC_NT) void k_rowc_scatter(const int32_t* __restrict__ row,
+                                                        const int32_t* __restrict__ col,
+                                                        int64_t E, int32_t m, int32_t n,
+                                                        int wbits, int nbk, int64_t T,
+                                                        const uint32_t* __restrict__ hist,
+                                                        int32_t* __restrict__ rows_out) {
+    __shared__ uint32_t cur[RC_BUCKETS];
+    const int64_t t = blockIdx.x;
+    for (int b = threadIdx.x; b < nbk; b += RC_NT) cur[b] = hist[(int64_t)b * T + t];
+    __syncthreads();
+    const int64_t lo = t * RC_TILE;
+    const int64_t hi = lo + RC_TILE < E ? lo + RC_TILE : E;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += RC_NT) {
+        const int32_t r = row[i], c = col[i];
+        const bool ok = (r >= 0) & (r < m) & (c >= 0) & (c < n);
+        if (ok) rows_out[atomicAdd(&cur[r >> wbits], 1u)] = r;
+    }
+}
+
+// Workgroup (bucket b, slice q): positions [start_b, end_b) of rows_out hold bucket b's rows.
+__global__ __launch_bounds__(RC_NT) void k_rowc_count(const int32_t* __restrict__ rows_out,
+                                                      const uint32_t* __restrict__ hist,
+                                                      const uint32_t* __restrict__ total,
+                                                      int64_t T, int nbk, int wbits, int32_t m,
+                                                      uint32_t* __restrict__ counts) {
+    __shared__ uint32_t c[1 << RC_WBITS_MAX];
+    const int b = blockIdx.x / RC_SLICES, q = blockIdx.x % RC_SLICES;
+    const int64_t start = hist[(int64_t)b * T];
+    const int64_t end = b + 1 < nbk ? (int64_t)hist[(int64_t)(b + 1) * T] : (int64_t)*total;
+    const int64_t len = end - start;
+    int slices = (int)((len + RC_SLICE - 1) / RC_SLICE);
+    if (slices < 1) slices = 1;
+    if (slices > RC_SLICES) slices = RC_SLICES;
+    if (q >= slices) return;  // uniform over the workgroup
+    const int W = 1 << wbits;
+    for (int i = threadIdx.x; i < W; i += RC_NT) c[i] = 0;
+    __syncthreads();
+    const int64_t s0 = start + len * q / slices, s1 = start + len * (q + 1) / slices;
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += RC_NT) atomicAdd(&c[rows_out[i] & (W - 1)], 1u);
+    __syncthreads();
+    const int64_t r0 = (int64_t)b << wbits;
+    for (int i = threadIdx.x; i < W; i += RC_NT) {
+        if (r0 + i >= m) break;
+        if (slices == 1) counts[r0 + i] = c[i];
+        else if (c[i]) atomicAdd(&counts[r0 + i], c[i]);
+    }
+}
+
+hipError_t launch_bcoh_rows_bucketed(const int32_t* row, const int32_t* col, int64_t E,
+                                     int32_t m, int32_t n, int wbits, uint32_t* hist,
+                                     int32_t* rows_out, uint32_t* tile_sums, uint32_t* total,
+                                     uint32_t* counts, uint32_t* err, hipStream_t s) {
+    if (E <= 0) return hipSuccess;
+    const int nbk = (int)(((int64_t)m + (1ll << wbits) - 1) >> wbits);
+    const int64_t T = (E + RC_TILE - 1) / RC_TILE;
+    SPX_LAUNCH("bcoh_rows_hist", k_rowc_hist, dim3((unsigned)T), dim3(RC_NT), 0, s, row, col, E,
+               m, n, wbits, nbk, T, hist, err);
+    const int64_t hn = (int64_t)nbk * T;
+    hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32B{hist}, hn, tile_sums, total, s);
+    if (e != hipSuccess) return e;
+    e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32B{hist}, StoreExclU32B{hist}, hn, tile_sums,
+                                               s);
+    if (e != hipSuccess) return e;
+    SPX_LAUNCH("bcoh_rows_scatter", k_rowc_scatter, dim3((unsigned)T), dim3(RC_NT), 0, s, row,
+               col, E, m, n, wbits, nbk, T, hist, rows_out);
+    SPX_LAUNCH("bcoh_rows_count", k_rowc_count, dim3((unsigned)(nbk * RC_SLICES)), dim3(RC_NT), 0,
+               s, rows_out, hist, total, T, nbk, wbits, m, counts);
+    return hipGetLastError();
+}
+
+size_t bcoh_rows_hist_elems(int32_t m, int64_t E, int wbits) {
+    const int64_t nbk = ((int64_t)m + (1ll << wbits) - 1) >> wbits;
+    return (size_t)(nbk * ((E + RC_TILE - 1) / RC_TILE));
 }
 
 // Row r starts a partition when it is row 0, a multiple of BH_WINDOW, or when the raw entries
@@ -68,10 +224,6 @@ hipError_t launch_bcoh_partitions(const uint32_t* cum, int32_t m, uint32_t targe
                                                   s);
 }
 
-struct LoadU32B {
-    const uint32_t* p;
-    __device__ uint32_t operator()(int64_t i) const { return p[i]; }
-};
 struct StoreInclU32 {
     uint32_t* p;
     __device__ void operator()(int64_t i, uint32_t incl, uint32_t) const { p[i] = incl; }
@@ -203,12 +355,6 @@ hipError_t spmv_bcoh(const spx_matrix_s* A, const double* x, double* y, hipStrea
     return hipGetLastError();
 }
 
-struct StoreExclU32B {
-    uint32_t* p;
-    __device__ void operator()(int64_t i, uint32_t incl, uint32_t item) const {
-        p[i] = incl - item;
-    }
-};
 
 hipError_t launch_excl_scan_u32(const uint32_t* in, uint32_t* out, int64_t n,
                                 uint32_t* tile_sums, uint32_t* total, hipStream_t s) {
