@@ -15,57 +15,6 @@
 
 // ------------------------------------------------------------------ conversion
 
-// Raw entries per row.  A popular row would take one global atomic per entry on one address
-// (R-MAT's first row holds about 1 in 1000 entries), so every row has `copies` counters, in
-// arrays of m + 1, and workgroup g adds into copy g mod copies; k_bcoh_rows_sum adds the copies.
-__global__ void k_bcoh_rows(const int32_t* __restrict__ row, const int32_t* __restrict__ col,
-                            int64_t E, int32_t m, int32_t n, uint32_t* __restrict__ counts,
-                            int copies, uint32_t* __restrict__ err) {
-    uint32_t* mine = counts + (int64_t)(blockIdx.x % copies) * ((int64_t)m + 1);
-    uint32_t bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t r = row[i], c = col[i];
-        const bool ok = (r >= 0) & (r < m) & (c >= 0) & (c < n);
-        if (ok) atomicAdd(&mine[r], 1u);
-        bad |= ok ? 0u : 1u;
-    }
-    if (__ballot(bad != 0) && __lane_id() == 0) atomicOr(err, 1u);
-}
-
-__global__ void k_bcoh_rows_sum(uint32_t* __restrict__ counts, int32_t m, int copies) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= m;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t c = counts[r];
-        for (int q = 1; q < copies; ++q) c += counts[(int64_t)q * ((int64_t)m + 1) + r];
-        counts[r] = c;
-    }
-}
-
-int bcoh_row_copies(int32_t m) {
-    // up to 16 copies, at most 1 GiB of counters
-    int c = 16;
-    while (c > 1 && (int64_t)c * ((int64_t)m + 1) * 4 > (1ll << 30)) c >>= 1;
-    return c;
-}
-
-hipError_t launch_bcoh_rows(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
-                            int32_t n, uint32_t* counts, uint32_t* err, hipStream_t s) {
-    if (E <= 0) return hipSuccess;
-    const int copies = bcoh_row_copies(m);
-    int64_t g = spx_div_up(E, 256);
-    if (g > 8192) g = 8192;
-    SPX_LAUNCH("bcoh_rows", k_bcoh_rows, dim3((unsigned)g), dim3(256), 0, s, row, col, E, m, n,
-               counts, copies, err);
-    if (copies > 1) {
-        int64_t gs = spx_div_up((int64_t)m + 1, 256);
-        if (gs > 65536) gs = 65536;
-        SPX_LAUNCH("bcoh_rows_sum", k_bcoh_rows_sum, dim3((unsigned)gs), dim3(256), 0, s, counts,
-                   m, copies);
-    }
-    return hipGetLastError();
-}
-
 struct LoadU32B {
     const uint32_t* p;
     __device__ uint32_t operator()(int64_t i) const { return p[i]; }

@@ -401,29 +401,26 @@ static spx_status convert_bcoh(const spx_coo_desc* coo, spx_format fmt, int k, i
     HIP_TRY(launch_init_readback(rb_dev, s));
     uint32_t *counts, *cum, *tsums;
     int32_t *part_of, *part_row;
+    // more than 2^26 rows need at least 8192 partitions and 27 Hilbert levels: 68 key bits
     const int wbits = bcoh_row_bucket_bits(m);
-    const int copies = wbits >= 0 ? 1 : bcoh_row_copies(m);
-    SPX_TRY(tmp.get(&counts, (size_t)copies * ((size_t)m + 1), "row counts"));
+    if (wbits < 0) return fail(SPX_ERR_RANGE, "BCOHC sort key exceeds 64 bits (m = %d)", m);
+    SPX_TRY(tmp.get(&counts, (size_t)m + 1, "row counts"));
     SPX_TRY(tmp.get(&cum, (size_t)m + 1, "row count scan"));
     SPX_TRY(tmp.get(&part_of, (size_t)m + 1, "row partitions"));
     SPX_TRY(tmp.get(&part_row, (size_t)m + 2, "partition rows"));
     size_t tsn = scan_tile_count((int64_t)m + 2);
     if (scan_tile_count(E + 1) > tsn) tsn = scan_tile_count(E + 1);
-    const size_t rhn = wbits >= 0 ? bcoh_rows_hist_elems(m, E, wbits) : 0;
+    const size_t rhn = bcoh_rows_hist_elems(m, E, wbits);
     if (scan_tile_count((int64_t)rhn) > tsn) tsn = scan_tile_count((int64_t)rhn);
     SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
-    HIP_TRY(launch_fill_i32((int32_t*)counts, (int64_t)copies * ((int64_t)m + 1), 0, s));
-    if (wbits >= 0) {
-        uint32_t *rhist, *rtotal;
-        int32_t* rows_out;
-        SPX_TRY(tmp.get(&rhist, rhn > 0 ? rhn : 1, "row bucket histogram"));
-        SPX_TRY(tmp.get(&rows_out, (size_t)E, "rows by bucket"));
-        SPX_TRY(tmp.get(&rtotal, 1, "row bucket total"));
-        HIP_TRY(launch_bcoh_rows_bucketed(coo->row, coo->col, E, m, coo->n, wbits, rhist,
-                                          rows_out, tsums, rtotal, counts, &rb_dev->err, s));
-    } else {
-        HIP_TRY(launch_bcoh_rows(coo->row, coo->col, E, m, coo->n, counts, &rb_dev->err, s));
-    }
+    HIP_TRY(launch_fill_i32((int32_t*)counts, (int64_t)m + 1, 0, s));
+    uint32_t *rhist, *rtotal;
+    int32_t* rows_out;
+    SPX_TRY(tmp.get(&rhist, rhn > 0 ? rhn : 1, "row bucket histogram"));
+    SPX_TRY(tmp.get(&rows_out, (size_t)(E > 0 ? E : 1), "rows by bucket"));
+    SPX_TRY(tmp.get(&rtotal, 1, "row bucket total"));
+    HIP_TRY(launch_bcoh_rows_bucketed(coo->row, coo->col, E, m, coo->n, wbits, rhist, rows_out,
+                                      tsums, rtotal, counts, &rb_dev->err, s));
     HIP_TRY(launch_excl_scan_u32(counts, cum, m, tsums, &rb_dev->totals[1], s));
     const int64_t target64 = (E + BH_PARTS_TARGET - 1) / BH_PARTS_TARGET;
     const uint32_t target = (uint32_t)(target64 > (1 << 16) ? target64 : (1 << 16));

@@ -256,7 +256,7 @@ static inline bool spx_is_bcoh(spx_format f) { return f == SPX_BCOHC || f == SPX
 #define BH_PARTS_TARGET 2048 // partitions by entry count: target = max(2^16, ceil(E / this))
 // row counts of the raw triplets (validating every index; err set on a bad one)
 // Exact raw entries per row by bucketing (no per-entry global atomics); wbits from
-// bcoh_row_bucket_bits(m) (-1: use launch_bcoh_rows).  hist: bcoh_rows_hist_elems words,
+// bcoh_row_bucket_bits(m) (-1: more than 2^26 rows, beyond what a 64-bit BCOH key can hold).  hist: bcoh_rows_hist_elems words,
 // rows_out: E words, total: one word, counts: m + 1 zeroed words.
 int bcoh_row_bucket_bits(int32_t m);
 size_t bcoh_rows_hist_elems(int32_t m, int64_t E, int wbits);
@@ -264,11 +264,7 @@ hipError_t launch_bcoh_rows_bucketed(const int32_t* row, const int32_t* col, int
                                      int32_t m, int32_t n, int wbits, uint32_t* hist,
                                      int32_t* rows_out, uint32_t* tile_sums, uint32_t* total,
                                      uint32_t* counts, uint32_t* err, hipStream_t s);
-// counts must hold bcoh_row_copies(m) * (m + 1) zeroed words; on return counts[0..m] hold the
-// raw entries per row (the other copies are scratch)
-int bcoh_row_copies(int32_t m);
-hipError_t launch_bcoh_rows(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
-                            int32_t n, uint32_t* counts, uint32_t* err, hipStream_t s);
+
 // partitions from the exclusive row-count scan cum[0..m): part_of[r] for every row, part_row[p]
 // for every partition (part_row[P] = m written by the caller); *total = P
 hipError_t launch_bcoh_partitions(const uint32_t* cum, int32_t m, uint32_t target,

@@ -389,6 +389,11 @@ def test_error_paths(spx):
         with pytest.raises(spx.SpxError) as e:
             spx.convert(_dev(r, torch.int32), _dev(bad_c, torch.int32), v, (5, 7), fmt)
         assert e.value.name == "SPX_ERR_INDEX"
+    # BCOH keys of a matrix with more than 2^26 rows need more than 64 bits
+    for fmt in ("bcohc", "bcohch"):
+        with pytest.raises(spx.SpxError) as e:
+            spx.convert(row, col, val, ((1 << 26) + 1, 8), fmt)
+        assert e.value.name == "SPX_ERR_RANGE"
     A = spx.convert(_dev(np.array([0, 4], np.int32), torch.int32), col, val, (5, 5), "rowsplit")
     buf = torch.zeros(10, dtype=torch.float64, device="cuda")
     with pytest.raises(spx.SpxError) as e:
