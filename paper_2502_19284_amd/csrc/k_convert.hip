@@ -890,7 +890,8 @@ __global__ __launch_bounds__(MSD_LNT) void k_msd_local(
         }
         __syncthreads();
     }
-    // keys in order; payload of the input position j goes to the final position of j
+    // keys in order; the payload of input position j is staged at the final position of j (in
+    // the key buffer, whose last reads are behind the pass loop's barrier) and written in order
 #pragma unroll
     for (int r = 0; r < MSD_LROUNDS; ++r) {
         const int j = wave_off + r * SPX_WAVE + lane;
@@ -903,7 +904,13 @@ __global__ __launch_bounds__(MSD_LNT) void k_msd_local(
 #pragma unroll
     for (int r = 0; r < MSD_LROUNDS; ++r) {
         const int j = wave_off + r * SPX_WAVE + lane;
-        if (j < n) vf[c.start + sidx[j]] = val[r];
+        if (j < n) skey[sidx[j]] = val[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < MSD_LROUNDS; ++r) {
+        const int j = wave_off + r * SPX_WAVE + lane;
+        if (j < n) vf[c.start + j] = skey[j];
     }
 }
 
