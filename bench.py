@@ -78,9 +78,15 @@ def spmv_bytes(fmt, m, nnz, n_touched, A, val_bytes=8, vec_bytes=8):
 def kernel_bytes(name, E, nnz, m, split_keys, split_levels):
     """Algorithmic bytes per launch of conversion kernels (None when not modelled).
 
-    The sort's split levels move different numbers of keys (every key at the top levels, only
-    those of still-large segments below); split_keys / split_levels is their mean per launch."""
+    The sort's segmented split levels move different numbers of keys (every key at the top
+    levels, only those of still-large segments below); split_keys / split_levels is their mean
+    per launch.  A CRS conversion's first level reads the triplets instead (msd_*0_csr)."""
     per_level = split_keys / split_levels if split_levels else 0
+    if name == "msd_scatter0_csr":
+        # row + col + value read, key + value written
+        return 32 * E
+    if name == "msd_count0_csr":
+        return 8 * E
     if name == "msd_scatter":
         # read 8-byte key + 8-byte value, write both
         return 32 * per_level
@@ -670,9 +676,11 @@ def main():
                 conv_ms[f].append(A.convert_ms)
                 spmv_ms[f].append(e0.elapsed_time(e1))
                 info[f] = dict(nnz=A.nnz, parts=A.parts, log2_beta=A.log2_beta, bytes=A.bytes,
-                               sort_levels=A.sort_levels, sort_split_keys=A.sort_split_keys)
-                sort_split["keys"] += A.sort_split_keys
-                sort_split["levels"] += A.sort_levels
+                               sort_levels=A.sort_levels, sort_split_keys=A.sort_split_keys,
+                               sort_first_fused=A.sort_first_fused)
+                # segmented levels only (a fused first level runs under its own kernel names)
+                sort_split["keys"] += A.sort_split_keys - (E if A.sort_first_fused else 0)
+                sort_split["levels"] += A.sort_levels - (1 if A.sort_first_fused else 0)
             A.close()
 
     for i in range(args.warmup):

@@ -767,6 +767,7 @@ __global__ __launch_bounds__(MSD_CLS_NT) void k_msd_classify(
 #define MSD_LWAVES (MSD_LNT / SPX_WAVE)
 #define MSD_LROUNDS (RS_LOCAL_MAX / MSD_LNT)
 static_assert(MSD_LNT >= 256 && RS_LOCAL_MAX % MSD_LNT == 0, "local sort shape");
+static_assert(RS_LOCAL_MAX <= SCAN_TILE, "a chunk meets at most two tiles of head counts");
 
 // One workgroup per chunk: keys and payloads of at most RS_LOCAL_MAX positions, stable LSD
 // passes in LDS over the digits below `hi` that vary inside the chunk, then the keys and the
@@ -774,7 +775,7 @@ static_assert(MSD_LNT >= 256 && RS_LOCAL_MAX % MSD_LNT == 0, "local sort shape")
 // RS_LOCAL_MAX hold equal keys and are copied.
 __global__ __launch_bounds__(MSD_LNT) void k_msd_local(
     const MsdChunk* __restrict__ chunks, const uint64_t* k0, const uint64_t* vfirst,
-    const uint64_t* v0, uint64_t* kf, uint64_t* vf) {
+    const uint64_t* v0, uint64_t* kf, uint64_t* vf, uint32_t* __restrict__ head_tiles) {
     __shared__ uint64_t skey[RS_LOCAL_MAX];
     __shared__ uint16_t sidx[RS_LOCAL_MAX];
     __shared__ uint32_t wcnt[MSD_LWAVES][256];
@@ -807,14 +808,13 @@ __global__ __launch_bounds__(MSD_LNT) void k_msd_local(
     for (int r = 0; r < MSD_LROUNDS; ++r) {
         const int j = wave_off + r * SPX_WAVE + lane;
         key[r] = j < n ? ks[c.start + j] : 0ull;
-        val[r] = j < n ? vs[c.start + j] : 0ull;
         idx[r] = (uint32_t)j;
         if (j < n) {
             vor |= key[r];
             vand &= key[r];
         }
     }
-    // every load has landed before any thread can write the chunk back (it may be in place)
+    // the key loads have landed before any thread can write the chunk back (it may be in place)
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     vor = wave_reduce<uint64_t, OpOr<uint64_t>>(vor);
     vand = wave_reduce<uint64_t, OpAnd<uint64_t>>(vand);
@@ -890,6 +890,14 @@ __global__ __launch_bounds__(MSD_LNT) void k_msd_local(
         }
         __syncthreads();
     }
+    // payloads fetched after the passes (fewer live registers during them); every thread uses
+    // its loads before the barrier ahead of the payload writes, so an in-place chunk is read
+    // completely before it is written
+#pragma unroll
+    for (int r = 0; r < MSD_LROUNDS; ++r) {
+        const int j = wave_off + r * SPX_WAVE + lane;
+        val[r] = j < n ? vs[c.start + j] : 0ull;
+    }
     // keys in order; the payload of input position j is staged at the final position of j (in
     // the key buffer, whose last reads are behind the pass loop's barrier) and written in order
 #pragma unroll
@@ -898,9 +906,31 @@ __global__ __launch_bounds__(MSD_LNT) void k_msd_local(
         if (j < n) {
             kf[c.start + j] = key[r];
             sidx[idx[r]] = (uint16_t)j;
+            if (head_tiles) skey[j] = key[r];
         }
     }
     __syncthreads();
+    if (head_tiles) {
+        // run heads at positions 1..n-1 of the chunk (position 0 is settled by
+        // k_msd_heads_first), counted per SCAN_TILE of positions: a chunk meets at most two
+        const int64_t ta = c.start / SCAN_TILE;
+        uint32_t ha = 0, hb = 0;
+#pragma unroll
+        for (int r = 0; r < MSD_LROUNDS; ++r) {
+            const int j = wave_off + r * SPX_WAVE + lane;
+            if (j >= 1 && j < n && skey[j] != skey[j - 1]) {
+                if ((c.start + j) / SCAN_TILE == ta) ++ha;
+                else ++hb;
+            }
+        }
+        ha = wave_reduce<uint32_t, OpSum<uint32_t>>(ha);
+        hb = wave_reduce<uint32_t, OpSum<uint32_t>>(hb);
+        if (lane == 0) {
+            if (ha) atomicAdd(&head_tiles[ta], ha);
+            if (hb) atomicAdd(&head_tiles[ta + 1], hb);
+        }
+        __syncthreads();  // skey is reused for the payloads below
+    }
 #pragma unroll
     for (int r = 0; r < MSD_LROUNDS; ++r) {
         const int j = wave_off + r * SPX_WAVE + lane;
@@ -912,6 +942,17 @@ __global__ __launch_bounds__(MSD_LNT) void k_msd_local(
         const int j = wave_off + r * SPX_WAVE + lane;
         if (j < n) vf[c.start + j] = skey[j];
     }
+}
+
+// Position 0 of every chunk is a run head when it is position 0 of the array or its key differs
+// from the key before it (which another chunk wrote).
+__global__ void k_msd_heads_first(const MsdChunk* __restrict__ chunks, uint32_t nchunks,
+                                  const uint64_t* __restrict__ kf,
+                                  uint32_t* __restrict__ head_tiles) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nchunks) return;
+    const int64_t p = chunks[i].start;
+    if (p == 0 || kf[p] != kf[p - 1]) atomicAdd(&head_tiles[p / SCAN_TILE], 1u);
 }
 
 MsdSizes msd_sizes(int64_t E) {
@@ -939,13 +980,18 @@ hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1
                           const uint64_t* vfirst, int64_t E, uint64_t vary, const MsdScratch& sc,
                           hipStream_t s, const uint64_t** keys_sorted,
                           const uint64_t** vals_sorted, int* failed, MsdStats* stats,
-                          const MsdCsrSource* csr) {
+                          const MsdCsrSource* csr, uint32_t* head_tiles, int* heads_counted) {
     *keys_sorted = k0;
     *vals_sorted = vfirst;
     *failed = 0;
     *stats = MsdStats{};
+    if (heads_counted) *heads_counted = 0;
     if (E <= 0) return hipSuccess;
     if (!csr && vary == 0) return hipSuccess;  // no key differs: the input order stands
+    if (head_tiles) {
+        hipError_t e0 = launch_fill_i32((int32_t*)head_tiles, spx_div_up(E, SCAN_TILE), 0, s);
+        if (e0 != hipSuccess) return e0;
+    }
     if (csr && E <= RS_LOCAL_MAX) return hipErrorInvalidValue;  // caller builds keys first
     MsdCounters* ctr = (MsdCounters*)sc.counters;
     MsdCounters h{};
@@ -964,8 +1010,8 @@ hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1
         while (tb < 63 && (kmax >> (tb + 1)) != 0) ++tb;
         const int shift0 = tb / RS_RADIX_BITS * RS_RADIX_BITS;
         const KeyFromCsr kf{csr->row, csr->col, csr->m, csr->n, csr->cbits};
-        SPX_LAUNCH("msd_count", k_msd_count0_csr, dim3(T), dim3(RSORT_NT), 0, s, kf, E, shift0, T,
-                   sc.hist, ctr);
+        SPX_LAUNCH("msd_count0_csr", k_msd_count0_csr, dim3(T), dim3(RSORT_NT), 0, s, kf, E,
+                   shift0, T, sc.hist, ctr);
         const int64_t hn = (int64_t)256 * T;
         e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32{sc.hist}, hn, sc.tile_sums,
                                                     (uint32_t*)nullptr, s);
@@ -973,8 +1019,8 @@ hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1
         e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32{sc.hist}, StoreExclU32{sc.hist}, hn,
                                                    sc.tile_sums, s);
         if (e != hipSuccess) return e;
-        SPX_LAUNCH("msd_scatter", k_msd_scatter0_csr, dim3(T), dim3(RSORT_NT), 0, s, kf, vfirst,
-                   k1, v1, E, shift0, T, sc.hist);
+        SPX_LAUNCH("msd_scatter0_csr", k_msd_scatter0_csr, dim3(T), dim3(RSORT_NT), 0, s, kf,
+                   vfirst, k1, v1, E, shift0, T, sc.hist);
         SPX_LAUNCH("msd_next_level", k_msd_next_level, dim3(1), dim3(1), 0, s, ctr);
         const uint32_t meta = (uint32_t)(shift0 + RS_RADIX_BITS) | (1u << 8);
         SPX_LAUNCH("msd_classify", k_msd_classify, dim3(1), dim3(MSD_CLS_NT), 0, s,
@@ -994,6 +1040,7 @@ hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1
         vary = (uint64_t)(h.kor ^ h.kand);
         stats->split_keys = E;
         stats->levels = 1;
+        stats->first_fused = 1;
         level_keys = h.bigkeys;
         nb = h.nbig;
         T = h.ntiles;
@@ -1067,9 +1114,15 @@ hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1
             return hipSuccess;
         }
     }
-    if (h.nchunks > 0)
+    if (h.nchunks > 0) {
         SPX_LAUNCH("msd_local", k_msd_local, dim3(h.nchunks), dim3(MSD_LNT), 0, s, sc.chunks,
-                   (const uint64_t*)k0, vfirst, (const uint64_t*)v0, k1, v1);
+                   (const uint64_t*)k0, vfirst, (const uint64_t*)v0, k1, v1, head_tiles);
+        if (head_tiles) {
+            SPX_LAUNCH("msd_heads_first", k_msd_heads_first, dim3(spx_div_up(h.nchunks, 256)),
+                       dim3(256), 0, s, sc.chunks, h.nchunks, (const uint64_t*)k1, head_tiles);
+            if (heads_counted) *heads_counted = 1;
+        }
+    }
     *keys_sorted = k1;
     *vals_sorted = v1;
     return hipGetLastError();
@@ -1083,6 +1136,13 @@ struct LoadHead {
         return (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
     }
 };
+hipError_t launch_head_tiles_scan(uint32_t* tile_counts, int64_t E, uint32_t* total,
+                                  hipStream_t s) {
+    SPX_LAUNCH("scan_tile_sums", (scan_tile_sums<uint32_t, OpSum<uint32_t>>), dim3(1),
+               dim3(SCAN_NT), 0, s, tile_counts, spx_div_up(E, SCAN_TILE), total);
+    return hipGetLastError();
+}
+
 hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_sums,
                               uint32_t* total, hipStream_t s) {
     return scan_phase12<uint32_t, OpSum<uint32_t>>(LoadHead{keys}, E, tile_sums, total, s);

@@ -188,7 +188,8 @@ static spx_status build_keys_and_sort(const spx_coo_desc* coo, spx_format fmt, i
                                       int cbits, const int32_t* part_of, int K2, uint64_t* k0,
                                       uint64_t* v0, uint64_t* k1, uint64_t* v1,
                                       const MsdScratch& sc, Readback* rb_dev, hipStream_t s,
-                                      SortedEntries* out, const uint64_t** vs, int* failed);
+                                      SortedEntries* out, const uint64_t** vs, int* failed,
+                                      uint32_t* head_tiles, int* heads);
 
 static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_format fmt, int k,
                                  int64_t nbc, int cbits, int sum_dup, hipStream_t s,
@@ -221,15 +222,17 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
 
     HIP_TRY(launch_init_readback(rb_dev, s));
     const uint64_t* vs = nullptr;
-    int failed = 0;
+    int failed = 0, heads = 0;
     if (!spx_is_bcoh(fmt) && !spx_is_csb(fmt) && E > RS_LOCAL_MAX) {
         // CRS: the sort's first level builds the keys from the triplets (and checks them)
         const MsdCsrSource src{coo->row, coo->col, coo->m, coo->n, cbits};
         HIP_TRY(radix_sort_msd(k0, v0, k1, v1, (const uint64_t*)coo->val, E, 0, sc, s,
-                               &out->keys, &vs, &failed, &out->sort, &src));
+                               &out->keys, &vs, &failed, &out->sort, &src,
+                               sum_dup ? tsums : nullptr, &heads));
     } else {
         SPX_TRY(build_keys_and_sort(coo, fmt, k, nbc, cbits, part_of, K2, k0, v0, k1, v1, sc,
-                                    rb_dev, s, out, &vs, &failed));
+                                    rb_dev, s, out, &vs, &failed, sum_dup ? tsums : nullptr,
+                                    &heads));
     }
     if (failed == 2)
         return fail(SPX_ERR_INDEX, "a triplet index lies outside [0,%d) x [0,%d)", coo->m, coo->n);
@@ -241,7 +244,10 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
         return SPX_OK;
     }
     Readback rb;
-    HIP_TRY(launch_dedup_count(out->keys, E, tsums, &rb_dev->totals[0], s));
+    if (heads)  // run heads were counted per tile inside the sort
+        HIP_TRY(launch_head_tiles_scan(tsums, E, &rb_dev->totals[0], s));
+    else
+        HIP_TRY(launch_dedup_count(out->keys, E, tsums, &rb_dev->totals[0], s));
     SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
     out->nnz_out = rb.totals[0];
     out->head_tiles = tsums;
@@ -253,7 +259,8 @@ static spx_status build_keys_and_sort(const spx_coo_desc* coo, spx_format fmt, i
                                       int cbits, const int32_t* part_of, int K2, uint64_t* k0,
                                       uint64_t* v0, uint64_t* k1, uint64_t* v1,
                                       const MsdScratch& sc, Readback* rb_dev, hipStream_t s,
-                                      SortedEntries* out, const uint64_t** vs, int* failed) {
+                                      SortedEntries* out, const uint64_t** vs, int* failed,
+                                      uint32_t* head_tiles, int* heads) {
     const int64_t E = coo->nnz;
     if (spx_is_bcoh(fmt))
         HIP_TRY(launch_keys_bcoh(coo->row, coo->col, E, coo->m, coo->n, part_of, k, K2,
@@ -272,7 +279,7 @@ static spx_status build_keys_and_sort(const spx_coo_desc* coo, spx_format fmt, i
     }
     const uint64_t vary = rb.masks[0] ^ rb.masks[1];
     HIP_TRY(radix_sort_msd(k0, v0, k1, v1, (const uint64_t*)coo->val, E, vary, sc, s, &out->keys,
-                           vs, failed, &out->sort));
+                           vs, failed, &out->sort, nullptr, head_tiles, heads));
     return SPX_OK;
 }
 
@@ -809,6 +816,7 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
         rep->parts = (int32_t)A->parts;
         rep->sort_split_keys = A->sort.split_keys;
         rep->sort_levels = A->sort.levels;
+        rep->sort_first_fused = A->sort.first_fused;
         (void)hipEventDestroy(ev0);
         (void)hipEventDestroy(ev1);
     }

@@ -46,6 +46,7 @@
 struct MsdStats {
     int32_t levels = 0;       // split levels run
     int64_t split_keys = 0;   // keys moved by them, summed over the levels
+    int32_t first_fused = 0;  // 1: the first level built CRS keys from the triplets
 };
 
 struct spx_matrix_s {
@@ -231,7 +232,13 @@ hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1
                           const uint64_t* vfirst, int64_t E, uint64_t vary, const MsdScratch& sc,
                           hipStream_t s, const uint64_t** keys_sorted,
                           const uint64_t** vals_sorted, int* failed, MsdStats* stats,
-                          const MsdCsrSource* csr = nullptr);
+                          const MsdCsrSource* csr = nullptr, uint32_t* head_tiles = nullptr,
+                          int* heads_counted = nullptr);
+// head_tiles (nullable, ceil(E / SCAN_TILE) words): when *heads_counted comes back 1, it holds
+// the number of run heads (first keys of runs of equal keys) in each SCAN_TILE of sorted
+// positions, ready for launch_head_tiles_scan (exclusive offsets in place, total to *total).
+hipError_t launch_head_tiles_scan(uint32_t* tile_counts, int64_t E, uint32_t* total,
+                                  hipStream_t s);
 hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_sums,
                               uint32_t* total, hipStream_t s);
 // Fused: scan of run heads (tile counts from launch_dedup_count) + run sums + index/value

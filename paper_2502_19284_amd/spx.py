@@ -52,7 +52,7 @@ class ConvertReport(ctypes.Structure):
     _fields_ = [("convert_ms", ctypes.c_float), ("nnz_out", ctypes.c_int64),
                 ("bytes", ctypes.c_int64), ("log2_beta", ctypes.c_int32),
                 ("parts", ctypes.c_int32), ("sort_split_keys", ctypes.c_int64),
-                ("sort_levels", ctypes.c_int32)]
+                ("sort_levels", ctypes.c_int32), ("sort_first_fused", ctypes.c_int32)]
 
 
 class MatrixInfo(ctypes.Structure):
@@ -279,6 +279,7 @@ class Matrix:
         self.convert_ms = float(report.convert_ms)
         self.sort_split_keys = int(report.sort_split_keys)
         self.sort_levels = int(report.sort_levels)
+        self.sort_first_fused = int(report.sort_first_fused)
         info = MatrixInfo()
         _check(load().spx_matrix_get_info(self._h, ctypes.byref(info)))
         self.shape = (info.m, info.n)
