@@ -161,9 +161,9 @@ spx_status spx_convert_opts_default(spx_convert_opts* opts);
  * rep:  host, may be NULL.  convert_ms covers all device work of the call.
  * The call returns after the device work is complete (it reads back the entry count).
  * Errors: INVALID_ARG, RANGE (m, n or nnz beyond int32, or a CSB / BCOHC key beyond 64 bits),
- * INDEX (validate=1 and an index out of range), UNSUPPORTED (reduced-precision values for the
- * block formats; sum_duplicates=0 for BCOHC / BCOHCH), NOMEM, HIP.  On error every temporary is
- * freed.
+ * INDEX (an index out of range; indices are always checked), UNSUPPORTED (reduced-precision values
+ * for the block formats; sum_duplicates=0 for BCOHC / BCOHCH), NOMEM, HIP, DEVICE (a device-side
+ * list of the sort outgrew its bound; not expected).  On error every temporary is freed.
  */
 spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt, const spx_convert_opts* opts,
                        void* stream, spx_matrix* out, spx_convert_report* rep);
