@@ -84,19 +84,32 @@ __global__ __launch_bounds__(CB_NT) void k_spmv_csbh(const int32_t* __restrict__
     }
 }
 
-__global__ __launch_bounds__(256) void k_spmv_csbh_reduce(const int4* __restrict__ split,
-                                                          const double* __restrict__ partials,
-                                                          double* __restrict__ y, int k,
-                                                          int32_t m) {
-    const int4 S = split[blockIdx.x];
+// Split block row S.x: y = sum of its S.z partial slices (slots S.y ..), added in slot order.
+// Workgroup = (split row, chunk of 256 rows); each thread keeps 8 slot loads in flight.
+#define CB_RED_NT 256
+__global__ __launch_bounds__(CB_RED_NT) void k_spmv_csbh_reduce(const int4* __restrict__ split,
+                                                               const double* __restrict__ partials,
+                                                               double* __restrict__ y, int k,
+                                                               int32_t m) {
     const int beta = 1 << k;
+    const int chunks = (beta + CB_RED_NT - 1) / CB_RED_NT;
+    const int4 S = split[blockIdx.x / chunks];
+    const int i = (blockIdx.x % chunks) * CB_RED_NT + threadIdx.x;
     const int row0 = S.x << k;
     const int rows = min(beta, m - row0);
-    for (int i = threadIdx.x; i < rows; i += 256) {
-        double acc = 0.0;
-        for (int q = 0; q < S.z; ++q) acc = acc + partials[(int64_t)(S.y + q) * beta + i];
-        y[row0 + i] = acc;
+    if (i >= rows) return;
+    const double* p = partials + (int64_t)S.y * beta + i;
+    double acc = 0.0;
+    int q = 0;
+    for (; q + 8 <= S.z; q += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = p[(int64_t)(q + u) * beta];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = acc + t[u];
     }
+    for (; q < S.z; ++q) acc = acc + p[(int64_t)q * beta];
+    y[row0 + i] = acc;
 }
 
 hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
@@ -113,7 +126,9 @@ hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStrea
                        A->packed, A->val, x, y, A->cb_partials, A->cb_units, A->log2_beta,
                        (int32_t)A->nbc, A->m, stage_bp);
     if (A->cb_nsplit > 0)
-        SPX_LAUNCH("spmv_csbh_reduce", k_spmv_csbh_reduce, dim3(A->cb_nsplit), dim3(256), 0, s, A->cb_split,
+        SPX_LAUNCH("spmv_csbh_reduce", k_spmv_csbh_reduce,
+                   dim3(A->cb_nsplit * (((1 << A->log2_beta) + CB_RED_NT - 1) / CB_RED_NT)),
+                   dim3(CB_RED_NT), 0, s, A->cb_split,
                            A->cb_partials, y, A->log2_beta, A->m);
     return hipGetLastError();
 }

@@ -130,6 +130,12 @@ def _cases():
                                synth.values(9000, seed=13))
     cases["all_equal_large"] = (40, 50, np.full(7000, 17, np.int32), np.full(7000, 33, np.int32),
                                 synth.values(7000, seed=14))
+    # sizes around one workgroup's share of the sort (4096 keys sorted whole in LDS; one more
+    # splits by the top digit first), with repeats
+    for E in (4096, 4097, 8193):
+        cases["size_%d" % E] = (3000, 2000, rng.integers(0, 3000, E).astype(np.int32),
+                                rng.integers(0, 2000, E).astype(np.int32),
+                                synth.values(E, seed=E))
     return cases
 
 
