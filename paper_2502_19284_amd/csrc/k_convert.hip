@@ -646,10 +646,10 @@ __global__ void k_msd_flush(const int64_t* __restrict__ seg_start,
     else atomicOr(&ctr->err, 8u);
 }
 
-// One wave per segment: the 256 part sizes go to LDS, lane 0 walks them in digit order, packing
-// consecutive small parts into chunks and listing the large ones for the next level (or as copy
-// chunks after the last varying digit); the wave then reserves its list entries with one atomic
-// per list and writes them in parallel.
+// One wave per segment: each lane loads the sizes of 4 of the 256 parts; the wave walks them in
+// digit order, packing consecutive small parts into chunks and listing the large ones for the
+// next level (or as copy chunks after the last varying digit); it then reserves its list entries
+// with one atomic per list and writes them in parallel.
 #define MSD_CLS_NT 256
 __global__ __launch_bounds__(MSD_CLS_NT) void k_msd_classify(
     const int64_t* __restrict__ seg_start, const uint32_t* __restrict__ seg_len,
@@ -657,8 +657,6 @@ __global__ __launch_bounds__(MSD_CLS_NT) void k_msd_classify(
     uint32_t meta, int64_t* __restrict__ nstart, uint32_t* __restrict__ nlen, uint32_t cap_big,
     MsdChunk* __restrict__ chunks, uint32_t cap_chunks, MsdCounters* ctr) {
     constexpr int NW = MSD_CLS_NT / SPX_WAVE;
-    __shared__ uint32_t s_cnt[NW][256];
-    __shared__ uint32_t s_off[NW][256];
     __shared__ uint32_t s_olen[NW][256];   // outputs in digit order: length,
     __shared__ uint32_t s_ooff[NW][256];   // offset in the segment,
     __shared__ uint8_t s_obig[NW][256];    // 1: next-level segment, 0: chunk
@@ -672,44 +670,45 @@ __global__ __launch_bounds__(MSD_CLS_NT) void k_msd_classify(
     const int64_t hs = tbase[sg + 1] - tbase[sg];
     const int64_t h0 = (int64_t)tbase[sg] * 256;
     const uint32_t x0 = hist[h0];
+    uint32_t cnt[4], off[4];  // lane l: digits l, l + 64, l + 128, l + 192
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int d = lane + 64 * q;
         const uint32_t xd = hist[h0 + d * hs];
         const uint32_t xe = d < 255 ? hist[h0 + (d + 1) * hs] : x0 + len;
-        s_cnt[w][d] = xe - xd;
-        s_off[w][d] = xd - x0;
+        cnt[q] = xe - xd;
+        off[q] = xd - x0;
     }
-    __builtin_amdgcn_wave_barrier();
-    if (lane == 0) {
-        uint32_t no = 0, nbig = 0, tiles = 0, coff = 0, cl = 0, bigkeys = 0;
-        for (int d = 0; d < 256; ++d) {
-            const uint32_t c = s_cnt[w][d];
+    // the walk in digit order is wave-uniform: every lane runs it on values read from their
+    // owning lanes (scalar reads), and lane 0 records the outputs
+    uint32_t no = 0, nbig = 0, tiles = 0, coff = 0, cl = 0, bigkeys = 0;
+    auto emit = [&](uint32_t len_, uint32_t off_, uint8_t big_) {
+        if (lane == 0) {
+            s_olen[w][no] = len_;
+            s_ooff[w][no] = off_;
+            s_obig[w][no] = big_;
+        }
+        ++no;
+    };
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        for (int l = 0; l < SPX_WAVE; ++l) {
+            const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cnt[q], l);
             if (c == 0) continue;
-            const uint32_t off = s_off[w][d];
+            const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)off[q], l);
             if (c <= RS_LOCAL_MAX) {
                 if (cl > 0 && cl + c <= RS_LOCAL_MAX) {
                     cl += c;
                     continue;
                 }
-                if (cl > 0) {
-                    s_olen[w][no] = cl;
-                    s_ooff[w][no] = coff;
-                    s_obig[w][no++] = 0;
-                }
-                coff = off;
+                if (cl > 0) emit(cl, coff, 0);
+                coff = o;
                 cl = c;
             } else {
-                if (cl > 0) {
-                    s_olen[w][no] = cl;
-                    s_ooff[w][no] = coff;
-                    s_obig[w][no++] = 0;
-                }
+                if (cl > 0) emit(cl, coff, 0);
                 cl = 0;
                 const bool big = !last;  // after the last varying digit: equal keys, copied
-                s_olen[w][no] = c;
-                s_ooff[w][no] = off;
-                s_obig[w][no++] = big ? 1 : 0;
+                emit(c, o, big ? 1 : 0);
                 if (big) {
                     ++nbig;
                     tiles += (c + RSORT_TILE - 1) / RSORT_TILE;
@@ -717,11 +716,9 @@ __global__ __launch_bounds__(MSD_CLS_NT) void k_msd_classify(
                 }
             }
         }
-        if (cl > 0) {
-            s_olen[w][no] = cl;
-            s_ooff[w][no] = coff;
-            s_obig[w][no++] = 0;
-        }
+    }
+    if (cl > 0) emit(cl, coff, 0);
+    if (lane == 0) {
         s_nout[w] = no;
         s_cbase[w] = no - nbig > 0 ? atomicAdd(&ctr->nchunks, no - nbig) : 0u;
         s_bbase[w] = nbig > 0 ? atomicAdd(&ctr->nbig, nbig) : 0u;
@@ -731,7 +728,6 @@ __global__ __launch_bounds__(MSD_CLS_NT) void k_msd_classify(
         }
     }
     __builtin_amdgcn_wave_barrier();
-    const uint32_t no = s_nout[w];
     uint32_t cb = s_cbase[w], bb = s_bbase[w];
     for (uint32_t o0 = 0; o0 < no; o0 += SPX_WAVE) {  // outputs in order, ranked by ballots
         const uint32_t o = o0 + lane;
