@@ -564,10 +564,9 @@ __global__ __launch_bounds__(RSORT_NT) void k_msd_scatter(
 
 // First level of a CRS conversion, straight from the triplets: digit counts of the tile (one
 // segment [0, E), equal tiles in the XCD order), the OR / AND of the keys and the index check.
-__global__ __launch_bounds__(RSORT_NT) void k_msd_count0_csr(KeyFromCsr kf, int64_t E, int shift,
-                                                             uint32_t T0,
-                                                             uint32_t* __restrict__ hist,
-                                                             MsdCounters* ctr) {
+__global__ __launch_bounds__(RSORT_NT) void k_msd_count0_csr(
+    KeyFromCsr kf, int64_t E, int shift, uint32_t T0, uint32_t* __restrict__ hist,
+    unsigned long long* __restrict__ tile_masks, MsdCounters* ctr) {
     __shared__ uint32_t cnt[RSORT_WAVES][256];
     __shared__ unsigned long long s_or[RSORT_WAVES], s_and[RSORT_WAVES];
     __shared__ uint32_t s_bad[RSORT_WAVES];
@@ -615,13 +614,44 @@ __global__ __launch_bounds__(RSORT_NT) void k_msd_count0_csr(KeyFromCsr kf, int6
             andv &= s_and[ww];
             b |= s_bad[ww];
         }
-        // OR only gains bits and AND only loses them, so a value read here (however stale)
-        // that already agrees makes the atomic a no-op: most workgroups skip it, and the two
-        // words are not hammered by every tile
-        const unsigned long long cur_or = ctr->kor, cur_and = ctr->kand;
-        if ((cur_or | orv) != cur_or) atomicOr(&ctr->kor, orv);
-        if ((cur_and & andv) != cur_and) atomicAnd(&ctr->kand, andv);
+        // the tile's OR / AND are combined by k_msd_masks: no global read or atomic here, so
+        // the workgroup's last wave does not wait on a round trip before its slots free up
+        tile_masks[2 * g] = orv;
+        tile_masks[2 * g + 1] = andv;
         if (b) atomicOr(&ctr->err, 1u);
+    }
+}
+
+static_assert(sizeof(MsdChunk) == 2 * sizeof(unsigned long long), "one tile's pair per chunk");
+
+// OR / AND over the first level's per-tile pairs, into the counters (one atomic each per
+// workgroup).
+#define MSD_MASK_NT 256
+__global__ __launch_bounds__(MSD_MASK_NT) void k_msd_masks(
+    const unsigned long long* __restrict__ tile_masks, uint32_t T0, MsdCounters* ctr) {
+    constexpr int NW = MSD_MASK_NT / SPX_WAVE;
+    __shared__ unsigned long long s_or[NW], s_and[NW];
+    unsigned long long orv = 0ull, andv = ~0ull;
+    for (uint32_t t = blockIdx.x * MSD_MASK_NT + threadIdx.x; t < T0;
+         t += gridDim.x * MSD_MASK_NT) {
+        orv |= tile_masks[2 * (int64_t)t];
+        andv &= tile_masks[2 * (int64_t)t + 1];
+    }
+    orv = wave_reduce<unsigned long long, OpOr<unsigned long long>>(orv);
+    andv = wave_reduce<unsigned long long, OpAnd<unsigned long long>>(andv);
+    const int w = threadIdx.x / SPX_WAVE;
+    if (__lane_id() == 0) {
+        s_or[w] = orv;
+        s_and[w] = andv;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int ww = 1; ww < NW; ++ww) {
+            orv |= s_or[ww];
+            andv &= s_and[ww];
+        }
+        atomicOr(&ctr->kor, orv);
+        atomicAnd(&ctr->kand, andv);
     }
 }
 
@@ -827,10 +857,12 @@ __global__ __launch_bounds__(MSD_LNT) void k_msd_local(
         vand &= sred[1][ww];
     }
     const uint64_t vm = (vor ^ vand) & (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull));
+    // a wave ranks against, and scatters with, its own row of wcnt only, so it clears that row
+    // itself: ahead of the first pass, and after each pass's last read of it (the scatter)
+    for (int i = lane; i < 256; i += SPX_WAVE) wcnt[w][i] = 0;
+    __builtin_amdgcn_wave_barrier();
     for (int ds = 0; ds < hi; ds += RS_RADIX_BITS) {
         if (((vm >> ds) & 255ull) == 0) continue;  // uniform: vm is the same in every thread
-        for (int i = tid; i < MSD_LWAVES * 256; i += MSD_LNT) (&wcnt[0][0])[i] = 0;
-        __syncthreads();
         uint32_t pos[MSD_LROUNDS];
 #pragma unroll
         for (int r = 0; r < MSD_LROUNDS; ++r) {
@@ -884,8 +916,13 @@ __global__ __launch_bounds__(MSD_LNT) void k_msd_local(
                 idx[r] = sidx[j];
             }
         }
-        __syncthreads();
+        // the next pass writes skey / sidx only after its two barriers, which every thread
+        // reaches after these reads; its scan rewrites wcnt only after the first of them
+        __builtin_amdgcn_wave_barrier();
+        for (int i = lane; i < 256; i += SPX_WAVE) wcnt[w][i] = 0;
+        __builtin_amdgcn_wave_barrier();
     }
+    __syncthreads();  // the last pass's reads of skey / sidx are done before the writes below
     // payloads fetched after the passes (fewer live registers during them); every thread uses
     // its loads before the barrier ahead of the payload writes, so an in-place chunk is read
     // completely before it is written
@@ -1006,8 +1043,15 @@ hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1
         while (tb < 63 && (kmax >> (tb + 1)) != 0) ++tb;
         const int shift0 = tb / RS_RADIX_BITS * RS_RADIX_BITS;
         const KeyFromCsr kf{csr->row, csr->col, csr->m, csr->n, csr->cbits};
+        // the per-tile OR / AND pairs borrow the chunk list, first written by the classification
+        // below (16 bytes per chunk, at least as many chunks as tiles)
+        if ((int64_t)T > sc.z.cap_chunks) return hipErrorInvalidValue;
+        unsigned long long* tile_masks = (unsigned long long*)sc.chunks;
         SPX_LAUNCH("msd_count0_csr", k_msd_count0_csr, dim3(T), dim3(RSORT_NT), 0, s, kf, E,
-                   shift0, T, sc.hist, ctr);
+                   shift0, T, sc.hist, tile_masks, ctr);
+        const uint32_t gm = T < 256u * MSD_MASK_NT ? (T + MSD_MASK_NT - 1) / MSD_MASK_NT : 256u;
+        SPX_LAUNCH("msd_masks", k_msd_masks, dim3(gm), dim3(MSD_MASK_NT), 0, s,
+                   (const unsigned long long*)tile_masks, T, ctr);
         const int64_t hn = (int64_t)256 * T;
         e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32{sc.hist}, hn, sc.tile_sums,
                                                     (uint32_t*)nullptr, s);
@@ -1292,6 +1336,15 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
             s_hb[j * NW + w] = bal;  // positions [j * DG_NT + 64 w, +64)
         }
     }
+    const uint64_t lowmask = (1ull << shiftbits) - 1ull;
+    // CRS: the hot-column map words of every head, all loads in flight across the prefix scan
+    uint4 hw[DG_IPT];
+#pragma unroll
+    for (int j = 0; j < DG_IPT; ++j) {
+        hw[j] = make_uint4(0u, 0u, 0u, 0u);
+        if (MODE == 0 && ((heads >> j) & 1u))
+            hw[j] = hm.word((uint32_t)(s_key[tid + j * DG_NT + 1] & lowmask));
+    }
     __syncthreads();
     if (w == 0) {  // exclusive prefix over the DG_IPT x NW counts in (row, wave) order
         const uint32_t c = s_pre[lane / NW][lane % NW];
@@ -1299,7 +1352,6 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
         s_pre[lane / NW][lane % NW] = tile_off[blockIdx.x] + incl - c;
     }
     __syncthreads();
-    const uint64_t lowmask = (1ull << shiftbits) - 1ull;
 #pragma unroll
     for (int j = 0; j < DG_IPT; ++j) {
         if (!((heads >> j) & 1u)) continue;
@@ -1359,7 +1411,7 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
             else zmorton_d2xy(k, d, &lc, &lr);
             idx_out[u] = (int32_t)((lr << 16) | lc);
         } else {
-            idx_out[u] = hm.map(d);
+            idx_out[u] = hm.words ? hm.map_word(d, hw[j]) : (int32_t)d;
         }
     }
     __syncthreads();

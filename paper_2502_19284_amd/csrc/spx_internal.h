@@ -173,6 +173,17 @@ struct HotMap {
         if (!(b & bit)) return (int32_t)c;
         return ~(int32_t)(wd.z + (uint32_t)__popcll(b & (bit - 1ull)));
     }
+    // the map word of column c, for a caller that loads it ahead of use
+    __device__ __forceinline__ uint4 word(uint32_t c) const {
+        return words ? words[c >> 6] : make_uint4(0u, 0u, 0u, 0u);
+    }
+    // map() given the word of column c loaded by word()
+    __device__ __forceinline__ int32_t map_word(uint32_t c, uint4 wd) const {
+        const uint64_t b = ((uint64_t)wd.y << 32) | (uint64_t)wd.x;
+        const uint64_t bit = 1ull << (c & 63u);
+        if (!(b & bit)) return (int32_t)c;
+        return ~(int32_t)(wd.z + (uint32_t)__popcll(b & (bit - 1ull)));
+    }
 };
 
 // ------------------------------------------------------------------ conversion launchers
