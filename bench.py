@@ -80,12 +80,13 @@ def kernel_bytes(name, E, nnz, m, split_keys, split_levels):
 
     The sort's segmented split levels move different numbers of keys (every key at the top
     levels, only those of still-large segments below); split_keys / split_levels is their mean
-    per launch.  A CRS conversion's first level reads the triplets instead (msd_*0_csr)."""
+    per launch.  A CRS or CSB conversion's first level reads the triplets instead (msd_*0_csr,
+    msd_*0_csb)."""
     per_level = split_keys / split_levels if split_levels else 0
-    if name == "msd_scatter0_csr":
+    if name in ("msd_scatter0_csr", "msd_scatter0_csb"):
         # row + col + value read, key + value written
         return 32 * E
-    if name == "msd_count0_csr":
+    if name in ("msd_count0_csr", "msd_count0_csb"):
         return 8 * E
     if name == "msd_scatter":
         # read 8-byte key + 8-byte value, write both

@@ -107,7 +107,7 @@ typedef struct {
     int32_t parts;     /* work units of the format (tiles, row blocks, block-row chunks)*/
     int64_t sort_split_keys; /* keys moved by the sort's global split levels, summed      */
     int32_t sort_levels;     /* global split levels the sort ran                          */
-    int32_t sort_first_fused; /* 1: the first level read the triplets (CRS keys built there) */
+    int32_t sort_first_fused; /* 1: the first level read the triplets (keys built there) */
 } spx_convert_report;
 
 typedef struct spx_matrix_s* spx_matrix;

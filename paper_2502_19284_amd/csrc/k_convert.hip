@@ -205,21 +205,24 @@ __device__ __forceinline__ int64_t rs_tile_of(int64_t b, int64_t tiles) {
     return x * q + (x < r ? x : r) + i;
 }
 
-// Key sources of the counting and scatter passes: a key array, or CRS keys built from triplets
-// (row << cbits | col; 0 for an index outside the matrix, which is reported separately).
+// Key sources of the counting and scatter passes: a key array, or keys built from triplets by a
+// format's key function (0 for an index outside the matrix, which is reported separately).
 struct KeyArr {
     const uint64_t* k;
     __device__ uint64_t operator()(int64_t i) const { return k[i]; }
 };
-struct KeyFromCsr {
+template <typename KeyFn>
+struct KeyFromTriplets {
     const int32_t* row;
     const int32_t* col;
     int32_t m, n;
-    int cbits;
+    KeyFn fn;
+    __device__ bool valid(int32_t r, int32_t c) const {
+        return (r >= 0) & (r < m) & (c >= 0) & (c < n);
+    }
     __device__ uint64_t operator()(int64_t i) const {
         const int32_t r = row[i], c = col[i];
-        const bool ok = (r >= 0) & (r < m) & (c >= 0) & (c < n);
-        return ok ? ((uint64_t)(uint32_t)r << cbits) | (uint64_t)(uint32_t)c : 0ull;
+        return valid(r, c) ? fn((uint32_t)r, (uint32_t)c) : 0ull;
     }
 };
 
@@ -564,8 +567,9 @@ __global__ __launch_bounds__(RSORT_NT) void k_msd_scatter(
 
 // First level of a CRS conversion, straight from the triplets: digit counts of the tile (one
 // segment [0, E), equal tiles in the XCD order), the OR / AND of the keys and the index check.
-__global__ __launch_bounds__(RSORT_NT) void k_msd_count0_csr(
-    KeyFromCsr kf, int64_t E, int shift, uint32_t T0, uint32_t* __restrict__ hist,
+template <typename KeyFn>
+__global__ __launch_bounds__(RSORT_NT) void k_msd_count0(
+    KeyFromTriplets<KeyFn> kf, int64_t E, int shift, uint32_t T0, uint32_t* __restrict__ hist,
     unsigned long long* __restrict__ tile_masks, MsdCounters* ctr) {
     __shared__ uint32_t cnt[RSORT_WAVES][256];
     __shared__ unsigned long long s_or[RSORT_WAVES], s_and[RSORT_WAVES];
@@ -583,9 +587,8 @@ __global__ __launch_bounds__(RSORT_NT) void k_msd_count0_csr(
         const int j = i * RSORT_NT + threadIdx.x;
         if (j < n) {
             const int32_t r = kf.row[lo + j], c = kf.col[lo + j];
-            const bool ok = (r >= 0) & (r < kf.m) & (c >= 0) & (c < kf.n);
-            const uint64_t key =
-                ok ? ((uint64_t)(uint32_t)r << kf.cbits) | (uint64_t)(uint32_t)c : 0ull;
+            const bool ok = kf.valid(r, c);
+            const uint64_t key = ok ? kf.fn((uint32_t)r, (uint32_t)c) : 0ull;
             bad |= ok ? 0u : 1u;
             orv |= key;
             andv &= key;
@@ -655,8 +658,9 @@ __global__ __launch_bounds__(MSD_MASK_NT) void k_msd_masks(
     }
 }
 
-__global__ __launch_bounds__(RSORT_NT) void k_msd_scatter0_csr(
-    KeyFromCsr kf, const uint64_t* __restrict__ vin, uint64_t* __restrict__ kout,
+template <typename KeyFn>
+__global__ __launch_bounds__(RSORT_NT) void k_msd_scatter0(
+    KeyFromTriplets<KeyFn> kf, const uint64_t* __restrict__ vin, uint64_t* __restrict__ kout,
     uint64_t* __restrict__ vout, int64_t E, int shift, uint32_t T0,
     const uint32_t* __restrict__ hist) {
     const int64_t g = rs_tile_of(blockIdx.x, T0);
@@ -1009,23 +1013,49 @@ static hipError_t msd_read(MsdCounters* host, const MsdCounters* dev, hipStream_
     return hipStreamSynchronize(s);
 }
 
+// The first level straight from the triplets: digit counts with the index check and the key
+// masks, the scan of the (digit, tile) table, the scatter of keys and values into (k1, v1).
+template <typename KeyFn>
+static hipError_t msd_first_level(const KeyFromTriplets<KeyFn>& kf, const char* count_name,
+                                  const char* scatter_name, const uint64_t* vfirst, uint64_t* k1,
+                                  uint64_t* v1, int64_t E, int shift0, uint32_t T,
+                                  const MsdScratch& sc, unsigned long long* tile_masks,
+                                  MsdCounters* ctr, hipStream_t s) {
+    SPX_LAUNCH(count_name, k_msd_count0<KeyFn>, dim3(T), dim3(RSORT_NT), 0, s, kf, E, shift0, T,
+               sc.hist, tile_masks, ctr);
+    const uint32_t gm = T < 256u * MSD_MASK_NT ? (T + MSD_MASK_NT - 1) / MSD_MASK_NT : 256u;
+    SPX_LAUNCH("msd_masks", k_msd_masks, dim3(gm), dim3(MSD_MASK_NT), 0, s,
+               (const unsigned long long*)tile_masks, T, ctr);
+    const int64_t hn = (int64_t)256 * T;
+    hipError_t e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32{sc.hist}, hn, sc.tile_sums,
+                                                           (uint32_t*)nullptr, s);
+    if (e != hipSuccess) return e;
+    e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32{sc.hist}, StoreExclU32{sc.hist}, hn,
+                                               sc.tile_sums, s);
+    if (e != hipSuccess) return e;
+    SPX_LAUNCH(scatter_name, k_msd_scatter0<KeyFn>, dim3(T), dim3(RSORT_NT), 0, s, kf, vfirst,
+               k1, v1, E, shift0, T, sc.hist);
+    return hipGetLastError();
+}
+
 hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1,
                           const uint64_t* vfirst, int64_t E, uint64_t vary, const MsdScratch& sc,
                           hipStream_t s, const uint64_t** keys_sorted,
                           const uint64_t** vals_sorted, int* failed, MsdStats* stats,
-                          const MsdCsrSource* csr, uint32_t* head_tiles, int* heads_counted) {
+                          const MsdTripletSource* trip, uint32_t* head_tiles,
+                          int* heads_counted) {
     *keys_sorted = k0;
     *vals_sorted = vfirst;
     *failed = 0;
     *stats = MsdStats{};
     if (heads_counted) *heads_counted = 0;
     if (E <= 0) return hipSuccess;
-    if (!csr && vary == 0) return hipSuccess;  // no key differs: the input order stands
+    if (!trip && vary == 0) return hipSuccess;  // no key differs: the input order stands
     if (head_tiles) {
         hipError_t e0 = launch_fill_i32((int32_t*)head_tiles, spx_div_up(E, SCAN_TILE), 0, s);
         if (e0 != hipSuccess) return e0;
     }
-    if (csr && E <= RS_LOCAL_MAX) return hipErrorInvalidValue;  // caller builds keys first
+    if (trip && E <= RS_LOCAL_MAX) return hipErrorInvalidValue;  // caller builds keys first
     MsdCounters* ctr = (MsdCounters*)sc.counters;
     MsdCounters h{};
     SPX_LAUNCH("msd_init", k_msd_init, dim3(1), dim3(1), 0, s, E, sc.seg_start[0], sc.seg_len[0],
@@ -1036,31 +1066,41 @@ hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1
     int64_t level_keys = E;
     int top = 64 - RS_RADIX_BITS;
     hipError_t e;
-    if (csr) {
+    if (trip) {
         // first level from the triplets, on the top digit the matrix shape allows
-        const uint64_t kmax = ((uint64_t)(csr->m - 1) << csr->cbits) | (uint64_t)(csr->n - 1);
+        uint64_t kmax;
+        if (trip->order == 0) {
+            kmax = ((uint64_t)(trip->m - 1) << trip->cbits) | (uint64_t)(trip->n - 1);
+        } else {
+            int64_t nbr = ((int64_t)trip->m + (1ll << trip->k) - 1) >> trip->k;
+            if (nbr < 1) nbr = 1;
+            kmax = ((uint64_t)(nbr * trip->nbc - 1) << (2 * trip->k)) |
+                   ((1ull << (2 * trip->k)) - 1ull);
+        }
         int tb = 0;
         while (tb < 63 && (kmax >> (tb + 1)) != 0) ++tb;
         const int shift0 = tb / RS_RADIX_BITS * RS_RADIX_BITS;
-        const KeyFromCsr kf{csr->row, csr->col, csr->m, csr->n, csr->cbits};
         // the per-tile OR / AND pairs borrow the chunk list, first written by the classification
         // below (16 bytes per chunk, at least as many chunks as tiles)
         if ((int64_t)T > sc.z.cap_chunks) return hipErrorInvalidValue;
         unsigned long long* tile_masks = (unsigned long long*)sc.chunks;
-        SPX_LAUNCH("msd_count0_csr", k_msd_count0_csr, dim3(T), dim3(RSORT_NT), 0, s, kf, E,
-                   shift0, T, sc.hist, tile_masks, ctr);
-        const uint32_t gm = T < 256u * MSD_MASK_NT ? (T + MSD_MASK_NT - 1) / MSD_MASK_NT : 256u;
-        SPX_LAUNCH("msd_masks", k_msd_masks, dim3(gm), dim3(MSD_MASK_NT), 0, s,
-                   (const unsigned long long*)tile_masks, T, ctr);
-        const int64_t hn = (int64_t)256 * T;
-        e = scan_phase12<uint32_t, OpSum<uint32_t>>(LoadU32{sc.hist}, hn, sc.tile_sums,
-                                                    (uint32_t*)nullptr, s);
+        if (trip->order == 0) {
+            const KeyFromTriplets<KeyCsr> kf{trip->row, trip->col, trip->m, trip->n,
+                                             KeyCsr{trip->cbits}};
+            e = msd_first_level(kf, "msd_count0_csr", "msd_scatter0_csr", vfirst, k1, v1, E,
+                                shift0, T, sc, tile_masks, ctr, s);
+        } else if (trip->order == 1) {
+            const KeyFromTriplets<KeyCsb<true>> kf{trip->row, trip->col, trip->m, trip->n,
+                                                   KeyCsb<true>{trip->k, (uint64_t)trip->nbc}};
+            e = msd_first_level(kf, "msd_count0_csb", "msd_scatter0_csb", vfirst, k1, v1, E,
+                                shift0, T, sc, tile_masks, ctr, s);
+        } else {
+            const KeyFromTriplets<KeyCsb<false>> kf{trip->row, trip->col, trip->m, trip->n,
+                                                    KeyCsb<false>{trip->k, (uint64_t)trip->nbc}};
+            e = msd_first_level(kf, "msd_count0_csb", "msd_scatter0_csb", vfirst, k1, v1, E,
+                                shift0, T, sc, tile_masks, ctr, s);
+        }
         if (e != hipSuccess) return e;
-        e = scan_phase3<uint32_t, OpSum<uint32_t>>(LoadU32{sc.hist}, StoreExclU32{sc.hist}, hn,
-                                                   sc.tile_sums, s);
-        if (e != hipSuccess) return e;
-        SPX_LAUNCH("msd_scatter0_csr", k_msd_scatter0_csr, dim3(T), dim3(RSORT_NT), 0, s, kf,
-                   vfirst, k1, v1, E, shift0, T, sc.hist);
         SPX_LAUNCH("msd_next_level", k_msd_next_level, dim3(1), dim3(1), 0, s, ctr);
         const uint32_t meta = (uint32_t)(shift0 + RS_RADIX_BITS) | (1u << 8);
         SPX_LAUNCH("msd_classify", k_msd_classify, dim3(1), dim3(MSD_CLS_NT), 0, s,

@@ -223,9 +223,11 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
     HIP_TRY(launch_init_readback(rb_dev, s));
     const uint64_t* vs = nullptr;
     int failed = 0, heads = 0;
-    if (!spx_is_bcoh(fmt) && !spx_is_csb(fmt) && E > RS_LOCAL_MAX) {
-        // CRS: the sort's first level builds the keys from the triplets (and checks them)
-        const MsdCsrSource src{coo->row, coo->col, coo->m, coo->n, cbits};
+    if (!spx_is_bcoh(fmt) && E > RS_LOCAL_MAX) {
+        // CRS and CSB: the sort's first level builds the keys from the triplets (and checks
+        // them)
+        const int order = !spx_is_csb(fmt) ? 0 : fmt == SPX_CSB_HILBERT ? 1 : 2;
+        const MsdTripletSource src{coo->row, coo->col, coo->m, coo->n, order, cbits, k, nbc};
         HIP_TRY(radix_sort_msd(k0, v0, k1, v1, (const uint64_t*)coo->val, E, 0, sc, s,
                                &out->keys, &vs, &failed, &out->sort, &src,
                                sum_dup ? tsums : nullptr, &heads));

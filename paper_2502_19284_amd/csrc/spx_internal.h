@@ -226,13 +226,19 @@ struct MsdScratch {
     MsdChunk* chunks = nullptr;    // cap_chunks
     void* counters = nullptr;      // 40 bytes, 8-byte aligned
 };
-// CRS keys built from the triplets inside the sort's first level (row << cbits | col); only for
-// E > RS_LOCAL_MAX.  An index outside the matrix sets *failed = 2.
-struct MsdCsrSource {
+// Keys built from the triplets inside the sort's first level; only for E > RS_LOCAL_MAX.  An
+// index outside the matrix sets *failed = 2.
+//   order 0 (CRS): row << cbits | col
+//   order 1 / 2 (CSB with Hilbert / Z-Morton order inside blocks of 2^k x 2^k):
+//     (block_row * nbc + block_col) << 2k | order_k(local_col, local_row)
+struct MsdTripletSource {
     const int32_t* row;
     const int32_t* col;
     int32_t m, n;
-    int cbits;
+    int order;
+    int cbits;    // order 0
+    int k;        // orders 1, 2
+    int64_t nbc;  // orders 1, 2
 };
 // segments of at most this many keys are finished in LDS by one workgroup
 #ifndef RS_LOCAL_MAX
@@ -243,7 +249,7 @@ hipError_t radix_sort_msd(uint64_t* k0, uint64_t* v0, uint64_t* k1, uint64_t* v1
                           const uint64_t* vfirst, int64_t E, uint64_t vary, const MsdScratch& sc,
                           hipStream_t s, const uint64_t** keys_sorted,
                           const uint64_t** vals_sorted, int* failed, MsdStats* stats,
-                          const MsdCsrSource* csr = nullptr, uint32_t* head_tiles = nullptr,
+                          const MsdTripletSource* trip = nullptr, uint32_t* head_tiles = nullptr,
                           int* heads_counted = nullptr);
 // head_tiles (nullable, ceil(E / SCAN_TILE) words): when *heads_counted comes back 1, it holds
 // the number of run heads (first keys of runs of equal keys) in each SCAN_TILE of sorted

@@ -378,13 +378,13 @@ def test_error_paths(spx):
     with pytest.raises(spx.SpxError) as e:
         spx.convert(_dev(np.array([0, -1], np.int32), torch.int32), col, val, (5, 5), "csbh")
     assert e.value.name == "SPX_ERR_INDEX"
-    # the same checks with more triplets than one workgroup sorts alone (CRS keys are then built
-    # inside the sort)
+    # the same checks with more triplets than one workgroup sorts alone (CRS and CSB keys are
+    # then built inside the sort)
     big = 9000
     r = np.arange(big, dtype=np.int32) % 5
     c = np.arange(big, dtype=np.int32) % 7
     v = _dev(np.ones(big), torch.float64)
-    for fmt in ("rowsplit", "merge"):
+    for fmt in ("rowsplit", "merge", "csbh", "csb"):
         bad_r = r.copy()
         bad_r[4321] = 5
         with pytest.raises(spx.SpxError) as e:
