@@ -360,10 +360,12 @@ static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot
     SPX_TRY(sync_read(hh.data(), fh, HOT_HIST_BINS * 4, s));
     uint64_t suffix = 0;  // count_ge(t) for t = HOT_HIST_BINS - 1 down to 1
     uint32_t tau = 0;
+    uint64_t nhot_hist = 0;  // count_ge(tau) when tau comes from the histogram
     for (int t = HOT_HIST_BINS - 1; t >= 1; --t) {
         suffix += hh[t];
         if (suffix > (uint64_t)hot_max) break;
         tau = (uint32_t)t;
+        nhot_hist = suffix;
     }
     if (tau == 0) {  // even count_ge(HOT_HIST_BINS - 1) exceeds hot_max
         uint64_t lo = HOT_HIST_BINS, hi = (uint64_t)ns + 1;  // no column has more than ns
@@ -377,8 +379,10 @@ static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot
         }
         tau = (uint32_t)lo;
     }
-    uint32_t nhot;
-    SPX_TRY(count_ge(tau, &nhot));
+    // the last bin holds every count >= HOT_HIST_BINS - 1, so for a threshold taken from the
+    // histogram the suffix sum is the exact column count (no second readback)
+    uint32_t nhot = (uint32_t)nhot_hist;
+    if (tau >= HOT_HIST_BINS) SPX_TRY(count_ge(tau, &nhot));
     if (nhot == 0) return SPX_OK;
     int32_t* hot_cols;
     double* x_hot;

@@ -301,6 +301,32 @@ def test_hot_column_compaction(spx, rmat14, fmt, hot):
         _check_structure(A, m, n, row, col, val)
 
 
+@pytest.mark.parametrize("fmt", ["rowsplit", "merge"])
+@pytest.mark.parametrize("hot", [1, 2, 3])
+def test_hot_threshold_beyond_histogram(spx, fmt, hot):
+    # three columns with more entries (9000, 7000, 5000) than the count histogram's last bin: the
+    # threshold for at most 1 or 2 hot columns is found by bisection on device-side counts, for
+    # 3 from the histogram
+    rng = np.random.default_rng(71)
+    m, n = 20_000, 400
+    col = np.concatenate([np.full(9000, 0), np.full(7000, 1), np.full(5000, 2),
+                          rng.integers(3, n, 30_000)]).astype(np.int32)
+    row = rng.integers(0, m, len(col)).astype(np.int32)
+    perm = rng.permutation(len(col))
+    row, col = row[perm], col[perm]
+    for kind in ("int", "float"):
+        val = synth.values(len(row), seed=72, kind=kind)
+        x = synth.xvec(n, seed=73, kind=kind)
+        ref = spmv.reference(m, n, row, col, val, x)
+        say("hot beyond histogram", fmt, hot, kind)
+        A, y = _run(spx, fmt, m, n, row, col, val, x, hot_columns=hot)
+        if kind == "int":
+            _check_int(y, ref, "hot bisection %s %d" % (fmt, hot))
+        else:
+            _check_float(y, ref, "hot bisection %s %d" % (fmt, hot))
+        _check_structure(A, m, n, row, col, val)
+
+
 # ---------------------------------------------------------------- invariants
 
 
