@@ -95,6 +95,9 @@ struct KeyCsr {
     __device__ uint64_t operator()(uint32_t r, uint32_t c) const {
         return ((uint64_t)r << cbits) | (uint64_t)c;
     }
+    // the key with its low order_bits() bits cleared, and their count (none here)
+    __device__ uint64_t high_part(uint32_t r, uint32_t c) const { return (*this)(r, c); }
+    __device__ int order_bits() const { return 0; }
 };
 
 template <bool HILBERT>
@@ -108,6 +111,11 @@ struct KeyCsb {
                                    : zmorton_xy2d(k, c & mask, r & mask);
         return (blk << (2 * k)) | (uint64_t)d;
     }
+    // the key without the position inside the block (the curve index), and that index's width
+    __device__ uint64_t high_part(uint32_t r, uint32_t c) const {
+        return ((uint64_t)(r >> k) * nbc + (uint64_t)(c >> k)) << (2 * k);
+    }
+    __device__ int order_bits() const { return 2 * k; }
 };
 
 // BCOHC: (partition, Hilbert index of the block, row-wise position inside the block);
@@ -582,15 +590,27 @@ __global__ __launch_bounds__(RSORT_NT) void k_msd_count0(
     const int n = E - lo < RSORT_TILE ? (int)(E - lo) : RSORT_TILE;
     unsigned long long orv = 0ull, andv = ~0ull;
     uint32_t bad = 0;
+    // When the digit lies above the within-block curve index (CSB), the index is not computed
+    // here: its bits are taken as varying (OR all ones, AND zero).  That only costs a split on a
+    // digit that turns out constant, on inputs whose entries all share those bits.
+    const int ob = kf.fn.order_bits();
+    const bool high_only = ob > 0 && shift >= ob;
+    const unsigned long long lowm = ob >= 64 ? ~0ull : (1ull << ob) - 1ull;
 #pragma unroll
     for (int i = 0; i < RSORT_IPT; ++i) {
         const int j = i * RSORT_NT + threadIdx.x;
         if (j < n) {
             const int32_t r = kf.row[lo + j], c = kf.col[lo + j];
             const bool ok = kf.valid(r, c);
-            const uint64_t key = ok ? kf.fn((uint32_t)r, (uint32_t)c) : 0ull;
             bad |= ok ? 0u : 1u;
-            orv |= key;
+            uint64_t key;
+            if (high_only) {
+                key = ok ? kf.fn.high_part((uint32_t)r, (uint32_t)c) : 0ull;
+                orv |= key | lowm;
+            } else {
+                key = ok ? kf.fn((uint32_t)r, (uint32_t)c) : 0ull;
+                orv |= key;
+            }
             andv &= key;
             atomicAdd(&cnt[w][(uint32_t)(key >> shift) & 255u], 1u);
         }
