@@ -892,13 +892,17 @@ __global__ __launch_bounds__(MSD_LNT) void k_msd_local(
         for (int r = 0; r < MSD_LROUNDS; ++r) {
             const bool valid = wave_off + r * SPX_WAVE + lane < n;
             const uint32_t d = (uint32_t)(key[r] >> ds) & 255u;
-            uint64_t peers = __ballot(valid);
+            // lanes whose digit differs from this lane's: for each bit, the bit's ballot xor this
+            // lane's bit spread over 32 bits (0 or all ones)
+            uint32_t mlo = 0u, mhi = 0u;
 #pragma unroll
             for (int b = 0; b < RS_RADIX_BITS; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const uint64_t bal = __ballot(bit);
-                peers &= bit ? bal : ~bal;
+                const uint32_t mb = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+                const uint64_t bal = __ballot((int)mb < 0);
+                mlo |= (uint32_t)bal ^ mb;
+                mhi |= (uint32_t)(bal >> 32) ^ mb;
             }
+            const uint64_t peers = __ballot(valid) & ~(((uint64_t)mhi << 32) | mlo);
             const uint32_t below = (uint32_t)__popcll(peers & lt);
             const uint32_t count = (uint32_t)__popcll(peers);
             const uint32_t basec = wcnt[w][d];
