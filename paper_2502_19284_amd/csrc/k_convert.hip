@@ -234,6 +234,21 @@ struct KeyFromTriplets {
     }
 };
 
+// Lanes of the wave whose 8-bit digit equals this lane's, among the valid lanes: for each bit,
+// the lanes that differ from this lane are the bit's ballot xor this lane's bit spread over 32
+// bits (0 or all ones); one OR per bit collects them.
+__device__ __forceinline__ uint64_t wave_digit_peers(uint32_t d, bool valid) {
+    uint32_t mlo = 0u, mhi = 0u;
+#pragma unroll
+    for (int b = 0; b < RS_RADIX_BITS; ++b) {
+        const uint32_t mb = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+        const uint64_t bal = __ballot((int)mb < 0);
+        mlo |= (uint32_t)bal ^ mb;
+        mhi |= (uint32_t)(bal >> 32) ^ mb;
+    }
+    return __ballot(valid) & ~(((uint64_t)mhi << 32) | mlo);
+}
+
 // Digit counts of keys[lo, lo + n), n <= RSORT_TILE: digit d's count is stored at hist[hb + d * hs].
 template <typename KeyLoad>
 __device__ __forceinline__ void rs_count_tile(KeyLoad keys, int64_t lo, int n, int shift,
@@ -288,13 +303,7 @@ __device__ __forceinline__ void rs_scatter_tile(KeyLoad kin, const uint64_t* __r
         key[r] = valid ? kin(lo + j) : 0ull;
         val[r] = valid ? vin[lo + j] : 0ull;  // payload fetched early, written after the keys
         const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < RS_RADIX_BITS; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
-        }
+        const uint64_t peers = wave_digit_peers(d, valid);
         const uint32_t below = (uint32_t)__popcll(peers & lt);
         const uint32_t count = (uint32_t)__popcll(peers);
         const uint32_t basec = wcnt[w][d];
@@ -892,17 +901,7 @@ __global__ __launch_bounds__(MSD_LNT) void k_msd_local(
         for (int r = 0; r < MSD_LROUNDS; ++r) {
             const bool valid = wave_off + r * SPX_WAVE + lane < n;
             const uint32_t d = (uint32_t)(key[r] >> ds) & 255u;
-            // lanes whose digit differs from this lane's: for each bit, the bit's ballot xor this
-            // lane's bit spread over 32 bits (0 or all ones)
-            uint32_t mlo = 0u, mhi = 0u;
-#pragma unroll
-            for (int b = 0; b < RS_RADIX_BITS; ++b) {
-                const uint32_t mb = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
-                const uint64_t bal = __ballot((int)mb < 0);
-                mlo |= (uint32_t)bal ^ mb;
-                mhi |= (uint32_t)(bal >> 32) ^ mb;
-            }
-            const uint64_t peers = __ballot(valid) & ~(((uint64_t)mhi << 32) | mlo);
+            const uint64_t peers = wave_digit_peers(d, valid);
             const uint32_t below = (uint32_t)__popcll(peers & lt);
             const uint32_t count = (uint32_t)__popcll(peers);
             const uint32_t basec = wcnt[w][d];
