@@ -238,13 +238,20 @@ struct KeyFromTriplets {
 // the lanes that differ from this lane are the bit's ballot xor this lane's bit spread over 32
 // bits (0 or all ones); one OR per bit collects them.
 __device__ __forceinline__ uint64_t wave_digit_peers(uint32_t d, bool valid) {
+    uint32_t mb[RS_RADIX_BITS];
+    uint64_t bal[RS_RADIX_BITS];
+#pragma unroll
+    for (int b = 0; b < RS_RADIX_BITS; ++b) {  // all ballots first: no wait on each one
+        mb[b] = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+        bal[b] = __ballot((int)mb[b] < 0);
+    }
     uint32_t mlo = 0u, mhi = 0u;
 #pragma unroll
     for (int b = 0; b < RS_RADIX_BITS; ++b) {
-        const uint32_t mb = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
-        const uint64_t bal = __ballot((int)mb < 0);
-        mlo |= (uint32_t)bal ^ mb;
-        mhi |= (uint32_t)(bal >> 32) ^ mb;
+        // acc | (ballot ^ mb) in one three-input bit operation per half (truth table 0xF6 for
+        // the operand order acc, ballot, mb)
+        mlo = __builtin_amdgcn_bitop3_b32(mlo, (uint32_t)bal[b], mb[b], 0xF6);
+        mhi = __builtin_amdgcn_bitop3_b32(mhi, (uint32_t)(bal[b] >> 32), mb[b], 0xF6);
     }
     return __ballot(valid) & ~(((uint64_t)mhi << 32) | mlo);
 }
