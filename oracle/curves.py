@@ -78,6 +78,22 @@ def zmorton_index(k, r, c):
     return d
 
 
+def zmorton_index_array(k, r, c):
+    """zmorton_index over arrays: the same quadrant descent (TL, TR, BL, BR, Section 3.1), level by
+    level from the top, applied to every cell at once."""
+    r = np.asarray(r, np.int64).copy()
+    c = np.asarray(c, np.int64).copy()
+    d = np.zeros(r.shape, np.int64)
+    while k > 0:
+        h = 1 << (k - 1)
+        q = 2 * (r >= h) + (c >= h)
+        d += q * h * h
+        r %= h
+        c %= h
+        k -= 1
+    return d
+
+
 def zmorton_order(k):
     side = 1 << k
     cells = [(r, c) for r in range(side) for c in range(side)]

@@ -125,7 +125,13 @@ def workload(name, seed=0, kind="float"):
     rmat24  : R-MAT scale 24, edge factor 16
     chunglu : Chung-Lu gamma 2.1, n = 10**7, E = 2*10**8
     rmatS   : R-MAT of scale S (e.g. 'rmat18')
+    rmatSp  : R-MAT of scale S under a random relabelling of rows and of columns (row r becomes
+              permutation(m, seed + 1)[r], column c becomes permutation(n, seed + 2)[c]); same
+              entries, values and x, with the generator's index locality removed
     """
+    relabel = name.startswith("rmat") and name.endswith("p")
+    if relabel:
+        name = name[:-1]
     if name == "chunglu":
         n = 10_000_000
         row, col = chunglu(n, 200_000_000, 2.1, seed)
@@ -136,6 +142,9 @@ def workload(name, seed=0, kind="float"):
         m = n = 1 << s
     else:
         raise ValueError("unknown workload " + name)
+    if relabel:
+        row = permutation(m, seed + 1).astype(np.int32)[row]
+        col = permutation(n, seed + 2).astype(np.int32)[col]
     val = values(len(row), seed, STREAM_VAL, kind)
     x = xvec(n, seed, kind)
     return dict(m=m, n=n, row=row, col=col, val=val, x=x)

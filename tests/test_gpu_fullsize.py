@@ -1,11 +1,13 @@
-"""Full-size parity on the benchmark workloads (R-MAT scale 24 and the Chung-Lu matrix with rows
-of up to ~1.8M entries), in the launch configuration the benchmark times.
+"""Full-size parity on the benchmark workloads (R-MAT scale 24, the same matrix under a random
+relabelling of rows and columns, and the Chung-Lu matrix with rows of up to ~1.8M entries), in
+the launch configuration the benchmark times.
 
 The oracle cannot canonicalise 2.7e8 triplets in seconds, so it is checked on sampled outputs:
   * sampled rows (random rows, the longest rows, first and last) against the oracle's Algorithm 1
     restricted to those rows (row-scaled error <= 1e-12), and their CRS slices bit-exactly;
-  * sampled CSBH block rows decoded and compared bit-exactly with the oracle's canonical triplets
-    of those rows, with the Hilbert order checked inside every block;
+  * sampled CSBH and CSB block rows decoded and compared bit-exactly with the oracle's canonical
+    triplets of those rows, with the Hilbert (CSBH) or Z-Morton (CSB) order checked inside every
+    block;
   * properties at every size: every merge tile start lies on the merge path; A 1 equals the row
     sums of the raw triplets within the row-scaled tolerance, for all rows.
 """
@@ -18,7 +20,7 @@ import synth
 from oracle import curves, measure, spmv
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
-FMTS = ["rowsplit", "merge", "csbh", "bcohc", "bcohch"]
+FMTS = ["rowsplit", "merge", "csbh", "csb", "bcohc", "bcohch"]
 
 
 def say(*a):
@@ -26,7 +28,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module", params=["rmat24", "chunglu"])
+@pytest.fixture(scope="module", params=["rmat24", "rmat24p", "chunglu"])
 def big(request):
     import torch
 
@@ -103,9 +105,10 @@ def test_crs_row_slices_exact(big):
     A.close()
 
 
-def test_csbh_block_rows_exact(big):
+@pytest.mark.parametrize("fmt", ["csbh", "csb"])
+def test_csb_block_rows_exact(big, fmt):
     spx, w, dev, _ = big
-    A = _convert(spx, w, dev, "csbh")
+    A = _convert(spx, w, dev, fmt)
     k = A.log2_beta
     beta = 1 << k
     assert k == measure.csb_log2_beta(w["m"], w["n"])
@@ -123,7 +126,10 @@ def test_csbh_block_rows_exact(big):
         lr, lc = p >> 16, p & 0xFFFF
         row = br * beta + lr
         colx = blk * beta + lc
-        h = curves.hilbert_index_array(k, lr, lc)
+        if fmt == "csbh":
+            h = curves.hilbert_index_array(k, lr, lc)
+        else:
+            h = curves.zmorton_index_array(k, lr, lc)
         same = blk[1:] == blk[:-1]
         assert np.all(h[1:][same] > h[:-1][same])
         sel = np.flatnonzero((w["row"] >= br * beta) & (w["row"] < (br + 1) * beta))

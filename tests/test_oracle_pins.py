@@ -571,6 +571,122 @@ def test_bcoh_partitions_and_order():
         assert [bkey(i) for i in perm] == [bkey(i) for i in want]
 
 
+def _bcoh_hand_made():
+    """A 4 x 4 matrix with beta = 2 (k = 1), written out by hand.
+
+    Raw triplets: row 0 holds 70000 raw entries (repeats of (0,0) and (0,3)), then (2,1), (3,0),
+    (3,1): E = 70003, target = 2^16, so the 65536th raw triplet lies in row 0 and row 1 starts the
+    second partition: partitions are rows [0,1) and [1,4).
+    Canonical entries: (0,0)=1, (0,3)=2, (2,1)=3, (3,0)=4, (3,1)=5.
+    Block Hilbert order (level 1, the figure's 2x2 order over (block row, block column)):
+    (0,0), (1,0), (1,1), (0,1).  Hilbert index of level 2 of the entries (figure's 4x4 order):
+    (0,0)->0, (0,3)->15, (2,1)->7, (3,0)->5, (3,1)->6.
+    """
+    raw_rows = np.array([0] * 70000 + [2, 3, 3])
+    crow, ccol, cval = [0, 0, 2, 3, 3], [0, 3, 1, 0, 1], [1.0, 2.0, 3.0, 4.0, 5.0]
+    part_row, part_blk = [0, 1, 4], [0, 2, 3]
+    blk_ptr = [0, 1, 2, 5]
+    blk_coord = [(0 << 16) | 0, (0 << 16) | 1, (1 << 16) | 0]
+    # BCOHC: partition 0 = blocks (0,0) then (0,1); partition 1 = block (1,0) row by row
+    c_packed = [0, 1, (0 << 16) | 1, (1 << 16) | 0, (1 << 16) | 1]
+    c_vals = [1.0, 2.0, 3.0, 4.0, 5.0]
+    # BCOHCH: partition 1 in Hilbert order of (row, col): (3,0), (3,1), (2,1)
+    h_packed = [0, 1, (1 << 16) | 0, (1 << 16) | 1, (0 << 16) | 1]
+    h_vals = [1.0, 2.0, 4.0, 5.0, 3.0]
+    return (raw_rows, crow, ccol, cval, part_row, part_blk, blk_ptr, blk_coord,
+            (c_packed, c_vals), (h_packed, h_vals))
+
+
+def test_bcoh_decode_and_check_hand_made():
+    from oracle import bcoh
+    (raw_rows, crow, ccol, cval, part_row, part_blk, blk_ptr, blk_coord, C, H) = _bcoh_hand_made()
+    E = len(raw_rows)
+    # decode gives the triplets in storage order
+    r, c, v = bcoh.decode(1, blk_ptr, blk_coord, *C)
+    assert r.tolist() == [0, 0, 2, 3, 3] and c.tolist() == [0, 3, 1, 0, 1]
+    assert v.tolist() == [1.0, 2.0, 3.0, 4.0, 5.0]
+    r, c, v = bcoh.decode(1, blk_ptr, blk_coord, *H)
+    assert r.tolist() == [0, 0, 3, 3, 2] and c.tolist() == [0, 3, 0, 1, 1]
+    for hil, (pk, vals) in ((False, C), (True, H)):
+        args = dict(m=4, n=4, k=1, raw_rows=raw_rows, E=E, part_row=part_row, part_blk=part_blk,
+                    blk_ptr=blk_ptr, blk_coord=blk_coord, packed=pk, values=vals, crow=crow,
+                    ccol=ccol, cval=cval, hilbert_entries=hil)
+        bcoh.check_bcoh(**args)
+        other = H if not hil else C      # the other format's storage order
+        bad = [dict(packed=other[0], values=other[1]),                 # wrong order inside a block
+               dict(part_row=[0, 4]),                                  # one partition only
+               dict(part_blk=[0, 1, 3]),                               # wrong first block
+               dict(blk_ptr=[0, 2, 2, 5]),                             # empty block
+               dict(blk_coord=[0, 1, (1 << 16) | 1]),                  # block (1,1) instead of (1,0)
+               dict(values=list(vals[:4]) + [np.nextafter(vals[4], 9.0)])]   # one value off by 1 ulp
+        for b in bad:
+            with pytest.raises(AssertionError):
+                bcoh.check_bcoh(**dict(args, **b))
+
+
+def _partition_starts_by_positions(m, raw_rows):
+    """Partition starts from the reading, computed through sorted triplet positions: the row after
+    the one holding the (j * target)-th raw triplet (1-based, triplets sorted by row) starts a
+    partition, for j = 1, 2, ...; so do row 0 and every multiple of the row window."""
+    from oracle import bcoh
+    srt = sorted(int(r) for r in raw_rows)
+    t = bcoh.target(len(srt))
+    starts = {0}
+    starts.update(range(0, m, bcoh.WINDOW))
+    j = 1
+    while j * t <= len(srt):
+        q = srt[j * t - 1]
+        if q + 1 < m:
+            starts.add(q + 1)
+        j += 1
+    return sorted(starts) + [m]
+
+
+def test_bcoh_partition_starts_brute_force():
+    from oracle import bcoh
+    rng = np.random.default_rng(11)
+    cases = [(30000, np.minimum(rng.zipf(1.3, 500_000) - 1, 29999)),     # heavy head rows
+             (20000, rng.integers(0, 20000, 300_000)),                   # uniform
+             (9000, np.repeat([3, 8191, 8192, 8999], [200_000, 10, 70_000, 5]))]  # long rows, window edge
+    for m, rows in cases:
+        got = bcoh.partition_starts(m, rows, len(rows)).tolist()
+        assert got == _partition_starts_by_positions(m, rows)
+
+
+def test_zmorton_array_matches_scalar_and_figure(golden):
+    # the vectorised descent agrees with the scalar one on every cell up to 64 x 64, and both with
+    # the figure's 8 x 8 order
+    for k in range(7):
+        side = 1 << k
+        r, c = np.divmod(np.arange(side * side), side)
+        want = [curves.zmorton_index(k, a, b) for a, b in zip(r, c)]
+        assert curves.zmorton_index_array(k, r, c).tolist() == want
+    for size, *cells in golden("zmorton_figure.txt"):
+        k = int(size).bit_length() - 1
+        rc = np.array(_cells(cells))
+        assert curves.zmorton_index_array(k, rc[:, 0], rc[:, 1]).tolist() == list(range(len(cells)))
+
+
+def test_check_csb_zmorton_hand_made():
+    # 4x4, beta = 2: block 0 holds (0,0)=1, (0,1)=3, (1,0)=2; block 3 holds (3,3)=4.
+    # Z-Morton order inside a 2x2 block (the paper's figure): TL, TR, BL, BR.
+    blk_ptr = [0, 3, 3, 3, 4]
+    z_packed = [(0 << 16) | 0, (0 << 16) | 1, (1 << 16) | 0, (1 << 16) | 1]
+    z_val = [1.0, 3.0, 2.0, 4.0]
+    canon = ([0, 0, 1, 3], [0, 1, 0, 3], [1.0, 3.0, 2.0, 4.0])
+    formats.check_csb(4, 4, 1, blk_ptr, z_packed, z_val, *canon, "zmorton")
+    # the Hilbert order of the same block is not Z-Morton order (and vice versa)
+    h_packed = [(0 << 16) | 0, (1 << 16) | 0, (0 << 16) | 1, (1 << 16) | 1]
+    h_val = [1.0, 2.0, 3.0, 4.0]
+    formats.check_csb(4, 4, 1, blk_ptr, h_packed, h_val, *canon, "hilbert")
+    with pytest.raises(AssertionError):
+        formats.check_csb(4, 4, 1, blk_ptr, h_packed, h_val, *canon, "zmorton")
+    with pytest.raises(AssertionError):
+        formats.check_csb(4, 4, 1, blk_ptr, z_packed, z_val, *canon, "hilbert")
+    with pytest.raises(AssertionError):   # entry moved to the wrong block
+        formats.check_csb(4, 4, 1, [0, 2, 3, 3, 4], z_packed, z_val, *canon, "zmorton")
+
+
 def test_parcrs_equals_algorithm1_bitwise():
     # the row-parallel loop sums every row in the same order as Algorithm 1
     rng = np.random.default_rng(6)
