@@ -61,6 +61,19 @@ typedef int32_t spx_format;
 #define SPX_BCOHC 4
 /* BCOHCH: as BCOHC with every partition's entries sorted by the Hilbert curve over (row, col). */
 #define SPX_BCOHCH 5
+/* Compressed sparse blocks over ranked columns, CSBR (the block idea of Section 3.1 -- a block row
+ * keeps its slice of y on chip and reads only part of x -- laid out for a GPU):
+ *   - columns are ranked by decreasing raw triplet count (ties: increasing column index); only
+ *     columns with at least one triplet are ranked, and rank i holds column col_order[i];
+ *   - rows form block rows (panels) of 2^13 rows, whose y slice lives in LDS during a product;
+ *   - a block is (panel, 2^19 consecutive ranks); blocks are stored panel by panel in rank order;
+ *   - inside a block, entries are stored column-major: by rank, then by row; each entry packs
+ *     (rank mod 2^19) << 13 | (row mod 2^13) into 32 bits.
+ * A product first gathers x into rank order (x_r[i] = x[col_order[i]]); a wave then reads
+ * consecutive entries whose ranks ascend, so lanes that share a column, or neighbouring ranks,
+ * share cache lines of x_r, and the most frequent columns occupy the first lines.
+ * Columns are limited to 2^26 (the column count is bucketed in LDS), FP64 values only. */
+#define SPX_CSB_RANKED 6
 
 typedef int32_t spx_dtype;
 #define SPX_F64 0
@@ -128,12 +141,16 @@ typedef int32_t spx_array;
 #define SPX_ARRAY_COL_IND 1 /* CRS formats: int32[nnz], ascending inside a row              */
 #define SPX_ARRAY_VALUES 2  /* all formats: values[nnz] in storage order, of the stored type */
 #define SPX_ARRAY_BLK_PTR 3 /* CSB/CSBH: int32[nbr*nbc+1], blocks in row-wise order;
+                             * CSBR: int32[panels*segments+1], block (panel, rank segment) at
+                             * panel * segments + segment;
                              * BCOHC/BCOHCH: int32[blocks+1], first entry of each stored block */
 #define SPX_ARRAY_PACKED 4  /* CSB/CSBH: uint32[nnz], (local_row << 16) | local_col, in the
-                             * block's Hilbert (CSBH) or Z-Morton (CSB) order                  */
+                             * block's Hilbert (CSBH) or Z-Morton (CSB) order; CSBR:
+                             * (rank mod 2^19) << 13 | (row mod 2^13), column-major in a block */
 #define SPX_ARRAY_PARTS 5   /* format's work-unit table, int32 (layout is internal; BCOHC /
                              * BCOHCH: P+1 partition first rows, then P+1 first blocks)     */
 #define SPX_ARRAY_BLK_COORD 6 /* BCOHC/BCOHCH: uint32[blocks], (block_row << 16) | block_col */
+#define SPX_ARRAY_COL_ORDER 7 /* CSBR: int32[ranked columns], the column of each rank          */
 
 /* Optional device allocator: alloc returns NULL on failure; free accepts what alloc returned. */
 typedef void* (*spx_alloc_fn)(size_t bytes, void* stream, void* ctx);
@@ -150,7 +167,9 @@ spx_status spx_convert_opts_default(spx_convert_opts* opts);
  * compress the arrays).  The sort is a stable device radix sort on the format's key:
  *   CRS:  (row, col);
  *   CSBH: (block row, block column, Hilbert index of the local (row, col) in the block);
- *   CSB:  the same with the Z-Morton index.
+ *   CSB:  the same with the Z-Morton index;
+ *   CSBR: (panel, column rank, row), after a count of the raw triplets per column and a sort of
+ *         the columns by that count.
  * Repeated coordinates become one entry whose value is the sum in increasing triplet index.
  * The work-unit table the product uses is built here as well, and counted in the conversion.
  *
@@ -160,7 +179,8 @@ spx_status spx_convert_opts_default(spx_convert_opts* opts);
  * out:  host; receives a new handle on success, NULL on any error.
  * rep:  host, may be NULL.  convert_ms covers all device work of the call.
  * The call returns after the device work is complete (it reads back the entry count).
- * Errors: INVALID_ARG, RANGE (m, n or nnz beyond int32, or a CSB / BCOHC key beyond 64 bits),
+ * Errors: INVALID_ARG, RANGE (m, n or nnz beyond int32, a CSB / BCOHC key beyond 64 bits, or
+ * more than 2^26 columns for CSBR),
  * INDEX (an index out of range; indices are always checked), UNSUPPORTED (reduced-precision values
  * for the block formats; sum_duplicates=0 for BCOHC / BCOHCH), NOMEM, HIP, DEVICE (a device-side
  * list of the sort outgrew its bound; not expected).  On error every temporary is freed.
@@ -174,7 +194,7 @@ spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt, const spx_conver
  * Asynchronous on `stream`.  A handle holds per-product scratch, so at most one product per
  * handle may be in flight at a time; products on different handles may overlap freely.
  * Summation order: fixed for the CRS formats (repeated products are bitwise identical); the block
- * formats (CSB, CSBH, BCOHC, BCOHCH) add products into an on-chip slice of y with float atomics,
+ * formats (CSB, CSBH, CSBR, BCOHC, BCOHCH) add products into an on-chip slice of y with float atomics,
  * so their last bits may differ from run to run (always within the row-scaled 1e-12 bound).
  */
 spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* stream);

@@ -85,3 +85,70 @@ def check_csb(m, n, log2_beta, blk_ptr, packed, val, canon_row, canon_col, canon
     a = v[order].view(np.int64)
     b = np.asarray(canon_val, np.float64).view(np.int64)
     assert np.array_equal(a, b), "values differ bitwise"
+
+
+# ---------------------------------------------------------------- CSB over ranked columns
+#
+# CSBR keeps the block idea of Section 3.1 (a block row's slice of y stays on chip, and a block
+# reads only a range of x) with two changes of layout, both pure reorderings of the stored
+# entries:
+#   * columns are ranked by decreasing number of raw triplets, ties by increasing column; only
+#     columns with at least one triplet get a rank;
+#   * block rows (panels) are 2^pb rows; a block is (panel, 2^rb consecutive ranks); blocks are
+#     stored panel by panel, segment by segment; inside a block the entries are ordered by rank,
+#     then row, and each packs (rank mod 2^rb) << pb | (row mod 2^pb).
+# The product is the same y = A x; only the summation order differs.
+
+CSBR_PB = 13
+CSBR_RB = 19
+
+
+def csbr_col_order(n, raw_cols):
+    """Column of each rank: decreasing raw triplet count, ties by increasing column index."""
+    cnt = np.bincount(np.asarray(raw_cols, np.int64), minlength=n)[:n]
+    cols = np.arange(n, dtype=np.int64)
+    order = sorted(cols[cnt > 0].tolist(), key=lambda c: (-int(cnt[c]), c))
+    return np.asarray(order, np.int64)
+
+
+def decode_csbr(m, blk_ptr, packed, col_order, pb=CSBR_PB, rb=CSBR_RB):
+    """Triplet coordinates in storage order: (row, col, panel, rank)."""
+    blk_ptr = np.asarray(blk_ptr, np.int64)
+    npan = max(1, -(-m // (1 << pb)))
+    nblk = len(blk_ptr) - 1
+    assert nblk % npan == 0, "blk_ptr length is not panels x segments + 1"
+    nseg = nblk // npan
+    blk = np.repeat(np.arange(nblk, dtype=np.int64), np.diff(blk_ptr))
+    panel, seg = blk // nseg, blk % nseg
+    p = np.asarray(packed, np.int64) & 0xFFFFFFFF
+    rank = (seg << rb) + (p >> pb)
+    row = (panel << pb) + (p & ((1 << pb) - 1))
+    col_order = np.asarray(col_order, np.int64)
+    assert np.all(rank < len(col_order)), "rank beyond the ranked columns"
+    return row, col_order[rank], panel, rank
+
+
+def check_csbr(m, n, raw_cols, blk_ptr, packed, val, col_order, canon_row, canon_col, canon_val,
+               pb=CSBR_PB, rb=CSBR_RB):
+    """Raise AssertionError unless the CSBR arrays hold exactly the canonical triplets in the
+    format's storage order: the ranking, the segment count, (panel, rank, row) strictly
+    increasing along storage, and bit-identical values."""
+    want_order = csbr_col_order(n, raw_cols)
+    assert np.array_equal(np.asarray(col_order, np.int64), want_order), "column ranking"
+    nr = len(want_order)
+    rbits = max(rb, (max(nr, 1) - 1).bit_length())
+    npan = max(1, -(-m // (1 << pb)))
+    blk_ptr = np.asarray(blk_ptr, np.int64)
+    assert len(blk_ptr) == npan * (1 << (rbits - rb)) + 1, "segments per panel"
+    assert blk_ptr[0] == 0 and blk_ptr[-1] == len(packed) == len(val), "blk_ptr ends"
+    assert np.all(np.diff(blk_ptr) >= 0), "blk_ptr not monotone"
+    row, col, panel, rank = decode_csbr(m, blk_ptr, packed, want_order, pb, rb)
+    assert np.all(row < m), "row outside the matrix"
+    key = [(int(a), int(b), int(c)) for a, b, c in zip(panel, rank, row)]
+    assert all(key[i] < key[i + 1] for i in range(len(key) - 1)), "not in (panel, rank, row) order"
+    order = np.lexsort((col, row))
+    assert np.array_equal(row[order], np.asarray(canon_row, np.int64)), "rows"
+    assert np.array_equal(col[order], np.asarray(canon_col, np.int64)), "cols"
+    a = np.asarray(val, np.float64)[order].view(np.int64)
+    b = np.asarray(canon_val, np.float64).view(np.int64)
+    assert np.array_equal(a, b), "values differ bitwise"

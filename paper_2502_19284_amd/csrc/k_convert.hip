@@ -140,6 +140,18 @@ struct KeyBcoh {
     }
 };
 
+// CSBR: (panel, rank of the column, row inside the panel); the rank field is rbits wide, so the
+// key shifted right by 32 (= CR_RB + CR_PB) is the block index panel * segments + segment
+struct KeyCsbr {
+    const int32_t* rank_of;
+    int rbits;
+    __device__ uint64_t operator()(uint32_t r, uint32_t c) const {
+        const uint64_t panel = r >> CR_PB;
+        const uint64_t rank = (uint32_t)rank_of[c];
+        return (panel << (rbits + CR_PB)) | (rank << CR_PB) | (uint64_t)(r & ((1u << CR_PB) - 1u));
+    }
+};
+
 template <typename KeyFn>
 __global__ __launch_bounds__(256) void k_keys(const int32_t* row, const int32_t* col, int64_t E,
                                               int32_t m, int32_t n, uint64_t* keys, uint32_t* err,
@@ -166,6 +178,53 @@ hipError_t launch_keys_csb(const int32_t* row, const int32_t* col, int64_t E, in
         SPX_LAUNCH("keys", (k_keys<KeyCsb<false>>), dim3(grid_for(E, 256, KEYS_MAX_GRID)),
                    dim3(256), 0, s, row, col, E, m, n, keys, err, masks,
                    KeyCsb<false>{k, (uint64_t)nbc});
+    return hipGetLastError();
+}
+
+hipError_t launch_keys_csbr(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+                            int32_t n, const int32_t* rank_of, int rbits, uint64_t* keys,
+                            uint32_t* err, unsigned long long* masks, hipStream_t s) {
+    SPX_LAUNCH("keys", (k_keys<KeyCsbr>), dim3(grid_for(E, 256, KEYS_MAX_GRID)), dim3(256), 0, s,
+               row, col, E, m, n, keys, err, masks, KeyCsbr{rank_of, rbits});
+    return hipGetLastError();
+}
+
+__global__ void k_rank_keys(const uint32_t* __restrict__ counts, int32_t n,
+                            uint64_t* __restrict__ keys) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (int64_t)gridDim.x * blockDim.x)
+        keys[c] = ((uint64_t)(0xFFFFFFFFu - counts[c]) << 32) | (uint64_t)c;
+}
+
+hipError_t launch_rank_keys(const uint32_t* counts, int32_t n, uint64_t* keys, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    SPX_LAUNCH("rank_keys", k_rank_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, counts, n, keys);
+    return hipGetLastError();
+}
+
+// Sorted position i holds column c = low half of the key; its count is zero when the high half is
+// all ones, and the counted columns come first.
+__global__ void k_rank_scatter(const uint64_t* __restrict__ sorted, int32_t n,
+                               int32_t* __restrict__ order, int32_t* __restrict__ rank_of,
+                               uint32_t* __restrict__ nranked) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = sorted[i];
+        const int32_t c = (int32_t)(uint32_t)key;
+        rank_of[c] = (int32_t)i;
+        if ((key >> 32) != 0xFFFFFFFFull) {
+            order[i] = c;
+            const bool last = i + 1 == n || (sorted[i + 1] >> 32) == 0xFFFFFFFFull;
+            if (last) *nranked = (uint32_t)(i + 1);
+        }
+    }
+}
+
+hipError_t launch_rank_scatter(const uint64_t* sorted, int32_t n, int32_t* order,
+                               int32_t* rank_of, uint32_t* nranked, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    SPX_LAUNCH("rank_scatter", k_rank_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, sorted, n,
+               order, rank_of, nranked);
     return hipGetLastError();
 }
 
@@ -1262,7 +1321,8 @@ hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_su
 // next head (or E).  Its value is vals[s] + vals[s+1] + ... in increasing position, i.e. in
 // increasing triplet index, because the sort that carried the values is stable.  The last entry
 // of each row (block) writes u+1 at its row (block), for the max-scan that follows.
-// MODE 0: CRS (column index), 1: CSB Hilbert, 2: CSB Z-Morton (packed local row/column)
+// MODE 0: CRS (column index), 1: CSB Hilbert, 2: CSB Z-Morton (packed local row/column),
+// 5: CSBR (the low 32 bits of the key are the packed (rank, row) position inside the block)
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ keys,
                                                 const double* __restrict__ vals,
@@ -1280,7 +1340,9 @@ __global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ key
         for (int64_t j = s + 1; j < e; ++j) acc = acc + vals[j];
         val_out[u] = acc;
         const uint64_t major = key >> shiftbits;
-        if (MODE != 0) {
+        if (MODE == 5) {
+            idx_out[u] = (int32_t)(uint32_t)(key & ((1ull << shiftbits) - 1ull));
+        } else if (MODE != 0) {
             const int k = shiftbits >> 1;
             const uint32_t d = (uint32_t)(key & ((1ull << shiftbits) - 1ull));
             uint32_t lc, lr;
@@ -1301,6 +1363,15 @@ hipError_t launch_gather_csr(const uint64_t* keys, const double* vals, const int
     if (nnz_out <= 0) return hipSuccess;
     SPX_LAUNCH("gather", (k_gather<0>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys,
                vals, head_pos, E, nnz_out, cbits, hm, col_out, val_out, row_end);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_csbr(const uint64_t* keys, const double* vals, const int32_t* head_pos,
+                              int64_t E, int64_t nnz_out, uint32_t* packed_out, double* val_out,
+                              int32_t* blk_end, hipStream_t s) {
+    if (nnz_out <= 0) return hipSuccess;
+    SPX_LAUNCH("gather", (k_gather<5>), dim3(grid_for(nnz_out, 256)), dim3(256), 0, s, keys, vals,
+               head_pos, E, nnz_out, 32, HotMap{}, (int32_t*)packed_out, val_out, blk_end);
     return hipGetLastError();
 }
 
@@ -1352,7 +1423,7 @@ __device__ __forceinline__ double dg_lane(double v, int k) {  // v of lane k (k 
 template <int MODE>
 __device__ __forceinline__ void dg_mark_end(int32_t* ends, uint64_t key, int shiftbits, int64_t u,
                                             bool more, uint64_t next) {
-    if (MODE >= 3) return;  // block starts are marked by the head
+    if (MODE == 3 || MODE == 4) return;  // block starts are marked by the head
     const uint64_t major = key >> shiftbits;
     if (!more || (next >> shiftbits) != major) ends[major] = (int32_t)(u + 1);
 }
@@ -1457,7 +1528,9 @@ __global__ __launch_bounds__(DG_NT) void k_dedup_gather(
         }
         const uint64_t major = key >> shiftbits;
         const uint32_t d = (uint32_t)(key & lowmask);
-        if (MODE >= 3) {  // BCOHC / BCOHCH: packed local position, block-start flag
+        if (MODE == 5) {  // CSBR: the packed position is the key's low half
+            idx_out[u] = (int32_t)d;
+        } else if (MODE == 3 || MODE == 4) {  // BCOHC / BCOHCH: packed local position, block-start flag
             const int k = shiftbits >> 1;
             const uint32_t mask = (1u << k) - 1u;
             uint32_t lc, lr;
@@ -1544,6 +1617,7 @@ hipError_t launch_dedup_gather(const uint64_t* keys, const double* vals, int64_t
         DG_CASE(2)
         DG_CASE(3)
         DG_CASE(4)
+        DG_CASE(5)
         default: return hipErrorInvalidValue;
     }
 #undef DG_CASE

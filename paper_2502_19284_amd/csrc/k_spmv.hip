@@ -132,3 +132,105 @@ hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStrea
                            A->cb_partials, y, A->log2_beta, A->m);
     return hipGetLastError();
 }
+
+// ================================================================== CSBR (Section 3.1 blocks over
+// ranked columns)
+//
+// x_r[i] = x[order[i]]: the ranked copy of x that the product reads.
+__global__ void k_csbr_xrank(const int32_t* __restrict__ order, int32_t nr,
+                             const double* __restrict__ x, double* __restrict__ xr) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nr) xr[i] = x[order[i]];
+}
+
+// Work unit u = entries [k0, k1) of panel p (CR_PB rows).  The workgroup keeps the panel's y
+// slice in LDS.  Entries are read in storage order, CR_NT consecutive entries per wave-row, so
+// the lanes of a wave hold ascending ranks: their x_r loads fall on few cache lines, and the
+// lines of the most frequent columns stay in L2 for every panel.  An entry's rank is its block's
+// segment (found from the panel's block starts) times 2^CR_RB plus the packed rank field.
+// Products are added into the slice with LDS float atomics; a unit covering its whole panel
+// writes the slice to y, otherwise to its partial slot, reduced in slot order afterwards.
+__global__ __launch_bounds__(CR_NT) void k_spmv_csbr(const int32_t* __restrict__ blk_ptr,
+                                                     const uint32_t* __restrict__ packed,
+                                                     const double* __restrict__ val,
+                                                     const double* __restrict__ xr,
+                                                     double* __restrict__ y,
+                                                     double* __restrict__ partials,
+                                                     const int4* __restrict__ units,
+                                                     int32_t nseg, int32_t m) {
+    __shared__ double s_y[1 << CR_PB];
+    __shared__ int32_t s_seg[CR_SEG_LDS];
+    const int tid = threadIdx.x;
+    const int4 U = units[blockIdx.x];
+    const int panel = U.x, k0 = U.y, k1 = U.z, slot = U.w;
+    const int32_t* gseg = blk_ptr + (int64_t)panel * nseg;
+    const bool lds_seg = nseg + 1 <= CR_SEG_LDS;
+    for (int i = tid; i < (1 << CR_PB); i += CR_NT) s_y[i] = 0.0;
+    if (lds_seg)
+        for (int i = tid; i <= nseg; i += CR_NT) s_seg[i] = gseg[i];
+    __syncthreads();
+    const int32_t* seg = lds_seg ? s_seg : gseg;
+    constexpr uint32_t lmask = (1u << CR_PB) - 1u;
+    // segment of this thread's first entry: the last s with seg[s] <= k (seg[0] <= k0)
+    int sg = 0;
+    {
+        const int kf = k0 + tid;
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (seg[mid] <= kf) lo = mid;
+            else hi = mid - 1;
+        }
+        sg = lo;
+    }
+    int next = sg + 1 < nseg ? seg[sg + 1] : INT32_MAX;
+    for (int base = k0; base < k1; base += CR_NT * CR_IPT) {
+        uint32_t p[CR_IPT];
+        double v[CR_IPT];
+#pragma unroll
+        for (int q = 0; q < CR_IPT; ++q) {
+            const int k = base + q * CR_NT + tid;
+            p[q] = k < k1 ? ntload(packed + k) : 0u;
+            v[q] = k < k1 ? ntload(val + k) : 0.0;
+        }
+        double xv[CR_IPT];
+#pragma unroll
+        for (int q = 0; q < CR_IPT; ++q) {
+            const int k = base + q * CR_NT + tid;
+            while (k >= next) {  // entries ascend per thread: walk the segments forward
+                ++sg;
+                next = sg + 1 < nseg ? seg[sg + 1] : INT32_MAX;
+            }
+            xv[q] = k < k1 ? xr[((int64_t)sg << CR_RB) + (p[q] >> CR_PB)] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < CR_IPT; ++q) {
+            const int k = base + q * CR_NT + tid;
+            if (k < k1) atomicAdd(&s_y[p[q] & lmask], v[q] * xv[q]);
+        }
+    }
+    __syncthreads();
+    const int row0 = panel << CR_PB;
+    const int rows = min(1 << CR_PB, m - row0);
+    if (slot < 0) {
+        for (int i = tid; i < rows; i += CR_NT) ntstore(y + row0 + i, s_y[i]);
+    } else {
+        double* dst = partials + ((int64_t)slot << CR_PB);
+        for (int i = tid; i < rows; i += CR_NT) dst[i] = s_y[i];
+    }
+}
+
+hipError_t spmv_csbr(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
+    if (A->cr_nranked > 0)
+        SPX_LAUNCH("csbr_xrank", k_csbr_xrank, dim3(spx_div_up(A->cr_nranked, 256)), dim3(256), 0,
+                   s, A->cr_order, A->cr_nranked, x, A->cr_xr);
+    if (A->cb_nunits > 0)
+        SPX_LAUNCH("spmv_csbr", k_spmv_csbr, dim3(A->cb_nunits), dim3(CR_NT), 0, s, A->blk_ptr,
+                   A->packed, A->val, A->cr_xr, y, A->cb_partials, A->cb_units, (int32_t)A->nbc,
+                   A->m);
+    if (A->cb_nsplit > 0)
+        SPX_LAUNCH("spmv_csbr_reduce", k_spmv_csbh_reduce,
+                   dim3(A->cb_nsplit * (((1 << CR_PB) + CB_RED_NT - 1) / CB_RED_NT)),
+                   dim3(CB_RED_NT), 0, s, A->cb_split, A->cb_partials, y, CR_PB, A->m);
+    return hipGetLastError();
+}

@@ -223,7 +223,7 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
     HIP_TRY(launch_init_readback(rb_dev, s));
     const uint64_t* vs = nullptr;
     int failed = 0, heads = 0;
-    if (!spx_is_bcoh(fmt) && E > RS_LOCAL_MAX) {
+    if (!spx_is_bcoh(fmt) && fmt != SPX_CSB_RANKED && E > RS_LOCAL_MAX) {
         // CRS and CSB: the sort's first level builds the keys from the triplets (and checks
         // them)
         const int order = !spx_is_csb(fmt) ? 0 : fmt == SPX_CSB_HILBERT ? 1 : 2;
@@ -267,6 +267,9 @@ static spx_status build_keys_and_sort(const spx_coo_desc* coo, spx_format fmt, i
     if (spx_is_bcoh(fmt))
         HIP_TRY(launch_keys_bcoh(coo->row, coo->col, E, coo->m, coo->n, part_of, k, K2,
                                  fmt == SPX_BCOHCH, k0, &rb_dev->err, rb_dev->masks, s));
+    else if (fmt == SPX_CSB_RANKED)  // part_of carries the column ranks, K2 the rank width
+        HIP_TRY(launch_keys_csbr(coo->row, coo->col, E, coo->m, coo->n, part_of, K2, k0,
+                                 &rb_dev->err, rb_dev->masks, s));
     else if (spx_is_csb(fmt))
         HIP_TRY(launch_keys_csb(coo->row, coo->col, E, coo->m, coo->n, k, nbc,
                                 fmt == SPX_CSB_HILBERT, k0, &rb_dev->err, rb_dev->masks, s));
@@ -500,6 +503,166 @@ static spx_status convert_bcoh(const spx_coo_desc* coo, spx_format fmt, int k, i
     return SPX_OK;
 }
 
+// CSBR: raw triplets per column (bucketed count, checking every index), columns ranked by a sort
+// of (decreasing count, increasing column), triplets sorted by (panel, rank, row) with repeats
+// summed, block pointers over (panel, rank segment), then the CSBH work-unit tables over panels.
+static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* o, hipStream_t s,
+                               spx_matrix_s* A, AllocSet& tmp) {
+    const int64_t E = coo->nnz;
+    const int32_t m = coo->m, n = coo->n;
+    const int wbits = bcoh_row_bucket_bits(n);
+    if (wbits < 0) return fail(SPX_ERR_RANGE, "CSBR: %d columns, more than 2^26", n);
+    const int64_t npan = std::max<int64_t>(1, ((int64_t)m + (1 << CR_PB) - 1) >> CR_PB);
+    Readback* rb_dev;
+    SPX_TRY(tmp.get(&rb_dev, 1, "readback"));
+    HIP_TRY(launch_init_readback(rb_dev, s));
+    // 1. raw triplets per column
+    uint32_t *counts, *chist, *ctotal, *tsums;
+    int32_t* cols_out;
+    const size_t chn = bcoh_rows_hist_elems(n, E, wbits);
+    SPX_TRY(tmp.get(&counts, (size_t)n + 1, "column counts"));
+    SPX_TRY(tmp.get(&chist, chn > 0 ? chn : 1, "column bucket histogram"));
+    SPX_TRY(tmp.get(&cols_out, (size_t)(E > 0 ? E : 1), "columns by bucket"));
+    SPX_TRY(tmp.get(&ctotal, 1, "column bucket total"));
+    size_t tsn = std::max(scan_tile_count(chn > 0 ? (int64_t)chn : 1),
+                          scan_tile_count((int64_t)n + 2));
+    SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
+    HIP_TRY(launch_fill_u32(counts, (int64_t)n + 1, 0u, s));
+    // rows and columns trade places: the bucketed count runs over the column indices
+    HIP_TRY(launch_bcoh_rows_bucketed(coo->col, coo->row, E, n, m, wbits, chist, cols_out, tsums,
+                                      ctotal, counts, &rb_dev->err, s));
+    Readback rb;
+    SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+    if (rb.err)
+        return fail(SPX_ERR_INDEX, "a triplet index lies outside [0,%d) x [0,%d)", m, n);
+    // 2. column ranks
+    int32_t *order, *rank_of;
+    SPX_TRY(tmp.get(&order, (size_t)std::max<int32_t>(n, 1), "column order"));
+    SPX_TRY(tmp.get(&rank_of, (size_t)std::max<int32_t>(n, 1), "column ranks"));
+    if (n > 0) {
+        uint64_t *rk0, *rk1, *rv0, *rv1;
+        SPX_TRY(tmp.get(&rk0, (size_t)n, "rank keys"));
+        SPX_TRY(tmp.get(&rk1, (size_t)n, "rank keys"));
+        SPX_TRY(tmp.get(&rv0, (size_t)n, "rank payload"));
+        SPX_TRY(tmp.get(&rv1, (size_t)n, "rank payload"));
+        MsdScratch sc;
+        sc.z = msd_sizes(n);
+        for (int i = 0; i < 2; ++i) {
+            SPX_TRY(tmp.get(&sc.seg_start[i], (size_t)sc.z.cap_big, "sort segments"));
+            SPX_TRY(tmp.get(&sc.seg_len[i], (size_t)sc.z.cap_big, "sort segments"));
+        }
+        SPX_TRY(tmp.get(&sc.tbase, (size_t)sc.z.cap_big + 1, "sort segment tiles"));
+        SPX_TRY(tmp.get(&sc.tile_seg, (size_t)sc.z.cap_tiles, "sort tile segments"));
+        SPX_TRY(tmp.get(&sc.hist, (size_t)sc.z.hist, "radix histogram"));
+        SPX_TRY(tmp.get(&sc.tile_sums, (size_t)sc.z.tile_sums, "scan tile sums"));
+        SPX_TRY(tmp.get(&sc.chunks, (size_t)sc.z.cap_chunks, "sort chunks"));
+        uint32_t* ctr;
+        SPX_TRY(tmp.get(&ctr, 16, "sort counters"));
+        sc.counters = ctr;
+        HIP_TRY(launch_rank_keys(counts, n, rk0, s));
+        // bits that can vary: the low bits of (2^32 - 1 - count) up to E, and the column
+        const int eb = ceil_log2_u64((uint64_t)E + 1);
+        const int nb = ceil_log2_u64((uint64_t)n);
+        const uint64_t vary = ((eb >= 32 ? 0xFFFFFFFFull : ((1ull << eb) - 1ull)) << 32) |
+                              (nb >= 32 ? 0xFFFFFFFFull : ((1ull << nb) - 1ull));
+        const uint64_t *sorted, *vs;
+        int failed = 0;
+        MsdStats st;
+        HIP_TRY(radix_sort_msd(rk0, rv0, rk1, rv1, rk0, n, vary, sc, s, &sorted, &vs, &failed,
+                               &st));
+        if (failed) return fail(SPX_ERR_DEVICE, "radix sort: a device-side list overflowed");
+        HIP_TRY(launch_rank_scatter(sorted, n, order, rank_of, &rb_dev->totals[3], s));
+        SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+    }
+    const int32_t nranked = (int32_t)rb.totals[3];
+    const int rbits = std::max(CR_RB, ceil_log2_u64((uint64_t)std::max<int32_t>(nranked, 1)));
+    const int64_t nseg = (int64_t)1 << (rbits - CR_RB);
+    if (ceil_log2_u64((uint64_t)npan) + rbits + CR_PB > 64)
+        return fail(SPX_ERR_RANGE, "CSBR sort key exceeds 64 bits");
+    if ((double)npan * (double)nseg >= 2147483647.0)
+        return fail(SPX_ERR_RANGE, "CSBR: %lld x %lld blocks exceed the int32 block pointer range",
+                    (long long)npan, (long long)nseg);
+    keep(tmp, A, order);
+    A->cr_order = order;
+    A->cr_nranked = nranked;
+    A->log2_beta = CR_PB;
+    A->nbr = npan;
+    A->nbc = nseg;
+    // 3. sort by (panel, rank, row), sum repeats, populate
+    SortedEntries se;
+    if (E > 0)
+        SPX_TRY(sort_and_dedup(tmp, coo, SPX_CSB_RANKED, 0, nseg, 0, o->sum_duplicates, s, &se,
+                               rank_of, rbits));
+    A->sort = se.sort;
+    const int64_t nnz = se.nnz_out;
+    A->nnz = nnz;
+    double* val_out;
+    uint32_t* packed;
+    int32_t* bp;
+    const int64_t nblk = npan * nseg;
+    SPX_TRY(tmp.get(&val_out, (size_t)nnz, "values"));
+    SPX_TRY(tmp.get(&packed, (size_t)nnz, "packed indices"));
+    SPX_TRY(tmp.get(&bp, (size_t)nblk + 1, "blk_ptr"));
+    keep(tmp, A, val_out);
+    keep(tmp, A, packed);
+    keep(tmp, A, bp);
+    A->val = val_out;
+    A->value_type = SPX_F64;
+    A->packed = packed;
+    A->blk_ptr = bp;
+    HIP_TRY(launch_fill_i32(bp, nblk + 1, 0, s));
+    if (se.head_tiles)
+        HIP_TRY(launch_dedup_gather(se.keys, se.vals, E, se.head_tiles, 5, 32, HotMap{},
+                                    (int32_t*)packed, val_out, bp + 1, s));
+    else
+        HIP_TRY(launch_gather_csbr(se.keys, se.vals, nullptr, E, nnz, packed, val_out, bp + 1, s));
+    if (scan_tile_count(nblk) > tsn) {
+        SPX_TRY(tmp.get(&tsums, scan_tile_count(nblk), "scan tile sums"));
+        tsn = scan_tile_count(nblk);
+    }
+    HIP_TRY(launch_max_scan_i32(bp + 1, nblk, tsums, s));
+    // 4. work units over panels (heaviest first in launch order)
+    const int64_t unit = o->tile_items > 0 ? o->tile_items : CR_UNIT_DEFAULT;
+    int32_t *unit_ptr, *slot_ptr, *split_ptr;
+    SPX_TRY(tmp.get(&unit_ptr, (size_t)npan, "unit ptr"));
+    SPX_TRY(tmp.get(&slot_ptr, (size_t)npan, "slot ptr"));
+    SPX_TRY(tmp.get(&split_ptr, (size_t)npan, "split ptr"));
+    HIP_TRY(csbh_plan(bp, npan, nseg, unit, unit_ptr, slot_ptr, split_ptr, rb_dev->totals, s));
+    SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+    A->cb_nunits = (int32_t)rb.totals[0];
+    A->cb_nslots = (int32_t)rb.totals[1];
+    A->cb_nsplit = (int32_t)rb.totals[2];
+    int4 *units, *split;
+    double *partials, *xr;
+    SPX_TRY(tmp.get(&units, (size_t)A->cb_nunits, "units"));
+    SPX_TRY(tmp.get(&split, (size_t)std::max<int32_t>(A->cb_nsplit, 1), "split panels"));
+    SPX_TRY(tmp.get(&partials, (size_t)std::max<int32_t>(A->cb_nslots, 1) << CR_PB,
+                    "partial slices"));
+    SPX_TRY(tmp.get(&xr, (size_t)std::max<int32_t>(nranked, 1), "ranked x"));
+    keep(tmp, A, units);
+    keep(tmp, A, split);
+    keep(tmp, A, partials);
+    keep(tmp, A, xr);
+    A->cb_units = units;
+    A->cb_split = split;
+    A->cb_partials = partials;
+    A->cr_xr = xr;
+    HIP_TRY(csbh_units(bp, npan, nseg, unit, unit_ptr, slot_ptr, split_ptr, units, split, s));
+    if (A->cb_nunits > 1) {
+        // a unit's run time grows with its entries: launching the largest first keeps one large
+        // unit from starting last (stable order among equal sizes)
+        std::vector<int4> hu((size_t)A->cb_nunits);
+        SPX_TRY(sync_read(hu.data(), units, hu.size() * sizeof(int4), s));
+        std::stable_sort(hu.begin(), hu.end(),
+                         [](const int4& a, const int4& b) { return a.z - a.y > b.z - b.y; });
+        HIP_TRY(hipMemcpyAsync(units, hu.data(), hu.size() * sizeof(int4), hipMemcpyHostToDevice,
+                               s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    A->parts = A->cb_nunits;
+    return SPX_OK;
+}
+
 static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
                                const spx_convert_opts* o, hipStream_t s, spx_matrix_s* A,
                                AllocSet& tmp) {
@@ -512,6 +675,7 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
     const int rbits = ceil_log2_u64((uint64_t)(m > 1 ? m : 1));
     int k = 0;
     int64_t nbr = 0, nbc = 0;
+    if (fmt == SPX_CSB_RANKED) return convert_csbr(coo, o, s, A, tmp);
     if (spx_is_bcoh(fmt)) {
         k = o->log2_beta > 0 ? o->log2_beta : csbh_default_log2_beta(m, n);
         if (k < 1 || k > 16)
@@ -741,7 +905,7 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
     if (!out) return fail(SPX_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!coo) return fail(SPX_ERR_INVALID_ARG, "coo is NULL");
-    if (fmt != SPX_CSR_ROWSPLIT && fmt != SPX_CSR_MERGE && !spx_is_csb(fmt) && !spx_is_bcoh(fmt))
+    if (!spx_is_crs(fmt) && !spx_is_csb(fmt) && !spx_is_bcoh(fmt) && fmt != SPX_CSB_RANKED)
         return fail(SPX_ERR_INVALID_ARG, "unknown format %d", (int)fmt);
     if (coo->m < 0 || coo->n < 0 || coo->nnz < 0)
         return fail(SPX_ERR_INVALID_ARG, "negative size (m=%d n=%d nnz=%lld)", coo->m, coo->n,
@@ -766,12 +930,15 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
     if (o.hot_columns < -1) return fail(SPX_ERR_INVALID_ARG, "hot_columns < -1");
     if (o.value_type != SPX_F64 && o.value_type != SPX_F32 && o.value_type != SPX_BF16)
         return fail(SPX_ERR_INVALID_ARG, "unknown value_type %d", (int)o.value_type);
-    if (o.value_type != SPX_F64 && (spx_is_csb(fmt) || spx_is_bcoh(fmt)))
+    if (o.value_type != SPX_F64 && !spx_is_crs(fmt))
         return fail(SPX_ERR_UNSUPPORTED, "reduced-precision values are built for the CRS formats");
+    if (fmt == SPX_CSB_RANKED && o.log2_beta != 0 && o.log2_beta != CR_PB)
+        return fail(SPX_ERR_UNSUPPORTED, "CSBR panels are 2^%d rows (log2_beta 0 or %d)", CR_PB,
+                    CR_PB);
     if (spx_is_bcoh(fmt) && !o.sum_duplicates)
         return fail(SPX_ERR_UNSUPPORTED, "BCOHC/BCOHCH are built with repeats summed");
-    if (!spx_is_csb(fmt) && o.tile_items != 0)
-        return fail(SPX_ERR_UNSUPPORTED, "tile_items is only adjustable for CSB/CSBH");
+    if (!spx_is_csb(fmt) && fmt != SPX_CSB_RANKED && o.tile_items != 0)
+        return fail(SPX_ERR_UNSUPPORTED, "tile_items is only adjustable for CSB/CSBH/CSBR");
 
     hipStream_t s = (hipStream_t)stream;
     int device = 0;
@@ -865,6 +1032,7 @@ extern "C" spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* s
         case SPX_CSB_ZMORTON: HIP_TRY(spmv_csbh(A, x, y, s)); break;
         case SPX_BCOHC:
         case SPX_BCOHCH: HIP_TRY(spmv_bcoh(A, x, y, s)); break;
+        case SPX_CSB_RANKED: HIP_TRY(spmv_csbr(A, x, y, s)); break;
         default: return fail(SPX_ERR_INVALID_ARG, "corrupt handle");
     }
     return SPX_OK;
@@ -890,7 +1058,7 @@ static spx_status grow_scratch(spx_matrix_s* A, void** p, size_t* have, size_t n
 extern "C" spx_status spx_spmm(spx_matrix A, int32_t k, const void* x, int64_t ldx, void* y,
                                int64_t ldy, spx_layout layout, void* stream) {
     if (!A) return fail(SPX_ERR_INVALID_ARG, "matrix handle is NULL");
-    if (spx_is_csb(A->fmt) || spx_is_bcoh(A->fmt))
+    if (!spx_is_crs(A->fmt))
         return fail(SPX_ERR_UNSUPPORTED, "products with several right-hand sides are provided for "
                                          "the CRS formats");
     if (k < 1) return fail(SPX_ERR_INVALID_ARG, "k = %d, must be >= 1", k);
@@ -992,7 +1160,7 @@ extern "C" spx_status spx_matrix_export(spx_matrix A, spx_array which, void* dst
     int64_t len = 0;
     bool exists = false;
     const bool bcoh = spx_is_bcoh(A->fmt);
-    const bool crs = !spx_is_csb(A->fmt) && !bcoh;
+    const bool crs = spx_is_crs(A->fmt);
     switch (which) {
         case SPX_ARRAY_ROW_PTR:
             exists = crs;
@@ -1013,6 +1181,11 @@ extern "C" spx_status spx_matrix_export(spx_matrix A, spx_array which, void* dst
             exists = !crs;
             src = bcoh ? A->bh_blk_ptr : A->blk_ptr;
             len = bcoh ? (A->bh_nblocks + 1) * 4 : (A->nbr * A->nbc + 1) * 4;
+            break;
+        case SPX_ARRAY_COL_ORDER:
+            exists = A->fmt == SPX_CSB_RANKED;
+            src = A->cr_order;
+            len = (int64_t)A->cr_nranked * 4;
             break;
         case SPX_ARRAY_BLK_COORD:
             exists = bcoh;

@@ -31,6 +31,15 @@
 #define CB_LDS_BUDGET (64 * 1024)    // bytes of the output slice kept in LDS
 #define CB_BP_STAGE_MAX 8192         // block pointers staged in LDS when nbc+1 <= this
 
+// CSBR: panels of 2^CR_PB rows (y slice in LDS), blocks of 2^CR_RB ranks, workgroup size and
+// entries per thread per sweep, default entries per work unit
+#define CR_PB 13
+#define CR_RB 19
+#define CR_NT 512
+#define CR_IPT 4
+#define CR_UNIT_DEFAULT (1 << 18)
+#define CR_SEG_LDS 1024  // segment starts of a panel staged in LDS when nseg + 1 <= this
+
 // radix sort: 8-bit digits, 1024 threads x 4 keys per tile (measured best of 256..1024 threads
 // and 2..16 keys per thread at 2^28 keys)
 #define RS_RADIX_BITS 8
@@ -87,6 +96,11 @@ struct spx_matrix_s {
     int32_t* rs_chunk_ptr = nullptr;  // nlong+1
     int32_t rs_nlong = 0, rs_nchunks = 0;
     double* rs_partials = nullptr;    // nchunks
+    // CSBR: column of each rank, ranked x copy (per-product scratch); blk_ptr / packed / nbr
+    // (panels) / nbc (rank segments per panel) and the cb_ unit tables as for CSBH
+    int32_t* cr_order = nullptr;  // nranked
+    int32_t cr_nranked = 0;
+    double* cr_xr = nullptr;      // nranked
     // CSBH partition
     int4* cb_units = nullptr;       // {block row, first entry, end entry, partial slot or -1}
     int32_t cb_nunits = 0;
@@ -272,8 +286,25 @@ hipError_t launch_gather_csr(const uint64_t* keys, const double* vals, const int
 hipError_t launch_gather_csb(const uint64_t* keys, const double* vals, const int32_t* head_pos,
                              int64_t E, int64_t nnz_out, int k, bool hilbert, uint32_t* packed_out,
                              double* val_out, int32_t* blk_end, hipStream_t s);
+hipError_t launch_gather_csbr(const uint64_t* keys, const double* vals, const int32_t* head_pos,
+                              int64_t E, int64_t nnz_out, uint32_t* packed_out, double* val_out,
+                              int32_t* blk_end, hipStream_t s);
 static inline bool spx_is_csb(spx_format f) { return f == SPX_CSB_HILBERT || f == SPX_CSB_ZMORTON; }
 static inline bool spx_is_bcoh(spx_format f) { return f == SPX_BCOHC || f == SPX_BCOHCH; }
+static inline bool spx_is_crs(spx_format f) { return f == SPX_CSR_ROWSPLIT || f == SPX_CSR_MERGE; }
+
+// ------------------------------------------------------------------ CSBR conversion
+// keys (panel << (rbits + CR_PB)) | (rank_of[col] << CR_PB) | (row mod 2^CR_PB), index check
+hipError_t launch_keys_csbr(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+                            int32_t n, const int32_t* rank_of, int rbits, uint64_t* keys,
+                            uint32_t* err, unsigned long long* masks, hipStream_t s);
+// column ranking keys (2^32 - 1 - count) << 32 | column: ascending order = decreasing count, then
+// increasing column; the payload is unused
+hipError_t launch_rank_keys(const uint32_t* counts, int32_t n, uint64_t* keys, hipStream_t s);
+// from the sorted ranking keys: rank_of[c] for every column, order[i] = column of rank i for the
+// ranked (counted) columns, *nranked = their number (left untouched when no column is counted)
+hipError_t launch_rank_scatter(const uint64_t* sorted, int32_t n, int32_t* order,
+                               int32_t* rank_of, uint32_t* nranked, hipStream_t s);
 
 // ------------------------------------------------------------------ BCOHC / BCOHCH
 #define BH_WINDOW 8192       // rows of one partition at most (its output slice lives in LDS)
@@ -384,3 +415,4 @@ hipError_t spmm_crs(const spx_matrix_s* A, const SpmmPlan& P, int32_t k, const v
                     int64_t ldx, void* y, int64_t ldy, int row_major, hipStream_t s);
 hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
 hipError_t spmv_bcoh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
+hipError_t spmv_csbr(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);

@@ -19,14 +19,14 @@ SPX_OK = 0
 STATUS = {0: "SPX_OK", -1: "SPX_ERR_INVALID_ARG", -2: "SPX_ERR_INDEX", -3: "SPX_ERR_RANGE",
           -4: "SPX_ERR_ALIAS", -5: "SPX_ERR_NOMEM", -6: "SPX_ERR_HIP", -7: "SPX_ERR_UNSUPPORTED",
           -8: "SPX_ERR_DEVICE"}
-FORMATS = {"rowsplit": 0, "merge": 1, "csbh": 2, "csb": 3, "bcohc": 4, "bcohch": 5}
+FORMATS = {"rowsplit": 0, "merge": 1, "csbh": 2, "csb": 3, "bcohc": 4, "bcohch": 5, "csbr": 6}
 FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
 LAYOUTS = {"col": 0, "row": 1}
 VALUE_TYPES = {"f64": 0, "f32": 1, "bf16": 2}
 VALUE_TORCH = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}
 ARRAYS = {"row_ptr": (0, torch.int32), "col_ind": (1, torch.int32), "values": (2, torch.float64),
           "blk_ptr": (3, torch.int32), "packed": (4, torch.int32), "parts": (5, torch.int32),
-          "blk_coord": (6, torch.int32)}
+          "blk_coord": (6, torch.int32), "col_order": (7, torch.int32)}
 
 
 class SpxError(RuntimeError):
@@ -565,7 +565,8 @@ def _layout_of(t):
 def convert(row, col, val, shape, fmt="merge", sum_duplicates=True, log2_beta=0,
             tile_items=0, hot_columns=-1, value_type="f64", stream=None):
     """Convert device triplets (int32 row, int32 col, float64 val) to a Matrix of format `fmt`
-    ('rowsplit', 'merge', 'csbh', 'csb', 'bcohc' or 'bcohch').  hot_columns: -1 automatic, 0 off, k > 0 at most k columns
+    ('rowsplit', 'merge', 'csbh', 'csb', 'bcohc', 'bcohch' or 'csbr').  hot_columns: -1
+    automatic, 0 off, k > 0 at most k columns
     in the compact x copy (CRS formats).  value_type: 'f64', or 'f32' / 'bf16' stored values
     (CRS formats; products then take float32 x and y)."""
     if fmt not in FORMATS:

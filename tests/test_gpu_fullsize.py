@@ -20,7 +20,7 @@ import synth
 from oracle import curves, measure, spmv
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
-FMTS = ["rowsplit", "merge", "csbh", "csb", "bcohc", "bcohch"]
+FMTS = ["rowsplit", "merge", "csbh", "csb", "bcohc", "bcohch", "csbr"]
 
 
 def say(*a):

@@ -13,7 +13,7 @@ import synth
 from oracle import bcoh, formats, measure, mergepath, spmv
 
 pytestmark = pytest.mark.gpu
-FMTS = ["rowsplit", "merge", "csbh", "csb", "bcohc", "bcohch"]
+FMTS = ["rowsplit", "merge", "csbh", "csb", "bcohc", "bcohch", "csbr"]
 BCOH = ("bcohc", "bcohch")
 TOL = 1e-12
 
@@ -71,6 +71,11 @@ def _check_structure(A, m, n, row, col, val):
                         A.export("blk_coord").cpu().numpy().view(np.uint32),
                         A.export("packed").cpu().numpy().view(np.uint32),
                         A.export("values").cpu().numpy(), cr, cc, cv, A.format == "bcohch")
+    elif A.format == "csbr":
+        formats.check_csbr(m, n, col, A.export("blk_ptr").cpu().numpy(),
+                           A.export("packed").cpu().numpy().view(np.uint32),
+                           A.export("values").cpu().numpy(), A.export("col_order").cpu().numpy(),
+                           cr, cc, cv)
     elif A.format in ("csbh", "csb"):
         formats.check_csb(m, n, A.log2_beta, A.export("blk_ptr").cpu().numpy(),
                           A.export("packed").cpu().numpy().view(np.uint32),
@@ -258,6 +263,38 @@ def test_csbh_block_sizes_and_split_rows(spx, log2_beta, unit, fmt):
     _check_structure(A, m, n, row, col, val)
 
 
+@pytest.mark.parametrize("unit", [0, 700, 5000, 100_000])
+@pytest.mark.parametrize("kind", ["int", "float"])
+def test_csbr_segments_and_split_panels(spx, unit, kind):
+    # more than 2^19 ranked columns (several rank segments per panel), panels split into many
+    # units with partial slices (small tile_items), a row count that is not a multiple of the
+    # panel height, long rows and a very frequent column
+    rng = np.random.default_rng(61)
+    m, n, E = 20_011, (1 << 21) + 3, 2_000_000
+    row = rng.integers(0, m, E)
+    col = rng.integers(0, n, E)
+    row[:30_000] = 8191           # a long row at a panel edge
+    col[30_000:90_000] = 12345    # one very frequent column
+    row[90_000:95_000] = m - 1
+    perm = rng.permutation(E)
+    row, col = row[perm].astype(np.int32), col[perm].astype(np.int32)
+    val = synth.values(E, seed=62, kind=kind)
+    x = synth.xvec(n, seed=63, kind=kind)
+    ref = spmv.reference(m, n, row, col, val, x)
+    say("csbr unit", unit, kind)
+    A, y = _run(spx, "csbr", m, n, row, col, val, x, tile_items=unit)
+    nranked = len(np.unique(col))
+    rbits = max(19, (nranked - 1).bit_length())
+    assert rbits >= 21                          # at least 4 rank segments per panel
+    assert A.export("blk_ptr").numel() == ((m + 8191) // 8192) * (1 << (rbits - 19)) + 1
+    if kind == "int":
+        _check_int(y, ref, "csbr int unit %d" % unit)
+    else:
+        _check_float(y, ref, "csbr float unit %d" % unit)
+    if unit in (0, 700):
+        _check_structure(A, m, n, row, col, val)
+
+
 def test_csbh_default_block_size_rule(spx, rmat14):
     import torch
     m, n, row, col, d = rmat14
@@ -410,7 +447,7 @@ def test_error_paths(spx):
     r = np.arange(big, dtype=np.int32) % 5
     c = np.arange(big, dtype=np.int32) % 7
     v = _dev(np.ones(big), torch.float64)
-    for fmt in ("rowsplit", "merge", "csbh", "csb"):
+    for fmt in ("rowsplit", "merge", "csbh", "csb", "csbr"):
         bad_r = r.copy()
         bad_r[4321] = 5
         with pytest.raises(spx.SpxError) as e:
@@ -426,6 +463,14 @@ def test_error_paths(spx):
         with pytest.raises(spx.SpxError) as e:
             spx.convert(row, col, val, ((1 << 26) + 1, 8), fmt)
         assert e.value.name == "SPX_ERR_RANGE"
+    # CSBR: more than 2^26 columns; a block size other than its fixed panel height
+    with pytest.raises(spx.SpxError) as e:
+        spx.convert(row, col, val, (8, (1 << 26) + 1), "csbr")
+    assert e.value.name == "SPX_ERR_RANGE"
+    with pytest.raises(spx.SpxError) as e:
+        spx.convert(_dev(np.array([0, 4], np.int32), torch.int32), col, val, (5, 5), "csbr",
+                    log2_beta=5)
+    assert e.value.name == "SPX_ERR_UNSUPPORTED"
     A = spx.convert(_dev(np.array([0, 4], np.int32), torch.int32), col, val, (5, 5), "rowsplit")
     buf = torch.zeros(10, dtype=torch.float64, device="cuda")
     with pytest.raises(spx.SpxError) as e:

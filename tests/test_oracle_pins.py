@@ -687,6 +687,44 @@ def test_check_csb_zmorton_hand_made():
         formats.check_csb(4, 4, 1, [0, 2, 3, 3, 4], z_packed, z_val, *canon, "zmorton")
 
 
+def test_csbr_check_hand_made():
+    # panels of 2 rows (pb = 1) and blocks of 2 ranks (rb = 1), written out by hand.
+    # raw triplets (row, col, value): (0,2,1) (0,2,2) (1,0,4) (2,2,5) (2,3,6) (1,2,7) (0,3,8)
+    # raw column counts: col 0 -> 1, col 1 -> 0, col 2 -> 4, col 3 -> 2, so the ranking is
+    # col 2, col 3, col 0 (col 1 has no triplet); 3 ranks -> rank field of 2 bits -> 2 segments.
+    raw_cols = [2, 2, 0, 2, 3, 2, 3]
+    canon = ([0, 0, 1, 1, 2, 2], [2, 3, 0, 2, 2, 3], [3.0, 8.0, 4.0, 7.0, 5.0, 6.0])
+    order = [2, 3, 0]
+    # panel 0 (rows 0-1), segment 0 (ranks 0-1): (0,2) (1,2) (0,3); segment 1: (1,0)
+    # panel 1 (row 2), segment 0: (2,2) (2,3); segment 1: empty
+    blk_ptr = [0, 3, 4, 6, 6]
+    packed = [0, 1, 2, 1, 0, 2]    # (rank mod 2) << 1 | (row mod 2)
+    vals = [3.0, 7.0, 8.0, 4.0, 5.0, 6.0]
+    assert formats.csbr_col_order(4, raw_cols).tolist() == order
+    r, c, panel, rank = formats.decode_csbr(3, blk_ptr, packed, order, pb=1, rb=1)
+    assert r.tolist() == [0, 1, 0, 1, 2, 2] and c.tolist() == [2, 2, 3, 0, 2, 3]
+    assert rank.tolist() == [0, 0, 1, 2, 0, 1]
+    ok = dict(m=3, n=4, raw_cols=raw_cols, blk_ptr=blk_ptr, packed=packed, val=vals,
+              col_order=order, canon_row=canon[0], canon_col=canon[1], canon_val=canon[2],
+              pb=1, rb=1)
+    formats.check_csbr(**ok)
+    bad = [dict(packed=[1, 0, 2, 1, 0, 2], val=[7.0, 3.0, 8.0, 4.0, 5.0, 6.0]),  # rows swapped
+           dict(col_order=[3, 2, 0]),                                         # ranking
+           dict(col_order=[2, 3, 0, 1]),                                      # untouched column
+           dict(blk_ptr=[0, 4, 4, 6, 6]),                                     # segment boundary
+           dict(blk_ptr=[0, 3, 4, 6]),                                        # segment count
+           dict(val=[3.0, 7.0, 8.0, 4.0, 5.0, np.nextafter(6.0, 9.0)])]       # one value 1 ulp off
+    for b in bad:
+        with pytest.raises(AssertionError):
+            formats.check_csbr(**dict(ok, **b))
+
+
+def test_csbr_ranking_ties_and_empty():
+    # equal counts keep increasing column order; columns without triplets are not ranked
+    assert formats.csbr_col_order(6, [5, 1, 3, 5, 1, 0]).tolist() == [1, 5, 0, 3]
+    assert formats.csbr_col_order(3, []).tolist() == []
+
+
 def test_parcrs_equals_algorithm1_bitwise():
     # the row-parallel loop sums every row in the same order as Algorithm 1
     rng = np.random.default_rng(6)
