@@ -1,17 +1,21 @@
 #!/usr/bin/env python3
 """SpMV benchmark on one MI355X: prints one JSON line.
 
-One step = one pass of the whole path over the resident triplets of the workload:
-  convert triplets -> row-split CRS, merge-path CRS and CSBH (validate, sort keys, radix sort,
-  sum repeats, offsets, work-unit tables), one y = A x in each format, and the conversion report
-  (conversion time and break-even count against row-split CRS).
-value = useful SpMV flops of the step (3 products x 2 nnz) / step time.
+One step = one product y = A x (Section 1) on the resident R-MAT scale-24 matrix, FP64 values and
+int32 indices, in the headline format (CSBR: compressed sparse blocks over frequency-ranked
+columns); the matrix and x are in HBM before the timed region.  --warmup untimed products, then
+--steps timed ones (the paper's protocol takes the minimum of 550, Section 5.2).
+value = 2 nnz / (mean time of a step), GFLOP/s.
 
-Beside the step, each format's product is also timed alone (the steady state of a resident
-matrix, 10 warm-up and --spmv-reps timed products, minimum and median as in the paper's
-protocol), and its kernels (summed) are set against the HBM roofline with the bytes model
-  B = 12 nnz + 4 (m+1) + 8 n_touched + 8 m (+ format-specific tables).
-Kernel durations come from the library's HIP-event profiler (events on the launch stream).
+roofline: the headline product's kernels (summed average durations from the library's HIP-event
+profiler on the launch stream) against the algorithmic bytes
+  B = 12 nnz + 8 n_touched + 8 m + the format's tables (block pointers, units, column order),
+and the 8 TB/s HBM peak; traffic = bytes measured by rocprofv3 counters for the same kernels.
+
+Beside the step: every format's conversion (minimum and median of --convert-reps) with its
+algorithmic fraction, its steady-state product (--spmv-reps) with its roofline, break-even
+counts against row-split CRS, the relabelled matrix, reduced precision, several right-hand
+sides, batches, the serving loop, and the oracle on the host (cpu_baseline).
 """
 import argparse
 import hashlib
@@ -27,20 +31,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 METRIC = "SpMV GFLOP/s + % HBM roofline (R-MAT s24); served p99 latency at req/s"
-FMTS = ("rowsplit", "merge", "csbh")
+FMTS = ("rowsplit", "merge", "csbh", "csb", "bcohc", "bcohch", "csbr")
+HEADLINE = "csbr"
 WORKLOADS = {
     "rmat24": "R-MAT scale 24 (m = n = 16,777,216), edge factor 16 (268,435,456 raw entries), "
               "(a,b,c,d) = (0.57,0.19,0.19,0.05), repeats summed, FP64 values and x U(-1,1), "
               "int32 indices, seed 0",
     "chunglu": "Chung-Lu power law, gamma 2.1, n = 10,000,000, 200,000,000 raw entries, repeats "
                "summed, FP64 values and x U(-1,1), int32 indices, seed 0",
+    "rmat24p": "R-MAT scale 24 as rmat24 under a random relabelling of rows and of columns "
+               "(seeded permutations, streams 3 with seeds 1 and 2)",
     "rmat14": "R-MAT scale 14 (m = n = 16,384), edge factor 16, (a,b,c,d) = "
               "(0.57,0.19,0.19,0.05), FP64 values and x U(-1,1), seed 0",
 }
 
 
 KERNEL_SOURCES = ("k_spmv.hip", "k_spmv_crs.hip", "k_spmm.hip", "k_convert.hip", "k_hot.hip",
-                  "k_partition.hip")
+                  "k_partition.hip", "k_bcoh.hip", "spx_internal.h")
 
 
 def log(*a):
@@ -72,6 +79,21 @@ def spmv_bytes(fmt, m, nnz, n_touched, A, val_bytes=8, vec_bytes=8):
     if fmt in ("bcohc", "bcohch"):
         nb = A.export("blk_coord").numel()
         b += 8 * (nb + 1) + 8 * (A.parts + 1)  # block pointers and coordinates, partition table
+    if fmt == "csbr":
+        # block pointers, unit table, column of each rank (the ranked copy of x is not counted:
+        # x is counted once, as read)
+        b += 4 * A.export("blk_ptr").numel() + 16 * A.parts + 4 * A.export("col_order").numel()
+    return b
+
+
+def convert_bytes(E, nnz, m, fmt, A):
+    """Algorithmic bytes of a conversion: the triplets read once (16 B each), the stored entries
+    written once (12 B each) and the offsets / block pointers written."""
+    b = 16 * E + 12 * nnz
+    if fmt in ("rowsplit", "merge"):
+        b += 4 * (m + 1)
+    else:
+        b += 4 * A.export("blk_ptr").numel()
     return b
 
 
@@ -127,6 +149,43 @@ def copy_probe(torch, nbytes=2 << 30, reps=20):
     return 2 * nbytes / (best * 1e-3) / 1e9
 
 
+def host_cpu():
+    """Host CPU as lscpu reports it: model, sockets, cores per socket, threads per core."""
+    import subprocess
+    info = {"logical_cpus": os.cpu_count()}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+    except Exception:
+        return info
+    keys = {"Model name": "model", "Socket(s)": "sockets", "Core(s) per socket": "cores_per_socket",
+            "Thread(s) per core": "threads_per_core", "CPU(s)": "logical_cpus",
+            "NUMA node(s)": "numa_nodes"}
+    for line in txt.splitlines():
+        k, _, v = line.partition(":")
+        k, v = k.strip(), v.strip()
+        if k in keys:
+            info[keys[k]] = int(v) if v.isdigit() else v
+    if isinstance(info.get("sockets"), int) and isinstance(info.get("cores_per_socket"), int):
+        info["physical_cores"] = info["sockets"] * info["cores_per_socket"]
+    return info
+
+
+def precision_errors(w, samples):
+    """Row-scaled error |y - y_ref| / sum_k |a_ik x_k| of reduced-precision results on sampled rows
+    against the FP64 oracle (its accurate Algorithm 1 restricted to those rows)."""
+    import numpy as np
+
+    from oracle import spmv as ref
+    rows = samples["rows"]
+    _, _, yr, sc = ref.rows_reference(w["m"], w["n"], w["row"], w["col"], w["val"], w["x"], rows)
+    out = {}
+    nz = sc > 0
+    for name, y in samples["results"].items():
+        e = np.abs(y - yr)[nz] / sc[nz]
+        out[name] = {"max": float(e.max()), "median": float(np.median(e)), "rows": int(nz.sum())}
+    return out
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The oracle on the GPU machine's host, on a bounded sample of the same matrix (the rows whose
     index hashes into 1/8 of the range): Algorithm 1 as printed (sequential, one core) -- the
@@ -162,7 +221,7 @@ def cpu_baseline(w, budget_s=12.0):
     ptimes = timed(lambda: ref.parcrs(rp, c, v, w["x"]), budget_s / 3, 200)
     best, pbest = min(times), min(ptimes)
     return {"value": round(2 * nnz / best / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "host": host_cpu(),
             "sample": "oracle Algorithm 1 (sequential, plain FP64) on the %d rows (1/8 of the "
                       "rows, chosen by a multiplicative hash of the row index) holding %d of "
                       "the workload's stored entries; minimum of %d runs, %.1f s of timed CPU work"
@@ -205,33 +264,19 @@ def product_kernels(ks):
             sum(ks[k]["min_ms"] for k in names))
 
 
-def precision_leg(spx, torch, args, row_d, col_d, val_d, x_d, m, n, n_touched, copy_gbs):
-    """FP32 and bfloat16 stored values (FP32 x, y) in the CRS formats: steady-state product, its
-    roofline, and the error against this library's FP64 product of the same matrix, per row
-    |y_lp - y_64| / (|A| |x|), with |A| |x| an FP64 product of the absolute stored values."""
-    A64 = spx.convert(row_d, col_d, val_d, (m, n), "rowsplit")
-    y64 = torch.empty(m, dtype=torch.float64, device="cuda")
-    A64.spmv(x_d, out=y64)
-    rp = A64.export("row_ptr").long()
-    ci = A64.export("col_ind")
-    va = A64.export("values")
-    A64.close()
-    rows = torch.repeat_interleave(torch.arange(m, device="cuda", dtype=torch.int32),
-                                   rp[1:] - rp[:-1])
-    Aabs = spx.convert(rows, ci, va.abs(), (m, n), "rowsplit")
-    s = torch.empty(m, dtype=torch.float64, device="cuda")
-    Aabs.spmv(x_d.abs(), out=s)
-    Aabs.close()
-    del rows, ci, va, rp
-    nzr = s > 0
+def precision_leg(spx, torch, args, row_d, col_d, val_d, x_d, m, n, n_touched, copy_gbs, rows):
+    """FP32 and bfloat16 stored values (FP32 x, y) in the CRS formats: steady-state product and
+    its roofline; the results on the sampled rows are kept for the error against the FP64 oracle
+    (computed in the host leg, where the oracle runs)."""
     x32 = x_d.float()
     y32 = torch.empty(m, dtype=torch.float32, device="cuda")
-    out = {}
+    rows_d = torch.from_numpy(rows).cuda()
+    out, results = {}, {}
     for vt, vb in (("f32", 4), ("bf16", 2)):
         for f in ("rowsplit", "merge"):
             A = spx.convert(row_d, col_d, val_d, (m, n), f, value_type=vt)
             ms, ks = time_products(spx, torch, A, x32, y32, args.spmv_reps)
-            err = ((y32.double() - y64).abs()[nzr] / s[nzr])
+            results["%s_%s" % (f, vt)] = y32[rows_d].double().cpu().numpy()
             kname, kavg, _ = product_kernels(ks)
             B = spmv_bytes(f, m, A.nnz, n_touched, A, val_bytes=vb, vec_bytes=4)
             ach = B / (kavg * 1e-3) / 1e9
@@ -244,14 +289,14 @@ def precision_leg(spx, torch, args, row_d, col_d, val_d, x_d, m, n, n_touched, c
                              "frac": round(ach / HBM_PEAK_GBS, 4),
                              "frac_of_copy": round(ach / copy_gbs, 4), "bytes_per_launch": int(B),
                              "avg_ms": round(kavg, 4)},
-                "scaled_error_vs_fp64": {"max": float(err.max()), "median": float(err.median())},
+                "scaled_error_vs_fp64_oracle": None,
                 "convert_ms": round(A.convert_ms, 3),
             }
-            log("spmv %-8s %-4s median %.4f ms  %.1f GFLOP/s  %.1f%% of HBM peak  err max %.2e"
+            log("spmv %-8s %-4s median %.4f ms  %.1f GFLOP/s  %.1f%% of HBM peak"
                 % (f, vt, statistics.median(ms), out["%s_%s" % (f, vt)]["gflops_median_time"],
-                   100 * ach / HBM_PEAK_GBS, float(err.max())))
+                   100 * ach / HBM_PEAK_GBS))
             A.close()
-    return out
+    return out, {"rows": rows, "results": results}
 
 
 def spmm_leg(spx, torch, np, synth, args):
@@ -527,9 +572,13 @@ def _short(name):
 
 
 def summarize_rocprof(prof_dir, label):
-    """Markdown summary of rocprofv3 CSV output (kernel stats + FETCH/WRITE per dispatch) and a
-    JSON traffic table for bench.py.  Counter calibration: the 2 GiB device copy of the copy
-    probe reads FETCH_SIZE / WRITE_SIZE for 2 GiB read and 2 GiB written."""
+    """Markdown summary of rocprofv3 output in prof_dir and the traffic table for bench.py.
+
+    prof_dir/trace: --kernel-trace --stats run; prof_dir/fetch: --pmc TCC_EA0_RDREQ_32B
+    TCC_EA0_RDREQ_64B TCC_EA0_RDREQ_128B TCC_EA0_RDREQ; prof_dir/write: --pmc TCC_EA0_WRREQ
+    TCC_EA0_WRREQ_64B.  Bytes read through the L2 = 32 / 64 / 128 x the requests of each size;
+    bytes written = 32 x (WRREQ - WRREQ_64B) + 64 x WRREQ_64B.  Both are calibrated on the
+    2 GiB device copy of the copy probe (2 GiB read and 2 GiB written)."""
     import csv
     import collections
     lines = []
@@ -537,59 +586,100 @@ def summarize_rocprof(prof_dir, label):
     rows = list(csv.DictReader(open(stats)))
     lines.append("| kernel | calls | avg ms | min ms | max ms | share |")
     lines.append("|---|---|---|---|---|---|")
-    for r in rows[:25]:
+    for r in rows[:30]:
         lines.append("| `%s` | %s | %.4f | %.4f | %.4f | %.1f%% |" % (
             r["Name"].split("(")[0].replace("void ", "")[:70], r["Calls"],
             float(r["AverageNs"]) / 1e6, float(r["MinNs"]) / 1e6, float(r["MaxNs"]) / 1e6,
             float(r["Percentage"])))
-    cnt = {}
+    per = {}
     for c in ("fetch", "write"):
-        agg = collections.defaultdict(list)
+        disp = collections.defaultdict(lambda: collections.defaultdict(float))
+        names = {}
         for r in csv.DictReader(open(os.path.join(prof_dir, c, label + "_counter_collection.csv"))):
-            agg[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
-        cnt[c] = agg
-    copy_key = [k for k in cnt["fetch"] if k[0].startswith("__amd_rocclr_copyBuffer")]
-    probe = max(copy_key, key=lambda k: max(cnt["fetch"][k]))
-    gib2 = 2 * 1024 * 1024  # KiB in 2 GiB
-    f_fac = gib2 / max(cnt["fetch"][probe])
-    w_fac = gib2 / max(cnt["write"][probe])
+            d = int(r["Dispatch_Id"])
+            disp[d][r["Counter_Name"]] += float(r["Counter_Value"])
+            names[d] = r["Kernel_Name"]
+        per[c] = {}
+        for d, v in disp.items():
+            if c == "fetch":
+                b = 32 * v["TCC_EA0_RDREQ_32B"] + 64 * v["TCC_EA0_RDREQ_64B"] + \
+                    128 * v["TCC_EA0_RDREQ_128B"]
+            else:
+                b = 32 * (v["TCC_EA0_WRREQ"] - v["TCC_EA0_WRREQ_64B"]) + 64 * v["TCC_EA0_WRREQ_64B"]
+            per[c][d] = (names[d], b)
+    gib2 = float(2 << 30)
+    fac = {}
+    for c in ("fetch", "write"):
+        copies = [b for (nm, b) in per[c].values() if nm.startswith("__amd_rocclr_copyBuffer")]
+        fac[c] = gib2 / max(copies) if copies else 1.0
     lines.append("")
-    lines.append("Counter calibration (2 GiB device copy of the copy probe): FETCH_SIZE x %.3f, "
-                 "WRITE_SIZE x %.3f." % (f_fac, w_fac))
+    lines.append("Calibration on the 2 GiB device copy of the copy probe: bytes read x %.4f, "
+                 "bytes written x %.4f." % (fac["fetch"], fac["write"]))
     lines.append("")
-    lines.append("| kernel | dispatches | FETCH KiB/dispatch | WRITE KiB/dispatch | "
-                 "HBM GB/dispatch (scaled) |")
+    lines.append("| kernel | dispatches | read GB/dispatch | written GB/dispatch | total GB/dispatch |")
     lines.append("|---|---|---|---|---|")
-    per = collections.defaultdict(lambda: [[], []])
-    for (k, _), v in cnt["fetch"].items():
-        per[_short(k)][0] += v
-    for (k, _), v in cnt["write"].items():
-        per[_short(k)][1] += v
+    agg = collections.defaultdict(lambda: [[], []])
+    for i, c in enumerate(("fetch", "write")):
+        for nm, b in per[c].values():
+            agg[_short(nm)][i].append(b * fac[c])
     traffic = {}
-    for k, (fv, wv) in sorted(per.items(), key=lambda kv: -sum(kv[1][0])):
+    for k, (fv, wv) in sorted(agg.items(), key=lambda kv: -sum(kv[1][0]) / max(len(kv[1][0]), 1)):
         fa = sum(fv) / max(len(fv), 1)
         wa = sum(wv) / max(len(wv), 1)
-        gb = (fa * f_fac + wa * w_fac) * 1024 / 1e9
-        traffic[k] = (fa * f_fac + wa * w_fac) * 1024
-        if gb > 0.01:
-            lines.append("| `%s` | %d | %.0f | %.0f | %.3f |" % (k[:60], len(fv), fa, wa, gb))
-    src = None
-    bj = os.path.join(prof_dir, "bench_trace.json")
-    if os.path.exists(bj):
-        src = json.loads(open(bj).read().strip().splitlines()[-1]).get("kernel_src")
-    return "\n".join(lines), {"kernel_src": src, "traffic_bytes_per_launch": traffic}
+        traffic[k] = fa + wa
+        if fa + wa > 1e7:
+            lines.append("| `%s` | %d | %.3f | %.3f | %.3f |" % (k[:60], len(fv), fa / 1e9, wa / 1e9,
+                                                               (fa + wa) / 1e9))
+    return "\n".join(lines), {"kernel_src": src_hash(*KERNEL_SOURCES),
+                              "traffic_bytes_per_launch": traffic}
 
 
-def load_traffic(kernel):
-    """Measured HBM bytes per launch of `kernel` from profiles/, if taken on the current source."""
+ALIASES = {"hot_gather": "k_hot_gather_t"}
+
+
+def load_traffic(kernels):
+    """Measured bytes per launch (reads + writes through the L2, from rocprofv3 counters) summed
+    over `kernels`, if the table in profiles/ was taken on the current kernel sources."""
     p = os.path.join(ROOT, "profiles", "traffic_rmat24.json")
     if not os.path.exists(p):
         return None
     t = json.load(open(p))
     if t.get("kernel_src") != src_hash(*KERNEL_SOURCES):
         return None
-    v = t["traffic_bytes_per_launch"].get(kernel) or t["traffic_bytes_per_launch"].get("k_" + kernel)
-    return None if v is None else int(v)
+    tb = t["traffic_bytes_per_launch"]
+    tot = 0
+    for k in kernels:
+        k = ALIASES.get(k, k)
+        v = tb.get(k) if k in tb else tb.get("k_" + k)
+        if v is None:
+            return None
+        tot += v
+    return int(tot)
+
+
+def timed_products(spx, torch, A, x, y, reps):
+    """Steady-state product of a resident matrix: times, per-kernel statistics and the roofline
+    of all the product's kernels against the bytes model."""
+    ms, ks = time_products(spx, torch, A, x, y, reps)
+    kname, kavg, kmin = product_kernels(ks)
+    return ms, ks, kname, kavg, kmin
+
+
+def product_record(f, A, ms, ks, kname, kavg, kmin, B, copy_gbs):
+    ach = B / (kavg * 1e-3) / 1e9
+    return {
+        "ms_min": round(min(ms), 4), "ms_median": round(statistics.median(ms), 4),
+        "runs": len(ms),
+        "gflops_min_time": round(2 * A.nnz / (min(ms) * 1e-3) / 1e9, 1),
+        "gflops_median_time": round(2 * A.nnz / (statistics.median(ms) * 1e-3) / 1e9, 1),
+        "kernels": {k: round(v["avg_ms"], 4) for k, v in ks.items()},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "frac_of_copy": round(ach / copy_gbs, 4), "bytes_per_launch": int(B),
+                     "avg_ms": round(kavg, 4), "min_ms": round(kmin, 4),
+                     "traffic": load_traffic(kname.split("+"))},
+        "parts": A.parts, "log2_beta": A.log2_beta,
+    }
 
 
 def main():
@@ -598,14 +688,16 @@ def main():
                     help="print a markdown summary of rocprofv3 CSV output in DIR and write "
                          "profiles/traffic_rmat24.json, then exit")
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=550, help="timed products of the step")
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
-    ap.add_argument("--spmv-reps", type=int, default=100)
+    ap.add_argument("--headline", default=HEADLINE, help="format of the timed step")
+    ap.add_argument("--spmv-reps", type=int, default=550)
+    ap.add_argument("--convert-reps", type=int, default=5)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--formats", default=",".join(FMTS))
-    ap.add_argument("--extra-formats", default="csb,bcohc,bcohch",
-                    help="formats timed outside the step: conversion and steady-state product")
+    ap.add_argument("--relabelled", type=int, default=1,
+                    help="also time the headline and merge-path products on the relabelled matrix")
     ap.add_argument("--precision", type=int, default=1,
                     help="also time the FP32 / bfloat16 forms of the CRS formats")
     ap.add_argument("--spmm", type=int, default=1,
@@ -632,6 +724,8 @@ def main():
               "sharding is described in DESIGN.md, not run)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     fmts = [f for f in args.formats.split(",") if f]
+    if args.headline not in fmts:
+        fmts.append(args.headline)
 
     import numpy as np
     import torch
@@ -650,161 +744,151 @@ def main():
     m, n, E = w["m"], w["n"], len(w["row"])
     log("generated %s: m=%d n=%d raw=%d in %.1f s" % (args.workload, m, n, E,
                                                        time.perf_counter() - t0))
+    counts = np.bincount(w["row"], minlength=m)
     n_touched = int(np.count_nonzero(np.bincount(w["col"], minlength=n)))
+    rng = np.random.default_rng(1)
+    sample_rows = np.unique(np.concatenate([rng.integers(0, m, 2000), np.argsort(counts)[-12:],
+                                            [0, m - 1]])).astype(np.int64)
     dev = lambda a, t: torch.from_numpy(a).to("cuda", dtype=t)
     row_d, col_d = dev(w["row"], torch.int32), dev(w["col"], torch.int32)
     val_d, x_d = dev(w["val"], torch.float64), dev(w["x"], torch.float64)
-    ybuf = {f: torch.empty(m, dtype=torch.float64, device="cuda") for f in fmts}
+    y_d = torch.empty(m, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     copy_gbs = copy_probe(torch)
     log("copy probe %.0f GB/s" % copy_gbs)
 
-    conv_ms = {f: [] for f in fmts}
-    spmv_ms = {f: [] for f in fmts}
-    info = {}
-    sort_split = {"keys": 0, "levels": 0}
-
-    def step(record):
-        for f in fmts:
-            A = spx.convert(row_d, col_d, val_d, (m, n), f)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            A.spmv(x_d, out=ybuf[f])
-            e1.record()
-            if record:
-                e1.synchronize()
-                conv_ms[f].append(A.convert_ms)
-                spmv_ms[f].append(e0.elapsed_time(e1))
-                info[f] = dict(nnz=A.nnz, parts=A.parts, log2_beta=A.log2_beta, bytes=A.bytes,
-                               sort_levels=A.sort_levels, sort_split_keys=A.sort_split_keys,
-                               sort_first_fused=A.sort_first_fused)
-                # segmented levels only (a fused first level runs under its own kernel names)
-                sort_split["keys"] += A.sort_split_keys - (E if A.sort_first_fused else 0)
-                sort_split["levels"] += A.sort_levels - (1 if A.sort_first_fused else 0)
-            A.close()
-
-    for i in range(args.warmup):
-        step(False)
-        log("warmup step %d done" % (i + 1))
-    torch.cuda.synchronize()
-    spx.profile_enable(True)
+    # ---------------------------------------------------------------- the step
+    A = spx.convert(row_d, col_d, val_d, (m, n), args.headline)
+    nnz = A.nnz
+    for _ in range(args.warmup):
+        A.spmv(x_d, out=y_d)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(True)
-        log("step %d done" % (i + 1))
+    for _ in range(args.steps):
+        A.spmv(x_d, out=y_d)
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t0
-    kstats = spx.profile_collect()
-    spx.profile_enable(False)
-    nnz = info[fmts[0]]["nnz"]
     ms_per_step = t_steps / args.steps * 1e3
-    value = len(fmts) * 2.0 * nnz / (ms_per_step * 1e-3) / 1e9
+    value = 2.0 * nnz / (ms_per_step * 1e-3) / 1e9
+    log("step: %d products (%s) in %.3f s, %.4f ms per product, %.1f GFLOP/s"
+        % (args.steps, args.headline, t_steps, ms_per_step, value))
+    ms, ks, kname, kavg, kmin = timed_products(spx, torch, A, x_d, y_d, args.spmv_reps)
+    B = spmv_bytes(args.headline, m, nnz, n_touched, A)
+    head = product_record(args.headline, A, ms, ks, kname, kavg, kmin, B, copy_gbs)
+    dom = max(ks.items(), key=lambda kv: kv[1]["avg_ms"])
+    roofline = dict(head["roofline"])
+    roofline.update({"launches_per_step": len(ks), "dominant_kernel": dom[0],
+                     "dominant_share": round(dom[1]["avg_ms"] / kavg, 3),
+                     "bytes_model": "12 nnz + 8 n_touched + 8 m + format tables"})
+    A.close()
 
-    # dominant kernel of the step
-    dom = max(kstats.items(), key=lambda kv: kv[1]["total_ms"])
-    dom_bytes = kernel_bytes(dom[0], E, nnz, m, sort_split["keys"], sort_split["levels"])
-    roofline = None
-    if dom_bytes is not None:
-        ach = dom_bytes / (dom[1]["avg_ms"] * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom[0]),
-                    "kernel": dom[0], "avg_ms": round(dom[1]["avg_ms"], 4),
-                    "launches": dom[1]["launches"], "bytes_per_launch": int(dom_bytes),
-                    "share_of_step": round(dom[1]["total_ms"] / (t_steps * 1e3), 3)}
-
-    # steady-state product of a resident matrix, per format (the extra formats also get their
-    # conversion timed here, best of two)
-    extra = [f for f in args.extra_formats.split(",") if f and f not in fmts]
+    # ---------------------------------------------------------------- every format
+    conv_ms = {}
     spmv = {}
-    for f in fmts + extra:
-        if f in extra:
-            ybuf[f] = torch.empty(m, dtype=torch.float64, device="cuda")
-            conv_ms[f] = []
-            for _ in range(2):
-                A = spx.convert(row_d, col_d, val_d, (m, n), f)
-                conv_ms[f].append(A.convert_ms)
-                if len(conv_ms[f]) < 2:
-                    A.close()
-        else:
+    conv_rec = {}
+    for f in fmts:
+        conv_ms[f] = []
+        A = None
+        for r in range(max(1, args.convert_reps)):
+            if A is not None:
+                A.close()
             A = spx.convert(row_d, col_d, val_d, (m, n), f)
-        ms, ks = time_products(spx, torch, A, x_d, ybuf[f], args.spmv_reps)
-        kname, kavg, kmin = product_kernels(ks)
-        B = spmv_bytes(f, m, A.nnz, n_touched, A)
-        ach = B / (kavg * 1e-3) / 1e9
-        spmv[f] = {
-            "ms_min": round(min(ms), 4), "ms_median": round(statistics.median(ms), 4),
-            "gflops_min_time": round(2 * A.nnz / (min(ms) * 1e-3) / 1e9, 1),
-            "gflops_median_time": round(2 * A.nnz / (statistics.median(ms) * 1e-3) / 1e9, 1),
-            "kernels": {k: round(v["avg_ms"], 4) for k, v in ks.items()},
-            "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1),
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                         "frac_of_copy": round(ach / copy_gbs, 4), "bytes_per_launch": int(B),
-                         "avg_ms": round(kavg, 4), "min_ms": round(kmin, 4)},
-            "parts": A.parts, "log2_beta": A.log2_beta,
-        }
-        log("spmv %-8s median %.4f ms  %.1f GFLOP/s  kernel %.4f ms  %.1f%% of HBM peak"
-            % (f, statistics.median(ms), spmv[f]["gflops_median_time"], kavg, 100 * ach / HBM_PEAK_GBS))
+            conv_ms[f].append(A.convert_ms)
+        Bc = convert_bytes(E, A.nnz, m, f, A)
+        sort_b = 32 * (A.sort_split_keys + E)
+        tmin = min(conv_ms[f])
+        conv_rec[f] = {"ms_min": round(tmin, 3), "ms_median": round(statistics.median(conv_ms[f]), 3),
+                       "runs": len(conv_ms[f]),
+                       "algorithmic_bytes": int(Bc),
+                       "algorithmic_frac": round(Bc / (tmin * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "sort_pass_bytes_model": int(sort_b),
+                       "sort_pass_frac": round(sort_b / (tmin * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "sort_levels": A.sort_levels, "sort_split_keys": A.sort_split_keys}
+        ms, ks, kname, kavg, kmin = timed_products(spx, torch, A, x_d, y_d, args.spmv_reps)
+        spmv[f] = product_record(f, A, ms, ks, kname, kavg, kmin,
+                                 spmv_bytes(f, m, A.nnz, n_touched, A), copy_gbs)
+        log("%-8s convert %.2f ms (%.1f%% of HBM peak on its algorithmic bytes); spmv median "
+            "%.4f ms  %.1f GFLOP/s  %.1f%% of HBM peak"
+            % (f, tmin, 100 * conv_rec[f]["algorithmic_frac"], spmv[f]["ms_median"],
+               spmv[f]["gflops_median_time"], 100 * spmv[f]["roofline"]["frac"]))
         A.close()
-
-    prec = precision_leg(spx, torch, args, row_d, col_d, val_d, x_d, m, n, n_touched, copy_gbs) \
-        if args.precision else None
-
-    mm = None
-    if args.spmm:
-        del ybuf
-        mm = spmm_leg(spx, torch, np, synth, args)
-
-    bt = None
-    if args.batch:
-        bt = batch_leg(spx, torch, np, synth, args)
-
-    served = None
-    if args.serve:
-        served = serving_leg(spx, torch, np, synth, args)
-
-    conv = {f: {"ms_min": round(min(conv_ms[f]), 3),
-                "ms_median": round(statistics.median(conv_ms[f]), 3)} for f in fmts + extra}
     be = {}
     if "rowsplit" in fmts:
-        ref_conv = conv["rowsplit"]["ms_min"]
+        ref_conv = conv_rec["rowsplit"]["ms_min"]
         ref_spmv = spmv["rowsplit"]["ms_min"]
-        for f in fmts + extra:
-            conv[f]["in_rowsplit_products"] = round(conv[f]["ms_min"] / ref_spmv, 1)
+        for f in fmts:
+            conv_rec[f]["in_rowsplit_products"] = round(conv_rec[f]["ms_min"] / ref_spmv, 1)
             if f != "rowsplit":
-                N = spx.break_even(conv[f]["ms_min"], ref_conv, ref_spmv, spmv[f]["ms_min"])
+                N = spx.break_even(conv_rec[f]["ms_min"], ref_conv, ref_spmv, spmv[f]["ms_min"])
                 be[f] = None if math.isinf(N) else round(N, 1)
 
-    best = max(fmts + extra, key=lambda f: spmv[f]["gflops_median_time"])
+    prec, prec_samples = (None, None)
+    if args.precision:
+        prec, prec_samples = precision_leg(spx, torch, args, row_d, col_d, val_d, x_d, m, n,
+                                           n_touched, copy_gbs, sample_rows)
+    del row_d, col_d, val_d, x_d, y_d
+    torch.cuda.empty_cache()
+
+    # ---------------------------------------------------------------- relabelled matrix
+    relab = None
+    if args.relabelled and args.workload == "rmat24":
+        t0 = time.perf_counter()
+        wp = synth.workload("rmat24p", seed=0)
+        log("generated rmat24p in %.1f s" % (time.perf_counter() - t0))
+        np_touched = int(np.count_nonzero(np.bincount(wp["col"], minlength=n)))
+        rd, cd = dev(wp["row"], torch.int32), dev(wp["col"], torch.int32)
+        vd, xd = dev(wp["val"], torch.float64), dev(wp["x"], torch.float64)
+        del wp
+        yd = torch.empty(m, dtype=torch.float64, device="cuda")
+        relab = {"workload": WORKLOADS["rmat24p"], "formats": {}}
+        for f in sorted({args.headline, "merge"}):
+            A = spx.convert(rd, cd, vd, (m, n), f)
+            ms, ks, kname, kavg, kmin = timed_products(spx, torch, A, xd, yd, args.spmv_reps)
+            rec = product_record(f, A, ms, ks, kname, kavg, kmin,
+                                 spmv_bytes(f, m, A.nnz, np_touched, A), copy_gbs)
+            rec["convert_ms"] = round(A.convert_ms, 3)
+            relab["formats"][f] = rec
+            log("relabelled %-8s spmv median %.4f ms  %.1f GFLOP/s  %.1f%% of HBM peak"
+                % (f, rec["ms_median"], rec["gflops_median_time"], 100 * rec["roofline"]["frac"]))
+            A.close()
+        del rd, cd, vd, xd, yd
+        torch.cuda.empty_cache()
+
+    mm = spmm_leg(spx, torch, np, synth, args) if args.spmm else None
+    bt = batch_leg(spx, torch, np, synth, args) if args.batch else None
+    served = serving_leg(spx, torch, np, synth, args) if args.serve else None
+
+    best = max(fmts, key=lambda f: spmv[f]["gflops_median_time"])
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GFLOP/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "m": m, "n": n, "raw_entries": E,
-                   "nnz": nnz, "n_touched_columns": n_touched, "formats": fmts,
-                   "extra_formats": extra,
-                   "step": "convert triplets to each format, one y = A x per format, "
-                           "conversion report"},
+                   "nnz": nnz, "n_touched_columns": n_touched, "format": args.headline,
+                   "step": "one y = A x on the resident matrix (matrix, x and y in HBM)"},
         "roofline": roofline,
-        "spmv_steady": {"best_format": best,
-                        "gflops": spmv[best]["gflops_median_time"],
+        "spmv_steady": {"best_format": best, "gflops": spmv[best]["gflops_median_time"],
                         "hbm_frac": spmv[best]["roofline"]["frac"]},
-        "spmv": spmv, "convert": conv, "break_even_vs_rowsplit": be,
+        "spmv": spmv, "convert": conv_rec, "break_even_vs_rowsplit": be,
+        "relabelled": relab,
         "reduced_precision": prec,
         "spmm": mm,
         "batch": bt,
         "serving": served,
         "copy_probe_gbs": round(copy_gbs, 1),
-        "step_kernels_avg_ms": {k: round(v["avg_ms"], 4) for k, v in kstats.items()},
         "kernel_src": src_hash(*KERNEL_SOURCES),
     }
     if args.cpu_baseline:
-        del row_d, col_d, val_d
         torch.cuda.empty_cache()
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(w)
+        if prec_samples is not None:
+            errs = precision_errors(w, prec_samples)
+            for k, e in errs.items():
+                prec[k]["scaled_error_vs_fp64_oracle"] = e
+                log("%s: error vs FP64 oracle on %d sampled rows: max %.3g median %.3g"
+                    % (k, e["rows"], e["max"], e["median"]))
     print(json.dumps(out), flush=True)
 
 

@@ -65,10 +65,10 @@ typedef int32_t spx_format;
  * keeps its slice of y on chip and reads only part of x -- laid out for a GPU):
  *   - columns are ranked by decreasing raw triplet count (ties: increasing column index); only
  *     columns with at least one triplet are ranked, and rank i holds column col_order[i];
- *   - rows form block rows (panels) of 2^13 rows, whose y slice lives in LDS during a product;
- *   - a block is (panel, 2^19 consecutive ranks); blocks are stored panel by panel in rank order;
+ *   - rows form block rows (panels) of 2^14 rows, whose y slice lives in LDS during a product;
+ *   - a block is (panel, 2^18 consecutive ranks); blocks are stored panel by panel in rank order;
  *   - inside a block, entries are stored column-major: by rank, then by row; each entry packs
- *     (rank mod 2^19) << 13 | (row mod 2^13) into 32 bits.
+ *     (rank mod 2^18) << 14 | (row mod 2^14) into 32 bits.
  * A product first gathers x into rank order (x_r[i] = x[col_order[i]]); a wave then reads
  * consecutive entries whose ranks ascend, so lanes that share a column, or neighbouring ranks,
  * share cache lines of x_r, and the most frequent columns occupy the first lines.
@@ -146,7 +146,7 @@ typedef int32_t spx_array;
                              * BCOHC/BCOHCH: int32[blocks+1], first entry of each stored block */
 #define SPX_ARRAY_PACKED 4  /* CSB/CSBH: uint32[nnz], (local_row << 16) | local_col, in the
                              * block's Hilbert (CSBH) or Z-Morton (CSB) order; CSBR:
-                             * (rank mod 2^19) << 13 | (row mod 2^13), column-major in a block */
+                             * (rank mod 2^18) << 14 | (row mod 2^14), column-major in a block */
 #define SPX_ARRAY_PARTS 5   /* format's work-unit table, int32 (layout is internal; BCOHC /
                              * BCOHCH: P+1 partition first rows, then P+1 first blocks)     */
 #define SPX_ARRAY_BLK_COORD 6 /* BCOHC/BCOHCH: uint32[blocks], (block_row << 16) | block_col */

@@ -99,8 +99,8 @@ def check_csb(m, n, log2_beta, blk_ptr, packed, val, canon_row, canon_col, canon
 #     then row, and each packs (rank mod 2^rb) << pb | (row mod 2^pb).
 # The product is the same y = A x; only the summation order differs.
 
-CSBR_PB = 13
-CSBR_RB = 19
+CSBR_PB = 14
+CSBR_RB = 18
 
 
 def csbr_col_order(n, raw_cols):

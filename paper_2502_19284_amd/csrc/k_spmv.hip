@@ -87,10 +87,9 @@ __global__ __launch_bounds__(CB_NT) void k_spmv_csbh(const int32_t* __restrict__
 // Split block row S.x: y = sum of its S.z partial slices (slots S.y ..), added in slot order.
 // Workgroup = (split row, chunk of 256 rows); each thread keeps 8 slot loads in flight.
 #define CB_RED_NT 256
-__global__ __launch_bounds__(CB_RED_NT) void k_spmv_csbh_reduce(const int4* __restrict__ split,
-                                                               const double* __restrict__ partials,
-                                                               double* __restrict__ y, int k,
-                                                               int32_t m) {
+__device__ __forceinline__ void csb_reduce_body(const int4* __restrict__ split,
+                                                const double* __restrict__ partials,
+                                                double* __restrict__ y, int k, int32_t m) {
     const int beta = 1 << k;
     const int chunks = (beta + CB_RED_NT - 1) / CB_RED_NT;
     const int4 S = split[blockIdx.x / chunks];
@@ -110,6 +109,21 @@ __global__ __launch_bounds__(CB_RED_NT) void k_spmv_csbh_reduce(const int4* __re
     }
     for (; q < S.z; ++q) acc = acc + p[(int64_t)q * beta];
     y[row0 + i] = acc;
+}
+
+__global__ __launch_bounds__(CB_RED_NT) void k_spmv_csbh_reduce(const int4* __restrict__ split,
+                                                               const double* __restrict__ partials,
+                                                               double* __restrict__ y, int k,
+                                                               int32_t m) {
+    csb_reduce_body(split, partials, y, k, m);
+}
+
+// the same reduction for CSBR panels (a kernel of its own, so profiles tell the formats apart)
+__global__ __launch_bounds__(CB_RED_NT) void k_spmv_csbr_reduce(const int4* __restrict__ split,
+                                                               const double* __restrict__ partials,
+                                                               double* __restrict__ y, int k,
+                                                               int32_t m) {
+    csb_reduce_body(split, partials, y, k, m);
 }
 
 hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
@@ -158,8 +172,9 @@ __global__ __launch_bounds__(CR_NT) void k_spmv_csbr(const int32_t* __restrict__
                                                      double* __restrict__ partials,
                                                      const int4* __restrict__ units,
                                                      int32_t nseg, int32_t m) {
-    __shared__ double s_y[1 << CR_PB];
-    __shared__ int32_t s_seg[CR_SEG_LDS];
+    extern __shared__ double s_dyn[];
+    double* s_y = s_dyn;                                // 2^CR_PB doubles
+    int32_t* s_seg = (int32_t*)(s_dyn + (1 << CR_PB));  // CR_SEG_LDS block starts
     const int tid = threadIdx.x;
     const int4 U = units[blockIdx.x];
     const int panel = U.x, k0 = U.y, k1 = U.z, slot = U.w;
@@ -224,12 +239,19 @@ hipError_t spmv_csbr(const spx_matrix_s* A, const double* x, double* y, hipStrea
     if (A->cr_nranked > 0)
         SPX_LAUNCH("csbr_xrank", k_csbr_xrank, dim3(spx_div_up(A->cr_nranked, 256)), dim3(256), 0,
                    s, A->cr_order, A->cr_nranked, x, A->cr_xr);
-    if (A->cb_nunits > 0)
-        SPX_LAUNCH("spmv_csbr", k_spmv_csbr, dim3(A->cb_nunits), dim3(CR_NT), 0, s, A->blk_ptr,
+    if (A->cb_nunits > 0) {
+        constexpr size_t lds = ((size_t)1 << CR_PB) * sizeof(double) + CR_SEG_LDS * sizeof(int32_t);
+        if (lds > 64 * 1024) {
+            const hipError_t e = hipFuncSetAttribute(
+                (const void*)k_spmv_csbr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        SPX_LAUNCH("spmv_csbr", k_spmv_csbr, dim3(A->cb_nunits), dim3(CR_NT), lds, s, A->blk_ptr,
                    A->packed, A->val, A->cr_xr, y, A->cb_partials, A->cb_units, (int32_t)A->nbc,
                    A->m);
+    }
     if (A->cb_nsplit > 0)
-        SPX_LAUNCH("spmv_csbr_reduce", k_spmv_csbh_reduce,
+        SPX_LAUNCH("spmv_csbr_reduce", k_spmv_csbr_reduce,
                    dim3(A->cb_nsplit * (((1 << CR_PB) + CB_RED_NT - 1) / CB_RED_NT)),
                    dim3(CB_RED_NT), 0, s, A->cb_split, A->cb_partials, y, CR_PB, A->m);
     return hipGetLastError();

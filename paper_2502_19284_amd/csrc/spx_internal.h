@@ -31,12 +31,20 @@
 #define CB_LDS_BUDGET (64 * 1024)    // bytes of the output slice kept in LDS
 #define CB_BP_STAGE_MAX 8192         // block pointers staged in LDS when nbc+1 <= this
 
-// CSBR: panels of 2^CR_PB rows (y slice in LDS), blocks of 2^CR_RB ranks, workgroup size and
-// entries per thread per sweep, default entries per work unit
-#define CR_PB 13
-#define CR_RB 19
-#define CR_NT 512
+// CSBR: panels of 2^CR_PB rows (y slice in LDS: 128 KiB, one workgroup of 16 waves per CU),
+// blocks of 2^CR_RB ranks, workgroup size and entries per thread per sweep, default entries per
+// work unit.  Measured at R-MAT scale 24: 2^13-row panels with 512-thread workgroups (two per CU)
+// 1.38 ms, 2^14-row panels with 1024 threads 1.29 ms (fewer lines of x per entry, same waves).
+#ifndef CR_PB
+#define CR_PB 14
+#endif
+#define CR_RB (32 - CR_PB)  // the packed (rank, row) position fills 32 bits
+#ifndef CR_NT
+#define CR_NT 1024
+#endif
+#ifndef CR_IPT
 #define CR_IPT 4
+#endif
 #define CR_UNIT_DEFAULT (1 << 18)
 #define CR_SEG_LDS 1024  // segment starts of a panel staged in LDS when nseg + 1 <= this
 

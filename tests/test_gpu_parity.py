@@ -273,7 +273,7 @@ def test_csbr_segments_and_split_panels(spx, unit, kind):
     m, n, E = 20_011, (1 << 21) + 3, 2_000_000
     row = rng.integers(0, m, E)
     col = rng.integers(0, n, E)
-    row[:30_000] = 8191           # a long row at a panel edge
+    row[:30_000] = 16383          # a long row at a panel edge
     col[30_000:90_000] = 12345    # one very frequent column
     row[90_000:95_000] = m - 1
     perm = rng.permutation(E)
@@ -284,9 +284,11 @@ def test_csbr_segments_and_split_panels(spx, unit, kind):
     say("csbr unit", unit, kind)
     A, y = _run(spx, "csbr", m, n, row, col, val, x, tile_items=unit)
     nranked = len(np.unique(col))
-    rbits = max(19, (nranked - 1).bit_length())
-    assert rbits >= 21                          # at least 4 rank segments per panel
-    assert A.export("blk_ptr").numel() == ((m + 8191) // 8192) * (1 << (rbits - 19)) + 1
+    pb, rb = formats.CSBR_PB, formats.CSBR_RB
+    rbits = max(rb, (nranked - 1).bit_length())
+    assert rbits >= rb + 2                      # at least 4 rank segments per panel
+    npan = (m + (1 << pb) - 1) >> pb
+    assert A.export("blk_ptr").numel() == npan * (1 << (rbits - rb)) + 1
     if kind == "int":
         _check_int(y, ref, "csbr int unit %d" % unit)
     else:
