@@ -186,6 +186,30 @@ def precision_errors(w, samples):
     return out
 
 
+def gather_probe(spx, torch, reps=10):
+    """Random 8-byte loads (library probe kernel): 2^28 loads from a 4 MiB window (inside one
+    XCD's L2: the L2 request rate) and from a 128 MiB window (every load misses: the 128-byte
+    line-fill rate that bounds a product's x gathers).  Rates in G loads/s, best of reps."""
+    x = torch.rand(1 << 24, dtype=torch.float64, device="cuda")
+    out = None
+    res = {}
+    n = 1 << 28
+    for name, window in (("l2_window_4MiB", 1 << 19), ("hbm_window_128MiB", 1 << 24)):
+        best = 1e30
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            out = spx.probe_gather(x, window, n, out)
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        res[name + "_Gloads_s"] = round(n / (best * 1e-3) / 1e9, 1)
+    res["line_fill_GB_s"] = round(res["hbm_window_128MiB_Gloads_s"] * 128, 1)
+    del x, out
+    return res
+
+
 def cpu_baseline(w, budget_s=12.0):
     """The oracle on the GPU machine's host, on a bounded sample of the same matrix (the rows whose
     index hashes into 1/8 of the range): Algorithm 1 as printed (sequential, one core) -- the
@@ -755,7 +779,8 @@ def main():
     y_d = torch.empty(m, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     copy_gbs = copy_probe(torch)
-    log("copy probe %.0f GB/s" % copy_gbs)
+    gprobe = gather_probe(spx, torch)
+    log("copy probe %.0f GB/s; gather probe %s" % (copy_gbs, gprobe))
 
     # ---------------------------------------------------------------- the step
     A = spx.convert(row_d, col_d, val_d, (m, n), args.headline)
@@ -877,6 +902,7 @@ def main():
         "batch": bt,
         "serving": served,
         "copy_probe_gbs": round(copy_gbs, 1),
+        "gather_probe": gprobe,
         "kernel_src": src_hash(*KERNEL_SOURCES),
     }
     if args.cpu_baseline:

@@ -270,6 +270,17 @@ spx_status spx_profile_enable(int32_t enable);
  * kernels recorded, which may exceed max. */
 spx_status spx_profile_collect(spx_kernel_stat* out, int32_t max, int32_t* count);
 
+/*
+ * Memory-system probe (measurement aid): `n` random 8-byte loads from the first `window` doubles
+ * of x (device; window a power of two, 1 <= window <= x's length), each thread summing its loads
+ * into out (device, spx_probe_out_len() doubles, overwritten).  Timed by the caller on `stream`.
+ * With a window far beyond the L2 every load fills one 128-byte line (the rate that bounds the x
+ * gathers of a product); inside the L2 it measures the L2 request rate.
+ * Errors: INVALID_ARG for a NULL pointer, a window that is not a power of two, or n < 0.
+ */
+spx_status spx_probe_gather(const double* x, int64_t window, int64_t n, double* out, void* stream);
+int64_t spx_probe_out_len(void);
+
 /* Static text for a status code. */
 const char* spx_status_string(spx_status s);
 

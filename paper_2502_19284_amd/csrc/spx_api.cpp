@@ -1243,3 +1243,17 @@ extern "C" spx_status spx_matrix_destroy(spx_matrix A) {
     delete A;
     return SPX_OK;
 }
+
+// ------------------------------------------------------------------ memory probe
+
+extern "C" int64_t spx_probe_out_len(void) { return probe_out_len(); }
+
+extern "C" spx_status spx_probe_gather(const double* x, int64_t window, int64_t n, double* out,
+                                       void* stream) {
+    if (!x || !out) return fail(SPX_ERR_INVALID_ARG, "NULL pointer");
+    if (window < 1 || (window & (window - 1)) != 0)
+        return fail(SPX_ERR_INVALID_ARG, "window %lld is not a power of two", (long long)window);
+    if (n < 0) return fail(SPX_ERR_INVALID_ARG, "n < 0");
+    HIP_TRY(launch_probe_gather(x, window, n, out, (hipStream_t)stream));
+    return SPX_OK;
+}

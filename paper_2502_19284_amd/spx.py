@@ -161,6 +161,10 @@ def load(path=LIB_PATH):
     L.spx_profile_collect.restype = ctypes.c_int32
     L.spx_break_even.argtypes = [ctypes.c_double] * 4
     L.spx_break_even.restype = ctypes.c_double
+    L.spx_probe_gather.argtypes = [P, ctypes.c_int64, ctypes.c_int64, P, P]
+    L.spx_probe_gather.restype = ctypes.c_int32
+    L.spx_probe_out_len.argtypes = []
+    L.spx_probe_out_len.restype = ctypes.c_int64
     L.spx_status_string.argtypes = [ctypes.c_int32]
     L.spx_status_string.restype = ctypes.c_char_p
     L.spx_last_error_message.argtypes = []
@@ -252,6 +256,20 @@ def profile_collect():
         out[s.name.decode()] = dict(launches=int(s.launches), total_ms=s.total_ms,
                                     min_ms=s.min_ms, max_ms=s.max_ms,
                                     avg_ms=s.total_ms / max(s.launches, 1))
+    return out
+
+
+def probe_gather(x, window, n, out=None, stream=None):
+    """n random 8-byte loads from the first `window` doubles of the float64 device tensor x
+    (library kernel); returns the per-thread sums tensor (timing is the caller's)."""
+    _dev_tensor(x, torch.float64, "x")
+    if window > x.numel():
+        raise ValueError("window beyond x")
+    L = load()
+    if out is None:
+        out = torch.empty(int(L.spx_probe_out_len()), dtype=torch.float64, device=x.device)
+    _check(L.spx_probe_gather(ctypes.c_void_p(x.data_ptr()), int(window), int(n),
+                              ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
 
 
@@ -605,6 +623,6 @@ def header_functions():
     for hdr in sorted(glob.glob(os.path.join(_PKG, "..", "include", "*.h"))):
         with open(hdr) as f:
             text = f.read()
-        names.update(re.findall(r"^\s*(?:const\s+)?[a-z_]+\*?\s+\**(spx_[a-z_0-9]+)\(", text, re.M))
+        names.update(re.findall(r"^\s*(?:const\s+)?[a-z_][a-z_0-9]*\*?\s+\**(spx_[a-z_0-9]+)\(", text, re.M))
     return sorted(names)
 
