@@ -225,6 +225,21 @@ spx_status spx_spmv_f32(spx_matrix A, const float* x, float* y, void* stream);
 spx_status spx_spmm(spx_matrix A, int32_t k, const void* X, int64_t ldx, void* Y, int64_t ldy,
                     spx_layout layout, void* stream);
 
+/*
+ * Y = A X exactly as spx_spmm (same arguments, results and errors), for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It makes no device allocation and calls no allocating routine.  Its scratch (the
+ * staging of column-major X and Y chunks, the hot rows of X, the merge tiles' carries and, for
+ * row-split matrices, the merge tile starts) lives in a static device array of 32 MiB that each
+ * GPU the library runs on holds until the process ends; a product needing more is refused with
+ * SPX_ERR_RANGE before any device work.  All calls on one GPU share that array, which keeps the
+ * last call's contents: calls that overlap on one GPU (other streams or threads) race, and the
+ * caller must serialise them.  The current device must be the matrix's (SPX_ERR_INVALID_ARG).
+ * Additional errors: HIP when the array's device address cannot be obtained.
+ */
+spx_status spx_spmm_noalloc(spx_matrix A, int32_t k, const void* X, int64_t ldx, void* Y,
+                            int64_t ldy, spx_layout layout, void* stream);
+
 /* Sizes and format of a handle.  info: host. */
 spx_status spx_matrix_get_info(spx_matrix A, spx_matrix_info* info);
 

@@ -1055,8 +1055,9 @@ static spx_status grow_scratch(spx_matrix_s* A, void** p, size_t* have, size_t n
     return SPX_OK;
 }
 
-extern "C" spx_status spx_spmm(spx_matrix A, int32_t k, const void* x, int64_t ldx, void* y,
-                               int64_t ldy, spx_layout layout, void* stream) {
+// Argument checks shared by spx_spmm and spx_spmm_noalloc (reported before any device work).
+spx_status spmm_check(spx_matrix A, int32_t k, const void* x, int64_t ldx, const void* y,
+                      int64_t ldy, spx_layout layout) {
     if (!A) return fail(SPX_ERR_INVALID_ARG, "matrix handle is NULL");
     if (!spx_is_crs(A->fmt))
         return fail(SPX_ERR_UNSUPPORTED, "products with several right-hand sides are provided for "
@@ -1088,6 +1089,14 @@ extern "C" spx_status spx_spmm(spx_matrix A, int32_t k, const void* x, int64_t l
     if (n > 0 && !x) return fail(SPX_ERR_INVALID_ARG, "X is NULL");
     if (ranges_overlap(x, (size_t)(xlen * es), y, (size_t)(ylen * es)))
         return fail(SPX_ERR_ALIAS, "X and Y overlap");
+    return SPX_OK;
+}
+
+extern "C" spx_status spx_spmm(spx_matrix A, int32_t k, const void* x, int64_t ldx, void* y,
+                               int64_t ldy, spx_layout layout, void* stream) {
+    SPX_TRY(spmm_check(A, k, x, ldx, y, ldy, layout));
+    const int64_t m = A->m, n = A->n;
+    const int64_t es = A->value_type == SPX_F64 ? 8 : 4;
     if (m == 0) return SPX_OK;
     hipStream_t s = (hipStream_t)stream;
 

@@ -161,6 +161,9 @@ def load(path=LIB_PATH):
     L.spx_profile_collect.restype = ctypes.c_int32
     L.spx_break_even.argtypes = [ctypes.c_double] * 4
     L.spx_break_even.restype = ctypes.c_double
+    L.spx_spmm_noalloc.argtypes = [P, ctypes.c_int32, P, ctypes.c_int64, P, ctypes.c_int64,
+                                   ctypes.c_int32, P]
+    L.spx_spmm_noalloc.restype = ctypes.c_int32
     L.spx_probe_gather.argtypes = [P, ctypes.c_int64, ctypes.c_int64, P, P]
     L.spx_probe_gather.restype = ctypes.c_int32
     L.spx_probe_out_len.argtypes = []
