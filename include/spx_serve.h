@@ -9,10 +9,15 @@
  *
  * Model:
  *   - A server owns a memory budget.  spx_server_add_matrix admits a matrix only if an upper
- *     bound of its footprint fits in what is left (otherwise SPX_ERR_NOMEM and nothing is
- *     converted); removing a matrix returns its bytes.
+ *     bound of its footprint, together with the slots' staging bound, fits in what is left
+ *     (otherwise SPX_ERR_NOMEM and nothing is converted); removing a matrix returns its bytes.
+ *     The staging bound is slots x the largest per-batch staging (x and y columns, hot rows, tile
+ *     carries for max_batch requests) of any matrix admitted so far; it is never released.
  *   - A request names a resident matrix, an input x (n floats) and an output y (m floats), both
- *     caller-owned device memory that must stay valid until the request completes.
+ *     caller-owned device memory that must stay valid until the request completes, and the
+ *     stream whose work produces x: the request's product waits (on the device) for the work
+ *     enqueued on that stream before the submission.  With a NULL stream the caller guarantees
+ *     that x is complete when it submits.
  *       SPX_REQ_SPMV:      y = A x
  *       SPX_REQ_PAGERANK:  y = d A x + (1 - d) / n   (one power-iteration step with damping d on a
  *                          column-stochastic A; the caller supplies the normalised matrix)
@@ -60,6 +65,8 @@ typedef struct {
     float damping;   /* d of SPX_REQ_PAGERANK, in [0, 1]; ignored for SPMV     */
     const float* x;  /* device, n floats                                       */
     float* y;        /* device, m floats, must not overlap x                   */
+    void* stream;    /* hipStream_t producing x (the product waits for it), or NULL
+                      * when x is already complete                              */
 } spx_request;
 
 typedef struct {
@@ -70,6 +77,7 @@ typedef struct {
     int64_t memory_budget;
     int32_t matrices;        /* resident                                               */
     int32_t in_flight;       /* batches on the device now                              */
+    int64_t bytes_staging;   /* staging bound reserved for the slots (within the budget) */
 } spx_server_stats;
 
 /* Defaults: budget 64 GiB, 4 slots, max_batch 32, coalesce 1, poll_us 0 (the scheduler yields
@@ -97,9 +105,10 @@ spx_status spx_server_add_matrix(spx_server S, const spx_coo_desc* coo, spx_form
 /* Wait for the matrix's requests, then free it and return its bytes to the budget. */
 spx_status spx_server_remove_matrix(spx_server S, int32_t id);
 
-/* Queue one request; *ticket identifies it for spx_server_wait.  Errors (INVALID_ARG for an
- * unknown matrix, NULL vectors or a bad kind, ALIAS for overlapping x and y) are reported here,
- * before anything is queued. */
+/* Queue one request; *ticket identifies it for spx_server_wait.  When req->stream is not NULL an
+ * event is recorded on it here and the product waits for that event.  Errors (INVALID_ARG for an
+ * unknown matrix, NULL vectors or a bad kind, ALIAS for overlapping x and y, HIP when the event
+ * cannot be recorded) are reported here, before anything is queued. */
 spx_status spx_server_submit(spx_server S, const spx_request* req, uint64_t* ticket);
 
 /* Block until the request completes (its y is written and visible to the device) and forget the

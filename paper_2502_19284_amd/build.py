@@ -25,10 +25,10 @@ FLAGS = [
 ]
 
 
-def _compile(src):
-    obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(PKG, "..", "include"), "-c",
-                             os.path.join(CSRC, src), "-o", obj]
+def _compile(src, out_dir=OUT_DIR, extra=()):
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + FLAGS + list(extra) + ["-I", os.path.join(PKG, "..", "include"), "-c",
+                                           os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -39,23 +39,27 @@ def _compile(src):
     return obj, warnings
 
 
-def build(verbose=False):
-    """Compile every source for gfx950 and link libspx.so (always rebuilds)."""
-    os.makedirs(OUT_DIR, exist_ok=True)
+def build(verbose=False, lib=LIB, extra_flags=()):
+    """Compile every source for gfx950 and link `lib` (always rebuilds).  extra_flags are added
+    to every compile and to the link (e.g. host-only sanitizer flags for a checking build)."""
+    out_dir = OUT_DIR if lib == LIB else os.path.join(os.path.dirname(lib), "_build_" +
+                                                      os.path.basename(lib))
+    os.makedirs(out_dir, exist_ok=True)
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        results = list(ex.map(_compile, SOURCES))
+        results = list(ex.map(lambda src: _compile(src, out_dir, extra_flags), SOURCES))
     objs = [o for o, _ in results]
     if verbose:
         for _, w in results:
             for line in w:
                 print(line, file=sys.stderr)
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + list(extra_flags) + \
+        ["-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

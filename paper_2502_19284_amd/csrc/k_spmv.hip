@@ -235,17 +235,23 @@ __global__ __launch_bounds__(CR_NT) void k_spmv_csbr(const int32_t* __restrict__
     }
 }
 
+static constexpr size_t kCsbrLds =
+    ((size_t)1 << CR_PB) * sizeof(double) + CR_SEG_LDS * sizeof(int32_t);
+
+// Raises the product kernel's dynamic LDS limit on the current device (called at conversion, so
+// that products, which may be captured in a graph, make no attribute calls).
+hipError_t csbr_prepare_kernel() {
+    if (kCsbrLds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute((const void*)k_spmv_csbr,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCsbrLds);
+}
+
 hipError_t spmv_csbr(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
+    constexpr size_t lds = kCsbrLds;
     if (A->cr_nranked > 0)
         SPX_LAUNCH("csbr_xrank", k_csbr_xrank, dim3(spx_div_up(A->cr_nranked, 256)), dim3(256), 0,
                    s, A->cr_order, A->cr_nranked, x, A->cr_xr);
     if (A->cb_nunits > 0) {
-        constexpr size_t lds = ((size_t)1 << CR_PB) * sizeof(double) + CR_SEG_LDS * sizeof(int32_t);
-        if (lds > 64 * 1024) {
-            const hipError_t e = hipFuncSetAttribute(
-                (const void*)k_spmv_csbr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-        }
         SPX_LAUNCH("spmv_csbr", k_spmv_csbr, dim3(A->cb_nunits), dim3(CR_NT), lds, s, A->blk_ptr,
                    A->packed, A->val, A->cr_xr, y, A->cb_partials, A->cb_units, (int32_t)A->nbc,
                    A->m);

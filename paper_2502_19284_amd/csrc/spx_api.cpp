@@ -508,6 +508,7 @@ static spx_status convert_bcoh(const spx_coo_desc* coo, spx_format fmt, int k, i
 // summed, block pointers over (panel, rank segment), then the CSBH work-unit tables over panels.
 static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* o, hipStream_t s,
                                spx_matrix_s* A, AllocSet& tmp) {
+    HIP_TRY(csbr_prepare_kernel());
     const int64_t E = coo->nnz;
     const int32_t m = coo->m, n = coo->n;
     const int wbits = bcoh_row_bucket_bits(n);

@@ -424,6 +424,7 @@ hipError_t spmm_crs(const spx_matrix_s* A, const SpmmPlan& P, int32_t k, const v
 hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
 hipError_t spmv_bcoh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
 hipError_t spmv_csbr(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
+hipError_t csbr_prepare_kernel();
 
 // ------------------------------------------------------------------ memory probe
 int64_t probe_out_len();

@@ -29,6 +29,7 @@ using clock_type = std::chrono::steady_clock;
 
 struct Req {
     spx_request r{};
+    hipEvent_t ready = nullptr;  // recorded on r.stream at submission (null: x complete)
     uint64_t ticket = 0;
     double t_submit = 0, t_done = 0;
     bool done = false;
@@ -82,6 +83,8 @@ struct spx_server_s {
     std::thread th;
     bool stop = false;
     int64_t used = 0, staging = 0;
+    int64_t stage_max = 0;               // largest per-slot staging bound of an admitted matrix
+    std::vector<hipEvent_t> ev_pool;     // recycled request events
     int64_t n_done = 0, n_batches = 0, widest = 0;
     int32_t in_flight = 0;
     int64_t waiting_total = 0;
@@ -125,6 +128,15 @@ static int64_t footprint_bound(const spx_coo_desc* c, int32_t vt, int32_t max_ba
     b += 20 * hot + 4 * hot * max_batch;                 // hot set, hot x copy, hot X rows
     b += (12 + 8 * (int64_t)max_batch) * tiles;          // product tiles, carry rows and values
     return b;
+}
+
+// Upper bound of one slot's staging for a batch of max_batch requests on a matrix: the x and y
+// columns (row-major X and Y), the hot rows of X and the tile carries (rows and values).
+static int64_t staging_bound(const spx_coo_desc* c, int32_t max_batch) {
+    const int64_t m = c->m, n = c->n, E = c->nnz;
+    const int64_t tiles = (m + E) / MP_TILE + 2;
+    const int64_t hot = std::min<int64_t>(n, HOT_AUTO_MAX);
+    return 4 * (m + n) * max_batch + 4 * hot * max_batch + (4 + 8 * (int64_t)max_batch) * tiles;
 }
 
 extern "C" spx_status spx_server_create(const spx_server_opts* opts, spx_server* out) {
@@ -176,6 +188,10 @@ void spx_server_s::retire(Slot& sl, double t, spx_status st) {
         q->t_done = t;
         q->status = st;
         q->done = true;
+        if (q->ready) {
+            ev_pool.push_back(q->ready);
+            q->ready = nullptr;
+        }
     }
     n_done += (int64_t)sl.batch.size();
     sl.mat->outstanding -= (int64_t)sl.batch.size();
@@ -209,6 +225,11 @@ spx_status spx_server_s::launch(Slot& sl) {
     hipError_t e;
     const spx_request& r0 = sl.batch[0]->r;
     const float beta0 = (1.0f - r0.damping) / (float)M->n;
+    for (Req* q : sl.batch)  // x of each request is produced on the submitter's stream
+        if (q->ready) {
+            e = hipStreamWaitEvent(s, q->ready, 0);
+            if (e != hipSuccess) return hip_fail(e, "waiting for a request's input");
+        }
     if (!o.coalesce) {
         spx_status st = spx_spmv_f32(M->A, r0.x, r0.y, s);
         if (st != SPX_OK) return st;
@@ -335,7 +356,11 @@ extern "C" spx_status spx_server_destroy(spx_server S) {
     }
     S->cv_sched.notify_all();
     S->th.join();
-    for (auto& kv : S->reqs) delete kv.second;
+    for (auto& kv : S->reqs) {
+        if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+        delete kv.second;
+    }
+    for (hipEvent_t ev : S->ev_pool) (void)hipEventDestroy(ev);
     for (auto& kv : S->mats) {
         spx_matrix_destroy(kv.second->A);
         delete kv.second;
@@ -364,16 +389,19 @@ extern "C" spx_status spx_server_add_matrix(spx_server S, const spx_coo_desc* co
     if (coo->m < 0 || coo->n < 0 || coo->nnz < 0)
         return spx_fail(SPX_ERR_INVALID_ARG, "negative size");
     const int64_t need = footprint_bound(coo, opts->value_type, S->o.max_batch);
+    const int64_t stage = staging_bound(coo, S->o.max_batch);
     {
         std::lock_guard<std::mutex> g(S->mu);
-        if (S->used + need > S->o.memory_budget) {
-            char buf[160];
-            snprintf(buf, sizeof buf, "admission: %lld bytes needed, %lld of %lld free",
-                     (long long)need, (long long)(S->o.memory_budget - S->used),
-                     (long long)S->o.memory_budget);
+        const int64_t stage_all = (int64_t)S->o.slots * std::max(S->stage_max, stage);
+        if (S->used + need + stage_all > S->o.memory_budget) {
+            char buf[200];
+            snprintf(buf, sizeof buf, "admission: %lld bytes needed and %lld for slot staging, "
+                     "%lld of %lld free", (long long)need, (long long)stage_all,
+                     (long long)(S->o.memory_budget - S->used), (long long)S->o.memory_budget);
             return spx_fail(SPX_ERR_NOMEM, buf);
         }
         S->used += need;  // reserved while converting
+        S->stage_max = std::max(S->stage_max, stage);
     }
     auto unreserve = [&] {
         std::lock_guard<std::mutex> g(S->mu);
@@ -466,9 +494,28 @@ static spx_status submit_locked(spx_server S, const spx_request* r, uint64_t* ti
         return spx_fail(SPX_ERR_INVALID_ARG, "x or y is NULL");
     if (overlap(r->x, (size_t)M->n * 4, r->y, (size_t)M->m * 4))
         return spx_fail(SPX_ERR_ALIAS, "x and y overlap");
+    hipEvent_t ev = nullptr;
+    if (r->stream && M->m > 0) {
+        hipError_t e = hipSuccess;
+        if (!S->ev_pool.empty()) {
+            ev = S->ev_pool.back();
+            S->ev_pool.pop_back();
+        } else {
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        }
+        if (e == hipSuccess) e = hipEventRecord(ev, (hipStream_t)r->stream);
+        if (e != hipSuccess) {
+            if (ev) S->ev_pool.push_back(ev);
+            return hip_fail(e, "recording the request's input event");
+        }
+    }
     Req* q = new (std::nothrow) Req;
-    if (!q) return spx_fail(SPX_ERR_NOMEM, "host allocation failed");
+    if (!q) {
+        if (ev) S->ev_pool.push_back(ev);
+        return spx_fail(SPX_ERR_NOMEM, "host allocation failed");
+    }
     q->r = *r;
+    q->ready = ev;
     q->ticket = S->next_ticket++;
     q->t_submit = S->now_us();
     if (M->m == 0) {  // nothing to compute
@@ -562,5 +609,6 @@ extern "C" spx_status spx_server_get_stats(spx_server S, spx_server_stats* st) {
     st->memory_budget = S->o.memory_budget;
     st->matrices = (int32_t)S->mats.size();
     st->in_flight = S->in_flight;
+    st->bytes_staging = (int64_t)S->o.slots * S->stage_max;
     return SPX_OK;
 }

@@ -76,14 +76,14 @@ class ServerOpts(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("matrix", ctypes.c_int32), ("kind", ctypes.c_int32), ("damping", ctypes.c_float),
-                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("stream", ctypes.c_void_p)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("requests", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("max_batch_seen", ctypes.c_int64), ("bytes_resident", ctypes.c_int64),
                 ("memory_budget", ctypes.c_int64), ("matrices", ctypes.c_int32),
-                ("in_flight", ctypes.c_int32)]
+                ("in_flight", ctypes.c_int32), ("bytes_staging", ctypes.c_int64)]
 
 
 REQUEST_KINDS = {"spmv": 0, "pagerank": 1}
@@ -512,15 +512,18 @@ class Server:
         _check(load().spx_server_remove_matrix(self._h, int(mid)))
         self._shapes.pop(mid, None)
 
-    def request(self, mid, x, y, kind="spmv", damping=0.85):
-        """A Request struct for submit / replay (x, y: float32 device vectors)."""
+    def request(self, mid, x, y, kind="spmv", damping=0.85, stream=None):
+        """A Request struct for submit / replay (x, y: float32 device vectors).  The product waits
+        for the work enqueued on `stream` (default: the current stream) before the submission."""
         _dev_tensor(x, torch.float32, "x")
         _dev_tensor(y, torch.float32, "y")
-        return Request(int(mid), REQUEST_KINDS[kind], float(damping), x.data_ptr(), y.data_ptr())
+        return Request(int(mid), REQUEST_KINDS[kind], float(damping), x.data_ptr(), y.data_ptr(),
+                       _stream_ptr(stream))
 
-    def submit(self, mid, x, y, kind="spmv", damping=0.85):
-        """Queue y = A x (kind 'spmv') or y = d A x + (1 - d) / n ('pagerank'); returns a ticket."""
-        r = self.request(mid, x, y, kind, damping)
+    def submit(self, mid, x, y, kind="spmv", damping=0.85, stream=None):
+        """Queue y = A x (kind 'spmv') or y = d A x + (1 - d) / n ('pagerank'); returns a ticket.
+        The product waits for the work enqueued on `stream` (default: current) before the call."""
+        r = self.request(mid, x, y, kind, damping, stream)
         t = ctypes.c_uint64()
         _check(load().spx_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
         self._held[t.value] = (x, y)

@@ -17,7 +17,7 @@ import pytest
 import synth
 from oracle import measure, spmv
 
-BLOCK_FORMATS = ("csbh", "csb", "bcohc", "bcohch")
+BLOCK_FORMATS = ("csbh", "csb", "bcohc", "bcohch", "csbr")
 
 pytestmark = pytest.mark.gpu
 
@@ -68,7 +68,7 @@ def _capture(fn):
 
 @pytest.mark.parametrize("fmt,vt", [("merge", "f64"), ("rowsplit", "f64"), ("csbh", "f64"),
                                     ("csb", "f64"), ("bcohc", "f64"), ("bcohch", "f64"),
-                                    ("merge", "f32"), ("rowsplit", "bf16")])
+                                    ("csbr", "f64"), ("merge", "f32"), ("rowsplit", "bf16")])
 def test_spmv_graph_replays(spx, rmat14, fmt, vt):
     import torch
     m, n, row, col, val = rmat14

@@ -161,15 +161,27 @@ def test_serve_admission_by_footprint(spx):
     args = (_dev(row, torch.int32), _dev(col, torch.int32), _dev(val, torch.float64), (m, n))
     probe = spx.Server()
     _, need = probe.add_matrix(*args, "merge", value_type="f32")
+    staging = probe.stats()["bytes_staging"]   # the slots' staging bound for this matrix
     probe.close()
-    S = spx.Server(memory_budget=int(2.5 * need))
+    assert staging > 0
+    # room for two matrices and the slots' staging, not for three
+    S = spx.Server(memory_budget=int(2.5 * need) + staging)
     a, _ = S.add_matrix(*args, "merge", value_type="f32")
     b, _ = S.add_matrix(*args, "merge", value_type="f32")
     with pytest.raises(spx.SpxError) as e:
         S.add_matrix(*args, "merge", value_type="f32")
     assert e.value.status == -5
     st = S.stats()
-    assert st["matrices"] == 2 and st["bytes_resident"] == 2 * need <= st["memory_budget"]
+    assert st["matrices"] == 2 and st["bytes_resident"] == 2 * need
+    assert st["bytes_staging"] == staging
+    assert st["bytes_resident"] + st["bytes_staging"] <= st["memory_budget"]
+    # without room for the staging, even the first matrix is refused
+    T = spx.Server(memory_budget=int(1.5 * need))
+    if 1.5 * need < need + staging:
+        with pytest.raises(spx.SpxError) as e:
+            T.add_matrix(*args, "merge", value_type="f32")
+        assert e.value.status == -5
+    T.close()
     # a removal returns the bytes; a request in flight is finished first
     x = _dev(synth.xvec(n, seed=1, kind="int"), torch.float32)
     y = torch.empty(m, dtype=torch.float32, device="cuda")
@@ -235,4 +247,31 @@ def test_serve_errors(spx):
     with pytest.raises(spx.SpxError):
         S.remove_matrix(mid + 99)
     assert torch.count_nonzero(y).item() == 0
+    S.close()
+
+
+def test_serve_waits_for_the_stream_producing_x(spx):
+    # x is written on a side stream behind a long-running kernel; the request names that stream,
+    # so its product must see the final x (not the zeros it held at submission)
+    import torch
+    mats = _matrices("int")
+    m, n, row, col, val = mats[0]
+    S = spx.Server(slots=2, max_batch=8)
+    mid, _ = S.add_matrix(_dev(row, torch.int32), _dev(col, torch.int32),
+                          _dev(val, torch.float64), (m, n), "merge", value_type="f32")
+    xh = synth.xvec(n, seed=77, kind="int")
+    x_true = _dev(xh, torch.float32)
+    side = torch.cuda.Stream()
+    for kind in ("spmv", "pagerank"):
+        x = torch.zeros(n, dtype=torch.float32, device="cuda")
+        y = torch.full((m,), -1.0, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            torch.cuda._sleep(20_000_000)   # a bounded spin, then the copy that produces x
+            x.copy_(x_true)
+        t = S.submit(mid, x, y, kind=kind, damping=0.85, stream=side)
+        S.wait(t)
+        torch.cuda.synchronize()
+        _check(y.cpu().numpy().astype(np.float64), _oracle(mats[0], "f32", xh, kind, 0.85),
+               "stream-ordered " + kind)
     S.close()
