@@ -240,14 +240,32 @@ hipError_t launch_bcoh_part_blk(const int32_t* blk_part, int64_t nb, int32_t P,
 
 // ------------------------------------------------------------------ product
 //
-// Workgroup p owns the rows [part_row[p], part_row[p+1]) and their slice of y in LDS.  It walks
-// the partition's entries in storage order, BH_IPT consecutive entries per thread: a thread finds
-// the block of its first entry by binary search over the partition's block pointers and moves
-// forward from there; each product is added into the slice (LDS float atomics), and the slice is
+// Workgroup p owns the rows [part_row[p], part_row[p+1]) and their slice of y in LDS.  It reads
+// the partition's entries in storage order, BH_NT consecutive entries per wave-row (loads of
+// whole lines), BH_IPT rows in flight per thread; a thread's entries ascend, so it keeps the block
+// of its last entry and moves forward (a few steps by walking the block pointers, a longer move by
+// binary search); each product is added into the slice (LDS float atomics), and the slice is
 // written to y at the end.
 
 #define BH_NT 512
 #define BH_IPT 8
+
+// Last block b in [b_from, b_end) with blk_ptr[b] <= k (blk_ptr[b_from] <= k < blk_ptr[b_end]).
+__device__ __forceinline__ int bcoh_block_of(const int32_t* __restrict__ bp, int b_from, int b_end,
+                                             int k) {
+#pragma unroll
+    for (int step = 0; step < 4; ++step) {
+        if (b_from + 1 >= b_end || bp[b_from + 1] > k) return b_from;
+        ++b_from;
+    }
+    int lo = b_from, hi = b_end - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bp[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 __global__ __launch_bounds__(BH_NT) void k_spmv_bcoh(
     const int32_t* __restrict__ part_row, const int32_t* __restrict__ part_blk,
@@ -263,33 +281,38 @@ __global__ __launch_bounds__(BH_NT) void k_spmv_bcoh(
     for (int i = tid; i < rows; i += BH_NT) s_y[i] = 0.0;
     __syncthreads();
     const uint32_t lmask = 0xFFFFu;
+    int b = b0;  // block of this thread's current entry
+    uint32_t bc = b0 < b1 ? blk_coord[b0] : 0u;
     for (int base = e0; base < e1; base += BH_NT * BH_IPT) {
-        const int kf = base + tid * BH_IPT;
-        if (kf < e1) {
-            int lo = b0, hi = b1 - 1;  // last block b with blk_ptr[b] <= kf
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (blk_ptr[mid] <= kf) lo = mid;
-                else hi = mid - 1;
-            }
-            int b = lo;
-            int next = blk_ptr[b + 1];
-            uint32_t bc = blk_coord[b];
+        uint32_t pk[BH_IPT];
+        double v[BH_IPT];
 #pragma unroll
-            for (int q = 0; q < BH_IPT; ++q) {
-                const int kk = kf + q;
-                if (kk < e1) {
-                    while (next <= kk) {
-                        ++b;
-                        next = blk_ptr[b + 1];
-                        bc = blk_coord[b];
-                    }
-                    const uint32_t pk = ntload(packed + kk);
-                    const int row = (int)((bc >> 16) << k) + (int)(pk >> 16);
-                    const int colx = (int)((bc & lmask) << k) + (int)(pk & lmask);
-                    atomicAdd(&s_y[row - r0], ntload(val + kk) * x[colx]);
+        for (int q = 0; q < BH_IPT; ++q) {
+            const int kk = base + q * BH_NT + tid;
+            pk[q] = kk < e1 ? ntload(packed + kk) : 0u;
+            v[q] = kk < e1 ? ntload(val + kk) : 0.0;
+        }
+        double xv[BH_IPT];
+        int rw[BH_IPT];
+#pragma unroll
+        for (int q = 0; q < BH_IPT; ++q) {
+            const int kk = base + q * BH_NT + tid;
+            xv[q] = 0.0;
+            rw[q] = 0;
+            if (kk < e1) {
+                const int nb = bcoh_block_of(blk_ptr, b, b1, kk);
+                if (nb != b) {
+                    b = nb;
+                    bc = blk_coord[b];
                 }
+                rw[q] = (int)((bc >> 16) << k) + (int)(pk[q] >> 16) - r0;
+                xv[q] = x[(int)((bc & lmask) << k) + (int)(pk[q] & lmask)];
             }
+        }
+#pragma unroll
+        for (int q = 0; q < BH_IPT; ++q) {
+            const int kk = base + q * BH_NT + tid;
+            if (kk < e1) atomicAdd(&s_y[rw[q]], v[q] * xv[q]);
         }
     }
     __syncthreads();

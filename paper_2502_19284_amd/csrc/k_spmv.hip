@@ -17,11 +17,30 @@ __device__ __forceinline__ void ntstore(T* p, T v) {
 //
 // Work unit u = entries [k0, k1) of block row br (at most the unit size).  The workgroup keeps
 // the block row's beta-entry slice of y in LDS and adds every product into it (LDS float atomics;
-// the Hilbert order keeps consecutive entries of a block in nearby rows and columns).  Each
-// thread takes CB_IPT consecutive entries; it finds the block of its first entry by binary search
-// over the block row's pointers (staged in LDS when they fit) and walks forward from there.
-// A unit that covers its whole block row writes the slice to y; otherwise it writes a partial
-// slice to scratch and k_spmv_csbh_reduce adds the partial slices of the block row in unit order.
+// the Hilbert order keeps consecutive entries of a block in nearby rows and columns).  The
+// workgroup reads its entries in storage order, CB_NT consecutive entries per wave-row (loads of
+// whole lines), CB_IPT rows in flight per thread; a thread's entries ascend, so it keeps the block
+// of its last entry and moves forward: a few steps by walking the block pointers (staged in LDS
+// when they fit), a longer move by binary search.  A unit that covers its whole block row writes
+// the slice to y; otherwise it writes a partial slice to scratch and k_spmv_csbh_reduce adds the
+// partial slices of the block row in unit order.
+
+// Last block b >= b_from with bp[b] <= k (bp non-decreasing, bp[b_from] <= k, bp[nb] > k).
+__device__ __forceinline__ int csb_block_of(const int32_t* __restrict__ bp, int b_from, int nb,
+                                            int k) {
+#pragma unroll
+    for (int step = 0; step < 4; ++step) {
+        if (b_from + 1 >= nb || bp[b_from + 1] > k) return b_from;
+        ++b_from;
+    }
+    int lo = b_from, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bp[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 __global__ __launch_bounds__(CB_NT) void k_spmv_csbh(const int32_t* __restrict__ blk_ptr,
                                                      const uint32_t* __restrict__ packed,
@@ -45,32 +64,30 @@ __global__ __launch_bounds__(CB_NT) void k_spmv_csbh(const int32_t* __restrict__
     __syncthreads();
     const int32_t* bp = stage_bp ? s_bp : gbp;
     const uint32_t lmask = (uint32_t)beta - 1u;
-
+    int b = 0;  // block of this thread's current entry (bp[0] <= kb)
     for (int base = kb; base < ke; base += CB_NT * CB_IPT) {
-        const int k_first = base + tid * CB_IPT;
-        if (k_first < ke) {
-            // block b with bp[b] <= k_first < bp[b+1]
-            int lo = 0, hi = nbc - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (bp[mid] <= k_first) lo = mid;
-                else hi = mid - 1;
-            }
-            int b = lo;
-            int next = bp[b + 1];
+        uint32_t p[CB_IPT];
+        double v[CB_IPT];
 #pragma unroll
-            for (int q = 0; q < CB_IPT; ++q) {
-                const int kk = k_first + q;
-                if (kk < ke) {
-                    while (next <= kk && b < nbc - 1) {
-                        ++b;
-                        next = bp[b + 1];
-                    }
-                    const uint32_t p = ntload(packed + kk);
-                    const int c = (b << k) + (int)(p & lmask);
-                    atomicAdd(&s_y[p >> 16], ntload(val + kk) * x[c]);
-                }
+        for (int q = 0; q < CB_IPT; ++q) {
+            const int kk = base + q * CB_NT + tid;
+            p[q] = kk < ke ? ntload(packed + kk) : 0u;
+            v[q] = kk < ke ? ntload(val + kk) : 0.0;
+        }
+        double xv[CB_IPT];
+#pragma unroll
+        for (int q = 0; q < CB_IPT; ++q) {
+            const int kk = base + q * CB_NT + tid;
+            xv[q] = 0.0;
+            if (kk < ke) {
+                b = csb_block_of(bp, b, nbc, kk);
+                xv[q] = x[(b << k) + (int)(p[q] & lmask)];
             }
+        }
+#pragma unroll
+        for (int q = 0; q < CB_IPT; ++q) {
+            const int kk = base + q * CB_NT + tid;
+            if (kk < ke) atomicAdd(&s_y[p[q] >> 16], v[q] * xv[q]);
         }
     }
     __syncthreads();
