@@ -19,8 +19,10 @@
  * rows allow) on the matrix alone, its tiles repeated to at least 8192 work items so that the
  * device is as full as inside a batch, and keeps the cheapest per pass.  It then times the whole
  * batch with one workgroup per item and with persistent grids of 4096 and 1024 workgroups, for
- * those plans and with 16-item merge tiles turned into 8-item ones (the largest tile sets the
- * launch's LDS size, hence the occupancy of every workgroup), and keeps the fastest.
+ * those plans, with 16-item merge tiles turned into 8-item ones (the largest tile sets the
+ * launch's LDS size, hence the occupancy of every workgroup), and with each single plan for all
+ * matrices, and keeps the fastest: the tuned batch is never slower than one fixed plan for all,
+ * to the precision of the timing.
  *
  * A product is two kernel launches with no allocation, no host synchronisation and no memset, so
  * it can be captured in a HIP graph and replayed.

@@ -118,10 +118,12 @@ static hipError_t build_tables(spx_batch_s* B, const std::vector<int32_t>& plan,
 }
 
 // Times the whole batch (zero x shared by all matrices, a scratch y per matrix) for the plans as
-// tuned and with 16-item merge tiles replaced by 8-item ones, each with one workgroup per item
-// and with persistent grids of 4096 and 1024 workgroups; keeps the fastest.
-static hipError_t tune_batch(spx_batch_s* B, const std::vector<int32_t>& plan, int64_t max_n,
-                             hipStream_t s) {
+// tuned, with 16-item merge tiles replaced by 8-item ones, and with every single plan for all
+// matrices (row tiles only where the rows allow, merge tiles of 8 items elsewhere), each with
+// one workgroup per item and with persistent grids of 4096 and 1024 workgroups; keeps the
+// fastest, so the result is never slower (to the timing's precision) than one plan for all.
+static hipError_t tune_batch(spx_batch_s* B, const std::vector<int32_t>& plan,
+                             const std::vector<uint32_t>& maxlen, int64_t max_n, hipStream_t s) {
     Dev tmp;
     tmp.s = s;
     int64_t total_m = 0;
@@ -153,6 +155,14 @@ static hipError_t tune_batch(spx_batch_s* B, const std::vector<int32_t>& plan, i
         for (int32_t& p : v)
             if (p == SPX_PLAN_MERGE_16) p = SPX_PLAN_MERGE_8;
         variants.push_back(v);
+    }
+    for (int cand : kCandidates) {
+        std::vector<int32_t> v(plan.size());
+        for (size_t i = 0; i < v.size(); ++i)
+            v[i] = (cand >= SPX_PLAN_ROWS_512 && maxlen[i] > (uint32_t)kRowPlanMaxRow)
+                       ? SPX_PLAN_MERGE_8
+                       : cand;
+        if (std::find(variants.begin(), variants.end(), v) == variants.end()) variants.push_back(v);
     }
     float best = 0;
     size_t best_v = 0;
@@ -359,7 +369,7 @@ extern "C" spx_status spx_batch_create(const spx_matrix* mats, int32_t count,
     if (e == hipSuccess && tune && B->nitems > 1024) {
         // whole-batch choices: the launch shape, and whether merge tiles of 16 items per thread
         // (which set the launch's LDS size for every workgroup) beat 8 items per thread
-        e = tune_batch(B, plan, max_n, s);
+        e = tune_batch(B, plan, maxlen, max_n, s);
     }
     if (e != hipSuccess) return bail(herr(e, "plans"));
     if (chosen)
