@@ -47,7 +47,7 @@ WORKLOADS = {
 
 
 KERNEL_SOURCES = ("k_spmv.hip", "k_spmv_crs.hip", "k_spmm.hip", "k_convert.hip", "k_hot.hip",
-                  "k_partition.hip", "k_bcoh.hip", "spx_internal.h")
+                  "k_partition.hip", "k_bcoh.hip", "spx_internal.h", "dev_merge.h")
 
 
 def log(*a):
@@ -603,9 +603,10 @@ def summarize_rocprof(prof_dir, label):
 
     prof_dir/trace: --kernel-trace --stats run; prof_dir/fetch: --pmc TCC_EA0_RDREQ_32B
     TCC_EA0_RDREQ_64B TCC_EA0_RDREQ_128B TCC_EA0_RDREQ; prof_dir/write: --pmc TCC_EA0_WRREQ
-    TCC_EA0_WRREQ_64B.  Bytes read through the L2 = 32 / 64 / 128 x the requests of each size;
-    bytes written = 32 x (WRREQ - WRREQ_64B) + 64 x WRREQ_64B.  Both are calibrated on the
-    2 GiB device copy of the copy probe (2 GiB read and 2 GiB written)."""
+    TCC_EA0_WRREQ_64B; optionally prof_dir/l2: --pmc TCC_REQ TCC_HIT TCC_MISS.  Bytes read
+    through the L2 = 32 / 64 / 128 x the requests of each size; bytes written = 32 x (WRREQ -
+    WRREQ_64B) + 64 x WRREQ_64B.  Both are calibrated on the 2 GiB device copy of the copy
+    probe (2 GiB read and 2 GiB written)."""
     import csv
     import collections
     lines = []
@@ -657,6 +658,35 @@ def summarize_rocprof(prof_dir, label):
         if fa + wa > 1e7:
             lines.append("| `%s` | %d | %.3f | %.3f | %.3f |" % (k[:60], len(fv), fa / 1e9, wa / 1e9,
                                                                (fa + wa) / 1e9))
+    l2dir = os.path.join(prof_dir, "l2", label + "_counter_collection.csv")
+    if os.path.exists(l2dir):
+        # L2 requests and hits per dispatch (TCC_REQ, TCC_HIT summed over the channels) beside
+        # the 128-byte lines fetched from memory: the two rates that bound a gather (about 261 G
+        # requests/s and 56 G lines/s on this chip)
+        disp = collections.defaultdict(lambda: collections.defaultdict(float))
+        names = {}
+        for r in csv.DictReader(open(l2dir)):
+            d = int(r["Dispatch_Id"])
+            disp[d][r["Counter_Name"]] += float(r["Counter_Value"])
+            names[d] = r["Kernel_Name"]
+        l2 = collections.defaultdict(list)
+        for d, v in disp.items():
+            l2[_short(names[d])].append((v.get("TCC_REQ", 0.0), v.get("TCC_HIT", 0.0)))
+        lines.append("")
+        lines.append("L2 requests and hits per dispatch (`--pmc TCC_REQ TCC_HIT TCC_MISS`), with the "
+                     "128-byte lines read from memory (read bytes above / 128):")
+        lines.append("")
+        lines.append("| kernel | L2 requests (M) | hits (M) | hit rate | lines read (M) |")
+        lines.append("|---|---|---|---|---|")
+        for k, vs in sorted(l2.items(), key=lambda kv: -sum(a for a, _ in kv[1]) / len(kv[1])):
+            req = sum(a for a, _ in vs) / len(vs)
+            hit = sum(b for _, b in vs) / len(vs)
+            if req < 1e6:
+                continue
+            fv = agg[k][0] if k in agg else []
+            rd = sum(fv) / max(len(fv), 1) / 128
+            lines.append("| `%s` | %.1f | %.1f | %.3f | %.1f |" % (k[:60], req / 1e6, hit / 1e6,
+                                                                hit / max(req, 1), rd / 1e6))
     return "\n".join(lines), {"kernel_src": src_hash(*KERNEL_SOURCES),
                               "traffic_bytes_per_launch": traffic}
 

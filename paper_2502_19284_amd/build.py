@@ -11,9 +11,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libspx.so")
-SOURCES = ["spx_api.cpp", "spx_prof.cpp", "spx_noalloc.cpp", "spx_serve.cpp", "spx_batch.cpp", "k_convert.hip",
-           "k_partition.hip", "k_spmv.hip", "k_spmv_crs.hip", "k_spmm.hip", "k_hot.hip",
-           "k_serve.hip", "k_batch.hip", "k_bcoh.hip", "k_probe.hip"]
+SOURCES = ["spx_api.cpp", "spx_prof.cpp", "spx_noalloc.cpp", "spx_serve.cpp", "spx_batch.cpp",
+           "k_convert.hip", "k_partition.hip", "k_spmv.hip", "k_spmv_crs.hip", "k_spmm.hip",
+           "k_hot.hip", "k_serve.hip", "k_batch.hip", "k_bcoh.hip", "k_probe.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -11,6 +11,7 @@
 //
 // Values are FP32 or bfloat16, x and y FP32; sums inside a tile are FP32, carries FP64.
 #include "dev_common.h"
+#include "dev_merge.h"
 #include "dev_values.h"
 #include "spx_internal.h"
 
@@ -24,12 +25,6 @@ __device__ __forceinline__ float bt_val(const BatchMat& M, int64_t k) {
 __device__ __forceinline__ float bt_x(const float* __restrict__ x,
                                       const int32_t* __restrict__ hot, int32_t c) {
     return c >= 0 ? x[c] : x[hot[~c]];
-}
-
-template <typename T>
-__device__ __forceinline__ void bt_seg(int& f, T& v, int f_later, T v_later) {
-    v = f_later ? v_later : v + v_later;
-    f = f | f_later;
 }
 
 template <int IPT>
@@ -49,90 +44,12 @@ __device__ void bt_merge(const BatchMat& M, int t, const float* __restrict__ x,
     }
     __syncthreads();
 
-    const int items = nrows + nnzt;
-    const int d = min(tid * IPT, items);
-    const int dend = min(d + IPT, items);
-    int lo = max(0, d - nnzt), hi = min(d, nrows);
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (s_end[mid] <= k0 + d - mid - 1) lo = mid + 1;
-        else hi = mid;
-    }
-    const int i0 = lo;
-    int i = lo, j = d - lo;
-    float run = 0;
-    float outv[IPT];
-    uint32_t endmask = 0;
-#pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-        outv[q] = 0;
-        if (d + q < dend) {
-            if (i < nrows && (j >= nnzt || s_end[i] <= k0 + j)) {
-                outv[q] = run;
-                run = 0;
-                endmask |= 1u << q;
-                ++i;
-            } else {
-                run += s_prod[j];
-                ++j;
-            }
-        }
-    }
-    int f = endmask != 0;
-    float v = run;
-    const int lane = __lane_id();
-#pragma unroll
-    for (int o = 1; o < SPX_WAVE; o <<= 1) {
-        const int fu = __shfl_up(f, o, SPX_WAVE);
-        const float vu = __shfl_up(v, o, SPX_WAVE);
-        if (lane >= o) {
-            int fa = fu;
-            float va = vu;
-            bt_seg(fa, va, f, v);
-            f = fa;
-            v = va;
-        }
-    }
-    const int w = tid / SPX_WAVE;
-    if (lane == SPX_WAVE - 1) {
-        s_wf[w] = f;
-        s_wv[w] = v;
-    }
-    int fex = __shfl_up(f, 1, SPX_WAVE);
-    float vex = __shfl_up(v, 1, SPX_WAVE);
-    if (lane == 0) {
-        fex = 0;
-        vex = 0;
-    }
-    __syncthreads();
-    int fp = 0;
-    float vp = 0;
-    for (int ww = 0; ww < w; ++ww) bt_seg(fp, vp, s_wf[ww], s_wv[ww]);
-    bt_seg(fp, vp, fex, vex);
-    const float carry_in = vp;
+    const float open = merge_tile_sums<BT_NT, IPT, float>(s_end, s_prod, nrows, nnzt, k0, s_wf,
+                                                          s_wv);
     if (tid == BT_NT - 1) {
-        int ft = fp;
-        float vt = vp;
-        bt_seg(ft, vt, (int)(endmask != 0), run);
         M.carry_row[t] = c1.x;  // m when nothing is left open
-        M.carry_val[t] = (double)vt;
+        M.carry_val[t] = (double)open;
     }
-    __syncthreads();
-    int r = i0;
-    bool first = true;
-#pragma unroll
-    for (int q = 0; q < IPT; ++q) {
-        if (endmask & (1u << q)) {
-            float o = outv[q];
-            if (first) {
-                o = carry_in + o;
-                first = false;
-            }
-            s_prod[r] = o;
-            ++r;
-        }
-    }
-    __syncthreads();
     for (int q = tid; q < nrows; q += BT_NT) y[r0 + q] = s_prod[q];
 }
 
@@ -181,7 +98,7 @@ __global__ __launch_bounds__(BT_NT) void k_batch_spmv(const BatchMat* __restrict
 }
 
 // One thread per work item: the first merge tile of every run of tiles that left the same row
-// open adds the run's carries (read 8 tiles per step, fixed combination order) into y.
+// open adds the run's carries (carry_run_sum: fixed order) into y.
 __global__ void k_batch_fixup(const BatchMat* __restrict__ mats, const int2* __restrict__ items,
                               int32_t nitems, float* const* __restrict__ ys) {
     const int it = blockIdx.x * blockDim.x + threadIdx.x;
@@ -193,23 +110,8 @@ __global__ void k_batch_fixup(const BatchMat* __restrict__ mats, const int2* __r
     const int r = M.carry_row[t];
     if (r >= M.m) return;
     if (t > 0 && M.carry_row[t - 1] == r) return;
-    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    bool go = true;
-    for (int u = t; go; u += 8) {
-        int rr[8];
-        double vv[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            rr[q] = u + q < M.tiles ? M.carry_row[u + q] : -1;
-            vv[q] = u + q < M.tiles ? M.carry_val[u + q] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            go = go && rr[q] == r;
-            if (go) a[q] += vv[q];
-        }
-    }
-    const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    const double acc =
+        carry_run_sum(M.carry_row, M.tiles, t, r, [&](int u) { return M.carry_val[u]; });
     float* y = ys[w.x];
     y[r] = (float)(acc + (double)y[r]);
 }

@@ -21,6 +21,7 @@
 // inside a tile is in ACC (FP64 for FP64 matrices, FP32 for FP32/bfloat16 values), across tiles in
 // FP64, as in the single-vector kernels.
 #include "dev_common.h"
+#include "dev_merge.h"
 #include "dev_values.h"
 #include "spx_internal.h"
 
@@ -75,12 +76,6 @@ __global__ void k_spmm_hot(const int32_t* __restrict__ hot_cols, int32_t nhot,
     h[e] = r[(int64_t)hot_cols[hh] * ldr + c];
 }
 
-template <typename T>
-__device__ __forceinline__ void mm_seg_combine(int& f, T& v, int f_later, T v_later) {
-    v = f_later ? v_later : v + v_later;
-    f = f | f_later;
-}
-
 template <typename X>
 __device__ __forceinline__ X* mm_yptr(X* y, int64_t ldy, int row_major, int64_t r, int c) {
     return row_major ? y + r * ldy + c : y + r + (int64_t)c * ldy;
@@ -119,17 +114,8 @@ __global__ __launch_bounds__(MP_NT) void k_spmm_merge(
     const int items = nrows + nnzt;
     const int d = min(g * IPG, items);
     const int de = min(d + IPG, items);
-    // split of diagonal dd: row ends consumed (ties consume the row end first)
-    auto split = [&](int dd) {
-        int lo = max(0, dd - nnzt), hi = min(dd, nrows);
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_end[mid] <= k0 + dd - mid - 1) lo = mid + 1;
-            else hi = mid;
-        }
-        return lo;
-    };
-    const int is = split(d), ie = split(de);
+    const int is = merge_split(s_end, nrows, nnzt, k0, d);
+    const int ie = merge_split(s_end, nrows, nnzt, k0, de);
     const int js = d - is, je = de - ie;
 
     ACC acc = 0;
@@ -195,7 +181,7 @@ __global__ __launch_bounds__(MP_NT) void k_spmm_merge(
         }
         __syncthreads();
         if (has) {
-            mm_seg_combine(fo, vo, f, v);
+            seg_combine(fo, vo, f, v);
             f = fo;
             v = vo;
             s_f[tid] = f;
@@ -212,9 +198,8 @@ __global__ __launch_bounds__(MP_NT) void k_spmm_merge(
     }
 }
 
-// Adds each tile's open values into Y in FP64 (one thread per run of tiles that left the same row
-// open, and column).  A row can stay open over many tiles (up to nnz / MP_TILE), so the run is
-// read 8 tiles per step into 8 partial sums, combined in a fixed order: deterministic.
+// Adds each tile's open values into Y in FP64: one thread per run of tiles that left the same row
+// open, and column (carry_run_sum: fixed order, deterministic).
 template <typename X>
 __global__ void k_spmm_fixup(const int32_t* __restrict__ carry_row,
                              const double* __restrict__ carry_val, int32_t tiles, int32_t kc,
@@ -225,23 +210,8 @@ __global__ void k_spmm_fixup(const int32_t* __restrict__ carry_row,
     const int r = carry_row[t];
     if (r >= m) return;
     if (t > 0 && carry_row[t - 1] == r) return;
-    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    bool go = true;
-    for (int u = t; go; u += 8) {
-        int rr[8];
-        double vv[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            rr[q] = u + q < tiles ? carry_row[u + q] : -1;
-            vv[q] = u + q < tiles ? carry_val[(int64_t)(u + q) * kc + c] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            go = go && rr[q] == r;
-            if (go) a[q] += vv[q];
-        }
-    }
-    const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    const double acc = carry_run_sum(carry_row, tiles, t, r,
+                                     [&](int u) { return carry_val[(int64_t)u * kc + c]; });
     X* p = mm_yptr(y, ldy, row_major, (int64_t)r, c);
     *p = (X)(acc + (double)*p);
 }

@@ -11,6 +11,7 @@
 // x_hot (see k_hot.hip).  Every y element has a single writer; partial sums go to scratch and are
 // added by a second kernel in a fixed order, so results are deterministic.
 #include "dev_common.h"
+#include "dev_merge.h"
 #include "dev_values.h"
 #include "spx_internal.h"
 
@@ -30,13 +31,6 @@ __device__ __forceinline__ X xval(const X* __restrict__ x, const X* __restrict__
 // running value, a row end emits it.  The running value a thread leaves open is passed to later
 // threads by a segmented scan; the value the tile leaves open goes to carry[t] and is added into
 // y by the fix-up kernel.
-
-// segmented-sum combine: (flag, value) of an earlier then a later segment
-template <typename T>
-__device__ __forceinline__ void seg_combine(int& f, T& v, int f_later, T v_later) {
-    v = f_later ? v_later : v + v_later;
-    f = f | f_later;
-}
 
 template <typename V, typename X, typename ACC>
 __global__ __launch_bounds__(MP_NT) void k_spmv_merge(
@@ -65,103 +59,19 @@ __global__ __launch_bounds__(MP_NT) void k_spmv_merge(
     }
     __syncthreads();
 
-    const int items = nrows + nnzt;
-    const int d = min(tid * MP_IPT, items);
-    const int dend = min(d + MP_IPT, items);
-    int lo = max(0, d - nnzt), hi = min(d, nrows);
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (s_end[mid] <= k0 + d - mid - 1) lo = mid + 1;
-        else hi = mid;
-    }
-    const int i0 = lo;
-    int i = lo, j = d - lo;
-    ACC run = 0;
-    ACC outv[MP_IPT];
-    uint32_t endmask = 0;
-#pragma unroll
-    for (int q = 0; q < MP_IPT; ++q) {
-        outv[q] = 0;
-        if (d + q < dend) {
-            if (i < nrows && (j >= nnzt || s_end[i] <= k0 + j)) {
-                outv[q] = run;
-                run = 0;
-                endmask |= 1u << q;
-                ++i;
-            } else {
-                run += s_prod[j];
-                ++j;
-            }
-        }
-    }
-
-    // segmented exclusive scan of (has_end, open value) over the threads of the tile
-    int f = endmask != 0;
-    ACC v = run;
-    const int lane = __lane_id();
-#pragma unroll
-    for (int o = 1; o < SPX_WAVE; o <<= 1) {
-        const int fu = __shfl_up(f, o, SPX_WAVE);
-        const ACC vu = __shfl_up(v, o, SPX_WAVE);
-        if (lane >= o) {
-            int fa = fu;
-            ACC va = vu;
-            seg_combine(fa, va, f, v);
-            f = fa;
-            v = va;
-        }
-    }
-    const int w = tid / SPX_WAVE;
-    if (lane == SPX_WAVE - 1) {
-        s_wf[w] = f;
-        s_wv[w] = v;
-    }
-    int fex = __shfl_up(f, 1, SPX_WAVE);
-    ACC vex = __shfl_up(v, 1, SPX_WAVE);
-    if (lane == 0) {
-        fex = 0;
-        vex = 0;
-    }
-    __syncthreads();
-    int fp = 0;
-    ACC vp = 0;
-    for (int ww = 0; ww < w; ++ww) seg_combine(fp, vp, s_wf[ww], s_wv[ww]);
-    seg_combine(fp, vp, fex, vex);
-    const ACC carry_in = vp;
-
+    const ACC open = merge_tile_sums<MP_NT, MP_IPT, ACC>(s_end, s_prod, nrows, nnzt, k0, s_wf,
+                                                          s_wv);
     // the tile's open value leaves through carry[t]
     if (tid == MP_NT - 1) {
-        int ft = fp;
-        ACC vt = vp;
-        seg_combine(ft, vt, (int)(endmask != 0), run);
         carry_row[t] = c1.x;  // m when nothing is left open
-        carry_val[t] = (double)vt;
+        carry_val[t] = (double)open;
     }
-
-    // emit rows: stage in LDS (reusing s_prod), then coalesced stores
-    __syncthreads();
-    int r = i0;
-    bool first = true;
-#pragma unroll
-    for (int q = 0; q < MP_IPT; ++q) {
-        if (endmask & (1u << q)) {
-            ACC o = outv[q];
-            if (first) {
-                o = carry_in + o;
-                first = false;
-            }
-            s_prod[r] = o;
-            ++r;
-        }
-    }
-    __syncthreads();
     for (int q = tid; q < nrows; q += MP_NT) ntstore(y + r0 + q, (X)s_prod[q]);
 }
 
 // Adds each tile's open value into y in FP64.  The first tile of a run of tiles that left the
-// same row open sums the whole run, so every row is updated by one thread; the run (up to
-// nnz / MP_TILE tiles for one long row) is read 8 tiles per step into 8 partial sums that are
-// combined in a fixed order, so results stay deterministic.
+// same row open sums the whole run (carry_run_sum: fixed order, deterministic), so every row is
+// updated by one thread.
 template <typename X>
 __global__ void k_spmv_merge_fixup(const int32_t* __restrict__ carry_row,
                                    const double* __restrict__ carry_val, int32_t tiles,
@@ -171,23 +81,8 @@ __global__ void k_spmv_merge_fixup(const int32_t* __restrict__ carry_row,
     const int r = carry_row[t];
     if (r >= m) return;
     if (t > 0 && carry_row[t - 1] == r) return;
-    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    bool go = true;
-    for (int u = t; go; u += 8) {
-        int rr[8];
-        double vv[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            rr[q] = u + q < tiles ? carry_row[u + q] : -1;
-            vv[q] = u + q < tiles ? carry_val[u + q] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            go = go && rr[q] == r;
-            if (go) a[q] += vv[q];
-        }
-    }
-    const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    const double acc =
+        carry_run_sum(carry_row, tiles, t, r, [&](int u) { return carry_val[u]; });
     y[r] = (X)(acc + (double)y[r]);
 }
 
