@@ -93,4 +93,27 @@ __device__ __forceinline__ T block_reduce(T v, T* s_tmp) {
     return tot;
 }
 
+// s[r] += v for every lane with r >= 0, by LDS float atomics.  When neighbouring lanes of the wave
+// hold the same r (runs of one row in storage order), each run is first summed by a segmented
+// scan across its lanes and only its last lane adds: atomics on one address are serialised, and
+// a run of 64 would cost 64 times one.  Every lane of the wave must call it (wave-uniform path).
+__device__ __forceinline__ void lds_add_runs(double* s, int r, double v) {
+    const int lane = __lane_id();
+    const int rp = __shfl_up(r, 1, SPX_WAVE);
+    const uint64_t heads = __ballot(lane == 0 || rp != r);
+    if (heads == ~0ull) {  // no two neighbours share a row
+        if (r >= 0) atomicAdd(&s[r], v);
+        return;
+    }
+    // first lane of this lane's run: the highest head at or below it ((2 << 63) - 1 = all lanes)
+    const int start = 63 - __clzll(heads & ((2ull << lane) - 1ull));
+#pragma unroll
+    for (int o = 1; o < SPX_WAVE; o <<= 1) {
+        const double t = __shfl_up(v, o, SPX_WAVE);
+        if (lane - o >= start) v += t;
+    }
+    const bool last = lane == SPX_WAVE - 1 || ((heads >> (lane + 1)) & 1ull);
+    if (last && r >= 0) atomicAdd(&s[r], v);
+}
+
 static inline unsigned spx_div_up(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }

@@ -244,11 +244,20 @@ hipError_t launch_bcoh_part_blk(const int32_t* blk_part, int64_t nb, int32_t P,
 // the partition's entries in storage order, BH_NT consecutive entries per wave-row (loads of
 // whole lines), BH_IPT rows in flight per thread; a thread's entries ascend, so it keeps the block
 // of its last entry and moves forward (a few steps by walking the block pointers, a longer move by
-// binary search); each product is added into the slice (LDS float atomics), and the slice is
-// written to y at the end.
+// binary search); each product is added into the slice (LDS float atomics; BCOHC stores a block
+// row by row, so neighbouring lanes often share a row, and such runs are summed across their
+// lanes before one atomic each), and the slice is written to y at the end.  The partition's block pointers, and its block coordinates when they
+// fit too, are staged in the LDS left over by the slice (BH_STAGE_WORDS words), so that the walk,
+// which carries a dependence from one entry to the next, reads LDS instead of the L2.
 
 #define BH_NT 512
 #define BH_IPT 8
+// LDS words after the output slice: two workgroups of 64 KiB + 16 KiB fill a CU's 160 KiB
+#define BH_STAGE_WORDS 4096
+
+// Most blocks whose pointers (nbk + 1 words) and coordinates (nbk words, after room for the
+// pointers of that many blocks) both fit in `words` words.
+__host__ __device__ constexpr int nbk_stage_max(int words) { return (words - 1) / 2; }
 
 // Last block b in [b_from, b_end) with blk_ptr[b] <= k (blk_ptr[b_from] <= k < blk_ptr[b_end]).
 __device__ __forceinline__ int bcoh_block_of(const int32_t* __restrict__ bp, int b_from, int b_end,
@@ -273,16 +282,27 @@ __global__ __launch_bounds__(BH_NT) void k_spmv_bcoh(
     const uint32_t* __restrict__ packed, const double* __restrict__ val,
     const double* __restrict__ x, double* __restrict__ y, int k) {
     extern __shared__ double s_y[];
+    int32_t* s_bp = (int32_t*)(s_y + BH_WINDOW);  // nbk + 1 block pointers
+    uint32_t* s_bc = (uint32_t*)(s_bp + nbk_stage_max(BH_STAGE_WORDS) + 1);  // nbk coordinates
     const int tid = threadIdx.x;
     const int p = blockIdx.x;
     const int r0 = part_row[p], rows = part_row[p + 1] - r0;
     const int b0 = part_blk[p], b1 = part_blk[p + 1];
+    const int nbk = b1 - b0;
     const int e0 = blk_ptr[b0], e1 = blk_ptr[b1];
+    const bool stage_bp = nbk + 1 <= BH_STAGE_WORDS;
+    const bool stage_bc = nbk <= nbk_stage_max(BH_STAGE_WORDS);
     for (int i = tid; i < rows; i += BH_NT) s_y[i] = 0.0;
+    if (stage_bp)
+        for (int i = tid; i <= nbk; i += BH_NT) s_bp[i] = blk_ptr[b0 + i];
+    if (stage_bc)
+        for (int i = tid; i < nbk; i += BH_NT) s_bc[i] = blk_coord[b0 + i];
     __syncthreads();
+    const int32_t* bp = stage_bp ? s_bp : blk_ptr + b0;  // partition-local block indices
+    const uint32_t* bcs = stage_bc ? s_bc : blk_coord + b0;
     const uint32_t lmask = 0xFFFFu;
-    int b = b0;  // block of this thread's current entry
-    uint32_t bc = b0 < b1 ? blk_coord[b0] : 0u;
+    int b = 0;  // partition-local block of this thread's current entry
+    uint32_t bc = nbk > 0 ? bcs[0] : 0u;
     for (int base = e0; base < e1; base += BH_NT * BH_IPT) {
         uint32_t pk[BH_IPT];
         double v[BH_IPT];
@@ -300,10 +320,10 @@ __global__ __launch_bounds__(BH_NT) void k_spmv_bcoh(
             xv[q] = 0.0;
             rw[q] = 0;
             if (kk < e1) {
-                const int nb = bcoh_block_of(blk_ptr, b, b1, kk);
+                const int nb = bcoh_block_of(bp, b, nbk, kk);
                 if (nb != b) {
                     b = nb;
-                    bc = blk_coord[b];
+                    bc = bcs[b];
                 }
                 rw[q] = (int)((bc >> 16) << k) + (int)(pk[q] >> 16) - r0;
                 xv[q] = x[(int)((bc & lmask) << k) + (int)(pk[q] & lmask)];
@@ -312,18 +332,27 @@ __global__ __launch_bounds__(BH_NT) void k_spmv_bcoh(
 #pragma unroll
         for (int q = 0; q < BH_IPT; ++q) {
             const int kk = base + q * BH_NT + tid;
-            if (kk < e1) atomicAdd(&s_y[rw[q]], v[q] * xv[q]);
+            lds_add_runs(s_y, kk < e1 ? rw[q] : -1, v[q] * xv[q]);
         }
     }
     __syncthreads();
     for (int i = tid; i < rows; i += BH_NT) ntstore(y + r0 + i, s_y[i]);
 }
 
+static constexpr size_t kBcohLds = (size_t)BH_WINDOW * sizeof(double) + BH_STAGE_WORDS * 4;
+
+// The product's LDS exceeds the default 64 KiB limit of dynamic LDS: raised once per device, at
+// conversion.
+hipError_t bcoh_prepare_kernel() {
+    return hipFuncSetAttribute((const void*)k_spmv_bcoh,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBcohLds);
+}
+
 hipError_t spmv_bcoh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
     if (A->bh_nparts <= 0) return hipSuccess;
-    SPX_LAUNCH("spmv_bcoh", k_spmv_bcoh, dim3(A->bh_nparts), dim3(BH_NT),
-               (size_t)BH_WINDOW * sizeof(double), s, A->bh_part_row, A->bh_part_blk,
-               A->bh_blk_ptr, A->bh_blk_coord, A->packed, A->val, x, y, A->log2_beta);
+    SPX_LAUNCH("spmv_bcoh", k_spmv_bcoh, dim3(A->bh_nparts), dim3(BH_NT), kBcohLds, s,
+               A->bh_part_row, A->bh_part_blk, A->bh_blk_ptr, A->bh_blk_coord, A->packed, A->val,
+               x, y, A->log2_beta);
     return hipGetLastError();
 }
 

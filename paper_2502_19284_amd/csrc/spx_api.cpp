@@ -409,6 +409,7 @@ static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot
 // the fused repeat-sum + populate step, and the block and partition tables.
 static spx_status convert_bcoh(const spx_coo_desc* coo, spx_format fmt, int k, int K2,
                                hipStream_t s, spx_matrix_s* A, AllocSet& tmp) {
+    HIP_TRY(bcoh_prepare_kernel());
     const int64_t E = coo->nnz;
     const int32_t m = coo->m;
     Readback* rb_dev;

@@ -425,6 +425,7 @@ hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStrea
 hipError_t spmv_bcoh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
 hipError_t spmv_csbr(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
 hipError_t csbr_prepare_kernel();
+hipError_t bcoh_prepare_kernel();
 
 // ------------------------------------------------------------------ memory probe
 int64_t probe_out_len();
