@@ -37,13 +37,15 @@ struct StoreExclU32B {
 #define RC_NT 1024
 #define RC_BUCKETS 4096
 #define RC_WBITS_MAX 14
-#define RC_SLICE (1 << 20)
+#define RC_SLICE (1 << 18)
 #define RC_SLICES 16
 
+// Buckets are as wide as the count's LDS allows (fewer buckets: longer runs per bucket in each
+// tile of the scatter, hence whole-line stores), narrower only when the rows fit fewer bits.
 int bcoh_row_bucket_bits(int32_t m) {  // -1: too many rows for the bucketed count
     int w = 0;
-    while (w <= RC_WBITS_MAX && (((int64_t)m + (1ll << w) - 1) >> w) > RC_BUCKETS) ++w;
-    return w <= RC_WBITS_MAX ? w : -1;
+    while (w < RC_WBITS_MAX && (1ll << w) < (int64_t)m) ++w;
+    return (((int64_t)m + (1ll << w) - 1) >> w) <= RC_BUCKETS ? w : -1;
 }
 
 __global__ __launch_bounds__(RC_NT) void k_rowc_hist(const int32_t* __restrict__ row,
@@ -81,7 +83,21 @@ __global__ __launch_bounds__(RC_NT) void k_rowc_scatter(const int32_t* __restric
     __syncthreads();
     const int64_t lo = t * RC_TILE;
     const int64_t hi = lo + RC_TILE < E ? lo + RC_TILE : E;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += RC_NT) {
+    int64_t i = lo + threadIdx.x;
+    for (; i + 3 * RC_NT < hi; i += 4 * RC_NT) {  // four entries in flight per thread
+        int32_t r[4], c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            r[u] = row[i + u * RC_NT];
+            c[u] = col[i + u * RC_NT];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool ok = (r[u] >= 0) & (r[u] < m) & (c[u] >= 0) & (c[u] < n);
+            if (ok) rows_out[atomicAdd(&cur[r[u] >> wbits], 1u)] = r[u];
+        }
+    }
+    for (; i < hi; i += RC_NT) {
         const int32_t r = row[i], c = col[i];
         const bool ok = (r >= 0) & (r < m) & (c >= 0) & (c < n);
         if (ok) rows_out[atomicAdd(&cur[r >> wbits], 1u)] = r;
@@ -107,7 +123,15 @@ __global__ __launch_bounds__(RC_NT) void k_rowc_count(const int32_t* __restrict_
     for (int i = threadIdx.x; i < W; i += RC_NT) c[i] = 0;
     __syncthreads();
     const int64_t s0 = start + len * q / slices, s1 = start + len * (q + 1) / slices;
-    for (int64_t i = s0 + threadIdx.x; i < s1; i += RC_NT) atomicAdd(&c[rows_out[i] & (W - 1)], 1u);
+    int64_t i = s0 + threadIdx.x;
+    for (; i + 3 * RC_NT < s1; i += 4 * RC_NT) {  // four loads in flight per thread
+        int32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = rows_out[i + u * RC_NT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) atomicAdd(&c[v[u] & (W - 1)], 1u);
+    }
+    for (; i < s1; i += RC_NT) atomicAdd(&c[rows_out[i] & (W - 1)], 1u);
     __syncthreads();
     const int64_t r0 = (int64_t)b << wbits;
     for (int i = threadIdx.x; i < W; i += RC_NT) {
