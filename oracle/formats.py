@@ -92,8 +92,10 @@ def check_csb(m, n, log2_beta, blk_ptr, packed, val, canon_row, canon_col, canon
 # CSBR keeps the block idea of Section 3.1 (a block row's slice of y stays on chip, and a block
 # reads only a range of x) with two changes of layout, both pure reorderings of the stored
 # entries:
-#   * columns are ranked by decreasing number of raw triplets, ties by increasing column; only
-#     columns with at least one triplet get a rank;
+#   * columns are ranked by decreasing number of raw triplets; among columns with equal counts,
+#     by increasing first panel (the panel of the column's lowest row), then increasing last
+#     panel (that of its highest row), then increasing column; only columns with at least one
+#     triplet get a rank;
 #   * block rows (panels) are 2^pb rows; a block is (panel, 2^rb consecutive ranks); blocks are
 #     stored panel by panel, segment by segment; inside a block the entries are ordered by rank,
 #     then row, and each packs (rank mod 2^rb) << pb | (row mod 2^pb).
@@ -103,12 +105,18 @@ CSBR_PB = 14
 CSBR_RB = 18
 
 
-def csbr_col_order(n, raw_cols):
-    """Column of each rank: decreasing raw triplet count, ties by increasing column index."""
-    cnt = np.bincount(np.asarray(raw_cols, np.int64), minlength=n)[:n]
-    cols = np.arange(n, dtype=np.int64)
-    order = sorted(cols[cnt > 0].tolist(), key=lambda c: (-int(cnt[c]), c))
-    return np.asarray(order, np.int64)
+def csbr_col_order(n, raw_rows, raw_cols, pb=CSBR_PB):
+    """Column of each rank: decreasing raw triplet count, then increasing first panel, increasing
+    last panel and increasing column index (panel of row r = r >> pb)."""
+    rows = np.asarray(raw_rows, np.int64)
+    cols = np.asarray(raw_cols, np.int64)
+    cnt = np.bincount(cols, minlength=n)[:n]
+    first = np.full(n, np.iinfo(np.int64).max, np.int64)
+    last = np.full(n, -1, np.int64)
+    np.minimum.at(first, cols, rows >> pb)
+    np.maximum.at(last, cols, rows >> pb)
+    c = np.flatnonzero(cnt > 0)
+    return c[np.lexsort((c, last[c], first[c], -cnt[c]))].astype(np.int64)
 
 
 def decode_csbr(m, blk_ptr, packed, col_order, pb=CSBR_PB, rb=CSBR_RB):
@@ -128,12 +136,12 @@ def decode_csbr(m, blk_ptr, packed, col_order, pb=CSBR_PB, rb=CSBR_RB):
     return row, col_order[rank], panel, rank
 
 
-def check_csbr(m, n, raw_cols, blk_ptr, packed, val, col_order, canon_row, canon_col, canon_val,
-               pb=CSBR_PB, rb=CSBR_RB):
+def check_csbr(m, n, raw_rows, raw_cols, blk_ptr, packed, val, col_order, canon_row, canon_col,
+               canon_val, pb=CSBR_PB, rb=CSBR_RB):
     """Raise AssertionError unless the CSBR arrays hold exactly the canonical triplets in the
     format's storage order: the ranking, the segment count, (panel, rank, row) strictly
     increasing along storage, and bit-identical values."""
-    want_order = csbr_col_order(n, raw_cols)
+    want_order = csbr_col_order(n, raw_rows, raw_cols, pb)
     assert np.array_equal(np.asarray(col_order, np.int64), want_order), "column ranking"
     nr = len(want_order)
     rbits = max(rb, (max(nr, 1) - 1).bit_length())

@@ -72,7 +72,7 @@ def _check_structure(A, m, n, row, col, val):
                         A.export("packed").cpu().numpy().view(np.uint32),
                         A.export("values").cpu().numpy(), cr, cc, cv, A.format == "bcohch")
     elif A.format == "csbr":
-        formats.check_csbr(m, n, col, A.export("blk_ptr").cpu().numpy(),
+        formats.check_csbr(m, n, row, col, A.export("blk_ptr").cpu().numpy(),
                            A.export("packed").cpu().numpy().view(np.uint32),
                            A.export("values").cpu().numpy(), A.export("col_order").cpu().numpy(),
                            cr, cc, cv)

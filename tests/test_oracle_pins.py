@@ -700,11 +700,13 @@ def test_csbr_check_hand_made():
     blk_ptr = [0, 3, 4, 6, 6]
     packed = [0, 1, 2, 1, 0, 2]    # (rank mod 2) << 1 | (row mod 2)
     vals = [3.0, 7.0, 8.0, 4.0, 5.0, 6.0]
-    assert formats.csbr_col_order(4, raw_cols).tolist() == order
+    raw_rows = [0, 0, 1, 2, 2, 1, 0]
+    assert formats.csbr_col_order(4, raw_rows, raw_cols, pb=1).tolist() == order
     r, c, panel, rank = formats.decode_csbr(3, blk_ptr, packed, order, pb=1, rb=1)
     assert r.tolist() == [0, 1, 0, 1, 2, 2] and c.tolist() == [2, 2, 3, 0, 2, 3]
     assert rank.tolist() == [0, 0, 1, 2, 0, 1]
-    ok = dict(m=3, n=4, raw_cols=raw_cols, blk_ptr=blk_ptr, packed=packed, val=vals,
+    ok = dict(m=3, n=4, raw_rows=raw_rows, raw_cols=raw_cols, blk_ptr=blk_ptr, packed=packed,
+              val=vals,
               col_order=order, canon_row=canon[0], canon_col=canon[1], canon_val=canon[2],
               pb=1, rb=1)
     formats.check_csbr(**ok)
@@ -720,9 +722,35 @@ def test_csbr_check_hand_made():
 
 
 def test_csbr_ranking_ties_and_empty():
-    # equal counts keep increasing column order; columns without triplets are not ranked
-    assert formats.csbr_col_order(6, [5, 1, 3, 5, 1, 0]).tolist() == [1, 5, 0, 3]
-    assert formats.csbr_col_order(3, []).tolist() == []
+    # panels of 2 rows (pb = 1).  Columns 0, 1, 3, 5 have two triplets each, column 4 one,
+    # column 2 none:
+    #   col 5: rows 4, 0 -> panels 2, 0 (first 0, last 2)
+    #   col 1: rows 1, 5 -> panels 0, 2 (first 0, last 2; ties col 5, lower column first)
+    #   col 3: rows 2, 3 -> panels 1, 1
+    #   col 0: rows 0, 1 -> panels 0, 0
+    # ranking: count 2 by (first, last, column): 0 (0,0), 1 (0,2), 5 (0,2), 3 (1,1); then 4.
+    rows = [4, 0, 1, 5, 2, 3, 0, 1, 6]
+    cols = [5, 5, 1, 1, 3, 3, 0, 0, 4]
+    assert formats.csbr_col_order(6, rows, cols, pb=1).tolist() == [0, 1, 5, 3, 4]
+    # one panel for all rows: equal counts fall back to increasing column order
+    assert formats.csbr_col_order(6, rows, cols, pb=3).tolist() == [0, 1, 3, 5, 4]
+    assert formats.csbr_col_order(3, [], []).tolist() == []
+
+
+def test_csbr_ranking_brute_force():
+    # tiny random cases against the rule applied column by column in plain Python
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        n, E, pb = int(rng.integers(1, 12)), int(rng.integers(0, 40)), int(rng.integers(0, 3))
+        rows = rng.integers(0, 16, E).tolist()
+        cols = rng.integers(0, n, E).tolist()
+        keyed = []
+        for c in range(n):
+            mine = [r >> pb for r, cc in zip(rows, cols) if cc == c]
+            if mine:
+                keyed.append(((-len(mine), min(mine), max(mine), c), c))
+        want = [c for _, c in sorted(keyed)]
+        assert formats.csbr_col_order(n, rows, cols, pb=pb).tolist() == want
 
 
 def test_parcrs_equals_algorithm1_bitwise():
