@@ -63,15 +63,18 @@ typedef int32_t spx_format;
 #define SPX_BCOHCH 5
 /* Compressed sparse blocks over ranked columns, CSBR (the block idea of Section 3.1 -- a block row
  * keeps its slice of y on chip and reads only part of x -- laid out for a GPU):
- *   - columns are ranked by decreasing raw triplet count (ties: increasing column index); only
- *     columns with at least one triplet are ranked, and rank i holds column col_order[i];
+ *   - columns are ranked by decreasing raw triplet count; equal counts by increasing first panel
+ *     (that of the column's lowest row), then increasing last panel (that of its highest row),
+ *     then increasing column index; only columns with at least one triplet are ranked, and rank
+ *     i holds column col_order[i];
  *   - rows form block rows (panels) of 2^14 rows, whose y slice lives in LDS during a product;
  *   - a block is (panel, 2^18 consecutive ranks); blocks are stored panel by panel in rank order;
  *   - inside a block, entries are stored column-major: by rank, then by row; each entry packs
  *     (rank mod 2^18) << 14 | (row mod 2^14) into 32 bits.
  * A product first gathers x into rank order (x_r[i] = x[col_order[i]]); a wave then reads
  * consecutive entries whose ranks ascend, so lanes that share a column, or neighbouring ranks,
- * share cache lines of x_r, and the most frequent columns occupy the first lines.
+ * share cache lines of x_r, and the most frequent columns occupy the first lines; the panel
+ * tie-break puts rare columns that meet the same panels next to each other.
  * Columns are limited to 2^26 (the column count is bucketed in LDS), FP64 values only. */
 #define SPX_CSB_RANKED 6
 
@@ -168,8 +171,8 @@ spx_status spx_convert_opts_default(spx_convert_opts* opts);
  *   CRS:  (row, col);
  *   CSBH: (block row, block column, Hilbert index of the local (row, col) in the block);
  *   CSB:  the same with the Z-Morton index;
- *   CSBR: (panel, column rank, row), after a count of the raw triplets per column and a sort of
- *         the columns by that count.
+ *   CSBR: (panel, column rank, row), after a count of the raw triplets per column (with the
+ *         first and last panel each column meets) and a sort of the columns by that count.
  * Repeated coordinates become one entry whose value is the sum in increasing triplet index.
  * The work-unit table the product uses is built here as well, and counted in the conversion.
  *

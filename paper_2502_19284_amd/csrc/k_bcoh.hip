@@ -71,12 +71,16 @@ __global__ __launch_bounds__(RC_NT) void k_rowc_hist(const int32_t* __restrict__
     for (int b = threadIdx.x; b < nbk; b += RC_NT) hist[(int64_t)b * T + t] = cnt[b];
 }
 
+// rows_out[pos] = the row, or with_aux: (row mod 2^wbits) | (col >> aux_shift) << wbits (the
+// count needs only the row's position in its bucket).
 __global__ __launch_bounds__(RC_NT) void k_rowc_scatter(const int32_t* __restrict__ row,
                                                         const int32_t* __restrict__ col,
                                                         int64_t E, int32_t m, int32_t n,
                                                         int wbits, int nbk, int64_t T,
                                                         const uint32_t* __restrict__ hist,
-                                                        int32_t* __restrict__ rows_out) {
+                                                        int32_t* __restrict__ rows_out,
+                                                        int with_aux, int aux_shift) {
+    const uint32_t wmask = (1u << wbits) - 1u;
     __shared__ uint32_t cur[RC_BUCKETS];
     const int64_t t = blockIdx.x;
     for (int b = threadIdx.x; b < nbk; b += RC_NT) cur[b] = hist[(int64_t)b * T + t];
@@ -94,13 +98,23 @@ __global__ __launch_bounds__(RC_NT) void k_rowc_scatter(const int32_t* __restric
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const bool ok = (r[u] >= 0) & (r[u] < m) & (c[u] >= 0) & (c[u] < n);
-            if (ok) rows_out[atomicAdd(&cur[r[u] >> wbits], 1u)] = r[u];
+            if (ok) {
+                const uint32_t pos = atomicAdd(&cur[r[u] >> wbits], 1u);
+                rows_out[pos] = with_aux ? (int32_t)(((uint32_t)r[u] & wmask) |
+                                                     ((uint32_t)(c[u] >> aux_shift) << wbits))
+                                         : r[u];
+            }
         }
     }
     for (; i < hi; i += RC_NT) {
         const int32_t r = row[i], c = col[i];
         const bool ok = (r >= 0) & (r < m) & (c >= 0) & (c < n);
-        if (ok) rows_out[atomicAdd(&cur[r >> wbits], 1u)] = r;
+        if (ok) {
+            const uint32_t pos = atomicAdd(&cur[r >> wbits], 1u);
+            rows_out[pos] = with_aux ? (int32_t)(((uint32_t)r & wmask) |
+                                                 ((uint32_t)(c >> aux_shift) << wbits))
+                                     : r;
+        }
     }
 }
 
@@ -141,10 +155,75 @@ __global__ __launch_bounds__(RC_NT) void k_rowc_count(const int32_t* __restrict_
     }
 }
 
+// Workgroup (bucket b, slice q) as in k_rowc_count, over entries scattered with their aux value
+// (row mod 2^wbits | aux << wbits): the least and greatest aux value of every row of the bucket
+// (lo / hi, which start at 0xFFFFFFFF / 0), in LDS, then stored (one slice) or merged by
+// atomics (several).  Dynamic LDS: 2 * 2^wbits words.
+__global__ __launch_bounds__(RC_NT) void k_rowc_extent(const int32_t* __restrict__ rows_out,
+                                                       const uint32_t* __restrict__ hist,
+                                                       const uint32_t* __restrict__ total,
+                                                       int64_t T, int nbk, int wbits, int32_t m,
+                                                       uint32_t* __restrict__ lo,
+                                                       uint32_t* __restrict__ hi) {
+    extern __shared__ uint32_t s_ext[];
+    const int W = 1 << wbits;
+    uint32_t* s_lo = s_ext;
+    uint32_t* s_hi = s_ext + W;
+    const int b = blockIdx.x / RC_SLICES, q = blockIdx.x % RC_SLICES;
+    const int64_t start = hist[(int64_t)b * T];
+    const int64_t end = b + 1 < nbk ? (int64_t)hist[(int64_t)(b + 1) * T] : (int64_t)*total;
+    const int64_t len = end - start;
+    int slices = (int)((len + RC_SLICE - 1) / RC_SLICE);
+    if (slices < 1) slices = 1;
+    if (slices > RC_SLICES) slices = RC_SLICES;
+    if (q >= slices) return;  // uniform over the workgroup
+    for (int i = threadIdx.x; i < W; i += RC_NT) {
+        s_lo[i] = 0xFFFFFFFFu;
+        s_hi[i] = 0u;
+    }
+    __syncthreads();
+    const int64_t s0 = start + len * q / slices, s1 = start + len * (q + 1) / slices;
+    int64_t i = s0 + threadIdx.x;
+    for (; i + 3 * RC_NT < s1; i += 4 * RC_NT) {  // four entries in flight per thread
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = (uint32_t)rows_out[i + u * RC_NT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            atomicMin(&s_lo[v[u] & (W - 1)], v[u] >> wbits);
+            atomicMax(&s_hi[v[u] & (W - 1)], v[u] >> wbits);
+        }
+    }
+    for (; i < s1; i += RC_NT) {
+        const uint32_t v = (uint32_t)rows_out[i];
+        atomicMin(&s_lo[v & (W - 1)], v >> wbits);
+        atomicMax(&s_hi[v & (W - 1)], v >> wbits);
+    }
+    __syncthreads();
+    const int64_t r0 = (int64_t)b << wbits;
+    for (int j = threadIdx.x; j < W; j += RC_NT) {
+        if (r0 + j >= m) break;
+        if (slices == 1) {
+            lo[r0 + j] = s_lo[j];
+            hi[r0 + j] = s_hi[j];
+        } else if (s_lo[j] != 0xFFFFFFFFu) {
+            atomicMin(&lo[r0 + j], s_lo[j]);
+            atomicMax(&hi[r0 + j], s_hi[j]);
+        }
+    }
+}
+
+hipError_t rowc_extent_prepare_kernel() {
+    return hipFuncSetAttribute((const void*)k_rowc_extent,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(2 * sizeof(uint32_t) << RC_WBITS_MAX));
+}
+
 hipError_t launch_bcoh_rows_bucketed(const int32_t* row, const int32_t* col, int64_t E,
                                      int32_t m, int32_t n, int wbits, uint32_t* hist,
                                      int32_t* rows_out, uint32_t* tile_sums, uint32_t* total,
-                                     uint32_t* counts, uint32_t* err, hipStream_t s) {
+                                     uint32_t* counts, uint32_t* err, hipStream_t s,
+                                     int aux_shift, uint32_t* lo, uint32_t* hi) {
     if (E <= 0) return hipSuccess;
     const int nbk = (int)(((int64_t)m + (1ll << wbits) - 1) >> wbits);
     const int64_t T = (E + RC_TILE - 1) / RC_TILE;
@@ -157,9 +236,13 @@ hipError_t launch_bcoh_rows_bucketed(const int32_t* row, const int32_t* col, int
                                                s);
     if (e != hipSuccess) return e;
     SPX_LAUNCH("bcoh_rows_scatter", k_rowc_scatter, dim3((unsigned)T), dim3(RC_NT), 0, s, row,
-               col, E, m, n, wbits, nbk, T, hist, rows_out);
+               col, E, m, n, wbits, nbk, T, hist, rows_out, lo != nullptr ? 1 : 0, aux_shift);
     SPX_LAUNCH("bcoh_rows_count", k_rowc_count, dim3((unsigned)(nbk * RC_SLICES)), dim3(RC_NT), 0,
                s, rows_out, hist, total, T, nbk, wbits, m, counts);
+    if (lo != nullptr)
+        SPX_LAUNCH("bcoh_rows_extent", k_rowc_extent, dim3((unsigned)(nbk * RC_SLICES)),
+                   dim3(RC_NT), (2 * sizeof(uint32_t)) << wbits, s, rows_out, hist, total, T, nbk,
+                   wbits, m, lo, hi);
     return hipGetLastError();
 }
 

@@ -189,42 +189,54 @@ hipError_t launch_keys_csbr(const int32_t* row, const int32_t* col, int64_t E, i
     return hipGetLastError();
 }
 
-__global__ void k_rank_keys(const uint32_t* __restrict__ counts, int32_t n,
-                            uint64_t* __restrict__ keys) {
+__global__ void k_rank_keys(const uint32_t* __restrict__ counts,
+                            const uint32_t* __restrict__ first, const uint32_t* __restrict__ last,
+                            int32_t n, int eb, int pbits, uint64_t* __restrict__ keys,
+                            uint64_t* __restrict__ cols) {
+    const uint64_t cmax = (1ull << eb) - 1ull;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-         c += (int64_t)gridDim.x * blockDim.x)
-        keys[c] = ((uint64_t)(0xFFFFFFFFu - counts[c]) << 32) | (uint64_t)c;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = counts[c];
+        const uint64_t f = k ? first[c] : 0u, l = k ? last[c] : 0u;
+        keys[c] = ((cmax - k) << (2 * pbits)) | (f << pbits) | l;
+        cols[c] = (uint64_t)c;
+    }
 }
 
-hipError_t launch_rank_keys(const uint32_t* counts, int32_t n, uint64_t* keys, hipStream_t s) {
+hipError_t launch_rank_keys(const uint32_t* counts, const uint32_t* first, const uint32_t* last,
+                            int32_t n, int eb, int pbits, uint64_t* keys, uint64_t* cols,
+                            hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    SPX_LAUNCH("rank_keys", k_rank_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, counts, n, keys);
+    SPX_LAUNCH("rank_keys", k_rank_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, counts, first,
+               last, n, eb, pbits, keys, cols);
     return hipGetLastError();
 }
 
-// Sorted position i holds column c = low half of the key; its count is zero when the high half is
+// Sorted position i holds column cols[i]; its count is zero when the count field of the key is
 // all ones, and the counted columns come first.
-__global__ void k_rank_scatter(const uint64_t* __restrict__ sorted, int32_t n,
+__global__ void k_rank_scatter(const uint64_t* __restrict__ sorted,
+                               const uint64_t* __restrict__ cols, int32_t n, int eb, int pbits,
                                int32_t* __restrict__ order, int32_t* __restrict__ rank_of,
                                uint32_t* __restrict__ nranked) {
+    const uint64_t cmax = (1ull << eb) - 1ull;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t key = sorted[i];
-        const int32_t c = (int32_t)(uint32_t)key;
+        const int32_t c = (int32_t)cols[i];
         rank_of[c] = (int32_t)i;
-        if ((key >> 32) != 0xFFFFFFFFull) {
+        if ((sorted[i] >> (2 * pbits)) != cmax) {
             order[i] = c;
-            const bool last = i + 1 == n || (sorted[i + 1] >> 32) == 0xFFFFFFFFull;
+            const bool last = i + 1 == n || (sorted[i + 1] >> (2 * pbits)) == cmax;
             if (last) *nranked = (uint32_t)(i + 1);
         }
     }
 }
 
-hipError_t launch_rank_scatter(const uint64_t* sorted, int32_t n, int32_t* order,
-                               int32_t* rank_of, uint32_t* nranked, hipStream_t s) {
+hipError_t launch_rank_scatter(const uint64_t* sorted, const uint64_t* cols, int32_t n, int eb,
+                               int pbits, int32_t* order, int32_t* rank_of, uint32_t* nranked,
+                               hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    SPX_LAUNCH("rank_scatter", k_rank_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, sorted, n,
-               order, rank_of, nranked);
+    SPX_LAUNCH("rank_scatter", k_rank_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, sorted,
+               cols, n, eb, pbits, order, rank_of, nranked);
     return hipGetLastError();
 }
 

@@ -504,9 +504,11 @@ static spx_status convert_bcoh(const spx_coo_desc* coo, spx_format fmt, int k, i
     return SPX_OK;
 }
 
-// CSBR: raw triplets per column (bucketed count, checking every index), columns ranked by a sort
-// of (decreasing count, increasing column), triplets sorted by (panel, rank, row) with repeats
-// summed, block pointers over (panel, rank segment), then the CSBH work-unit tables over panels.
+// CSBR: raw triplets per column and the first and last panel each column meets (bucketed count,
+// checking every index), columns ranked by a stable sort of (decreasing count, increasing first
+// panel, increasing last panel) with the column as payload, triplets sorted by (panel, rank, row)
+// with repeats summed, block pointers over (panel, rank segment), then the CSBH work-unit tables
+// over panels.
 static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* o, hipStream_t s,
                                spx_matrix_s* A, AllocSet& tmp) {
     HIP_TRY(csbr_prepare_kernel());
@@ -518,11 +520,18 @@ static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* 
     Readback* rb_dev;
     SPX_TRY(tmp.get(&rb_dev, 1, "readback"));
     HIP_TRY(launch_init_readback(rb_dev, s));
-    // 1. raw triplets per column
-    uint32_t *counts, *chist, *ctotal, *tsums;
+    const int eb = ceil_log2_u64((uint64_t)E + 1);  // bits of a count
+    const int pbits = ceil_log2_u64((uint64_t)npan);  // bits of a panel
+    if (eb + 2 * pbits > 64)
+        return fail(SPX_ERR_RANGE, "CSBR: ranking key of %d bits exceeds 64", eb + 2 * pbits);
+    HIP_TRY(rowc_extent_prepare_kernel());
+    // 1. raw triplets per column, and the first and last panel each column meets
+    uint32_t *counts, *chist, *ctotal, *tsums, *first, *last;
     int32_t* cols_out;
     const size_t chn = bcoh_rows_hist_elems(n, E, wbits);
     SPX_TRY(tmp.get(&counts, (size_t)n + 1, "column counts"));
+    SPX_TRY(tmp.get(&first, (size_t)std::max<int32_t>(n, 1), "first panel of each column"));
+    SPX_TRY(tmp.get(&last, (size_t)std::max<int32_t>(n, 1), "last panel of each column"));
     SPX_TRY(tmp.get(&chist, chn > 0 ? chn : 1, "column bucket histogram"));
     SPX_TRY(tmp.get(&cols_out, (size_t)(E > 0 ? E : 1), "columns by bucket"));
     SPX_TRY(tmp.get(&ctotal, 1, "column bucket total"));
@@ -530,9 +539,13 @@ static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* 
                           scan_tile_count((int64_t)n + 2));
     SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
     HIP_TRY(launch_fill_u32(counts, (int64_t)n + 1, 0u, s));
-    // rows and columns trade places: the bucketed count runs over the column indices
+    HIP_TRY(launch_fill_u32(first, n, 0xFFFFFFFFu, s));
+    HIP_TRY(launch_fill_u32(last, n, 0u, s));
+    // rows and columns trade places: the bucketed count runs over the column indices, and the
+    // panel (row >> CR_PB, below 2^17) rides along in the bits above a column's place in its
+    // bucket for the extents
     HIP_TRY(launch_bcoh_rows_bucketed(coo->col, coo->row, E, n, m, wbits, chist, cols_out, tsums,
-                                      ctotal, counts, &rb_dev->err, s));
+                                      ctotal, counts, &rb_dev->err, s, CR_PB, first, last));
     Readback rb;
     SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
     if (rb.err)
@@ -542,7 +555,8 @@ static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* 
     SPX_TRY(tmp.get(&order, (size_t)std::max<int32_t>(n, 1), "column order"));
     SPX_TRY(tmp.get(&rank_of, (size_t)std::max<int32_t>(n, 1), "column ranks"));
     if (n > 0) {
-        uint64_t *rk0, *rk1, *rv0, *rv1;
+        uint64_t *rk0, *rk1, *rv0, *rv1, *rcols;
+        SPX_TRY(tmp.get(&rcols, (size_t)n, "rank payload"));
         SPX_TRY(tmp.get(&rk0, (size_t)n, "rank keys"));
         SPX_TRY(tmp.get(&rk1, (size_t)n, "rank keys"));
         SPX_TRY(tmp.get(&rv0, (size_t)n, "rank payload"));
@@ -561,19 +575,17 @@ static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* 
         uint32_t* ctr;
         SPX_TRY(tmp.get(&ctr, 16, "sort counters"));
         sc.counters = ctr;
-        HIP_TRY(launch_rank_keys(counts, n, rk0, s));
-        // bits that can vary: the low bits of (2^32 - 1 - count) up to E, and the column
-        const int eb = ceil_log2_u64((uint64_t)E + 1);
-        const int nb = ceil_log2_u64((uint64_t)n);
-        const uint64_t vary = ((eb >= 32 ? 0xFFFFFFFFull : ((1ull << eb) - 1ull)) << 32) |
-                              (nb >= 32 ? 0xFFFFFFFFull : ((1ull << nb) - 1ull));
+        HIP_TRY(launch_rank_keys(counts, first, last, n, eb, pbits, rk0, rcols, s));
+        const int kb = eb + 2 * pbits;  // bits that can vary
+        const uint64_t vary = kb >= 64 ? ~0ull : ((1ull << kb) - 1ull);
         const uint64_t *sorted, *vs;
         int failed = 0;
         MsdStats st;
-        HIP_TRY(radix_sort_msd(rk0, rv0, rk1, rv1, rk0, n, vary, sc, s, &sorted, &vs, &failed,
+        HIP_TRY(radix_sort_msd(rk0, rv0, rk1, rv1, rcols, n, vary, sc, s, &sorted, &vs, &failed,
                                &st));
         if (failed) return fail(SPX_ERR_DEVICE, "radix sort: a device-side list overflowed");
-        HIP_TRY(launch_rank_scatter(sorted, n, order, rank_of, &rb_dev->totals[3], s));
+        HIP_TRY(launch_rank_scatter(sorted, vs, n, eb, pbits, order, rank_of,
+                                    &rb_dev->totals[3], s));
         SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
     }
     const int32_t nranked = (int32_t)rb.totals[3];

@@ -306,27 +306,39 @@ static inline bool spx_is_crs(spx_format f) { return f == SPX_CSR_ROWSPLIT || f 
 hipError_t launch_keys_csbr(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
                             int32_t n, const int32_t* rank_of, int rbits, uint64_t* keys,
                             uint32_t* err, unsigned long long* masks, hipStream_t s);
-// column ranking keys (2^32 - 1 - count) << 32 | column: ascending order = decreasing count, then
-// increasing column; the payload is unused
-hipError_t launch_rank_keys(const uint32_t* counts, int32_t n, uint64_t* keys, hipStream_t s);
-// from the sorted ranking keys: rank_of[c] for every column, order[i] = column of rank i for the
-// ranked (counted) columns, *nranked = their number (left untouched when no column is counted)
-hipError_t launch_rank_scatter(const uint64_t* sorted, int32_t n, int32_t* order,
-                               int32_t* rank_of, uint32_t* nranked, hipStream_t s);
+// column ranking keys (2^eb - 1 - count) << 2pbits | first << pbits | last, with the column as
+// payload (cols[c] = c): in a stable ascending sort, decreasing count, then increasing first and
+// last panel, then increasing column.  count < 2^eb, panels < 2^pbits, eb + 2 pbits <= 64; the
+// panels of an uncounted column are taken as 0.
+hipError_t launch_rank_keys(const uint32_t* counts, const uint32_t* first, const uint32_t* last,
+                            int32_t n, int eb, int pbits, uint64_t* keys, uint64_t* cols,
+                            hipStream_t s);
+// from the sorted ranking keys and columns: rank_of[c] for every column, order[i] = column of rank
+// i for the ranked (counted) columns, *nranked = their number (left untouched when no column is
+// counted)
+hipError_t launch_rank_scatter(const uint64_t* sorted, const uint64_t* cols, int32_t n, int eb,
+                               int pbits, int32_t* order, int32_t* rank_of, uint32_t* nranked,
+                               hipStream_t s);
 
 // ------------------------------------------------------------------ BCOHC / BCOHCH
 #define BH_WINDOW 8192       // rows of one partition at most (its output slice lives in LDS)
 #define BH_PARTS_TARGET 2048 // partitions by entry count: target = max(2^16, ceil(E / this))
 // row counts of the raw triplets (validating every index; err set on a bad one)
 // Exact raw entries per row by bucketing (no per-entry global atomics); wbits from
-// bcoh_row_bucket_bits(m) (-1: more than 2^26 rows, beyond what a 64-bit BCOH key can hold).  hist: bcoh_rows_hist_elems words,
-// rows_out: E words, total: one word, counts: m + 1 zeroed words.
+// bcoh_row_bucket_bits(m) (-1: more than 2^26 rows, beyond what a 64-bit BCOH key can hold).
+// hist: bcoh_rows_hist_elems words, rows_out: E words, total: one word, counts: m + 1 zeroed
+// words.  With lo / hi (m words each, filled with 0xFFFFFFFF / 0 beforehand) also the least and
+// greatest col >> aux_shift of every row (rows without entries keep the fill); that value must
+// fit 32 - wbits bits, and rowc_extent_prepare_kernel() must have run on the device first.
 int bcoh_row_bucket_bits(int32_t m);
 size_t bcoh_rows_hist_elems(int32_t m, int64_t E, int wbits);
+hipError_t rowc_extent_prepare_kernel();
 hipError_t launch_bcoh_rows_bucketed(const int32_t* row, const int32_t* col, int64_t E,
                                      int32_t m, int32_t n, int wbits, uint32_t* hist,
                                      int32_t* rows_out, uint32_t* tile_sums, uint32_t* total,
-                                     uint32_t* counts, uint32_t* err, hipStream_t s);
+                                     uint32_t* counts, uint32_t* err, hipStream_t s,
+                                     int aux_shift = 0, uint32_t* lo = nullptr,
+                                     uint32_t* hi = nullptr);
 
 // partitions from the exclusive row-count scan cum[0..m): part_of[r] for every row, part_row[p]
 // for every partition (part_row[P] = m written by the caller); *total = P
