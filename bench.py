@@ -80,9 +80,10 @@ def spmv_bytes(fmt, m, nnz, n_touched, A, val_bytes=8, vec_bytes=8):
         nb = A.export("blk_coord").numel()
         b += 8 * (nb + 1) + 8 * (A.parts + 1)  # block pointers and coordinates, partition table
     if fmt == "csbr":
-        # block pointers, unit table, column of each rank (the ranked copy of x is not counted:
-        # x is counted once, as read)
+        # block pointers, unit table, column of each column rank, rank of each row (the ranked
+        # copies of x and y are not counted: x is counted once, as read, and y once, as written)
         b += 4 * A.export("blk_ptr").numel() + 16 * A.parts + 4 * A.export("col_order").numel()
+        b += 4 * m
     return b
 
 

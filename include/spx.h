@@ -61,21 +61,28 @@ typedef int32_t spx_format;
 #define SPX_BCOHC 4
 /* BCOHCH: as BCOHC with every partition's entries sorted by the Hilbert curve over (row, col). */
 #define SPX_BCOHCH 5
-/* Compressed sparse blocks over ranked columns, CSBR (the block idea of Section 3.1 -- a block row
- * keeps its slice of y on chip and reads only part of x -- laid out for a GPU):
+/* Compressed sparse blocks over ranked rows and columns, CSBR (the block idea of Section 3.1 -- a
+ * block row keeps its slice of y on chip and reads only part of x -- laid out for a GPU):
+ *   - rows are ranked by decreasing raw triplet count, ties by increasing row index; only rows
+ *     with at least one triplet are ranked (the others get y = 0), rank i holds row
+ *     row_order[i];
+ *   - block rows (panels) are 2^14 consecutive row ranks, whose y slice lives in LDS during a
+ *     product;
  *   - columns are ranked by decreasing raw triplet count; equal counts by increasing first panel
- *     (that of the column's lowest row), then increasing last panel (that of its highest row),
+ *     (the least panel among the column's triplets), then increasing last panel (the greatest),
  *     then increasing column index; only columns with at least one triplet are ranked, and rank
  *     i holds column col_order[i];
- *   - rows form block rows (panels) of 2^14 rows, whose y slice lives in LDS during a product;
- *   - a block is (panel, 2^18 consecutive ranks); blocks are stored panel by panel in rank order;
- *   - inside a block, entries are stored column-major: by rank, then by row; each entry packs
- *     (rank mod 2^18) << 14 | (row mod 2^14) into 32 bits.
+ *   - a block is (panel, 2^18 consecutive column ranks); blocks are stored panel by panel in
+ *     rank order;
+ *   - inside a block, entries are stored column-major: by column rank, then by row rank; each
+ *     entry packs (column rank mod 2^18) << 14 | (row rank mod 2^14) into 32 bits.
  * A product first gathers x into rank order (x_r[i] = x[col_order[i]]); a wave then reads
  * consecutive entries whose ranks ascend, so lanes that share a column, or neighbouring ranks,
- * share cache lines of x_r, and the most frequent columns occupy the first lines; the panel
- * tie-break puts rare columns that meet the same panels next to each other.
- * Columns are limited to 2^26 (the column count is bucketed in LDS), FP64 values only. */
+ * share cache lines of x_r, and the most frequent columns occupy the first lines.  Ranking the
+ * rows gathers the longest rows into the first panels, and the panel tie-break puts rare columns
+ * that meet the same panels next to each other: both cut the x_r lines a product fetches.  The
+ * panels' slices form y in row-rank order, which a last pass permutes into y.
+ * Rows and columns are limited to 2^26 (their counts are bucketed in LDS), FP64 values only. */
 #define SPX_CSB_RANKED 6
 
 typedef int32_t spx_dtype;
@@ -149,11 +156,13 @@ typedef int32_t spx_array;
                              * BCOHC/BCOHCH: int32[blocks+1], first entry of each stored block */
 #define SPX_ARRAY_PACKED 4  /* CSB/CSBH: uint32[nnz], (local_row << 16) | local_col, in the
                              * block's Hilbert (CSBH) or Z-Morton (CSB) order; CSBR:
-                             * (rank mod 2^18) << 14 | (row mod 2^14), column-major in a block */
+                             * (column rank mod 2^18) << 14 | (row rank mod 2^14), column-major
+                             * in a block */
 #define SPX_ARRAY_PARTS 5   /* format's work-unit table, int32 (layout is internal; BCOHC /
                              * BCOHCH: P+1 partition first rows, then P+1 first blocks)     */
 #define SPX_ARRAY_BLK_COORD 6 /* BCOHC/BCOHCH: uint32[blocks], (block_row << 16) | block_col */
 #define SPX_ARRAY_COL_ORDER 7 /* CSBR: int32[ranked columns], the column of each rank          */
+#define SPX_ARRAY_ROW_ORDER 8 /* CSBR: int32[ranked rows], the row of each row rank             */
 
 /* Optional device allocator: alloc returns NULL on failure; free accepts what alloc returned. */
 typedef void* (*spx_alloc_fn)(size_t bytes, void* stream, void* ctx);
@@ -171,8 +180,9 @@ spx_status spx_convert_opts_default(spx_convert_opts* opts);
  *   CRS:  (row, col);
  *   CSBH: (block row, block column, Hilbert index of the local (row, col) in the block);
  *   CSB:  the same with the Z-Morton index;
- *   CSBR: (panel, column rank, row), after a count of the raw triplets per column (with the
- *         first and last panel each column meets) and a sort of the columns by that count.
+ *   CSBR: (panel, column rank, row rank), after counts of the raw triplets per row and per
+ *         column (with the first and last panel each column meets) and sorts of the rows and the
+ *         columns by those counts.
  * Repeated coordinates become one entry whose value is the sum in increasing triplet index.
  * The work-unit table the product uses is built here as well, and counted in the conversion.
  *

@@ -87,73 +87,89 @@ def check_csb(m, n, log2_beta, blk_ptr, packed, val, canon_row, canon_col, canon
     assert np.array_equal(a, b), "values differ bitwise"
 
 
-# ---------------------------------------------------------------- CSB over ranked columns
+# ---------------------------------------------------------------- CSB over ranked rows and columns
 #
 # CSBR keeps the block idea of Section 3.1 (a block row's slice of y stays on chip, and a block
-# reads only a range of x) with two changes of layout, both pure reorderings of the stored
-# entries:
+# reads only a range of x) with rows and columns renumbered; both are pure reorderings of the
+# stored entries:
+#   * rows are ranked by decreasing number of raw triplets, ties by increasing row; only rows with
+#     at least one triplet get a rank (the others have y = 0);
+#   * block rows (panels) are 2^pb consecutive row ranks;
 #   * columns are ranked by decreasing number of raw triplets; among columns with equal counts,
-#     by increasing first panel (the panel of the column's lowest row), then increasing last
-#     panel (that of its highest row), then increasing column; only columns with at least one
-#     triplet get a rank;
-#   * block rows (panels) are 2^pb rows; a block is (panel, 2^rb consecutive ranks); blocks are
-#     stored panel by panel, segment by segment; inside a block the entries are ordered by rank,
-#     then row, and each packs (rank mod 2^rb) << pb | (row mod 2^pb).
+#     by increasing first panel (the least panel among its triplets), then increasing last panel
+#     (the greatest), then increasing column; only columns with at least one triplet get a rank;
+#   * a block is (panel, 2^rb consecutive column ranks); blocks are stored panel by panel, segment
+#     by segment; inside a block the entries are ordered by column rank, then row rank, and each
+#     packs (column rank mod 2^rb) << pb | (row rank mod 2^pb).
 # The product is the same y = A x; only the summation order differs.
 
 CSBR_PB = 14
 CSBR_RB = 18
 
 
-def csbr_col_order(n, raw_rows, raw_cols, pb=CSBR_PB):
-    """Column of each rank: decreasing raw triplet count, then increasing first panel, increasing
-    last panel and increasing column index (panel of row r = r >> pb)."""
+def csbr_row_order(m, raw_rows):
+    """Row of each row rank: decreasing raw triplet count, ties by increasing row index."""
+    cnt = np.bincount(np.asarray(raw_rows, np.int64), minlength=m)[:m]
+    r = np.flatnonzero(cnt > 0)
+    return r[np.lexsort((r, -cnt[r]))].astype(np.int64)
+
+
+def csbr_col_order(m, n, raw_rows, raw_cols, pb=CSBR_PB):
+    """Column of each column rank: decreasing raw triplet count, then increasing first panel,
+    increasing last panel and increasing column index (panel of row r = its row rank >> pb)."""
     rows = np.asarray(raw_rows, np.int64)
     cols = np.asarray(raw_cols, np.int64)
+    ranked = csbr_row_order(m, rows)
+    row_rank = np.zeros(m, np.int64)
+    row_rank[ranked] = np.arange(len(ranked))
     cnt = np.bincount(cols, minlength=n)[:n]
     first = np.full(n, np.iinfo(np.int64).max, np.int64)
     last = np.full(n, -1, np.int64)
-    np.minimum.at(first, cols, rows >> pb)
-    np.maximum.at(last, cols, rows >> pb)
+    np.minimum.at(first, cols, row_rank[rows] >> pb)
+    np.maximum.at(last, cols, row_rank[rows] >> pb)
     c = np.flatnonzero(cnt > 0)
     return c[np.lexsort((c, last[c], first[c], -cnt[c]))].astype(np.int64)
 
 
-def decode_csbr(m, blk_ptr, packed, col_order, pb=CSBR_PB, rb=CSBR_RB):
-    """Triplet coordinates in storage order: (row, col, panel, rank)."""
+def decode_csbr(row_order, blk_ptr, packed, col_order, pb=CSBR_PB, rb=CSBR_RB):
+    """Triplet coordinates in storage order: (row, col, panel, column rank, row rank)."""
     blk_ptr = np.asarray(blk_ptr, np.int64)
-    npan = max(1, -(-m // (1 << pb)))
+    row_order = np.asarray(row_order, np.int64)
+    npan = max(1, -(-len(row_order) // (1 << pb)))
     nblk = len(blk_ptr) - 1
     assert nblk % npan == 0, "blk_ptr length is not panels x segments + 1"
     nseg = nblk // npan
     blk = np.repeat(np.arange(nblk, dtype=np.int64), np.diff(blk_ptr))
     panel, seg = blk // nseg, blk % nseg
     p = np.asarray(packed, np.int64) & 0xFFFFFFFF
-    rank = (seg << rb) + (p >> pb)
-    row = (panel << pb) + (p & ((1 << pb) - 1))
+    crank = (seg << rb) + (p >> pb)
+    rrank = (panel << pb) + (p & ((1 << pb) - 1))
     col_order = np.asarray(col_order, np.int64)
-    assert np.all(rank < len(col_order)), "rank beyond the ranked columns"
-    return row, col_order[rank], panel, rank
+    assert np.all(crank < len(col_order)), "column rank beyond the ranked columns"
+    assert np.all(rrank < len(row_order)), "row rank beyond the ranked rows"
+    return row_order[rrank], col_order[crank], panel, crank, rrank
 
 
-def check_csbr(m, n, raw_rows, raw_cols, blk_ptr, packed, val, col_order, canon_row, canon_col,
-               canon_val, pb=CSBR_PB, rb=CSBR_RB):
+def check_csbr(m, n, raw_rows, raw_cols, blk_ptr, packed, val, col_order, row_order, canon_row,
+               canon_col, canon_val, pb=CSBR_PB, rb=CSBR_RB):
     """Raise AssertionError unless the CSBR arrays hold exactly the canonical triplets in the
-    format's storage order: the ranking, the segment count, (panel, rank, row) strictly
-    increasing along storage, and bit-identical values."""
-    want_order = csbr_col_order(n, raw_rows, raw_cols, pb)
-    assert np.array_equal(np.asarray(col_order, np.int64), want_order), "column ranking"
-    nr = len(want_order)
+    format's storage order: both rankings, the segment count, (panel, column rank, row rank)
+    strictly increasing along storage, and bit-identical values."""
+    want_rows = csbr_row_order(m, raw_rows)
+    assert np.array_equal(np.asarray(row_order, np.int64), want_rows), "row ranking"
+    want_cols = csbr_col_order(m, n, raw_rows, raw_cols, pb)
+    assert np.array_equal(np.asarray(col_order, np.int64), want_cols), "column ranking"
+    nr = len(want_cols)
     rbits = max(rb, (max(nr, 1) - 1).bit_length())
-    npan = max(1, -(-m // (1 << pb)))
+    npan = max(1, -(-len(want_rows) // (1 << pb)))
     blk_ptr = np.asarray(blk_ptr, np.int64)
     assert len(blk_ptr) == npan * (1 << (rbits - rb)) + 1, "segments per panel"
     assert blk_ptr[0] == 0 and blk_ptr[-1] == len(packed) == len(val), "blk_ptr ends"
     assert np.all(np.diff(blk_ptr) >= 0), "blk_ptr not monotone"
-    row, col, panel, rank = decode_csbr(m, blk_ptr, packed, want_order, pb, rb)
-    assert np.all(row < m), "row outside the matrix"
-    key = [(int(a), int(b), int(c)) for a, b, c in zip(panel, rank, row)]
-    assert all(key[i] < key[i + 1] for i in range(len(key) - 1)), "not in (panel, rank, row) order"
+    row, col, panel, crank, rrank = decode_csbr(want_rows, blk_ptr, packed, want_cols, pb, rb)
+    key = [(int(a), int(b), int(c)) for a, b, c in zip(panel, crank, rrank)]
+    assert all(key[i] < key[i + 1] for i in range(len(key) - 1)), \
+        "not in (panel, column rank, row rank) order"
     order = np.lexsort((col, row))
     assert np.array_equal(row[order], np.asarray(canon_row, np.int64)), "rows"
     assert np.array_equal(col[order], np.asarray(canon_col, np.int64)), "cols"

@@ -71,15 +71,18 @@ __global__ __launch_bounds__(RC_NT) void k_rowc_hist(const int32_t* __restrict__
     for (int b = threadIdx.x; b < nbk; b += RC_NT) hist[(int64_t)b * T + t] = cnt[b];
 }
 
-// rows_out[pos] = the row, or with_aux: (row mod 2^wbits) | (col >> aux_shift) << wbits (the
-// count needs only the row's position in its bucket).
+// rows_out[pos] = the row, or with_aux: (row mod 2^wbits) | aux << wbits with aux =
+// map[col] >> aux_shift (map NULL: col >> aux_shift); the count needs only the row's position in
+// its bucket.  keep (nullable, with a map) receives map[col] at the entry's own index.
 __global__ __launch_bounds__(RC_NT) void k_rowc_scatter(const int32_t* __restrict__ row,
                                                         const int32_t* __restrict__ col,
                                                         int64_t E, int32_t m, int32_t n,
                                                         int wbits, int nbk, int64_t T,
                                                         const uint32_t* __restrict__ hist,
                                                         int32_t* __restrict__ rows_out,
-                                                        int with_aux, int aux_shift) {
+                                                        int with_aux, int aux_shift,
+                                                        const int32_t* __restrict__ aux_map,
+                                                        int32_t* __restrict__ keep) {
     const uint32_t wmask = (1u << wbits) - 1u;
     __shared__ uint32_t cur[RC_BUCKETS];
     const int64_t t = blockIdx.x;
@@ -100,9 +103,14 @@ __global__ __launch_bounds__(RC_NT) void k_rowc_scatter(const int32_t* __restric
             const bool ok = (r[u] >= 0) & (r[u] < m) & (c[u] >= 0) & (c[u] < n);
             if (ok) {
                 const uint32_t pos = atomicAdd(&cur[r[u] >> wbits], 1u);
-                rows_out[pos] = with_aux ? (int32_t)(((uint32_t)r[u] & wmask) |
-                                                     ((uint32_t)(c[u] >> aux_shift) << wbits))
-                                         : r[u];
+                int32_t v = r[u];
+                if (with_aux) {
+                    const int32_t mc = aux_map ? aux_map[c[u]] : c[u];
+                    if (keep) keep[i + u * RC_NT] = mc;
+                    v = (int32_t)(((uint32_t)r[u] & wmask) |
+                                  ((uint32_t)(mc >> aux_shift) << wbits));
+                }
+                rows_out[pos] = v;
             }
         }
     }
@@ -111,9 +119,13 @@ __global__ __launch_bounds__(RC_NT) void k_rowc_scatter(const int32_t* __restric
         const bool ok = (r >= 0) & (r < m) & (c >= 0) & (c < n);
         if (ok) {
             const uint32_t pos = atomicAdd(&cur[r >> wbits], 1u);
-            rows_out[pos] = with_aux ? (int32_t)(((uint32_t)r & wmask) |
-                                                 ((uint32_t)(c >> aux_shift) << wbits))
-                                     : r;
+            int32_t v = r;
+            if (with_aux) {
+                const int32_t mc = aux_map ? aux_map[c] : c;
+                if (keep) keep[i] = mc;
+                v = (int32_t)(((uint32_t)r & wmask) | ((uint32_t)(mc >> aux_shift) << wbits));
+            }
+            rows_out[pos] = v;
         }
     }
 }
@@ -223,7 +235,8 @@ hipError_t launch_bcoh_rows_bucketed(const int32_t* row, const int32_t* col, int
                                      int32_t m, int32_t n, int wbits, uint32_t* hist,
                                      int32_t* rows_out, uint32_t* tile_sums, uint32_t* total,
                                      uint32_t* counts, uint32_t* err, hipStream_t s,
-                                     int aux_shift, uint32_t* lo, uint32_t* hi) {
+                                     int aux_shift, uint32_t* lo, uint32_t* hi,
+                                     const int32_t* aux_map, int32_t* aux_keep) {
     if (E <= 0) return hipSuccess;
     const int nbk = (int)(((int64_t)m + (1ll << wbits) - 1) >> wbits);
     const int64_t T = (E + RC_TILE - 1) / RC_TILE;
@@ -236,7 +249,8 @@ hipError_t launch_bcoh_rows_bucketed(const int32_t* row, const int32_t* col, int
                                                s);
     if (e != hipSuccess) return e;
     SPX_LAUNCH("bcoh_rows_scatter", k_rowc_scatter, dim3((unsigned)T), dim3(RC_NT), 0, s, row,
-               col, E, m, n, wbits, nbk, T, hist, rows_out, lo != nullptr ? 1 : 0, aux_shift);
+               col, E, m, n, wbits, nbk, T, hist, rows_out, lo != nullptr ? 1 : 0, aux_shift,
+               aux_map, aux_keep);
     SPX_LAUNCH("bcoh_rows_count", k_rowc_count, dim3((unsigned)(nbk * RC_SLICES)), dim3(RC_NT), 0,
                s, rows_out, hist, total, T, nbk, wbits, m, counts);
     if (lo != nullptr)
@@ -353,9 +367,10 @@ hipError_t launch_bcoh_part_blk(const int32_t* blk_part, int64_t nb, int32_t P,
 // of its last entry and moves forward (a few steps by walking the block pointers, a longer move by
 // binary search); each product is added into the slice (LDS float atomics; BCOHC stores a block
 // row by row, so neighbouring lanes often share a row, and such runs are summed across their
-// lanes before one atomic each), and the slice is written to y at the end.  The partition's block pointers, and its block coordinates when they
-// fit too, are staged in the LDS left over by the slice (BH_STAGE_WORDS words), so that the walk,
-// which carries a dependence from one entry to the next, reads LDS instead of the L2.
+// lanes before one atomic each), and the slice is written to y at the end.  The partition's
+// block pointers, and its block coordinates when they fit too, are staged in the LDS left over
+// by the slice (BH_STAGE_WORDS words), so that the walk, which carries a dependence from one
+// entry to the next, reads LDS instead of the L2.
 
 #define BH_NT 512
 #define BH_IPT 8

@@ -142,13 +142,15 @@ struct KeyBcoh {
 
 // CSBR: (panel, rank of the column, row inside the panel); the rank field is rbits wide, so the
 // key shifted right by 32 (= CR_RB + CR_PB) is the block index panel * segments + segment
+// (rr, c) = (row rank, column) of a triplet
 struct KeyCsbr {
     const int32_t* rank_of;
     int rbits;
-    __device__ uint64_t operator()(uint32_t r, uint32_t c) const {
-        const uint64_t panel = r >> CR_PB;
+    __device__ uint64_t operator()(uint32_t rr, uint32_t c) const {
+        const uint64_t panel = rr >> CR_PB;
         const uint64_t rank = (uint32_t)rank_of[c];
-        return (panel << (rbits + CR_PB)) | (rank << CR_PB) | (uint64_t)(r & ((1u << CR_PB) - 1u));
+        return (panel << (rbits + CR_PB)) | (rank << CR_PB) |
+               (uint64_t)(rr & ((1u << CR_PB) - 1u));
     }
 };
 
@@ -181,41 +183,42 @@ hipError_t launch_keys_csb(const int32_t* row, const int32_t* col, int64_t E, in
     return hipGetLastError();
 }
 
-hipError_t launch_keys_csbr(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+hipError_t launch_keys_csbr(const int32_t* rrank, const int32_t* col, int64_t E, int32_t m,
                             int32_t n, const int32_t* rank_of, int rbits, uint64_t* keys,
                             uint32_t* err, unsigned long long* masks, hipStream_t s) {
     SPX_LAUNCH("keys", (k_keys<KeyCsbr>), dim3(grid_for(E, 256, KEYS_MAX_GRID)), dim3(256), 0, s,
-               row, col, E, m, n, keys, err, masks, KeyCsbr{rank_of, rbits});
+               rrank, col, E, m, n, keys, err, masks, KeyCsbr{rank_of, rbits});
     return hipGetLastError();
 }
 
 __global__ void k_rank_keys(const uint32_t* __restrict__ counts,
                             const uint32_t* __restrict__ first, const uint32_t* __restrict__ last,
-                            int32_t n, int eb, int pbits, uint64_t* __restrict__ keys,
-                            uint64_t* __restrict__ cols) {
+                            int32_t n, int eb, int pbits, int ib, int ishift,
+                            uint64_t* __restrict__ keys, uint64_t* __restrict__ cols) {
     const uint64_t cmax = (1ull << eb) - 1ull;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
          c += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t k = counts[c];
-        const uint64_t f = k ? first[c] : 0u, l = k ? last[c] : 0u;
-        keys[c] = ((cmax - k) << (2 * pbits)) | (f << pbits) | l;
+        const uint64_t f = k && first ? first[c] : 0u, l = k && last ? last[c] : 0u;
+        keys[c] = ((cmax - k) << (2 * pbits + ib)) | (f << (pbits + ib)) | (l << ib) |
+                  ((uint64_t)c >> ishift);
         cols[c] = (uint64_t)c;
     }
 }
 
 hipError_t launch_rank_keys(const uint32_t* counts, const uint32_t* first, const uint32_t* last,
-                            int32_t n, int eb, int pbits, uint64_t* keys, uint64_t* cols,
-                            hipStream_t s) {
+                            int32_t n, int eb, int pbits, int ib, int ishift, uint64_t* keys,
+                            uint64_t* cols, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     SPX_LAUNCH("rank_keys", k_rank_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, counts, first,
-               last, n, eb, pbits, keys, cols);
+               last, n, eb, pbits, ib, ishift, keys, cols);
     return hipGetLastError();
 }
 
-// Sorted position i holds column cols[i]; its count is zero when the count field of the key is
-// all ones, and the counted columns come first.
+// Sorted position i holds index cols[i]; its count is zero when the count field of the key is
+// all ones, and the counted indices come first.
 __global__ void k_rank_scatter(const uint64_t* __restrict__ sorted,
-                               const uint64_t* __restrict__ cols, int32_t n, int eb, int pbits,
+                               const uint64_t* __restrict__ cols, int32_t n, int eb, int fshift,
                                int32_t* __restrict__ order, int32_t* __restrict__ rank_of,
                                uint32_t* __restrict__ nranked) {
     const uint64_t cmax = (1ull << eb) - 1ull;
@@ -223,20 +226,20 @@ __global__ void k_rank_scatter(const uint64_t* __restrict__ sorted,
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t c = (int32_t)cols[i];
         rank_of[c] = (int32_t)i;
-        if ((sorted[i] >> (2 * pbits)) != cmax) {
+        if ((sorted[i] >> fshift) != cmax) {
             order[i] = c;
-            const bool last = i + 1 == n || (sorted[i + 1] >> (2 * pbits)) == cmax;
+            const bool last = i + 1 == n || (sorted[i + 1] >> fshift) == cmax;
             if (last) *nranked = (uint32_t)(i + 1);
         }
     }
 }
 
 hipError_t launch_rank_scatter(const uint64_t* sorted, const uint64_t* cols, int32_t n, int eb,
-                               int pbits, int32_t* order, int32_t* rank_of, uint32_t* nranked,
+                               int fshift, int32_t* order, int32_t* rank_of, uint32_t* nranked,
                                hipStream_t s) {
     if (n <= 0) return hipSuccess;
     SPX_LAUNCH("rank_scatter", k_rank_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, sorted,
-               cols, n, eb, pbits, order, rank_of, nranked);
+               cols, n, eb, fshift, order, rank_of, nranked);
     return hipGetLastError();
 }
 

@@ -165,7 +165,7 @@ hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStrea
 }
 
 // ================================================================== CSBR (Section 3.1 blocks over
-// ranked columns)
+// ranked rows and columns)
 //
 // x_r[i] = x[order[i]]: the ranked copy of x that the product reads.
 __global__ void k_csbr_xrank(const int32_t* __restrict__ order, int32_t nr,
@@ -174,21 +174,22 @@ __global__ void k_csbr_xrank(const int32_t* __restrict__ order, int32_t nr,
     if (i < nr) xr[i] = x[order[i]];
 }
 
-// Work unit u = entries [k0, k1) of panel p (CR_PB rows).  The workgroup keeps the panel's y
-// slice in LDS.  Entries are read in storage order, CR_NT consecutive entries per wave-row, so
-// the lanes of a wave hold ascending ranks: their x_r loads fall on few cache lines, and the
-// lines of the most frequent columns stay in L2 for every panel.  An entry's rank is its block's
-// segment (found from the panel's block starts) times 2^CR_RB plus the packed rank field.
-// Products are added into the slice with LDS float atomics; a unit covering its whole panel
-// writes the slice to y, otherwise to its partial slot, reduced in slot order afterwards.
+// Work unit u = entries [k0, k1) of panel p (2^CR_PB row ranks).  The workgroup keeps the panel's
+// slice of y_r (y in row-rank order) in LDS.  Entries are read in storage order, CR_NT
+// consecutive entries per wave-row, so the lanes of a wave hold ascending column ranks: their x_r
+// loads fall on few cache lines, and the lines of the most frequent columns stay in L2 for every
+// panel.  An entry's column rank is its block's segment (found from the panel's block starts)
+// times 2^CR_RB plus the packed rank field.  Products are added into the slice with LDS float
+// atomics; a unit covering its whole panel writes the slice to y_r, otherwise to its partial
+// slot, reduced in slot order afterwards.
 __global__ __launch_bounds__(CR_NT) void k_spmv_csbr(const int32_t* __restrict__ blk_ptr,
                                                      const uint32_t* __restrict__ packed,
                                                      const double* __restrict__ val,
                                                      const double* __restrict__ xr,
-                                                     double* __restrict__ y,
+                                                     double* __restrict__ yr,
                                                      double* __restrict__ partials,
                                                      const int4* __restrict__ units,
-                                                     int32_t nseg, int32_t m) {
+                                                     int32_t nseg, int32_t nrows) {
     extern __shared__ double s_dyn[];
     double* s_y = s_dyn;                                // 2^CR_PB doubles
     int32_t* s_seg = (int32_t*)(s_dyn + (1 << CR_PB));  // CR_SEG_LDS block starts
@@ -243,9 +244,9 @@ __global__ __launch_bounds__(CR_NT) void k_spmv_csbr(const int32_t* __restrict__
     }
     __syncthreads();
     const int row0 = panel << CR_PB;
-    const int rows = min(1 << CR_PB, m - row0);
+    const int rows = min(1 << CR_PB, nrows - row0);
     if (slot < 0) {
-        for (int i = tid; i < rows; i += CR_NT) ntstore(y + row0 + i, s_y[i]);
+        for (int i = tid; i < rows; i += CR_NT) yr[row0 + i] = s_y[i];
     } else {
         double* dst = partials + ((int64_t)slot << CR_PB);
         for (int i = tid; i < rows; i += CR_NT) dst[i] = s_y[i];
@@ -263,6 +264,15 @@ hipError_t csbr_prepare_kernel() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCsbrLds);
 }
 
+// y[r] = y_r[row_rank[r]]; rows without entries (rank >= nrows) get 0.
+__global__ void k_csbr_yperm(const int32_t* __restrict__ row_rank, int32_t m, int32_t nrows,
+                             const double* __restrict__ yr, double* __restrict__ y) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int32_t rr = ntload(row_rank + r);
+    ntstore(y + r, rr < nrows ? yr[rr] : 0.0);
+}
+
 hipError_t spmv_csbr(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
     constexpr size_t lds = kCsbrLds;
     if (A->cr_nranked > 0)
@@ -270,12 +280,16 @@ hipError_t spmv_csbr(const spx_matrix_s* A, const double* x, double* y, hipStrea
                    s, A->cr_order, A->cr_nranked, x, A->cr_xr);
     if (A->cb_nunits > 0) {
         SPX_LAUNCH("spmv_csbr", k_spmv_csbr, dim3(A->cb_nunits), dim3(CR_NT), lds, s, A->blk_ptr,
-                   A->packed, A->val, A->cr_xr, y, A->cb_partials, A->cb_units, (int32_t)A->nbc,
-                   A->m);
+                   A->packed, A->val, A->cr_xr, A->cr_yr, A->cb_partials, A->cb_units,
+                   (int32_t)A->nbc, A->cr_nrows);
     }
     if (A->cb_nsplit > 0)
         SPX_LAUNCH("spmv_csbr_reduce", k_spmv_csbr_reduce,
                    dim3(A->cb_nsplit * (((1 << CR_PB) + CB_RED_NT - 1) / CB_RED_NT)),
-                   dim3(CB_RED_NT), 0, s, A->cb_split, A->cb_partials, y, CR_PB, A->m);
+                   dim3(CB_RED_NT), 0, s, A->cb_split, A->cb_partials, A->cr_yr, CR_PB,
+                   A->cr_nrows);
+    if (A->m > 0)
+        SPX_LAUNCH("csbr_yperm", k_csbr_yperm, dim3(spx_div_up(A->m, 256)), dim3(256), 0, s,
+                   A->cr_row_rank, A->m, A->cr_nrows, A->cr_yr, y);
     return hipGetLastError();
 }

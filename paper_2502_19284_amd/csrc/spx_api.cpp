@@ -189,12 +189,15 @@ static spx_status build_keys_and_sort(const spx_coo_desc* coo, spx_format fmt, i
                                       uint64_t* v0, uint64_t* k1, uint64_t* v1,
                                       const MsdScratch& sc, Readback* rb_dev, hipStream_t s,
                                       SortedEntries* out, const uint64_t** vs, int* failed,
-                                      uint32_t* head_tiles, int* heads);
+                                      uint32_t* head_tiles, int* heads,
+                                      const int32_t* row_map);
 
+// part_of / K2: BCOH partitions and Hilbert level, or CSBR column ranks and rank width; row_map:
+// CSBR row rank of every triplet.
 static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_format fmt, int k,
                                  int64_t nbc, int cbits, int sum_dup, hipStream_t s,
                                  SortedEntries* out, const int32_t* part_of = nullptr,
-                                 int K2 = 0) {
+                                 int K2 = 0, const int32_t* row_map = nullptr) {
     const int64_t E = coo->nnz;
     uint64_t *k0, *k1, *v0, *v1;
     uint32_t* tsums;
@@ -234,7 +237,7 @@ static spx_status sort_and_dedup(AllocSet& tmp, const spx_coo_desc* coo, spx_for
     } else {
         SPX_TRY(build_keys_and_sort(coo, fmt, k, nbc, cbits, part_of, K2, k0, v0, k1, v1, sc,
                                     rb_dev, s, out, &vs, &failed, sum_dup ? tsums : nullptr,
-                                    &heads));
+                                    &heads, row_map));
     }
     if (failed == 2)
         return fail(SPX_ERR_INDEX, "a triplet index lies outside [0,%d) x [0,%d)", coo->m, coo->n);
@@ -262,13 +265,15 @@ static spx_status build_keys_and_sort(const spx_coo_desc* coo, spx_format fmt, i
                                       uint64_t* v0, uint64_t* k1, uint64_t* v1,
                                       const MsdScratch& sc, Readback* rb_dev, hipStream_t s,
                                       SortedEntries* out, const uint64_t** vs, int* failed,
-                                      uint32_t* head_tiles, int* heads) {
+                                      uint32_t* head_tiles, int* heads,
+                                      const int32_t* row_map) {
     const int64_t E = coo->nnz;
     if (spx_is_bcoh(fmt))
         HIP_TRY(launch_keys_bcoh(coo->row, coo->col, E, coo->m, coo->n, part_of, k, K2,
                                  fmt == SPX_BCOHCH, k0, &rb_dev->err, rb_dev->masks, s));
-    else if (fmt == SPX_CSB_RANKED)  // part_of carries the column ranks, K2 the rank width
-        HIP_TRY(launch_keys_csbr(coo->row, coo->col, E, coo->m, coo->n, part_of, K2, k0,
+    else if (fmt == SPX_CSB_RANKED)  // part_of: column ranks, row_map: triplets' row ranks,
+                                     // K2: rank width
+        HIP_TRY(launch_keys_csbr(row_map, coo->col, E, coo->m, coo->n, part_of, K2, k0,
                                  &rb_dev->err, rb_dev->masks, s));
     else if (spx_is_csb(fmt))
         HIP_TRY(launch_keys_csb(coo->row, coo->col, E, coo->m, coo->n, k, nbc,
@@ -504,90 +509,123 @@ static spx_status convert_bcoh(const spx_coo_desc* coo, spx_format fmt, int k, i
     return SPX_OK;
 }
 
-// CSBR: raw triplets per column and the first and last panel each column meets (bucketed count,
-// checking every index), columns ranked by a stable sort of (decreasing count, increasing first
-// panel, increasing last panel) with the column as payload, triplets sorted by (panel, rank, row)
-// with repeats summed, block pointers over (panel, rank segment), then the CSBH work-unit tables
-// over panels.
+// Ranks by a stable device sort of (2^eb - 1 - count, first panel, last panel) with the index as
+// payload (first / last NULL: by count alone): order[i] = index of rank i for the counted indices,
+// rank_of[c] for all, *nranked_dev (device word) = their number.
+static spx_status rank_by_counts(AllocSet& tmp, const uint32_t* counts, const uint32_t* first,
+                                 const uint32_t* last, int32_t n, int eb, int pbits,
+                                 int32_t* order, int32_t* rank_of, uint32_t* nranked_dev,
+                                 hipStream_t s) {
+    if (n <= 0) return SPX_OK;
+    uint64_t *rk0, *rk1, *rv0, *rv1, *ridx;
+    SPX_TRY(tmp.get(&ridx, (size_t)n, "rank payload"));
+    SPX_TRY(tmp.get(&rk0, (size_t)n, "rank keys"));
+    SPX_TRY(tmp.get(&rk1, (size_t)n, "rank keys"));
+    SPX_TRY(tmp.get(&rv0, (size_t)n, "rank payload"));
+    SPX_TRY(tmp.get(&rv1, (size_t)n, "rank payload"));
+    MsdScratch sc;
+    sc.z = msd_sizes(n);
+    for (int i = 0; i < 2; ++i) {
+        SPX_TRY(tmp.get(&sc.seg_start[i], (size_t)sc.z.cap_big, "sort segments"));
+        SPX_TRY(tmp.get(&sc.seg_len[i], (size_t)sc.z.cap_big, "sort segments"));
+    }
+    SPX_TRY(tmp.get(&sc.tbase, (size_t)sc.z.cap_big + 1, "sort segment tiles"));
+    SPX_TRY(tmp.get(&sc.tile_seg, (size_t)sc.z.cap_tiles, "sort tile segments"));
+    SPX_TRY(tmp.get(&sc.hist, (size_t)sc.z.hist, "radix histogram"));
+    SPX_TRY(tmp.get(&sc.tile_sums, (size_t)sc.z.tile_sums, "scan tile sums"));
+    SPX_TRY(tmp.get(&sc.chunks, (size_t)sc.z.cap_chunks, "sort chunks"));
+    uint32_t* ctr;
+    SPX_TRY(tmp.get(&ctr, 16, "sort counters"));
+    sc.counters = ctr;
+    // the high bits of the index fill what the key has left: equal keys only among indices
+    // that share them (a sort finishes long runs of equal keys by copying them, one workgroup
+    // per run)
+    const int cb = ceil_log2_u64((uint64_t)n);
+    const int ib = std::max(0, std::min(cb, 64 - eb - 2 * pbits));
+    HIP_TRY(launch_rank_keys(counts, first, last, n, eb, pbits, ib, cb - ib, rk0, ridx, s));
+    const int kb = eb + 2 * pbits + ib;  // bits that can vary
+    const uint64_t vary = kb >= 64 ? ~0ull : ((1ull << kb) - 1ull);
+    const uint64_t *sorted, *vs;
+    int failed = 0;
+    MsdStats st;
+    HIP_TRY(radix_sort_msd(rk0, rv0, rk1, rv1, ridx, n, vary, sc, s, &sorted, &vs, &failed, &st));
+    if (failed) return fail(SPX_ERR_DEVICE, "radix sort: a device-side list overflowed");
+    HIP_TRY(launch_rank_scatter(sorted, vs, n, eb, 2 * pbits + ib, order, rank_of, nranked_dev,
+                                s));
+    return SPX_OK;
+}
+
+// CSBR: raw triplets per row (bucketed count, checking every index) and the row ranking; raw
+// triplets per column with the first and last panel each column meets, and the column ranking;
+// triplets sorted by (panel, column rank, row rank) with repeats summed, block pointers over
+// (panel, rank segment), then the CSBH work-unit tables over panels.
 static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* o, hipStream_t s,
                                spx_matrix_s* A, AllocSet& tmp) {
     HIP_TRY(csbr_prepare_kernel());
+    HIP_TRY(rowc_extent_prepare_kernel());
     const int64_t E = coo->nnz;
     const int32_t m = coo->m, n = coo->n;
-    const int wbits = bcoh_row_bucket_bits(n);
-    if (wbits < 0) return fail(SPX_ERR_RANGE, "CSBR: %d columns, more than 2^26", n);
-    const int64_t npan = std::max<int64_t>(1, ((int64_t)m + (1 << CR_PB) - 1) >> CR_PB);
+    const int wbr = bcoh_row_bucket_bits(m);
+    if (wbr < 0) return fail(SPX_ERR_RANGE, "CSBR: %d rows, more than 2^26", m);
+    const int wbc = bcoh_row_bucket_bits(n);
+    if (wbc < 0) return fail(SPX_ERR_RANGE, "CSBR: %d columns, more than 2^26", n);
+    const int eb = ceil_log2_u64((uint64_t)E + 1);  // bits of a count
     Readback* rb_dev;
     SPX_TRY(tmp.get(&rb_dev, 1, "readback"));
     HIP_TRY(launch_init_readback(rb_dev, s));
-    const int eb = ceil_log2_u64((uint64_t)E + 1);  // bits of a count
-    const int pbits = ceil_log2_u64((uint64_t)npan);  // bits of a panel
-    if (eb + 2 * pbits > 64)
-        return fail(SPX_ERR_RANGE, "CSBR: ranking key of %d bits exceeds 64", eb + 2 * pbits);
-    HIP_TRY(rowc_extent_prepare_kernel());
-    // 1. raw triplets per column, and the first and last panel each column meets
-    uint32_t *counts, *chist, *ctotal, *tsums, *first, *last;
-    int32_t* cols_out;
-    const size_t chn = bcoh_rows_hist_elems(n, E, wbits);
-    SPX_TRY(tmp.get(&counts, (size_t)n + 1, "column counts"));
-    SPX_TRY(tmp.get(&first, (size_t)std::max<int32_t>(n, 1), "first panel of each column"));
-    SPX_TRY(tmp.get(&last, (size_t)std::max<int32_t>(n, 1), "last panel of each column"));
-    SPX_TRY(tmp.get(&chist, chn > 0 ? chn : 1, "column bucket histogram"));
-    SPX_TRY(tmp.get(&cols_out, (size_t)(E > 0 ? E : 1), "columns by bucket"));
-    SPX_TRY(tmp.get(&ctotal, 1, "column bucket total"));
-    size_t tsn = std::max(scan_tile_count(chn > 0 ? (int64_t)chn : 1),
-                          scan_tile_count((int64_t)n + 2));
+    // scratch of both bucketed counts
+    uint32_t *hist, *btotal, *tsums;
+    int32_t* bucketed;
+    const size_t hn = std::max(bcoh_rows_hist_elems(m, E, wbr), bcoh_rows_hist_elems(n, E, wbc));
+    SPX_TRY(tmp.get(&hist, hn > 0 ? hn : 1, "bucket histogram"));
+    SPX_TRY(tmp.get(&bucketed, (size_t)(E > 0 ? E : 1), "indices by bucket"));
+    SPX_TRY(tmp.get(&btotal, 1, "bucket total"));
+    size_t tsn = std::max(scan_tile_count(hn > 0 ? (int64_t)hn : 1),
+                          scan_tile_count((int64_t)std::max(m, n) + 2));
     SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
-    HIP_TRY(launch_fill_u32(counts, (int64_t)n + 1, 0u, s));
-    HIP_TRY(launch_fill_u32(first, n, 0xFFFFFFFFu, s));
-    HIP_TRY(launch_fill_u32(last, n, 0u, s));
-    // rows and columns trade places: the bucketed count runs over the column indices, and the
-    // panel (row >> CR_PB, below 2^17) rides along in the bits above a column's place in its
-    // bucket for the extents
-    HIP_TRY(launch_bcoh_rows_bucketed(coo->col, coo->row, E, n, m, wbits, chist, cols_out, tsums,
-                                      ctotal, counts, &rb_dev->err, s, CR_PB, first, last));
+    // 1. raw triplets per row, then the row ranks
+    uint32_t* rcounts;
+    int32_t *row_order, *row_rank;
+    SPX_TRY(tmp.get(&rcounts, (size_t)m + 1, "row counts"));
+    SPX_TRY(tmp.get(&row_order, (size_t)std::max<int32_t>(m, 1), "row order"));
+    SPX_TRY(tmp.get(&row_rank, (size_t)std::max<int32_t>(m, 1), "row ranks"));
+    HIP_TRY(launch_fill_u32(rcounts, (int64_t)m + 1, 0u, s));
+    HIP_TRY(launch_bcoh_rows_bucketed(coo->row, coo->col, E, m, n, wbr, hist, bucketed, tsums,
+                                      btotal, rcounts, &rb_dev->err, s));
     Readback rb;
     SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
     if (rb.err)
         return fail(SPX_ERR_INDEX, "a triplet index lies outside [0,%d) x [0,%d)", m, n);
-    // 2. column ranks
+    SPX_TRY(rank_by_counts(tmp, rcounts, nullptr, nullptr, m, eb, 0, row_order, row_rank,
+                           &rb_dev->totals[2], s));
+    SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
+    const int32_t nrows = (int32_t)rb.totals[2];
+    const int64_t npan = std::max<int64_t>(1, ((int64_t)nrows + (1 << CR_PB) - 1) >> CR_PB);
+    const int pbits = ceil_log2_u64((uint64_t)npan);  // bits of a panel
+    if (eb + 2 * pbits > 64)
+        return fail(SPX_ERR_RANGE, "CSBR: ranking key of %d bits exceeds 64", eb + 2 * pbits);
+    // 2. raw triplets per column, with the first and last panel each column meets, then the
+    //    column ranks.  Rows and columns trade places in the bucketed count, and a triplet's
+    //    panel (row rank >> CR_PB, below 2^17) rides along in the bits above the column's place
+    //    in its bucket.
+    uint32_t *counts, *first, *last;
+    SPX_TRY(tmp.get(&counts, (size_t)n + 1, "column counts"));
+    SPX_TRY(tmp.get(&first, (size_t)std::max<int32_t>(n, 1), "first panel of each column"));
+    SPX_TRY(tmp.get(&last, (size_t)std::max<int32_t>(n, 1), "last panel of each column"));
+    HIP_TRY(launch_fill_u32(counts, (int64_t)n + 1, 0u, s));
+    HIP_TRY(launch_fill_u32(first, n, 0xFFFFFFFFu, s));
+    HIP_TRY(launch_fill_u32(last, n, 0u, s));
+    int32_t* trank;  // row rank of every triplet, for the sort keys
+    SPX_TRY(tmp.get(&trank, (size_t)(E > 0 ? E : 1), "row rank of each triplet"));
+    HIP_TRY(launch_bcoh_rows_bucketed(coo->col, coo->row, E, n, m, wbc, hist, bucketed, tsums,
+                                      btotal, counts, &rb_dev->err, s, CR_PB, first, last,
+                                      row_rank, trank));
     int32_t *order, *rank_of;
     SPX_TRY(tmp.get(&order, (size_t)std::max<int32_t>(n, 1), "column order"));
     SPX_TRY(tmp.get(&rank_of, (size_t)std::max<int32_t>(n, 1), "column ranks"));
-    if (n > 0) {
-        uint64_t *rk0, *rk1, *rv0, *rv1, *rcols;
-        SPX_TRY(tmp.get(&rcols, (size_t)n, "rank payload"));
-        SPX_TRY(tmp.get(&rk0, (size_t)n, "rank keys"));
-        SPX_TRY(tmp.get(&rk1, (size_t)n, "rank keys"));
-        SPX_TRY(tmp.get(&rv0, (size_t)n, "rank payload"));
-        SPX_TRY(tmp.get(&rv1, (size_t)n, "rank payload"));
-        MsdScratch sc;
-        sc.z = msd_sizes(n);
-        for (int i = 0; i < 2; ++i) {
-            SPX_TRY(tmp.get(&sc.seg_start[i], (size_t)sc.z.cap_big, "sort segments"));
-            SPX_TRY(tmp.get(&sc.seg_len[i], (size_t)sc.z.cap_big, "sort segments"));
-        }
-        SPX_TRY(tmp.get(&sc.tbase, (size_t)sc.z.cap_big + 1, "sort segment tiles"));
-        SPX_TRY(tmp.get(&sc.tile_seg, (size_t)sc.z.cap_tiles, "sort tile segments"));
-        SPX_TRY(tmp.get(&sc.hist, (size_t)sc.z.hist, "radix histogram"));
-        SPX_TRY(tmp.get(&sc.tile_sums, (size_t)sc.z.tile_sums, "scan tile sums"));
-        SPX_TRY(tmp.get(&sc.chunks, (size_t)sc.z.cap_chunks, "sort chunks"));
-        uint32_t* ctr;
-        SPX_TRY(tmp.get(&ctr, 16, "sort counters"));
-        sc.counters = ctr;
-        HIP_TRY(launch_rank_keys(counts, first, last, n, eb, pbits, rk0, rcols, s));
-        const int kb = eb + 2 * pbits;  // bits that can vary
-        const uint64_t vary = kb >= 64 ? ~0ull : ((1ull << kb) - 1ull);
-        const uint64_t *sorted, *vs;
-        int failed = 0;
-        MsdStats st;
-        HIP_TRY(radix_sort_msd(rk0, rv0, rk1, rv1, rcols, n, vary, sc, s, &sorted, &vs, &failed,
-                               &st));
-        if (failed) return fail(SPX_ERR_DEVICE, "radix sort: a device-side list overflowed");
-        HIP_TRY(launch_rank_scatter(sorted, vs, n, eb, pbits, order, rank_of,
-                                    &rb_dev->totals[3], s));
-        SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
-    }
+    SPX_TRY(rank_by_counts(tmp, counts, first, last, n, eb, pbits, order, rank_of,
+                           &rb_dev->totals[3], s));
+    SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
     const int32_t nranked = (int32_t)rb.totals[3];
     const int rbits = std::max(CR_RB, ceil_log2_u64((uint64_t)std::max<int32_t>(nranked, 1)));
     const int64_t nseg = (int64_t)1 << (rbits - CR_RB);
@@ -597,16 +635,21 @@ static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* 
         return fail(SPX_ERR_RANGE, "CSBR: %lld x %lld blocks exceed the int32 block pointer range",
                     (long long)npan, (long long)nseg);
     keep(tmp, A, order);
+    keep(tmp, A, row_order);
+    keep(tmp, A, row_rank);
     A->cr_order = order;
     A->cr_nranked = nranked;
+    A->cr_row_order = row_order;
+    A->cr_row_rank = row_rank;
+    A->cr_nrows = nrows;
     A->log2_beta = CR_PB;
     A->nbr = npan;
     A->nbc = nseg;
-    // 3. sort by (panel, rank, row), sum repeats, populate
+    // 3. sort by (panel, column rank, row rank), sum repeats, populate
     SortedEntries se;
     if (E > 0)
         SPX_TRY(sort_and_dedup(tmp, coo, SPX_CSB_RANKED, 0, nseg, 0, o->sum_duplicates, s, &se,
-                               rank_of, rbits));
+                               rank_of, rbits, trank));
     A->sort = se.sort;
     const int64_t nnz = se.nnz_out;
     A->nnz = nnz;
@@ -652,15 +695,19 @@ static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* 
     SPX_TRY(tmp.get(&split, (size_t)std::max<int32_t>(A->cb_nsplit, 1), "split panels"));
     SPX_TRY(tmp.get(&partials, (size_t)std::max<int32_t>(A->cb_nslots, 1) << CR_PB,
                     "partial slices"));
+    double* yr;
     SPX_TRY(tmp.get(&xr, (size_t)std::max<int32_t>(nranked, 1), "ranked x"));
+    SPX_TRY(tmp.get(&yr, (size_t)std::max<int32_t>(nrows, 1), "ranked y"));
     keep(tmp, A, units);
     keep(tmp, A, split);
     keep(tmp, A, partials);
     keep(tmp, A, xr);
+    keep(tmp, A, yr);
     A->cb_units = units;
     A->cb_split = split;
     A->cb_partials = partials;
     A->cr_xr = xr;
+    A->cr_yr = yr;
     HIP_TRY(csbh_units(bp, npan, nseg, unit, unit_ptr, slot_ptr, split_ptr, units, split, s));
     if (A->cb_nunits > 1) {
         // a unit's run time grows with its entries: launching the largest first keeps one large
@@ -1209,6 +1256,11 @@ extern "C" spx_status spx_matrix_export(spx_matrix A, spx_array which, void* dst
             exists = A->fmt == SPX_CSB_RANKED;
             src = A->cr_order;
             len = (int64_t)A->cr_nranked * 4;
+            break;
+        case SPX_ARRAY_ROW_ORDER:
+            exists = A->fmt == SPX_CSB_RANKED;
+            src = A->cr_row_order;
+            len = (int64_t)A->cr_nrows * 4;
             break;
         case SPX_ARRAY_BLK_COORD:
             exists = bcoh;

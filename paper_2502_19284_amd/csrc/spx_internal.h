@@ -104,11 +104,16 @@ struct spx_matrix_s {
     int32_t* rs_chunk_ptr = nullptr;  // nlong+1
     int32_t rs_nlong = 0, rs_nchunks = 0;
     double* rs_partials = nullptr;    // nchunks
-    // CSBR: column of each rank, ranked x copy (per-product scratch); blk_ptr / packed / nbr
+    // CSBR: column of each column rank, ranked x copy (per-product scratch), rank of every row,
+    // row of each row rank, y in row-rank order (per-product scratch); blk_ptr / packed / nbr
     // (panels) / nbc (rank segments per panel) and the cb_ unit tables as for CSBH
-    int32_t* cr_order = nullptr;  // nranked
+    int32_t* cr_order = nullptr;      // nranked
     int32_t cr_nranked = 0;
-    double* cr_xr = nullptr;      // nranked
+    double* cr_xr = nullptr;          // nranked
+    int32_t* cr_row_rank = nullptr;   // m (ranks >= cr_nrows: rows without entries)
+    int32_t* cr_row_order = nullptr;  // nrows
+    int32_t cr_nrows = 0;
+    double* cr_yr = nullptr;          // nrows
     // CSBH partition
     int4* cb_units = nullptr;       // {block row, first entry, end entry, partial slot or -1}
     int32_t cb_nunits = 0;
@@ -302,22 +307,24 @@ static inline bool spx_is_bcoh(spx_format f) { return f == SPX_BCOHC || f == SPX
 static inline bool spx_is_crs(spx_format f) { return f == SPX_CSR_ROWSPLIT || f == SPX_CSR_MERGE; }
 
 // ------------------------------------------------------------------ CSBR conversion
-// keys (panel << (rbits + CR_PB)) | (rank_of[col] << CR_PB) | (row mod 2^CR_PB), index check
-hipError_t launch_keys_csbr(const int32_t* row, const int32_t* col, int64_t E, int32_t m,
+// keys (panel << (rbits + CR_PB)) | (rank_of[col] << CR_PB) | (row rank mod 2^CR_PB) with
+// panel = row rank >> CR_PB, from each triplet's row rank (rrank, E words) and column; index check
+hipError_t launch_keys_csbr(const int32_t* rrank, const int32_t* col, int64_t E, int32_t m,
                             int32_t n, const int32_t* rank_of, int rbits, uint64_t* keys,
                             uint32_t* err, unsigned long long* masks, hipStream_t s);
-// column ranking keys (2^eb - 1 - count) << 2pbits | first << pbits | last, with the column as
-// payload (cols[c] = c): in a stable ascending sort, decreasing count, then increasing first and
-// last panel, then increasing column.  count < 2^eb, panels < 2^pbits, eb + 2 pbits <= 64; the
-// panels of an uncounted column are taken as 0.
+// ranking keys ((2^eb - 1 - count) << 2 pbits | first << pbits | last) << ib | (index >> ishift),
+// with the index as payload (cols[c] = c): in a stable ascending sort, decreasing count, then
+// increasing first and last panel, then increasing index (its high bits in the key keep runs of
+// equal keys short).  count < 2^eb, panels < 2^pbits, eb + 2 pbits + ib <= 64; the panels of an
+// uncounted index are taken as 0, and so are all panels when first / last are NULL (pbits = 0).
 hipError_t launch_rank_keys(const uint32_t* counts, const uint32_t* first, const uint32_t* last,
-                            int32_t n, int eb, int pbits, uint64_t* keys, uint64_t* cols,
-                            hipStream_t s);
-// from the sorted ranking keys and columns: rank_of[c] for every column, order[i] = column of rank
-// i for the ranked (counted) columns, *nranked = their number (left untouched when no column is
-// counted)
+                            int32_t n, int eb, int pbits, int ib, int ishift, uint64_t* keys,
+                            uint64_t* cols, hipStream_t s);
+// from the sorted ranking keys and indices (count field above bit fshift): rank_of[c] for every
+// index, order[i] = index of rank i for the counted indices, *nranked = their number (left
+// untouched when nothing is counted)
 hipError_t launch_rank_scatter(const uint64_t* sorted, const uint64_t* cols, int32_t n, int eb,
-                               int pbits, int32_t* order, int32_t* rank_of, uint32_t* nranked,
+                               int fshift, int32_t* order, int32_t* rank_of, uint32_t* nranked,
                                hipStream_t s);
 
 // ------------------------------------------------------------------ BCOHC / BCOHCH
@@ -328,8 +335,9 @@ hipError_t launch_rank_scatter(const uint64_t* sorted, const uint64_t* cols, int
 // bcoh_row_bucket_bits(m) (-1: more than 2^26 rows, beyond what a 64-bit BCOH key can hold).
 // hist: bcoh_rows_hist_elems words, rows_out: E words, total: one word, counts: m + 1 zeroed
 // words.  With lo / hi (m words each, filled with 0xFFFFFFFF / 0 beforehand) also the least and
-// greatest col >> aux_shift of every row (rows without entries keep the fill); that value must
-// fit 32 - wbits bits, and rowc_extent_prepare_kernel() must have run on the device first.
+// greatest aux = map[col] >> aux_shift (map NULL: col >> aux_shift) of every row (rows without
+// entries keep the fill); aux must fit 32 - wbits bits, and rowc_extent_prepare_kernel() must
+// have run on the device first.  aux_keep (E words, nullable; with a map) receives map[col[i]].
 int bcoh_row_bucket_bits(int32_t m);
 size_t bcoh_rows_hist_elems(int32_t m, int64_t E, int wbits);
 hipError_t rowc_extent_prepare_kernel();
@@ -338,7 +346,8 @@ hipError_t launch_bcoh_rows_bucketed(const int32_t* row, const int32_t* col, int
                                      int32_t* rows_out, uint32_t* tile_sums, uint32_t* total,
                                      uint32_t* counts, uint32_t* err, hipStream_t s,
                                      int aux_shift = 0, uint32_t* lo = nullptr,
-                                     uint32_t* hi = nullptr);
+                                     uint32_t* hi = nullptr, const int32_t* aux_map = nullptr,
+                                     int32_t* aux_keep = nullptr);
 
 // partitions from the exclusive row-count scan cum[0..m): part_of[r] for every row, part_row[p]
 // for every partition (part_row[P] = m written by the caller); *total = P

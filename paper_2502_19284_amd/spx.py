@@ -26,7 +26,8 @@ VALUE_TYPES = {"f64": 0, "f32": 1, "bf16": 2}
 VALUE_TORCH = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}
 ARRAYS = {"row_ptr": (0, torch.int32), "col_ind": (1, torch.int32), "values": (2, torch.float64),
           "blk_ptr": (3, torch.int32), "packed": (4, torch.int32), "parts": (5, torch.int32),
-          "blk_coord": (6, torch.int32), "col_order": (7, torch.int32)}
+          "blk_coord": (6, torch.int32), "col_order": (7, torch.int32),
+          "row_order": (8, torch.int32)}
 
 
 class SpxError(RuntimeError):

@@ -75,7 +75,7 @@ def _check_structure(A, m, n, row, col, val):
         formats.check_csbr(m, n, row, col, A.export("blk_ptr").cpu().numpy(),
                            A.export("packed").cpu().numpy().view(np.uint32),
                            A.export("values").cpu().numpy(), A.export("col_order").cpu().numpy(),
-                           cr, cc, cv)
+                           A.export("row_order").cpu().numpy(), cr, cc, cv)
     elif A.format in ("csbh", "csb"):
         formats.check_csb(m, n, A.log2_beta, A.export("blk_ptr").cpu().numpy(),
                           A.export("packed").cpu().numpy().view(np.uint32),
@@ -267,8 +267,8 @@ def test_csbh_block_sizes_and_split_rows(spx, log2_beta, unit, fmt):
 @pytest.mark.parametrize("kind", ["int", "float"])
 def test_csbr_segments_and_split_panels(spx, unit, kind):
     # more than 2^19 ranked columns (several rank segments per panel), panels split into many
-    # units with partial slices (small tile_items), a row count that is not a multiple of the
-    # panel height, long rows and a very frequent column
+    # units with partial slices (small tile_items), a ranked-row count that is not a multiple of
+    # the panel height, long rows, empty rows and a very frequent column
     rng = np.random.default_rng(61)
     m, n, E = 20_011, (1 << 21) + 3, 2_000_000
     row = rng.integers(0, m, E)
@@ -276,6 +276,7 @@ def test_csbr_segments_and_split_panels(spx, unit, kind):
     row[:30_000] = 16383          # a long row at a panel edge
     col[30_000:90_000] = 12345    # one very frequent column
     row[90_000:95_000] = m - 1
+    row[row % 97 == 5] = 0        # rows without triplets
     perm = rng.permutation(E)
     row, col = row[perm].astype(np.int32), col[perm].astype(np.int32)
     val = synth.values(E, seed=62, kind=kind)
@@ -287,7 +288,7 @@ def test_csbr_segments_and_split_panels(spx, unit, kind):
     pb, rb = formats.CSBR_PB, formats.CSBR_RB
     rbits = max(rb, (nranked - 1).bit_length())
     assert rbits >= rb + 2                      # at least 4 rank segments per panel
-    npan = (m + (1 << pb) - 1) >> pb
+    npan = (len(np.unique(row)) + (1 << pb) - 1) >> pb
     assert A.export("blk_ptr").numel() == npan * (1 << (rbits - rb)) + 1
     if kind == "int":
         _check_int(y, ref, "csbr int unit %d" % unit)

@@ -690,29 +690,32 @@ def test_check_csb_zmorton_hand_made():
 def test_csbr_check_hand_made():
     # panels of 2 rows (pb = 1) and blocks of 2 ranks (rb = 1), written out by hand.
     # raw triplets (row, col, value): (0,2,1) (0,2,2) (1,0,4) (2,2,5) (2,3,6) (1,2,7) (0,3,8)
+    # raw row counts 3, 2, 2: row ranking 0, 1, 2 (the tie by increasing row)
     # raw column counts: col 0 -> 1, col 1 -> 0, col 2 -> 4, col 3 -> 2, so the ranking is
     # col 2, col 3, col 0 (col 1 has no triplet); 3 ranks -> rank field of 2 bits -> 2 segments.
+    raw_rows = [0, 0, 1, 2, 2, 1, 0]
     raw_cols = [2, 2, 0, 2, 3, 2, 3]
     canon = ([0, 0, 1, 1, 2, 2], [2, 3, 0, 2, 2, 3], [3.0, 8.0, 4.0, 7.0, 5.0, 6.0])
     order = [2, 3, 0]
+    rows = [0, 1, 2]
     # panel 0 (rows 0-1), segment 0 (ranks 0-1): (0,2) (1,2) (0,3); segment 1: (1,0)
     # panel 1 (row 2), segment 0: (2,2) (2,3); segment 1: empty
     blk_ptr = [0, 3, 4, 6, 6]
-    packed = [0, 1, 2, 1, 0, 2]    # (rank mod 2) << 1 | (row mod 2)
+    packed = [0, 1, 2, 1, 0, 2]    # (rank mod 2) << 1 | (row rank mod 2)
     vals = [3.0, 7.0, 8.0, 4.0, 5.0, 6.0]
-    raw_rows = [0, 0, 1, 2, 2, 1, 0]
-    assert formats.csbr_col_order(4, raw_rows, raw_cols, pb=1).tolist() == order
-    r, c, panel, rank = formats.decode_csbr(3, blk_ptr, packed, order, pb=1, rb=1)
+    assert formats.csbr_row_order(3, raw_rows).tolist() == rows
+    assert formats.csbr_col_order(3, 4, raw_rows, raw_cols, pb=1).tolist() == order
+    r, c, panel, crank, rrank = formats.decode_csbr(rows, blk_ptr, packed, order, pb=1, rb=1)
     assert r.tolist() == [0, 1, 0, 1, 2, 2] and c.tolist() == [2, 2, 3, 0, 2, 3]
-    assert rank.tolist() == [0, 0, 1, 2, 0, 1]
+    assert crank.tolist() == [0, 0, 1, 2, 0, 1]
     ok = dict(m=3, n=4, raw_rows=raw_rows, raw_cols=raw_cols, blk_ptr=blk_ptr, packed=packed,
-              val=vals,
-              col_order=order, canon_row=canon[0], canon_col=canon[1], canon_val=canon[2],
-              pb=1, rb=1)
+              val=vals, col_order=order, row_order=rows, canon_row=canon[0], canon_col=canon[1],
+              canon_val=canon[2], pb=1, rb=1)
     formats.check_csbr(**ok)
     bad = [dict(packed=[1, 0, 2, 1, 0, 2], val=[7.0, 3.0, 8.0, 4.0, 5.0, 6.0]),  # rows swapped
            dict(col_order=[3, 2, 0]),                                         # ranking
            dict(col_order=[2, 3, 0, 1]),                                      # untouched column
+           dict(row_order=[1, 0, 2]),                                         # row ranking
            dict(blk_ptr=[0, 4, 4, 6, 6]),                                     # segment boundary
            dict(blk_ptr=[0, 3, 4, 6]),                                        # segment count
            dict(val=[3.0, 7.0, 8.0, 4.0, 5.0, np.nextafter(6.0, 9.0)])]       # one value 1 ulp off
@@ -721,9 +724,41 @@ def test_csbr_check_hand_made():
             formats.check_csbr(**dict(ok, **b))
 
 
+def test_csbr_ranked_rows_hand_made():
+    # rows reordered by the ranking (pb = 1, rb = 1), written out by hand.
+    # raw triplets (row, col, value): (3,0,1) (3,1,2) (3,2,3) (1,1,4) (0,2,5) (0,0,6)
+    # row counts: row 3 -> 3, row 0 -> 2, row 1 -> 1, row 2 -> 0: row ranking 3, 0, 1 (row 2 has
+    # no rank); panel 0 = row ranks 0-1 (rows 3, 0), panel 1 = row rank 2 (row 1).
+    # column counts all 2; first/last panel: col 0 (0,0), col 1 (0,1), col 2 (0,0) -> column
+    # ranking 0, 2, 1.  (panel, column rank, row rank) of each triplet, in storage order:
+    # (0,0,0)=1 (0,0,1)=6 (0,1,0)=3 (0,1,1)=5 | (0,2,0)=2 | panel 1 segment 0 empty | (1,2,2)=4
+    raw_rows = [3, 3, 3, 1, 0, 0]
+    raw_cols = [0, 1, 2, 1, 2, 0]
+    rows, order = [3, 0, 1], [0, 2, 1]
+    assert formats.csbr_row_order(4, raw_rows).tolist() == rows
+    assert formats.csbr_col_order(4, 3, raw_rows, raw_cols, pb=1).tolist() == order
+    blk_ptr = [0, 4, 5, 5, 6]
+    packed = [0, 1, 2, 3, 0, 0]
+    vals = [1.0, 6.0, 3.0, 5.0, 2.0, 4.0]
+    canon = ([0, 0, 1, 3, 3, 3], [0, 2, 1, 0, 1, 2], [6.0, 5.0, 4.0, 1.0, 2.0, 3.0])
+    ok = dict(m=4, n=3, raw_rows=raw_rows, raw_cols=raw_cols, blk_ptr=blk_ptr, packed=packed,
+              val=vals, col_order=order, row_order=rows, canon_row=canon[0], canon_col=canon[1],
+              canon_val=canon[2], pb=1, rb=1)
+    formats.check_csbr(**ok)
+    r, c, _, _, _ = formats.decode_csbr(rows, blk_ptr, packed, order, pb=1, rb=1)
+    y = np.zeros(4)
+    np.add.at(y, r, np.asarray(vals) * np.array([1.0, 10.0, 100.0])[c])
+    assert y.tolist() == [506.0, 40.0, 0.0, 321.0]
+    for b in (dict(row_order=[3, 1, 0]), dict(col_order=[0, 1, 2]),
+              dict(blk_ptr=[0, 4, 4, 5, 6])):
+        with pytest.raises(AssertionError):
+            formats.check_csbr(**dict(ok, **b))
+
+
 def test_csbr_ranking_ties_and_empty():
-    # panels of 2 rows (pb = 1).  Columns 0, 1, 3, 5 have two triplets each, column 4 one,
-    # column 2 none:
+    # panels of 2 rows (pb = 1).  Rows 0-6 hold 2, 2, 1, 1, 1, 1, 1 triplets, so the row ranking
+    # is 0, 1, 2, 3, 4, 5, 6 (the identity) and a row's panel is row >> 1.
+    # Columns 0, 1, 3, 5 have two triplets each, column 4 one, column 2 none:
     #   col 5: rows 4, 0 -> panels 2, 0 (first 0, last 2)
     #   col 1: rows 1, 5 -> panels 0, 2 (first 0, last 2; ties col 5, lower column first)
     #   col 3: rows 2, 3 -> panels 1, 1
@@ -731,26 +766,34 @@ def test_csbr_ranking_ties_and_empty():
     # ranking: count 2 by (first, last, column): 0 (0,0), 1 (0,2), 5 (0,2), 3 (1,1); then 4.
     rows = [4, 0, 1, 5, 2, 3, 0, 1, 6]
     cols = [5, 5, 1, 1, 3, 3, 0, 0, 4]
-    assert formats.csbr_col_order(6, rows, cols, pb=1).tolist() == [0, 1, 5, 3, 4]
+    assert formats.csbr_row_order(7, rows).tolist() == [0, 1, 2, 3, 4, 5, 6]
+    assert formats.csbr_col_order(7, 6, rows, cols, pb=1).tolist() == [0, 1, 5, 3, 4]
     # one panel for all rows: equal counts fall back to increasing column order
-    assert formats.csbr_col_order(6, rows, cols, pb=3).tolist() == [0, 1, 3, 5, 4]
-    assert formats.csbr_col_order(3, [], []).tolist() == []
+    assert formats.csbr_col_order(7, 6, rows, cols, pb=3).tolist() == [0, 1, 3, 5, 4]
+    assert formats.csbr_col_order(3, 3, [], []).tolist() == []
+    assert formats.csbr_row_order(3, []).tolist() == []
 
 
 def test_csbr_ranking_brute_force():
-    # tiny random cases against the rule applied column by column in plain Python
+    # tiny random cases against both rules applied row by row and column by column in plain
+    # Python
     rng = np.random.default_rng(11)
     for _ in range(200):
-        n, E, pb = int(rng.integers(1, 12)), int(rng.integers(0, 40)), int(rng.integers(0, 3))
-        rows = rng.integers(0, 16, E).tolist()
+        m, n = int(rng.integers(1, 16)), int(rng.integers(1, 12))
+        E, pb = int(rng.integers(0, 40)), int(rng.integers(0, 3))
+        rows = rng.integers(0, m, E).tolist()
         cols = rng.integers(0, n, E).tolist()
+        rk = sorted((-rows.count(r), r) for r in range(m) if rows.count(r) > 0)
+        want_rows = [r for _, r in rk]
+        assert formats.csbr_row_order(m, rows).tolist() == want_rows
+        rank_of = {r: i for i, r in enumerate(want_rows)}
         keyed = []
         for c in range(n):
-            mine = [r >> pb for r, cc in zip(rows, cols) if cc == c]
+            mine = [rank_of[r] >> pb for r, cc in zip(rows, cols) if cc == c]
             if mine:
                 keyed.append(((-len(mine), min(mine), max(mine), c), c))
         want = [c for _, c in sorted(keyed)]
-        assert formats.csbr_col_order(n, rows, cols, pb=pb).tolist() == want
+        assert formats.csbr_col_order(m, n, rows, cols, pb=pb).tolist() == want
 
 
 def test_parcrs_equals_algorithm1_bitwise():
