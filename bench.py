@@ -715,6 +715,72 @@ def load_traffic(kernels):
     return int(tot)
 
 
+def line_model(name):
+    """Modelled 128-byte lines of x per product (16 doubles per line) on a workload, on the CPU:
+    the floor each layout's order sets, used to choose the layouts (no GPU, no oracle).
+
+    * CRS: distinct x lines among every 64 consecutive entries (one wave's gathers).
+    * CSBH (beta = 2^13): distinct (block, x line) pairs - each block's lines fetched once - and
+      the lines if blocks with at least T entries staged their whole 512-line x window in LDS.
+    * CSBR: lines of the columns beyond the 2^18 most frequent ranks, counted once per (panel,
+      line) - the frequent ones stay in L2 - for rows as given or ranked by count, columns
+      ranked by count alone or by (count, first panel, last panel); and the lines the ranked
+      copy of x gathers (distinct x lines among 64 consecutive ranks)."""
+    import numpy as np
+
+    import synth
+    w = synth.workload(name, seed=0)
+    m, n = w["m"], w["n"]
+    key = np.unique((w["row"].astype(np.int64) << 32) | w["col"].astype(np.int64))
+    del w
+    r, c = key >> 32, key & 0xFFFFFFFF
+    del key
+    out = {"workload": name, "nnz": int(len(r))}
+    out["crs_wave_lines_M"] = round(len(np.unique(((np.arange(len(r)) >> 6) << 32) |
+                                                  (c >> 4))) / 1e6, 1)
+    k = 13
+    nbc = (n + (1 << k) - 1) >> k
+    blk = (r >> k) * nbc + (c >> k)
+    cnt_b = np.bincount(blk)
+    pairs = np.unique((blk << 9) | ((c & ((1 << k) - 1)) >> 4))
+    lines_b = np.bincount(pairs >> 9, minlength=len(cnt_b))
+    out["csbh_block_lines_M"] = round(len(pairs) / 1e6, 1)
+    out["csbh_staged"] = {}
+    for T in (512, 2048, 8192):
+        d = cnt_b >= T
+        out["csbh_staged"][T] = {"entries_pct": round(100 * cnt_b[d].sum() / len(r), 1),
+                                 "lines_gathered_M": round(lines_b[d].sum() / 1e6, 2),
+                                 "lines_staged_M": round(int(d.sum()) * 512 / 1e6, 2)}
+    del blk, pairs
+    cnt = np.bincount(c, minlength=n)
+    rcnt = np.bincount(r, minlength=m)
+    order = np.lexsort((np.arange(m), -rcnt))
+    ranked_rows = np.empty(m, np.int64)
+    ranked_rows[order] = np.arange(m)
+    H, PB = 1 << 18, 14
+    out["csbr"] = {}
+    for rows_name, rowmap in (("rows as given", None), ("rows ranked", ranked_rows)):
+        panel = (r if rowmap is None else rowmap[r]) >> PB
+        first = np.full(n, 1 << 40, np.int64)
+        last = np.full(n, -1, np.int64)
+        np.minimum.at(first, c, panel)
+        np.maximum.at(last, c, panel)
+        for cols_name, keys in (("count", (np.arange(n), -cnt)),
+                                ("count, first, last", (np.arange(n), last, first, -cnt))):
+            oc = np.lexsort(keys)
+            rank = np.empty(n, np.int64)
+            rank[oc] = np.arange(n)
+            rk = rank[c]
+            cold = rk >= H
+            cold_lines = len(np.unique((panel[cold] << 32) | (rk[cold] >> 4)))
+            nr = int((cnt > 0).sum())
+            xr_lines = len(np.unique(((np.arange(nr) >> 6) << 32) | (oc[:nr] >> 4)))
+            out["csbr"]["%s; columns by %s" % (rows_name, cols_name)] = {
+                "cold_lines_M": round(cold_lines / 1e6, 1), "x_r_gather_lines_M":
+                round(xr_lines / 1e6, 1)}
+    return out
+
+
 def timed_products(spx, torch, A, x, y, reps):
     """Steady-state product of a resident matrix: times, per-kernel statistics and the roofline
     of all the product's kernels against the bytes model."""
@@ -745,6 +811,9 @@ def main():
     ap.add_argument("--summarize-rocprof", metavar="DIR",
                     help="print a markdown summary of rocprofv3 CSV output in DIR and write "
                          "profiles/traffic_rmat24.json, then exit")
+    ap.add_argument("--line-model", metavar="WORKLOAD",
+                    help="print the modelled x lines per product of each layout on WORKLOAD "
+                         "(CPU only, minutes; about 20 GB of host memory at scale 24), then exit")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=550, help="timed products of the step")
     ap.add_argument("--warmup", type=int, default=10)
@@ -776,6 +845,9 @@ def main():
         with open(os.path.join(ROOT, "profiles", "traffic_rmat24.json"), "w") as f:
             json.dump(tj, f, indent=1, sort_keys=True)
         print(md)
+        return
+    if args.line_model:
+        print(json.dumps(line_model(args.line_model), indent=1))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported (the multi-GPU "
