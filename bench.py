@@ -290,15 +290,15 @@ def product_kernels(ks):
 
 
 def precision_leg(spx, torch, args, row_d, col_d, val_d, x_d, m, n, n_touched, copy_gbs, rows):
-    """FP32 and bfloat16 stored values (FP32 x, y) in the CRS formats: steady-state product and
-    its roofline; the results on the sampled rows are kept for the error against the FP64 oracle
-    (computed in the host leg, where the oracle runs)."""
+    """FP32 and bfloat16 stored values (FP32 x, y) in the CRS formats and CSBR: steady-state
+    product and its roofline; the results on the sampled rows are kept for the error against the
+    FP64 oracle (computed in the host leg, where the oracle runs)."""
     x32 = x_d.float()
     y32 = torch.empty(m, dtype=torch.float32, device="cuda")
     rows_d = torch.from_numpy(rows).cuda()
     out, results = {}, {}
     for vt, vb in (("f32", 4), ("bf16", 2)):
-        for f in ("rowsplit", "merge"):
+        for f in ("rowsplit", "merge", "csbr"):
             A = spx.convert(row_d, col_d, val_d, (m, n), f, value_type=vt)
             ms, ks = time_products(spx, torch, A, x32, y32, args.spmv_reps)
             results["%s_%s" % (f, vt)] = y32[rows_d].double().cpu().numpy()

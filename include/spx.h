@@ -82,7 +82,8 @@ typedef int32_t spx_format;
  * rows gathers the longest rows into the first panels, and the panel tie-break puts rare columns
  * that meet the same panels next to each other: both cut the x_r lines a product fetches.  The
  * panels' slices form y in row-rank order, which a last pass permutes into y.
- * Rows and columns are limited to 2^26 (their counts are bucketed in LDS), FP64 values only. */
+ * Rows and columns are limited to 2^26 (their counts are bucketed in LDS).  Values FP64, or FP32
+ * / bfloat16 (products FP32, every sum FP64: the slice, the partial slices and their reduction). */
 #define SPX_CSB_RANKED 6
 
 typedef int32_t spx_dtype;
@@ -119,7 +120,8 @@ typedef struct {
                              * compact copy of their x values per product (x_hot); -1 = automatic
                              * (up to 2^19 when n >= 2^19), 0 = off.  y is unchanged by it.      */
     spx_dtype value_type;   /* stored value type: SPX_F64 (default), or SPX_F32 / SPX_BF16 for
-                             * the CRS formats (repeats are summed in FP64, then rounded once)   */
+                             * the CRS formats and CSBR (repeats are summed in FP64, then rounded
+                             * once)                                                           */
 } spx_convert_opts;
 
 typedef struct {
@@ -193,10 +195,10 @@ spx_status spx_convert_opts_default(spx_convert_opts* opts);
  * rep:  host, may be NULL.  convert_ms covers all device work of the call.
  * The call returns after the device work is complete (it reads back the entry count).
  * Errors: INVALID_ARG, RANGE (m, n or nnz beyond int32, a CSB / BCOHC key beyond 64 bits, or
- * more than 2^26 columns for CSBR),
- * INDEX (an index out of range; indices are always checked), UNSUPPORTED (reduced-precision values
- * for the block formats; sum_duplicates=0 for BCOHC / BCOHCH), NOMEM, HIP, DEVICE (a device-side
- * list of the sort outgrew its bound; not expected).  On error every temporary is freed.
+ * more than 2^26 rows or columns for CSBR), INDEX (an index out of range; indices are always
+ * checked), UNSUPPORTED (reduced-precision values for CSB, CSBH, BCOHC, BCOHCH; sum_duplicates=0
+ * for BCOHC / BCOHCH), NOMEM, HIP, DEVICE (a device-side list of the sort outgrew its bound; not
+ * expected).  On error every temporary is freed.
  */
 spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt, const spx_convert_opts* opts,
                        void* stream, spx_matrix* out, spx_convert_report* rep);
@@ -213,9 +215,10 @@ spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt, const spx_conver
 spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* stream);
 
 /*
- * Reduced-precision product y = A x for a CRS matrix stored in FP32 or bfloat16 (value_type at
- * conversion): x (n floats) and y (m floats) are device FP32; products and sums inside a merge
- * tile or row block are FP32, sums that cross tiles and rows longer than a row block are FP64.
+ * Reduced-precision product y = A x for a CRS or CSBR matrix stored in FP32 or bfloat16
+ * (value_type at conversion): x (n floats) and y (m floats) are device FP32.  CRS: products and
+ * sums inside a merge tile or row block are FP32, sums that cross tiles and rows longer than a
+ * row block are FP64.  CSBR: products FP32, every sum FP64; y rounded to FP32 once.
  * Otherwise as spx_spmv.  Errors: UNSUPPORTED for an FP64 matrix (use spx_spmv), and spx_spmv
  * returns UNSUPPORTED for a reduced-precision matrix.
  */

@@ -18,6 +18,10 @@ __device__ __forceinline__ float vget(const float* p) { return ntload(p); }
 __device__ __forceinline__ float vget(const uint16_t* p) {  // bfloat16: the upper half of a float
     return __uint_as_float((uint32_t)ntload(p) << 16);
 }
+// a stored value already loaded -> arithmetic type (lets a kernel issue all its loads first)
+__device__ __forceinline__ double vdec(double v) { return v; }
+__device__ __forceinline__ float vdec(float v) { return v; }
+__device__ __forceinline__ float vdec(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
 __device__ __forceinline__ double vget_plain(const double* p) { return *p; }
 __device__ __forceinline__ float vget_plain(const float* p) { return *p; }
 __device__ __forceinline__ float vget_plain(const uint16_t* p) {

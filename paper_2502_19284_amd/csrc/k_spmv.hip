@@ -1,17 +1,10 @@
-// k_spmv.hip -- y = A x for the compressed-sparse-block formats CSB and CSBH (gfx950, FP64
-// values, int32 indices).  The CRS kernels are in k_spmv_crs.hip.
+// k_spmv.hip -- y = A x for the compressed-sparse-block formats CSB, CSBH (FP64 values) and
+// CSBR (FP64, FP32 or bfloat16 values), int32 indices, gfx950.  The CRS kernels are in
+// k_spmv_crs.hip.  Matrix streams are read with non-temporal loads (ntload, dev_values.h), so
+// that they do not displace x from L2.
 #include "dev_common.h"
+#include "dev_values.h"
 #include "spx_internal.h"
-
-// Streamed once per product: non-temporal loads/stores keep them from displacing x in L2.
-template <typename T>
-__device__ __forceinline__ T ntload(const T* p) {
-    return __builtin_nontemporal_load(p);
-}
-template <typename T>
-__device__ __forceinline__ void ntstore(T* p, T v) {
-    __builtin_nontemporal_store(v, p);
-}
 
 // ================================================================== CSBH (Sections 3.1, 4.1)
 //
@@ -167,9 +160,11 @@ hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStrea
 // ================================================================== CSBR (Section 3.1 blocks over
 // ranked rows and columns)
 //
-// x_r[i] = x[order[i]]: the ranked copy of x that the product reads.
+// x_r[i] = x[order[i]]: the ranked copy of x that the product reads (FP64, or FP32 for the
+// reduced-precision forms).
+template <typename X>
 __global__ void k_csbr_xrank(const int32_t* __restrict__ order, int32_t nr,
-                             const double* __restrict__ x, double* __restrict__ xr) {
+                             const X* __restrict__ x, X* __restrict__ xr) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nr) xr[i] = x[order[i]];
 }
@@ -181,11 +176,15 @@ __global__ void k_csbr_xrank(const int32_t* __restrict__ order, int32_t nr,
 // panel.  An entry's column rank is its block's segment (found from the panel's block starts)
 // times 2^CR_RB plus the packed rank field.  Products are added into the slice with LDS float
 // atomics; a unit covering its whole panel writes the slice to y_r, otherwise to its partial
-// slot, reduced in slot order afterwards.
+// slot, reduced in slot order afterwards.  V / X: stored value and vector types (double /
+// double, or float or bfloat16 bits / float); a product is formed in the value's arithmetic type
+// (FP64, or FP32 for the reduced forms) and every sum is FP64 (the slice, the partial slices and
+// their reduction).
+template <typename V, typename X, int IPT, bool SERIAL>
 __global__ __launch_bounds__(CR_NT) void k_spmv_csbr(const int32_t* __restrict__ blk_ptr,
                                                      const uint32_t* __restrict__ packed,
-                                                     const double* __restrict__ val,
-                                                     const double* __restrict__ xr,
+                                                     const V* __restrict__ val,
+                                                     const X* __restrict__ xr,
                                                      double* __restrict__ yr,
                                                      double* __restrict__ partials,
                                                      const int4* __restrict__ units,
@@ -217,29 +216,53 @@ __global__ __launch_bounds__(CR_NT) void k_spmv_csbr(const int32_t* __restrict__
         sg = lo;
     }
     int next = sg + 1 < nseg ? seg[sg + 1] : INT32_MAX;
-    for (int base = k0; base < k1; base += CR_NT * CR_IPT) {
-        uint32_t p[CR_IPT];
-        double v[CR_IPT];
+    using T = decltype(vget(val));  // arithmetic type of a product
+    for (int base = k0; base < k1; base += CR_NT * IPT) {
+        // the matrix loads of a round are issued before any is used, without branches: entries
+        // past k1 read entry k1 - 1 again (base < k1) and their products are dropped
+        int kc[IPT];
 #pragma unroll
-        for (int q = 0; q < CR_IPT; ++q) {
-            const int k = base + q * CR_NT + tid;
-            p[q] = k < k1 ? ntload(packed + k) : 0u;
-            v[q] = k < k1 ? ntload(val + k) : 0.0;
+        for (int q = 0; q < IPT; ++q) kc[q] = min(base + q * CR_NT + tid, k1 - 1);
+        uint32_t p[IPT];
+        V raw[IPT];
+#pragma unroll
+        for (int q = 0; q < IPT; ++q) {
+            p[q] = ntload(packed + kc[q]);
+            raw[q] = ntload(val + kc[q]);
         }
-        double xv[CR_IPT];
+        T xv[IPT];
+        if constexpr (SERIAL) {
+            // one x gather in flight per thread: each waits for the previous (the branch on the
+            // entry's range orders them)
 #pragma unroll
-        for (int q = 0; q < CR_IPT; ++q) {
-            const int k = base + q * CR_NT + tid;
-            while (k >= next) {  // entries ascend per thread: walk the segments forward
-                ++sg;
-                next = sg + 1 < nseg ? seg[sg + 1] : INT32_MAX;
+            for (int q = 0; q < IPT; ++q) {
+                while (kc[q] >= next) {  // entries ascend per thread: walk the segments forward
+                    ++sg;
+                    next = sg + 1 < nseg ? seg[sg + 1] : INT32_MAX;
+                }
+                xv[q] = base + q * CR_NT + tid < k1
+                            ? (T)xr[((int64_t)sg << CR_RB) + (p[q] >> CR_PB)]
+                            : (T)0;
             }
-            xv[q] = k < k1 ? xr[((int64_t)sg << CR_RB) + (p[q] >> CR_PB)] : 0.0;
+        } else {
+            // all the round's x gathers in flight together
+            int sq[IPT];
+#pragma unroll
+            for (int q = 0; q < IPT; ++q) {
+                while (kc[q] >= next) {
+                    ++sg;
+                    next = sg + 1 < nseg ? seg[sg + 1] : INT32_MAX;
+                }
+                sq[q] = sg;
+            }
+#pragma unroll
+            for (int q = 0; q < IPT; ++q)
+                xv[q] = (T)xr[((int64_t)sq[q] << CR_RB) + (p[q] >> CR_PB)];
         }
 #pragma unroll
-        for (int q = 0; q < CR_IPT; ++q) {
-            const int k = base + q * CR_NT + tid;
-            if (k < k1) atomicAdd(&s_y[p[q] & lmask], v[q] * xv[q]);
+        for (int q = 0; q < IPT; ++q) {
+            if (base + q * CR_NT + tid < k1)
+                atomicAdd(&s_y[p[q] & lmask], (double)(vdec(raw[q]) * xv[q]));
         }
     }
     __syncthreads();
@@ -256,40 +279,91 @@ __global__ __launch_bounds__(CR_NT) void k_spmv_csbr(const int32_t* __restrict__
 static constexpr size_t kCsbrLds =
     ((size_t)1 << CR_PB) * sizeof(double) + CR_SEG_LDS * sizeof(int32_t);
 
-// Raises the product kernel's dynamic LDS limit on the current device (called at conversion, so
+// Raises the product kernels' dynamic LDS limit on the current device (called at conversion, so
 // that products, which may be captured in a graph, make no attribute calls).
+// Rounds per thread and gather order by value type, measured at R-MAT scale 24 (product kernel,
+// ms, rounds of 2 / 4 / 8 entries, all gathers of a round together): FP64 0.89 / 0.86 / 0.84 and
+// 0.79 with 4 entries and one gather at a time; FP32 0.82 / 0.61 / 0.56; bfloat16 0.71 / 0.53 /
+// 0.48.  With FP64 x_r (16 values per line) more gathers in flight fetch more lines.
+#ifndef CSBR_F64_IPT
+#define CSBR_F64_IPT 4
+#endif
+#ifndef CSBR_F64_SERIAL
+#define CSBR_F64_SERIAL true
+#endif
+#ifndef CSBR_LP_IPT
+#define CSBR_LP_IPT 8
+#endif
+template <typename V>
+struct CsbrShape {
+    static constexpr int ipt = CSBR_LP_IPT;
+    static constexpr bool serial = false;
+};
+template <>
+struct CsbrShape<double> {
+    static constexpr int ipt = CSBR_F64_IPT;
+    static constexpr bool serial = CSBR_F64_SERIAL;
+};
+template <typename V, typename X>
+static const void* csbr_kernel() {
+    return (const void*)k_spmv_csbr<V, X, CsbrShape<V>::ipt, CsbrShape<V>::serial>;
+}
+
+template <typename V, typename X>
+static hipError_t csbr_prepare_one() {
+    return hipFuncSetAttribute(csbr_kernel<V, X>(), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kCsbrLds);
+}
+
 hipError_t csbr_prepare_kernel() {
     if (kCsbrLds <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute((const void*)k_spmv_csbr,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCsbrLds);
+    hipError_t e = csbr_prepare_one<double, double>();
+    if (e == hipSuccess) e = csbr_prepare_one<float, float>();
+    if (e == hipSuccess) e = csbr_prepare_one<uint16_t, float>();
+    return e;
 }
 
 // y[r] = y_r[row_rank[r]]; rows without entries (rank >= nrows) get 0.
+template <typename X>
 __global__ void k_csbr_yperm(const int32_t* __restrict__ row_rank, int32_t m, int32_t nrows,
-                             const double* __restrict__ yr, double* __restrict__ y) {
+                             const double* __restrict__ yr, X* __restrict__ y) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= m) return;
     const int32_t rr = ntload(row_rank + r);
-    ntstore(y + r, rr < nrows ? yr[rr] : 0.0);
+    ntstore(y + r, (X)(rr < nrows ? yr[rr] : 0.0));
 }
 
-hipError_t spmv_csbr(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
+template <typename V, typename X>
+static hipError_t csbr_run(const spx_matrix_s* A, const V* val, const X* x, X* y,
+                           hipStream_t s) {
     constexpr size_t lds = kCsbrLds;
+    X* xr = (X*)A->cr_xr;  // sized for FP64, so it holds either type
     if (A->cr_nranked > 0)
-        SPX_LAUNCH("csbr_xrank", k_csbr_xrank, dim3(spx_div_up(A->cr_nranked, 256)), dim3(256), 0,
-                   s, A->cr_order, A->cr_nranked, x, A->cr_xr);
-    if (A->cb_nunits > 0) {
-        SPX_LAUNCH("spmv_csbr", k_spmv_csbr, dim3(A->cb_nunits), dim3(CR_NT), lds, s, A->blk_ptr,
-                   A->packed, A->val, A->cr_xr, A->cr_yr, A->cb_partials, A->cb_units,
-                   (int32_t)A->nbc, A->cr_nrows);
-    }
+        SPX_LAUNCH("csbr_xrank", k_csbr_xrank<X>, dim3(spx_div_up(A->cr_nranked, 256)),
+                   dim3(256), 0, s, A->cr_order, A->cr_nranked, x, xr);
+    if (A->cb_nunits > 0)
+        SPX_LAUNCH("spmv_csbr",
+                   (k_spmv_csbr<V, X, CsbrShape<V>::ipt, CsbrShape<V>::serial>),
+                   dim3(A->cb_nunits), dim3(CR_NT), lds, s,
+                   A->blk_ptr, A->packed, val, (const X*)xr, A->cr_yr, A->cb_partials,
+                   A->cb_units, (int32_t)A->nbc, A->cr_nrows);
     if (A->cb_nsplit > 0)
         SPX_LAUNCH("spmv_csbr_reduce", k_spmv_csbr_reduce,
                    dim3(A->cb_nsplit * (((1 << CR_PB) + CB_RED_NT - 1) / CB_RED_NT)),
                    dim3(CB_RED_NT), 0, s, A->cb_split, A->cb_partials, A->cr_yr, CR_PB,
                    A->cr_nrows);
     if (A->m > 0)
-        SPX_LAUNCH("csbr_yperm", k_csbr_yperm, dim3(spx_div_up(A->m, 256)), dim3(256), 0, s,
+        SPX_LAUNCH("csbr_yperm", k_csbr_yperm<X>, dim3(spx_div_up(A->m, 256)), dim3(256), 0, s,
                    A->cr_row_rank, A->m, A->cr_nrows, A->cr_yr, y);
     return hipGetLastError();
+}
+
+hipError_t spmv_csbr(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
+    return csbr_run<double, double>(A, A->val, x, y, s);
+}
+
+hipError_t spmv_csbr_f32(const spx_matrix_s* A, const float* x, float* y, hipStream_t s) {
+    if (A->value_type == SPX_F32)
+        return csbr_run<float, float>(A, (const float*)A->val_lp, x, y, s);
+    return csbr_run<uint16_t, float>(A, (const uint16_t*)A->val_lp, x, y, s);
 }

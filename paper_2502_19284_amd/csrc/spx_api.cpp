@@ -660,11 +660,15 @@ static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* 
     SPX_TRY(tmp.get(&val_out, (size_t)nnz, "values"));
     SPX_TRY(tmp.get(&packed, (size_t)nnz, "packed indices"));
     SPX_TRY(tmp.get(&bp, (size_t)nblk + 1, "blk_ptr"));
-    keep(tmp, A, val_out);
+    // FP64 values: kept by the handle, or (reduced precision) rounded once after the repeats are
+    // summed and then released with the other temporaries
+    A->value_type = o->value_type;
+    if (o->value_type == SPX_F64) {
+        keep(tmp, A, val_out);
+        A->val = val_out;
+    }
     keep(tmp, A, packed);
     keep(tmp, A, bp);
-    A->val = val_out;
-    A->value_type = SPX_F64;
     A->packed = packed;
     A->blk_ptr = bp;
     HIP_TRY(launch_fill_i32(bp, nblk + 1, 0, s));
@@ -678,6 +682,21 @@ static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* 
         tsn = scan_tile_count(nblk);
     }
     HIP_TRY(launch_max_scan_i32(bp + 1, nblk, tsums, s));
+    if (o->value_type != SPX_F64) {
+        void* lp = nullptr;
+        if (o->value_type == SPX_F32) {
+            float* f;
+            SPX_TRY(tmp.get(&f, (size_t)std::max<int64_t>(nnz, 1), "FP32 values"));
+            lp = f;
+        } else {
+            uint16_t* h;
+            SPX_TRY(tmp.get(&h, (size_t)std::max<int64_t>(nnz, 1), "bfloat16 values"));
+            lp = h;
+        }
+        keep(tmp, A, lp);
+        A->val_lp = lp;
+        HIP_TRY(launch_round_values(val_out, nnz, o->value_type, lp, s));
+    }
     // 4. work units over panels (heaviest first in launch order)
     const int64_t unit = o->tile_items > 0 ? o->tile_items : CR_UNIT_DEFAULT;
     int32_t *unit_ptr, *slot_ptr, *split_ptr;
@@ -991,8 +1010,9 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
     if (o.hot_columns < -1) return fail(SPX_ERR_INVALID_ARG, "hot_columns < -1");
     if (o.value_type != SPX_F64 && o.value_type != SPX_F32 && o.value_type != SPX_BF16)
         return fail(SPX_ERR_INVALID_ARG, "unknown value_type %d", (int)o.value_type);
-    if (o.value_type != SPX_F64 && !spx_is_crs(fmt))
-        return fail(SPX_ERR_UNSUPPORTED, "reduced-precision values are built for the CRS formats");
+    if (o.value_type != SPX_F64 && !spx_is_crs(fmt) && fmt != SPX_CSB_RANKED)
+        return fail(SPX_ERR_UNSUPPORTED,
+                    "reduced-precision values are built for the CRS formats and CSBR");
     if (fmt == SPX_CSB_RANKED && o.log2_beta != 0 && o.log2_beta != CR_PB)
         return fail(SPX_ERR_UNSUPPORTED, "CSBR panels are 2^%d rows (log2_beta 0 or %d)", CR_PB,
                     CR_PB);
@@ -1071,7 +1091,8 @@ extern "C" spx_status spx_spmv_f32(spx_matrix A, const float* x, float* y, void*
     if (A->m == 0) return SPX_OK;
     hipStream_t s = (hipStream_t)stream;
     A->last_stream = s;
-    HIP_TRY(spmv_crs_f32(A, x, y, s));
+    if (A->fmt == SPX_CSB_RANKED) HIP_TRY(spmv_csbr_f32(A, x, y, s));
+    else HIP_TRY(spmv_crs_f32(A, x, y, s));
     return SPX_OK;
 }
 

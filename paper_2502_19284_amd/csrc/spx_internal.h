@@ -42,9 +42,6 @@
 #ifndef CR_NT
 #define CR_NT 1024
 #endif
-#ifndef CR_IPT
-#define CR_IPT 4
-#endif
 #define CR_UNIT_DEFAULT (1 << 18)
 #define CR_SEG_LDS 1024  // segment starts of a panel staged in LDS when nseg + 1 <= this
 
@@ -445,6 +442,8 @@ hipError_t spmm_crs(const spx_matrix_s* A, const SpmmPlan& P, int32_t k, const v
 hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
 hipError_t spmv_bcoh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
 hipError_t spmv_csbr(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
+// reduced-precision CSBR (value_type FP32 or bfloat16): FP32 x and y
+hipError_t spmv_csbr_f32(const spx_matrix_s* A, const float* x, float* y, hipStream_t s);
 hipError_t csbr_prepare_kernel();
 hipError_t bcoh_prepare_kernel();
 

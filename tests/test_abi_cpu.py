@@ -99,9 +99,7 @@ def test_convert_argument_errors(L):
         assert st == -7
         st, _ = _convert(L, d, fmt=fmt, opts=B.ConvertOpts(0, 0, 1, 0, -1, 0))
         assert st == -7
-    # CSBR (6): FP64 values only, panels of fixed height
-    st, _ = _convert(L, d, fmt=6, opts=B.ConvertOpts(1, 0, 1, 0, -1, 1))
-    assert st == -7
+    # CSBR (6): panels of fixed height
     st, _ = _convert(L, d, fmt=6, opts=B.ConvertOpts(1, 5, 1, 0, -1, 0))
     assert st == -7
     st, _ = _convert(L, d, fmt=7)

@@ -1,4 +1,5 @@
-"""GPU parity of the reduced-precision forms (FP32 / bfloat16 stored values, FP32 x and y).
+"""GPU parity of the reduced-precision forms (FP32 / bfloat16 stored values, FP32 x and y) of
+the CRS formats and of CSBR.
 
 Bar: integer-valued inputs are bit-exact (every value, product and partial sum is an integer
 below 2^24); float inputs stay within the worst-case FP32 dot-product bound of
@@ -10,10 +11,11 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import measure, precision, spmv
+from oracle import formats, measure, precision, spmv
 
 pytestmark = pytest.mark.gpu
 CRS = ["rowsplit", "merge"]
+FMTS = CRS + ["csbr"]  # CSBR: FP32 products, FP64 sums
 UVAL = {"f32": precision.U32, "bf16": precision.UBF16}
 
 
@@ -64,8 +66,15 @@ def _check(A, vt, m, n, row, col, val, x, y, kind):
         e64 = measure.scaled_error(y, y64, s64)
         assert np.all(e64 <= precision.dot_error_bound(lens, UVAL[vt]))
         say("  %s vs FP64 oracle: max %.3g median %.3g" % (vt, e64.max(), np.median(e64)))
-    # stored values are the oracle's rounding, bit for bit
+    # stored values are the oracle's rounding, bit for bit (CSBR: taken to canonical order through
+    # its decoded coordinates)
     got = A.export("values").cpu()
+    if A.format == "csbr":
+        r, c, _, _, _ = formats.decode_csbr(A.export("row_order").cpu().numpy(),
+                                            A.export("blk_ptr").cpu().numpy(),
+                                            A.export("packed").cpu().numpy().view(np.uint32),
+                                            A.export("col_order").cpu().numpy())
+        got = got[__import__("torch").from_numpy(np.lexsort((c, r)))]
     if vt == "f32":
         assert np.array_equal(got.numpy().astype(np.float64), rv)
     else:
@@ -79,7 +88,7 @@ def rmat14():
     return (1 << 14), (1 << 14), row, col
 
 
-@pytest.mark.parametrize("fmt", CRS)
+@pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("vt", ["f32", "bf16"])
 @pytest.mark.parametrize("kind", ["int", "float"])
 def test_precision_rmat14(spx, rmat14, fmt, vt, kind):
@@ -92,11 +101,11 @@ def test_precision_rmat14(spx, rmat14, fmt, vt, kind):
     _check(A, vt, m, n, row, col, val, x, y, kind)
 
 
-@pytest.mark.parametrize("fmt", CRS)
+@pytest.mark.parametrize("fmt", FMTS)
 @pytest.mark.parametrize("vt", ["f32", "bf16"])
 def test_precision_long_rows_and_hot_columns(spx, fmt, vt):
     # rows longer than a tile / row block / chunk (FP64 across tiles and for long rows), with the
-    # hot-column copy forced on
+    # hot-column copy forced on (CRS); CSBR with panels split into many units (FP64 partials)
     rng = np.random.default_rng(5)
     m, n = 4001, 6007
     row = np.concatenate([rng.integers(0, m, 80_000), np.full(40_000, 7), np.full(5000, 3000)])
@@ -106,7 +115,8 @@ def test_precision_long_rows_and_hot_columns(spx, fmt, vt):
     for kind in ("int", "float"):
         val = synth.values(len(row), seed=9, kind=kind)
         x = synth.xvec(n, seed=9, kind=kind)
-        A, y = _run(spx, fmt, vt, m, n, row, col, val, x, hot_columns=500)
+        kw = dict(hot_columns=500) if fmt in CRS else dict(tile_items=3000)
+        A, y = _run(spx, fmt, vt, m, n, row, col, val, x, **kw)
         _check(A, vt, m, n, row, col, val, x, y, kind)
 
 
