@@ -119,9 +119,8 @@ typedef struct {
     int32_t hot_columns;    /* CRS formats: at most this many of the most frequent columns get a
                              * compact copy of their x values per product (x_hot); -1 = automatic
                              * (up to 2^19 when n >= 2^19), 0 = off.  y is unchanged by it.      */
-    spx_dtype value_type;   /* stored value type: SPX_F64 (default), or SPX_F32 / SPX_BF16 for
-                             * the CRS formats and CSBR (repeats are summed in FP64, then rounded
-                             * once)                                                           */
+    spx_dtype value_type;   /* stored value type: SPX_F64 (default), or SPX_F32 / SPX_BF16
+                             * (repeats are summed in FP64, then rounded once)                 */
 } spx_convert_opts;
 
 typedef struct {
@@ -196,9 +195,8 @@ spx_status spx_convert_opts_default(spx_convert_opts* opts);
  * The call returns after the device work is complete (it reads back the entry count).
  * Errors: INVALID_ARG, RANGE (m, n or nnz beyond int32, a CSB / BCOHC key beyond 64 bits, or
  * more than 2^26 rows or columns for CSBR), INDEX (an index out of range; indices are always
- * checked), UNSUPPORTED (reduced-precision values for CSB, CSBH, BCOHC, BCOHCH; sum_duplicates=0
- * for BCOHC / BCOHCH), NOMEM, HIP, DEVICE (a device-side list of the sort outgrew its bound; not
- * expected).  On error every temporary is freed.
+ * checked), UNSUPPORTED (sum_duplicates=0 for BCOHC / BCOHCH), NOMEM, HIP, DEVICE (a device-side
+ * list of the sort outgrew its bound; not expected).  On error every temporary is freed.
  */
 spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt, const spx_convert_opts* opts,
                        void* stream, spx_matrix* out, spx_convert_report* rep);
@@ -215,10 +213,11 @@ spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt, const spx_conver
 spx_status spx_spmv(spx_matrix A, const double* x, double* y, void* stream);
 
 /*
- * Reduced-precision product y = A x for a CRS or CSBR matrix stored in FP32 or bfloat16
- * (value_type at conversion): x (n floats) and y (m floats) are device FP32.  CRS: products and
- * sums inside a merge tile or row block are FP32, sums that cross tiles and rows longer than a
- * row block are FP64.  CSBR: products FP32, every sum FP64; y rounded to FP32 once.
+ * Reduced-precision product y = A x for a matrix stored in FP32 or bfloat16 (value_type at
+ * conversion): x (n floats) and y (m floats) are device FP32.  CRS formats: products and sums
+ * inside a merge tile or row block are FP32, sums that cross tiles and rows longer than a row
+ * block are FP64.  Block formats (CSB, CSBH, BCOHC, BCOHCH, CSBR): products FP32, every sum FP64
+ * (the on-chip slice of y); y rounded to FP32 once.
  * Otherwise as spx_spmv.  Errors: UNSUPPORTED for an FP64 matrix (use spx_spmv), and spx_spmv
  * returns UNSUPPORTED for a reduced-precision matrix.
  */

@@ -398,11 +398,12 @@ __device__ __forceinline__ int bcoh_block_of(const int32_t* __restrict__ bp, int
     return lo;
 }
 
+template <typename V, typename X>
 __global__ __launch_bounds__(BH_NT) void k_spmv_bcoh(
     const int32_t* __restrict__ part_row, const int32_t* __restrict__ part_blk,
     const int32_t* __restrict__ blk_ptr, const uint32_t* __restrict__ blk_coord,
-    const uint32_t* __restrict__ packed, const double* __restrict__ val,
-    const double* __restrict__ x, double* __restrict__ y, int k) {
+    const uint32_t* __restrict__ packed, const V* __restrict__ val,
+    const X* __restrict__ x, X* __restrict__ y, int k) {
     extern __shared__ double s_y[];
     int32_t* s_bp = (int32_t*)(s_y + BH_WINDOW);  // nbk + 1 block pointers
     uint32_t* s_bc = (uint32_t*)(s_bp + nbk_stage_max(BH_STAGE_WORDS) + 1);  // nbk coordinates
@@ -423,59 +424,83 @@ __global__ __launch_bounds__(BH_NT) void k_spmv_bcoh(
     const int32_t* bp = stage_bp ? s_bp : blk_ptr + b0;  // partition-local block indices
     const uint32_t* bcs = stage_bc ? s_bc : blk_coord + b0;
     const uint32_t lmask = 0xFFFFu;
+    using T = decltype(vget(val));  // arithmetic type of a product
     int b = 0;  // partition-local block of this thread's current entry
     uint32_t bc = nbk > 0 ? bcs[0] : 0u;
     for (int base = e0; base < e1; base += BH_NT * BH_IPT) {
+        // matrix loads issued unconditionally (entries past e1 read entry e1 - 1 again and are
+        // dropped), so none waits inside a branch
+        int kc[BH_IPT];
+#pragma unroll
+        for (int q = 0; q < BH_IPT; ++q) kc[q] = min(base + q * BH_NT + tid, e1 - 1);
         uint32_t pk[BH_IPT];
-        double v[BH_IPT];
+        V raw[BH_IPT];
 #pragma unroll
         for (int q = 0; q < BH_IPT; ++q) {
-            const int kk = base + q * BH_NT + tid;
-            pk[q] = kk < e1 ? ntload(packed + kk) : 0u;
-            v[q] = kk < e1 ? ntload(val + kk) : 0.0;
+            pk[q] = ntload(packed + kc[q]);
+            raw[q] = ntload(val + kc[q]);
         }
-        double xv[BH_IPT];
+        T xv[BH_IPT];
         int rw[BH_IPT];
 #pragma unroll
         for (int q = 0; q < BH_IPT; ++q) {
-            const int kk = base + q * BH_NT + tid;
-            xv[q] = 0.0;
+            xv[q] = (T)0;
             rw[q] = 0;
-            if (kk < e1) {
-                const int nb = bcoh_block_of(bp, b, nbk, kk);
+            if (base + q * BH_NT + tid < e1) {
+                const int nb = bcoh_block_of(bp, b, nbk, kc[q]);
                 if (nb != b) {
                     b = nb;
                     bc = bcs[b];
                 }
                 rw[q] = (int)((bc >> 16) << k) + (int)(pk[q] >> 16) - r0;
-                xv[q] = x[(int)((bc & lmask) << k) + (int)(pk[q] & lmask)];
+                xv[q] = (T)x[(int)((bc & lmask) << k) + (int)(pk[q] & lmask)];
             }
         }
 #pragma unroll
         for (int q = 0; q < BH_IPT; ++q) {
             const int kk = base + q * BH_NT + tid;
-            lds_add_runs(s_y, kk < e1 ? rw[q] : -1, v[q] * xv[q]);
+            lds_add_runs(s_y, kk < e1 ? rw[q] : -1, (double)(vdec(raw[q]) * xv[q]));
         }
     }
     __syncthreads();
-    for (int i = tid; i < rows; i += BH_NT) ntstore(y + r0 + i, s_y[i]);
+    for (int i = tid; i < rows; i += BH_NT) ntstore(y + r0 + i, (X)s_y[i]);
 }
 
 static constexpr size_t kBcohLds = (size_t)BH_WINDOW * sizeof(double) + BH_STAGE_WORDS * 4;
 
 // The product's LDS exceeds the default 64 KiB limit of dynamic LDS: raised once per device, at
 // conversion.
-hipError_t bcoh_prepare_kernel() {
-    return hipFuncSetAttribute((const void*)k_spmv_bcoh,
+template <typename V, typename X>
+static hipError_t bcoh_prepare_one() {
+    return hipFuncSetAttribute((const void*)k_spmv_bcoh<V, X>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBcohLds);
 }
 
-hipError_t spmv_bcoh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
+hipError_t bcoh_prepare_kernel() {
+    hipError_t e = bcoh_prepare_one<double, double>();
+    if (e == hipSuccess) e = bcoh_prepare_one<float, float>();
+    if (e == hipSuccess) e = bcoh_prepare_one<uint16_t, float>();
+    return e;
+}
+
+template <typename V, typename X>
+static hipError_t bcoh_run(const spx_matrix_s* A, const V* val, const X* x, X* y,
+                           hipStream_t s) {
     if (A->bh_nparts <= 0) return hipSuccess;
-    SPX_LAUNCH("spmv_bcoh", k_spmv_bcoh, dim3(A->bh_nparts), dim3(BH_NT), kBcohLds, s,
-               A->bh_part_row, A->bh_part_blk, A->bh_blk_ptr, A->bh_blk_coord, A->packed, A->val,
+    SPX_LAUNCH("spmv_bcoh", (k_spmv_bcoh<V, X>), dim3(A->bh_nparts), dim3(BH_NT), kBcohLds, s,
+               A->bh_part_row, A->bh_part_blk, A->bh_blk_ptr, A->bh_blk_coord, A->packed, val,
                x, y, A->log2_beta);
     return hipGetLastError();
+}
+
+hipError_t spmv_bcoh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
+    return bcoh_run<double, double>(A, A->val, x, y, s);
+}
+
+hipError_t spmv_bcoh_f32(const spx_matrix_s* A, const float* x, float* y, hipStream_t s) {
+    if (A->value_type == SPX_F32)
+        return bcoh_run<float, float>(A, (const float*)A->val_lp, x, y, s);
+    return bcoh_run<uint16_t, float>(A, (const uint16_t*)A->val_lp, x, y, s);
 }
 
 

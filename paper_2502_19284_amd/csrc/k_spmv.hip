@@ -35,11 +35,12 @@ __device__ __forceinline__ int csb_block_of(const int32_t* __restrict__ bp, int 
     return lo;
 }
 
+template <typename V, typename X>
 __global__ __launch_bounds__(CB_NT) void k_spmv_csbh(const int32_t* __restrict__ blk_ptr,
                                                      const uint32_t* __restrict__ packed,
-                                                     const double* __restrict__ val,
-                                                     const double* __restrict__ x,
-                                                     double* __restrict__ y,
+                                                     const V* __restrict__ val,
+                                                     const X* __restrict__ x,
+                                                     X* __restrict__ y,
                                                      double* __restrict__ partials,
                                                      const int4* __restrict__ units, int k,
                                                      int32_t nbc, int32_t m, int stage_bp) {
@@ -57,37 +58,41 @@ __global__ __launch_bounds__(CB_NT) void k_spmv_csbh(const int32_t* __restrict__
     __syncthreads();
     const int32_t* bp = stage_bp ? s_bp : gbp;
     const uint32_t lmask = (uint32_t)beta - 1u;
+    using T = decltype(vget(val));  // arithmetic type of a product
     int b = 0;  // block of this thread's current entry (bp[0] <= kb)
     for (int base = kb; base < ke; base += CB_NT * CB_IPT) {
+        // matrix loads issued unconditionally (entries past ke read entry ke - 1 again and are
+        // dropped), so none waits inside a branch
+        int kc[CB_IPT];
+#pragma unroll
+        for (int q = 0; q < CB_IPT; ++q) kc[q] = min(base + q * CB_NT + tid, ke - 1);
         uint32_t p[CB_IPT];
-        double v[CB_IPT];
+        V raw[CB_IPT];
 #pragma unroll
         for (int q = 0; q < CB_IPT; ++q) {
-            const int kk = base + q * CB_NT + tid;
-            p[q] = kk < ke ? ntload(packed + kk) : 0u;
-            v[q] = kk < ke ? ntload(val + kk) : 0.0;
+            p[q] = ntload(packed + kc[q]);
+            raw[q] = ntload(val + kc[q]);
         }
-        double xv[CB_IPT];
+        T xv[CB_IPT];
 #pragma unroll
         for (int q = 0; q < CB_IPT; ++q) {
-            const int kk = base + q * CB_NT + tid;
-            xv[q] = 0.0;
-            if (kk < ke) {
-                b = csb_block_of(bp, b, nbc, kk);
-                xv[q] = x[(b << k) + (int)(p[q] & lmask)];
+            xv[q] = (T)0;
+            if (base + q * CB_NT + tid < ke) {
+                b = csb_block_of(bp, b, nbc, kc[q]);
+                xv[q] = (T)x[(b << k) + (int)(p[q] & lmask)];
             }
         }
 #pragma unroll
         for (int q = 0; q < CB_IPT; ++q) {
-            const int kk = base + q * CB_NT + tid;
-            if (kk < ke) atomicAdd(&s_y[p[q] >> 16], v[q] * xv[q]);
+            if (base + q * CB_NT + tid < ke)
+                atomicAdd(&s_y[p[q] >> 16], (double)(vdec(raw[q]) * xv[q]));
         }
     }
     __syncthreads();
     const int row0 = br << k;
     const int rows = min(beta, m - row0);
     if (slot < 0) {
-        for (int i = tid; i < rows; i += CB_NT) ntstore(y + row0 + i, s_y[i]);
+        for (int i = tid; i < rows; i += CB_NT) ntstore(y + row0 + i, (X)s_y[i]);
     } else {
         double* dst = partials + (int64_t)slot * beta;
         for (int i = tid; i < rows; i += CB_NT) dst[i] = s_y[i];
@@ -97,9 +102,10 @@ __global__ __launch_bounds__(CB_NT) void k_spmv_csbh(const int32_t* __restrict__
 // Split block row S.x: y = sum of its S.z partial slices (slots S.y ..), added in slot order.
 // Workgroup = (split row, chunk of 256 rows); each thread keeps 8 slot loads in flight.
 #define CB_RED_NT 256
+template <typename X>
 __device__ __forceinline__ void csb_reduce_body(const int4* __restrict__ split,
                                                 const double* __restrict__ partials,
-                                                double* __restrict__ y, int k, int32_t m) {
+                                                X* __restrict__ y, int k, int32_t m) {
     const int beta = 1 << k;
     const int chunks = (beta + CB_RED_NT - 1) / CB_RED_NT;
     const int4 S = split[blockIdx.x / chunks];
@@ -118,12 +124,13 @@ __device__ __forceinline__ void csb_reduce_body(const int4* __restrict__ split,
         for (int u = 0; u < 8; ++u) acc = acc + t[u];
     }
     for (; q < S.z; ++q) acc = acc + p[(int64_t)q * beta];
-    y[row0 + i] = acc;
+    y[row0 + i] = (X)acc;
 }
 
+template <typename X>
 __global__ __launch_bounds__(CB_RED_NT) void k_spmv_csbh_reduce(const int4* __restrict__ split,
                                                                const double* __restrict__ partials,
-                                                               double* __restrict__ y, int k,
+                                                               X* __restrict__ y, int k,
                                                                int32_t m) {
     csb_reduce_body(split, partials, y, k, m);
 }
@@ -136,25 +143,36 @@ __global__ __launch_bounds__(CB_RED_NT) void k_spmv_csbr_reduce(const int4* __re
     csb_reduce_body(split, partials, y, k, m);
 }
 
-hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
+template <typename V, typename X>
+static hipError_t csbh_run(const spx_matrix_s* A, const V* val, const X* x, X* y,
+                           hipStream_t s) {
     if (A->cb_nunits <= 0) return hipSuccess;
     const int beta = 1 << A->log2_beta;
     const int stage_bp = (A->nbc + 1 <= CB_BP_STAGE_MAX) ? 1 : 0;
     const size_t lds = (size_t)beta * sizeof(double) + (stage_bp ? (size_t)(A->nbc + 1) * 4 : 0);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_spmv_csbh,
+        hipError_t e = hipFuncSetAttribute((const void*)k_spmv_csbh<V, X>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    SPX_LAUNCH("spmv_csbh", k_spmv_csbh, dim3(A->cb_nunits), dim3(CB_NT), lds, s, A->blk_ptr,
-                       A->packed, A->val, x, y, A->cb_partials, A->cb_units, A->log2_beta,
-                       (int32_t)A->nbc, A->m, stage_bp);
+    SPX_LAUNCH("spmv_csbh", (k_spmv_csbh<V, X>), dim3(A->cb_nunits), dim3(CB_NT), lds, s,
+               A->blk_ptr, A->packed, val, x, y, A->cb_partials, A->cb_units, A->log2_beta,
+               (int32_t)A->nbc, A->m, stage_bp);
     if (A->cb_nsplit > 0)
-        SPX_LAUNCH("spmv_csbh_reduce", k_spmv_csbh_reduce,
+        SPX_LAUNCH("spmv_csbh_reduce", k_spmv_csbh_reduce<X>,
                    dim3(A->cb_nsplit * (((1 << A->log2_beta) + CB_RED_NT - 1) / CB_RED_NT)),
-                   dim3(CB_RED_NT), 0, s, A->cb_split,
-                           A->cb_partials, y, A->log2_beta, A->m);
+                   dim3(CB_RED_NT), 0, s, A->cb_split, A->cb_partials, y, A->log2_beta, A->m);
     return hipGetLastError();
+}
+
+hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s) {
+    return csbh_run<double, double>(A, A->val, x, y, s);
+}
+
+hipError_t spmv_csbh_f32(const spx_matrix_s* A, const float* x, float* y, hipStream_t s) {
+    if (A->value_type == SPX_F32)
+        return csbh_run<float, float>(A, (const float*)A->val_lp, x, y, s);
+    return csbh_run<uint16_t, float>(A, (const uint16_t*)A->val_lp, x, y, s);
 }
 
 // ================================================================== CSBR (Section 3.1 blocks over

@@ -304,6 +304,33 @@ static void keep(AllocSet& tmp, spx_matrix_s* A, void* p) {
         }
 }
 
+// The stored values, once val_out holds the FP64 sums of every run: FP64 values are kept by the
+// handle; reduced-precision ones are rounded once into a buffer of their own, and val_out is left
+// to be released with the other temporaries.
+static spx_status finish_values(AllocSet& tmp, spx_matrix_s* A, double* val_out, int64_t nnz,
+                                spx_dtype vt, hipStream_t s) {
+    A->value_type = vt;
+    if (vt == SPX_F64) {
+        keep(tmp, A, val_out);
+        A->val = val_out;
+        return SPX_OK;
+    }
+    void* lp = nullptr;
+    if (vt == SPX_F32) {
+        float* f;
+        SPX_TRY(tmp.get(&f, (size_t)std::max<int64_t>(nnz, 1), "FP32 values"));
+        lp = f;
+    } else {
+        uint16_t* h;
+        SPX_TRY(tmp.get(&h, (size_t)std::max<int64_t>(nnz, 1), "bfloat16 values"));
+        lp = h;
+    }
+    keep(tmp, A, lp);
+    A->val_lp = lp;
+    HIP_TRY(launch_round_values(val_out, nnz, vt, lp, s));
+    return SPX_OK;
+}
+
 // Hot-column compaction: the (at most hot_max) columns with the largest sampled entry counts get
 // dense ranks, and their entries will store ~rank.  Counts are sampled from the sorted keys
 // (repeats included).  The threshold is the smallest sampled count whose column set fits in
@@ -413,7 +440,7 @@ static spx_status select_hot_columns(AllocSet& tmp, spx_matrix_s* A, int32_t hot
 // BH_WINDOW rows each), then one sort by (partition, Hilbert block index, position in block),
 // the fused repeat-sum + populate step, and the block and partition tables.
 static spx_status convert_bcoh(const spx_coo_desc* coo, spx_format fmt, int k, int K2,
-                               hipStream_t s, spx_matrix_s* A, AllocSet& tmp) {
+                               spx_dtype vt, hipStream_t s, spx_matrix_s* A, AllocSet& tmp) {
     HIP_TRY(bcoh_prepare_kernel());
     const int64_t E = coo->nnz;
     const int32_t m = coo->m;
@@ -468,9 +495,7 @@ static spx_status convert_bcoh(const spx_coo_desc* coo, spx_format fmt, int k, i
     SPX_TRY(tmp.get(&packed, (size_t)nnz, "packed indices"));
     SPX_TRY(tmp.get(&flags, (size_t)nnz, "block flags"));
     SPX_TRY(tmp.get(&majors, (size_t)nnz, "block keys"));
-    keep(tmp, A, val_out);
     keep(tmp, A, packed);
-    A->val = val_out;
     A->packed = packed;
     int64_t nb = 0;
     if (nnz > 0) {
@@ -485,6 +510,7 @@ static spx_status convert_bcoh(const spx_coo_desc* coo, spx_format fmt, int k, i
         SPX_TRY(sync_read(&rb, rb_dev, sizeof rb, s));
         nb = rb.totals[2];
     }
+    SPX_TRY(finish_values(tmp, A, val_out, nnz, vt, s));
     int32_t *bptr, *bpart, *parts;
     uint32_t* bcoord;
     SPX_TRY(tmp.get(&bptr, (size_t)nb + 1, "block pointers"));
@@ -660,13 +686,6 @@ static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* 
     SPX_TRY(tmp.get(&val_out, (size_t)nnz, "values"));
     SPX_TRY(tmp.get(&packed, (size_t)nnz, "packed indices"));
     SPX_TRY(tmp.get(&bp, (size_t)nblk + 1, "blk_ptr"));
-    // FP64 values: kept by the handle, or (reduced precision) rounded once after the repeats are
-    // summed and then released with the other temporaries
-    A->value_type = o->value_type;
-    if (o->value_type == SPX_F64) {
-        keep(tmp, A, val_out);
-        A->val = val_out;
-    }
     keep(tmp, A, packed);
     keep(tmp, A, bp);
     A->packed = packed;
@@ -682,21 +701,7 @@ static spx_status convert_csbr(const spx_coo_desc* coo, const spx_convert_opts* 
         tsn = scan_tile_count(nblk);
     }
     HIP_TRY(launch_max_scan_i32(bp + 1, nblk, tsums, s));
-    if (o->value_type != SPX_F64) {
-        void* lp = nullptr;
-        if (o->value_type == SPX_F32) {
-            float* f;
-            SPX_TRY(tmp.get(&f, (size_t)std::max<int64_t>(nnz, 1), "FP32 values"));
-            lp = f;
-        } else {
-            uint16_t* h;
-            SPX_TRY(tmp.get(&h, (size_t)std::max<int64_t>(nnz, 1), "bfloat16 values"));
-            lp = h;
-        }
-        keep(tmp, A, lp);
-        A->val_lp = lp;
-        HIP_TRY(launch_round_values(val_out, nnz, o->value_type, lp, s));
-    }
+    SPX_TRY(finish_values(tmp, A, val_out, nnz, o->value_type, s));
     // 4. work units over panels (heaviest first in launch order)
     const int64_t unit = o->tile_items > 0 ? o->tile_items : CR_UNIT_DEFAULT;
     int32_t *unit_ptr, *slot_ptr, *split_ptr;
@@ -767,8 +772,7 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
         A->log2_beta = k;
         A->nbr = nbr;
         A->nbc = nbc;
-        A->value_type = SPX_F64;
-        return convert_bcoh(coo, fmt, k, K2, s, A, tmp);
+        return convert_bcoh(coo, fmt, k, K2, o->value_type, s, A, tmp);
     }
     if (spx_is_csb(fmt)) {
         k = o->log2_beta > 0 ? o->log2_beta : csbh_default_log2_beta(m, n);
@@ -804,15 +808,8 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
     SPX_TRY(tmp.get(&rb_dev, 1, "readback"));
     HIP_TRY(launch_init_readback(rb_dev, s));
 
-    // FP64 values: kept by the handle, or (reduced precision) rounded once after the repeats are
-    // summed and then released with the other temporaries
-    double* val_out;
+    double* val_out;  // FP64 run sums (finish_values keeps or rounds them)
     SPX_TRY(tmp.get(&val_out, (size_t)nnz, "values"));
-    A->value_type = o->value_type;
-    if (o->value_type == SPX_F64) {
-        keep(tmp, A, val_out);
-        A->val = val_out;
-    }
 
     if (spx_is_csb(fmt)) {
         const int64_t nblk = nbr * nbc;
@@ -835,6 +832,7 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
         if (scan_tile_count(nblk) > tsn) tsn = scan_tile_count(nblk);
         SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
         HIP_TRY(launch_max_scan_i32(bp + 1, nblk, tsums, s));
+        SPX_TRY(finish_values(tmp, A, val_out, nnz, o->value_type, s));
         // work units
         int64_t unit = o->tile_items > 0 ? o->tile_items : CB_UNIT_DEFAULT;
         int32_t *unit_ptr, *slot_ptr, *split_ptr;
@@ -883,22 +881,8 @@ static spx_status convert_impl(const spx_coo_desc* coo, spx_format fmt,
                               rp + 1, s));
     SPX_TRY(tmp.get(&tsums, tsn, "scan tile sums"));
     HIP_TRY(launch_max_scan_i32(rp + 1, m, tsums, s));
-    if (o->value_type != SPX_F64) {
-        void* lp = nullptr;
-        if (o->value_type == SPX_F32) {
-            float* f;
-            SPX_TRY(tmp.get(&f, (size_t)nnz, "FP32 values"));
-            lp = f;
-        } else {
-            uint16_t* h;
-            SPX_TRY(tmp.get(&h, (size_t)nnz, "bfloat16 values"));
-            lp = h;
-        }
-        keep(tmp, A, lp);
-        A->val_lp = lp;
-        HIP_TRY(launch_round_values(val_out, nnz, o->value_type, lp, s));
-        // hot x copy holds FP32 values for these matrices (the buffer is large enough)
-    }
+    // (reduced precision: the hot x copy holds FP32 values, the buffer is large enough)
+    SPX_TRY(finish_values(tmp, A, val_out, nnz, o->value_type, s));
 
     if (fmt == SPX_CSR_MERGE) {
         const int64_t total = (int64_t)m + nnz;
@@ -1010,9 +994,6 @@ extern "C" spx_status spx_convert(const spx_coo_desc* coo, spx_format fmt,
     if (o.hot_columns < -1) return fail(SPX_ERR_INVALID_ARG, "hot_columns < -1");
     if (o.value_type != SPX_F64 && o.value_type != SPX_F32 && o.value_type != SPX_BF16)
         return fail(SPX_ERR_INVALID_ARG, "unknown value_type %d", (int)o.value_type);
-    if (o.value_type != SPX_F64 && !spx_is_crs(fmt) && fmt != SPX_CSB_RANKED)
-        return fail(SPX_ERR_UNSUPPORTED,
-                    "reduced-precision values are built for the CRS formats and CSBR");
     if (fmt == SPX_CSB_RANKED && o.log2_beta != 0 && o.log2_beta != CR_PB)
         return fail(SPX_ERR_UNSUPPORTED, "CSBR panels are 2^%d rows (log2_beta 0 or %d)", CR_PB,
                     CR_PB);
@@ -1091,8 +1072,16 @@ extern "C" spx_status spx_spmv_f32(spx_matrix A, const float* x, float* y, void*
     if (A->m == 0) return SPX_OK;
     hipStream_t s = (hipStream_t)stream;
     A->last_stream = s;
-    if (A->fmt == SPX_CSB_RANKED) HIP_TRY(spmv_csbr_f32(A, x, y, s));
-    else HIP_TRY(spmv_crs_f32(A, x, y, s));
+    switch (A->fmt) {
+        case SPX_CSR_MERGE:
+        case SPX_CSR_ROWSPLIT: HIP_TRY(spmv_crs_f32(A, x, y, s)); break;
+        case SPX_CSB_HILBERT:
+        case SPX_CSB_ZMORTON: HIP_TRY(spmv_csbh_f32(A, x, y, s)); break;
+        case SPX_BCOHC:
+        case SPX_BCOHCH: HIP_TRY(spmv_bcoh_f32(A, x, y, s)); break;
+        case SPX_CSB_RANKED: HIP_TRY(spmv_csbr_f32(A, x, y, s)); break;
+        default: return fail(SPX_ERR_INVALID_ARG, "corrupt handle");
+    }
     return SPX_OK;
 }
 

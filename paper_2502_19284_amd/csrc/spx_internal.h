@@ -441,6 +441,10 @@ hipError_t spmm_crs(const spx_matrix_s* A, const SpmmPlan& P, int32_t k, const v
                     int64_t ldx, void* y, int64_t ldy, int row_major, hipStream_t s);
 hipError_t spmv_csbh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
 hipError_t spmv_bcoh(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
+// reduced-precision CSB / CSBH and BCOHC / BCOHCH (value_type FP32 or bfloat16): FP32 x and y,
+// FP32 products, FP64 sums
+hipError_t spmv_csbh_f32(const spx_matrix_s* A, const float* x, float* y, hipStream_t s);
+hipError_t spmv_bcoh_f32(const spx_matrix_s* A, const float* x, float* y, hipStream_t s);
 hipError_t spmv_csbr(const spx_matrix_s* A, const double* x, double* y, hipStream_t s);
 // reduced-precision CSBR (value_type FP32 or bfloat16): FP32 x and y
 hipError_t spmv_csbr_f32(const spx_matrix_s* A, const float* x, float* y, hipStream_t s);

@@ -92,11 +92,7 @@ def test_convert_argument_errors(L):
     assert st == -7
     st, _ = _convert(L, d, fmt=1, opts=B.ConvertOpts(1, 0, 1, 0, -1, 5))
     assert st == -1
-    st, _ = _convert(L, d, fmt=2, opts=B.ConvertOpts(1, 0, 1, 0, -1, 1))
-    assert st == -7  # reduced precision is built for the CRS formats
-    for fmt in (4, 5):  # BCOHC / BCOHCH: FP64 values and summed repeats only
-        st, _ = _convert(L, d, fmt=fmt, opts=B.ConvertOpts(1, 0, 1, 0, -1, 2))
-        assert st == -7
+    for fmt in (4, 5):  # BCOHC / BCOHCH: summed repeats only
         st, _ = _convert(L, d, fmt=fmt, opts=B.ConvertOpts(0, 0, 1, 0, -1, 0))
         assert st == -7
     # CSBR (6): panels of fixed height

@@ -165,7 +165,7 @@ def _sampled_crs(w, rows):
     return spmv.crs(len(rows), w["n"], local, w["col"][sel], w["val"][sel])
 
 
-@pytest.mark.parametrize("fmt", ["rowsplit", "merge", "csbr"])
+@pytest.mark.parametrize("fmt", ["rowsplit", "merge", "csbr", "csbh", "bcohc"])
 @pytest.mark.parametrize("vt", ["f32", "bf16"])
 def test_sampled_rows_reduced_precision(big, fmt, vt):
     # FP32 / bfloat16 stored values at full size: sampled rows within the FP32 dot-product bound

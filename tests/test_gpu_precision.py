@@ -1,5 +1,6 @@
 """GPU parity of the reduced-precision forms (FP32 / bfloat16 stored values, FP32 x and y) of
-the CRS formats and of CSBR.
+every format: the CRS formats (FP32 sums inside a tile or row block) and the block formats
+(FP32 products, FP64 sums).
 
 Bar: integer-valued inputs are bit-exact (every value, product and partial sum is an integer
 below 2^24); float inputs stay within the worst-case FP32 dot-product bound of
@@ -11,11 +12,12 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import formats, measure, precision, spmv
+from oracle import bcoh, formats, measure, precision, spmv
 
 pytestmark = pytest.mark.gpu
 CRS = ["rowsplit", "merge"]
-FMTS = CRS + ["csbr"]  # CSBR: FP32 products, FP64 sums
+BLOCK = ["csbh", "csb", "bcohc", "bcohch", "csbr"]  # FP32 products, FP64 sums
+FMTS = CRS + BLOCK
 UVAL = {"f32": precision.U32, "bf16": precision.UBF16}
 
 
@@ -69,11 +71,19 @@ def _check(A, vt, m, n, row, col, val, x, y, kind):
     # stored values are the oracle's rounding, bit for bit (CSBR: taken to canonical order through
     # its decoded coordinates)
     got = A.export("values").cpu()
-    if A.format == "csbr":
-        r, c, _, _, _ = formats.decode_csbr(A.export("row_order").cpu().numpy(),
-                                            A.export("blk_ptr").cpu().numpy(),
-                                            A.export("packed").cpu().numpy().view(np.uint32),
-                                            A.export("col_order").cpu().numpy())
+    if A.format in BLOCK:  # storage order -> canonical order through the decoded coordinates
+        packed = A.export("packed").cpu().numpy().view(np.uint32)
+        bp = A.export("blk_ptr").cpu().numpy()
+        if A.format == "csbr":
+            r, c, _, _, _ = formats.decode_csbr(A.export("row_order").cpu().numpy(), bp, packed,
+                                                A.export("col_order").cpu().numpy())
+        elif A.format in ("csbh", "csb"):
+            r, c, _, _, _, _ = formats.decode_csbh(m, n, A.log2_beta, bp, packed,
+                                                   np.zeros(len(packed)))
+        else:
+            r, c, _ = bcoh.decode(A.log2_beta, bp,
+                                  A.export("blk_coord").cpu().numpy().view(np.uint32), packed,
+                                  np.zeros(len(packed)))
         got = got[__import__("torch").from_numpy(np.lexsort((c, r)))]
     if vt == "f32":
         assert np.array_equal(got.numpy().astype(np.float64), rv)
@@ -115,7 +125,8 @@ def test_precision_long_rows_and_hot_columns(spx, fmt, vt):
     for kind in ("int", "float"):
         val = synth.values(len(row), seed=9, kind=kind)
         x = synth.xvec(n, seed=9, kind=kind)
-        kw = dict(hot_columns=500) if fmt in CRS else dict(tile_items=3000)
+        kw = (dict(hot_columns=500) if fmt in CRS else
+              dict(tile_items=3000) if fmt in ("csbr", "csbh", "csb") else {})
         A, y = _run(spx, fmt, vt, m, n, row, col, val, x, **kw)
         _check(A, vt, m, n, row, col, val, x, y, kind)
 
@@ -136,6 +147,7 @@ def test_precision_entry_points_reject_mismatch(spx, rmat14):
     yb = torch.zeros(m, dtype=torch.float64, device="cuda")
     st = L.spx_spmv(A.handle, ctypes.c_void_p(xb.data_ptr()), ctypes.c_void_p(yb.data_ptr()), None)
     assert st == -7
-    with pytest.raises(spx.SpxError):
-        spx.convert(d(row, torch.int32), d(col, torch.int32), d(val, torch.float64), (m, n),
+    B = spx.convert(d(row, torch.int32), d(col, torch.int32), d(val, torch.float64), (m, n),
                     "csbh", value_type="bf16")
+    st = L.spx_spmv(B.handle, ctypes.c_void_p(xb.data_ptr()), ctypes.c_void_p(yb.data_ptr()), None)
+    assert st == -7
