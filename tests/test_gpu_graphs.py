@@ -3,10 +3,11 @@ eager product bit for bit, with unrelated eager work between replays; and the se
 several submitting threads.
 
 Bar: bitwise equality with the eager launch for graphs of the CRS formats (their sums have a fixed
-order); the block formats (CSB, CSBH, BCOHC, BCOHCH) add products into an LDS slice with float
-atomics, whose order varies from run to run, so their replays are held to the product tolerance
-(row-scaled 1e-12) instead; for the threaded server, integer-valued results bit-exact against the
-oracle.
+order); the block formats (CSB, CSBH, BCOHC, BCOHCH, CSBR) add products into an LDS slice with
+float atomics, whose order varies from run to run, so their replays are held to the product
+tolerance (row-scaled 1e-12; for their FP32 / bfloat16 forms, which round y to FP32 once, one
+FP32 rounding step, 2^-23 of the row scale) instead; for the threaded server, integer-valued
+results bit-exact against the oracle.
 """
 import sys
 import threading
@@ -68,7 +69,8 @@ def _capture(fn):
 
 @pytest.mark.parametrize("fmt,vt", [("merge", "f64"), ("rowsplit", "f64"), ("csbh", "f64"),
                                     ("csb", "f64"), ("bcohc", "f64"), ("bcohch", "f64"),
-                                    ("csbr", "f64"), ("merge", "f32"), ("rowsplit", "bf16")])
+                                    ("csbr", "f64"), ("merge", "f32"), ("rowsplit", "bf16"),
+                                    ("csbr", "f32"), ("csbh", "bf16"), ("bcohch", "f32")])
 def test_spmv_graph_replays(spx, rmat14, fmt, vt):
     import torch
     m, n, row, col, val = rmat14
@@ -94,8 +96,12 @@ def test_spmv_graph_replays(spx, rmat14, fmt, vt):
         if scale is None:
             assert torch.equal(y, eager), "%s %s replay %d" % (fmt, vt, rep)
         else:
-            err = measure.scaled_error(y.cpu().numpy(), eager.cpu().numpy(), scale)
-            assert err.max() <= 1e-12, "%s replay %d: %.3g" % (fmt, rep, err.max())
+            # FP64 sums in a varying order; reduced forms then round y to FP32, where two such
+            # sums can land one FP32 rounding step apart
+            tol = 1e-12 if vt == "f64" else 2.0 ** -23
+            err = measure.scaled_error(y.double().cpu().numpy(), eager.double().cpu().numpy(),
+                                       scale)
+            assert err.max() <= tol, "%s %s replay %d: %.3g" % (fmt, vt, rep, err.max())
     del g
     A.close()
 
