@@ -54,11 +54,37 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_text(src):
+    """C++ source without its comments and with runs of white space made one blank: what the
+    compiler sees, so that an edit of a comment does not mark measurements of the code stale."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        ch = src[i]
+        if ch in "\"'":  # string or character literal, copied whole
+            j = i + 1
+            while j < n and src[j] != ch:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(ch)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def src_hash(*names):
+    """Hash of the kernel sources' code (comments and layout left out)."""
     h = hashlib.sha256()
     for n in names:
-        with open(os.path.join(ROOT, "paper_2502_19284_amd", "csrc", n), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2502_19284_amd", "csrc", n), encoding="utf-8") as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

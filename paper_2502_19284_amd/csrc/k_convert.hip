@@ -1337,7 +1337,8 @@ hipError_t launch_dedup_count(const uint64_t* keys, int64_t E, uint32_t* tile_su
 // increasing triplet index, because the sort that carried the values is stable.  The last entry
 // of each row (block) writes u+1 at its row (block), for the max-scan that follows.
 // MODE 0: CRS (column index), 1: CSB Hilbert, 2: CSB Z-Morton (packed local row/column),
-// 5: CSBR (the low 32 bits of the key are the packed (rank, row) position inside the block)
+// 5: CSBR (the low 32 bits of the key are the packed (column rank, row rank) position inside the
+// block)
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gather(const uint64_t* __restrict__ keys,
                                                 const double* __restrict__ vals,

@@ -31,14 +31,15 @@
 #define CB_LDS_BUDGET (64 * 1024)    // bytes of the output slice kept in LDS
 #define CB_BP_STAGE_MAX 8192         // block pointers staged in LDS when nbc+1 <= this
 
-// CSBR: panels of 2^CR_PB rows (y slice in LDS: 128 KiB, one workgroup of 16 waves per CU),
-// blocks of 2^CR_RB ranks, workgroup size and entries per thread per sweep, default entries per
-// work unit.  Measured at R-MAT scale 24: 2^13-row panels with 512-thread workgroups (two per CU)
-// 1.38 ms, 2^14-row panels with 1024 threads 1.29 ms (fewer lines of x per entry, same waves).
+// CSBR: panels of 2^CR_PB row ranks (y slice in LDS: 128 KiB, one workgroup of 16 waves per
+// CU), blocks of 2^CR_RB column ranks, workgroup size, default entries per work unit (2^17 /
+// 2^18 / 2^19 / 2^20 measured 0.83 / 0.80 / 0.83 / 0.86 ms at R-MAT scale 24).  With rows as
+// given: 2^13-row panels with 512-thread workgroups (two per CU) 1.38 ms, 2^14-row panels with
+// 1024 threads 1.29 ms (fewer lines of x per entry, same waves).
 #ifndef CR_PB
 #define CR_PB 14
 #endif
-#define CR_RB (32 - CR_PB)  // the packed (rank, row) position fills 32 bits
+#define CR_RB (32 - CR_PB)  // the packed (column rank, row rank) position fills 32 bits
 #ifndef CR_NT
 #define CR_NT 1024
 #endif
