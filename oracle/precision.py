@@ -21,13 +21,17 @@ def round_f32(v):
 def round_bf16(v):
     """Round float64 values to bfloat16 (8 significant bits, round to nearest, ties to even),
     returned as float64.  Written from the definition: in the binade [2^(e-1), 2^e) representable
-    values are multiples of 2^(e-8); the nearest multiple is taken, ties to the even one."""
+    values are multiples of 2^(e-8), and below the smallest normal 2^-126 multiples of the
+    subnormal spacing 2^-133; the nearest multiple is taken, ties to the even one.  A result
+    beyond the largest finite value, (2 - 2^-7) 2^127, is an infinity of the same sign."""
     v = np.asarray(v, np.float64)
     out = np.zeros_like(v)
     nz = v != 0
     m, e = np.frexp(v[nz])          # v = m 2^e, 0.5 <= |m| < 1
-    q = np.ldexp(1.0, e - 8)        # spacing of 8-bit significands in that binade
-    out[nz] = np.rint(v[nz] / q) * q  # np.rint rounds halves to even
+    q = np.ldexp(1.0, np.maximum(e, -125) - 8)  # spacing of representable values there
+    r = np.rint(v[nz] / q) * q      # np.rint rounds halves to even
+    out[nz] = np.where(np.abs(r) >= 2.0 ** 128, np.copysign(np.inf, r), r)
+    out[~nz] = v[~nz]               # +0 and -0 kept
     return out
 
 

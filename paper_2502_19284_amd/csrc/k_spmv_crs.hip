@@ -304,17 +304,35 @@ hipError_t spmv_crs_f32(const spx_matrix_s* A, const float* x, float* y, hipStre
 
 // ================================================================== value rounding at conversion
 
-// round-to-nearest-even of a double to bfloat16 (8 significant bits), returned as its 16 bits
+// Round-to-nearest-even of a double to bfloat16, returned as its 16 bits (sign, 8-bit exponent
+// with bias 127, 7 fraction bits), from the bit fields of the double: in the normal range the 52
+// fraction bits are cut to 7 and the 45 cut bits decide the rounding (above half: up; exactly
+// half: up only if the kept fraction is odd), a carry out of the fraction stepping the exponent
+// (up to the infinity); below 2^-126 the value is counted in units of the subnormal spacing
+// 2^-133 with the same rule.  NaN stays a (quiet) NaN, zeros and infinities keep their sign.
 __device__ __forceinline__ uint16_t bf16_rne(double v) {
-    if (v == 0.0 || !isfinite(v)) {
-        const float f = (float)v;
-        return (uint16_t)(__float_as_uint(f) >> 16);
+    const uint64_t bits = (uint64_t)__double_as_longlong(v);
+    const uint16_t sign = (uint16_t)((bits >> 48) & 0x8000u);
+    const int ex = (int)((bits >> 52) & 0x7FF);
+    const uint64_t frac = bits & ((1ull << 52) - 1ull);
+    if (ex == 0x7FF) return sign | (frac ? 0x7FC0u : 0x7F80u);  // NaN / infinity
+    const int E = ex - 1023;                                     // v = 1.frac 2^E (ex > 0)
+    if (ex == 0 || E < -134) return sign;  // below half the subnormal spacing (or a zero)
+    uint64_t kept, cut, half;
+    if (E >= -126) {  // normal: exponent field E + 127, 7 fraction bits
+        kept = ((uint64_t)(E + 127) << 7) | (frac >> 45);
+        cut = frac & ((1ull << 45) - 1ull);
+        half = 1ull << 44;
+    } else {  // subnormal: |v| / 2^-133 = (2^52 + frac) 2^(E + 81), shift = -(E + 81) in 46..53
+        const uint64_t sig = (1ull << 52) | frac;
+        const int sh = -(E + 81);
+        kept = sig >> sh;
+        cut = sig & ((1ull << sh) - 1ull);
+        half = 1ull << (sh - 1);
     }
-    int e;
-    frexp(v, &e);                      // |v| in [2^(e-1), 2^e)
-    const double q = ldexp(1.0, e - 8);  // spacing of 8-bit significands in that binade
-    const double r = rint(v / q) * q;  // v/q exact (power-of-two scaling); rint rounds to even
-    return (uint16_t)(__float_as_uint((float)r) >> 16);  // r has 8 significant bits: exact
+    const bool up = cut > half || (cut == half && (kept & 1ull));
+    kept += up ? 1u : 0u;  // may carry into the exponent; 0x7F80 is the infinity
+    return sign | (uint16_t)(kept > 0x7F80u ? 0x7F80u : kept);
 }
 
 __global__ void k_round_values(const double* __restrict__ in, int64_t n, int32_t vt,

@@ -151,3 +151,34 @@ def test_precision_entry_points_reject_mismatch(spx, rmat14):
                     "csbh", value_type="bf16")
     st = L.spx_spmv(B.handle, ctypes.c_void_p(xb.data_ptr()), ctypes.c_void_p(yb.data_ptr()), None)
     assert st == -7
+
+
+@pytest.mark.parametrize("vt", ["f32", "bf16"])
+def test_stored_value_rounding_edges(spx, vt):
+    # the device's rounding of stored values against the oracle's on edge values: bfloat16
+    # subnormals (spacing 2^-133) and their ties, the smallest normal, values that overflow to
+    # the infinity, exact ties in the normal range, signed zeros
+    import torch
+    vals = np.array([2.0 ** -134, 3 * 2.0 ** -135, 1.5 * 2.0 ** -133, 2.5 * 2.0 ** -133,
+                     2.0 ** -126, (1 - 2.0 ** -9) * 2.0 ** -126, 1e-40, -1e-40, 1e-45,
+                     (2 - 2.0 ** -7) * 2.0 ** 127, (2 - 2.0 ** -8) * 2.0 ** 127, -3.4e38, 1e300,
+                     1 + 2.0 ** -8, 1 + 3 * 2.0 ** -9, 257.0, -0.0, 0.0, 1e-320, 0.1, -7.0])
+    rng = np.random.default_rng(21)
+    vals = np.concatenate([vals, np.ldexp(rng.uniform(-1, 1, 2000), rng.integers(-140, 128,
+                                                                               2000))])
+    n = len(vals)
+    row = np.arange(n, dtype=np.int32)  # one entry per row: canonical order = input order
+    col = np.zeros(n, dtype=np.int32)
+    d = lambda a, t: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype=t)
+    A = spx.convert(d(row, torch.int32), d(col, torch.int32), d(vals, torch.float64), (n, 1),
+                    "rowsplit", value_type=vt)
+    got = A.export("values").cpu()
+    if vt == "f32":
+        want = np.asarray(vals, np.float64).astype(np.float32).view(np.uint32)
+        assert np.array_equal(got.numpy().view(np.uint32), want)
+    else:
+        bits = got.view(dtype=torch.int16).numpy().view(np.uint16)
+        want = precision.bf16_bits(vals)
+        bad = np.flatnonzero(bits != want)
+        assert len(bad) == 0, [(vals[i], hex(bits[i]), hex(want[i])) for i in bad[:5]]
+    A.close()

@@ -465,9 +465,12 @@ def _bf16_candidates(x):
 
 def test_bf16_rounding_brute_force():
     rng = np.random.default_rng(17)
+    sub = np.ldexp(rng.uniform(0.5, 1, 300), rng.integers(-140, -124, 300))  # near 2^-126
     vals = np.concatenate([rng.uniform(-1, 1, 3000), rng.uniform(-300, 300, 1000),
+                           sub, -sub, np.ldexp(rng.uniform(0.5, 1, 200), 127),
                            [1.0, -1.0, 3.0, 255.0, 256.0, 257.0, 1 + 2 ** -8, 1 + 3 * 2 ** -9,
-                            2 ** -130 * 0 + 1e-3]])
+                            1e-3, 2.0 ** -126, 2.0 ** -133, 1.5 * 2.0 ** -133, 2.5 * 2.0 ** -133,
+                            2.0 ** -134, 3 * 2.0 ** -135]])
     got = precision.round_bf16(vals)
     for v, g in zip(vals, got):
         cands = _bf16_candidates(v)
@@ -478,6 +481,15 @@ def test_bf16_rounding_brute_force():
         assert g == near[0][0], (v, g, near)
     # integers up to 256 are exact; 257 ties to 256 (even)
     assert list(precision.round_bf16([3.0, -3.0, 256.0, 257.0])) == [3.0, -3.0, 256.0, 256.0]
+    # subnormals: spacing 2^-133; 2^-134 ties to 0 (even), 3 2^-135 rounds up to 2^-133
+    assert list(precision.round_bf16([2.0 ** -134, 3 * 2.0 ** -135, 1.5 * 2.0 ** -133])) == \
+        [0.0, 2.0 ** -133, 2.0 ** -132]
+    # overflow: the largest finite value is (2 - 2^-7) 2^127; halfway to 2^128 ties to the even
+    # significand, which is the infinity
+    big = (2 - 2.0 ** -7) * 2.0 ** 127
+    assert precision.round_bf16([big, -big])[0] == big
+    assert np.isinf(precision.round_bf16([(2 - 2.0 ** -8) * 2.0 ** 127])[0])
+    assert np.array_equal(np.signbit(precision.round_bf16([-0.0, 0.0])), [True, False])
     assert precision.round_bf16([1 + 2 ** -8])[0] == 1.0          # tie -> even
     assert precision.round_bf16([1 + 3 * 2 ** -9])[0] == 1 + 2 ** -7
 
