@@ -959,6 +959,9 @@ static int64_t sum_owned_bytes(const spx_matrix_s* A) {
     b += (A->cb_units ? (int64_t)A->cb_nunits * 16 + (int64_t)A->cb_nsplit * 16 : 0);
     b += (A->cb_partials ? ((int64_t)A->cb_nslots << A->log2_beta) * 8 : 0);
     b += (int64_t)A->nhot * 12;
+    // CSBR: column order and ranked x, row order and ranked y, rank of every row
+    b += ((int64_t)A->cr_nranked * 12 + (int64_t)A->cr_nrows * 12 +
+          (A->cr_row_rank ? (int64_t)A->m * 4 : 0));
     return b;
 }
 
