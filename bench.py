@@ -718,6 +718,44 @@ def summarize_rocprof(prof_dir, label):
                               "traffic_bytes_per_launch": traffic}
 
 
+PIPE_COUNTERS = ("TA_TA_BUSY_sum", "TD_TD_BUSY_sum", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU",
+                 "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD")
+
+
+def summarize_pipe(prof_dir, label, cus=256, xcds=8):
+    """Markdown table of the vector memory pipeline counters of one `--pmc` pass (PIPE_COUNTERS)
+    per product kernel: the texture address (TA) and texture data (TD) units' busy cycles as a
+    share of each CU's active cycles (TA / TD busy summed over the `cus` CUs, GRBM_GUI_ACTIVE
+    summed over the `xcds` XCDs), and the VALU, LDS and vector-memory read instructions issued
+    per dispatch (wave instructions, millions)."""
+    import csv
+    import collections
+    disp = collections.defaultdict(lambda: collections.defaultdict(float))
+    names = {}
+    for r in csv.DictReader(open(os.path.join(prof_dir, label + "_counter_collection.csv"))):
+        d = int(r["Dispatch_Id"])
+        disp[d][r["Counter_Name"]] += float(r["Counter_Value"])
+        names[d] = r["Kernel_Name"]
+    agg = collections.defaultdict(list)
+    for d, v in disp.items():
+        agg[_short(names[d])].append(v)
+    lines = ["| kernel | dispatches | TA busy | TD busy | VALU (M) | LDS (M) | VMEM reads (M) |",
+             "|---|---|---|---|---|---|---|"]
+    for k in sorted(agg):
+        if not k.startswith("k_spmv") and not k.startswith("k_csbr"):
+            continue
+        vs = agg[k]
+        mean = lambda c: sum(v[c] for v in vs) / len(vs)
+        cyc = mean("GRBM_GUI_ACTIVE") / xcds
+        if cyc <= 0:
+            continue
+        lines.append("| `%s` | %d | %.0f%% | %.0f%% | %.1f | %.1f | %.1f |" % (
+            k[:60], len(vs), 100 * mean("TA_TA_BUSY_sum") / cus / cyc,
+            100 * mean("TD_TD_BUSY_sum") / cus / cyc, mean("SQ_INSTS_VALU") / 1e6,
+            mean("SQ_INSTS_LDS") / 1e6, mean("SQ_INSTS_VMEM_RD") / 1e6))
+    return "\n".join(lines)
+
+
 ALIASES = {"hot_gather": "k_hot_gather_t"}
 
 
@@ -837,6 +875,8 @@ def main():
     ap.add_argument("--summarize-rocprof", metavar="DIR",
                     help="print a markdown summary of rocprofv3 CSV output in DIR and write "
                          "profiles/traffic_rmat24.json, then exit")
+    ap.add_argument("--summarize-pipe", metavar="DIR",
+                    help="print the pipeline counter table of a --pmc run (PIPE_COUNTERS) in DIR")
     ap.add_argument("--line-model", metavar="WORKLOAD",
                     help="print the modelled x lines per product of each layout on WORKLOAD "
                          "(CPU only, minutes; about 20 GB of host memory at scale 24), then exit")
@@ -871,6 +911,9 @@ def main():
         with open(os.path.join(ROOT, "profiles", "traffic_rmat24.json"), "w") as f:
             json.dump(tj, f, indent=1, sort_keys=True)
         print(md)
+        return
+    if args.summarize_pipe:
+        print(summarize_pipe(args.summarize_pipe, "rmat24"))
         return
     if args.line_model:
         print(json.dumps(line_model(args.line_model), indent=1))
