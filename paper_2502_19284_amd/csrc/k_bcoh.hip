@@ -74,6 +74,11 @@ __global__ __launch_bounds__(RC_NT) void k_rowc_hist(const int32_t* __restrict__
 // rows_out[pos] = the row, or with_aux: (row mod 2^wbits) | aux << wbits with aux =
 // map[col] >> aux_shift (map NULL: col >> aux_shift); the count needs only the row's position in
 // its bucket.  keep (nullable, with a map) receives map[col] at the entry's own index.
+// The scatter stages each sub-tile of RC_SUB entries in LDS grouped by bucket (a count, an
+// exclusive scan and a placement), then writes every bucket's run of the sub-tile to consecutive
+// output positions, so that the stores of a wave land on few lines; placing each entry straight
+// from its LDS cursor spread a wave's stores over as many partly written lines as it has lanes.
+#define RC_SUB (RC_NT * 8)
 __global__ __launch_bounds__(RC_NT) void k_rowc_scatter(const int32_t* __restrict__ row,
                                                         const int32_t* __restrict__ col,
                                                         int64_t E, int32_t m, int32_t n,
@@ -83,50 +88,96 @@ __global__ __launch_bounds__(RC_NT) void k_rowc_scatter(const int32_t* __restric
                                                         int with_aux, int aux_shift,
                                                         const int32_t* __restrict__ aux_map,
                                                         int32_t* __restrict__ keep) {
+    static_assert(RC_BUCKETS == 4 * RC_NT, "the scan takes four buckets per thread");
+    static_assert(RC_BUCKETS <= 65536, "staged bucket numbers are 16-bit");
+    constexpr int U = RC_SUB / RC_NT;
     const uint32_t wmask = (1u << wbits) - 1u;
-    __shared__ uint32_t cur[RC_BUCKETS];
+    __shared__ uint32_t cur[RC_BUCKETS];      // this tile's next output position of each bucket
+    __shared__ uint32_t off[RC_BUCKETS + 1];  // a sub-tile's counts, then their exclusive prefix
+    __shared__ int32_t stage[RC_SUB];         // the sub-tile's values grouped by bucket
+    __shared__ uint16_t sbk[RC_SUB];          // the bucket of each staged value
+    __shared__ uint32_t wtot[RC_NT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t t = blockIdx.x;
-    for (int b = threadIdx.x; b < nbk; b += RC_NT) cur[b] = hist[(int64_t)b * T + t];
-    __syncthreads();
+    for (int b = tid; b < nbk; b += RC_NT) cur[b] = hist[(int64_t)b * T + t];
     const int64_t lo = t * RC_TILE;
     const int64_t hi = lo + RC_TILE < E ? lo + RC_TILE : E;
-    int64_t i = lo + threadIdx.x;
-    for (; i + 3 * RC_NT < hi; i += 4 * RC_NT) {  // four entries in flight per thread
-        int32_t r[4], c[4];
+    for (int64_t s0 = lo; s0 < hi; s0 += RC_SUB) {
+        for (int b = tid; b <= nbk; b += RC_NT) off[b] = 0;
+        __syncthreads();
+        int32_t r[U], c[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            r[u] = row[i + u * RC_NT];
-            c[u] = col[i + u * RC_NT];
+        for (int u = 0; u < U; ++u) {  // every load of the sub-tile in flight together
+            const int64_t i = s0 + u * RC_NT + tid;
+            r[u] = i < hi ? row[i] : -1;
+            c[u] = i < hi ? col[i] : -1;
         }
+        int32_t v[U];
+        int bk[U];
+        uint32_t rk[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const bool ok = (r[u] >= 0) & (r[u] < m) & (c[u] >= 0) & (c[u] < n);
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = s0 + u * RC_NT + tid;
+            const bool ok = (i < hi) & (r[u] >= 0) & (r[u] < m) & (c[u] >= 0) & (c[u] < n);
+            bk[u] = ok ? (r[u] >> wbits) : -1;
+            v[u] = r[u];
+            rk[u] = 0;
             if (ok) {
-                const uint32_t pos = atomicAdd(&cur[r[u] >> wbits], 1u);
-                int32_t v = r[u];
                 if (with_aux) {
                     const int32_t mc = aux_map ? aux_map[c[u]] : c[u];
-                    if (keep) keep[i + u * RC_NT] = mc;
-                    v = (int32_t)(((uint32_t)r[u] & wmask) |
-                                  ((uint32_t)(mc >> aux_shift) << wbits));
+                    if (keep) keep[i] = mc;
+                    v[u] = (int32_t)(((uint32_t)r[u] & wmask) |
+                                     ((uint32_t)(mc >> aux_shift) << wbits));
                 }
-                rows_out[pos] = v;
+                rk[u] = atomicAdd(&off[bk[u]], 1u);
             }
         }
-    }
-    for (; i < hi; i += RC_NT) {
-        const int32_t r = row[i], c = col[i];
-        const bool ok = (r >= 0) & (r < m) & (c >= 0) & (c < n);
-        if (ok) {
-            const uint32_t pos = atomicAdd(&cur[r >> wbits], 1u);
-            int32_t v = r;
-            if (with_aux) {
-                const int32_t mc = aux_map ? aux_map[c] : c;
-                if (keep) keep[i] = mc;
-                v = (int32_t)(((uint32_t)r & wmask) | ((uint32_t)(mc >> aux_shift) << wbits));
+        __syncthreads();
+        {  // exclusive scan of the counts: four buckets per thread, then waves, then the block
+            uint32_t a[4], sum = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int b = tid * 4 + j;
+                a[j] = b < nbk ? off[b] : 0u;
+                sum += a[j];
             }
-            rows_out[pos] = v;
+            uint32_t x = sum;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t y = __shfl_up(x, d, 64);
+                if (lane >= d) x += y;
+            }
+            if (lane == 63) wtot[wave] = x;
+            __syncthreads();
+            uint32_t base = 0;
+            for (int w = 0; w < wave; ++w) base += wtot[w];
+            uint32_t e = base + x - sum;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int b = tid * 4 + j;
+                if (b < nbk) off[b] = e;
+                e += a[j];
+            }
+            if (tid == RC_NT - 1) off[nbk] = base + x;
         }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (bk[u] >= 0) {
+                const uint32_t p = off[bk[u]] + rk[u];
+                stage[p] = v[u];
+                sbk[p] = (uint16_t)bk[u];
+            }
+        }
+        __syncthreads();
+        const uint32_t ns = off[nbk];
+        for (uint32_t j = tid; j < ns; j += RC_NT) {
+            const int b = sbk[j];
+            rows_out[cur[b] + (j - off[b])] = stage[j];
+        }
+        __syncthreads();
+        for (int b = tid; b < nbk; b += RC_NT) cur[b] += off[b + 1] - off[b];
+        __syncthreads();
     }
 }
 
