@@ -238,8 +238,8 @@ def gather_probe(spx, torch, reps=10):
 
 
 def cpu_baseline(w, budget_s=12.0):
-    """The oracle on the GPU machine's host, on a bounded sample of the same matrix (the rows whose
-    index hashes into 1/8 of the range): Algorithm 1 as printed (sequential, one core) -- the
+    """The oracle on the benchmarked GPU's host cores, on a bounded sample of the same matrix (the
+    rows whose index hashes into 1/8 of the range): Algorithm 1 as printed (sequential, one core) -- the
     reported value -- and, beside it, the oracle's ParCRS (Section 5.1: rows in dynamic chunks of
     512 over all host threads) and its triplet -> CRS conversion of the sample.  Only the
     products (and the conversion, separately) are timed."""
@@ -920,7 +920,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported (the multi-GPU "
-              "sharding is described in DESIGN.md, not run)" % args.gpus, file=sys.stderr)
+              "sharding is described, not run)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     fmts = [f for f in args.formats.split(",") if f]
     if args.headline not in fmts:

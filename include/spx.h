@@ -234,7 +234,8 @@ spx_status spx_spmv_f32(spx_matrix A, const float* x, float* y, void* stream);
  * the handle, grown on demand and freed by spx_matrix_destroy; as for spx_spmv, one product call
  * per handle may be in flight at a time.
  * Errors: INVALID_ARG for k < 1, an unknown layout, a leading dimension below its minimum or a
- * NULL operand; ALIAS when the spans of X and Y overlap; UNSUPPORTED for the CSB formats; RANGE
+ * NULL operand; ALIAS when the spans of X and Y overlap; UNSUPPORTED for the block formats (CSB,
+ * CSBH, BCOHC, BCOHCH, CSBR); RANGE
  * when a span does not fit in 64 bits; NOMEM when scratch cannot be allocated.
  */
 spx_status spx_spmm(spx_matrix A, int32_t k, const void* X, int64_t ldx, void* Y, int64_t ldy,
