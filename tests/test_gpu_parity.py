@@ -263,6 +263,34 @@ def test_csbh_block_sizes_and_split_rows(spx, log2_beta, unit, fmt):
     _check_structure(A, m, n, row, col, val)
 
 
+@pytest.mark.parametrize("fmt", ["csbr", "bcohc"])
+def test_bucketed_count_many_buckets(spx, fmt):
+    # rows and columns of CSBR just under the 2^26 limit of the bucketed counts: 4096 buckets of
+    # 2^14 indices (the whole range of the scatter's bucket scan); BCOHC, whose key holds the
+    # partition (at most 8192 rows each) and the Hilbert index, fits 64 bits up to 2^25 rows
+    # (2048 buckets).  Few triplets per bucket, most buckets of a sub-tile empty, heavy rows in
+    # the first and the last bucket and a heavy column
+    rng = np.random.default_rng(71)
+    m = (1 << 26) - 3 if fmt == "csbr" else (1 << 25) - 3
+    n = m if fmt == "csbr" else 4096
+    E = 400_000
+    row = rng.integers(0, m, E)
+    col = rng.integers(0, n, E)
+    row[:20_000] = 5
+    row[20_000:30_000] = m - 1
+    col[30_000:40_000] = n - 2
+    perm = rng.permutation(E)
+    row, col = row[perm].astype(np.int32), col[perm].astype(np.int32)
+    val = synth.values(E, seed=72, kind="int")
+    x = synth.xvec(n, seed=73, kind="int")
+    ref = spmv.reference(m, n, row, col, val, x)
+    say("bucketed count, 4096 buckets", fmt)
+    A, y = _run(spx, fmt, m, n, row, col, val, x)
+    _check_int(y, ref, "%s with 4096 buckets" % fmt)
+    if fmt == "csbr":
+        _check_structure(A, m, n, row, col, val)
+
+
 @pytest.mark.parametrize("unit", [0, 700, 5000, 100_000])
 @pytest.mark.parametrize("kind", ["int", "float"])
 def test_csbr_segments_and_split_panels(spx, unit, kind):
