@@ -886,7 +886,7 @@ def main():
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--headline", default=HEADLINE, help="format of the timed step")
     ap.add_argument("--spmv-reps", type=int, default=550)
-    ap.add_argument("--convert-reps", type=int, default=5)
+    ap.add_argument("--convert-reps", type=int, default=25)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--formats", default=",".join(FMTS))
     ap.add_argument("--relabelled", type=int, default=1,
@@ -949,8 +949,20 @@ def main():
     sample_rows = np.unique(np.concatenate([rng.integers(0, m, 2000), np.argsort(counts)[-12:],
                                             [0, m - 1]])).astype(np.int64)
     dev = lambda a, t: torch.from_numpy(a).to("cuda", dtype=t)
+    torch.zeros(1, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()  # the caller's upload of the triplets (pageable host memory)
     row_d, col_d = dev(w["row"], torch.int32), dev(w["col"], torch.int32)
-    val_d, x_d = dev(w["val"], torch.float64), dev(w["x"], torch.float64)
+    val_d = dev(w["val"], torch.float64)
+    torch.cuda.synchronize()
+    up_ms = (time.perf_counter() - t0) * 1e3
+    up_bytes = E * (4 + 4 + 8)
+    upload = {"bytes": up_bytes, "ms": round(up_ms, 2),
+              "GB_s": round(up_bytes / (up_ms * 1e-3) / 1e9, 1),
+              "what": "row, col (int32) and val (FP64) of the raw triplets, host numpy (pageable) "
+                      "to device, before any conversion; not part of convert ms"}
+    log("triplet upload %.1f ms (%.1f GB/s)" % (up_ms, upload["GB_s"]))
+    x_d = dev(w["x"], torch.float64)
     y_d = torch.empty(m, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     copy_gbs = copy_probe(torch)
@@ -1070,7 +1082,8 @@ def main():
         "roofline": roofline,
         "spmv_steady": {"best_format": best, "gflops": spmv[best]["gflops_median_time"],
                         "hbm_frac": spmv[best]["roofline"]["frac"]},
-        "spmv": spmv, "convert": conv_rec, "break_even_vs_rowsplit": be,
+        "spmv": spmv, "convert": conv_rec, "triplet_upload": upload,
+        "break_even_vs_rowsplit": be,
         "relabelled": relab,
         "reduced_precision": prec,
         "spmm": mm,
