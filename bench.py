@@ -1078,7 +1078,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "m": m, "n": n, "raw_entries": E,
                    "nnz": nnz, "n_touched_columns": n_touched, "format": args.headline,
-                   "step": "one y = A x on the resident matrix (matrix, x and y in HBM)"},
+                   "step": "one y = A x on the resident matrix (matrix, x and y in HBM)",
+                   "residency": "the matrix (%.1f GB) is larger than the 256 MiB MALL and streams "
+                                "from HBM in every product; x (%d MB) and its ranked copy fit the "
+                                "MALL and may stay there between products"
+                                % (12 * nnz / 1e9, round(8 * n / 1e6))},
         "roofline": roofline,
         "spmv_steady": {"best_format": best, "gflops": spmv[best]["gflops_median_time"],
                         "hbm_frac": spmv[best]["roofline"]["frac"]},
