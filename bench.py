@@ -271,7 +271,12 @@ def cpu_baseline(w, budget_s=12.0):
     threads = ref.parcrs(rp, c, v, w["x"])[1]
     ptimes = timed(lambda: ref.parcrs(rp, c, v, w["x"]), budget_s / 3, 200)
     best, pbest = min(times), min(ptimes)
+    # the bytes model of the GPU products, on the sample: CRS arrays, touched x, y
+    touched = int(np.count_nonzero(np.bincount(c, minlength=n)))
+    B = 12 * nnz + 4 * (nrows + 1) + 8 * (touched + nrows)
+    Bc = 16 * int(sel.sum()) + 12 * nnz + 4 * (nrows + 1)  # triplets read, CRS written
     return {"value": round(2 * nnz / best / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
+            "gb_s": round(B / best / 1e9, 3), "bytes_model": B,
             "kind": "oracle", "host": host_cpu(),
             "sample": "oracle Algorithm 1 (sequential, plain FP64) on the %d rows (1/8 of the "
                       "rows, chosen by a multiplicative hash of the row index) holding %d of "
@@ -279,10 +284,12 @@ def cpu_baseline(w, budget_s=12.0):
                       % (nrows, nnz, len(times), sum(times)),
             "ms_min": round(best * 1e3, 3), "ms_median": round(statistics.median(times) * 1e3, 3),
             "parcrs": {"value": round(2 * nnz / pbest / 1e9, 4), "unit": "GFLOP/s",
+                       "gb_s": round(B / pbest / 1e9, 3),
                        "threads": threads, "ms_min": round(pbest * 1e3, 3),
                        "ms_median": round(statistics.median(ptimes) * 1e3, 3),
                        "runs": len(ptimes)},
-            "crs_conversion_ms": round(conv_s * 1e3, 1)}
+            "crs_conversion_ms": round(conv_s * 1e3, 1),
+            "crs_conversion_gb_s": round(Bc / conv_s / 1e9, 3)}
 
 
 def time_products(spx, torch, A, x, y, reps):
