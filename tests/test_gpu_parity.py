@@ -442,6 +442,33 @@ def test_repeat_runs_bitwise_identical(spx, rmat14, fmt):
     assert np.array_equal(y1.view(np.int64), y2.view(np.int64))
 
 
+EXPORTS = {"rowsplit": ("row_ptr", "col_ind", "values", "parts"),
+           "merge": ("row_ptr", "col_ind", "values", "parts"),
+           "csbh": ("blk_ptr", "packed", "values", "parts"),
+           "csb": ("blk_ptr", "packed", "values", "parts"),
+           "bcohc": ("blk_ptr", "packed", "values", "parts", "blk_coord"),
+           "bcohch": ("blk_ptr", "packed", "values", "parts", "blk_coord"),
+           "csbr": ("blk_ptr", "packed", "values", "parts", "col_order", "row_order")}
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_conversion_deterministic(spx, rmat14, fmt):
+    # the same triplets convert to bit-identical arrays every time, although some steps run in
+    # an order that varies (LDS atomics place entries in the bucketed counts' scatter; the
+    # counts and extents they feed do not depend on it)
+    import torch
+    m, n, row, col, d = rmat14
+    val, _, _ = d["float"]
+    got = []
+    for _ in range(2):
+        A = spx.convert(_dev(row, torch.int32), _dev(col, torch.int32),
+                        _dev(val, torch.float64), (m, n), fmt)
+        got.append({a: A.export(a).cpu().numpy().tobytes() for a in EXPORTS[fmt]})
+        A.close()
+    for a in EXPORTS[fmt]:
+        assert got[0][a] == got[1][a], "%s: %s differs between conversions" % (fmt, a)
+
+
 def test_linearity_float(spx, rmat14):
     import torch
     m, n, row, col, d = rmat14
